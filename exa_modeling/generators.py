@@ -1,0 +1,260 @@
+"""Seeded synthetic workloads shaped like the paper's benchmark families.
+
+The paper measures on PGLib-OPF power-flow cases, on COPS and on the
+Luksan-Vlcek set (Sec. 8.1).  None of those files is available here, so
+these generators draw synthetic instances with the same algebraic patterns
+and comparable sizes; they stand in for those suites and are not copies of
+any of their instances.
+
+* :func:`acopf` -- AC optimal power flow in polar form, built in the layered
+  way of Sec. 3.3.2 (base balance rows plus augmentations), 13 patterns.
+* :func:`pde` -- distributed control of a semilinear elliptic PDE on an
+  n x n grid (5-point Laplacian), a COPS-like shape.
+* :func:`rosenbrock` -- the extended Rosenbrock objective, eq. rosenbrock.
+
+Every random draw comes from ``numpy.random.Generator(PCG64(seed))`` in a
+fixed order, documented per function.  Nothing here evaluates the model.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict
+
+import numpy as np
+
+from .ir import DataSet, Model, cos, sin, exp
+
+
+@dataclass
+class Workload:
+    """A model plus one evaluation point (x, y, sigma) drawn with it."""
+    model: Model
+    x: np.ndarray
+    y: np.ndarray
+    sigma: float = 1.0
+    meta: Dict = field(default_factory=dict)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def acopf_topology(rng: np.random.Generator, nb: int):
+    """Ring over the buses plus ``ceil(0.35 nb)`` random chords.
+
+    Chords are drawn as (from, to) pairs uniformly over the buses and
+    rejected when they are self-loops or repeat an existing branch in either
+    direction.  Returns (fr, to) int arrays of length nl.
+    """
+    nc = (35 * nb + 99) // 100
+    fr = list(range(nb))
+    to = [(i + 1) % nb for i in range(nb)]
+    seen = set()
+    for a, b in zip(fr, to):
+        seen.add((min(a, b), max(a, b)))
+    cf, ct = [], []
+    while len(cf) < nc:
+        need = nc - len(cf)
+        cand = rng.integers(0, nb, size=(2 * need + 8, 2))
+        for a, b in cand:
+            a, b = int(a), int(b)
+            key = (min(a, b), max(a, b))
+            if a == b or key in seen:
+                continue
+            seen.add(key)
+            cf.append(a)
+            ct.append(b)
+            if len(cf) == nc:
+                break
+    return (np.asarray(fr + cf, dtype=np.int64), np.asarray(to + ct, dtype=np.int64))
+
+
+def acopf(nb: int, seed: int, *, load_perturb: bool = False, gb_in_theta: bool = False,
+          rng: np.random.Generator = None) -> Workload:
+    """ACOPF-shaped NLP in polar form with ``nb`` buses.
+
+    Draw order: topology (ring, chords), generator buses, g, b, rate, pd, qd,
+    c0, c1, c2, then the point x (va, vm, pg, qg, p, q), then y; with
+    ``load_perturb`` one factor U(0.9, 1.1) per bus is drawn last and scales
+    pd and qd.
+
+    Variables: va[nb], vm[nb], pg[ng], qg[ng], p[2 nl], q[2 nl] where arc
+    ``l`` (0 <= l < nl) is the from end of branch l and arc ``nl + l`` its to
+    end.  Parameters theta = (pd[nb], qd[nb], c1[ng], c2[ng]) and, with
+    ``gb_in_theta``, also (g[nl], b[nl]).
+
+    Patterns, in declaration order:
+      0 O    sum over generators of c2 pg^2 + c1 pg + c0
+      1 C_pf p_f - (g vm_f^2 - vm_f vm_t (g cos(va_f - va_t) + b sin(va_f - va_t)))
+      2 C_qf q_f - (-b vm_f^2 - vm_f vm_t (g sin(va_f - va_t) - b cos(va_f - va_t)))
+      3 C_pt, 4 C_qt   the same at the to end (f and t swapped)
+      5 B_p  pd_b  (one row per bus)       6 B_q  qd_b
+      7 A_pg B_p[bus(g)] += -pg_g          8 A_qg B_q[bus(g)] += -qg_g
+      9 A_p  B_p[bus(a)] += p_a            10 A_q B_q[bus(a)] += q_a
+      11 T_f p_f^2 + q_f^2 <= rate^2       12 T_t p_t^2 + q_t^2 <= rate^2
+    """
+    if rng is None:
+        rng = _rng(seed)
+    nb = int(nb)
+    fr, to = acopf_topology(rng, nb)
+    nl = fr.size
+    ng = (nb + 2) // 5
+    gen_bus = rng.choice(nb, size=ng, replace=False).astype(np.int64)
+    g = rng.uniform(1.0, 10.0, nl)
+    b = rng.uniform(-20.0, -5.0, nl)
+    rate = rng.uniform(0.5, 5.0, nl)
+    pd = rng.uniform(0.0, 1.0, nb)
+    qd = rng.uniform(0.0, 1.0, nb)
+    c0 = rng.uniform(0.0, 1.0, ng)
+    c1 = rng.uniform(10.0, 40.0, ng)
+    c2 = rng.uniform(0.01, 0.1, ng)
+    va0 = rng.uniform(-0.3, 0.3, nb)
+    vm0 = rng.uniform(0.9, 1.1, nb)
+    pg0 = rng.uniform(0.0, 2.0, ng)
+    qg0 = rng.uniform(-1.0, 1.0, ng)
+    p0 = rng.uniform(-1.0, 1.0, 2 * nl)
+    q0 = rng.uniform(-1.0, 1.0, 2 * nl)
+    m_rows = 6 * nl + 2 * nb
+    y = rng.standard_normal(m_rows)
+    if load_perturb:
+        fac = rng.uniform(0.9, 1.1, nb)
+        pd = pd * fac
+        qd = qd * fac
+
+    m = Model(f"acopf{nb}")
+    va = m.add_var(nb, name="va", start=0.0)
+    vm = m.add_var(nb, lvar=0.9, uvar=1.1, start=1.0, name="vm")
+    pg = m.add_var(ng, lvar=0.0, uvar=2.0, name="pg")
+    qg = m.add_var(ng, lvar=-1.0, uvar=1.0, name="qg")
+    p = m.add_var(2 * nl, name="p")
+    q = m.add_var(2 * nl, name="q")
+    th_pd = m.add_par(pd, "pd")
+    th_qd = m.add_par(qd, "qd")
+    th_c1 = m.add_par(c1, "c1")
+    th_c2 = m.add_par(c2, "c2")
+
+    gens = DataSet(ng, i=np.arange(ng), bus=gen_bus, c0=c0)
+    m.add_obj(th_c2[gens.i] * pg[gens.i] ** 2 + th_c1[gens.i] * pg[gens.i] + gens.c0, gens, "O")
+
+    br = DataSet(nl, l=np.arange(nl), f=fr, t=to, g=g, b=b)
+    if gb_in_theta:
+        th_g = m.add_par(g, "g")
+        th_b = m.add_par(b, "b")
+        G, B = th_g[br.l], th_b[br.l]
+    else:
+        G, B = br.g, br.b
+
+    def flow_p(pi, vi, vj, ai, aj):
+        return pi - (G * vi ** 2 - vi * vj * (G * cos(ai - aj) + B * sin(ai - aj)))
+
+    def flow_q(qi, vi, vj, ai, aj):
+        return qi - (-B * vi ** 2 - vi * vj * (G * sin(ai - aj) - B * cos(ai - aj)))
+
+    vf, vt, af, at = vm[br.f], vm[br.t], va[br.f], va[br.t]
+    m.add_con(flow_p(p[br.l], vm[br.f], vm[br.t], va[br.f], va[br.t]), br, name="C_pf")
+    m.add_con(flow_q(q[br.l], vm[br.f], vm[br.t], va[br.f], va[br.t]), br, name="C_qf")
+    m.add_con(flow_p(p[br.l + nl], vm[br.t], vm[br.f], va[br.t], va[br.f]), br, name="C_pt")
+    m.add_con(flow_q(q[br.l + nl], vm[br.t], vm[br.f], va[br.t], va[br.f]), br, name="C_qt")
+    del vf, vt, af, at
+
+    buses = DataSet(nb, b=np.arange(nb))
+    bp = m.add_con(th_pd[buses.b], buses, name="B_p")
+    bq = m.add_con(th_qd[buses.b], buses, name="B_q")
+    m.add_con_aug(bp, gens.bus, -pg[gens.i], gens, name="A_pg")
+    m.add_con_aug(bq, gens.bus, -qg[gens.i], gens, name="A_qg")
+    arcs = DataSet(2 * nl, a=np.arange(2 * nl), bus=np.concatenate([fr, to]))
+    m.add_con_aug(bp, arcs.bus, p[arcs.a], arcs, name="A_p")
+    m.add_con_aug(bq, arcs.bus, q[arcs.a], arcs, name="A_q")
+    m.add_con(p[br.l] ** 2 + q[br.l] ** 2, br, lcon=-np.inf, ucon=rate ** 2, name="T_f")
+    m.add_con(p[br.l + nl] ** 2 + q[br.l + nl] ** 2, br, lcon=-np.inf, ucon=rate ** 2, name="T_t")
+
+    x = np.concatenate([va0, vm0, pg0, qg0, p0, q0])
+    assert x.size == m.nvar and m.ncon == m_rows
+    meta = dict(nb=nb, nl=nl, ng=ng, seed=seed, fr=fr, to=to, gen_bus=gen_bus,
+                offsets=dict(va=va.offset, vm=vm.offset, pg=pg.offset, qg=qg.offset,
+                             p=p.offset, q=q.offset),
+                theta_offsets=dict(pd=th_pd.offset, qd=th_qd.offset, c1=th_c1.offset,
+                                   c2=th_c2.offset))
+    return Workload(m, x, y, 1.0, meta)
+
+
+def acopf_batch_sizes(count: int, first_seed: int, lo: int = 500, hi: int = 20000):
+    """Bus counts log-uniform in [lo, hi], one generator per instance seed.
+
+    Instance ``i`` uses seed ``first_seed + i``; its first draw is the bus
+    count ``round(exp(U(ln lo, ln hi)))``, after which :func:`acopf` continues
+    on the same generator.
+    """
+    out = []
+    for i in range(count):
+        rng = _rng(first_seed + i)
+        nb = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        out.append((first_seed + i, nb, rng))
+    return out
+
+
+def acopf_batch(count: int = 256, first_seed: int = 1000, lo: int = 500, hi: int = 20000):
+    """The uneven batch of ACOPF instances with loads perturbed by U(0.9, 1.1)."""
+    return [acopf(nb, seed, load_perturb=True, rng=rng)
+            for seed, nb, rng in acopf_batch_sizes(count, first_seed, lo, hi)]
+
+
+def pde(n: int, seed: int) -> Workload:
+    """Distributed control of -Laplace(u) + exp(u) = f on an n x n grid.
+
+    h = 1/(n-1), grid point (i, j) at (i h, j h), linear index c = i n + j.
+    Variables: u[n^2], f[n^2] (state and control).  Objective (no quadrature
+    weights): sum 0.5 (u_c - ut_c)^2 + sum 1e-4 f_c^2 with
+    ut = sin(pi x) sin(pi y).  One constraint per interior point:
+    (4 u_c - u_{c-n} - u_{c+n} - u_{c+1} - u_{c-1}) / h^2 + exp(u_c) - f_c = 0.
+    Bounds: u = 0 on the boundary, 0 <= f <= 10.
+
+    Draw order: u = ut + 0.1 N(0, 1) (n^2 values), f ~ U(0, 10), y ~ N(0, 1).
+    """
+    rng = _rng(seed)
+    n = int(n)
+    if n < 3:
+        raise ValueError("the grid needs n >= 3")
+    N = n * n
+    h = 1.0 / (n - 1)
+    ih2 = float((n - 1) ** 2)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ut = (np.sin(math.pi * ii * h) * np.sin(math.pi * jj * h)).reshape(-1)
+    boundary = ((ii == 0) | (ii == n - 1) | (jj == 0) | (jj == n - 1)).reshape(-1)
+    interior = np.flatnonzero(~boundary)
+
+    m = Model(f"pde{n}")
+    ul = np.where(boundary, 0.0, -np.inf)
+    uu = np.where(boundary, 0.0, np.inf)
+    u = m.add_var(N, lvar=ul, uvar=uu, name="u")
+    f = m.add_var(N, lvar=0.0, uvar=10.0, name="f")
+    pts = DataSet(N, c=np.arange(N), ut=ut)
+    m.add_obj(0.5 * (u[pts.c] - pts.ut) ** 2, pts, "O_u")
+    m.add_obj(1e-4 * f[pts.c] ** 2, pts, "O_f")
+    inn = DataSet(interior.size, c=interior)
+    c = inn.c
+    m.add_con((4 * u[c] - u[c - n] - u[c + n] - u[c + 1] - u[c - 1]) * ih2 + exp(u[c]) - f[c],
+              inn, name="C_pde")
+
+    u0 = ut + 0.1 * rng.standard_normal(N)
+    f0 = rng.uniform(0.0, 10.0, N)
+    y = rng.standard_normal(interior.size)
+    x = np.concatenate([u0, f0])
+    return Workload(m, x, y, 1.0, dict(n=n, interior=interior, h=h))
+
+
+def rosenbrock(N: int, seed: int = 0) -> Workload:
+    """Extended Rosenbrock, eq. rosenbrock, written as in Sec. 4.1.2.
+
+    Data points i = 1 .. N-1 (0-based) with terms
+    100 (x_{i-1}^2 - x_i)^2 + (x_{i-1} - 1)^2.  Point x ~ U(-2, 2).
+    """
+    rng = _rng(seed)
+    m = Model(f"rosenbrock{N}")
+    x = m.add_var(N, name="x")
+    d = DataSet(N - 1, i=np.arange(1, N))
+    i = d.i
+    m.add_obj(100 * (x[i - 1] ** 2 - x[i]) ** 2 + (x[i - 1] - 1) ** 2, d, "rosen")
+    x0 = rng.uniform(-2.0, 2.0, N)
+    return Workload(m, x0, np.zeros(0), 1.0, dict(N=N))
