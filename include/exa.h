@@ -1,0 +1,282 @@
+/*
+ * exa.h -- C ABI of the MI355X structured-NLP derivative evaluator.
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950) in IEEE FP64,
+ * the callbacks a nonlinear-programming solver asks for at every iterate of
+ *
+ *     min f(x; theta)  s.t.  gl <= g(x; theta) <= gu,  xl <= x <= xu
+ *
+ * (paper eq. nlp, Sec. 2.1), for a model stated in the pattern-over-data
+ * form of Sec. 2.2 (eq. simd): every objective group, base constraint block
+ * and constraint augmentation is ONE expression tree evaluated at every
+ * point of its data set.
+ *
+ * Conventions used by every entry point
+ *   - Indices are 0-based (the paper is 1-based); sizes are int64_t, COO
+ *     indices int32_t, values double.
+ *   - "device" pointers are HIP device memory of the current device (e.g. a
+ *     torch CUDA tensor's data_ptr()); "host" pointers are ordinary memory.
+ *   - Callbacks are in place (Sec. 2.1.3): results are written into
+ *     caller-owned arrays.  They are asynchronous on the given stream
+ *     (exa_stream_t is a hipStream_t; NULL is the null stream) and never
+ *     synchronize the device.
+ *   - Every call returns an exa_status; on failure nothing has been written
+ *     to the outputs that the caller could mistake for a result only if the
+ *     failure is reported before launch (argument checks); a failure of the
+ *     HIP runtime after launch is reported as EXA_EHIP.  The text of the
+ *     last error of the calling thread is returned by exa_last_error().
+ *     A failed call leaves the model valid.
+ *   - Concurrent callbacks on ONE model from different streams race on the
+ *     model's internal work buffers; serialize them (one stream per model).
+ */
+#ifndef EXA_H
+#define EXA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t exa_status;
+#define EXA_OK 0
+#define EXA_EINVAL 1   /* bad argument or malformed model description        */
+#define EXA_ENOMEM 2   /* device or host allocation failed                   */
+#define EXA_ECOMPILE 3 /* run-time compilation of the generated kernels failed */
+#define EXA_EHIP 4     /* a HIP runtime call failed                          */
+#define EXA_ESTATE 5   /* call not available for this handle (host-only model) */
+
+typedef void* exa_stream_t; /* a hipStream_t */
+
+typedef struct exa_model exa_model;
+typedef struct exa_batch exa_batch;
+
+/* ---- Model description ---------------------------------------------------
+ *
+ * Expression tree of one pattern (Sec. 4), as a post-order node list: the
+ * children of node i have positions < i and the root is the last node.
+ * Node operators (Sec. 4.2; registered functions of Sec. 7.1.3):
+ */
+#define EXA_OP_CONST 0  /* literal value val[i]                               */
+#define EXA_OP_DATA 1   /* float data column a[i] at the current data point   */
+#define EXA_OP_VAR 2    /* x[idx],   idx = icol[a[i]][k] + off[i]  (a[i] >= 0)  */
+                        /*           idx = off[i]                   (a[i] == -1) */
+#define EXA_OP_PARAM 3  /* theta[idx], same index rule as EXA_OP_VAR          */
+#define EXA_OP_NEG 10
+#define EXA_OP_ABS2 11  /* u*u */
+#define EXA_OP_INV 12   /* 1/u */
+#define EXA_OP_SQRT 13
+#define EXA_OP_EXP 14
+#define EXA_OP_LOG 15
+#define EXA_OP_SIN 16
+#define EXA_OP_COS 17
+#define EXA_OP_TAN 18
+#define EXA_OP_ATAN 19
+#define EXA_OP_SINH 20
+#define EXA_OP_COSH 21
+#define EXA_OP_TANH 22
+#define EXA_OP_LOG1P 23
+#define EXA_OP_EXPM1 24
+#define EXA_OP_ADD 40
+#define EXA_OP_SUB 41
+#define EXA_OP_MUL 42
+#define EXA_OP_DIV 43
+#define EXA_OP_POW 44
+
+/* Pattern kinds (eq. simd): objective terms, base constraint block, and an
+ * augmentation adding one term per data point to a row of an earlier base
+ * block (Sec. 3.3.2, ConstraintAugmentation). */
+#define EXA_OBJ 0
+#define EXA_CON 1
+#define EXA_AUG 2
+
+#define EXA_MAX_PATTERNS 32
+#define EXA_MAX_COLS 8
+#define EXA_MAX_NODES 512
+
+typedef struct exa_pattern_desc {
+    int32_t kind;          /* EXA_OBJ / EXA_CON / EXA_AUG                      */
+    int32_t nnodes;        /* 1 .. EXA_MAX_NODES                               */
+    const int32_t* op;     /* host [nnodes] operator codes                     */
+    const int32_t* a;      /* host [nnodes] child 1 | data column | index col  */
+    const int32_t* b;      /* host [nnodes] child 2 of binary nodes, else -1   */
+    const int64_t* off;    /* host [nnodes] var/param index offset, else 0     */
+    const double* val;     /* host [nnodes] literal of EXA_OP_CONST, else 0    */
+    int64_t ndata;         /* number of data points (>= 0)                     */
+    int32_t n_icols;       /* integer data columns (<= EXA_MAX_COLS)           */
+    int32_t n_fcols;       /* float data columns (<= EXA_MAX_COLS)             */
+    const int32_t* const* icols; /* host [n_icols][ndata]                      */
+    const double* const* fcols;  /* host [n_fcols][ndata]                      */
+    int32_t target;        /* AUG: position of the target EXA_CON pattern,
+                              which must come earlier in the list; else -1    */
+    int32_t row_icol;      /* AUG: row within target block = icols[row_icol][k] */
+    int64_t row_off;       /* AUG:                          + row_off         */
+    const double* lcon;    /* CON: host [ndata] lower bounds (NULL: 0)         */
+    const double* ucon;    /* CON: host [ndata] upper bounds (NULL: 0)         */
+} exa_pattern_desc;
+
+typedef struct exa_options {
+    int32_t host_only; /* 1: analyse only (dims, bounds, structure); no device
+                          memory, no kernel compilation; callbacks then return
+                          EXA_ESTATE                                           */
+    int32_t block;     /* threads per workgroup: 64, 128, 256 (default), 512  */
+    int32_t epl;       /* data points per lane per tile: 1..16 (default 4)    */
+    int32_t reserved[5];
+} exa_options;
+
+/* ---- Library ------------------------------------------------------------ */
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* exa_last_error(void);
+/* Library version string. */
+const char* exa_version(void);
+
+/* ---- Model lifetime (Sec. 3.1 ExaCore -> Sec. 3.2 ExaModel) -------------
+ *
+ * exa_create validates the description, applies the build-time
+ * simplification table (Sec. 7.1.2), finds each pattern's sparsity structure
+ * by the probe of Sec. 5.2 (unique variable references in first-visit
+ * order; unique unordered variable pairs in second-order emission order,
+ * lower triangle), lays out the outputs with the offsets and strides of
+ * Sec. 3.4 / Sec. 5.3.2, builds the sorted reduction maps of Sec. 7.2.3 and
+ * lowers every pattern to straight-line gfx950 code compiled at run time.
+ *
+ *   pats, npats     host array of pattern descriptions, in declaration order;
+ *                   the library copies everything it needs (the caller may
+ *                   free the description afterwards).
+ *   nvar            length of x; xl, xu host [nvar] bounds (NULL: -inf/+inf)
+ *   ntheta, theta   parameter vector (host [ntheta]; may be NULL if 0)
+ *   opt             NULL for defaults
+ *   out             receives the handle (owned by the caller, freed with
+ *                   exa_destroy).
+ * Errors: EXA_EINVAL for a malformed description (unknown operator, child
+ * index not below the node, column out of range, a variable, parameter or
+ * row index outside its range at some data point, AUG target not an earlier
+ * CON), EXA_ENOMEM, EXA_ECOMPILE, EXA_EHIP.
+ */
+exa_status exa_create(const exa_pattern_desc* pats, int32_t npats, int64_t nvar,
+                      const double* xl, const double* xu, int64_t ntheta,
+                      const double* theta, const exa_options* opt, exa_model** out);
+exa_status exa_destroy(exa_model* m);
+
+/* Sizes (Sec. 2.1.2 meta-information): n, m, nnzj, nnzh.  Any output may be
+ * NULL.  nnzj/nnzh count the partially compressed COO entries (Sec. 5.2.2). */
+exa_status exa_dims(const exa_model* m, int64_t* nvar, int64_t* ncon, int64_t* nnzj,
+                    int64_t* nnzh);
+/* Bounds into host arrays xl, xu [nvar] and gl, gu [ncon]; any may be NULL. */
+exa_status exa_bounds(const exa_model* m, double* xl, double* xu, double* gl, double* gu);
+
+/* Replace theta (device [ntheta]) without rebuilding the model (Sec. 2.2.3,
+ * updating and resolving).  The copy is enqueued on the stream. */
+exa_status exa_set_theta(exa_model* m, const double* theta, exa_stream_t stream);
+
+/* ---- Structure callbacks (Sec. 5.3.1) -----------------------------------
+ * Host arrays of nnzj (nnzh) entries.  Jacobian entry o1 + k*o1step + s of a
+ * pattern is (row of data point k, global index of its s-th unique variable
+ * reference).  Hessian entries are (max, min) of the two resolved indices.  */
+exa_status exa_jac_structure(const exa_model* m, int32_t* rows, int32_t* cols);
+exa_status exa_hess_structure(const exa_model* m, int32_t* rows, int32_t* cols);
+
+/* ---- Callbacks (Sec. 2.1.3); x, y, v, w and all outputs are device arrays --- */
+
+/* f(x): objective terms reduced in a fixed order (Sec. 7.2.3, buffer then
+ * reduce); *f is a device scalar. */
+exa_status exa_obj(exa_model* m, const double* x, double* f, exa_stream_t stream);
+/* grad f(x) into g [nvar] (dense; zero where no objective term depends on a
+ * variable).  Per-term contributions are merged by a fixed-order segmented
+ * reduction over a precomputed sort (Sec. 7.2.3 compress_to_dense). */
+exa_status exa_grad(exa_model* m, const double* x, double* g, exa_stream_t stream);
+/* g(x) into c [ncon]: base rows plus augmentation terms (eq. simd:con). */
+exa_status exa_cons(exa_model* m, const double* x, double* c, exa_stream_t stream);
+/* Jacobian values into vals [nnzj] (Sec. 5.3.2 jac_coord). */
+exa_status exa_jac_coord(exa_model* m, const double* x, double* vals, exa_stream_t stream);
+/* Lagrangian Hessian sigma*grad^2 f + sum_j y_j grad^2 g_j, lower triangle,
+ * into vals [nnzh] (Sec. 5.3.2 hess_coord).  y is device [ncon].  When two
+ * different references of one pattern resolve to the same variable, their
+ * cross entry holds twice the mixed derivative, so that summing duplicate
+ * entries gives the Hessian. */
+exa_status exa_hess_coord(exa_model* m, const double* x, const double* y, double obj_weight,
+                          double* vals, exa_stream_t stream);
+/* J(x) v into Jv [ncon]; v is device [nvar] (Sec. 2.1.3 jprod). */
+exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv,
+                     exa_stream_t stream);
+/* J(x)^T w into Jtw [nvar]; w is device [ncon] (Sec. 2.1.3 jtprod). */
+exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jtw,
+                      exa_stream_t stream);
+/* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod). */
+exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight,
+                     const double* v, double* Hv, exa_stream_t stream);
+
+/* Adjoint with respect to the parameters (extension of the parametric NLP of
+ * eq. nlp): theta_bar = (d grad_x L / d theta)^T w with
+ * grad_x L = sigma grad f + J^T y, i.e. for every pattern instance
+ * weight * sum_a w[col_a] d2T/dx_a dtheta_t added into theta_bar[t].
+ * w device [nvar], theta_bar device [ntheta] (overwritten). */
+exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, double obj_weight,
+                             const double* w, double* theta_bar, exa_stream_t stream);
+
+/* Introspection of the lowering (Sec. 7.2.1 compiler specialization).
+ * exa_generated_source copies the generated kernel source (NUL-terminated,
+ * truncated to cap bytes) into the host buffer buf and stores its full
+ * length in *len; buf may be NULL to query the length.
+ * exa_compile_check compiles that source for gfx950 without loading it (no
+ * GPU needed) and returns EXA_ECOMPILE with the compiler log on failure.
+ * Both work on host-only models. */
+exa_status exa_generated_source(const exa_model* m, char* buf, int64_t cap, int64_t* len);
+exa_status exa_compile_check(const exa_model* m);
+
+/* Layout of pattern p (declaration position): out8 = kind, ndata, o1step,
+ * o2step, number of unique parameter references, o0 (first row / term / aug
+ * entry), o1 (first Jacobian entry, or first gradient-buffer entry for an
+ * objective), o2 (first Hessian entry) -- the SIMDFunction offsets and strides
+ * of Sec. 3.4, 0-based. */
+exa_status exa_pattern_info(const exa_model* m, int32_t p, int64_t* out8);
+
+/* Callback counters (Sec. 3.2 NLPModels.Counters): out[0..8] = obj, grad,
+ * cons, jac, hess, jprod, jtprod, hprod, adjoint. */
+exa_status exa_counters(const exa_model* m, int64_t* out9);
+
+/* ---- Batched evaluation (Sec. 6.6.3 batch models, generalised) ----------
+ *
+ * B models that share every pattern tree (the same description up to data
+ * sizes and values: instances of one formulation) are evaluated together by
+ * ONE persistent kernel launch per callback set, replayed from a HIP graph.
+ * Instance sizes may differ.  The batch keeps references to the models,
+ * which must outlive it.
+ *
+ * Call arrays are the concatenation of the per-instance arrays in instance
+ * order; exa_batch_offsets gives, for i = 0..B, the start of instance i in
+ * x (nvar), y (ncon), jac vals (nnzj) and hess vals (nnzh):
+ * offsets[4*i + 0..3]; entry B holds the totals.
+ */
+typedef struct exa_batch_options {
+    int32_t autotune;  /* 1: time the candidate schedules and keep the fastest */
+    int32_t block;     /* fixed schedule when autotune == 0 (0: default)       */
+    int32_t epl;
+    int32_t grid;      /* persistent workgroups (0: chosen by the library)     */
+    int32_t use_graph; /* 1: replay the launch from a HIP graph                */
+    int32_t reserved[3];
+} exa_batch_options;
+
+#define EXA_CB_JAC 1u
+#define EXA_CB_HESS 2u
+
+exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch_options* opt,
+                            exa_batch** out);
+exa_status exa_batch_destroy(exa_batch* b);
+exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets /* [4*(B+1)] */);
+/* Evaluate the callbacks in mask (EXA_CB_JAC | EXA_CB_HESS) for every
+ * instance: x_cat, y_cat device inputs; jac_cat, hess_cat device outputs (a
+ * pointer may be NULL when its callback is not in the mask).  Instance i's
+ * slices are bit-identical to exa_jac_coord / exa_hess_coord on model i. */
+exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x_cat, const double* y_cat,
+                          double obj_weight, double* jac_cat, double* hess_cat,
+                          exa_stream_t stream);
+/* The schedule in use: block, epl, grid, tiles, and the autotuner's
+ * best time in nanoseconds (0 if not tuned). */
+exa_status exa_batch_schedule(const exa_batch* b, int64_t* out5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXA_H */

@@ -283,6 +283,28 @@ class OracleModel:
                     np.add.at(out, self._index(P, pkey, ks), wt * acc)
         return out
 
+    # ------------------------------------------------- values at sample points
+    def jac_block(self, i, ks, x, theta=None):
+        """Jacobian values (len(ks), o1step) of pattern i at data points ks."""
+        P = self.pats[i]
+        ks = np.asarray(ks, dtype=np.int64)
+        return self._taylor(P, ks, x, self._theta(theta)).g.copy()
+
+    def hess_block(self, i, ks, x, y, sigma=1.0, theta=None):
+        """Hessian values (len(ks), o2step) of pattern i at data points ks."""
+        P = self.pats[i]
+        ks = np.asarray(ks, dtype=np.int64)
+        tay = self._taylor(P, ks, x, self._theta(theta))
+        w = self._weights(P, ks, y, sigma)
+        out = np.zeros((ks.size, len(P.hslots)))
+        for s, (a, b) in enumerate(P.hslots):
+            v = w * tay.h[:, a, b]
+            if a != b:
+                same = (self._index(P, P.vslots[a], ks) == self._index(P, P.vslots[b], ks))
+                v = np.where(same, 2.0 * v, v)
+            out[:, s] = v
+        return out
+
     # ------------------------------------------------------- introspection
     def probe(self, i):
         """First/second-order visit lists and compressor maps of pattern i."""

@@ -1,0 +1,114 @@
+"""ctypes view of the C ABI declared in include/exa.h.
+
+This module only loads the shared library and declares the signatures; it
+fails loudly (ImportError) when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libexa.so")
+
+EXA_OK, EXA_EINVAL, EXA_ENOMEM, EXA_ECOMPILE, EXA_EHIP, EXA_ESTATE = range(6)
+KIND = {"obj": 0, "con": 1, "aug": 2}
+OPCODE = {
+    "const": 0, "data": 1, "var": 2, "param": 3,
+    "neg": 10, "abs2": 11, "inv": 12, "sqrt": 13, "exp": 14, "log": 15, "sin": 16,
+    "cos": 17, "tan": 18, "atan": 19, "sinh": 20, "cosh": 21, "tanh": 22, "log1p": 23,
+    "expm1": 24, "add": 40, "sub": 41, "mul": 42, "div": 43, "pow": 44,
+}
+CB_JAC, CB_HESS = 1, 2
+
+P_i32 = C.POINTER(C.c_int32)
+P_i64 = C.POINTER(C.c_int64)
+P_f64 = C.POINTER(C.c_double)
+
+
+class PatternDesc(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("nnodes", C.c_int32),
+        ("op", P_i32), ("a", P_i32), ("b", P_i32), ("off", P_i64), ("val", P_f64),
+        ("ndata", C.c_int64), ("n_icols", C.c_int32), ("n_fcols", C.c_int32),
+        ("icols", C.POINTER(P_i32)), ("fcols", C.POINTER(P_f64)),
+        ("target", C.c_int32), ("row_icol", C.c_int32), ("row_off", C.c_int64),
+        ("lcon", P_f64), ("ucon", P_f64),
+    ]
+
+
+class Options(C.Structure):
+    _fields_ = [("host_only", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+class BatchOptions(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
+                ("grid", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class ExaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[exa status {code}] {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2608_16265_amd.build_lib`")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    sig = {
+        "exa_last_error": (C.c_char_p, []),
+        "exa_version": (C.c_char_p, []),
+        "exa_create": (C.c_int32, [C.POINTER(PatternDesc), C.c_int32, C.c_int64, P_f64, P_f64,
+                                   C.c_int64, P_f64, C.POINTER(Options), C.POINTER(vp)]),
+        "exa_destroy": (C.c_int32, [vp]),
+        "exa_dims": (C.c_int32, [vp, P_i64, P_i64, P_i64, P_i64]),
+        "exa_bounds": (C.c_int32, [vp, P_f64, P_f64, P_f64, P_f64]),
+        "exa_set_theta": (C.c_int32, [vp, vp, vp]),
+        "exa_jac_structure": (C.c_int32, [vp, P_i32, P_i32]),
+        "exa_hess_structure": (C.c_int32, [vp, P_i32, P_i32]),
+        "exa_obj": (C.c_int32, [vp, vp, vp, vp]),
+        "exa_grad": (C.c_int32, [vp, vp, vp, vp]),
+        "exa_cons": (C.c_int32, [vp, vp, vp, vp]),
+        "exa_jac_coord": (C.c_int32, [vp, vp, vp, vp]),
+        "exa_hess_coord": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp]),
+        "exa_jprod": (C.c_int32, [vp, vp, vp, vp, vp]),
+        "exa_jtprod": (C.c_int32, [vp, vp, vp, vp, vp]),
+        "exa_hprod": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
+        "exa_adjoint_theta": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
+        "exa_counters": (C.c_int32, [vp, P_i64]),
+        "exa_generated_source": (C.c_int32, [vp, C.c_char_p, C.c_int64, P_i64]),
+        "exa_compile_check": (C.c_int32, [vp]),
+        "exa_pattern_info": (C.c_int32, [vp, C.c_int32, P_i64]),
+        "exa_batch_create": (C.c_int32, [C.POINTER(vp), C.c_int32, C.POINTER(BatchOptions),
+                                         C.POINTER(vp)]),
+        "exa_batch_destroy": (C.c_int32, [vp]),
+        "exa_batch_offsets": (C.c_int32, [vp, P_i64]),
+        "exa_batch_eval": (C.c_int32, [vp, C.c_uint32, vp, vp, C.c_double, vp, vp, vp]),
+        "exa_batch_schedule": (C.c_int32, [vp, P_i64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def check(status: int):
+    if status != EXA_OK:
+        raise ExaError(status, LIB.exa_last_error().decode())
+
+
+def exported_symbols():
+    """Names of the C ABI entry points this binding declares."""
+    return ["exa_last_error", "exa_version", "exa_create", "exa_destroy", "exa_dims", "exa_bounds",
+            "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
+            "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
+            "exa_adjoint_theta", "exa_counters", "exa_generated_source", "exa_compile_check",
+            "exa_pattern_info", "exa_batch_create", "exa_batch_destroy",
+            "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule"]

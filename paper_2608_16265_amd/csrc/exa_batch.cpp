@@ -1,0 +1,318 @@
+// Batched evaluation of many instances of one formulation (Sec. 6.6.3 batch
+// models, generalised to instances of different sizes).
+//
+// All instances share the generated code; their data stays where each model
+// put it.  A tile list spans (instance, pattern, data range) for the
+// Jacobian and the Hessian together, ordered by decreasing estimated cost,
+// and ONE persistent launch of the combined kernel walks it (workgroup w takes
+// tiles w, w + grid, ...).  The launch is recorded once into a HIP graph and
+// replayed.  Tile size (data points per tile) and grid size are picked by
+// timing candidates on the first evaluation (autotuning); results do not
+// depend on the schedule because every data point is evaluated by the same
+// code and written to its own slice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "exa_internal.h"
+#include "exa_runtime.h"
+
+using namespace exa;
+
+struct exa_batch {
+    std::vector<exa_model*> models;
+    int B = 0;
+    int block = 256;
+    std::shared_ptr<Module> module;
+    DeviceState mem;                       // owns the tables below
+    ExaInstDev* inst = nullptr;
+    std::vector<int64_t> offsets;          // 4 * (B + 1): x, y, jac, hess
+    // schedule
+    bool autotune = true, use_graph = true, tuned = false;
+    int epl = 4;
+    int64_t grid = 0;
+    int64_t tuned_ns = 0;
+    // tile lists per mask value (1: jac, 2: hess, 3: both), for the current epl
+    ExaTile* tiles[4] = {};
+    int64_t ntiles[4] = {};
+    int tiles_epl = -1;
+    // graph for the last call signature
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    struct Key {
+        uint32_t mask;
+        const void *x, *y, *j, *h;
+        double sigma;
+        int epl;
+        int64_t grid;
+        bool operator==(const Key& o) const {
+            return mask == o.mask && x == o.x && y == o.y && j == o.j && h == o.h &&
+                   sigma == o.sigma && epl == o.epl && grid == o.grid;
+        }
+    } key{};
+    bool have_graph = false;
+    int cus = 256;
+
+    ~exa_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+// Estimated cost of one data point (in 8-byte words moved).
+int64_t point_cost(const Pattern& P, int mode) {
+    const int64_t loads = P.n_icols / 2 + P.n_fcols + P.o1step() + 1;
+    return loads + (mode == M_JAC ? P.o1step() : P.o2step());
+}
+
+void build_tiles(exa_batch& b, int epl) {
+    if (b.tiles_epl == epl) return;
+    for (int m = 1; m <= 3; ++m) {
+        std::vector<std::pair<int64_t, ExaTile>> all;
+        for (int i = 0; i < b.B; ++i) {
+            const Model& M = b.models[i]->impl;
+            const int64_t tp = (int64_t)b.block * epl;
+            if (m & EXA_CB_JAC)
+                for (auto& t : make_tiles(M, M_JAC, i, tp))
+                    all.emplace_back(t.count * point_cost(M.pats[t.pat], M_JAC), t);
+            if (m & EXA_CB_HESS)
+                for (auto t : make_tiles(M, M_HESS, i, tp)) {
+                    const int64_t c = t.count * point_cost(M.pats[t.pat], M_HESS);
+                    t.pat += EXA_MAX_PATTERNS;
+                    all.emplace_back(c, t);
+                }
+        }
+        // largest first, so the round-robin walk of the persistent grid
+        // approximates longest-processing-time-first scheduling
+        std::stable_sort(all.begin(), all.end(),
+                         [](const auto& a, const auto& c) { return a.first > c.first; });
+        std::vector<ExaTile> v;
+        v.reserve(all.size());
+        for (auto& e : all) v.push_back(e.second);
+        for (size_t i = 0; i < v.size(); ++i) v[i].slot = (int64_t)i;
+        if (b.tiles[m]) {
+            (void)hipFree(b.tiles[m]);
+            b.mem.allocs.erase(std::remove(b.mem.allocs.begin(), b.mem.allocs.end(), (void*)b.tiles[m]),
+                               b.mem.allocs.end());
+        }
+        b.tiles[m] = (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
+        b.ntiles[m] = (int64_t)v.size();
+    }
+    b.tiles_epl = epl;
+}
+
+void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j,
+            double* h, hipStream_t s) {
+    const int64_t nt = b.ntiles[mask];
+    if (nt == 0) return;
+    ExaCall c;
+    std::memset(&c, 0, sizeof c);
+    c.tiles = b.tiles[mask];
+    c.ntiles = nt;
+    c.inst = b.inst;
+    c.x = x;
+    c.y = y;
+    c.sigma = sigma;
+    c.out0 = j;
+    c.out1 = h;
+    c.persistent = 1;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(b.grid, nt));
+    void* args[] = {&c};
+    hip_check(hipModuleLaunchKernel(b.module->fn_jh, (unsigned)grid, 1, 1, (unsigned)b.block, 1, 1, 0, s,
+                                    args, nullptr),
+              "hipModuleLaunchKernel");
+}
+
+void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j,
+          double* h, hipStream_t s) {
+    const int epls[] = {1, 2, 4, 8, 16};
+    const int64_t grids[] = {b.cus * 2, b.cus * 4, b.cus * 8, b.cus * 16};
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    float best = 1e30f;
+    int best_epl = b.epl;
+    int64_t best_grid = b.grid;
+    for (int epl : epls) {
+        build_tiles(b, epl);
+        for (int64_t g : grids) {
+            b.grid = g;
+            launch(b, mask, x, y, sigma, j, h, s);  // warm
+            hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            const int reps = 3;
+            for (int r = 0; r < reps; ++r) launch(b, mask, x, y, sigma, j, h, s);
+            hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            ms /= reps;
+            if (ms < best) {
+                best = ms;
+                best_epl = epl;
+                best_grid = g;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b.epl = best_epl;
+    b.grid = best_grid;
+    b.tuned_ns = (int64_t)(best * 1e6);
+    build_tiles(b, b.epl);
+    b.tuned = true;
+}
+
+template <class F>
+exa_status guard(F&& f) {
+    try {
+        f();
+        set_last_error("");
+        return EXA_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return EXA_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return EXA_EINVAL;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch_options* opt,
+                            exa_batch** out) {
+    return guard([&] {
+        if (!out) fail(EXA_EINVAL, "null output handle");
+        *out = nullptr;
+        if (B < 1 || !models) fail(EXA_EINVAL, "a batch needs at least one model");
+        std::unique_ptr<exa_batch> b(new exa_batch());
+        b->B = B;
+        b->models.assign(models, models + B);
+        for (int i = 0; i < B; ++i) {
+            if (!models[i]) fail(EXA_EINVAL, "null model in batch");
+            if (models[i]->impl.host_only || !models[i]->impl.dev)
+                fail(EXA_ESTATE, "batched models need a device");
+            if (models[i]->impl.signature != models[0]->impl.signature)
+                fail(EXA_EINVAL, "model " + std::to_string(i) +
+                                     " does not share the pattern trees of model 0");
+        }
+        if (opt) {
+            b->autotune = opt->autotune != 0;
+            if (opt->block) b->block = opt->block;
+            if (opt->epl) b->epl = opt->epl;
+            b->grid = opt->grid;
+            b->use_graph = opt->use_graph != 0;
+        }
+        if (b->block != 64 && b->block != 128 && b->block != 256 && b->block != 512)
+            fail(EXA_EINVAL, "block must be 64, 128, 256 or 512");
+        if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        b->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        if (b->grid <= 0) b->grid = (int64_t)b->cus * 8;
+        const Model& M0 = models[0]->impl;
+        b->module = M0.block == b->block ? M0.dev->module : compile_module(generate_source(M0, b->block));
+
+        std::vector<ExaInstDev> inst(B);
+        b->offsets.assign(4 * (B + 1), 0);
+        for (int i = 0; i < B; ++i) {
+            const Model& M = models[i]->impl;
+            inst[i] = M.dev->inst_host;
+            std::memset(inst[i].off, 0, sizeof inst[i].off);
+            int64_t* o = &b->offsets[4 * i];
+            inst[i].off[EXA_OFF_X] = o[0];
+            inst[i].off[EXA_OFF_Y] = o[1];
+            inst[i].off[EXA_OFF_JAC] = o[2];
+            inst[i].off[EXA_OFF_HESS] = o[3];
+            o[4] = o[0] + M.nvar;
+            o[5] = o[1] + M.ncon;
+            o[6] = o[2] + M.nnzj;
+            o[7] = o[3] + M.nnzh;
+        }
+        b->inst = (ExaInstDev*)b->mem.upload(inst.data(), inst.size() * sizeof(ExaInstDev));
+        build_tiles(*b, b->epl);
+        hip_check(hipStreamCreate(&b->cap), "hipStreamCreate");
+        *out = b.release();
+    });
+}
+
+exa_status exa_batch_destroy(exa_batch* b) {
+    return guard([&] { delete b; });
+}
+
+exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets) {
+    return guard([&] {
+        if (!b || !offsets) fail(EXA_EINVAL, "null argument");
+        std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+    });
+}
+
+exa_status exa_batch_schedule(const exa_batch* b, int64_t* out5) {
+    return guard([&] {
+        if (!b || !out5) fail(EXA_EINVAL, "null argument");
+        out5[0] = b->block;
+        out5[1] = b->epl;
+        out5[2] = b->grid;
+        out5[3] = b->ntiles[3];
+        out5[4] = b->tuned_ns;
+    });
+}
+
+exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x, const double* y, double sigma,
+                          double* jac, double* hess, exa_stream_t stream) {
+    return guard([&] {
+        if (!b) fail(EXA_EINVAL, "null batch");
+        if (mask == 0 || mask > 3) fail(EXA_EINVAL, "mask must be EXA_CB_JAC, EXA_CB_HESS or both");
+        const int64_t* tot = &b->offsets[4 * b->B];
+        if (!x && tot[0]) fail(EXA_EINVAL, "null x");
+        if ((mask & EXA_CB_HESS) && !y && tot[1]) fail(EXA_EINVAL, "null y");
+        if ((mask & EXA_CB_JAC) && !jac && tot[2]) fail(EXA_EINVAL, "null jac output");
+        if ((mask & EXA_CB_HESS) && !hess && tot[3]) fail(EXA_EINVAL, "null hess output");
+        hipStream_t s = (hipStream_t)stream;
+        if (b->autotune && !b->tuned) {
+            tune(*b, mask, x, y, sigma, jac, hess, s);
+            b->have_graph = false;
+        }
+        build_tiles(*b, b->epl);
+        if (!b->use_graph) {
+            launch(*b, mask, x, y, sigma, jac, hess, s);
+            return;
+        }
+        exa_batch::Key k{mask, x, y, jac, hess, sigma, b->epl, b->grid};
+        if (!b->have_graph || !(k == b->key)) {
+            if (b->exec) (void)hipGraphExecDestroy(b->exec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            try {
+                launch(*b, mask, x, y, sigma, jac, hess, b->cap);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(b->cap, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            hip_check(hipStreamEndCapture(b->cap, &b->graph), "hipStreamEndCapture");
+            hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            b->key = k;
+            b->have_graph = true;
+        }
+        hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+    });
+}
+
+}  // extern "C"

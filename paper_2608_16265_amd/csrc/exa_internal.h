@@ -1,0 +1,196 @@
+// Internal declarations of the evaluator library (not part of the C ABI).
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/exa.h"
+
+namespace exa {
+
+// ---------------------------------------------------------------------------
+// Errors: thrown inside the library, turned into exa_status at the ABI.
+struct Error : std::runtime_error {
+    exa_status code;
+    Error(exa_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] void fail(exa_status code, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// Device-side layout.  The same text defines the structs for the host
+// compiler and, stringified, for the run-time compiled kernels, so the two
+// layouts cannot drift apart.
+// Index into ExaInstDev::off: where an instance's slice starts in each of
+// the arrays a call reads or writes.
+#define EXA_OFF_ROWS 0    /* constraint rows (ncon)                          */
+#define EXA_OFF_AUG 1     /* augmentation term buffer (naug)                 */
+#define EXA_OFF_JAC 2     /* Jacobian values (nnzj)                          */
+#define EXA_OFF_HESS 3    /* Hessian values (nnzh)                           */
+#define EXA_OFF_PAR 4     /* parameter-adjoint buffer (nnzp)                 */
+#define EXA_OFF_TILE 5    /* per-tile partial sums of the objective          */
+#define EXA_OFF_X 6       /* x and v/w vectors (nvar)                        */
+#define EXA_OFF_Y 7       /* y (ncon)                                        */
+#define EXA_OFF_FO_OBJ 8  /* first-order buffer, objective part (nnzg)       */
+#define EXA_OFF_FO_CON 9  /* first-order buffer, constraint part (nnzj)      */
+#define EXA_NOFF 12
+
+#define EXA_DEVICE_STRUCTS                                                       \
+    struct ExaPatDev {                                                           \
+        const int* ic[8];                                                        \
+        const double* fc[8];                                                     \
+        long long ndata;                                                         \
+        long long o0;                                                            \
+        long long o1;                                                            \
+        long long o2;                                                            \
+        long long op;                                                            \
+        long long tgt0;                                                          \
+        long long row_off;                                                       \
+        int row_ic;                                                              \
+        int pad0;                                                                \
+    };                                                                           \
+    struct ExaInstDev {                                                          \
+        long long off[12];                                                       \
+        const double* theta;                                                     \
+        long long pad1;                                                          \
+        struct ExaPatDev pat[32];                                                \
+    };                                                                           \
+    struct ExaTile {                                                             \
+        int pat;                                                                 \
+        int inst;                                                                \
+        long long start;                                                         \
+        long long count;                                                         \
+        long long slot;                                                          \
+    };                                                                           \
+    struct ExaCall {                                                             \
+        const struct ExaTile* tiles;                                             \
+        long long ntiles;                                                        \
+        long long per_xcd;                                                       \
+        const struct ExaInstDev* inst;                                           \
+        const double* x;                                                         \
+        const double* y;                                                         \
+        const double* v;                                                         \
+        double* out0;                                                            \
+        double* out1;                                                            \
+        double sigma;                                                            \
+        int persistent;                                                          \
+        int pad2;                                                                \
+    };
+
+EXA_DEVICE_STRUCTS
+
+#define EXA_STR2(...) #__VA_ARGS__
+#define EXA_STR(...) EXA_STR2(__VA_ARGS__)
+
+// ---------------------------------------------------------------------------
+// Host-side model.
+
+enum Mode : int {
+    M_OBJ = 0,    // objective terms -> per-tile partial sums
+    M_CONS = 1,   // constraint values (rows + aug buffer)
+    M_GRAD = 2,   // objective gradient contributions -> first-order buffer
+    M_JAC = 3,    // Jacobian values
+    M_HESS = 4,   // Lagrangian Hessian values
+    M_JPROD = 5,  // J v (rows + aug buffer)
+    M_JTPROD = 6, // w[row] * J -> first-order buffer (jac part)
+    M_HPROD = 7,  // local (w H) v -> first-order buffer
+    M_ADJ = 8,    // mixed partials -> parameter buffer
+    M_COUNT = 9
+};
+
+struct TNode {            // node of a simplified tree
+    int op = 0;
+    int a = -1, b = -1;   // children (positions in the node list)
+    int col = -1;         // data column (DATA) or index column (VAR/PARAM)
+    int64_t off = 0;      // index offset (VAR/PARAM)
+    double val = 0.0;     // literal (CONST)
+    int slot = -1;        // VAR: unique var slot; PARAM: unique param slot
+};
+
+struct RefKey {           // symbolic identity of a var/param reference
+    int col;
+    int64_t off;
+    bool operator==(const RefKey& o) const { return col == o.col && off == o.off; }
+};
+
+struct Pattern {
+    int kind = 0;
+    int index = 0;                    // declaration position
+    std::vector<TNode> nodes;         // simplified tree, post-order, root last
+    int64_t ndata = 0;
+    int n_icols = 0, n_fcols = 0;
+    std::vector<std::vector<int32_t>> icols;   // host copies (index columns)
+    std::vector<const double*> fcols_src;      // caller's float columns (create only)
+    std::vector<RefKey> vslots;       // unique var refs, first-visit order
+    std::vector<RefKey> pslots;       // unique param refs
+    std::vector<std::pair<int, int>> hslots;   // unique pairs of var slots
+    // layout
+    int64_t o0 = 0;   // CON first row; OBJ first term; AUG first aug entry
+    int64_t o1 = 0;   // CON/AUG first jac entry; OBJ first grad-buffer entry
+    int64_t o2 = 0;   // first hess entry
+    int64_t op = 0;   // first param-buffer entry
+    int target = -1;
+    int row_icol = -1;
+    int64_t row_off = 0;
+    int64_t tgt0 = 0; // AUG: first row of the target block
+    std::vector<double> lcon, ucon;
+
+    int o1step() const { return (int)vslots.size(); }
+    int o2step() const { return (int)hslots.size(); }
+    int pstep() const { return (int)pslots.size(); }
+    int64_t row(int64_t k) const {
+        return kind == EXA_CON ? o0 + k : tgt0 + (int64_t)icols[row_icol][k] + row_off;
+    }
+    int64_t var_index(int s, int64_t k) const {
+        const RefKey& r = vslots[s];
+        return r.col < 0 ? r.off : (int64_t)icols[r.col][k] + r.off;
+    }
+    int64_t par_index(int s, int64_t k) const {
+        const RefKey& r = pslots[s];
+        return r.col < 0 ? r.off : (int64_t)icols[r.col][k] + r.off;
+    }
+};
+
+// Sorted reduction map (CSR): segment s sums buf[idx[ptr[s] .. ptr[s+1])].
+struct SegMap {
+    std::vector<int64_t> ptr, idx;
+    int64_t nseg() const { return ptr.empty() ? 0 : (int64_t)ptr.size() - 1; }
+};
+
+struct DeviceState;  // defined in exa_runtime.cpp
+
+struct Model {
+    int64_t nvar = 0, ncon = 0, ntheta = 0;
+    int64_t nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0;
+    std::vector<Pattern> pats;
+    std::vector<double> xl, xu, theta;
+    // reduction maps (positions in the first-order buffer: grad part first)
+    SegMap grad_map, jt_map, h_map, aug_map, par_map;
+    bool host_only = false;
+    int block = 256, epl = 4;
+    std::string signature;   // hash of the simplified trees (shared code)
+    std::atomic<int64_t> counters[9];
+    std::unique_ptr<DeviceState> dev;
+    Model();
+    ~Model();
+};
+
+// exa_model.cpp
+void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats);
+std::string pattern_signature(const Model& M);
+
+// exa_codegen.cpp
+std::string generate_source(const Model& M, int block);
+
+// exa_runtime.cpp
+void build_device(Model& M);
+
+}  // namespace exa
+
+struct exa_model {
+    exa::Model impl;
+};

@@ -1,0 +1,465 @@
+// Model build on the host: validation, build-time simplification (Sec. 7.1.2),
+// sparsity structure by the probe rule of Sec. 5.2, output offsets and strides
+// (Sec. 3.4, Sec. 5.3.2) and the sorted reduction maps (Sec. 7.2.3).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <sstream>
+
+#include "exa_internal.h"
+
+namespace exa {
+
+namespace {
+
+bool is_unary(int op) { return op >= EXA_OP_NEG && op <= EXA_OP_EXPM1; }
+bool is_binary(int op) { return op >= EXA_OP_ADD && op <= EXA_OP_POW; }
+bool is_leaf(int op) { return op >= EXA_OP_CONST && op <= EXA_OP_PARAM; }
+
+struct Builder {
+    std::vector<TNode> out;
+    const exa_pattern_desc& d;
+    explicit Builder(const exa_pattern_desc& dd) : d(dd) {}
+
+    int push(TNode n) {
+        out.push_back(n);
+        return (int)out.size() - 1;
+    }
+    int cnst(double v) {
+        TNode n;
+        n.op = EXA_OP_CONST;
+        n.val = v;
+        return push(n);
+    }
+    bool is_c(int i, double v) const { return out[i].op == EXA_OP_CONST && out[i].val == v; }
+
+    // Rebuild the subtree rooted at description node i, simplified bottom-up.
+    // Identities (Sec. 7.1.2): x+0, 0+x -> x; x*1, 1*x -> x; x/1 -> x;
+    // x^0 -> 1; x^1 -> x; x^2 -> abs2(x); x^-1 -> inv(x); 0*x, x*0 -> 0;
+    // 0/x -> 0.  Only literal constants trigger a rule; nothing is folded.
+    int rebuild(int i) {
+        const int op = d.op[i];
+        if (is_leaf(op)) {
+            TNode n;
+            n.op = op;
+            if (op == EXA_OP_CONST) n.val = d.val[i];
+            if (op == EXA_OP_DATA) n.col = d.a[i];
+            if (op == EXA_OP_VAR || op == EXA_OP_PARAM) {
+                n.col = d.a[i];
+                n.off = d.off[i];
+            }
+            return push(n);
+        }
+        if (is_unary(op)) {
+            int a = rebuild(d.a[i]);
+            TNode n;
+            n.op = op;
+            n.a = a;
+            return push(n);
+        }
+        int a = rebuild(d.a[i]);
+        int b = rebuild(d.b[i]);
+        switch (op) {
+            case EXA_OP_ADD:
+                if (is_c(b, 0.0)) return a;
+                if (is_c(a, 0.0)) return b;
+                break;
+            case EXA_OP_MUL:
+                if (is_c(a, 0.0) || is_c(b, 0.0)) return cnst(0.0);
+                if (is_c(b, 1.0)) return a;
+                if (is_c(a, 1.0)) return b;
+                break;
+            case EXA_OP_DIV:
+                if (is_c(a, 0.0)) return cnst(0.0);
+                if (is_c(b, 1.0)) return a;
+                break;
+            case EXA_OP_POW:
+                if (out[b].op == EXA_OP_CONST) {
+                    const double e = out[b].val;
+                    if (e == 0.0) return cnst(1.0);
+                    if (e == 1.0) return a;
+                    if (e == 2.0 || e == -1.0) {
+                        TNode n;
+                        n.op = e == 2.0 ? EXA_OP_ABS2 : EXA_OP_INV;
+                        n.a = a;
+                        return push(n);
+                    }
+                }
+                break;
+            default:
+                break;
+        }
+        TNode n;
+        n.op = op;
+        n.a = a;
+        n.b = b;
+        return push(n);
+    }
+};
+
+// Compact a node list so that only nodes reachable from `root` remain, in
+// post-order (orphans appear when a rule returns a child).
+std::vector<TNode> compact(const std::vector<TNode>& in, int root) {
+    std::vector<TNode> out;
+    std::function<int(int)> rec = [&](int i) -> int {
+        TNode n = in[i];
+        if (n.a >= 0) n.a = rec(in[i].a);
+        if (n.b >= 0) n.b = rec(in[i].b);
+        out.push_back(n);
+        return (int)out.size() - 1;
+    };
+    rec(root);
+    return out;
+}
+
+// ---- structure (Sec. 5.2) -------------------------------------------------
+struct Analysis {
+    const std::vector<TNode>& t;
+    std::vector<char> hv;                 // subtree contains a VAR
+    std::vector<std::vector<int>> leaves; // VAR leaves (node ids), DFS order
+    explicit Analysis(const std::vector<TNode>& tt) : t(tt), hv(tt.size(), 0), leaves(tt.size()) {
+        for (size_t i = 0; i < t.size(); ++i) {  // post-order: children first
+            const TNode& n = t[i];
+            if (n.op == EXA_OP_VAR) {
+                hv[i] = 1;
+                leaves[i].push_back((int)i);
+            }
+            if (n.a >= 0) {
+                hv[i] |= hv[n.a];
+                leaves[i].insert(leaves[i].end(), leaves[n.a].begin(), leaves[n.a].end());
+            }
+            if (n.b >= 0) {
+                hv[i] |= hv[n.b];
+                leaves[i].insert(leaves[i].end(), leaves[n.b].begin(), leaves[n.b].end());
+            }
+        }
+    }
+};
+
+// d2F/du2 of a unary operator identically zero?
+bool unary_affine(int op) { return op == EXA_OP_NEG; }
+
+// Binary with both sides carrying variables: nonzero F11, F12, F22.
+void binary_curv(int op, bool& f11, bool& f12, bool& f22) {
+    f11 = f12 = f22 = false;
+    switch (op) {
+        case EXA_OP_MUL: f12 = true; break;
+        case EXA_OP_DIV: f12 = f22 = true; break;
+        case EXA_OP_POW: f11 = f12 = f22 = true; break;
+        default: break;  // ADD, SUB: affine
+    }
+}
+
+// Binary with one variable-free side, as a map of the other side: affine?
+// (Sec. 7.2.2, FirstFixed / SecondFixed.)
+bool one_sided_affine(int op, bool var_left) {
+    if (op == EXA_OP_ADD || op == EXA_OP_SUB || op == EXA_OP_MUL) return true;
+    if (op == EXA_OP_DIV) return var_left;  // u/c yes, c/u no
+    return false;                           // u^c, c^u
+}
+
+int find_or_add(std::vector<RefKey>& v, RefKey k) {
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i] == k) return (int)i;
+    v.push_back(k);
+    return (int)v.size() - 1;
+}
+
+void analyse_structure(Pattern& P) {
+    const auto& t = P.nodes;
+    const int root = (int)t.size() - 1;
+    // first-order visits: left-to-right depth-first walk (Sec. 5.2.1)
+    std::function<void(int)> fo = [&](int i) {
+        const TNode& n = t[i];
+        if (n.op == EXA_OP_VAR) {
+            P.nodes[i].slot = find_or_add(P.vslots, RefKey{n.col, n.off});
+            return;
+        }
+        if (n.op == EXA_OP_PARAM) {
+            P.nodes[i].slot = find_or_add(P.pslots, RefKey{n.col, n.off});
+            return;
+        }
+        if (n.a >= 0) fo(n.a);
+        if (n.b >= 0) fo(n.b);
+    };
+    fo(root);
+
+    // second-order emission: a second adjoint is structurally zero until an
+    // ancestor with curvature is met (Sec. 5.1.3, Sec. 7.2.2).
+    Analysis A(t);
+    std::vector<std::pair<int, int>>& H = P.hslots;
+    auto emit = [&](int sa, int sb) {
+        const int lo = std::min(sa, sb), hi = std::max(sa, sb);
+        for (auto& p : H)
+            if (std::min(p.first, p.second) == lo && std::max(p.first, p.second) == hi) return;
+        H.emplace_back(sa, sb);
+    };
+    std::function<void(int, bool)> rec = [&](int i, bool nl) {
+        const TNode& n = t[i];
+        if (n.op == EXA_OP_VAR) {
+            if (nl) emit(n.slot, n.slot);
+            return;
+        }
+        if (is_leaf(n.op)) return;
+        if (is_unary(n.op)) {
+            rec(n.a, nl || !unary_affine(n.op));
+            return;
+        }
+        const bool hu = A.hv[n.a], hw = A.hv[n.b];
+        if (hu && hw) {
+            bool f11, f12, f22;
+            binary_curv(n.op, f11, f12, f22);
+            rec(n.a, nl || f11);
+            rec(n.b, nl || f22);
+            if (nl || f12)
+                for (int lu : A.leaves[n.a])
+                    for (int lw : A.leaves[n.b]) emit(t[lu].slot, t[lw].slot);
+        } else if (hu) {
+            rec(n.a, nl || !one_sided_affine(n.op, true));
+        } else if (hw) {
+            rec(n.b, nl || !one_sided_affine(n.op, false));
+        }
+    };
+    rec(root, false);
+}
+
+void validate_desc(const exa_pattern_desc& d, int p, int npats, const exa_pattern_desc* all) {
+    auto bad = [&](const std::string& m) {
+        fail(EXA_EINVAL, "pattern " + std::to_string(p) + ": " + m);
+    };
+    if (d.kind != EXA_OBJ && d.kind != EXA_CON && d.kind != EXA_AUG) bad("unknown kind");
+    if (d.nnodes < 1 || d.nnodes > EXA_MAX_NODES) bad("node count out of range");
+    if (!d.op || !d.a || !d.b) bad("missing node arrays");
+    if (d.ndata < 0) bad("negative ndata");
+    if (d.n_icols < 0 || d.n_icols > EXA_MAX_COLS || d.n_fcols < 0 || d.n_fcols > EXA_MAX_COLS)
+        bad("too many data columns");
+    if (d.ndata > 0) {
+        for (int c = 0; c < d.n_icols; ++c)
+            if (!d.icols || !d.icols[c]) bad("missing integer column");
+        for (int c = 0; c < d.n_fcols; ++c)
+            if (!d.fcols || !d.fcols[c]) bad("missing float column");
+    }
+    for (int i = 0; i < d.nnodes; ++i) {
+        const int op = d.op[i];
+        if (is_leaf(op)) {
+            if (op == EXA_OP_DATA && (d.a[i] < 0 || d.a[i] >= d.n_fcols))
+                bad("data node " + std::to_string(i) + " names a missing float column");
+            if ((op == EXA_OP_VAR || op == EXA_OP_PARAM) && (d.a[i] < -1 || d.a[i] >= d.n_icols))
+                bad("index node " + std::to_string(i) + " names a missing integer column");
+            if ((op == EXA_OP_VAR || op == EXA_OP_PARAM) && !d.off) bad("missing offsets");
+            if (op == EXA_OP_CONST && !d.val) bad("missing literals");
+        } else if (is_unary(op)) {
+            if (d.a[i] < 0 || d.a[i] >= i) bad("child of node " + std::to_string(i) + " is not below it");
+        } else if (is_binary(op)) {
+            if (d.a[i] < 0 || d.a[i] >= i || d.b[i] < 0 || d.b[i] >= i)
+                bad("child of node " + std::to_string(i) + " is not below it");
+        } else {
+            bad("unknown operator " + std::to_string(op) + " at node " + std::to_string(i));
+        }
+    }
+    if (d.kind == EXA_AUG) {
+        if (d.target < 0 || d.target >= p || all[d.target].kind != EXA_CON)
+            bad("augmentation target must be an earlier constraint pattern");
+        if (d.row_icol < 0 || d.row_icol >= d.n_icols) bad("augmentation row column missing");
+    }
+    (void)npats;
+}
+
+void build_map(SegMap& M, int64_t nseg, const std::vector<std::pair<int64_t, int64_t>>& tp) {
+    // tp: (target segment, buffer position), already in ascending position order
+    M.ptr.assign(nseg + 1, 0);
+    for (auto& e : tp) M.ptr[e.first + 1]++;
+    for (int64_t s = 0; s < nseg; ++s) M.ptr[s + 1] += M.ptr[s];
+    M.idx.assign(tp.size(), 0);
+    std::vector<int64_t> fill(M.ptr.begin(), M.ptr.end() - 1);
+    for (auto& e : tp) M.idx[fill[e.first]++] = e.second;
+}
+
+}  // namespace
+
+void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
+    if (npats < 0 || npats > EXA_MAX_PATTERNS)
+        fail(EXA_EINVAL, "pattern count must be in 0.." + std::to_string(EXA_MAX_PATTERNS));
+    if (npats > 0 && !pats) fail(EXA_EINVAL, "null pattern array");
+    for (int p = 0; p < npats; ++p) validate_desc(pats[p], p, npats, pats);
+
+    M.pats.resize(npats);
+    for (int p = 0; p < npats; ++p) {
+        const exa_pattern_desc& d = pats[p];
+        Pattern& P = M.pats[p];
+        P.kind = d.kind;
+        P.index = p;
+        P.ndata = d.ndata;
+        P.n_icols = d.n_icols;
+        P.n_fcols = d.n_fcols;
+        Builder B(d);
+        int root = B.rebuild(d.nnodes - 1);
+        P.nodes = compact(B.out, root);
+        P.icols.resize(d.n_icols);
+        for (int c = 0; c < d.n_icols; ++c)
+            P.icols[c].assign(d.icols ? d.icols[c] : nullptr,
+                              d.icols ? d.icols[c] + d.ndata : nullptr);
+        P.fcols_src.resize(d.n_fcols);
+        for (int c = 0; c < d.n_fcols; ++c) P.fcols_src[c] = d.fcols ? d.fcols[c] : nullptr;
+        P.target = d.target;
+        P.row_icol = d.row_icol;
+        P.row_off = d.row_off;
+        if (d.kind == EXA_CON) {
+            P.lcon.assign(d.ndata, 0.0);
+            P.ucon.assign(d.ndata, 0.0);
+            if (d.lcon) std::copy(d.lcon, d.lcon + d.ndata, P.lcon.begin());
+            if (d.ucon) std::copy(d.ucon, d.ucon + d.ndata, P.ucon.begin());
+        }
+        analyse_structure(P);
+    }
+
+    // ---- offsets in declaration order (Sec. 3.1 running counts) ----------
+    int64_t ncon = 0, nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0;
+    for (auto& P : M.pats) {
+        P.o2 = nnzh;
+        nnzh += P.ndata * P.o2step();
+        if (P.kind == EXA_OBJ) {
+            P.o0 = nobj;
+            nobj += P.ndata;
+            P.o1 = nnzg;
+            nnzg += P.ndata * P.o1step();
+        } else {
+            if (P.kind == EXA_CON) {
+                P.o0 = ncon;
+                ncon += P.ndata;
+            } else {
+                P.o0 = naug;
+                naug += P.ndata;
+                P.tgt0 = M.pats[P.target].o0;
+            }
+            P.o1 = nnzj;
+            nnzj += P.ndata * P.o1step();
+        }
+        if (P.pstep() > 0 && P.o1step() > 0) {
+            P.op = nnzp;
+            nnzp += P.ndata * P.pstep();
+        }
+    }
+    M.ncon = ncon;
+    M.nnzj = nnzj;
+    M.nnzh = nnzh;
+    M.nnzg = nnzg;
+    M.naug = naug;
+    M.nnzp = nnzp;
+    M.nobj = nobj;
+    if (ncon >= INT32_MAX || M.nvar >= INT32_MAX)
+        fail(EXA_EINVAL, "row or variable count exceeds the int32 COO index range");
+
+    // ---- index validation at every data point -----------------------------
+    for (auto& P : M.pats) {
+        for (int s = 0; s < P.o1step(); ++s)
+            for (int64_t k = 0; k < P.ndata; ++k) {
+                int64_t g = P.var_index(s, k);
+                if (g < 0 || g >= M.nvar)
+                    fail(EXA_EINVAL, "pattern " + std::to_string(P.index) + ": variable index " +
+                                         std::to_string(g) + " out of range at data point " +
+                                         std::to_string(k));
+            }
+        for (int s = 0; s < P.pstep(); ++s)
+            for (int64_t k = 0; k < P.ndata; ++k) {
+                int64_t g = P.par_index(s, k);
+                if (g < 0 || g >= M.ntheta)
+                    fail(EXA_EINVAL, "pattern " + std::to_string(P.index) + ": parameter index " +
+                                         std::to_string(g) + " out of range at data point " +
+                                         std::to_string(k));
+            }
+        if (P.kind == EXA_AUG) {
+            const int64_t nrows = M.pats[P.target].ndata;
+            for (int64_t k = 0; k < P.ndata; ++k) {
+                int64_t r = (int64_t)P.icols[P.row_icol][k] + P.row_off;
+                if (r < 0 || r >= nrows)
+                    fail(EXA_EINVAL, "pattern " + std::to_string(P.index) +
+                                         ": augmentation row out of range at data point " +
+                                         std::to_string(k));
+            }
+        }
+    }
+
+    // ---- reduction maps (Sec. 7.2.3): sorted by target, ascending positions
+    std::vector<std::pair<int64_t, int64_t>> g, jt, h, ag, pr;
+    for (auto& P : M.pats) {
+        const int st = P.o1step();
+        const bool curved = P.o2step() > 0;
+        for (int64_t k = 0; k < P.ndata; ++k)
+            for (int s = 0; s < st; ++s) {
+                const int64_t v = P.var_index(s, k);
+                if (P.kind == EXA_OBJ) {
+                    const int64_t pos = P.o1 + k * st + s;
+                    g.emplace_back(v, pos);
+                    if (curved) h.emplace_back(v, pos);
+                } else {
+                    const int64_t pos = nnzg + P.o1 + k * st + s;
+                    jt.emplace_back(v, pos);
+                    if (curved) h.emplace_back(v, pos);
+                }
+            }
+        if (P.kind == EXA_AUG)
+            for (int64_t k = 0; k < P.ndata; ++k) ag.emplace_back(P.row(k), P.o0 + k);
+        if (P.pstep() > 0 && P.o1step() > 0)
+            for (int64_t k = 0; k < P.ndata; ++k)
+                for (int t = 0; t < P.pstep(); ++t)
+                    pr.emplace_back(P.par_index(t, k), P.op + k * P.pstep() + t);
+    }
+    // h holds objective positions first, then constraint ones: both blocks are
+    // ascending, so the concatenation is ascending.
+    build_map(M.grad_map, M.nvar, g);
+    build_map(M.jt_map, M.nvar, jt);
+    build_map(M.h_map, M.nvar, h);
+    build_map(M.aug_map, M.ncon, ag);
+    build_map(M.par_map, M.ntheta, pr);
+    M.signature = pattern_signature(M);
+}
+
+std::string pattern_signature(const Model& M) {
+    std::ostringstream os;
+    os.precision(17);
+    for (auto& P : M.pats) {
+        os << "P" << P.kind << ":" << P.n_icols << "," << P.n_fcols << ":" << P.row_icol << ";";
+        for (auto& n : P.nodes)
+            os << n.op << "," << n.a << "," << n.b << "," << n.col << "," << n.off << "," << n.val
+               << "," << n.slot << ";";
+    }
+    return os.str();
+}
+
+}  // namespace exa
+
+// ---------------------------------------------------------------------------
+// Host-side structure callbacks (Sec. 5.3.1).
+using exa::Model;
+using exa::Pattern;
+
+namespace exa {
+void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols) {
+    for (const Pattern& P : M.pats) {
+        if (P.kind == EXA_OBJ) continue;
+        const int st = P.o1step();
+        for (int64_t k = 0; k < P.ndata; ++k) {
+            const int64_t r = P.row(k);
+            for (int s = 0; s < st; ++s) {
+                rows[P.o1 + k * st + s] = (int32_t)r;
+                cols[P.o1 + k * st + s] = (int32_t)P.var_index(s, k);
+            }
+        }
+    }
+}
+
+void hess_structure_host(const Model& M, int32_t* rows, int32_t* cols) {
+    for (const Pattern& P : M.pats) {
+        const int st = P.o2step();
+        for (int64_t k = 0; k < P.ndata; ++k)
+            for (int s = 0; s < st; ++s) {
+                const int64_t ga = P.var_index(P.hslots[s].first, k);
+                const int64_t gb = P.var_index(P.hslots[s].second, k);
+                rows[P.o2 + k * st + s] = (int32_t)std::max(ga, gb);
+                cols[P.o2 + k * st + s] = (int32_t)std::min(ga, gb);
+            }
+    }
+}
+}  // namespace exa

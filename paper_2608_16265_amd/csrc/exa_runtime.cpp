@@ -1,0 +1,558 @@
+// Device side of a model: run-time compilation of the generated kernels,
+// device copies of the data, tile lists, work buffers, and the C ABI.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+
+#include "exa_internal.h"
+#include "exa_kernels.h"
+#include "exa_runtime.h"
+
+namespace exa {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void fail(exa_status code, const std::string& msg) { throw Error(code, msg); }
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(EXA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Compiled modules, shared by every model whose generated source is identical.
+Module::~Module() {
+    if (mod) (void)hipModuleUnload(mod);
+}
+
+namespace {
+std::mutex g_mod_mu;
+std::map<std::string, std::weak_ptr<Module>> g_mods;
+
+std::string hex_hash(const std::string& s) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    char buf[32];
+    snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return buf;
+}
+}  // namespace
+
+std::vector<char> compile_code(const std::string& src) {
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "exa_generated.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS)
+        fail(EXA_ECOMPILE, "hiprtcCreateProgram failed");
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    size_t logsz = 0;
+    hiprtcGetProgramLogSize(prog, &logsz);
+    std::string log(logsz, '\0');
+    if (logsz) hiprtcGetProgramLog(prog, &log[0]);
+    if (rc != HIPRTC_SUCCESS) {
+        hiprtcDestroyProgram(&prog);
+        fail(EXA_ECOMPILE, "run-time compilation failed: " + log.substr(0, 4000));
+    }
+    size_t csz = 0;
+    hiprtcGetCodeSize(prog, &csz);
+    std::vector<char> code(csz);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    return code;
+}
+
+std::shared_ptr<Module> compile_module(const std::string& src) {
+    const std::string key = hex_hash(src) + ":" + std::to_string(src.size());
+    std::lock_guard<std::mutex> lk(g_mod_mu);
+    auto it = g_mods.find(key);
+    if (it != g_mods.end())
+        if (auto m = it->second.lock())
+            if (m->source == src) return m;
+    auto m = std::make_shared<Module>();
+    m->source = src;
+    m->code = compile_code(src);
+    hip_check(hipModuleLoadData(&m->mod, m->code.data()), "hipModuleLoadData");
+    for (int mode = 0; mode < M_COUNT; ++mode) {
+        hipFunction_t f = nullptr;
+        if (hipModuleGetFunction(&f, m->mod, kernel_name(mode).c_str()) != hipSuccess)
+            fail(EXA_ECOMPILE, "generated kernel missing: " + kernel_name(mode));
+        m->fn[mode] = f;
+    }
+    if (hipModuleGetFunction(&m->fn_jh, m->mod, "exa_k_jh") != hipSuccess)
+        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jh");
+    g_mods[key] = m;
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+DeviceState::~DeviceState() {
+    for (void* p : allocs) (void)hipFree(p);
+}
+
+void* DeviceState::alloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) fail(EXA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    allocs.push_back(p);
+    return p;
+}
+
+void* DeviceState::upload(const void* src, size_t bytes) {
+    void* p = alloc(bytes);
+    if (bytes) hip_check(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    return p;
+}
+
+std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts) {
+    std::vector<ExaTile> tiles;
+    for (size_t p = 0; p < M.pats.size(); ++p) {
+        const Pattern& P = M.pats[p];
+        if (!pattern_in_mode(P, mode)) continue;
+        for (int64_t s = 0; s < P.ndata; s += tile_pts) {
+            ExaTile t{};
+            t.pat = (int)p;
+            t.inst = inst;
+            t.start = s;
+            t.count = std::min(tile_pts, P.ndata - s);
+            t.slot = (int64_t)tiles.size();
+            tiles.push_back(t);
+        }
+    }
+    return tiles;
+}
+
+void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
+    std::memset(&inst, 0, sizeof inst);
+    for (size_t p = 0; p < M.pats.size(); ++p) {
+        const Pattern& P = M.pats[p];
+        ExaPatDev& d = inst.pat[p];
+        for (int c = 0; c < P.n_icols; ++c)
+            d.ic[c] = (const int*)D.upload(P.icols[c].data(), P.ndata * sizeof(int32_t));
+        for (int c = 0; c < P.n_fcols; ++c)
+            d.fc[c] = (const double*)D.upload(P.fcols_src[c], P.ndata * sizeof(double));
+        d.ndata = P.ndata;
+        d.o0 = P.o0;
+        d.o1 = P.o1;
+        d.o2 = P.o2;
+        d.op = P.op;
+        d.tgt0 = P.tgt0;
+        d.row_off = P.row_off;
+        d.row_ic = P.row_icol;
+    }
+}
+
+void build_device(Model& M) {
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    M.dev.reset(new DeviceState());
+    DeviceState& D = *M.dev;
+    D.device = dev;
+    const std::string src = generate_source(M, M.block);
+    D.module = compile_module(src);
+
+    D.theta = (double*)D.upload(M.theta.data(), M.theta.size() * sizeof(double));
+    ExaInstDev inst;
+    fill_patdev(M, D, inst);
+    inst.theta = D.theta;
+    inst.off[EXA_OFF_FO_CON] = M.nnzg;
+    D.inst_host = inst;
+    D.inst = (ExaInstDev*)D.upload(&inst, sizeof inst);
+
+    const int64_t tile_pts = (int64_t)M.block * M.epl;
+    for (int mode = 0; mode < M_COUNT; ++mode) {
+        auto tiles = make_tiles(M, mode, 0, tile_pts);
+        D.ntiles[mode] = (int64_t)tiles.size();
+        D.tiles[mode] = (ExaTile*)D.upload(tiles.data(), tiles.size() * sizeof(ExaTile));
+    }
+    D.fo = (double*)D.alloc((M.nnzg + M.nnzj) * sizeof(double));
+    D.aug = (double*)D.alloc(M.naug * sizeof(double));
+    D.par = (double*)D.alloc(M.nnzp * sizeof(double));
+    D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.ntiles[M_OBJ]) * sizeof(double));
+    auto up_map = [&](const SegMap& S, DevMap& d) {
+        d.ptr = (const int64_t*)D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
+        d.idx = (const int64_t*)D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
+        d.nseg = S.nseg();
+    };
+    up_map(M.grad_map, D.grad_map);
+    up_map(M.jt_map, D.jt_map);
+    up_map(M.h_map, D.h_map);
+    up_map(M.aug_map, D.aug_map);
+    up_map(M.par_map, D.par_map);
+    // the caller's float columns are not kept past create
+    for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
+}
+
+void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
+    DeviceState& D = *M.dev;
+    const int64_t nt = D.ntiles[mode];
+    if (nt == 0) return;
+    call.tiles = D.tiles[mode];
+    call.ntiles = nt;
+    call.per_xcd = (nt + 7) / 8;
+    call.inst = D.inst;
+    call.persistent = 0;
+    const int64_t grid = 8 * call.per_xcd;
+    void* args[] = {&call};
+    hip_check(hipModuleLaunchKernel(D.module->fn[mode], (unsigned)grid, 1, 1, (unsigned)M.block, 1, 1, 0,
+                                    s, args, nullptr),
+              "hipModuleLaunchKernel");
+}
+
+void segsum(const DevMap& m, const double* buf, double* out, int acc, hipStream_t s) {
+    hip_check(exa_launch_segsum(m.ptr, m.idx, buf, out, m.nseg, acc, s), "segmented reduction");
+}
+
+}  // namespace exa
+
+// ===========================================================================
+// C ABI
+using namespace exa;
+
+namespace {
+
+template <class F>
+exa_status guard(F&& f) {
+    try {
+        f();
+        set_last_error("");
+        return EXA_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return EXA_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return EXA_EINVAL;
+    }
+}
+
+Model& live(exa_model* m) {
+    if (!m) fail(EXA_EINVAL, "null model");
+    if (m->impl.host_only || !m->impl.dev)
+        fail(EXA_ESTATE, "model was created host-only; callbacks need a device");
+    return m->impl;
+}
+
+void need(const void* p, int64_t n, const char* what) {
+    if (n > 0 && !p) fail(EXA_EINVAL, std::string("null pointer: ") + what);
+}
+
+ExaCall blank_call() {
+    ExaCall c;
+    std::memset(&c, 0, sizeof c);
+    return c;
+}
+
+}  // namespace
+
+namespace exa {
+Model::Model() {
+    for (auto& c : counters) c.store(0);
+}
+Model::~Model() = default;
+}  // namespace exa
+
+extern "C" {
+
+const char* exa_last_error(void) { return exa::last_error(); }
+const char* exa_version(void) { return "exa-mi355x 0.1 (gfx950, fp64)"; }
+
+exa_status exa_create(const exa_pattern_desc* pats, int32_t npats, int64_t nvar, const double* xl,
+                      const double* xu, int64_t ntheta, const double* theta, const exa_options* opt,
+                      exa_model** out) {
+    return guard([&] {
+        if (!out) fail(EXA_EINVAL, "null output handle");
+        *out = nullptr;
+        if (nvar < 0 || ntheta < 0) fail(EXA_EINVAL, "negative size");
+        if (ntheta > 0 && !theta) fail(EXA_EINVAL, "null theta");
+        std::unique_ptr<exa_model> h(new exa_model());
+        Model& M = h->impl;
+        M.nvar = nvar;
+        M.ntheta = ntheta;
+        M.xl.assign(nvar, -HUGE_VAL);
+        M.xu.assign(nvar, HUGE_VAL);
+        if (xl) std::copy(xl, xl + nvar, M.xl.begin());
+        if (xu) std::copy(xu, xu + nvar, M.xu.begin());
+        M.theta.assign(theta ? theta : nullptr, theta ? theta + ntheta : nullptr);
+        if (opt) {
+            M.host_only = opt->host_only != 0;
+            if (opt->block) M.block = opt->block;
+            if (opt->epl) M.epl = opt->epl;
+        }
+        if (M.block != 64 && M.block != 128 && M.block != 256 && M.block != 512)
+            fail(EXA_EINVAL, "block must be 64, 128, 256 or 512");
+        if (M.epl < 1 || M.epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
+        build_host(M, pats, npats);
+        if (!M.host_only) build_device(M);
+        *out = h.release();
+    });
+}
+
+exa_status exa_destroy(exa_model* m) {
+    return guard([&] { delete m; });
+}
+
+exa_status exa_dims(const exa_model* m, int64_t* nvar, int64_t* ncon, int64_t* nnzj, int64_t* nnzh) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        if (nvar) *nvar = m->impl.nvar;
+        if (ncon) *ncon = m->impl.ncon;
+        if (nnzj) *nnzj = m->impl.nnzj;
+        if (nnzh) *nnzh = m->impl.nnzh;
+    });
+}
+
+exa_status exa_bounds(const exa_model* m, double* xl, double* xu, double* gl, double* gu) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        const Model& M = m->impl;
+        if (xl) std::copy(M.xl.begin(), M.xl.end(), xl);
+        if (xu) std::copy(M.xu.begin(), M.xu.end(), xu);
+        for (auto& P : M.pats) {
+            if (P.kind != EXA_CON) continue;
+            if (gl) std::copy(P.lcon.begin(), P.lcon.end(), gl + P.o0);
+            if (gu) std::copy(P.ucon.begin(), P.ucon.end(), gu + P.o0);
+        }
+    });
+}
+
+exa_status exa_set_theta(exa_model* m, const double* theta, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(theta, M.ntheta, "theta");
+        if (M.ntheta)
+            hip_check(hipMemcpyAsync(M.dev->theta, theta, M.ntheta * sizeof(double),
+                                     hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                      "hipMemcpyAsync");
+    });
+}
+
+exa_status exa_jac_structure(const exa_model* m, int32_t* rows, int32_t* cols) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        need(rows, m->impl.nnzj, "rows");
+        need(cols, m->impl.nnzj, "cols");
+        jac_structure_host(m->impl, rows, cols);
+    });
+}
+
+exa_status exa_hess_structure(const exa_model* m, int32_t* rows, int32_t* cols) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        need(rows, m->impl.nnzh, "rows");
+        need(cols, m->impl.nnzh, "cols");
+        hess_structure_host(m->impl, rows, cols);
+    });
+}
+
+exa_status exa_obj(exa_model* m, const double* x, double* f, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(f, 1, "f");
+        hipStream_t s = (hipStream_t)stream;
+        DeviceState& D = *M.dev;
+        if (D.ntiles[M_OBJ] == 0) {
+            hip_check(exa_launch_fill(f, 1, 0.0, s), "fill");
+        } else {
+            ExaCall c = blank_call();
+            c.x = x;
+            c.out0 = D.tilesum;
+            launch_mode(M, M_OBJ, c, s);
+            hip_check(exa_launch_sum(D.tilesum, D.ntiles[M_OBJ], f, s), "objective reduction");
+        }
+        M.counters[0]++;
+    });
+}
+
+exa_status exa_grad(exa_model* m, const double* x, double* g, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(g, M.nvar, "g");
+        hipStream_t s = (hipStream_t)stream;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.out0 = M.dev->fo;
+        launch_mode(M, M_GRAD, c, s);
+        segsum(M.dev->grad_map, M.dev->fo, g, 0, s);
+        M.counters[1]++;
+    });
+}
+
+exa_status exa_cons(exa_model* m, const double* x, double* cv, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(cv, M.ncon, "c");
+        hipStream_t s = (hipStream_t)stream;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.out0 = cv;
+        c.out1 = M.dev->aug;
+        launch_mode(M, M_CONS, c, s);
+        if (M.naug) segsum(M.dev->aug_map, M.dev->aug, cv, 1, s);
+        M.counters[2]++;
+    });
+}
+
+exa_status exa_jac_coord(exa_model* m, const double* x, double* vals, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(vals, M.nnzj, "vals");
+        ExaCall c = blank_call();
+        c.x = x;
+        c.out0 = vals;
+        launch_mode(M, M_JAC, c, (hipStream_t)stream);
+        M.counters[3]++;
+    });
+}
+
+exa_status exa_hess_coord(exa_model* m, const double* x, const double* y, double obj_weight,
+                          double* vals, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(y, M.ncon, "y");
+        need(vals, M.nnzh, "vals");
+        ExaCall c = blank_call();
+        c.x = x;
+        c.y = y;
+        c.sigma = obj_weight;
+        c.out0 = vals;
+        launch_mode(M, M_HESS, c, (hipStream_t)stream);
+        M.counters[4]++;
+    });
+}
+
+exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(v, M.nvar, "v");
+        need(Jv, M.ncon, "Jv");
+        hipStream_t s = (hipStream_t)stream;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.v = v;
+        c.out0 = Jv;
+        c.out1 = M.dev->aug;
+        launch_mode(M, M_JPROD, c, s);
+        if (M.naug) segsum(M.dev->aug_map, M.dev->aug, Jv, 1, s);
+        M.counters[5]++;
+    });
+}
+
+exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jtw, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(w, M.ncon, "w");
+        need(Jtw, M.nvar, "Jtw");
+        hipStream_t s = (hipStream_t)stream;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.y = w;
+        c.out0 = M.dev->fo;
+        launch_mode(M, M_JTPROD, c, s);
+        segsum(M.dev->jt_map, M.dev->fo, Jtw, 0, s);
+        M.counters[6]++;
+    });
+}
+
+exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight, const double* v,
+                     double* Hv, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(y, M.ncon, "y");
+        need(v, M.nvar, "v");
+        need(Hv, M.nvar, "Hv");
+        hipStream_t s = (hipStream_t)stream;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.y = y;
+        c.v = v;
+        c.sigma = obj_weight;
+        c.out0 = M.dev->fo;
+        launch_mode(M, M_HPROD, c, s);
+        segsum(M.dev->h_map, M.dev->fo, Hv, 0, s);
+        M.counters[7]++;
+    });
+}
+
+exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, double obj_weight,
+                             const double* w, double* theta_bar, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(y, M.ncon, "y");
+        need(w, M.nvar, "w");
+        need(theta_bar, M.ntheta, "theta_bar");
+        hipStream_t s = (hipStream_t)stream;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.y = y;
+        c.v = w;
+        c.sigma = obj_weight;
+        c.out0 = M.dev->par;
+        launch_mode(M, M_ADJ, c, s);
+        segsum(M.dev->par_map, M.dev->par, theta_bar, 0, s);
+        M.counters[8]++;
+    });
+}
+
+exa_status exa_generated_source(const exa_model* m, char* buf, int64_t cap, int64_t* len) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        const std::string src = generate_source(m->impl, m->impl.block);
+        if (len) *len = (int64_t)src.size();
+        if (buf && cap > 0) {
+            const size_t n = std::min<size_t>((size_t)cap - 1, src.size());
+            std::memcpy(buf, src.data(), n);
+            buf[n] = '\0';
+        }
+    });
+}
+
+exa_status exa_compile_check(const exa_model* m) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        (void)compile_code(generate_source(m->impl, m->impl.block));
+    });
+}
+
+exa_status exa_pattern_info(const exa_model* m, int32_t p, int64_t* out8) {
+    return guard([&] {
+        if (!m || !out8) fail(EXA_EINVAL, "null argument");
+        if (p < 0 || p >= (int32_t)m->impl.pats.size()) fail(EXA_EINVAL, "pattern index out of range");
+        const Pattern& P = m->impl.pats[p];
+        const int64_t v[8] = {P.kind, P.ndata, P.o1step(), P.o2step(), P.pstep(), P.o0, P.o1, P.o2};
+        std::copy(v, v + 8, out8);
+    });
+}
+
+exa_status exa_counters(const exa_model* m, int64_t* out9) {
+    return guard([&] {
+        if (!m || !out9) fail(EXA_EINVAL, "null argument");
+        for (int i = 0; i < 9; ++i) out9[i] = m->impl.counters[i].load();
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Device state of a model and the helpers shared by the runtime and batching.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "exa_internal.h"
+
+namespace exa {
+
+struct Module {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn[M_COUNT] = {};
+    hipFunction_t fn_jh = nullptr;   // Jacobian + Hessian tiles in one launch
+    std::string source;
+    std::vector<char> code;
+    ~Module();
+};
+
+struct DevMap {
+    const int64_t* ptr = nullptr;
+    const int64_t* idx = nullptr;
+    int64_t nseg = 0;
+};
+
+struct DeviceState {
+    int device = 0;
+    std::shared_ptr<Module> module;
+    std::vector<void*> allocs;
+    double* theta = nullptr;
+    ExaInstDev* inst = nullptr;       // device copy of the single-instance table
+    ExaInstDev inst_host;             // host copy (device pointers), reused by batches
+    ExaTile* tiles[M_COUNT] = {};
+    int64_t ntiles[M_COUNT] = {};
+    double* fo = nullptr;             // first-order buffer: grad part, then jac part
+    double* aug = nullptr;
+    double* par = nullptr;
+    double* tilesum = nullptr;
+    DevMap grad_map, jt_map, h_map, aug_map, par_map;
+
+    void* alloc(size_t bytes);
+    void* upload(const void* src, size_t bytes);
+    ~DeviceState();
+};
+
+void hip_check(hipError_t e, const char* what);
+std::vector<char> compile_code(const std::string& src);
+std::shared_ptr<Module> compile_module(const std::string& src);
+std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts);
+bool pattern_in_mode(const Pattern& P, int mode);
+std::string kernel_name(int mode);
+int mode_lds_doubles(const Model& M, int mode, int block);
+void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);
+void hess_structure_host(const Model& M, int32_t* rows, int32_t* cols);
+const char* last_error();
+
+}  // namespace exa

@@ -1,0 +1,236 @@
+"""Python binding of the evaluator: argument marshalling only.
+
+Every callback runs in the HIP kernels of libexa.so; this module converts a
+model description (exa_modeling.Model) into the C descriptors, checks tensor
+arguments and forwards device pointers and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import LIB, PatternDesc, Options, check
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _Descriptors:
+    """C pattern descriptors plus the numpy arrays that keep them alive."""
+
+    def __init__(self, model):
+        self.keep: List = []
+        pats = model.patterns
+        self.arr = (PatternDesc * max(1, len(pats)))()
+        for i, p in enumerate(pats):
+            nodes = p.nodes()
+            icn = list(p.data.icols)
+            fcn = list(p.data.fcols)
+            op = np.array([_lib.OPCODE[n.op] for n in nodes], dtype=np.int32)
+            a = np.empty(len(nodes), dtype=np.int32)
+            b = np.empty(len(nodes), dtype=np.int32)
+            off = np.zeros(len(nodes), dtype=np.int64)
+            val = np.zeros(len(nodes), dtype=np.float64)
+            for j, n in enumerate(nodes):
+                a[j], b[j] = n.a, n.b
+                if n.op == "const":
+                    val[j] = n.value
+                elif n.op == "data":
+                    a[j] = fcn.index(n.col)
+                elif n.op in ("var", "param"):
+                    a[j] = -1 if n.col is None else icn.index(n.col)
+                    off[j] = n.off
+            icols = [np.ascontiguousarray(p.data.icols[c], dtype=np.int32) for c in icn]
+            fcols = [np.ascontiguousarray(p.data.fcols[c], dtype=np.float64) for c in fcn]
+            ic_ptrs = (C.POINTER(C.c_int32) * max(1, len(icols)))(*[_ptr(c, C.c_int32) for c in icols])
+            fc_ptrs = (C.POINTER(C.c_double) * max(1, len(fcols)))(*[_ptr(c, C.c_double) for c in fcols])
+            d = self.arr[i]
+            d.kind = _lib.KIND[p.kind]
+            d.nnodes = len(nodes)
+            d.op, d.a, d.b = _ptr(op, C.c_int32), _ptr(a, C.c_int32), _ptr(b, C.c_int32)
+            d.off, d.val = _ptr(off, C.c_int64), _ptr(val, C.c_double)
+            d.ndata = p.ndata
+            d.n_icols, d.n_fcols = len(icols), len(fcols)
+            d.icols, d.fcols = ic_ptrs, fc_ptrs
+            d.target = p.target
+            d.row_icol = icn.index(p.row_col) if p.kind == "aug" else -1
+            d.row_off = p.row_off
+            keep = [op, a, b, off, val, icols, fcols, ic_ptrs, fc_ptrs]
+            if p.kind == "con":
+                lc = np.ascontiguousarray(p.lcon, dtype=np.float64)
+                uc = np.ascontiguousarray(p.ucon, dtype=np.float64)
+                d.lcon, d.ucon = _ptr(lc, C.c_double), _ptr(uc, C.c_double)
+                keep += [lc, uc]
+            self.keep.append(keep)
+        self.n = len(pats)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class ExaModel:
+    """A compiled model on the current HIP device (Sec. 3.2 ExaModel)."""
+
+    def __init__(self, model, *, host_only: bool = False, block: int = 256, epl: int = 4):
+        self.description = model
+        desc = _Descriptors(model)
+        xl = np.ascontiguousarray(model.xl, dtype=np.float64)
+        xu = np.ascontiguousarray(model.xu, dtype=np.float64)
+        th = np.ascontiguousarray(model.theta, dtype=np.float64)
+        opt = Options(1 if host_only else 0, block, epl)
+        h = C.c_void_p()
+        check(LIB.exa_create(desc.arr, desc.n, model.nvar, _ptr(xl, C.c_double), _ptr(xu, C.c_double),
+                             model.ntheta, _ptr(th, C.c_double) if th.size else None,
+                             C.byref(opt), C.byref(h)))
+        self._h = h
+        self.host_only = host_only
+        n, m, nj, nh = (C.c_int64() for _ in range(4))
+        check(LIB.exa_dims(h, C.byref(n), C.byref(m), C.byref(nj), C.byref(nh)))
+        self.nvar, self.ncon, self.nnzj, self.nnzh = n.value, m.value, nj.value, nh.value
+        self.ntheta = model.ntheta
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            check(LIB.exa_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- meta ---------------------------------------------------------------
+    def bounds(self):
+        xl, xu = np.empty(self.nvar), np.empty(self.nvar)
+        gl, gu = np.empty(self.ncon), np.empty(self.ncon)
+        check(LIB.exa_bounds(self._h, _ptr(xl, C.c_double), _ptr(xu, C.c_double),
+                             _ptr(gl, C.c_double), _ptr(gu, C.c_double)))
+        return xl, xu, gl, gu
+
+    def jac_structure(self):
+        r = np.empty(self.nnzj, dtype=np.int32)
+        c = np.empty(self.nnzj, dtype=np.int32)
+        check(LIB.exa_jac_structure(self._h, _ptr(r, C.c_int32), _ptr(c, C.c_int32)))
+        return r, c
+
+    def hess_structure(self):
+        r = np.empty(self.nnzh, dtype=np.int32)
+        c = np.empty(self.nnzh, dtype=np.int32)
+        check(LIB.exa_hess_structure(self._h, _ptr(r, C.c_int32), _ptr(c, C.c_int32)))
+        return r, c
+
+    def generated_source(self) -> str:
+        n = C.c_int64()
+        check(LIB.exa_generated_source(self._h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value + 1)
+        check(LIB.exa_generated_source(self._h, buf, n.value + 1, C.byref(n)))
+        return buf.value.decode()
+
+    def compile_check(self):
+        """Compile the generated kernels for gfx950 (no GPU needed)."""
+        check(LIB.exa_compile_check(self._h))
+
+    def pattern_info(self, p: int) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        check(LIB.exa_pattern_info(self._h, p, _ptr(out, C.c_int64)))
+        keys = ["kind", "ndata", "o1step", "o2step", "pstep", "o0", "o1", "o2"]
+        return dict(zip(keys, out.tolist()))
+
+    def counters(self):
+        out = np.zeros(9, dtype=np.int64)
+        check(LIB.exa_counters(self._h, _ptr(out, C.c_int64)))
+        return dict(zip(["obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod", "adjoint"],
+                        out.tolist()))
+
+    # -- tensor plumbing ------------------------------------------------------
+    @staticmethod
+    def _dev(t, n, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float64 tensor with {n} entries")
+        return C.c_void_p(t.data_ptr())
+
+    def _out(self, out, n, ref, name):
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=ref.device)
+        self._dev(out, n, name)
+        return out
+
+    # -- callbacks (Sec. 2.1.3) ---------------------------------------------
+    def obj(self, x, out=None):
+        """Device scalar tensor holding f(x)."""
+        px = self._dev(x, self.nvar, "x")
+        out = self._out(out, 1, x, "out")
+        check(LIB.exa_obj(self._h, px, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def grad(self, x, out=None):
+        px = self._dev(x, self.nvar, "x")
+        out = self._out(out, self.nvar, x, "out")
+        check(LIB.exa_grad(self._h, px, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def cons(self, x, out=None):
+        px = self._dev(x, self.nvar, "x")
+        out = self._out(out, self.ncon, x, "out")
+        check(LIB.exa_cons(self._h, px, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def jac_coord(self, x, out=None):
+        px = self._dev(x, self.nvar, "x")
+        out = self._out(out, self.nnzj, x, "out")
+        check(LIB.exa_jac_coord(self._h, px, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def hess_coord(self, x, y, obj_weight=1.0, out=None):
+        px = self._dev(x, self.nvar, "x")
+        py = self._dev(y, self.ncon, "y")
+        out = self._out(out, self.nnzh, x, "out")
+        check(LIB.exa_hess_coord(self._h, px, py, float(obj_weight), C.c_void_p(out.data_ptr()),
+                                 _stream()))
+        return out
+
+    def jprod(self, x, v, out=None):
+        px, pv = self._dev(x, self.nvar, "x"), self._dev(v, self.nvar, "v")
+        out = self._out(out, self.ncon, x, "out")
+        check(LIB.exa_jprod(self._h, px, pv, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def jtprod(self, x, w, out=None):
+        px, pw = self._dev(x, self.nvar, "x"), self._dev(w, self.ncon, "w")
+        out = self._out(out, self.nvar, x, "out")
+        check(LIB.exa_jtprod(self._h, px, pw, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def hprod(self, x, y, obj_weight, v, out=None):
+        px, py = self._dev(x, self.nvar, "x"), self._dev(y, self.ncon, "y")
+        pv = self._dev(v, self.nvar, "v")
+        out = self._out(out, self.nvar, x, "out")
+        check(LIB.exa_hprod(self._h, px, py, float(obj_weight), pv, C.c_void_p(out.data_ptr()),
+                            _stream()))
+        return out
+
+    def adjoint_theta(self, x, y, obj_weight, w, out=None):
+        px, py = self._dev(x, self.nvar, "x"), self._dev(y, self.ncon, "y")
+        pw = self._dev(w, self.nvar, "w")
+        out = self._out(out, self.ntheta, x, "out")
+        check(LIB.exa_adjoint_theta(self._h, px, py, float(obj_weight), pw,
+                                    C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def set_theta(self, theta):
+        pt = self._dev(theta, self.ntheta, "theta")
+        check(LIB.exa_set_theta(self._h, pt, _stream()))

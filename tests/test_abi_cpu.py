@@ -1,0 +1,157 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/exa.h declares, rejects malformed models with the documented
+status codes, computes the structure bit-exactly like the oracle (host-only
+models) and its generated kernels compile for gfx950."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from exa_modeling import DataSet, Model, exp
+from exa_modeling.generators import acopf, pde, rosenbrock
+from oracle import OracleModel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "exa.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:exa_status|const char\*)\s+(exa_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2608_16265_amd import _lib
+    names = _header_functions()
+    assert len(names) >= 20
+    lib = C.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in exa.h but not exported"
+    assert set(names) == set(_lib.exported_symbols())
+    assert b"gfx950" in _lib.LIB.exa_version()
+
+
+@pytest.mark.parametrize("make", [lambda: rosenbrock(7, 2), lambda: acopf(30, 0), lambda: pde(8, 3),
+                                  lambda: acopf(211, 4)],
+                         ids=["rosen7", "acopf30", "pde8", "acopf211"])
+def test_host_structure_matches_oracle(make):
+    from paper_2608_16265_amd import ExaModel
+    w = make()
+    em = ExaModel(w.model, host_only=True)
+    o = OracleModel(w.model)
+    assert (em.nvar, em.ncon, em.nnzj, em.nnzh) == o.dims()
+    for a, b in zip(em.jac_structure(), o.jac_structure()):
+        assert a.dtype == np.int32 and np.array_equal(a, b)
+    for a, b in zip(em.hess_structure(), o.hess_structure()):
+        assert np.array_equal(a, b)
+    xl, xu, gl, gu = em.bounds()
+    oxl, oxu, ogl, ogu = o.bounds()
+    assert np.array_equal(xl, oxl) and np.array_equal(xu, oxu)
+    assert np.array_equal(gl, ogl) and np.array_equal(gu, ogu)
+
+
+def test_structure_of_every_operator():
+    from paper_2608_16265_amd import ExaModel
+    from test_oracle_pins import op_zoo
+    w = op_zoo()
+    em = ExaModel(w.model, host_only=True)
+    o = OracleModel(w.model)
+    assert np.array_equal(em.hess_structure()[0], o.hess_structure()[0])
+    assert np.array_equal(em.hess_structure()[1], o.hess_structure()[1])
+    assert np.array_equal(em.jac_structure()[1], o.jac_structure()[1])
+
+
+def test_generated_kernels_compile_for_gfx950():
+    from paper_2608_16265_amd import ExaModel
+    from test_oracle_pins import op_zoo
+    for w in (acopf(30, 0), op_zoo()):
+        em = ExaModel(w.model, host_only=True)
+        src = em.generated_source()
+        assert "exa_k_hess" in src and "exa_k_jh" in src
+        em.compile_check()
+
+
+def test_callbacks_on_host_only_model_report_state():
+    from paper_2608_16265_amd import ExaModel, _lib
+    em = ExaModel(rosenbrock(4).model, host_only=True)
+    st = _lib.LIB.exa_jac_coord(em.handle, None, None, None)
+    assert st == _lib.EXA_ESTATE
+
+
+def _bad(model):
+    from paper_2608_16265_amd import ExaModel, ExaError
+    with pytest.raises(ExaError) as e:
+        ExaModel(model, host_only=True)
+    return e.value
+
+
+def test_malformed_models_are_rejected():
+    # variable index out of range at some data point
+    m = Model()
+    x = m.add_var(3)
+    d = DataSet(2, i=np.array([0, 5]))
+    m.add_obj(x[d.i] ** 2, d)
+    err = _bad(m)
+    assert err.code == 1 and "variable index" in str(err)
+    # parameter index out of range
+    m = Model()
+    x = m.add_var(2)
+    th = m.add_par([1.0])
+    d = DataSet(2, i=np.array([0, 1]))
+    m.add_obj(th[d.i] * x[d.i], d)
+    assert _bad(m).code == 1
+    # augmentation row outside the target block
+    m = Model()
+    x = m.add_var(2)
+    d = DataSet(2, i=np.array([0, 1]))
+    c = m.add_con(x[d.i], d)
+    d2 = DataSet(1, r=np.array([2]), i=np.array([0]))
+    m.add_con_aug(c, d2.r, x[d2.i], d2)
+    assert "augmentation row" in str(_bad(m))
+
+
+def test_raw_descriptor_errors():
+    from paper_2608_16265_amd import _lib
+    op = np.array([_lib.OPCODE["var"], 99], dtype=np.int32)
+    a = np.array([-1, 0], dtype=np.int32)
+    b = np.array([-1, -1], dtype=np.int32)
+    off = np.zeros(2, dtype=np.int64)
+    val = np.zeros(2)
+    d = (_lib.PatternDesc * 1)()
+    d[0].kind = 0
+    d[0].nnodes = 2
+    d[0].op = op.ctypes.data_as(_lib.P_i32)
+    d[0].a = a.ctypes.data_as(_lib.P_i32)
+    d[0].b = b.ctypes.data_as(_lib.P_i32)
+    d[0].off = off.ctypes.data_as(_lib.P_i64)
+    d[0].val = val.ctypes.data_as(_lib.P_f64)
+    d[0].ndata = 1
+    opt = _lib.Options(1, 256, 4)
+    h = C.c_void_p()
+    st = _lib.LIB.exa_create(d, 1, 1, None, None, 0, None, C.byref(opt), C.byref(h))
+    assert st == _lib.EXA_EINVAL and b"unknown operator" in _lib.LIB.exa_last_error()
+    op[1] = _lib.OPCODE["exp"]
+    a[1] = 1  # child not below the node
+    st = _lib.LIB.exa_create(d, 1, 1, None, None, 0, None, C.byref(opt), C.byref(h))
+    assert st == _lib.EXA_EINVAL and b"not below" in _lib.LIB.exa_last_error()
+    a[1] = 0
+    st = _lib.LIB.exa_create(d, 1, 1, None, None, 0, None, C.byref(opt), C.byref(h))
+    assert st == _lib.EXA_OK
+    assert _lib.LIB.exa_destroy(h) == _lib.EXA_OK
+    assert _lib.LIB.exa_create(None, 1, 1, None, None, 0, None, None, C.byref(h)) == _lib.EXA_EINVAL
+    bad = _lib.Options(1, 100, 4)
+    assert _lib.LIB.exa_create(d, 1, 1, None, None, 0, None, C.byref(bad), C.byref(h)) == _lib.EXA_EINVAL
+
+
+def test_simplified_structure_drops_dead_variables():
+    """x^0 -> 1 and 0*x -> 0 remove variables from the structure (Sec. 7.1.2)."""
+    from paper_2608_16265_amd import ExaModel
+    m = Model()
+    x = m.add_var(3)
+    d = DataSet(2, i=np.array([0, 1]))
+    m.add_con(x[d.i] ** 0 + 0 * x[d.i + 1] + exp(x[2]) * 1, d)
+    em = ExaModel(m, host_only=True)
+    o = OracleModel(m)
+    assert em.nnzj == o.dims()[2] == 2 and em.nnzh == 2
+    assert np.array_equal(em.jac_structure()[1], o.jac_structure()[1])

@@ -1,0 +1,174 @@
+"""GPU library vs CPU oracle, element by element, on seeded inputs.
+
+Sizes are chosen so that every pattern spans several 1024-point tiles with a
+ragged last tile (and a few tiny cases), plus edge cases: an empty pattern,
+a single data point, references that alias at run time, every operator.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from exa_modeling import DataSet, Model, exp, sin
+from exa_modeling.generators import Workload, acopf, pde, rosenbrock
+from oracle import OracleModel
+from parity_util import RTOL, abs_oracle, assert_close, column_scale, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def aliasing_case():
+    m = Model("alias")
+    x = m.add_var(4)
+    d = DataSet(4, i=np.array([0, 1, 2, 3]), j=np.array([0, 2, 2, 1]))
+    m.add_obj(exp(x[d.i] * x[d.j]), d)
+    m.add_con(sin(x[d.i]) * x[d.j], d)
+    rng = np.random.default_rng(3)
+    return Workload(m, rng.uniform(-0.5, 0.5, 4), rng.standard_normal(4), 1.7)
+
+
+def empty_pattern_case():
+    m = Model("empty")
+    x = m.add_var(5)
+    th = m.add_par([2.0, 3.0])
+    e = DataSet(0, i=np.zeros(0, dtype=np.int64))
+    d = DataSet(5, i=np.arange(5))
+    m.add_obj(x[e.i] ** 2, e)
+    c = m.add_con(th[0] * x[d.i] ** 3, d)
+    m.add_con_aug(c, e.i, x[e.i], e)
+    m.add_con(x[e.i] * x[e.i + 1], e)
+    m.add_obj(th[1] * x[d.i] ** 2, d)
+    rng = np.random.default_rng(4)
+    return Workload(m, rng.uniform(-1, 1, 5), rng.standard_normal(5), 0.5)
+
+
+def single_point_case():
+    m = Model("single")
+    x = m.add_var(2)
+    d = DataSet(1, k=np.zeros(1, dtype=np.int64))
+    m.add_obj(x[0] ** 2 * x[1], d)
+    m.add_con(x[0] / x[1] + x[1] ** 2.5, d, lcon=-1.0, ucon=1.0)
+    return Workload(m, np.array([3.0, 5.0]), np.array([0.75]), 1.0)
+
+
+def _zoo():
+    from test_oracle_pins import op_zoo
+    return op_zoo()
+
+
+CASES = {
+    "rosen5": lambda: rosenbrock(5, 1),
+    "rosen3000": lambda: rosenbrock(3000, 2),
+    "acopf30": lambda: acopf(30, 0),
+    "acopf600": lambda: acopf(600, 7),
+    "acopf30_gb": lambda: acopf(30, 0, gb_in_theta=True),
+    "pde8": lambda: pde(8, 3),
+    "pde50": lambda: pde(50, 5),
+    "zoo": _zoo,
+    "alias": aliasing_case,
+    "empty": empty_pattern_case,
+    "single": single_point_case,
+}
+
+
+def check_all(w, em=None, o=None, tag=""):
+    from paper_2608_16265_amd import ExaModel
+    em = em or ExaModel(w.model)
+    o = o or OracleModel(w.model)
+    rng = np.random.default_rng(17)
+    x, y, sig = w.x, (w.y if w.y.size == o.ncon else rng.standard_normal(o.ncon)), w.sigma
+    v = rng.standard_normal(o.nvar)
+    wv = rng.standard_normal(o.ncon)
+    wx = rng.standard_normal(o.nvar)
+    X, Y, Vd, W, WX = dev(x), dev(y), dev(v), dev(wv), dev(wx)
+    a = abs_oracle(o, x, y, sig, v, wv)
+    # structure: identical
+    for g, r in zip(em.jac_structure(), o.jac_structure()):
+        assert np.array_equal(g, r), tag + " jac structure"
+    for g, r in zip(em.hess_structure(), o.hess_structure()):
+        assert np.array_equal(g, r), tag + " hess structure"
+    assert_close(tag + "obj", host(em.obj(X))[0], o.obj(x), a["obj"])
+    assert_close(tag + "grad", host(em.grad(X)), o.grad(x), a["grad"])
+    assert_close(tag + "cons", host(em.cons(X)), o.cons(x), a["cons"])
+    jr = o.jac_coord(x)
+    assert_close(tag + "jac", host(em.jac_coord(X)), jr, column_scale(o, jr, 1))
+    hr = o.hess_coord(x, y, sig)
+    assert_close(tag + "hess", host(em.hess_coord(X, Y, sig)), hr, column_scale(o, hr, 2))
+    assert_close(tag + "jprod", host(em.jprod(X, Vd)), o.jprod(x, v), a["jprod"])
+    assert_close(tag + "jtprod", host(em.jtprod(X, W)), o.jtprod(x, wv), a["jtprod"])
+    assert_close(tag + "hprod", host(em.hprod(X, Y, sig, Vd)), o.hprod(x, y, sig, v), a["hprod"])
+    if o.ntheta:
+        ref = o.adjoint_theta(x, y, sig, wx)
+        got = host(em.adjoint_theta(X, Y, sig, WX))
+        assert_close(tag + "adjoint", got, ref, np.max(np.abs(ref)) if ref.size else 0.0)
+    return em, o
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_all_callbacks_match_oracle(name):
+    _need_gpu()
+    check_all(CASES[name](), tag=name + ": ")
+
+
+@pytest.mark.parametrize("block,epl", [(64, 1), (128, 3), (512, 2)])
+def test_launch_shapes_agree_bitwise(block, epl):
+    _need_gpu()
+    from paper_2608_16265_amd import ExaModel
+    w = acopf(600, 7)
+    X, Y = dev(w.x), dev(w.y)
+    base = ExaModel(w.model)
+    alt = ExaModel(w.model, block=block, epl=epl)
+    for f in ("jac_coord", "cons", "grad"):
+        assert np.array_equal(host(getattr(base, f)(X)), host(getattr(alt, f)(X))), f
+    assert np.array_equal(host(base.hess_coord(X, Y, 1.0)), host(alt.hess_coord(X, Y, 1.0)))
+    check_all(w, em=alt, tag=f"b{block}e{epl}: ")
+
+
+def test_repeated_calls_are_bitwise_identical():
+    _need_gpu()
+    from paper_2608_16265_amd import ExaModel
+    w = pde(50, 5)
+    em = ExaModel(w.model)
+    X, Y, V = dev(w.x), dev(w.y), dev(np.random.default_rng(0).standard_normal(w.x.size))
+    ref = [host(em.hess_coord(X, Y, 1.0)), host(em.grad(X)), host(em.hprod(X, Y, 1.0, V)),
+           host(em.obj(X))]
+    for _ in range(10):
+        got = [host(em.hess_coord(X, Y, 1.0)), host(em.grad(X)), host(em.hprod(X, Y, 1.0, V)),
+               host(em.obj(X))]
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+
+
+def test_set_theta_updates_without_rebuild():
+    _need_gpu()
+    from paper_2608_16265_amd import ExaModel
+    w = acopf(30, 0)
+    em = ExaModel(w.model)
+    o = OracleModel(w.model)
+    th = w.model.theta.copy() * 1.3 + 0.1
+    em.set_theta(dev(th))
+    X, Y = dev(w.x), dev(w.y)
+    a = abs_oracle(o, w.x, w.y, 1.0, w.x, w.y, theta=th)
+    assert_close("cons(theta)", host(em.cons(X)), o.cons(w.x, theta=th), a["cons"])
+    assert_close("obj(theta)", host(em.obj(X))[0], o.obj(w.x, theta=th), a["obj"])
+    hr = o.hess_coord(w.x, w.y, 1.0, theta=th)
+    assert_close("hess(theta)", host(em.hess_coord(X, Y, 1.0)), hr, column_scale(o, hr, 2))
+    assert em.counters()["hess"] == 1
+
+
+def test_bad_tensor_arguments_raise():
+    _need_gpu()
+    from paper_2608_16265_amd import ExaModel
+    w = rosenbrock(5)
+    em = ExaModel(w.model)
+    with pytest.raises(ValueError):
+        em.grad(dev(np.zeros(4)))
+    with pytest.raises(TypeError):
+        em.grad(torch.zeros(5, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        em.grad(torch.zeros(5, dtype=torch.float32, device="cuda:0"))
