@@ -174,9 +174,11 @@ class PatternCg {
 
     bool rev_active(int i) const { return hasvar_[i] || (mode_ == M_ADJ && haspar_[i]); }
 
-    std::string idx_expr(const RefKey& r) const {
-        if (r.col < 0) return std::to_string(r.off) + "LL";
-        return "(ic" + std::to_string(r.col) + " + " + std::to_string(r.off) + "LL)";
+    // Index of reference slot s (variables 0.., parameters after them); the
+    // offset comes from the instance's descriptor, not from the code.
+    std::string idx_expr(const RefKey& r, int s) const {
+        if (r.col < 0) return "P.roff[" + std::to_string(s) + "]";
+        return "(ic" + std::to_string(r.col) + " + P.roff[" + std::to_string(s) + "])";
     }
 
     void loads(Em& e) {
@@ -189,14 +191,14 @@ class PatternCg {
         for (int c : ic) e.os << e.ind << "const long long ic" << c << " = P.ic[" << c << "][k];\n";
         for (int c : fc) e.os << e.ind << "const double fc" << c << " = P.fc[" << c << "][k];\n";
         for (int s = 0; s < P_.o1step(); ++s) {
-            e.os << e.ind << "const long long ix" << s << " = " << idx_expr(P_.vslots[s]) << ";\n";
+            e.os << e.ind << "const long long ix" << s << " = " << idx_expr(P_.vslots[s], s) << ";\n";
             e.os << e.ind << "const double x" << s << " = X[ix" << s << "];\n";
         }
         if (mode_ == M_JPROD || mode_ == M_HPROD || mode_ == M_ADJ)
             for (int s = 0; s < P_.o1step(); ++s)
                 e.os << e.ind << "const double v" << s << " = V[ix" << s << "];\n";
         for (int s = 0; s < P_.pstep(); ++s)
-            e.os << e.ind << "const double p" << s << " = TH[" << idx_expr(P_.pslots[s]) << "];\n";
+            e.os << e.ind << "const double p" << s << " = TH[" << idx_expr(P_.pslots[s], P_.o1step() + s) << "];\n";
         if (needs_weight()) {
             if (P_.kind == EXA_OBJ) {
                 e.os << e.ind << "const double wgt = C.sigma;\n";
@@ -508,8 +510,9 @@ class PatternCg {
             std::string h = col.count(b) ? col[b][a] : col[a][b];
             const RefKey& ra = P_.vslots[a];
             const RefKey& rb = P_.vslots[b];
-            const bool may_alias = a != b && !(ra.col == rb.col && ra.off != rb.off) &&
-                                   !(ra.col < 0 && rb.col < 0);
+            // different slots over the same index column (or both literal)
+            // have different offsets, so only different columns can alias
+            const bool may_alias = a != b && ra.col != rb.col;
             if (may_alias && h != Z)
                 e.os << e.ind << "o[" << s << "] = (ix" << a << " == ix" << b << ") ? 2.0 * " << h << " : " << h << ";\n";
             else

@@ -38,6 +38,10 @@ void set_last_error(const std::string& msg);
 #define EXA_OFF_FO_OBJ 8  /* first-order buffer, objective part (nnzg)       */
 #define EXA_OFF_FO_CON 9  /* first-order buffer, constraint part (nnzj)      */
 #define EXA_NOFF 12
+// Index offsets of a pattern's unique references live in ExaPatDev::roff
+// (variable slots first, then parameter slots), so that every instance of a
+// formulation runs the same code whatever its block offsets.
+#define EXA_MAX_REFS 48
 
 #define EXA_DEVICE_STRUCTS                                                       \
     struct ExaPatDev {                                                           \
@@ -52,6 +56,7 @@ void set_last_error(const std::string& msg);
         long long row_off;                                                       \
         int row_ic;                                                              \
         int pad0;                                                                \
+        long long roff[48];                                                      \
     };                                                                           \
     struct ExaInstDev {                                                          \
         long long off[12];                                                       \

@@ -312,6 +312,9 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             if (d.ucon) std::copy(d.ucon, d.ucon + d.ndata, P.ucon.begin());
         }
         analyse_structure(P);
+        if (P.o1step() + P.pstep() > EXA_MAX_REFS)
+            fail(EXA_EINVAL, "pattern " + std::to_string(p) + " has more than " +
+                                 std::to_string(EXA_MAX_REFS) + " distinct variable/parameter references");
     }
 
     // ---- offsets in declaration order (Sec. 3.1 running counts) ----------
@@ -421,9 +424,10 @@ std::string pattern_signature(const Model& M) {
     os.precision(17);
     for (auto& P : M.pats) {
         os << "P" << P.kind << ":" << P.n_icols << "," << P.n_fcols << ":" << P.row_icol << ";";
+        // reference offsets are per-instance data (ExaPatDev::roff): left out
         for (auto& n : P.nodes)
-            os << n.op << "," << n.a << "," << n.b << "," << n.col << "," << n.off << "," << n.val
-               << "," << n.slot << ";";
+            os << n.op << "," << n.a << "," << n.b << "," << n.col << "," << n.val << "," << n.slot
+               << ";";
     }
     return os.str();
 }

@@ -151,6 +151,8 @@ void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
         d.tgt0 = P.tgt0;
         d.row_off = P.row_off;
         d.row_ic = P.row_icol;
+        for (int r = 0; r < P.o1step(); ++r) d.roff[r] = P.vslots[r].off;
+        for (int r = 0; r < P.pstep(); ++r) d.roff[P.o1step() + r] = P.pslots[r].off;
     }
 }
 

@@ -1,6 +1,6 @@
 """Helpers for comparing the GPU library with the CPU oracle.
 
-Tolerance (values): an entry passes when
+Tolerance (values), the rule "|gpu - ref| <= 1e-12 max(|ref|, s_P)": an entry passes when
     |gpu - ref| <= RTOL * max(|ref|, scale)
 where ``scale`` is the magnitude the entry's rounding is measured against:
 for COO values the largest |ref| in the same (pattern, slot) column, for
@@ -57,34 +57,44 @@ def column_scale(o, vals, order):
 
 
 def abs_oracle(o, x, y, sigma, v, w, theta=None):
-    """Sums of absolute contributions for the dense outputs."""
+    """Scales for the dense outputs: every contribution counts with the
+    largest magnitude in its (pattern, slot) column, so that cancellation
+    inside a pattern value (g cos + b sin, p - P(v, theta) ...) is measured
+    against the size of the pattern's terms, as for the COO values."""
     import scipy.sparse as sp
     out = {}
-    # cons: sum |terms| per row
+    th = o._theta(theta)
+    # cons / obj: per pattern, the largest |value| over its data points
     c = np.zeros(o.ncon)
+    tot_obj = 0.0
     for i, P in enumerate(o.pats):
-        if P.kind == "obj" or P.ndata == 0:
+        if P.ndata == 0:
             continue
-        np.add.at(c, o._rows(P, np.arange(P.ndata)), np.abs(o.pattern_values(i, x, theta)))
+        sP = float(np.max(np.abs(o.pattern_values(i, x, theta))))
+        if P.kind == "obj":
+            tot_obj += P.ndata * sP
+        else:
+            np.add.at(c, o._rows(P, np.arange(P.ndata)), sP)
     out["cons"] = c
-    J = o.jac_matrix(x, theta)
-    Ja = sp.coo_matrix((np.abs(J.data), (J.row, J.col)), shape=J.shape)
+    out["obj"] = tot_obj
+    rj, cj = o.jac_structure()
+    jv = column_scale(o, o.jac_coord(x, theta), 1)
+    Ja = sp.coo_matrix((jv, (rj, cj)), shape=(o.ncon, o.nvar))
     out["jprod"] = Ja @ np.abs(v)
     out["jtprod"] = Ja.T @ np.abs(w)
-    H = o.hess_matrix(x, y, sigma, theta).tocoo()
-    Ha = sp.coo_matrix((np.abs(H.data), (H.row, H.col)), shape=H.shape)
+    rh, ch = o.hess_structure()
+    hv = column_scale(o, o.hess_coord(x, y, sigma, theta), 2)
+    L = sp.coo_matrix((hv, (rh, ch)), shape=(o.nvar, o.nvar)).tocsr()
+    Ha = L + L.T - sp.diags(L.diagonal())
     out["hprod"] = Ha @ np.abs(v)
-    # grad: sum |contributions| per variable
+    # grad: per-variable sum of column maxima of the objective slots
     g = np.zeros(o.nvar)
-    th = o._theta(theta)
     for P in o.pats:
         if P.kind != "obj" or P.ndata == 0:
             continue
         ks = np.arange(P.ndata)
         tay = o._taylor(P, ks, x, th)
-        for s, key in enumerate(P.vslots):
-            np.add.at(g, o._index(P, key, ks), np.abs(tay.g[:, s]))
+        for s_, key in enumerate(P.vslots):
+            np.add.at(g, o._index(P, key, ks), np.max(np.abs(tay.g[:, s_])))
     out["grad"] = g
-    out["obj"] = float(sum(np.sum(np.abs(o.pattern_values(i, x, theta)))
-                           for i, P in enumerate(o.pats) if P.kind == "obj"))
     return out
