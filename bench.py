@@ -49,10 +49,18 @@ def parse():
     ap.add_argument("--only", choices=["acopf", "pde", "batch"], default=None,
                     help="run one leg only (used for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--quick", action="store_true",
+                    help="few repetitions per measurement (for runs under a profiler)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB, 5 times (calibrates "
+                         "the profiler's HBM byte counters)")
     return ap.parse_args()
 
 
 # --------------------------------------------------------------- measurement
+QUICK = False
+
+
 def best_of_3(fn, min_s=0.2):
     """The paper's protocol: warm up, N back-to-back calls spanning >= min_s,
     one synchronization, best of three batches.  Returns seconds per call."""
@@ -64,7 +72,7 @@ def best_of_3(fn, min_s=0.2):
         fn()
     torch.cuda.synchronize()
     per = max((time.perf_counter() - t0) / 3, 1e-7)
-    n = max(3, int(min_s / per))
+    n = 3 if QUICK else max(3, int(min_s / per))
     best = float("inf")
     for _ in range(3):
         torch.cuda.synchronize()
@@ -82,6 +90,8 @@ def kernel_ms(fn, n=200):
     matrix product so that the host stays ahead of the device and the event
     pairs bracket only the kernel (plus its dispatch)."""
     import torch
+    if QUICK:
+        n = min(n, 10)
     a = torch.ones(4096, 4096, dtype=torch.float64, device="cuda:0")
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(n)]
@@ -98,40 +108,12 @@ def kernel_ms(fn, n=200):
     return float(np.mean(ts)), float(np.median(ts))
 
 
-def hess_bytes(em, model):
-    """Algorithmic bytes of one Hessian launch: every input the kernel needs
-    read once (index and float data columns it uses, y of constraint rows,
-    the distinct x and theta entries it touches) plus every output written
-    once (8 bytes per Hessian entry)."""
-    total = 0
-    xs, ts = set(), set()
-    xidx, tidx = [], []
-    for p, P in enumerate(model.patterns):
-        info = em.pattern_info(p)
-        if info["o2step"] == 0 or P.ndata == 0:
-            continue
-        nodes = P.nodes()
-        icols = {n.col for n in nodes if n.op in ("var", "param") and n.col is not None}
-        fcols = {n.col for n in nodes if n.op == "data"}
-        if P.kind == "aug":
-            icols.add(P.row_col)
-        total += P.ndata * (4 * len(icols) + 8 * len(fcols) + (8 if P.kind != "obj" else 0)
-                            + 8 * info["o2step"])
-        for n in nodes:
-            if n.op in ("var", "param"):
-                idx = (P.data.icols[n.col].astype(np.int64) + n.off) if n.col else np.array([n.off])
-                (xidx if n.op == "var" else tidx).append(idx)
-    nx = np.unique(np.concatenate(xidx)).size if xidx else 0
-    nt = np.unique(np.concatenate(tidx)).size if tidx else 0
-    return total + 8 * nx + 8 * nt
-
-
 # ------------------------------------------------------------------- legs
 def leg_single(name, wl, steps, warmup, full_step=True):
     import torch
     from paper_2608_16265_amd import ExaModel
     t0 = time.perf_counter()
-    em = ExaModel(wl.model)
+    em = ExaModel(wl.model, autotune=True)
     build_s = time.perf_counter() - t0
     dev = "cuda:0"
     X = torch.as_tensor(wl.x, device=dev)
@@ -163,7 +145,7 @@ def leg_single(name, wl, steps, warmup, full_step=True):
         for k in order:
             cbs[k]()
 
-    for _ in range(warmup):
+    for _ in range(max(1, warmup)):  # the first call of each callback tunes it
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -174,7 +156,9 @@ def leg_single(name, wl, steps, warmup, full_step=True):
     per_cb = {k: best_of_3(fn) * 1e6 for k, fn in cbs.items()}
     k_mean, k_med = kernel_ms(cbs["hess_coord"])
     kj_mean, _ = kernel_ms(cbs["jac_coord"])
-    nbytes = hess_bytes(em, wl.model)
+    rd, wr = em.kernel_bytes("hess")
+    nbytes = rd + wr
+    sched = {k: em.schedule(k) for k in ("jac", "hess")}
     nnz = em.nnzj + em.nnzh
     res = dict(
         name=name, nvar=em.nvar, ncon=em.ncon, nnzj=em.nnzj, nnzh=em.nnzh,
@@ -183,7 +167,8 @@ def leg_single(name, wl, steps, warmup, full_step=True):
         callbacks_us={k: round(v, 2) for k, v in per_cb.items()},
         hess_kernel_us=round(k_mean * 1e3, 3), hess_kernel_median_us=round(k_med * 1e3, 3),
         jac_kernel_us=round(kj_mean * 1e3, 3), hess_bytes=nbytes,
-        hess_gbs=nbytes / (k_mean * 1e-3) / 1e9,
+        hess_gbs=nbytes / (k_mean * 1e-3) / 1e9, hess_read_bytes=rd, hess_write_bytes=wr,
+        schedule=sched,
     )
     em.close()
     return res
@@ -227,12 +212,16 @@ def leg_batch(count=256, first_seed=1000):
         same &= bool(torch.equal(H[off[i, 3]:off[i + 1, 3]], hs[i]))
     sched = b.schedule()
     k_mean, _ = kernel_ms(lambda: b.eval(X, Y, 1.0, J, H), n=50)
+    rd, wr = b.kernel_bytes()
     res = dict(instances=count, buses=int(sum(w.meta["nb"] for w in wls)), nnz=int(nnz),
                build_s=round(build_s, 2), batched_us=round(t_batch * 1e6, 1),
                plain_us=round(t_plain * 1e6, 1), speedup=t_plain / t_batch,
                batched_nnz_per_s=nnz / t_batch, plain_nnz_per_s=nnz / t_plain,
                bitwise_equal_sampled=same, schedule=sched,
-               kernel_us=round(k_mean * 1e3, 1))
+               kernel_us=round(k_mean * 1e3, 1), read_bytes=rd, write_bytes=wr,
+               roofline={"kernel": "exa_k_jh", "bound": "hbm",
+                         "achieved": (rd + wr) / (k_mean * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": (rd + wr) / (k_mean * 1e-3) / 1e9 / HBM_PEAK_GBS})
     b.close()
     for e in ems:
         e.close()
@@ -260,8 +249,24 @@ def cpu_baseline(wl, seconds):
                        f"{per:.3f} s each, numpy float64 single thread")
 
 
+def copy_only(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8}))
+
+
 def main():
+    global QUICK
     args = parse()
+    QUICK = args.quick
+    if args.copy_mib:
+        copy_only(args.copy_mib)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(instances of a batch would be sharded across GPUs with no exchange; not built).",
@@ -285,13 +290,14 @@ def main():
         out["config"] = {"workload": "acopf-10000-bus (13,500 branches, 2,000 generators, seed 1)",
                          "step": "obj+grad+cons+jac_coord+hess_coord+jprod+jtprod+hprod",
                          "nvar": r["nvar"], "ncon": r["ncon"], "nnzj": r["nnzj"],
-                         "nnzh": r["nnzh"], "block": 256, "points_per_lane": 4}
+                         "nnzh": r["nnzh"], "schedule": r["schedule"]}
         out["callbacks_us"] = r["callbacks_us"]
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
         out["roofline"] = {"kernel": "exa_k_hess", "bound": "hbm", "achieved": r["hess_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": r["hess_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                           "bytes_per_launch": r["hess_bytes"], "launch_us": r["hess_kernel_us"]}
+                           "bytes_per_launch": r["hess_bytes"], "read_bytes": r["hess_read_bytes"],
+                           "write_bytes": r["hess_write_bytes"], "launch_us": r["hess_kernel_us"]}
         if not args.no_cpu_baseline:
             log("leg: cpu baseline")
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -119,9 +119,16 @@ typedef struct exa_options {
     int32_t host_only; /* 1: analyse only (dims, bounds, structure); no device
                           memory, no kernel compilation; callbacks then return
                           EXA_ESTATE                                           */
-    int32_t block;     /* threads per workgroup: 64, 128, 256 (default), 512  */
-    int32_t epl;       /* data points per lane per tile: 1..16 (default 4)    */
-    int32_t reserved[5];
+    int32_t block;     /* threads per workgroup: 64, 128 or 256 (0: 256)      */
+    int32_t epl;       /* data points per lane per tile: 1..16 (0: 4)         */
+    int32_t autotune;  /* 1: at its first call, each callback times candidate
+                          schedules (workgroup size, points per lane, fused or
+                          separate patterns) and keeps the fastest; results do
+                          not depend on the schedule                          */
+    int32_t fuse;      /* without autotune: 1 evaluates patterns declared over
+                          the same data arrays in one lane (shared loads),
+                          0 evaluates them separately                          */
+    int32_t reserved[3];
 } exa_options;
 
 /* ---- Library ------------------------------------------------------------ */
@@ -225,6 +232,19 @@ exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, dou
 exa_status exa_generated_source(const exa_model* m, char* buf, int64_t cap, int64_t* len);
 exa_status exa_compile_check(const exa_model* m);
 
+/* Algorithmic traffic of one launch of a callback's evaluation kernel under
+ * its current schedule: bytes every data point needs (the data columns, y
+ * entries and outputs the generated code really reads or writes after dead
+ * code is removed) plus each distinct entry of x, v and theta it reads, once.
+ * callback: 0 obj, 1 grad, 2 cons, 3 jac, 4 hess, 5 jprod, 6 jtprod,
+ * 7 hprod, 8 adjoint (the order of exa_counters).  Host-only models report
+ * the unfused schedule. */
+exa_status exa_kernel_bytes(const exa_model* m, int32_t callback, int64_t* read_bytes,
+                            int64_t* write_bytes);
+/* The schedule a callback's kernel uses: out4 = workgroup size, points per
+ * lane, fused (1/0), number of tiles. */
+exa_status exa_schedule(const exa_model* m, int32_t callback, int64_t* out4);
+
 /* Layout of pattern p (declaration position): out8 = kind, ndata, o1step,
  * o2step, number of unique parameter references, o0 (first row / term / aug
  * entry), o1 (first Jacobian entry, or first gradient-buffer entry for an
@@ -255,7 +275,11 @@ typedef struct exa_batch_options {
     int32_t epl;
     int32_t grid;      /* persistent workgroups (0: chosen by the library)     */
     int32_t use_graph; /* 1: replay the launch from a HIP graph                */
-    int32_t reserved[3];
+    int32_t fuse;      /* 1: patterns over the same data arrays share a lane   */
+    int32_t xcd_aware; /* 1: instances are split over the 8 XCDs by cost and
+                          each XCD walks its own instances one after another
+                          (their x stays in that XCD's L2)                     */
+    int32_t reserved;
 } exa_batch_options;
 
 #define EXA_CB_JAC 1u
@@ -272,6 +296,10 @@ exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets /* [4*(B+1)] *
 exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x_cat, const double* y_cat,
                           double obj_weight, double* jac_cat, double* hess_cat,
                           exa_stream_t stream);
+/* Algorithmic traffic of one batched launch for the callbacks in mask, summed
+ * over the instances (see exa_kernel_bytes; an instance's x entries count once
+ * for the Jacobian and the Hessian together). */
+exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes);
 /* The schedule in use: block, epl, grid, tiles, and the autotuner's
  * best time in nanoseconds (0 if not tuned). */
 exa_status exa_batch_schedule(const exa_batch* b, int64_t* out5);

@@ -39,12 +39,16 @@ class PatternDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("autotune", C.c_int32), ("fuse", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class BatchOptions(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
-                ("grid", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("grid", C.c_int32), ("use_graph", C.c_int32), ("fuse", C.c_int32),
+                ("xcd_aware", C.c_int32), ("reserved", C.c_int32)]
+
+
+CALLBACKS = ["obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod", "adjoint"]
 
 
 class ExaError(RuntimeError):
@@ -82,12 +86,15 @@ def _load():
         "exa_generated_source": (C.c_int32, [vp, C.c_char_p, C.c_int64, P_i64]),
         "exa_compile_check": (C.c_int32, [vp]),
         "exa_pattern_info": (C.c_int32, [vp, C.c_int32, P_i64]),
+        "exa_kernel_bytes": (C.c_int32, [vp, C.c_int32, P_i64, P_i64]),
+        "exa_schedule": (C.c_int32, [vp, C.c_int32, P_i64]),
         "exa_batch_create": (C.c_int32, [C.POINTER(vp), C.c_int32, C.POINTER(BatchOptions),
                                          C.POINTER(vp)]),
         "exa_batch_destroy": (C.c_int32, [vp]),
         "exa_batch_offsets": (C.c_int32, [vp, P_i64]),
         "exa_batch_eval": (C.c_int32, [vp, C.c_uint32, vp, vp, C.c_double, vp, vp, vp]),
         "exa_batch_schedule": (C.c_int32, [vp, P_i64]),
+        "exa_batch_bytes": (C.c_int32, [vp, C.c_uint32, P_i64, P_i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -110,5 +117,5 @@ def exported_symbols():
             "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
             "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
             "exa_adjoint_theta", "exa_counters", "exa_generated_source", "exa_compile_check",
-            "exa_pattern_info", "exa_batch_create", "exa_batch_destroy",
-            "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule"]
+            "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",
+            "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule", "exa_batch_bytes"]

@@ -19,10 +19,12 @@ from .model import ExaModel, _stream
 
 class ExaBatch:
     def __init__(self, models: Sequence[ExaModel], *, autotune: bool = True, block: int = 256,
-                 epl: int = 4, grid: int = 0, use_graph: bool = True):
+                 epl: int = 4, grid: int = 0, use_graph: bool = True, fuse: bool = True,
+                 xcd_aware: bool = True):
         self.models = list(models)  # the models must outlive the batch
         arr = (C.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
-        opt = BatchOptions(1 if autotune else 0, block, epl, grid, 1 if use_graph else 0)
+        opt = BatchOptions(1 if autotune else 0, block, epl, grid, 1 if use_graph else 0,
+                           1 if fuse else 0, 1 if xcd_aware else 0)
         h = C.c_void_p()
         check(LIB.exa_batch_create(arr, len(self.models), C.byref(opt), C.byref(h)))
         self._h = h
@@ -62,6 +64,12 @@ class ExaBatch:
         check(LIB.exa_batch_eval(self._h, mask, px, py, float(obj_weight),
                                  self._p(jac, self.total("jac"), "jac"),
                                  self._p(hess, self.total("hess"), "hess"), _stream()))
+
+    def kernel_bytes(self, jac: bool = True, hess: bool = True):
+        mask = (CB_JAC if jac else 0) | (CB_HESS if hess else 0)
+        rd, wr = C.c_int64(), C.c_int64()
+        check(LIB.exa_batch_bytes(self._h, mask, C.byref(rd), C.byref(wr)))
+        return rd.value, wr.value
 
     def schedule(self) -> dict:
         out = np.zeros(5, dtype=np.int64)

@@ -30,7 +30,9 @@ struct exa_batch {
     ExaInstDev* inst = nullptr;
     std::vector<int64_t> offsets;          // 4 * (B + 1): x, y, jac, hess
     // schedule
-    bool autotune = true, use_graph = true, tuned = false;
+    bool autotune = true, use_graph = true, tuned = false, fuse = true, xcd_aware = true;
+    long long* xcd_range = nullptr;       // device [9] per mask when xcd_aware
+    long long* xcd_ranges[4] = {};
     int epl = 4;
     int64_t grid = 0;
     int64_t tuned_ns = 0;
@@ -73,36 +75,76 @@ int64_t point_cost(const Pattern& P, int mode) {
 
 void build_tiles(exa_batch& b, int epl) {
     if (b.tiles_epl == epl) return;
+    const int64_t tp = (int64_t)b.block * epl;
     for (int m = 1; m <= 3; ++m) {
-        std::vector<std::pair<int64_t, ExaTile>> all;
+        // per instance: its tiles and their total cost
+        std::vector<std::vector<ExaTile>> per(b.B);
+        std::vector<int64_t> cost(b.B, 0);
         for (int i = 0; i < b.B; ++i) {
             const Model& M = b.models[i]->impl;
-            const int64_t tp = (int64_t)b.block * epl;
-            if (m & EXA_CB_JAC)
-                for (auto& t : make_tiles(M, M_JAC, i, tp))
-                    all.emplace_back(t.count * point_cost(M.pats[t.pat], M_JAC), t);
-            if (m & EXA_CB_HESS)
-                for (auto t : make_tiles(M, M_HESS, i, tp)) {
-                    const int64_t c = t.count * point_cost(M.pats[t.pat], M_HESS);
-                    t.pat += EXA_MAX_PATTERNS;
-                    all.emplace_back(c, t);
+            for (int mode : {M_JAC, M_HESS}) {
+                if (!(m & (mode == M_JAC ? EXA_CB_JAC : EXA_CB_HESS))) continue;
+                for (const Unit& u : units_for(M, mode, b.fuse)) {
+                    int64_t pc = 0;
+                    for (int p : u.members) pc += point_cost(M.pats[p], mode);
+                    for (int64_t s = 0; s < u.ndata; s += tp) {
+                        ExaTile t{};
+                        t.pat = u.code + (mode == M_HESS ? 64 : 0);
+                        t.inst = i;
+                        t.start = s;
+                        t.count = std::min(tp, u.ndata - s);
+                        per[i].push_back(t);
+                        cost[i] += t.count * pc;
+                    }
                 }
+            }
         }
-        // largest first, so the round-robin walk of the persistent grid
-        // approximates longest-processing-time-first scheduling
-        std::stable_sort(all.begin(), all.end(),
-                         [](const auto& a, const auto& c) { return a.first > c.first; });
         std::vector<ExaTile> v;
-        v.reserve(all.size());
-        for (auto& e : all) v.push_back(e.second);
-        for (size_t i = 0; i < v.size(); ++i) v[i].slot = (int64_t)i;
-        if (b.tiles[m]) {
-            (void)hipFree(b.tiles[m]);
-            b.mem.allocs.erase(std::remove(b.mem.allocs.begin(), b.mem.allocs.end(), (void*)b.tiles[m]),
-                               b.mem.allocs.end());
+        std::vector<long long> range(9, 0);
+        if (b.xcd_aware) {
+            // instances to 8 bins, largest first into the lightest bin; each
+            // bin lists its instances one after another
+            std::vector<int> order(b.B);
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+            std::vector<std::vector<int>> bins(8);
+            std::vector<int64_t> load(8, 0);
+            for (int i : order) {
+                const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                bins[j].push_back(i);
+                load[j] += cost[i];
+            }
+            for (int j = 0; j < 8; ++j) {
+                range[j] = (long long)v.size();
+                for (int i : bins[j]) v.insert(v.end(), per[i].begin(), per[i].end());
+            }
+            range[8] = (long long)v.size();
+        } else {
+            // all tiles, largest first, so the round-robin walk of the
+            // persistent grid approximates longest-processing-time-first
+            std::vector<std::pair<int64_t, ExaTile>> all;
+            for (int i = 0; i < b.B; ++i)
+                for (auto& t : per[i]) {
+                    const Model& M = b.models[i]->impl;
+                    const bool hess = t.pat >= 64;
+                    const int code = t.pat % 64;
+                    int64_t pc = 0;
+                    for (const Unit& u : units_for(M, hess ? M_HESS : M_JAC, b.fuse))
+                        if (u.code == code)
+                            for (int p : u.members) pc += point_cost(M.pats[p], hess ? M_HESS : M_JAC);
+                    all.emplace_back(t.count * pc, t);
+                }
+            std::stable_sort(all.begin(), all.end(),
+                             [](const auto& a, const auto& c) { return a.first > c.first; });
+            for (auto& e : all) v.push_back(e.second);
         }
+        for (size_t i = 0; i < v.size(); ++i) v[i].slot = (int64_t)i;
+        b.mem.release(b.tiles[m]);
+        b.mem.release(b.xcd_ranges[m]);
         b.tiles[m] = (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
         b.ntiles[m] = (int64_t)v.size();
+        b.xcd_ranges[m] = b.xcd_aware ? (long long*)b.mem.upload(range.data(), range.size() * sizeof(long long))
+                                      : nullptr;
     }
     b.tiles_epl = epl;
 }
@@ -122,7 +164,9 @@ void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, doubl
     c.out0 = j;
     c.out1 = h;
     c.persistent = 1;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(b.grid, nt));
+    c.xcd_range = b.xcd_ranges[mask];
+    int64_t grid = std::max<int64_t>(8, std::min<int64_t>(b.grid, nt));
+    grid = (grid + 7) / 8 * 8;  // a multiple of 8 (one share per XCD)
     void* args[] = {&c};
     hip_check(hipModuleLaunchKernel(b.module->fn_jh, (unsigned)grid, 1, 1, (unsigned)b.block, 1, 1, 0, s,
                                     args, nullptr),
@@ -213,9 +257,11 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             if (opt->epl) b->epl = opt->epl;
             b->grid = opt->grid;
             b->use_graph = opt->use_graph != 0;
+            b->fuse = opt->fuse != 0;
+            b->xcd_aware = opt->xcd_aware != 0;
         }
-        if (b->block != 64 && b->block != 128 && b->block != 256 && b->block != 512)
-            fail(EXA_EINVAL, "block must be 64, 128, 256 or 512");
+        if (b->block != 64 && b->block != 128 && b->block != 256)
+            fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
         int dev = 0;
         hip_check(hipGetDevice(&dev), "hipGetDevice");
@@ -224,7 +270,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         b->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         if (b->grid <= 0) b->grid = (int64_t)b->cus * 8;
         const Model& M0 = models[0]->impl;
-        b->module = M0.block == b->block ? M0.dev->module : compile_module(generate_source(M0, b->block));
+        b->module = M0.dev->module;  // every instance runs the same generated code
 
         std::vector<ExaInstDev> inst(B);
         b->offsets.assign(4 * (B + 1), 0);
@@ -268,6 +314,24 @@ exa_status exa_batch_schedule(const exa_batch* b, int64_t* out5) {
         out5[2] = b->grid;
         out5[3] = b->ntiles[3];
         out5[4] = b->tuned_ns;
+    });
+}
+
+exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes) {
+    return guard([&] {
+        if (!b) fail(EXA_EINVAL, "null batch");
+        std::vector<int> modes;
+        if (mask & EXA_CB_JAC) modes.push_back(M_JAC);
+        if (mask & EXA_CB_HESS) modes.push_back(M_HESS);
+        int64_t rd = 0, wr = 0;
+        for (int i = 0; i < b->B; ++i) {
+            int64_t r = 0, w = 0;
+            kernel_bytes(b->models[i]->impl, modes, b->fuse, r, w);
+            rd += r;
+            wr += w;
+        }
+        if (read_bytes) *read_bytes = rd;
+        if (write_bytes) *write_bytes = wr;
     });
 }
 

@@ -1,21 +1,29 @@
 // Lowering of pattern trees to straight-line gfx950 code (Sec. 6.2, Sec. 7.2.1).
 //
 // For every callback ("mode") one kernel is generated.  A workgroup takes one
-// tile (pattern, first data point, count) from a tile list; each lane runs the
+// tile (unit, first data point, count) from a tile list; each lane runs the
 // whole evaluation of one data point at a time: coalesced struct-of-arrays
 // loads, gathers of x, the forward sweep, and depending on the mode a reverse
 // sweep (gradient, Jacobian rows), a forward tangent (J v), or
-// forward-over-reverse (Hessian columns, H v, parameter adjoint).  All sweeps
-// are emitted as scalar code with structural zeros and ones removed, so only
-// the work a pattern really needs survives (Sec. 7.2.2 affine nodes).  Results
-// of a lane go to its own disjoint slice (Sec. 5.3.2); multi-entry slices are
-// staged through LDS so that the workgroup writes them with contiguous stores.
+// forward-over-reverse (Hessian columns, H v, parameter adjoint).
+//
+// A unit is one pattern, or several patterns declared over the same data
+// arrays evaluated in the same lane (their loads, gathers and common
+// subexpressions are then shared: the cross-pattern fusion the paper points
+// to in Sec. 8.3).  All sweeps are emitted as scalar SSA statements with the
+// structural zeros and ones folded away (Sec. 7.2.2 affine nodes); a liveness
+// pass keeps only the statements that reach an output, and records which
+// inputs a unit really reads.  Results of a lane go to its own disjoint slice
+// (Sec. 5.3.2); multi-entry slices are staged through LDS so that the
+// workgroup writes contiguous memory.
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <map>
 #include <set>
 #include <sstream>
+#include <unordered_map>
 
 #include "exa_internal.h"
 
@@ -42,17 +50,46 @@ std::string lit(double v) {
 
 bool is_unary(int op) { return op >= EXA_OP_NEG && op <= EXA_OP_EXPM1; }
 
-// Emits SSA statements and folds the literals 0, 1, -1.
-struct Em {
-    std::ostringstream& os;
-    int& ntmp;
-    std::string ind;
-    Em(std::ostringstream& o, int& n, std::string i) : os(o), ntmp(n), ind(std::move(i)) {}
+// ---------------------------------------------------------------------------
+// Statement recorder: SSA definitions, folding of the literals 0, 1, -1, and
+// liveness from the outputs back to the loads.
+struct Stmt {
+    std::string type, name, expr;
+    std::vector<int> deps;
+    bool out = false;
+};
 
-    std::string def(const std::string& e) {
-        std::string n = "t" + std::to_string(ntmp++);
-        os << ind << "const double " << n << " = " << e << ";\n";
-        return n;
+struct Em {
+    std::vector<Stmt> st;
+    std::unordered_map<std::string, int> byname;
+    int& ntmp;
+    explicit Em(int& n) : ntmp(n) {}
+
+    std::vector<int> deps_of(const std::string& e) const {
+        std::vector<int> d;
+        for (size_t i = 0; i < e.size();) {
+            if (std::isalpha((unsigned char)e[i]) || e[i] == '_') {
+                size_t j = i;
+                while (j < e.size() && (std::isalnum((unsigned char)e[j]) || e[j] == '_')) ++j;
+                auto it = byname.find(e.substr(i, j - i));
+                if (it != byname.end()) d.push_back(it->second);
+                i = j;
+            } else {
+                ++i;
+            }
+        }
+        return d;
+    }
+    std::string named(const std::string& type, const std::string& name, const std::string& e) {
+        Stmt s{type, name, e, deps_of(e), false};
+        st.push_back(s);
+        byname[name] = (int)st.size() - 1;
+        return name;
+    }
+    std::string def(const std::string& e) { return named("double", "t" + std::to_string(ntmp++), e); }
+    void out(const std::string& lhs, const std::string& e) {
+        Stmt s{"", lhs, e, deps_of(e), true};
+        st.push_back(s);
     }
     std::string mul(const std::string& a, const std::string& b) {
         if (a == Z || b == Z) return Z;
@@ -78,19 +115,42 @@ struct Em {
         if (a == MONE) return ONE;
         return def("-" + a);
     }
+    // Emit live statements; returns the set of live names.
+    std::set<std::string> emit(std::ostream& os, const std::string& ind) const {
+        std::vector<char> live(st.size(), 0);
+        for (size_t i = st.size(); i-- > 0;) {
+            if (st[i].out) live[i] = 1;
+            if (live[i])
+                for (int d : st[i].deps) live[d] = 1;
+        }
+        std::set<std::string> names;
+        for (size_t i = 0; i < st.size(); ++i) {
+            if (!live[i]) continue;
+            const Stmt& s = st[i];
+            if (s.out) {
+                os << ind << s.name << " = " << s.expr << ";\n";
+            } else {
+                os << ind << "const " << s.type << " " << s.name << " = " << s.expr << ";\n";
+                names.insert(s.name);
+            }
+        }
+        return names;
+    }
 };
 
-struct Sweep {
-    // per-node symbolic quantities
-    std::vector<std::string> val, d1, d2;       // unary: F', F''; binary: dA, dB
-    std::vector<std::string> daa, dab, dbb;     // binary second partials
+enum SeedKind { SEED_DIR, SEED_VEC };
+
+// Names of a pattern's inputs inside a unit (group-level loads).
+struct Names {
+    std::vector<std::string> x, v, ix, p;  // per var slot / param slot
+    std::string wgt;
 };
 
-enum SeedKind { SEED_NONE, SEED_DIR, SEED_VEC };
-
+// ---------------------------------------------------------------------------
+// Sweeps over one pattern tree.
 class PatternCg {
   public:
-    PatternCg(const Pattern& P, int mode) : P_(P), mode_(mode), t_(P.nodes) {
+    PatternCg(const Pattern& P, int mode, Em& e, const Names& nm) : P_(P), mode_(mode), t_(P.nodes), e_(e), nm_(nm) {
         const size_t n = t_.size();
         hasvar_.assign(n, 0);
         haspar_.assign(n, 0);
@@ -103,146 +163,103 @@ class PatternCg {
         }
     }
 
-    // Body evaluated for one data point; defines the outputs named o0..o{n-1}
-    // (or "res" for value modes).  Variables in scope: k, P, I, C, X, V, Y, TH.
-    std::string body(int& ntmp) {
-        std::ostringstream os;
-        Em e(os, ntmp, "            ");
-        loads(e);
+    // Records the statements of this pattern; outputs go to `out`[s] (array
+    // modes) or to `out` itself (scalar modes).
+    void body(const std::string& out) {
         const bool second = mode_ == M_HESS || mode_ == M_HPROD || mode_ == M_ADJ;
         const bool first = mode_ != M_OBJ && mode_ != M_CONS;
-        forward(e, first, second);
+        forward(first, second);
         const int root = (int)t_.size() - 1;
+        auto slot = [&](int s) { return out + "[" + std::to_string(s) + "]"; };
         switch (mode_) {
             case M_OBJ:
             case M_CONS:
-                os << e.ind << "res = " << S_.val[root] << ";\n";
+                e_.out(out, val_[root]);
                 break;
             case M_GRAD:
             case M_JAC:
             case M_JTPROD: {
-                std::string seed = mode_ == M_JTPROD ? "wgt" : ONE;
-                std::vector<std::string> J(P_.o1step(), Z), Pacc;
-                std::vector<std::string> adj;
-                reverse(e, seed, adj, J, Pacc, false);
-                for (int s = 0; s < P_.o1step(); ++s) os << e.ind << "o[" << s << "] = " << J[s] << ";\n";
+                std::vector<std::string> J(P_.o1step(), Z), Pacc, adj;
+                reverse(mode_ == M_JTPROD ? nm_.wgt : ONE, adj, J, Pacc, false);
+                for (int s = 0; s < P_.o1step(); ++s) e_.out(slot(s), J[s]);
                 break;
             }
             case M_JPROD: {
                 std::vector<std::string> tg;
-                tangent(e, SEED_VEC, -1, tg);
-                os << e.ind << "res = " << tg[root] << ";\n";
+                tangent(SEED_VEC, -1, tg);
+                e_.out(out, tg[root]);
                 break;
             }
             case M_HESS:
-                hessian(e);
+                hessian(slot);
                 break;
             case M_HPROD: {
                 std::vector<std::string> J(P_.o1step(), Z), Pacc, adj;
-                reverse(e, "wgt", adj, J, Pacc, false);
+                reverse(nm_.wgt, adj, J, Pacc, false);
                 std::vector<std::string> tg;
-                tangent(e, SEED_VEC, -1, tg);
+                tangent(SEED_VEC, -1, tg);
                 std::vector<std::string> Hc(P_.o1step(), Z), Pt;
-                reverse_tangent(e, adj, tg, Hc, Pt, false);
-                for (int s = 0; s < P_.o1step(); ++s) os << e.ind << "o[" << s << "] = " << Hc[s] << ";\n";
+                reverse_tangent(adj, tg, Hc, Pt, false);
+                for (int s = 0; s < P_.o1step(); ++s) e_.out(slot(s), Hc[s]);
                 break;
             }
             case M_ADJ: {
                 std::vector<std::string> J(P_.o1step(), Z), Pacc(P_.pstep(), Z), adj;
-                reverse(e, "wgt", adj, J, Pacc, true);
+                reverse(nm_.wgt, adj, J, Pacc, true);
                 std::vector<std::string> tg;
-                tangent(e, SEED_VEC, -1, tg);
+                tangent(SEED_VEC, -1, tg);
                 std::vector<std::string> Hc(P_.o1step(), Z), Pt(P_.pstep(), Z);
-                reverse_tangent(e, adj, tg, Hc, Pt, true);
-                for (int s = 0; s < P_.pstep(); ++s) os << e.ind << "o[" << s << "] = " << Pt[s] << ";\n";
+                reverse_tangent(adj, tg, Hc, Pt, true);
+                for (int s = 0; s < P_.pstep(); ++s) e_.out(slot(s), Pt[s]);
                 break;
             }
             default:
                 break;
         }
-        return os.str();
     }
-
-    bool needs_weight() const { return mode_ == M_HESS || mode_ == M_HPROD || mode_ == M_ADJ || mode_ == M_JTPROD; }
 
   private:
     const Pattern& P_;
     int mode_;
     const std::vector<TNode>& t_;
+    Em& e_;
+    const Names& nm_;
     std::vector<char> hasvar_, haspar_;
-    Sweep S_;
+    std::vector<std::string> val_, d1_, d2_, daa_, dab_, dbb_;  // unary: F', F''; binary: dA, dB
 
     bool rev_active(int i) const { return hasvar_[i] || (mode_ == M_ADJ && haspar_[i]); }
 
-    // Index of reference slot s (variables 0.., parameters after them); the
-    // offset comes from the instance's descriptor, not from the code.
-    std::string idx_expr(const RefKey& r, int s) const {
-        if (r.col < 0) return "P.roff[" + std::to_string(s) + "]";
-        return "(ic" + std::to_string(r.col) + " + P.roff[" + std::to_string(s) + "])";
-    }
-
-    void loads(Em& e) {
-        std::set<int> ic, fc;
-        for (auto& r : P_.vslots) if (r.col >= 0) ic.insert(r.col);
-        for (auto& r : P_.pslots) if (r.col >= 0) ic.insert(r.col);
-        for (auto& q : t_) if (q.op == EXA_OP_DATA) fc.insert(q.col);
-        const bool need_row = P_.kind != EXA_OBJ && needs_weight();
-        if (need_row && P_.kind == EXA_AUG) ic.insert(P_.row_icol);
-        for (int c : ic) e.os << e.ind << "const long long ic" << c << " = P.ic[" << c << "][k];\n";
-        for (int c : fc) e.os << e.ind << "const double fc" << c << " = P.fc[" << c << "][k];\n";
-        for (int s = 0; s < P_.o1step(); ++s) {
-            e.os << e.ind << "const long long ix" << s << " = " << idx_expr(P_.vslots[s], s) << ";\n";
-            e.os << e.ind << "const double x" << s << " = X[ix" << s << "];\n";
-        }
-        if (mode_ == M_JPROD || mode_ == M_HPROD || mode_ == M_ADJ)
-            for (int s = 0; s < P_.o1step(); ++s)
-                e.os << e.ind << "const double v" << s << " = V[ix" << s << "];\n";
-        for (int s = 0; s < P_.pstep(); ++s)
-            e.os << e.ind << "const double p" << s << " = TH[" << idx_expr(P_.pslots[s], P_.o1step() + s) << "];\n";
-        if (needs_weight()) {
-            if (P_.kind == EXA_OBJ) {
-                e.os << e.ind << "const double wgt = C.sigma;\n";
-            } else if (P_.kind == EXA_CON) {
-                e.os << e.ind << "const double wgt = Y[P.o0 + k];\n";
-            } else {
-                e.os << e.ind << "const double wgt = Y[P.tgt0 + ic" << P_.row_icol << " + P.row_off];\n";
-            }
-        }
-    }
-
-    // Forward sweep: values, and local partials of active children.
-    void forward(Em& e, bool first, bool second) {
+    void forward(bool first, bool second) {
         const size_t n = t_.size();
-        S_.val.assign(n, Z);
-        S_.d1.assign(n, Z);
-        S_.d2.assign(n, Z);
-        S_.daa.assign(n, Z);
-        S_.dab.assign(n, Z);
-        S_.dbb.assign(n, Z);
+        val_.assign(n, Z);
+        d1_.assign(n, Z);
+        d2_.assign(n, Z);
+        daa_.assign(n, Z);
+        dab_.assign(n, Z);
+        dbb_.assign(n, Z);
         for (size_t i = 0; i < n; ++i) {
             const TNode& q = t_[i];
-            auto& v = S_.val[i];
             switch (q.op) {
-                case EXA_OP_CONST: v = lit(q.val); continue;
-                case EXA_OP_DATA: v = "fc" + std::to_string(q.col); continue;
-                case EXA_OP_VAR: v = "x" + std::to_string(q.slot); continue;
-                case EXA_OP_PARAM: v = "p" + std::to_string(q.slot); continue;
+                case EXA_OP_CONST: val_[i] = lit(q.val); continue;
+                case EXA_OP_DATA: val_[i] = "fc" + std::to_string(q.col); continue;
+                case EXA_OP_VAR: val_[i] = nm_.x[q.slot]; continue;
+                case EXA_OP_PARAM: val_[i] = nm_.p[q.slot]; continue;
                 default: break;
             }
-            if (is_unary(q.op)) {
-                unary(e, (int)i, first && rev_active(q.a), second && rev_active(q.a));
-            } else {
-                binary(e, (int)i, first, second);
-            }
+            if (is_unary(q.op))
+                unary((int)i, first && rev_active(q.a), second && rev_active(q.a));
+            else
+                binary((int)i, first, second);
         }
     }
 
-    void unary(Em& e, int i, bool f1, bool f2) {
+    void unary(int i, bool f1, bool f2) {
+        Em& e = e_;
         const TNode& q = t_[i];
-        const std::string u = S_.val[q.a];
-        std::string& v = S_.val[i];
-        std::string& d = S_.d1[i];
-        std::string& dd = S_.d2[i];
+        const std::string u = val_[q.a];
+        std::string& v = val_[i];
+        std::string& d = d1_[i];
+        std::string& dd = d2_[i];
         switch (q.op) {
             case EXA_OP_NEG:
                 v = e.neg(u);
@@ -331,14 +348,15 @@ class PatternCg {
         return true;
     }
 
-    void binary(Em& e, int i, bool first, bool second) {
+    void binary(int i, bool first, bool second) {
+        Em& e = e_;
         const TNode& q = t_[i];
-        const std::string u = S_.val[q.a], w = S_.val[q.b];
+        const std::string u = val_[q.a], w = val_[q.b];
         const bool ua = rev_active(q.a), wa = rev_active(q.b);
         const bool f1 = first && (ua || wa), f2 = second && (ua || wa);
-        std::string& v = S_.val[i];
-        std::string& dA = S_.d1[i];
-        std::string& dB = S_.d2[i];
+        std::string& v = val_[i];
+        std::string& dA = d1_[i];
+        std::string& dB = d2_[i];
         switch (q.op) {
             case EXA_OP_ADD:
                 v = e.add(u, w);
@@ -351,7 +369,7 @@ class PatternCg {
             case EXA_OP_MUL:
                 v = e.mul(u, w);
                 if (f1) { dA = w; dB = u; }
-                if (f2 && ua && wa) S_.dab[i] = ONE;
+                if (f2 && ua && wa) dab_[i] = ONE;
                 break;
             case EXA_OP_DIV: {
                 v = e.def(u + " / " + w);
@@ -359,8 +377,8 @@ class PatternCg {
                     const std::string iw = e.def("1.0 / " + w);
                     dA = iw;
                     if (wa) dB = e.def("-(" + v + " * " + iw + ")");
-                    if (f2 && ua && wa) S_.dab[i] = e.def("-(" + iw + " * " + iw + ")");
-                    if (f2 && wa) S_.dbb[i] = e.def("2.0 * " + v + " * " + iw + " * " + iw);
+                    if (f2 && ua && wa) dab_[i] = e.def("-(" + iw + " * " + iw + ")");
+                    if (f2 && wa) dbb_[i] = e.def("2.0 * " + v + " * " + iw + " * " + iw);
                 }
                 break;
             }
@@ -368,19 +386,22 @@ class PatternCg {
                 int n = 0;
                 if (!wa && small_int(t_[q.b], n)) {
                     v = e.def("exa_powi(" + u + ", " + std::to_string(n) + ")");
-                    if (f1 || f2) dA = e.def(std::to_string(n) + ".0 * exa_powi(" + u + ", " + std::to_string(n - 1) + ")");
-                    if (f2) S_.daa[i] = (n - 1 == 0) ? Z
-                        : e.def(std::to_string(n * (n - 1)) + ".0 * exa_powi(" + u + ", " + std::to_string(n - 2) + ")");
+                    if (f1 || f2)
+                        dA = e.def(std::to_string(n) + ".0 * exa_powi(" + u + ", " + std::to_string(n - 1) + ")");
+                    if (f2)
+                        daa_[i] = (n - 1 == 0) ? Z
+                                  : e.def(std::to_string(n * (n - 1)) + ".0 * exa_powi(" + u + ", " +
+                                          std::to_string(n - 2) + ")");
                 } else if (!wa) {
                     v = e.def("pow(" + u + ", " + w + ")");
                     if (f1 || f2) dA = e.def(w + " * pow(" + u + ", " + w + " - 1.0)");
-                    if (f2) S_.daa[i] = e.def(w + " * (" + w + " - 1.0) * pow(" + u + ", " + w + " - 2.0)");
+                    if (f2) daa_[i] = e.def(w + " * (" + w + " - 1.0) * pow(" + u + ", " + w + " - 2.0)");
                 } else if (!ua) {
                     v = e.def("pow(" + u + ", " + w + ")");
                     if (f1 || f2) {
                         const std::string lu = e.def("log(" + u + ")");
                         dB = e.def(v + " * " + lu);
-                        if (f2) S_.dbb[i] = e.def(dB + " * " + lu);
+                        if (f2) dbb_[i] = e.def(dB + " * " + lu);
                     }
                 } else {
                     v = e.def("pow(" + u + ", " + w + ")");
@@ -390,9 +411,9 @@ class PatternCg {
                         dA = e.def(w + " * " + pm1);
                         dB = e.def(v + " * " + lu);
                         if (f2) {
-                            S_.daa[i] = e.def(w + " * (" + w + " - 1.0) * pow(" + u + ", " + w + " - 2.0)");
-                            S_.dab[i] = e.def(pm1 + " * (1.0 + " + w + " * " + lu + ")");
-                            S_.dbb[i] = e.def(dB + " * " + lu);
+                            daa_[i] = e.def(w + " * (" + w + " - 1.0) * pow(" + u + ", " + w + " - 2.0)");
+                            dab_[i] = e.def(pm1 + " * (1.0 + " + w + " * " + lu + ")");
+                            dbb_[i] = e.def(dB + " * " + lu);
                         }
                     }
                 }
@@ -401,14 +422,15 @@ class PatternCg {
             default:
                 fail(EXA_EINVAL, "codegen: unknown binary operator");
         }
-        if (!ua) { dA = Z; S_.daa[i] = Z; S_.dab[i] = Z; }
-        if (!wa) { dB = Z; S_.dbb[i] = Z; S_.dab[i] = Z; }
+        if (!ua) { dA = Z; daa_[i] = Z; dab_[i] = Z; }
+        if (!wa) { dB = Z; dbb_[i] = Z; dab_[i] = Z; }
     }
 
     // Reverse sweep: adjoint of every node from the root seed; var leaves
     // accumulate into J, param leaves (when with_par) into Pacc.
-    void reverse(Em& e, const std::string& seed, std::vector<std::string>& adj,
-                 std::vector<std::string>& J, std::vector<std::string>& Pacc, bool with_par) {
+    void reverse(const std::string& seed, std::vector<std::string>& adj, std::vector<std::string>& J,
+                 std::vector<std::string>& Pacc, bool with_par) {
+        Em& e = e_;
         const int n = (int)t_.size();
         adj.assign(n, Z);
         adj[n - 1] = seed;
@@ -418,38 +440,35 @@ class PatternCg {
             if (q.op == EXA_OP_VAR) { J[q.slot] = e.add(J[q.slot], a); continue; }
             if (q.op == EXA_OP_PARAM) { if (with_par) Pacc[q.slot] = e.add(Pacc[q.slot], a); continue; }
             if (q.a < 0 || a == Z) continue;
-            if (is_unary(q.op)) {
-                if (rev_active(q.a)) adj[q.a] = e.mul(a, S_.d1[i]);
-            } else {
-                if (rev_active(q.a)) adj[q.a] = e.mul(a, S_.d1[i]);
-                if (rev_active(q.b)) adj[q.b] = e.mul(a, S_.d2[i]);
-            }
+            if (rev_active(q.a)) adj[q.a] = e.mul(a, d1_[i]);
+            if (!is_unary(q.op) && rev_active(q.b)) adj[q.b] = e.mul(a, d2_[i]);
         }
     }
 
     // Forward tangent: SEED_DIR seeds 1 on var slot `dir`; SEED_VEC seeds v_s.
-    void tangent(Em& e, SeedKind kind, int dir, std::vector<std::string>& tg) {
+    void tangent(SeedKind kind, int dir, std::vector<std::string>& tg) {
+        Em& e = e_;
         const int n = (int)t_.size();
         tg.assign(n, Z);
         for (int i = 0; i < n; ++i) {
             const TNode& q = t_[i];
             if (q.op == EXA_OP_VAR) {
-                tg[i] = kind == SEED_DIR ? (q.slot == dir ? ONE : Z) : "v" + std::to_string(q.slot);
+                tg[i] = kind == SEED_DIR ? (q.slot == dir ? ONE : Z) : nm_.v[q.slot];
                 continue;
             }
             if (q.a < 0) continue;
-            if (is_unary(q.op)) {
-                tg[i] = e.mul(S_.d1[i], tg[q.a]);
-            } else {
-                tg[i] = e.add(e.mul(S_.d1[i], tg[q.a]), e.mul(S_.d2[i], tg[q.b]));
-            }
+            if (is_unary(q.op))
+                tg[i] = e.mul(d1_[i], tg[q.a]);
+            else
+                tg[i] = e.add(e.mul(d1_[i], tg[q.a]), e.mul(d2_[i], tg[q.b]));
         }
     }
 
     // Reverse sweep of the tangent (forward-over-reverse): the tangent of every
     // adjoint; var leaves accumulate into Hc, param leaves into Pt.
-    void reverse_tangent(Em& e, const std::vector<std::string>& adj, const std::vector<std::string>& tg,
+    void reverse_tangent(const std::vector<std::string>& adj, const std::vector<std::string>& tg,
                          std::vector<std::string>& Hc, std::vector<std::string>& Pt, bool with_par) {
+        Em& e = e_;
         const int n = (int)t_.size();
         std::vector<std::string> ta(n, Z);
         for (int i = n - 1; i >= 0; --i) {
@@ -459,13 +478,13 @@ class PatternCg {
             if (q.a < 0) continue;
             if (is_unary(q.op)) {
                 if (!rev_active(q.a)) continue;
-                const std::string td = e.mul(S_.d2[i], tg[q.a]);
-                ta[q.a] = e.add(e.mul(ta[i], S_.d1[i]), e.mul(adj[i], td));
+                const std::string td = e.mul(d2_[i], tg[q.a]);
+                ta[q.a] = e.add(e.mul(ta[i], d1_[i]), e.mul(adj[i], td));
             } else {
-                const std::string tdA = e.add(e.mul(S_.daa[i], tg[q.a]), e.mul(S_.dab[i], tg[q.b]));
-                const std::string tdB = e.add(e.mul(S_.dab[i], tg[q.a]), e.mul(S_.dbb[i], tg[q.b]));
-                if (rev_active(q.a)) ta[q.a] = e.add(e.mul(ta[i], S_.d1[i]), e.mul(adj[i], tdA));
-                if (rev_active(q.b)) ta[q.b] = e.add(e.mul(ta[i], S_.d2[i]), e.mul(adj[i], tdB));
+                const std::string tdA = e.add(e.mul(daa_[i], tg[q.a]), e.mul(dab_[i], tg[q.b]));
+                const std::string tdB = e.add(e.mul(dab_[i], tg[q.a]), e.mul(dbb_[i], tg[q.b]));
+                if (rev_active(q.a)) ta[q.a] = e.add(e.mul(ta[i], d1_[i]), e.mul(adj[i], tdA));
+                if (rev_active(q.b)) ta[q.b] = e.add(e.mul(ta[i], d2_[i]), e.mul(adj[i], tdB));
             }
         }
     }
@@ -476,12 +495,12 @@ class PatternCg {
         const int k = P_.o1step();
         std::vector<int> best;
         int best_n = k + 1;
-        if (k > 20) {  // fall back to every variable
+        if (k > 20) {
             for (int s = 0; s < k; ++s) best.push_back(s);
             return best;
         }
         for (unsigned mask = 0; mask < (1u << k); ++mask) {
-            int cnt = __builtin_popcount(mask);
+            const int cnt = __builtin_popcount(mask);
             if (cnt >= best_n) continue;
             bool ok = true;
             for (auto& h : P_.hslots)
@@ -489,34 +508,35 @@ class PatternCg {
             if (!ok) continue;
             best_n = cnt;
             best.clear();
-            for (int s = 0; s < k; ++s) if ((mask >> s) & 1u) best.push_back(s);
+            for (int s = 0; s < k; ++s)
+                if ((mask >> s) & 1u) best.push_back(s);
         }
         return best;
     }
 
-    void hessian(Em& e) {
+    template <class SlotName>
+    void hessian(SlotName slot) {
         std::vector<std::string> J(P_.o1step(), Z), Pacc, adj;
-        reverse(e, "wgt", adj, J, Pacc, false);
-        const std::vector<int> D = directions();
+        reverse(nm_.wgt, adj, J, Pacc, false);
         std::map<int, std::vector<std::string>> col;  // direction -> column
-        for (int d : D) {
+        for (int d : directions()) {
             std::vector<std::string> tg, Hc(P_.o1step(), Z), Pt;
-            tangent(e, SEED_DIR, d, tg);
-            reverse_tangent(e, adj, tg, Hc, Pt, false);
+            tangent(SEED_DIR, d, tg);
+            reverse_tangent(adj, tg, Hc, Pt, false);
             col[d] = Hc;
         }
         for (int s = 0; s < P_.o2step(); ++s) {
             const int a = P_.hslots[s].first, b = P_.hslots[s].second;
-            std::string h = col.count(b) ? col[b][a] : col[a][b];
+            const std::string h = col.count(b) ? col[b][a] : col[a][b];
             const RefKey& ra = P_.vslots[a];
             const RefKey& rb = P_.vslots[b];
             // different slots over the same index column (or both literal)
             // have different offsets, so only different columns can alias
             const bool may_alias = a != b && ra.col != rb.col;
             if (may_alias && h != Z)
-                e.os << e.ind << "o[" << s << "] = (ix" << a << " == ix" << b << ") ? 2.0 * " << h << " : " << h << ";\n";
+                e_.out(slot(s), "(" + nm_.ix[a] + " == " + nm_.ix[b] + ") ? 2.0 * " + h + " : " + h);
             else
-                e.os << e.ind << "o[" << s << "] = " << h << ";\n";
+                e_.out(slot(s), h);
         }
     }
 };
@@ -530,9 +550,179 @@ int out_step(const Pattern& P, int mode) {
     }
 }
 
+bool scalar_mode(int mode) { return mode == M_OBJ || mode == M_CONS || mode == M_JPROD; }
+
 const char* mode_name(int m) {
     static const char* n[] = {"obj", "cons", "grad", "jac", "hess", "jprod", "jtprod", "hprod", "adj"};
     return n[m];
+}
+
+// Staging through LDS is used while a workgroup's slice fits in this many
+// doubles (64 KiB at the largest workgroup); wider patterns store directly.
+constexpr int kLdsCapDoubles = 8192;
+
+bool staged(const Pattern& P, int mode) { return out_step(P, mode) * EXA_BLOCK_MAX <= kLdsCapDoubles; }
+
+// Output destination of member P's slice for data point kb (first of the
+// workgroup's current points).
+std::string dest(const Pattern& P, int mode, const std::string& pd) {
+    const std::string st = std::to_string(out_step(P, mode));
+    switch (mode) {
+        case M_GRAD: return "C.out0 + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1 + kb * " + st;
+        case M_JAC: return "C.out0 + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1 + kb * " + st;
+        case M_JTPROD: return "C.out0 + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1 + kb * " + st;
+        case M_HPROD:
+            return "C.out0 + I.off[" + std::to_string(P.kind == EXA_OBJ ? EXA_OFF_FO_OBJ : EXA_OFF_FO_CON) +
+                   "] + " + pd + ".o1 + kb * " + st;
+        case M_HESS: return "C.out0 + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2 + kb * " + st;
+        case M_ADJ: return "C.out0 + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op + kb * " + st;
+        default: return "";
+    }
+}
+
+bool needs_weight(int mode) { return mode == M_HESS || mode == M_HPROD || mode == M_ADJ || mode == M_JTPROD; }
+
+// Generates the tile function of one unit; fills `live`.
+std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLive& live) {
+    const Group& G = M.groups[U.group];
+    const int m0 = G.members[0];  // owner of the shared column pointers
+    std::ostringstream os;
+    const std::string fn = std::string("unit_") + mode_name(mode) + "_" + std::to_string(U.code);
+    os << "__device__ __forceinline__ void " << fn
+       << "(const ExaCall& C, const ExaInstDev& I, const ExaTile& T, double* lds) {\n";
+    os << "    const ExaPatDev& P0 = I.pat[" << m0 << "];\n";
+    for (int p : U.members) os << "    const ExaPatDev& P" << p << "_ = I.pat[" << p << "];\n";
+    os << "    const double* __restrict__ X = C.x + I.off[" << EXA_OFF_X << "];\n";
+    os << "    const double* __restrict__ V = C.v + I.off[" << EXA_OFF_X << "];\n";
+    os << "    const double* __restrict__ Y = C.y + I.off[" << EXA_OFF_Y << "];\n";
+    os << "    const double* __restrict__ TH = I.theta;\n";
+    os << "    (void)X; (void)V; (void)Y; (void)TH; (void)P0;\n";
+    os << "    const int nthr = (int)blockDim.x;\n";
+    os << "    const long long kend = T.start + T.count;\n";
+    if (mode == M_OBJ) os << "    double acc = 0.0;\n";
+    os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
+    os << "        const long long k = kb + threadIdx.x;\n";
+    os << "        const int npts = (int)((kend - kb) < nthr ? (kend - kb) : nthr);\n";
+    for (int p : U.members) {
+        const Pattern& P = M.pats[p];
+        if (scalar_mode(mode))
+            os << "        double r" << p << " = 0.0;\n";
+        else
+            os << "        double o" << p << "[" << out_step(P, mode) << "] = {};\n";
+    }
+    os << "        if (k < kend) {\n";
+
+    // ---- statements: loads (all candidates), then every member's sweeps
+    Em e(ntmp);
+    std::set<int> icols, fcols;
+    for (int p : U.members) {
+        const Pattern& P = M.pats[p];
+        for (auto& r : P.vslots) if (r.col >= 0) icols.insert(r.col);
+        for (auto& r : P.pslots) if (r.col >= 0) icols.insert(r.col);
+        for (auto& q : P.nodes) if (q.op == EXA_OP_DATA) fcols.insert(q.col);
+        if (needs_weight(mode) && P.kind == EXA_AUG) icols.insert(P.row_icol);
+    }
+    for (int c : icols) e.named("long long", "ic" + std::to_string(c), "P0.ic[" + std::to_string(c) + "][k]");
+    for (int c : fcols) e.named("double", "fc" + std::to_string(c), "P0.fc[" + std::to_string(c) + "][k]");
+    std::set<int> vrefs, prefs;
+    for (int p : U.members) {
+        for (int r : M.pats[p].vg) vrefs.insert(r);
+        for (int r : M.pats[p].pg) prefs.insert(r);
+    }
+    const bool seeds = mode == M_JPROD || mode == M_HPROD || mode == M_ADJ;
+    for (int r : vrefs) {
+        const RefKey& k = G.vrefs[r];
+        const std::pair<int, int> src = G.vsrc[r];
+        const std::string off = "I.pat[" + std::to_string(G.members[src.first]) + "].roff[" +
+                                std::to_string(src.second) + "]";
+        const std::string idx = k.col < 0 ? off : "ic" + std::to_string(k.col) + " + " + off;
+        e.named("long long", "ix" + std::to_string(r), idx);
+        e.named("double", "x" + std::to_string(r), "X[ix" + std::to_string(r) + "]");
+        if (seeds) e.named("double", "v" + std::to_string(r), "V[ix" + std::to_string(r) + "]");
+    }
+    for (int r : prefs) {
+        const RefKey& k = G.prefs[r];
+        const std::pair<int, int> src = G.psrc[r];
+        const int member = G.members[src.first];
+        // a parameter slot's offset sits after the member's variable slots
+        const std::string off = "I.pat[" + std::to_string(member) + "].roff[" +
+                                std::to_string(M.pats[member].o1step() + src.second) + "]";
+        const std::string idx = k.col < 0 ? off : "ic" + std::to_string(k.col) + " + " + off;
+        e.named("double", "p" + std::to_string(r), "TH[" + idx + "]");
+    }
+    for (int p : U.members) {
+        const Pattern& P = M.pats[p];
+        Names nm;
+        for (int s = 0; s < P.o1step(); ++s) {
+            nm.x.push_back("x" + std::to_string(P.vg[s]));
+            nm.v.push_back("v" + std::to_string(P.vg[s]));
+            nm.ix.push_back("ix" + std::to_string(P.vg[s]));
+        }
+        for (int s = 0; s < P.pstep(); ++s) nm.p.push_back("p" + std::to_string(P.pg[s]));
+        if (needs_weight(mode)) {
+            const std::string pd = "P" + std::to_string(p) + "_";
+            std::string w;
+            if (P.kind == EXA_OBJ)
+                w = "C.sigma";
+            else if (P.kind == EXA_CON)
+                w = "Y[" + pd + ".o0 + k]";
+            else
+                w = "Y[" + pd + ".tgt0 + ic" + std::to_string(P.row_icol) + " + " + pd + ".row_off]";
+            nm.wgt = e.named("double", "w" + std::to_string(p), w);
+        }
+        PatternCg cg(P, mode, e, nm);
+        cg.body(scalar_mode(mode) ? "r" + std::to_string(p) : "o" + std::to_string(p));
+    }
+    const std::set<std::string> names = e.emit(os, "            ");
+    os << "        }\n";
+
+    // ---- liveness record
+    for (int c : icols) if (names.count("ic" + std::to_string(c))) live.icols.push_back(c);
+    for (int c : fcols) if (names.count("fc" + std::to_string(c))) live.fcols.push_back(c);
+    for (int r : vrefs) {
+        if (names.count("x" + std::to_string(r))) live.vrefs.push_back(r);
+        if (names.count("v" + std::to_string(r))) live.vseeds.push_back(r);
+    }
+    for (int r : prefs) if (names.count("p" + std::to_string(r))) live.prefs.push_back(r);
+    for (int p : U.members) {
+        // an objective's weight is the scalar sigma, not a per-point load
+        if (M.pats[p].kind != EXA_OBJ && names.count("w" + std::to_string(p))) live.weights++;
+        live.outputs += out_step(M.pats[p], mode);
+    }
+
+    // ---- outputs
+    switch (mode) {
+        case M_OBJ: {
+            std::string sum;
+            for (int p : U.members) sum += (sum.empty() ? "" : " + ") + std::string("r") + std::to_string(p);
+            os << "        acc += exa_block_sum(" << sum << ", lds);\n";
+            break;
+        }
+        case M_CONS:
+        case M_JPROD:
+            for (int p : U.members) {
+                const Pattern& P = M.pats[p];
+                const std::string pd = "P" + std::to_string(p) + "_";
+                if (P.kind == EXA_CON)
+                    os << "        if (k < kend) C.out0[I.off[" << EXA_OFF_ROWS << "] + " << pd << ".o0 + k] = r" << p
+                       << ";\n";
+                else
+                    os << "        if (k < kend) C.out1[I.off[" << EXA_OFF_AUG << "] + " << pd << ".o0 + k] = r" << p
+                       << ";\n";
+            }
+            break;
+        default:
+            for (int p : U.members) {
+                const Pattern& P = M.pats[p];
+                const std::string pd = "P" + std::to_string(p) + "_";
+                os << "        " << (staged(P, mode) ? "exa_store<" : "exa_store_direct<") << out_step(P, mode)
+                   << ">(" << dest(P, mode, pd) << ", o" << p << ", npts, lds);\n";
+            }
+    }
+    os << "    }\n";
+    if (mode == M_OBJ) os << "    if (threadIdx.x == 0) C.out0[I.off[" << EXA_OFF_TILE << "] + T.slot] = acc;\n";
+    os << "}\n";
+    return os.str();
 }
 
 }  // namespace
@@ -553,27 +743,50 @@ bool pattern_in_mode(const Pattern& P, int mode) {
     }
 }
 
-// Staging through LDS is used while a workgroup's slice fits in this many
-// doubles (64 KiB); wider patterns store their slices directly.
-constexpr int kLdsCapDoubles = 8192;
-
-bool staged(const Pattern& P, int mode, int block) {
-    return out_step(P, mode) * block <= kLdsCapDoubles;
+std::vector<Unit> units_for(const Model& M, int mode, bool fused) {
+    std::vector<Unit> out;
+    for (size_t g = 0; g < M.groups.size(); ++g) {
+        const Group& G = M.groups[g];
+        std::vector<int> in;
+        for (int p : G.members)
+            if (pattern_in_mode(M.pats[p], mode)) in.push_back(p);
+        if (in.empty()) continue;
+        if (fused && in.size() > 1) {
+            Unit u;
+            u.code = EXA_MAX_PATTERNS + (int)g;
+            u.group = (int)g;
+            u.members = in;
+            u.ndata = G.ndata;
+            out.push_back(u);
+        } else {
+            for (int p : in) {
+                Unit u;
+                u.code = p;
+                u.group = (int)g;
+                u.members = {p};
+                u.ndata = M.pats[p].ndata;
+                out.push_back(u);
+            }
+        }
+    }
+    // declaration order of the first member keeps tile lists stable
+    std::stable_sort(out.begin(), out.end(),
+                     [](const Unit& a, const Unit& b) { return a.members[0] < b.members[0]; });
+    return out;
 }
 
-int mode_lds_doubles(const Model& M, int mode, int block) {
+int mode_lds_doubles(const Model& M, int mode) {
     int st = 1;
     for (auto& P : M.pats)
-        if (pattern_in_mode(P, mode) && staged(P, mode, block)) st = std::max(st, out_step(P, mode));
-    return st * block;
+        if (pattern_in_mode(P, mode) && staged(P, mode)) st = std::max(st, out_step(P, mode));
+    return st * EXA_BLOCK_MAX;
 }
 
 std::string kernel_name(int mode) { return std::string("exa_k_") + mode_name(mode); }
 
-std::string generate_source(const Model& M, int block) {
+std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live) {
     std::ostringstream os;
     os << "// generated: straight-line evaluation kernels for one pattern set\n";
-    os << "#define EXA_BLOCK " << block << "\n";
     os << EXA_STR(EXA_DEVICE_STRUCTS) << "\n";
     os << "static_assert(sizeof(ExaPatDev) == " << sizeof(ExaPatDev) << ", \"layout\");\n";
     os << "static_assert(sizeof(ExaInstDev) == " << sizeof(ExaInstDev) << ", \"layout\");\n";
@@ -598,7 +811,7 @@ __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double
     for (int s = 0; s < ST; ++s) lds[threadIdx.x * ST + s] = o[s];
     __syncthreads();
     const int n = npts * ST;
-    for (int i = threadIdx.x; i < n; i += EXA_BLOCK) dst[i] = lds[i];
+    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) dst[i] = lds[i];
     __syncthreads();
 }
 // Direct (unstaged) variant for slices too wide for LDS.
@@ -613,8 +826,7 @@ __device__ __forceinline__ void exa_store_direct(double* __restrict__ dst, const
 __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
     lds[threadIdx.x] = v;
     __syncthreads();
-#pragma unroll
-    for (int s = EXA_BLOCK / 2; s > 0; s >>= 1) {
+    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
         __syncthreads();
     }
@@ -625,77 +837,18 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
 )";
     int ntmp = 0;
     for (int mode = 0; mode < M_COUNT; ++mode) {
-        std::vector<int> members;
-        for (size_t p = 0; p < M.pats.size(); ++p)
-            if (pattern_in_mode(M.pats[p], mode)) members.push_back((int)p);
-        // tile functions
-        for (int p : members) {
-            const Pattern& P = M.pats[p];
-            PatternCg cg(P, mode);
-            const int st = out_step(P, mode);
-            os << "__device__ __forceinline__ void tile_" << mode_name(mode) << "_" << p
-               << "(const ExaCall& C, const ExaInstDev& I, const ExaTile& T, double* lds) {\n";
-            os << "    const ExaPatDev& P = I.pat[" << p << "];\n";
-            os << "    const double* __restrict__ X = C.x + I.off[" << EXA_OFF_X << "];\n";
-            os << "    const double* __restrict__ V = C.v + I.off[" << EXA_OFF_X << "];\n";
-            os << "    const double* __restrict__ Y = C.y + I.off[" << EXA_OFF_Y << "];\n";
-            os << "    const double* __restrict__ TH = I.theta;\n";
-            os << "    (void)X; (void)V; (void)Y; (void)TH;\n";
-            os << "    const long long kend = T.start + T.count;\n";
-            if (mode == M_OBJ) os << "    double acc = 0.0;\n";
-            os << "    for (long long kb = T.start; kb < kend; kb += EXA_BLOCK) {\n";
-            os << "        const long long k = kb + threadIdx.x;\n";
-            os << "        const int npts = (int)((kend - kb) < EXA_BLOCK ? (kend - kb) : EXA_BLOCK);\n";
-            const bool scalar_out = mode == M_OBJ || mode == M_CONS || mode == M_JPROD;
-            const std::string store = staged(P, mode, block) ? "exa_store<" : "exa_store_direct<";
-            if (scalar_out) os << "        double res = 0.0;\n";
-            else os << "        double o[" << st << "];\n";
-            os << "        if (k < kend) {\n";
-            os << cg.body(ntmp);
-            os << "        } else {\n";
-            if (!scalar_out) os << "            for (int s = 0; s < " << st << "; ++s) o[s] = 0.0;\n";
-            os << "        }\n";
-            switch (mode) {
-                case M_OBJ:
-                    os << "        acc += exa_block_sum(res, lds);\n";
-                    break;
-                case M_CONS:
-                case M_JPROD:
-                    if (P.kind == EXA_CON)
-                        os << "        if (k < kend) C.out0[I.off[" << EXA_OFF_ROWS << "] + P.o0 + k] = res;\n";
-                    else
-                        os << "        if (k < kend) C.out1[I.off[" << EXA_OFF_AUG << "] + P.o0 + k] = res;\n";
-                    break;
-                case M_GRAD:
-                    os << "        " << store << st << ">(C.out0 + I.off[" << EXA_OFF_FO_OBJ << "] + P.o1 + kb * " << st << ", o, npts, lds);\n";
-                    break;
-                case M_JAC:
-                    os << "        " << store << st << ">(C.out0 + I.off[" << EXA_OFF_JAC << "] + P.o1 + kb * " << st << ", o, npts, lds);\n";
-                    break;
-                case M_JTPROD:
-                    os << "        " << store << st << ">(C.out0 + I.off[" << EXA_OFF_FO_CON << "] + P.o1 + kb * " << st << ", o, npts, lds);\n";
-                    break;
-                case M_HPROD:
-                    os << "        " << store << st << ">(C.out0 + I.off[" << (P.kind == EXA_OBJ ? EXA_OFF_FO_OBJ : EXA_OFF_FO_CON)
-                       << "] + P.o1 + kb * " << st << ", o, npts, lds);\n";
-                    break;
-                case M_HESS:
-                    os << "        " << store << st << ">(C.out0 + I.off[" << EXA_OFF_HESS << "] + P.o2 + kb * " << st << ", o, npts, lds);\n";
-                    break;
-                case M_ADJ:
-                    os << "        " << store << st << ">(C.out0 + I.off[" << EXA_OFF_PAR << "] + P.op + kb * " << st << ", o, npts, lds);\n";
-                    break;
-            }
-            os << "    }\n";
-            if (mode == M_OBJ)
-                os << "    if (threadIdx.x == 0) C.out0[I.off[" << EXA_OFF_TILE << "] + T.slot] = acc;\n";
-            os << "}\n";
+        // units of both schedules (separate patterns, fused groups)
+        std::map<int, Unit> all;
+        for (int fused = 0; fused < 2; ++fused)
+            for (auto& u : units_for(M, mode, fused != 0)) all[u.code] = u;
+        for (auto& kv : all) {
+            UnitLive L;
+            os << unit_tile(M, mode, kv.second, ntmp, L);
+            if (live) (*live)[{mode, kv.first}] = L;
         }
-        // kernel
-        const int lds = mode_lds_doubles(M, mode, block);
-        os << "extern \"C\" __global__ void __launch_bounds__(EXA_BLOCK) " << kernel_name(mode)
+        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") " << kernel_name(mode)
            << "(ExaCall C) {\n";
-        os << "    __shared__ double lds[" << lds << "];\n";
+        os << "    __shared__ double lds[" << mode_lds_doubles(M, mode) << "];\n";
         os << "    (void)lds;\n";
         os << "    long long w = blockIdx.x;\n";
         os << "    for (;;) {\n";
@@ -711,8 +864,9 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
         os << "        const ExaTile T = C.tiles[t];\n";
         os << "        const ExaInstDev& I = C.inst[T.inst];\n";
         os << "        switch (T.pat) {\n";
-        for (int p : members)
-            os << "            case " << p << ": tile_" << mode_name(mode) << "_" << p << "(C, I, T, lds); break;\n";
+        for (auto& kv : all)
+            os << "            case " << kv.first << ": unit_" << mode_name(mode) << "_" << kv.first
+               << "(C, I, T, lds); break;\n";
         os << "            default: break;\n";
         os << "        }\n";
         os << "        if (!C.persistent) return;\n";
@@ -721,24 +875,36 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
         os << "}\n";
     }
     // Jacobian and Hessian values in one launch (batched evaluation): tile
-    // pat < 32 is a Jacobian tile of pattern pat, pat >= 32 a Hessian tile of
-    // pattern pat - 32; Jacobian values go to out0, Hessian values to out1.
+    // codes below 64 are Jacobian units, codes 64 + u Hessian unit u;
+    // Jacobian values go to out0, Hessian values to out1.
     {
-        const int lds = std::max(mode_lds_doubles(M, M_JAC, block), mode_lds_doubles(M, M_HESS, block));
-        os << "extern \"C\" __global__ void __launch_bounds__(EXA_BLOCK) exa_k_jh(ExaCall C) {\n";
+        const int lds = std::max(mode_lds_doubles(M, M_JAC), mode_lds_doubles(M, M_HESS));
+        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") exa_k_jh(ExaCall C) {\n";
         os << "    __shared__ double lds[" << lds << "];\n";
         os << "    (void)lds;\n";
         os << "    ExaCall H = C;\n";
         os << "    H.out0 = C.out1;\n";
-        os << "    for (long long w = blockIdx.x; w < C.ntiles; w += gridDim.x) {\n";
+        os << "    // workgroup b runs on XCD b % 8; with xcd_range, XCD j walks tiles\n";
+        os << "    // [xcd_range[j], xcd_range[j+1]) (grid is a multiple of 8)\n";
+        os << "    long long lo = 0, hi = C.ntiles, w0 = blockIdx.x, step = gridDim.x;\n";
+        os << "    if (C.xcd_range) {\n";
+        os << "        const int j = blockIdx.x % 8;\n";
+        os << "        lo = C.xcd_range[j];\n";
+        os << "        hi = C.xcd_range[j + 1];\n";
+        os << "        w0 = lo + blockIdx.x / 8;\n";
+        os << "        step = gridDim.x / 8;\n";
+        os << "    }\n";
+        os << "    for (long long w = w0; w < hi; w += step) {\n";
         os << "        const ExaTile T = C.tiles[w];\n";
         os << "        const ExaInstDev& I = C.inst[T.inst];\n";
         os << "        switch (T.pat) {\n";
-        for (size_t p = 0; p < M.pats.size(); ++p) {
-            if (pattern_in_mode(M.pats[p], M_JAC))
-                os << "            case " << p << ": tile_jac_" << p << "(C, I, T, lds); break;\n";
-            if (pattern_in_mode(M.pats[p], M_HESS))
-                os << "            case " << (p + EXA_MAX_PATTERNS) << ": tile_hess_" << p << "(H, I, T, lds); break;\n";
+        for (int mode : {M_JAC, M_HESS}) {
+            std::set<int> codes;
+            for (int fused = 0; fused < 2; ++fused)
+                for (auto& u : units_for(M, mode, fused != 0)) codes.insert(u.code);
+            for (int c : codes)
+                os << "            case " << (c + (mode == M_HESS ? 64 : 0)) << ": unit_" << mode_name(mode) << "_"
+                   << c << (mode == M_HESS ? "(H, I, T, lds)" : "(C, I, T, lds)") << "; break;\n";
         }
         os << "            default: break;\n";
         os << "        }\n";

@@ -3,6 +3,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -84,6 +85,7 @@ void set_last_error(const std::string& msg);
         double sigma;                                                            \
         int persistent;                                                          \
         int pad2;                                                                \
+        const long long* xcd_range;                                              \
     };
 
 EXA_DEVICE_STRUCTS
@@ -143,6 +145,10 @@ struct Pattern {
     int64_t row_off = 0;
     int64_t tgt0 = 0; // AUG: first row of the target block
     std::vector<double> lcon, ucon;
+    // data-set group (patterns over the same data arrays) and the group-level
+    // reference each of this pattern's var / param slots maps to
+    int group = -1;
+    std::vector<int> vg, pg;
 
     int o1step() const { return (int)vslots.size(); }
     int o2step() const { return (int)hslots.size(); }
@@ -160,6 +166,34 @@ struct Pattern {
     }
 };
 
+// Patterns declared over the very same data arrays (same ndata, same column
+// arrays in the same order).  Their evaluations can share one lane: the data
+// loads, the gathers of x and common subexpressions are then done once.
+struct Group {
+    std::vector<int> members;          // pattern positions, declaration order
+    std::vector<RefKey> vrefs, prefs;  // distinct references over all members
+    std::vector<std::pair<int, int>> vsrc, psrc;  // first (member, slot) of each
+    int64_t ndata = 0;
+};
+
+// A unit of generated code for one callback: one pattern, or the members of
+// a group evaluated together.  Tile codes: pattern p -> p, group g -> 32 + g.
+struct Unit {
+    int code = 0;
+    int group = 0;
+    std::vector<int> members;
+    int64_t ndata = 0;
+};
+
+// Inputs a unit's generated code really reads for one data point (after
+// dead-code elimination), used to report algorithmic traffic.
+struct UnitLive {
+    std::vector<int> icols, fcols;     // data columns
+    std::vector<int> vrefs, vseeds, prefs;  // group-level references
+    int weights = 0;                   // y entries (one per member that needs it)
+    int64_t outputs = 0;               // doubles written per data point
+};
+
 // Sorted reduction map (CSR): segment s sums buf[idx[ptr[s] .. ptr[s+1])].
 struct SegMap {
     std::vector<int64_t> ptr, idx;
@@ -172,12 +206,16 @@ struct Model {
     int64_t nvar = 0, ncon = 0, ntheta = 0;
     int64_t nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0;
     std::vector<Pattern> pats;
+    std::vector<Group> groups;
     std::vector<double> xl, xu, theta;
     // reduction maps (positions in the first-order buffer: grad part first)
     SegMap grad_map, jt_map, h_map, aug_map, par_map;
     bool host_only = false;
     int block = 256, epl = 4;
+    bool autotune = false, fuse = false;
     std::string signature;   // hash of the simplified trees (shared code)
+    // inputs each generated unit really reads, per (mode, unit code)
+    std::map<std::pair<int, int>, UnitLive> live;
     std::atomic<int64_t> counters[9];
     std::unique_ptr<DeviceState> dev;
     Model();
@@ -189,7 +227,11 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats);
 std::string pattern_signature(const Model& M);
 
 // exa_codegen.cpp
-std::string generate_source(const Model& M, int block);
+#define EXA_BLOCK_MAX 256
+bool pattern_in_mode(const Pattern& P, int mode);
+std::vector<Unit> units_for(const Model& M, int mode, bool fused);
+// Generated source for all callbacks; fills live[(mode, unit code)].
+std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr);
 
 // exa_runtime.cpp
 void build_device(Model& M);

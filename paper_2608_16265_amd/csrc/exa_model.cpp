@@ -317,6 +317,40 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
                                  std::to_string(EXA_MAX_REFS) + " distinct variable/parameter references");
     }
 
+    // ---- data-set groups ---------------------------------------------------
+    for (int p = 0; p < npats; ++p) {
+        const exa_pattern_desc& d = pats[p];
+        int g = -1;
+        for (size_t q = 0; q < M.groups.size() && g < 0; ++q) {
+            const exa_pattern_desc& e = pats[M.groups[q].members[0]];
+            bool same = d.ndata > 0 && e.ndata == d.ndata && e.n_icols == d.n_icols &&
+                        e.n_fcols == d.n_fcols;
+            for (int c = 0; same && c < d.n_icols; ++c) same = d.icols[c] == e.icols[c];
+            for (int c = 0; same && c < d.n_fcols; ++c) same = d.fcols[c] == e.fcols[c];
+            if (same) g = (int)q;
+        }
+        if (g < 0) {
+            M.groups.emplace_back();
+            g = (int)M.groups.size() - 1;
+            M.groups[g].ndata = d.ndata;
+        }
+        Group& G = M.groups[g];
+        Pattern& P = M.pats[p];
+        P.group = g;
+        const int mi = (int)G.members.size();
+        G.members.push_back(p);
+        for (int s = 0; s < P.o1step(); ++s) {
+            int r = find_or_add(G.vrefs, P.vslots[s]);
+            if (r == (int)G.vsrc.size()) G.vsrc.emplace_back(mi, s);
+            P.vg.push_back(r);
+        }
+        for (int s = 0; s < P.pstep(); ++s) {
+            int r = find_or_add(G.prefs, P.pslots[s]);
+            if (r == (int)G.psrc.size()) G.psrc.emplace_back(mi, s);
+            P.pg.push_back(r);
+        }
+    }
+
     // ---- offsets in declaration order (Sec. 3.1 running counts) ----------
     int64_t ncon = 0, nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0;
     for (auto& P : M.pats) {
@@ -424,10 +458,16 @@ std::string pattern_signature(const Model& M) {
     os.precision(17);
     for (auto& P : M.pats) {
         os << "P" << P.kind << ":" << P.n_icols << "," << P.n_fcols << ":" << P.row_icol << ";";
-        // reference offsets are per-instance data (ExaPatDev::roff): left out
+        // reference offsets are per-instance data (ExaPatDev::roff): left out;
+        // which references coincide inside a data-set group is kept
         for (auto& n : P.nodes)
             os << n.op << "," << n.a << "," << n.b << "," << n.col << "," << n.val << "," << n.slot
                << ";";
+        os << "G" << P.group << ":";
+        for (int r : P.vg) os << r << ",";
+        os << "|";
+        for (int r : P.pg) os << r << ",";
+        os << ";";
     }
     return os.str();
 }

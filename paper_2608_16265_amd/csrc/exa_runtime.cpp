@@ -54,7 +54,10 @@ std::vector<char> compile_code(const std::string& src) {
     if (hiprtcCreateProgram(&prog, src.c_str(), "exa_generated.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         fail(EXA_ECOMPILE, "hiprtcCreateProgram failed");
-    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+    // -ffp-contract=off: every multiply and add is rounded on its own, so a
+    // data point's result does not depend on how its code was scheduled or
+    // fused with other patterns (bitwise-equal batched and plain results)
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
     hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
     size_t logsz = 0;
@@ -116,17 +119,25 @@ void* DeviceState::upload(const void* src, size_t bytes) {
     return p;
 }
 
-std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts) {
+void DeviceState::release(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+        (void)hipFree(p);
+        allocs.erase(it);
+    }
+}
+
+// Tiles of `tile_pts` consecutive data points over the units of a callback.
+std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused) {
     std::vector<ExaTile> tiles;
-    for (size_t p = 0; p < M.pats.size(); ++p) {
-        const Pattern& P = M.pats[p];
-        if (!pattern_in_mode(P, mode)) continue;
-        for (int64_t s = 0; s < P.ndata; s += tile_pts) {
+    for (const Unit& u : units_for(M, mode, fused)) {
+        for (int64_t s = 0; s < u.ndata; s += tile_pts) {
             ExaTile t{};
-            t.pat = (int)p;
+            t.pat = u.code;
             t.inst = inst;
             t.start = s;
-            t.count = std::min(tile_pts, P.ndata - s);
+            t.count = std::min(tile_pts, u.ndata - s);
             t.slot = (int64_t)tiles.size();
             tiles.push_back(t);
         }
@@ -139,10 +150,17 @@ void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
     for (size_t p = 0; p < M.pats.size(); ++p) {
         const Pattern& P = M.pats[p];
         ExaPatDev& d = inst.pat[p];
-        for (int c = 0; c < P.n_icols; ++c)
-            d.ic[c] = (const int*)D.upload(P.icols[c].data(), P.ndata * sizeof(int32_t));
-        for (int c = 0; c < P.n_fcols; ++c)
-            d.fc[c] = (const double*)D.upload(P.fcols_src[c], P.ndata * sizeof(double));
+        const int first = M.groups[P.group].members[0];
+        if (first != (int)p) {
+            // same data arrays as the group's first pattern: share the copies
+            for (int c = 0; c < P.n_icols; ++c) d.ic[c] = inst.pat[first].ic[c];
+            for (int c = 0; c < P.n_fcols; ++c) d.fc[c] = inst.pat[first].fc[c];
+        } else {
+            for (int c = 0; c < P.n_icols; ++c)
+                d.ic[c] = (const int*)D.upload(P.icols[c].data(), P.ndata * sizeof(int32_t));
+            for (int c = 0; c < P.n_fcols; ++c)
+                d.fc[c] = (const double*)D.upload(P.fcols_src[c], P.ndata * sizeof(double));
+        }
         d.ndata = P.ndata;
         d.o0 = P.o0;
         d.o1 = P.o1;
@@ -162,7 +180,7 @@ void build_device(Model& M) {
     M.dev.reset(new DeviceState());
     DeviceState& D = *M.dev;
     D.device = dev;
-    const std::string src = generate_source(M, M.block);
+    const std::string src = generate_source(M, &M.live);
     D.module = compile_module(src);
 
     D.theta = (double*)D.upload(M.theta.data(), M.theta.size() * sizeof(double));
@@ -173,16 +191,17 @@ void build_device(Model& M) {
     D.inst_host = inst;
     D.inst = (ExaInstDev*)D.upload(&inst, sizeof inst);
 
-    const int64_t tile_pts = (int64_t)M.block * M.epl;
     for (int mode = 0; mode < M_COUNT; ++mode) {
-        auto tiles = make_tiles(M, mode, 0, tile_pts);
-        D.ntiles[mode] = (int64_t)tiles.size();
-        D.tiles[mode] = (ExaTile*)D.upload(tiles.data(), tiles.size() * sizeof(ExaTile));
+        // the objective keeps one fixed schedule, so that its reduction order
+        // (and hence its value) never depends on tuning
+        const bool fixed = mode == M_OBJ;
+        set_schedule(M, mode, fixed ? 256 : M.block, fixed ? 4 : M.epl, fixed ? false : M.fuse);
+        D.sched[mode].tuned = fixed || !M.autotune;
     }
     D.fo = (double*)D.alloc((M.nnzg + M.nnzj) * sizeof(double));
     D.aug = (double*)D.alloc(M.naug * sizeof(double));
     D.par = (double*)D.alloc(M.nnzp * sizeof(double));
-    D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.ntiles[M_OBJ]) * sizeof(double));
+    D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
     auto up_map = [&](const SegMap& S, DevMap& d) {
         d.ptr = (const int64_t*)D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
         d.idx = (const int64_t*)D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
@@ -197,20 +216,122 @@ void build_device(Model& M) {
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
 }
 
-void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
+void set_schedule(Model& M, int mode, int block, int epl, bool fused) {
     DeviceState& D = *M.dev;
-    const int64_t nt = D.ntiles[mode];
-    if (nt == 0) return;
-    call.tiles = D.tiles[mode];
-    call.ntiles = nt;
-    call.per_xcd = (nt + 7) / 8;
+    DeviceState::Sched& S = D.sched[mode];
+    auto tiles = make_tiles(M, mode, 0, (int64_t)block * epl, fused);
+    D.release(S.tiles);
+    S.tiles = (ExaTile*)D.upload(tiles.data(), tiles.size() * sizeof(ExaTile));
+    S.ntiles = (int64_t)tiles.size();
+    S.block = block;
+    S.epl = epl;
+    S.fused = fused;
+}
+
+namespace {
+void raw_launch(Model& M, int mode, ExaCall call, hipStream_t s) {
+    DeviceState& D = *M.dev;
+    const DeviceState::Sched& S = D.sched[mode];
+    if (S.ntiles == 0) return;
+    call.tiles = S.tiles;
+    call.ntiles = S.ntiles;
+    call.per_xcd = (S.ntiles + 7) / 8;
     call.inst = D.inst;
     call.persistent = 0;
     const int64_t grid = 8 * call.per_xcd;
     void* args[] = {&call};
-    hip_check(hipModuleLaunchKernel(D.module->fn[mode], (unsigned)grid, 1, 1, (unsigned)M.block, 1, 1, 0,
-                                    s, args, nullptr),
+    hip_check(hipModuleLaunchKernel(D.module->fn[mode], (unsigned)grid, 1, 1, (unsigned)S.block, 1, 1, 0, s,
+                                    args, nullptr),
               "hipModuleLaunchKernel");
+}
+
+bool has_fusable_group(const Model& M, int mode) {
+    for (const Unit& u : units_for(M, mode, true))
+        if (u.members.size() > 1) return true;
+    return false;
+}
+
+// First call of a callback with autotuning on: time every candidate
+// schedule on the caller's own arguments and keep the fastest.  Every
+// candidate evaluates each data point with the same code, so outputs are the
+// same whichever wins.
+void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
+    const int blocks[] = {64, 128, 256};
+    const int epls[] = {1, 2, 4, 8};
+    std::vector<int> fuses = {0};
+    if (has_fusable_group(M, mode)) fuses.push_back(1);
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    float best = 1e30f;
+    int bb = M.block, be = M.epl;
+    bool bf = M.fuse;
+    try {
+        for (int f : fuses)
+            for (int b : blocks)
+                for (int ep : epls) {
+                    set_schedule(M, mode, b, ep, f != 0);
+                    raw_launch(M, mode, call, s);
+                    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                    for (int r = 0; r < 3; ++r) raw_launch(M, mode, call, s);
+                    hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0;
+                    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    if (ms < best) {
+                        best = ms;
+                        bb = b;
+                        be = ep;
+                        bf = f != 0;
+                    }
+                }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_schedule(M, mode, bb, be, bf);
+    M.dev->sched[mode].tuned = true;
+}
+}  // namespace
+
+void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
+    if (!M.dev->sched[mode].tuned) tune(M, mode, call, s);
+    raw_launch(M, mode, call, s);
+}
+
+// Algorithmic bytes of one launch evaluating `modes` under schedule
+// `fused`: per-point inputs and outputs of every unit, plus each distinct x,
+// v and theta entry read, counted once over the launch.
+void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr) {
+    rd = wr = 0;
+    std::vector<char> xs(M.nvar, 0), vs(M.nvar, 0), ts(M.ntheta, 0);
+    for (int mode : modes)
+    for (const Unit& u : units_for(M, mode, fused)) {
+        auto it = M.live.find({mode, u.code});
+        if (it == M.live.end()) continue;
+        const UnitLive& L = it->second;
+        const Group& G = M.groups[u.group];
+        const Pattern& P0 = M.pats[G.members[0]];
+        rd += u.ndata * (4 * (int64_t)L.icols.size() + 8 * (int64_t)L.fcols.size() + 8 * (int64_t)L.weights);
+        wr += u.ndata * 8 * L.outputs;
+        auto mark = [&](const RefKey& r, std::vector<char>& seen) {
+            if (r.col < 0) {
+                if (r.off >= 0 && r.off < (int64_t)seen.size()) seen[r.off] = 1;
+                return;
+            }
+            const std::vector<int32_t>& c = P0.icols[r.col];
+            for (int64_t k = 0; k < u.ndata; ++k) seen[(int64_t)c[k] + r.off] = 1;
+        };
+        for (int r : L.vrefs) mark(G.vrefs[r], xs);
+        for (int r : L.vseeds) mark(G.vrefs[r], vs);
+        for (int r : L.prefs) mark(G.prefs[r], ts);
+    }
+    for (char c : xs) rd += c ? 8 : 0;
+    for (char c : vs) rd += c ? 8 : 0;
+    for (char c : ts) rd += c ? 8 : 0;
 }
 
 void segsum(const DevMap& m, const double* buf, double* out, int acc, hipStream_t s) {
@@ -295,9 +416,11 @@ exa_status exa_create(const exa_pattern_desc* pats, int32_t npats, int64_t nvar,
             M.host_only = opt->host_only != 0;
             if (opt->block) M.block = opt->block;
             if (opt->epl) M.epl = opt->epl;
+            M.autotune = opt->autotune != 0;
+            M.fuse = opt->fuse != 0;
         }
-        if (M.block != 64 && M.block != 128 && M.block != 256 && M.block != 512)
-            fail(EXA_EINVAL, "block must be 64, 128, 256 or 512");
+        if (M.block != 64 && M.block != 128 && M.block != 256)
+            fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (M.epl < 1 || M.epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
         build_host(M, pats, npats);
         if (!M.host_only) build_device(M);
@@ -369,14 +492,14 @@ exa_status exa_obj(exa_model* m, const double* x, double* f, exa_stream_t stream
         need(f, 1, "f");
         hipStream_t s = (hipStream_t)stream;
         DeviceState& D = *M.dev;
-        if (D.ntiles[M_OBJ] == 0) {
+        if (D.sched[M_OBJ].ntiles == 0) {
             hip_check(exa_launch_fill(f, 1, 0.0, s), "fill");
         } else {
             ExaCall c = blank_call();
             c.x = x;
             c.out0 = D.tilesum;
             launch_mode(M, M_OBJ, c, s);
-            hip_check(exa_launch_sum(D.tilesum, D.ntiles[M_OBJ], f, s), "objective reduction");
+            hip_check(exa_launch_sum(D.tilesum, D.sched[M_OBJ].ntiles, f, s), "objective reduction");
         }
         M.counters[0]++;
     });
@@ -520,10 +643,46 @@ exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, dou
     });
 }
 
+namespace {
+// public callback ids (exa_counters order) -> internal modes
+int mode_of_callback(int32_t cb) {
+    static const int map[9] = {M_OBJ, M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_JTPROD, M_HPROD, M_ADJ};
+    if (cb < 0 || cb > 8) fail(EXA_EINVAL, "callback id must be in 0..8");
+    return map[cb];
+}
+}  // namespace
+
+exa_status exa_kernel_bytes(const exa_model* m, int32_t callback, int64_t* read_bytes, int64_t* write_bytes) {
+    return guard([&] {
+        if (!m) fail(EXA_EINVAL, "null model");
+        const int mode = mode_of_callback(callback);
+        const Model& M = m->impl;
+        if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
+        const bool fused = M.dev ? M.dev->sched[mode].fused : false;
+        int64_t rd = 0, wr = 0;
+        kernel_bytes(M, {mode}, fused, rd, wr);
+        if (read_bytes) *read_bytes = rd;
+        if (write_bytes) *write_bytes = wr;
+    });
+}
+
+exa_status exa_schedule(const exa_model* m, int32_t callback, int64_t* out4) {
+    return guard([&] {
+        if (!m || !out4) fail(EXA_EINVAL, "null argument");
+        const int mode = mode_of_callback(callback);
+        if (!m->impl.dev) fail(EXA_ESTATE, "host-only model has no schedule");
+        const DeviceState::Sched& S = m->impl.dev->sched[mode];
+        out4[0] = S.block;
+        out4[1] = S.epl;
+        out4[2] = S.fused ? 1 : 0;
+        out4[3] = S.ntiles;
+    });
+}
+
 exa_status exa_generated_source(const exa_model* m, char* buf, int64_t cap, int64_t* len) {
     return guard([&] {
         if (!m) fail(EXA_EINVAL, "null model");
-        const std::string src = generate_source(m->impl, m->impl.block);
+        const std::string src = generate_source(m->impl);
         if (len) *len = (int64_t)src.size();
         if (buf && cap > 0) {
             const size_t n = std::min<size_t>((size_t)cap - 1, src.size());
@@ -536,7 +695,7 @@ exa_status exa_generated_source(const exa_model* m, char* buf, int64_t cap, int6
 exa_status exa_compile_check(const exa_model* m) {
     return guard([&] {
         if (!m) fail(EXA_EINVAL, "null model");
-        (void)compile_code(generate_source(m->impl, m->impl.block));
+        (void)compile_code(generate_source(m->impl));
     });
 }
 

@@ -32,8 +32,13 @@ struct DeviceState {
     double* theta = nullptr;
     ExaInstDev* inst = nullptr;       // device copy of the single-instance table
     ExaInstDev inst_host;             // host copy (device pointers), reused by batches
-    ExaTile* tiles[M_COUNT] = {};
-    int64_t ntiles[M_COUNT] = {};
+    // schedule of each callback's evaluation kernel
+    struct Sched {
+        int block = 256, epl = 4;
+        bool fused = false, tuned = false;
+        ExaTile* tiles = nullptr;
+        int64_t ntiles = 0;
+    } sched[M_COUNT];
     double* fo = nullptr;             // first-order buffer: grad part, then jac part
     double* aug = nullptr;
     double* par = nullptr;
@@ -42,16 +47,18 @@ struct DeviceState {
 
     void* alloc(size_t bytes);
     void* upload(const void* src, size_t bytes);
+    void release(void* p);
     ~DeviceState();
 };
 
 void hip_check(hipError_t e, const char* what);
 std::vector<char> compile_code(const std::string& src);
 std::shared_ptr<Module> compile_module(const std::string& src);
-std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts);
-bool pattern_in_mode(const Pattern& P, int mode);
+std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused);
 std::string kernel_name(int mode);
-int mode_lds_doubles(const Model& M, int mode, int block);
+int mode_lds_doubles(const Model& M, int mode);
+void set_schedule(Model& M, int mode, int block, int epl, bool fused);
+void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);
 void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);
 void hess_structure_host(const Model& M, int32_t* rows, int32_t* cols);
 const char* last_error();

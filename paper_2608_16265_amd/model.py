@@ -77,13 +77,14 @@ def _stream():
 class ExaModel:
     """A compiled model on the current HIP device (Sec. 3.2 ExaModel)."""
 
-    def __init__(self, model, *, host_only: bool = False, block: int = 256, epl: int = 4):
+    def __init__(self, model, *, host_only: bool = False, block: int = 256, epl: int = 4,
+                 autotune: bool = False, fuse: bool = False):
         self.description = model
         desc = _Descriptors(model)
         xl = np.ascontiguousarray(model.xl, dtype=np.float64)
         xu = np.ascontiguousarray(model.xu, dtype=np.float64)
         th = np.ascontiguousarray(model.theta, dtype=np.float64)
-        opt = Options(1 if host_only else 0, block, epl)
+        opt = Options(1 if host_only else 0, block, epl, 1 if autotune else 0, 1 if fuse else 0)
         h = C.c_void_p()
         check(LIB.exa_create(desc.arr, desc.n, model.nvar, _ptr(xl, C.c_double), _ptr(xu, C.c_double),
                              model.ntheta, _ptr(th, C.c_double) if th.size else None,
@@ -147,6 +148,18 @@ class ExaModel:
         check(LIB.exa_pattern_info(self._h, p, _ptr(out, C.c_int64)))
         keys = ["kind", "ndata", "o1step", "o2step", "pstep", "o0", "o1", "o2"]
         return dict(zip(keys, out.tolist()))
+
+    def kernel_bytes(self, callback: str):
+        """(read, write) algorithmic bytes of one launch of a callback's
+        evaluation kernel under its current schedule."""
+        rd, wr = C.c_int64(), C.c_int64()
+        check(LIB.exa_kernel_bytes(self._h, _lib.CALLBACKS.index(callback), C.byref(rd), C.byref(wr)))
+        return rd.value, wr.value
+
+    def schedule(self, callback: str) -> dict:
+        out = np.zeros(4, dtype=np.int64)
+        check(LIB.exa_schedule(self._h, _lib.CALLBACKS.index(callback), _ptr(out, C.c_int64)))
+        return dict(zip(["block", "points_per_lane", "fused", "tiles"], out.tolist()))
 
     def counters(self):
         out = np.zeros(9, dtype=np.int64)

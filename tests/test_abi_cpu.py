@@ -155,3 +155,25 @@ def test_simplified_structure_drops_dead_variables():
     o = OracleModel(m)
     assert em.nnzj == o.dims()[2] == 2 and em.nnzh == 2
     assert np.array_equal(em.jac_structure()[1], o.jac_structure()[1])
+
+
+def test_kernel_bytes_accounting():
+    """Outputs are counted once per entry; inputs as the code really reads them."""
+    from paper_2608_16265_amd import ExaModel
+    w = pde(9, 3)
+    em = ExaModel(w.model, host_only=True)
+    n = 9
+    ni = (n - 2) ** 2
+    rd, wr = em.kernel_bytes("hess")
+    assert wr == 8 * em.nnzh
+    # objective Hessians are constants (no input); the constraint needs the
+    # interior index, y and u at the interior points
+    assert rd == ni * (4 + 8) + 8 * ni
+    rd, wr = em.kernel_bytes("jac")
+    assert wr == 8 * em.nnzj
+    # the Jacobian of the stencil row needs only u_c (exp), the index column
+    assert rd == ni * 4 + 8 * ni
+    w = acopf(30, 0)
+    em = ExaModel(w.model, host_only=True)
+    rd, wr = em.kernel_bytes("hess")
+    assert wr == 8 * em.nnzh and rd > 0

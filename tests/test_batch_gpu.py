@@ -17,15 +17,17 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("autotune,epl,grid,graph", [(False, 1, 64, True), (False, 8, 0, False),
-                                                     (True, 4, 0, True)])
-def test_batch_bitwise_equal_to_plain(autotune, epl, grid, graph):
+@pytest.mark.parametrize("autotune,epl,grid,graph,fuse,xcd", [
+    (False, 1, 64, True, False, False), (False, 8, 0, False, True, False),
+    (False, 2, 16, True, False, True), (True, 4, 0, True, True, True)])
+def test_batch_bitwise_equal_to_plain(autotune, epl, grid, graph, fuse, xcd):
     _gpu()
     from paper_2608_16265_amd import ExaModel
     from paper_2608_16265_amd.batch import ExaBatch
     wls = acopf_batch(6, 1000, lo=30, hi=900)
     ems = [ExaModel(w.model) for w in wls]
-    b = ExaBatch(ems, autotune=autotune, epl=epl, grid=grid, use_graph=graph)
+    b = ExaBatch(ems, autotune=autotune, epl=epl, grid=grid, use_graph=graph, fuse=fuse,
+                 xcd_aware=xcd)
     X = b.concat_x([w.x for w in wls])
     Y = b.concat_y([w.y for w in wls])
     J = torch.full((b.total("jac"),), np.nan, dtype=torch.float64, device="cuda:0")

@@ -115,18 +115,27 @@ def test_all_callbacks_match_oracle(name):
     check_all(CASES[name](), tag=name + ": ")
 
 
-@pytest.mark.parametrize("block,epl", [(64, 1), (128, 3), (512, 2)])
-def test_launch_shapes_agree_bitwise(block, epl):
+@pytest.mark.parametrize("case,block,epl,fuse,tune", [
+    ("acopf600", 64, 1, False, False), ("acopf600", 128, 3, True, False),
+    ("acopf600", 256, 2, False, True), ("pde50", 64, 5, True, False), ("pde50", 256, 1, False, True)])
+def test_schedules_agree_bitwise(case, block, epl, fuse, tune):
+    """Workgroup size, points per lane, fused or separate patterns and the
+    autotuner's choice change how work is laid out, never a result."""
     _need_gpu()
     from paper_2608_16265_amd import ExaModel
-    w = acopf(600, 7)
+    w = CASES[case]()
     X, Y = dev(w.x), dev(w.y)
+    V = dev(np.random.default_rng(1).standard_normal(w.x.size))
     base = ExaModel(w.model)
-    alt = ExaModel(w.model, block=block, epl=epl)
-    for f in ("jac_coord", "cons", "grad"):
+    alt = ExaModel(w.model, block=block, epl=epl, fuse=fuse, autotune=tune)
+    for f in ("jac_coord", "cons", "grad", "obj"):
         assert np.array_equal(host(getattr(base, f)(X)), host(getattr(alt, f)(X))), f
     assert np.array_equal(host(base.hess_coord(X, Y, 1.0)), host(alt.hess_coord(X, Y, 1.0)))
-    check_all(w, em=alt, tag=f"b{block}e{epl}: ")
+    assert np.array_equal(host(base.hprod(X, Y, 1.0, V)), host(alt.hprod(X, Y, 1.0, V)))
+    assert np.array_equal(host(base.jprod(X, V)), host(alt.jprod(X, V)))
+    check_all(w, em=alt, tag=f"{case} b{block}e{epl}f{int(fuse)}t{int(tune)}: ")
+    if not tune:
+        assert alt.schedule("hess")["block"] == block
 
 
 def test_repeated_calls_are_bitwise_identical():
