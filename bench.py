@@ -16,7 +16,10 @@ Also reported on the same JSON line:
 * pde           -- the PDE-control model on a 1000 x 1000 grid
   (HBM-bound), jac + hess nnz/s and its Hessian roofline;
 * batched       -- 256 uneven ACOPF instances (500 to 20,000 buses) in one
-  persistent graph-replayed launch vs 256 sequential plain calls.
+  persistent graph-replayed launch vs 256 sequential plain calls;
+* adjoint       -- 64 instances of the 10,000-bus model: grad_x L(theta)
+  through torch.autograd and its hand-written adjoint, timed against the
+  forward and the plain gradient.
 """
 from __future__ import annotations
 
@@ -46,7 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the PDE and batched legs")
-    ap.add_argument("--only", choices=["acopf", "pde", "batch"], default=None,
+    ap.add_argument("--only", choices=["acopf", "pde", "batch", "adjoint"], default=None,
                     help="run one leg only (used for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--quick", action="store_true",
@@ -85,27 +88,25 @@ def best_of_3(fn, min_s=0.2):
 
 
 def kernel_ms(fn, n=200):
-    """Average device duration of one call, from HIP events recorded around
-    each call on the launch stream.  The queue is first filled with a long
-    matrix product so that the host stays ahead of the device and the event
-    pairs bracket only the kernel (plus its dispatch)."""
+    """Average device time of one call: HIP events on the launch stream
+    around n back-to-back calls, divided by n.  The queue is first filled with
+    a long matrix product so that the host stays ahead of the device and the
+    calls run back to back."""
     import torch
     if QUICK:
-        n = min(n, 10)
+        n = min(n, 20)
     a = torch.ones(4096, 4096, dtype=torch.float64, device="cuda:0")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(n)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fn()
     torch.cuda.synchronize()
     for _ in range(6):
         a = a @ a * 1e-4
-    for e0, e1 in evs:
-        e0.record()
+    e0.record()
+    for _ in range(n):
         fn()
-        e1.record()
+    e1.record()
     torch.cuda.synchronize()
-    ts = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
-    return float(np.mean(ts)), float(np.median(ts))
+    return e0.elapsed_time(e1) / n, n
 
 
 # ------------------------------------------------------------------- legs
@@ -154,7 +155,7 @@ def leg_single(name, wl, steps, warmup, full_step=True):
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / steps
     per_cb = {k: best_of_3(fn) * 1e6 for k, fn in cbs.items()}
-    k_mean, k_med = kernel_ms(cbs["hess_coord"])
+    k_mean, k_n = kernel_ms(cbs["hess_coord"])
     kj_mean, _ = kernel_ms(cbs["jac_coord"])
     rd, wr = em.kernel_bytes("hess")
     nbytes = rd + wr
@@ -165,7 +166,7 @@ def leg_single(name, wl, steps, warmup, full_step=True):
         build_s=round(build_s, 3), step_s=step_s, nnz_per_s=nnz / step_s,
         jac_hess_nnz_per_s=nnz / ((per_cb["jac_coord"] + per_cb["hess_coord"]) * 1e-6),
         callbacks_us={k: round(v, 2) for k, v in per_cb.items()},
-        hess_kernel_us=round(k_mean * 1e3, 3), hess_kernel_median_us=round(k_med * 1e3, 3),
+        hess_kernel_us=round(k_mean * 1e3, 3), hess_kernel_launches_timed=k_n,
         jac_kernel_us=round(kj_mean * 1e3, 3), hess_bytes=nbytes,
         hess_gbs=nbytes / (k_mean * 1e-3) / 1e9, hess_read_bytes=rd, hess_write_bytes=wr,
         schedule=sched,
@@ -181,7 +182,11 @@ def leg_batch(count=256, first_seed=1000):
     from paper_2608_16265_amd.batch import ExaBatch
     t0 = time.perf_counter()
     wls = acopf_batch(count, first_seed)
-    ems = [ExaModel(w.model) for w in wls]
+    ems = []
+    for i, w in enumerate(wls):
+        ems.append(ExaModel(w.model))
+        if (i + 1) % 64 == 0:
+            log(f"  batch: {i + 1}/{count} models built")
     build_s = time.perf_counter() - t0
     b = ExaBatch(ems, autotune=True)
     X = b.concat_x([w.x for w in wls])
@@ -226,6 +231,56 @@ def leg_batch(count=256, first_seed=1000):
     for e in ems:
         e.close()
     return res
+
+
+def leg_adjoint(count=64, first_seed=2000):
+    """64 instances of the 10,000-bus model: the Lagrangian gradient as a
+    function of theta (forward) and its hand-written adjoint (backward),
+    through torch.autograd, vs the plain gradient callback."""
+    import torch
+    from exa_modeling.generators import acopf
+    from paper_2608_16265_amd import ExaModel
+    from paper_2608_16265_amd.adjoint import lagrangian_gradient
+    t0 = time.perf_counter()
+    wls, ems = [], []
+    for i in range(count):
+        wls.append(acopf(10000, first_seed + i))
+        ems.append(ExaModel(wls[-1].model))
+        if (i + 1) % 16 == 0:
+            log(f"  adjoint: {i + 1}/{count} models built")
+    build_s = time.perf_counter() - t0
+    dev = "cuda:0"
+    xs = [torch.as_tensor(w.x, device=dev) for w in wls]
+    ys = [torch.as_tensor(w.y, device=dev) for w in wls]
+    ths = [torch.as_tensor(w.model.theta, device=dev).requires_grad_(True) for w in wls]
+    ws = [torch.as_tensor(np.random.default_rng(first_seed + i).standard_normal(e.nvar), device=dev)
+          for i, e in enumerate(ems)]
+    gs = [torch.empty(e.nvar, dtype=torch.float64, device=dev) for e in ems]
+
+    def forward():
+        return [lagrangian_gradient(th, e, x, y, 1.0) for th, e, x, y in zip(ths, ems, xs, ys)]
+
+    def fwd_bwd():
+        outs = forward()
+        torch.autograd.backward(outs, ws)
+
+    def backward_only():
+        for th, e, x, y, w in zip(ths, ems, xs, ys, ws):
+            e.adjoint_theta(x, y, 1.0, w)
+
+    def grad_only():
+        for e, x, g in zip(ems, xs, gs):
+            e.grad(x, g)
+
+    t_fwd = best_of_3(lambda: forward(), min_s=0.2)
+    t_fb = best_of_3(fwd_bwd, min_s=0.2)
+    t_bwd = best_of_3(backward_only, min_s=0.2)
+    t_grad = best_of_3(grad_only, min_s=0.2)
+    return dict(instances=count, buses_each=10000, ntheta_each=ems[0].ntheta,
+                build_s=round(build_s, 2), forward_us=round(t_fwd * 1e6, 1),
+                forward_backward_us=round(t_fb * 1e6, 1), adjoint_kernel_path_us=round(t_bwd * 1e6, 1),
+                grad_us=round(t_grad * 1e6, 1), backward_over_forward=t_bwd / t_fwd,
+                backward_over_grad=t_bwd / t_grad)
 
 
 def cpu_baseline(wl, seconds):
@@ -323,6 +378,11 @@ def main():
         out["batched"] = r
         if args.only == "batch":
             out.update(value=r["batched_nnz_per_s"], ms_per_step=r["batched_us"] * 1e-3)
+    if not args.no_extras and args.only in (None, "adjoint"):
+        log("leg: adjoint 64 x 10k")
+        r = leg_adjoint()
+        log(json.dumps(r))
+        out["adjoint"] = r
     print(json.dumps(out), flush=True)
 
 

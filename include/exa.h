@@ -204,6 +204,12 @@ exa_status exa_jac_coord(exa_model* m, const double* x, double* vals, exa_stream
  * entries gives the Hessian. */
 exa_status exa_hess_coord(exa_model* m, const double* x, const double* y, double obj_weight,
                           double* vals, exa_stream_t stream);
+/* Jacobian and Hessian values together (what a solver asks for at every
+ * iterate): each data point's Jacobian row block and Hessian block come from
+ * one pass over its loads and forward sweep, in one launch.  Outputs are
+ * bit-identical to exa_jac_coord and exa_hess_coord. */
+exa_status exa_jac_hess_coord(exa_model* m, const double* x, const double* y, double obj_weight,
+                              double* jac_vals, double* hess_vals, exa_stream_t stream);
 /* J(x) v into Jv [ncon]; v is device [nvar] (Sec. 2.1.3 jprod). */
 exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv,
                      exa_stream_t stream);
@@ -237,8 +243,8 @@ exa_status exa_compile_check(const exa_model* m);
  * entries and outputs the generated code really reads or writes after dead
  * code is removed) plus each distinct entry of x, v and theta it reads, once.
  * callback: 0 obj, 1 grad, 2 cons, 3 jac, 4 hess, 5 jprod, 6 jtprod,
- * 7 hprod, 8 adjoint (the order of exa_counters).  Host-only models report
- * the unfused schedule. */
+ * 7 hprod, 8 adjoint (the order of exa_counters), 9 jac_hess.  Host-only
+ * models report the unfused schedule. */
 exa_status exa_kernel_bytes(const exa_model* m, int32_t callback, int64_t* read_bytes,
                             int64_t* write_bytes);
 /* The schedule a callback's kernel uses: out4 = workgroup size, points per
@@ -279,7 +285,8 @@ typedef struct exa_batch_options {
     int32_t xcd_aware; /* 1: instances are split over the 8 XCDs by cost and
                           each XCD walks its own instances one after another
                           (their x stays in that XCD's L2)                     */
-    int32_t reserved;
+    int32_t separate;  /* without autotune: 1 keeps Jacobian and Hessian tiles
+                          apart; 0 evaluates both for a data point in one pass */
 } exa_batch_options;
 
 #define EXA_CB_JAC 1u
@@ -300,9 +307,10 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x_cat, cons
  * over the instances (see exa_kernel_bytes; an instance's x entries count once
  * for the Jacobian and the Hessian together). */
 exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes);
-/* The schedule in use: block, epl, grid, tiles, and the autotuner's
- * best time in nanoseconds (0 if not tuned). */
-exa_status exa_batch_schedule(const exa_batch* b, int64_t* out5);
+/* The schedule in use: out6 = block, points per lane, grid, tiles (both
+ * callbacks), the autotuner's best time in nanoseconds (0 if not tuned), and
+ * 1 when Jacobian and Hessian are evaluated in one pass per data point. */
+exa_status exa_batch_schedule(const exa_batch* b, int64_t* out6);
 
 #ifdef __cplusplus
 }

@@ -45,10 +45,10 @@ class Options(C.Structure):
 class BatchOptions(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
                 ("grid", C.c_int32), ("use_graph", C.c_int32), ("fuse", C.c_int32),
-                ("xcd_aware", C.c_int32), ("reserved", C.c_int32)]
+                ("xcd_aware", C.c_int32), ("separate", C.c_int32)]
 
 
-CALLBACKS = ["obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod", "adjoint"]
+CALLBACKS = ["obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod", "adjoint", "jac_hess"]
 
 
 class ExaError(RuntimeError):
@@ -79,6 +79,7 @@ def _load():
         "exa_jac_coord": (C.c_int32, [vp, vp, vp, vp]),
         "exa_hess_coord": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp]),
         "exa_jprod": (C.c_int32, [vp, vp, vp, vp, vp]),
+        "exa_jac_hess_coord": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_jtprod": (C.c_int32, [vp, vp, vp, vp, vp]),
         "exa_hprod": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_adjoint_theta": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
@@ -115,7 +116,7 @@ def exported_symbols():
     """Names of the C ABI entry points this binding declares."""
     return ["exa_last_error", "exa_version", "exa_create", "exa_destroy", "exa_dims", "exa_bounds",
             "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
-            "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
+            "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jac_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
             "exa_adjoint_theta", "exa_counters", "exa_generated_source", "exa_compile_check",
             "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",
             "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule", "exa_batch_bytes"]

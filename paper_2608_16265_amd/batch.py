@@ -20,11 +20,11 @@ from .model import ExaModel, _stream
 class ExaBatch:
     def __init__(self, models: Sequence[ExaModel], *, autotune: bool = True, block: int = 256,
                  epl: int = 4, grid: int = 0, use_graph: bool = True, fuse: bool = True,
-                 xcd_aware: bool = True):
+                 xcd_aware: bool = True, separate: bool = False):
         self.models = list(models)  # the models must outlive the batch
         arr = (C.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
         opt = BatchOptions(1 if autotune else 0, block, epl, grid, 1 if use_graph else 0,
-                           1 if fuse else 0, 1 if xcd_aware else 0)
+                           1 if fuse else 0, 1 if xcd_aware else 0, 1 if separate else 0)
         h = C.c_void_p()
         check(LIB.exa_batch_create(arr, len(self.models), C.byref(opt), C.byref(h)))
         self._h = h
@@ -72,9 +72,10 @@ class ExaBatch:
         return rd.value, wr.value
 
     def schedule(self) -> dict:
-        out = np.zeros(5, dtype=np.int64)
+        out = np.zeros(6, dtype=np.int64)
         check(LIB.exa_batch_schedule(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))))
-        return dict(zip(["block", "points_per_lane", "grid", "tiles", "tuned_ns"], out.tolist()))
+        return dict(zip(["block", "points_per_lane", "grid", "tiles", "tuned_ns", "combined"],
+                        out.tolist()))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

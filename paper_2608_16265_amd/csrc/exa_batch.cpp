@@ -2,12 +2,15 @@
 // models, generalised to instances of different sizes).
 //
 // All instances share the generated code; their data stays where each model
-// put it.  A tile list spans (instance, pattern, data range) for the
-// Jacobian and the Hessian together, ordered by decreasing estimated cost,
-// and ONE persistent launch of the combined kernel walks it (workgroup w takes
-// tiles w, w + grid, ...).  The launch is recorded once into a HIP graph and
-// replayed.  Tile size (data points per tile) and grid size are picked by
-// timing candidates on the first evaluation (autotuning); results do not
+// put it, and their sizes and offsets are table data.  A tile list spans
+// (instance, unit, data range); ONE persistent launch walks it and the launch
+// is recorded once into a HIP graph and replayed.  For the Jacobian and the
+// Hessian together the tiles are either combined units (both sweeps of a data
+// point in one pass over one set of loads) or separate Jacobian and Hessian
+// tiles.  With xcd_aware, instances are binned over the 8 XCDs by estimated
+// cost and each XCD walks its bin instance by instance, so an instance's x
+// stays in that XCD's L2.  Points per tile, grid size and combined/separate
+// are picked by timing candidates at the first evaluation; results do not
 // depend on the schedule because every data point is evaluated by the same
 // code and written to its own slice.
 #include <hip/hip_runtime.h>
@@ -31,15 +34,16 @@ struct exa_batch {
     std::vector<int64_t> offsets;          // 4 * (B + 1): x, y, jac, hess
     // schedule
     bool autotune = true, use_graph = true, tuned = false, fuse = true, xcd_aware = true;
-    long long* xcd_range = nullptr;       // device [9] per mask when xcd_aware
-    long long* xcd_ranges[4] = {};
+    bool combined = true;                  // Jacobian + Hessian units (mask 3)
     int epl = 4;
     int64_t grid = 0;
     int64_t tuned_ns = 0;
-    // tile lists per mask value (1: jac, 2: hess, 3: both), for the current epl
+    // tile lists per mask value (1: jac, 2: hess, 3: both) for (epl, combined)
     ExaTile* tiles[4] = {};
+    long long* xcd_ranges[4] = {};
     int64_t ntiles[4] = {};
     int tiles_epl = -1;
+    bool tiles_combined = true;
     // graph for the last call signature
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -50,9 +54,10 @@ struct exa_batch {
         double sigma;
         int epl;
         int64_t grid;
+        bool combined;
         bool operator==(const Key& o) const {
-            return mask == o.mask && x == o.x && y == o.y && j == o.j && h == o.h &&
-                   sigma == o.sigma && epl == o.epl && grid == o.grid;
+            return mask == o.mask && x == o.x && y == o.y && j == o.j && h == o.h && sigma == o.sigma &&
+                   epl == o.epl && grid == o.grid && combined == o.combined;
         }
     } key{};
     bool have_graph = false;
@@ -67,33 +72,41 @@ struct exa_batch {
 
 namespace {
 
-// Estimated cost of one data point (in 8-byte words moved).
+// Estimated cost of one data point of pattern P (in 8-byte words moved).
 int64_t point_cost(const Pattern& P, int mode) {
     const int64_t loads = P.n_icols / 2 + P.n_fcols + P.o1step() + 1;
+    if (mode == M_JH) return loads + P.o1step() + P.o2step();
     return loads + (mode == M_JAC ? P.o1step() : P.o2step());
 }
 
-void build_tiles(exa_batch& b, int epl) {
-    if (b.tiles_epl == epl) return;
+// Modes whose tiles a mask launches: (mode, tile code offset).
+std::vector<std::pair<int, int>> mask_modes(uint32_t mask, bool combined) {
+    if (mask == 1) return {{M_JAC, 0}};
+    if (mask == 2) return {{M_HESS, 0}};
+    if (combined) return {{M_JH, 0}};
+    return {{M_JAC, 0}, {M_HESS, 64}};
+}
+
+void build_tiles(exa_batch& b, int epl, bool combined) {
+    if (b.tiles_epl == epl && b.tiles_combined == combined) return;
     const int64_t tp = (int64_t)b.block * epl;
     for (int m = 1; m <= 3; ++m) {
         // per instance: its tiles and their total cost
-        std::vector<std::vector<ExaTile>> per(b.B);
+        std::vector<std::vector<std::pair<int64_t, ExaTile>>> per(b.B);
         std::vector<int64_t> cost(b.B, 0);
         for (int i = 0; i < b.B; ++i) {
             const Model& M = b.models[i]->impl;
-            for (int mode : {M_JAC, M_HESS}) {
-                if (!(m & (mode == M_JAC ? EXA_CB_JAC : EXA_CB_HESS))) continue;
-                for (const Unit& u : units_for(M, mode, b.fuse)) {
+            for (auto mc : mask_modes((uint32_t)m, combined)) {
+                for (const Unit& u : units_for(M, mc.first, b.fuse)) {
                     int64_t pc = 0;
-                    for (int p : u.members) pc += point_cost(M.pats[p], mode);
+                    for (int p : u.members) pc += point_cost(M.pats[p], mc.first);
                     for (int64_t s = 0; s < u.ndata; s += tp) {
                         ExaTile t{};
-                        t.pat = u.code + (mode == M_HESS ? 64 : 0);
+                        t.pat = u.code + mc.second;
                         t.inst = i;
                         t.start = s;
                         t.count = std::min(tp, u.ndata - s);
-                        per[i].push_back(t);
+                        per[i].emplace_back(t.count * pc, t);
                         cost[i] += t.count * pc;
                     }
                 }
@@ -116,24 +129,15 @@ void build_tiles(exa_batch& b, int epl) {
             }
             for (int j = 0; j < 8; ++j) {
                 range[j] = (long long)v.size();
-                for (int i : bins[j]) v.insert(v.end(), per[i].begin(), per[i].end());
+                for (int i : bins[j])
+                    for (auto& e : per[i]) v.push_back(e.second);
             }
             range[8] = (long long)v.size();
         } else {
-            // all tiles, largest first, so the round-robin walk of the
+            // all tiles, largest first, so the grid-stride walk of the
             // persistent grid approximates longest-processing-time-first
             std::vector<std::pair<int64_t, ExaTile>> all;
-            for (int i = 0; i < b.B; ++i)
-                for (auto& t : per[i]) {
-                    const Model& M = b.models[i]->impl;
-                    const bool hess = t.pat >= 64;
-                    const int code = t.pat % 64;
-                    int64_t pc = 0;
-                    for (const Unit& u : units_for(M, hess ? M_HESS : M_JAC, b.fuse))
-                        if (u.code == code)
-                            for (int p : u.members) pc += point_cost(M.pats[p], hess ? M_HESS : M_JAC);
-                    all.emplace_back(t.count * pc, t);
-                }
+            for (auto& pi : per) all.insert(all.end(), pi.begin(), pi.end());
             std::stable_sort(all.begin(), all.end(),
                              [](const auto& a, const auto& c) { return a.first > c.first; });
             for (auto& e : all) v.push_back(e.second);
@@ -143,14 +147,15 @@ void build_tiles(exa_batch& b, int epl) {
         b.mem.release(b.xcd_ranges[m]);
         b.tiles[m] = (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
         b.ntiles[m] = (int64_t)v.size();
-        b.xcd_ranges[m] = b.xcd_aware ? (long long*)b.mem.upload(range.data(), range.size() * sizeof(long long))
-                                      : nullptr;
+        b.xcd_ranges[m] =
+            b.xcd_aware ? (long long*)b.mem.upload(range.data(), range.size() * sizeof(long long)) : nullptr;
     }
     b.tiles_epl = epl;
+    b.tiles_combined = combined;
 }
 
-void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j,
-            double* h, hipStream_t s) {
+void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j, double* h,
+            hipStream_t s) {
     const int64_t nt = b.ntiles[mask];
     if (nt == 0) return;
     ExaCall c;
@@ -161,54 +166,75 @@ void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, doubl
     c.x = x;
     c.y = y;
     c.sigma = sigma;
-    c.out0 = j;
-    c.out1 = h;
     c.persistent = 1;
     c.xcd_range = b.xcd_ranges[mask];
+    hipFunction_t fn;
+    if (mask == 1) {
+        fn = b.module->fn[M_JAC];
+        c.out0 = j;
+    } else if (mask == 2) {
+        fn = b.module->fn[M_HESS];
+        c.out0 = h;
+    } else {
+        fn = b.tiles_combined ? b.module->fn[M_JH] : b.module->fn_sep;
+        c.out0 = j;
+        c.out1 = h;
+    }
     int64_t grid = std::max<int64_t>(8, std::min<int64_t>(b.grid, nt));
     grid = (grid + 7) / 8 * 8;  // a multiple of 8 (one share per XCD)
     void* args[] = {&c};
-    hip_check(hipModuleLaunchKernel(b.module->fn_jh, (unsigned)grid, 1, 1, (unsigned)b.block, 1, 1, 0, s,
-                                    args, nullptr),
+    hip_check(hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)b.block, 1, 1, 0, s, args, nullptr),
               "hipModuleLaunchKernel");
 }
 
-void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j,
-          double* h, hipStream_t s) {
+void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j, double* h,
+          hipStream_t s) {
     const int epls[] = {1, 2, 4, 8, 16};
     const int64_t grids[] = {b.cus * 2, b.cus * 4, b.cus * 8, b.cus * 16};
+    std::vector<int> combos = {1};
+    if (mask == 3) combos.push_back(0);
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     float best = 1e30f;
     int best_epl = b.epl;
     int64_t best_grid = b.grid;
-    for (int epl : epls) {
-        build_tiles(b, epl);
-        for (int64_t g : grids) {
-            b.grid = g;
-            launch(b, mask, x, y, sigma, j, h, s);  // warm
-            hip_check(hipEventRecord(e0, s), "hipEventRecord");
-            const int reps = 3;
-            for (int r = 0; r < reps; ++r) launch(b, mask, x, y, sigma, j, h, s);
-            hip_check(hipEventRecord(e1, s), "hipEventRecord");
-            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-            float ms = 0;
-            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-            ms /= reps;
-            if (ms < best) {
-                best = ms;
-                best_epl = epl;
-                best_grid = g;
+    bool best_comb = b.combined;
+    try {
+        for (int comb : combos)
+            for (int epl : epls) {
+                build_tiles(b, epl, comb != 0);
+                for (int64_t g : grids) {
+                    b.grid = g;
+                    launch(b, mask, x, y, sigma, j, h, s);  // warm
+                    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                    const int reps = 3;
+                    for (int r = 0; r < reps; ++r) launch(b, mask, x, y, sigma, j, h, s);
+                    hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0;
+                    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    ms /= reps;
+                    if (ms < best) {
+                        best = ms;
+                        best_epl = epl;
+                        best_grid = g;
+                        best_comb = comb != 0;
+                    }
+                }
             }
-        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b.epl = best_epl;
     b.grid = best_grid;
+    b.combined = best_comb;
     b.tuned_ns = (int64_t)(best * 1e6);
-    build_tiles(b, b.epl);
+    build_tiles(b, b.epl, b.combined);
     b.tuned = true;
 }
 
@@ -248,8 +274,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             if (models[i]->impl.host_only || !models[i]->impl.dev)
                 fail(EXA_ESTATE, "batched models need a device");
             if (models[i]->impl.signature != models[0]->impl.signature)
-                fail(EXA_EINVAL, "model " + std::to_string(i) +
-                                     " does not share the pattern trees of model 0");
+                fail(EXA_EINVAL, "model " + std::to_string(i) + " does not share the pattern trees of model 0");
         }
         if (opt) {
             b->autotune = opt->autotune != 0;
@@ -259,9 +284,9 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             b->use_graph = opt->use_graph != 0;
             b->fuse = opt->fuse != 0;
             b->xcd_aware = opt->xcd_aware != 0;
+            b->combined = opt->separate == 0;
         }
-        if (b->block != 64 && b->block != 128 && b->block != 256)
-            fail(EXA_EINVAL, "block must be 64, 128 or 256");
+        if (b->block != 64 && b->block != 128 && b->block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
         int dev = 0;
         hip_check(hipGetDevice(&dev), "hipGetDevice");
@@ -269,8 +294,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
         b->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         if (b->grid <= 0) b->grid = (int64_t)b->cus * 8;
-        const Model& M0 = models[0]->impl;
-        b->module = M0.dev->module;  // every instance runs the same generated code
+        b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
 
         std::vector<ExaInstDev> inst(B);
         b->offsets.assign(4 * (B + 1), 0);
@@ -289,7 +313,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             o[7] = o[3] + M.nnzh;
         }
         b->inst = (ExaInstDev*)b->mem.upload(inst.data(), inst.size() * sizeof(ExaInstDev));
-        build_tiles(*b, b->epl);
+        build_tiles(*b, b->epl, b->combined);
         hip_check(hipStreamCreate(&b->cap), "hipStreamCreate");
         *out = b.release();
     });
@@ -306,23 +330,24 @@ exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets) {
     });
 }
 
-exa_status exa_batch_schedule(const exa_batch* b, int64_t* out5) {
+exa_status exa_batch_schedule(const exa_batch* b, int64_t* out6) {
     return guard([&] {
-        if (!b || !out5) fail(EXA_EINVAL, "null argument");
-        out5[0] = b->block;
-        out5[1] = b->epl;
-        out5[2] = b->grid;
-        out5[3] = b->ntiles[3];
-        out5[4] = b->tuned_ns;
+        if (!b || !out6) fail(EXA_EINVAL, "null argument");
+        out6[0] = b->block;
+        out6[1] = b->epl;
+        out6[2] = b->grid;
+        out6[3] = b->ntiles[3];
+        out6[4] = b->tuned_ns;
+        out6[5] = b->combined ? 1 : 0;
     });
 }
 
 exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes) {
     return guard([&] {
         if (!b) fail(EXA_EINVAL, "null batch");
+        if (mask == 0 || mask > 3) fail(EXA_EINVAL, "mask must be EXA_CB_JAC, EXA_CB_HESS or both");
         std::vector<int> modes;
-        if (mask & EXA_CB_JAC) modes.push_back(M_JAC);
-        if (mask & EXA_CB_HESS) modes.push_back(M_HESS);
+        for (auto mc : mask_modes(mask, b->combined)) modes.push_back(mc.first);
         int64_t rd = 0, wr = 0;
         for (int i = 0; i < b->B; ++i) {
             int64_t r = 0, w = 0;
@@ -350,12 +375,12 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x, const do
             tune(*b, mask, x, y, sigma, jac, hess, s);
             b->have_graph = false;
         }
-        build_tiles(*b, b->epl);
+        build_tiles(*b, b->epl, b->combined);
         if (!b->use_graph) {
             launch(*b, mask, x, y, sigma, jac, hess, s);
             return;
         }
-        exa_batch::Key k{mask, x, y, jac, hess, sigma, b->epl, b->grid};
+        exa_batch::Key k{mask, x, y, jac, hess, sigma, b->epl, b->grid, b->combined};
         if (!b->have_graph || !(k == b->key)) {
             if (b->exec) (void)hipGraphExecDestroy(b->exec);
             if (b->graph) (void)hipGraphDestroy(b->graph);

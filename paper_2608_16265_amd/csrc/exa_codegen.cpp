@@ -86,7 +86,16 @@ struct Em {
         byname[name] = (int)st.size() - 1;
         return name;
     }
-    std::string def(const std::string& e) { return named("double", "t" + std::to_string(ntmp++), e); }
+    // identical pure expressions get one name (common subexpressions within
+    // and across the patterns of a unit, and across Jacobian/Hessian sweeps)
+    std::unordered_map<std::string, std::string> memo;
+    std::string def(const std::string& e) {
+        auto it = memo.find(e);
+        if (it != memo.end()) return it->second;
+        const std::string n = named("double", "t" + std::to_string(ntmp++), e);
+        memo[e] = n;
+        return n;
+    }
     void out(const std::string& lhs, const std::string& e) {
         Stmt s{"", lhs, e, deps_of(e), true};
         st.push_back(s);
@@ -297,7 +306,7 @@ class PatternCg {
                 break;
             case EXA_OP_COS:
                 v = e.def("cos(" + u + ")");
-                if (f1) d = e.def("-sin(" + u + ")");
+                if (f1) d = e.neg(e.def("sin(" + u + ")"));
                 if (f2) dd = e.neg(v);
                 break;
             case EXA_OP_TAN:
@@ -553,7 +562,7 @@ int out_step(const Pattern& P, int mode) {
 bool scalar_mode(int mode) { return mode == M_OBJ || mode == M_CONS || mode == M_JPROD; }
 
 const char* mode_name(int m) {
-    static const char* n[] = {"obj", "cons", "grad", "jac", "hess", "jprod", "jtprod", "hprod", "adj"};
+    static const char* n[] = {"obj", "cons", "grad", "jac", "hess", "jprod", "jtprod", "hprod", "adj", "jh"};
     return n[m];
 }
 
@@ -565,19 +574,40 @@ bool staged(const Pattern& P, int mode) { return out_step(P, mode) * EXA_BLOCK_M
 
 // Output destination of member P's slice for data point kb (first of the
 // workgroup's current points).
-std::string dest(const Pattern& P, int mode, const std::string& pd) {
+std::string dest(const Pattern& P, int mode, const std::string& pd, const std::string& out = "C.out0") {
     const std::string st = std::to_string(out_step(P, mode));
     switch (mode) {
-        case M_GRAD: return "C.out0 + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1 + kb * " + st;
-        case M_JAC: return "C.out0 + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1 + kb * " + st;
-        case M_JTPROD: return "C.out0 + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1 + kb * " + st;
+        case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1 + kb * " + st;
+        case M_JAC: return out + " + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1 + kb * " + st;
+        case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1 + kb * " + st;
         case M_HPROD:
-            return "C.out0 + I.off[" + std::to_string(P.kind == EXA_OBJ ? EXA_OFF_FO_OBJ : EXA_OFF_FO_CON) +
+            return out + " + I.off[" + std::to_string(P.kind == EXA_OBJ ? EXA_OFF_FO_OBJ : EXA_OFF_FO_CON) +
                    "] + " + pd + ".o1 + kb * " + st;
-        case M_HESS: return "C.out0 + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2 + kb * " + st;
-        case M_ADJ: return "C.out0 + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op + kb * " + st;
+        case M_HESS: return out + " + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2 + kb * " + st;
+        case M_ADJ: return out + " + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op + kb * " + st;
         default: return "";
     }
+}
+
+// The evaluations a unit performs for one data point: (pattern, sub-mode).
+// A combined Jacobian + Hessian unit runs both sweeps of each member over
+// one set of loads (Jacobian values to out0, Hessian values to out1).
+struct Job {
+    int p, mode;
+    std::string out;
+};
+
+std::vector<Job> jobs_of(const Model& M, int mode, const Unit& U) {
+    std::vector<Job> j;
+    for (int p : U.members) {
+        if (mode != M_JH) {
+            j.push_back({p, mode, "C.out0"});
+            continue;
+        }
+        if (pattern_in_mode(M.pats[p], M_JAC)) j.push_back({p, M_JAC, "C.out0"});
+        if (pattern_in_mode(M.pats[p], M_HESS)) j.push_back({p, M_HESS, "C.out1"});
+    }
+    return j;
 }
 
 bool needs_weight(int mode) { return mode == M_HESS || mode == M_HPROD || mode == M_ADJ || mode == M_JTPROD; }
@@ -603,12 +633,15 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
     os << "        const long long k = kb + threadIdx.x;\n";
     os << "        const int npts = (int)((kend - kb) < nthr ? (kend - kb) : nthr);\n";
-    for (int p : U.members) {
-        const Pattern& P = M.pats[p];
-        if (scalar_mode(mode))
-            os << "        double r" << p << " = 0.0;\n";
+    const std::vector<Job> jobs = jobs_of(M, mode, U);
+    auto oname = [&](const Job& j) {
+        return (scalar_mode(j.mode) ? "r" : "o") + std::to_string(j.p) + (mode == M_JH ? std::string("_") + mode_name(j.mode) : "");
+    };
+    for (const Job& j : jobs) {
+        if (scalar_mode(j.mode))
+            os << "        double " << oname(j) << " = 0.0;\n";
         else
-            os << "        double o" << p << "[" << out_step(P, mode) << "] = {};\n";
+            os << "        double " << oname(j) << "[" << out_step(M.pats[j.p], j.mode) << "] = {};\n";
     }
     os << "        if (k < kend) {\n";
 
@@ -620,7 +653,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         for (auto& r : P.vslots) if (r.col >= 0) icols.insert(r.col);
         for (auto& r : P.pslots) if (r.col >= 0) icols.insert(r.col);
         for (auto& q : P.nodes) if (q.op == EXA_OP_DATA) fcols.insert(q.col);
-        if (needs_weight(mode) && P.kind == EXA_AUG) icols.insert(P.row_icol);
+        if ((needs_weight(mode) || mode == M_JH) && P.kind == EXA_AUG) icols.insert(P.row_icol);
     }
     for (int c : icols) e.named("long long", "ic" + std::to_string(c), "P0.ic[" + std::to_string(c) + "][k]");
     for (int c : fcols) e.named("double", "fc" + std::to_string(c), "P0.fc[" + std::to_string(c) + "][k]");
@@ -650,7 +683,8 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         const std::string idx = k.col < 0 ? off : "ic" + std::to_string(k.col) + " + " + off;
         e.named("double", "p" + std::to_string(r), "TH[" + idx + "]");
     }
-    for (int p : U.members) {
+    for (const Job& j : jobs) {
+        const int p = j.p;
         const Pattern& P = M.pats[p];
         Names nm;
         for (int s = 0; s < P.o1step(); ++s) {
@@ -659,7 +693,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
             nm.ix.push_back("ix" + std::to_string(P.vg[s]));
         }
         for (int s = 0; s < P.pstep(); ++s) nm.p.push_back("p" + std::to_string(P.pg[s]));
-        if (needs_weight(mode)) {
+        if (needs_weight(j.mode)) {
             const std::string pd = "P" + std::to_string(p) + "_";
             std::string w;
             if (P.kind == EXA_OBJ)
@@ -670,8 +704,8 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 w = "Y[" + pd + ".tgt0 + ic" + std::to_string(P.row_icol) + " + " + pd + ".row_off]";
             nm.wgt = e.named("double", "w" + std::to_string(p), w);
         }
-        PatternCg cg(P, mode, e, nm);
-        cg.body(scalar_mode(mode) ? "r" + std::to_string(p) : "o" + std::to_string(p));
+        PatternCg cg(P, j.mode, e, nm);
+        cg.body(oname(j));
     }
     const std::set<std::string> names = e.emit(os, "            ");
     os << "        }\n";
@@ -684,17 +718,16 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         if (names.count("v" + std::to_string(r))) live.vseeds.push_back(r);
     }
     for (int r : prefs) if (names.count("p" + std::to_string(r))) live.prefs.push_back(r);
-    for (int p : U.members) {
+    for (int p : U.members)
         // an objective's weight is the scalar sigma, not a per-point load
         if (M.pats[p].kind != EXA_OBJ && names.count("w" + std::to_string(p))) live.weights++;
-        live.outputs += out_step(M.pats[p], mode);
-    }
+    for (const Job& j : jobs) live.outputs += out_step(M.pats[j.p], j.mode);
 
     // ---- outputs
     switch (mode) {
         case M_OBJ: {
             std::string sum;
-            for (int p : U.members) sum += (sum.empty() ? "" : " + ") + std::string("r") + std::to_string(p);
+            for (const Job& j : jobs) sum += (sum.empty() ? "" : " + ") + oname(j);
             os << "        acc += exa_block_sum(" << sum << ", lds);\n";
             break;
         }
@@ -712,11 +745,12 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
             }
             break;
         default:
-            for (int p : U.members) {
-                const Pattern& P = M.pats[p];
-                const std::string pd = "P" + std::to_string(p) + "_";
-                os << "        " << (staged(P, mode) ? "exa_store<" : "exa_store_direct<") << out_step(P, mode)
-                   << ">(" << dest(P, mode, pd) << ", o" << p << ", npts, lds);\n";
+            for (const Job& j : jobs) {
+                const Pattern& P = M.pats[j.p];
+                const std::string pd = "P" + std::to_string(j.p) + "_";
+                os << "        " << (staged(P, j.mode) ? "exa_store<" : "exa_store_direct<")
+                   << out_step(P, j.mode) << ">(" << dest(P, j.mode, pd, j.out) << ", " << oname(j)
+                   << ", npts, lds);\n";
             }
     }
     os << "    }\n";
@@ -739,6 +773,7 @@ bool pattern_in_mode(const Pattern& P, int mode) {
         case M_JTPROD: return P.kind != EXA_OBJ && P.o1step() > 0;
         case M_HPROD: return P.o2step() > 0;
         case M_ADJ: return P.pstep() > 0 && P.o1step() > 0;
+        case M_JH: return pattern_in_mode(P, M_JAC) || pattern_in_mode(P, M_HESS);
         default: return false;
     }
 }
@@ -776,6 +811,7 @@ std::vector<Unit> units_for(const Model& M, int mode, bool fused) {
 }
 
 int mode_lds_doubles(const Model& M, int mode) {
+    if (mode == M_JH) return std::max(mode_lds_doubles(M, M_JAC), mode_lds_doubles(M, M_HESS));
     int st = 1;
     for (auto& P : M.pats)
         if (pattern_in_mode(P, mode) && staged(P, mode)) st = std::max(st, out_step(P, mode));
@@ -836,80 +872,72 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
 }
 )";
     int ntmp = 0;
-    for (int mode = 0; mode < M_COUNT; ++mode) {
-        // units of both schedules (separate patterns, fused groups)
-        std::map<int, Unit> all;
-        for (int fused = 0; fused < 2; ++fused)
-            for (auto& u : units_for(M, mode, fused != 0)) all[u.code] = u;
-        for (auto& kv : all) {
-            UnitLive L;
-            os << unit_tile(M, mode, kv.second, ntmp, L);
-            if (live) (*live)[{mode, kv.first}] = L;
-        }
-        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") " << kernel_name(mode)
-           << "(ExaCall C) {\n";
-        os << "    __shared__ double lds[" << mode_lds_doubles(M, mode) << "];\n";
-        os << "    (void)lds;\n";
-        os << "    long long w = blockIdx.x;\n";
-        os << "    for (;;) {\n";
-        os << "        long long t;\n";
-        os << "        if (C.persistent) {\n";
-        os << "            if (w >= C.ntiles) return;\n";
-        os << "            t = w;\n";
-        os << "        } else {\n";
-        os << "            // workgroup w runs on XCD w % 8: give each XCD a contiguous tile range\n";
-        os << "            t = (w % 8) * C.per_xcd + w / 8;\n";
-        os << "            if (t >= C.ntiles) return;\n";
-        os << "        }\n";
-        os << "        const ExaTile T = C.tiles[t];\n";
-        os << "        const ExaInstDev& I = C.inst[T.inst];\n";
-        os << "        switch (T.pat) {\n";
-        for (auto& kv : all)
-            os << "            case " << kv.first << ": unit_" << mode_name(mode) << "_" << kv.first
-               << "(C, I, T, lds); break;\n";
-        os << "            default: break;\n";
-        os << "        }\n";
-        os << "        if (!C.persistent) return;\n";
-        os << "        w += gridDim.x;\n";
-        os << "    }\n";
-        os << "}\n";
-    }
-    // Jacobian and Hessian values in one launch (batched evaluation): tile
-    // codes below 64 are Jacobian units, codes 64 + u Hessian unit u;
-    // Jacobian values go to out0, Hessian values to out1.
-    {
-        const int lds = std::max(mode_lds_doubles(M, M_JAC), mode_lds_doubles(M, M_HESS));
-        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") exa_k_jh(ExaCall C) {\n";
+    // Tile loop shared by every kernel.  Non-persistent launches take one
+    // tile per workgroup; workgroup w runs on XCD w % 8, so tile indices are
+    // remapped to give each XCD a contiguous range.  Persistent launches walk
+    // the list with a grid stride, or, with xcd_range, XCD j walks tiles
+    // [xcd_range[j], xcd_range[j+1]) (the grid is then a multiple of 8).
+    auto kernel = [&](const std::string& name, int lds, const std::vector<std::string>& cases) {
+        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") " << name << "(ExaCall C) {\n";
         os << "    __shared__ double lds[" << lds << "];\n";
         os << "    (void)lds;\n";
         os << "    ExaCall H = C;\n";
         os << "    H.out0 = C.out1;\n";
-        os << "    // workgroup b runs on XCD b % 8; with xcd_range, XCD j walks tiles\n";
-        os << "    // [xcd_range[j], xcd_range[j+1]) (grid is a multiple of 8)\n";
-        os << "    long long lo = 0, hi = C.ntiles, w0 = blockIdx.x, step = gridDim.x;\n";
-        os << "    if (C.xcd_range) {\n";
+        os << "    (void)H;\n";
+        os << "    long long w0, hi, step;\n";
+        os << "    if (!C.persistent) {\n";
+        os << "        w0 = (blockIdx.x % 8) * C.per_xcd + blockIdx.x / 8;\n";
+        os << "        hi = w0 < C.ntiles ? w0 + 1 : 0;\n";
+        os << "        step = 1;\n";
+        os << "    } else if (C.xcd_range) {\n";
         os << "        const int j = blockIdx.x % 8;\n";
-        os << "        lo = C.xcd_range[j];\n";
+        os << "        w0 = C.xcd_range[j] + blockIdx.x / 8;\n";
         os << "        hi = C.xcd_range[j + 1];\n";
-        os << "        w0 = lo + blockIdx.x / 8;\n";
         os << "        step = gridDim.x / 8;\n";
+        os << "    } else {\n";
+        os << "        w0 = blockIdx.x;\n";
+        os << "        hi = C.ntiles;\n";
+        os << "        step = gridDim.x;\n";
         os << "    }\n";
         os << "    for (long long w = w0; w < hi; w += step) {\n";
         os << "        const ExaTile T = C.tiles[w];\n";
         os << "        const ExaInstDev& I = C.inst[T.inst];\n";
         os << "        switch (T.pat) {\n";
+        for (auto& c : cases) os << "            " << c << "\n";
+        os << "            default: break;\n";
+        os << "        }\n";
+        os << "    }\n";
+        os << "}\n";
+    };
+    for (int mode = 0; mode < M_COUNT; ++mode) {
+        // units of both schedules (separate patterns, fused groups)
+        std::map<int, Unit> all;
+        for (int fused = 0; fused < 2; ++fused)
+            for (auto& u : units_for(M, mode, fused != 0)) all[u.code] = u;
+        std::vector<std::string> cases;
+        for (auto& kv : all) {
+            UnitLive L;
+            os << unit_tile(M, mode, kv.second, ntmp, L);
+            if (live) (*live)[{mode, kv.first}] = L;
+            cases.push_back("case " + std::to_string(kv.first) + ": unit_" + mode_name(mode) + "_" +
+                            std::to_string(kv.first) + "(C, I, T, lds); break;");
+        }
+        kernel(kernel_name(mode), mode_lds_doubles(M, mode), cases);
+    }
+    // Jacobian tiles (codes < 64, values to out0) and Hessian tiles (codes
+    // 64 + u, values to out1) of separate units in one launch.
+    {
+        std::vector<std::string> cases;
         for (int mode : {M_JAC, M_HESS}) {
             std::set<int> codes;
             for (int fused = 0; fused < 2; ++fused)
                 for (auto& u : units_for(M, mode, fused != 0)) codes.insert(u.code);
             for (int c : codes)
-                os << "            case " << (c + (mode == M_HESS ? 64 : 0)) << ": unit_" << mode_name(mode) << "_"
-                   << c << (mode == M_HESS ? "(H, I, T, lds)" : "(C, I, T, lds)") << "; break;\n";
+                cases.push_back("case " + std::to_string(c + (mode == M_HESS ? 64 : 0)) + ": unit_" + mode_name(mode) +
+                                "_" + std::to_string(c) + (mode == M_HESS ? "(H, I, T, lds)" : "(C, I, T, lds)") +
+                                "; break;");
         }
-        os << "            default: break;\n";
-        os << "        }\n";
-        os << "    }\n";
-        os << "}\n";
+        kernel("exa_k_jhsep", mode_lds_doubles(M, M_JH), cases);
     }
     return os.str();
 }

@@ -106,7 +106,8 @@ enum Mode : int {
     M_JTPROD = 6, // w[row] * J -> first-order buffer (jac part)
     M_HPROD = 7,  // local (w H) v -> first-order buffer
     M_ADJ = 8,    // mixed partials -> parameter buffer
-    M_COUNT = 9
+    M_JH = 9,     // Jacobian and Hessian values of each data point in one pass
+    M_COUNT = 10
 };
 
 struct TNode {            // node of a simplified tree

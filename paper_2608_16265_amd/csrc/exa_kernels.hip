@@ -13,14 +13,26 @@ constexpr int kSegBlock = 256;
 // out[s] (+)= sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
 // the sparse-to-dense compression of Sec. 7.2.3, one lane per segment, with
 // a fixed summation order so the result does not depend on scheduling.
+template <class I>
 __global__ void __launch_bounds__(kSegBlock)
-k_segsum(const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
-         const double* __restrict__ buf, double* __restrict__ out, int64_t nseg, int accumulate) {
+k_segsum(const I* __restrict__ ptr, const I* __restrict__ idx, const double* __restrict__ buf,
+         double* __restrict__ out, int64_t nseg, int accumulate) {
     const int64_t s = (int64_t)blockIdx.x * kSegBlock + threadIdx.x;
     if (s >= nseg) return;
     const int64_t b = ptr[s], e = ptr[s + 1];
     double acc = accumulate ? out[s] : 0.0;
-    for (int64_t j = b; j < e; ++j) acc += buf[idx[j]];
+    int64_t j = b;
+    // four entries at a time: their index and value loads are issued
+    // together, the additions stay in ascending order
+    for (; j + 4 <= e; j += 4) {
+        const I i0 = idx[j], i1 = idx[j + 1], i2 = idx[j + 2], i3 = idx[j + 3];
+        const double v0 = buf[i0], v1 = buf[i1], v2 = buf[i2], v3 = buf[i3];
+        acc += v0;
+        acc += v1;
+        acc += v2;
+        acc += v3;
+    }
+    for (; j < e; ++j) acc += buf[idx[j]];
     out[s] = acc;
 }
 
@@ -46,12 +58,16 @@ __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, int64_t n,
 
 }  // namespace
 
-hipError_t exa_launch_segsum(const int64_t* ptr, const int64_t* idx, const double* buf, double* out,
+hipError_t exa_launch_segsum(const void* ptr, const void* idx, int wide, const double* buf, double* out,
                              int64_t nseg, int accumulate, hipStream_t s) {
     if (nseg <= 0) return hipSuccess;
     const int64_t grid = (nseg + kSegBlock - 1) / kSegBlock;
-    hipLaunchKernelGGL(k_segsum, dim3((unsigned)grid), dim3(kSegBlock), 0, s, ptr, idx, buf, out, nseg,
-                       accumulate);
+    if (wide)
+        hipLaunchKernelGGL(k_segsum<int64_t>, dim3((unsigned)grid), dim3(kSegBlock), 0, s,
+                           (const int64_t*)ptr, (const int64_t*)idx, buf, out, nseg, accumulate);
+    else
+        hipLaunchKernelGGL(k_segsum<int32_t>, dim3((unsigned)grid), dim3(kSegBlock), 0, s,
+                           (const int32_t*)ptr, (const int32_t*)idx, buf, out, nseg, accumulate);
     return hipGetLastError();
 }
 

@@ -93,8 +93,8 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
             fail(EXA_ECOMPILE, "generated kernel missing: " + kernel_name(mode));
         m->fn[mode] = f;
     }
-    if (hipModuleGetFunction(&m->fn_jh, m->mod, "exa_k_jh") != hipSuccess)
-        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jh");
+    if (hipModuleGetFunction(&m->fn_sep, m->mod, "exa_k_jhsep") != hipSuccess)
+        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jhsep");
     g_mods[key] = m;
     return m;
 }
@@ -202,10 +202,20 @@ void build_device(Model& M) {
     D.aug = (double*)D.alloc(M.naug * sizeof(double));
     D.par = (double*)D.alloc(M.nnzp * sizeof(double));
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
+    // maps go to the device as int32 whenever every position fits
     auto up_map = [&](const SegMap& S, DevMap& d) {
-        d.ptr = (const int64_t*)D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
-        d.idx = (const int64_t*)D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
         d.nseg = S.nseg();
+        int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
+        top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
+        d.wide = top >= INT32_MAX ? 1 : 0;
+        if (d.wide) {
+            d.ptr = D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
+            d.idx = D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
+        } else {
+            std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
+            d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
+            d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
+        }
     };
     up_map(M.grad_map, D.grad_map);
     up_map(M.jt_map, D.jt_map);
@@ -335,7 +345,7 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
 }
 
 void segsum(const DevMap& m, const double* buf, double* out, int acc, hipStream_t s) {
-    hip_check(exa_launch_segsum(m.ptr, m.idx, buf, out, m.nseg, acc, s), "segmented reduction");
+    hip_check(exa_launch_segsum(m.ptr, m.idx, m.wide, buf, out, m.nseg, acc, s), "segmented reduction");
 }
 
 }  // namespace exa
@@ -566,6 +576,26 @@ exa_status exa_hess_coord(exa_model* m, const double* x, const double* y, double
     });
 }
 
+exa_status exa_jac_hess_coord(exa_model* m, const double* x, const double* y, double obj_weight,
+                              double* jac_vals, double* hess_vals, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        need(y, M.ncon, "y");
+        need(jac_vals, M.nnzj, "jac_vals");
+        need(hess_vals, M.nnzh, "hess_vals");
+        ExaCall c = blank_call();
+        c.x = x;
+        c.y = y;
+        c.sigma = obj_weight;
+        c.out0 = jac_vals;
+        c.out1 = hess_vals;
+        launch_mode(M, M_JH, c, (hipStream_t)stream);
+        M.counters[3]++;
+        M.counters[4]++;
+    });
+}
+
 exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv, exa_stream_t stream) {
     return guard([&] {
         Model& M = live(m);
@@ -646,8 +676,8 @@ exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, dou
 namespace {
 // public callback ids (exa_counters order) -> internal modes
 int mode_of_callback(int32_t cb) {
-    static const int map[9] = {M_OBJ, M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_JTPROD, M_HPROD, M_ADJ};
-    if (cb < 0 || cb > 8) fail(EXA_EINVAL, "callback id must be in 0..8");
+    static const int map[10] = {M_OBJ, M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_JTPROD, M_HPROD, M_ADJ, M_JH};
+    if (cb < 0 || cb > 9) fail(EXA_EINVAL, "callback id must be in 0..9");
     return map[cb];
 }
 }  // namespace

@@ -13,16 +13,17 @@ namespace exa {
 struct Module {
     hipModule_t mod = nullptr;
     hipFunction_t fn[M_COUNT] = {};
-    hipFunction_t fn_jh = nullptr;   // Jacobian + Hessian tiles in one launch
+    hipFunction_t fn_sep = nullptr;  // separate Jacobian and Hessian tiles in one launch
     std::string source;
     std::vector<char> code;
     ~Module();
 };
 
 struct DevMap {
-    const int64_t* ptr = nullptr;
-    const int64_t* idx = nullptr;
+    const void* ptr = nullptr;  // int32 entries unless wide
+    const void* idx = nullptr;
     int64_t nseg = 0;
+    int wide = 0;
 };
 
 struct DeviceState {

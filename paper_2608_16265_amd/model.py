@@ -216,6 +216,17 @@ class ExaModel:
                                  _stream()))
         return out
 
+    def jac_hess_coord(self, x, y, obj_weight=1.0, jac=None, hess=None):
+        """Jacobian and Hessian values from one launch (bit-identical to the
+        separate callbacks)."""
+        px = self._dev(x, self.nvar, "x")
+        py = self._dev(y, self.ncon, "y")
+        jac = self._out(jac, self.nnzj, x, "jac")
+        hess = self._out(hess, self.nnzh, x, "hess")
+        check(LIB.exa_jac_hess_coord(self._h, px, py, float(obj_weight), C.c_void_p(jac.data_ptr()),
+                                     C.c_void_p(hess.data_ptr()), _stream()))
+        return jac, hess
+
     def jprod(self, x, v, out=None):
         px, pv = self._dev(x, self.nvar, "x"), self._dev(v, self.nvar, "v")
         out = self._out(out, self.ncon, x, "out")

@@ -1,0 +1,85 @@
+"""The parameter adjoint behind torch.autograd.Function: against the
+oracle's mixed partials, against central finite differences (h = 1e-6) of
+the forward, and the closed forms of the loads / cost coefficients."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from exa_modeling.generators import acopf, pde
+from oracle import OracleModel
+from parity_util import assert_close, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("gb", [False, True])
+def test_autograd_backward_matches_oracle_and_fd(gb):
+    _gpu()
+    from paper_2608_16265_amd import ExaModel
+    from paper_2608_16265_amd.adjoint import lagrangian_gradient
+    w = acopf(30, 0, gb_in_theta=gb)
+    em = ExaModel(w.model)
+    o = OracleModel(w.model)
+    X, Y = dev(w.x), dev(w.y)
+    sig = 0.8
+    th0 = w.model.theta.copy()
+    theta = dev(th0).requires_grad_(True)
+    F = lagrangian_gradient(theta, em, X, Y, sig)
+    assert_close("forward", host(F), o.grad_lagrangian(w.x, w.y, sig),
+                 np.abs(o.grad_lagrangian(w.x, w.y, sig)).max())
+    rng = np.random.default_rng(21)
+    wv = rng.standard_normal(o.nvar)
+    (F * dev(wv)).sum().backward()
+    tb = host(theta.grad)
+    ref = o.adjoint_theta(w.x, w.y, sig, wv)
+    assert_close("adjoint", tb, ref, np.abs(ref).max())
+    # central finite differences of the GPU forward, h = 1e-6
+    h = 1e-6
+    idx = rng.choice(th0.size, 12, replace=False)
+    for t in idx:
+        tp, tm = th0.copy(), th0.copy()
+        tp[t] += h
+        tm[t] -= h
+        fp = host(lagrangian_gradient(dev(tp), em, X, Y, sig)) @ wv
+        fm = host(lagrangian_gradient(dev(tm), em, X, Y, sig)) @ wv
+        fd = (fp - fm) / (2 * h)
+        assert abs(tb[t] - fd) <= 1e-6 * max(1.0, abs(fd)), (t, tb[t], fd)
+    # closed forms: loads enter additively; d/dc1 = sigma w_pg; d/dc2 = 2 sigma pg w_pg
+    to, ng, nb = w.meta["theta_offsets"], w.meta["ng"], w.meta["nb"]
+    pg = w.x[w.meta["offsets"]["pg"]:][:ng]
+    wpg = wv[w.meta["offsets"]["pg"]:][:ng]
+    assert np.all(tb[to["pd"]:to["pd"] + 2 * nb] == 0.0)
+    assert np.array_equal(tb[to["c1"]:to["c1"] + ng], sig * wpg)
+    assert np.allclose(tb[to["c2"]:to["c2"] + ng], 2 * sig * pg * wpg, rtol=1e-15, atol=0)
+
+
+def test_adjoint_10k_matches_oracle():
+    _gpu()
+    from paper_2608_16265_amd import ExaModel
+    w = acopf(10000, 2000)
+    em = ExaModel(w.model)
+    o = OracleModel(w.model)
+    wv = np.random.default_rng(2000).standard_normal(o.nvar)
+    got = host(em.adjoint_theta(dev(w.x), dev(w.y), 1.0, dev(wv)))
+    ref = o.adjoint_theta(w.x, w.y, 1.0, wv)
+    assert_close("adjoint10k", got, ref, np.abs(ref).max())
+
+
+def test_gradcheck_small():
+    """torch.autograd.gradcheck on a PDE model whose theta is empty would be
+    vacuous, so use the branch-parameter ACOPF with a few entries perturbed."""
+    _gpu()
+    from paper_2608_16265_amd import ExaModel
+    from paper_2608_16265_amd.adjoint import LagrangianGradient
+    w = acopf(30, 3, gb_in_theta=True)
+    em = ExaModel(w.model)
+    X, Y = dev(w.x), dev(w.y)
+    theta = dev(w.model.theta).requires_grad_(True)
+    f = lambda th: LagrangianGradient.apply(th, em, X, Y, 1.0)
+    assert torch.autograd.gradcheck(f, (theta,), eps=1e-6, atol=1e-5, rtol=1e-6, fast_mode=True)

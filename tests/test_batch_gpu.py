@@ -17,17 +17,18 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("autotune,epl,grid,graph,fuse,xcd", [
-    (False, 1, 64, True, False, False), (False, 8, 0, False, True, False),
-    (False, 2, 16, True, False, True), (True, 4, 0, True, True, True)])
-def test_batch_bitwise_equal_to_plain(autotune, epl, grid, graph, fuse, xcd):
+@pytest.mark.parametrize("autotune,epl,grid,graph,fuse,xcd,sep", [
+    (False, 1, 64, True, False, False, True), (False, 8, 0, False, True, False, False),
+    (False, 2, 16, True, False, True, False), (False, 3, 24, True, True, True, True),
+    (True, 4, 0, True, True, True, False)])
+def test_batch_bitwise_equal_to_plain(autotune, epl, grid, graph, fuse, xcd, sep):
     _gpu()
     from paper_2608_16265_amd import ExaModel
     from paper_2608_16265_amd.batch import ExaBatch
     wls = acopf_batch(6, 1000, lo=30, hi=900)
     ems = [ExaModel(w.model) for w in wls]
     b = ExaBatch(ems, autotune=autotune, epl=epl, grid=grid, use_graph=graph, fuse=fuse,
-                 xcd_aware=xcd)
+                 xcd_aware=xcd, separate=sep)
     X = b.concat_x([w.x for w in wls])
     Y = b.concat_y([w.y for w in wls])
     J = torch.full((b.total("jac"),), np.nan, dtype=torch.float64, device="cuda:0")

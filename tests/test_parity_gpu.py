@@ -99,6 +99,9 @@ def check_all(w, em=None, o=None, tag=""):
     assert_close(tag + "jac", host(em.jac_coord(X)), jr, column_scale(o, jr, 1))
     hr = o.hess_coord(x, y, sig)
     assert_close(tag + "hess", host(em.hess_coord(X, Y, sig)), hr, column_scale(o, hr, 2))
+    jc, hc = em.jac_hess_coord(X, Y, sig)
+    assert np.array_equal(host(jc), host(em.jac_coord(X))), tag + "jac_hess vs jac"
+    assert np.array_equal(host(hc), host(em.hess_coord(X, Y, sig))), tag + "jac_hess vs hess"
     assert_close(tag + "jprod", host(em.jprod(X, Vd)), o.jprod(x, v), a["jprod"])
     assert_close(tag + "jtprod", host(em.jtprod(X, W)), o.jtprod(x, wv), a["jtprod"])
     assert_close(tag + "hprod", host(em.hprod(X, Y, sig, Vd)), o.hprod(x, y, sig, v), a["hprod"])
