@@ -136,11 +136,17 @@ def leg_single(name, wl, steps, warmup, full_step=True):
         "cons": lambda: em.cons(X, c),
         "jac_coord": lambda: em.jac_coord(X, jv),
         "hess_coord": lambda: em.hess_coord(X, Y, 1.0, hv),
+        "jac_hess_coord": lambda: em.jac_hess_coord(X, Y, 1.0, jv, hv),
         "jprod": lambda: em.jprod(X, V, Jv),
         "jtprod": lambda: em.jtprod(X, W, Jtw),
         "hprod": lambda: em.hprod(X, Y, 1.0, V, Hv),
     }
-    order = list(cbs) if full_step else ["jac_coord", "hess_coord"]
+    # a solver iterate: every callback once; Jacobian and Hessian values come
+    # from the combined call (bit-identical to jac_coord + hess_coord)
+    order = (["obj", "grad", "cons", "jac_hess_coord", "jprod", "jtprod", "hprod"] if full_step
+             else ["jac_hess_coord"])
+    for k in ("jac_coord", "hess_coord"):  # tune the separate callbacks too
+        cbs[k]()
 
     def step():
         for k in order:
@@ -155,20 +161,25 @@ def leg_single(name, wl, steps, warmup, full_step=True):
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / steps
     per_cb = {k: best_of_3(fn) * 1e6 for k, fn in cbs.items()}
-    k_mean, k_n = kernel_ms(cbs["hess_coord"])
+    k_mean, k_n = kernel_ms(cbs["jac_hess_coord"])
+    kh_mean, _ = kernel_ms(cbs["hess_coord"])
     kj_mean, _ = kernel_ms(cbs["jac_coord"])
-    rd, wr = em.kernel_bytes("hess")
+    rd, wr = em.kernel_bytes("jac_hess")
     nbytes = rd + wr
-    sched = {k: em.schedule(k) for k in ("jac", "hess")}
+    hrd, hwr = em.kernel_bytes("hess")
+    sched = {k: em.schedule(k) for k in ("jac", "hess", "jac_hess")}
     nnz = em.nnzj + em.nnzh
     res = dict(
         name=name, nvar=em.nvar, ncon=em.ncon, nnzj=em.nnzj, nnzh=em.nnzh,
         build_s=round(build_s, 3), step_s=step_s, nnz_per_s=nnz / step_s,
-        jac_hess_nnz_per_s=nnz / ((per_cb["jac_coord"] + per_cb["hess_coord"]) * 1e-6),
+        jac_hess_nnz_per_s=nnz / (per_cb["jac_hess_coord"] * 1e-6),
+        jac_plus_hess_nnz_per_s=nnz / ((per_cb["jac_coord"] + per_cb["hess_coord"]) * 1e-6),
         callbacks_us={k: round(v, 2) for k, v in per_cb.items()},
-        hess_kernel_us=round(k_mean * 1e3, 3), hess_kernel_launches_timed=k_n,
-        jac_kernel_us=round(kj_mean * 1e3, 3), hess_bytes=nbytes,
-        hess_gbs=nbytes / (k_mean * 1e-3) / 1e9, hess_read_bytes=rd, hess_write_bytes=wr,
+        jh_kernel_us=round(k_mean * 1e3, 3), kernel_launches_timed=k_n,
+        hess_kernel_us=round(kh_mean * 1e3, 3), jac_kernel_us=round(kj_mean * 1e3, 3),
+        jh_bytes=nbytes, jh_read_bytes=rd, jh_write_bytes=wr,
+        jh_gbs=nbytes / (k_mean * 1e-3) / 1e9,
+        hess_bytes=hrd + hwr, hess_gbs=(hrd + hwr) / (kh_mean * 1e-3) / 1e9,
         schedule=sched,
     )
     em.close()
@@ -343,16 +354,21 @@ def main():
         log(json.dumps(r))
         out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
         out["config"] = {"workload": "acopf-10000-bus (13,500 branches, 2,000 generators, seed 1)",
-                         "step": "obj+grad+cons+jac_coord+hess_coord+jprod+jtprod+hprod",
+                         "step": "obj+grad+cons+jac_hess_coord+jprod+jtprod+hprod",
                          "nvar": r["nvar"], "ncon": r["ncon"], "nnzj": r["nnzj"],
                          "nnzh": r["nnzh"], "schedule": r["schedule"]}
         out["callbacks_us"] = r["callbacks_us"]
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
-        out["roofline"] = {"kernel": "exa_k_hess", "bound": "hbm", "achieved": r["hess_gbs"],
+        out["jac_plus_hess_nnz_per_s"] = r["jac_plus_hess_nnz_per_s"]
+        out["roofline"] = {"kernel": "exa_k_jh", "bound": "hbm", "achieved": r["jh_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": r["hess_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                           "bytes_per_launch": r["hess_bytes"], "read_bytes": r["hess_read_bytes"],
-                           "write_bytes": r["hess_write_bytes"], "launch_us": r["hess_kernel_us"]}
+                           "frac": r["jh_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": r["jh_bytes"], "read_bytes": r["jh_read_bytes"],
+                           "write_bytes": r["jh_write_bytes"], "launch_us": r["jh_kernel_us"]}
+        out["roofline_hess_kernel"] = {"kernel": "exa_k_hess", "achieved": r["hess_gbs"],
+                                       "frac": r["hess_gbs"] / HBM_PEAK_GBS,
+                                       "bytes_per_launch": r["hess_bytes"],
+                                       "launch_us": r["hess_kernel_us"]}
         if not args.no_cpu_baseline:
             log("leg: cpu baseline")
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
@@ -365,8 +381,14 @@ def main():
                       "nnzj": r["nnzj"], "nnzh": r["nnzh"],
                       "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"],
                       "callbacks_us": r["callbacks_us"],
-                      "roofline_hess": {"achieved": r["hess_gbs"], "peak": HBM_PEAK_GBS,
-                                        "unit": "GB/s", "frac": r["hess_gbs"] / HBM_PEAK_GBS,
+                      "roofline_jh": {"kernel": "exa_k_jh", "achieved": r["jh_gbs"],
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": r["jh_gbs"] / HBM_PEAK_GBS,
+                                      "bytes_per_launch": r["jh_bytes"],
+                                      "launch_us": r["jh_kernel_us"]},
+                      "roofline_hess": {"kernel": "exa_k_hess", "achieved": r["hess_gbs"],
+                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": r["hess_gbs"] / HBM_PEAK_GBS,
                                         "bytes_per_launch": r["hess_bytes"],
                                         "launch_us": r["hess_kernel_us"]}}
         if args.only == "pde":

@@ -737,8 +737,8 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 const Pattern& P = M.pats[p];
                 const std::string pd = "P" + std::to_string(p) + "_";
                 if (P.kind == EXA_CON)
-                    os << "        if (k < kend) C.out0[I.off[" << EXA_OFF_ROWS << "] + " << pd << ".o0 + k] = r" << p
-                       << ";\n";
+                    os << "        if (k < kend) __builtin_nontemporal_store(r" << p << ", &C.out0[I.off[" << EXA_OFF_ROWS
+                       << "] + " << pd << ".o0 + k]);\n";
                 else
                     os << "        if (k < kend) C.out1[I.off[" << EXA_OFF_AUG << "] + " << pd << ".o0 + k] = r" << p
                        << ";\n";
@@ -748,9 +748,12 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
             for (const Job& j : jobs) {
                 const Pattern& P = M.pats[j.p];
                 const std::string pd = "P" + std::to_string(j.p) + "_";
-                os << "        " << (staged(P, j.mode) ? "exa_store<" : "exa_store_direct<")
-                   << out_step(P, j.mode) << ">(" << dest(P, j.mode, pd, j.out) << ", " << oname(j)
-                   << ", npts, lds);\n";
+                const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
+                if (staged(P, j.mode))
+                    os << "        exa_store<" << out_step(P, j.mode) << ", " << (final_out ? "true" : "false") << ">(";
+                else
+                    os << "        exa_store_direct<" << out_step(P, j.mode) << ">(";
+                os << dest(P, j.mode, pd, j.out) << ", " << oname(j) << ", npts, lds);\n";
             }
     }
     os << "    }\n";
@@ -828,7 +831,7 @@ std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLi
     os << "static_assert(sizeof(ExaInstDev) == " << sizeof(ExaInstDev) << ", \"layout\");\n";
     os << "static_assert(sizeof(ExaTile) == " << sizeof(ExaTile) << ", \"layout\");\n";
     os << "static_assert(sizeof(ExaCall) == " << sizeof(ExaCall) << ", \"layout\");\n";
-    os << R"(
+    std::string pre = R"(
 __device__ __forceinline__ double exa_powi(double u, int n) {
     double r = 1.0, b = u;
     unsigned m = n < 0 ? (unsigned)(-n) : (unsigned)n;
@@ -837,17 +840,27 @@ __device__ __forceinline__ double exa_powi(double u, int n) {
 }
 // Writes the per-lane slices of `npts` consecutive data points (ST doubles
 // each) to dst through LDS, so that the workgroup stores contiguous memory.
-template <int ST>
+// NT marks final outputs, written with non-temporal stores: they are never
+// read back by the kernel, and streaming them past the caches keeps x and the
+// data columns resident (intermediate buffers read back by a reduction use
+// ordinary stores).
+template <int ST, bool NT>
 __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double* o, int npts, double* lds) {
     if (ST == 1) {
-        if ((int)threadIdx.x < npts) dst[threadIdx.x] = o[0];
+        if ((int)threadIdx.x < npts) {
+            if (NT) __builtin_nontemporal_store(o[0], &dst[threadIdx.x]);
+            else dst[threadIdx.x] = o[0];
+        }
         return;
     }
 #pragma unroll
     for (int s = 0; s < ST; ++s) lds[threadIdx.x * ST + s] = o[s];
     __syncthreads();
     const int n = npts * ST;
-    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) dst[i] = lds[i];
+    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
+        if (NT) __builtin_nontemporal_store(lds[i], &dst[i]);
+        else dst[i] = lds[i];
+    }
     __syncthreads();
 }
 // Direct (unstaged) variant for slices too wide for LDS.
@@ -871,6 +884,7 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
     return r;
 }
 )";
+    os << pre;
     int ntmp = 0;
     // Tile loop shared by every kernel.  Non-persistent launches take one
     // tile per workgroup; workgroup w runs on XCD w % 8, so tile indices are

@@ -202,6 +202,7 @@ void build_device(Model& M) {
     D.aug = (double*)D.alloc(M.naug * sizeof(double));
     D.par = (double*)D.alloc(M.nnzp * sizeof(double));
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
+
     // maps go to the device as int32 whenever every position fits
     auto up_map = [&](const SegMap& S, DevMap& d) {
         d.nseg = S.nseg();
