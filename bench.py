@@ -99,7 +99,7 @@ def kernel_ms(fn, n=200):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fn()
     torch.cuda.synchronize()
-    for _ in range(6):
+    for _ in range(24):  # ~50 ms of device work, longer than enqueueing n calls
         a = a @ a * 1e-4
     e0.record()
     for _ in range(n):
@@ -107,6 +107,29 @@ def kernel_ms(fn, n=200):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / n, n
+
+
+def profiled_traffic(summary, model):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    calibrated on a plain copy) as committed in profiles/, or None when the
+    generated kernels have changed since (their source hash differs)."""
+    import hashlib
+    from paper_2608_16265_amd import ExaModel
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = ExaModel(model, host_only=True).generated_source()
+    if hashlib.sha256(src.encode()).hexdigest()[:16] != kv.get("source_sha256_16"):
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 # ------------------------------------------------------------------- legs
@@ -360,9 +383,11 @@ def main():
         out["callbacks_us"] = r["callbacks_us"]
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
         out["jac_plus_hess_nnz_per_s"] = r["jac_plus_hess_nnz_per_s"]
+        from exa_modeling.generators import acopf as _acopf
+        traffic = profiled_traffic("acopf10k_jac_hess.md", _acopf(30, 0).model)
         out["roofline"] = {"kernel": "exa_k_jh", "bound": "hbm", "achieved": r["jh_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": r["jh_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "frac": r["jh_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                            "bytes_per_launch": r["jh_bytes"], "read_bytes": r["jh_read_bytes"],
                            "write_bytes": r["jh_write_bytes"], "launch_us": r["jh_kernel_us"]}
         out["roofline_hess_kernel"] = {"kernel": "exa_k_hess", "achieved": r["hess_gbs"],

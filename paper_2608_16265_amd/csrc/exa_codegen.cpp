@@ -209,7 +209,7 @@ class PatternCg {
                 tangent(SEED_VEC, -1, tg);
                 std::vector<std::string> Hc(P_.o1step(), Z), Pt;
                 reverse_tangent(adj, tg, Hc, Pt, false);
-                for (int s = 0; s < P_.o1step(); ++s) e_.out(slot(s), Hc[s]);
+                for (size_t i = 0; i < P_.hvs.size(); ++i) e_.out(slot((int)i), Hc[P_.hvs[i]]);
                 break;
             }
             case M_ADJ: {
@@ -552,7 +552,8 @@ class PatternCg {
 
 int out_step(const Pattern& P, int mode) {
     switch (mode) {
-        case M_GRAD: case M_JAC: case M_JTPROD: case M_HPROD: return P.o1step();
+        case M_HPROD: return (int)P.hvs.size();
+        case M_GRAD: case M_JAC: case M_JTPROD: return P.o1step();
         case M_HESS: return P.o2step();
         case M_ADJ: return P.pstep();
         default: return 1;
@@ -580,9 +581,7 @@ std::string dest(const Pattern& P, int mode, const std::string& pd, const std::s
         case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1 + kb * " + st;
         case M_JAC: return out + " + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1 + kb * " + st;
         case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1 + kb * " + st;
-        case M_HPROD:
-            return out + " + I.off[" + std::to_string(P.kind == EXA_OBJ ? EXA_OFF_FO_OBJ : EXA_OFF_FO_CON) +
-                   "] + " + pd + ".o1 + kb * " + st;
+        case M_HPROD: return out + " + " + pd + ".oh + kb * " + st;
         case M_HESS: return out + " + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2 + kb * " + st;
         case M_ADJ: return out + " + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op + kb * " + st;
         default: return "";
@@ -611,6 +610,59 @@ std::vector<Job> jobs_of(const Model& M, int mode, const Unit& U) {
 }
 
 bool needs_weight(int mode) { return mode == M_HESS || mode == M_HPROD || mode == M_ADJ || mode == M_JTPROD; }
+
+// Value (cons) or tangent (jprod) of augmentation pattern a at one of its
+// data points, for the base row that pulls it; fills `live`.
+std::string aug_fn(const Model& M, int mode, int a, int& ntmp, UnitLive& live) {
+    const Pattern& P = M.pats[a];
+    std::ostringstream os;
+    os << "__device__ __forceinline__ double aug_" << mode_name(mode) << "_" << a
+       << "(const ExaCall& C, const ExaInstDev& I, long long k) {\n";
+    os << "    const ExaPatDev& Pa = I.pat[" << a << "];\n";
+    os << "    const double* __restrict__ X = C.x + I.off[" << EXA_OFF_X << "];\n";
+    os << "    const double* __restrict__ V = C.v + I.off[" << EXA_OFF_X << "];\n";
+    os << "    const double* __restrict__ TH = I.theta;\n";
+    os << "    (void)X; (void)V; (void)TH;\n";
+    os << "    double r = 0.0;\n";
+    Em e(ntmp);
+    std::set<int> icols, fcols;
+    for (auto& r : P.vslots) if (r.col >= 0) icols.insert(r.col);
+    for (auto& r : P.pslots) if (r.col >= 0) icols.insert(r.col);
+    for (auto& q : P.nodes) if (q.op == EXA_OP_DATA) fcols.insert(q.col);
+    for (int c : icols) e.named("long long", "ic" + std::to_string(c), "Pa.ic[" + std::to_string(c) + "][k]");
+    for (int c : fcols) e.named("double", "fc" + std::to_string(c), "Pa.fc[" + std::to_string(c) + "][k]");
+    Names nm;
+    for (int s = 0; s < P.o1step(); ++s) {
+        const RefKey& k = P.vslots[s];
+        const std::string off = "Pa.roff[" + std::to_string(s) + "]";
+        const std::string idx = k.col < 0 ? off : "ic" + std::to_string(k.col) + " + " + off;
+        e.named("long long", "ix" + std::to_string(s), idx);
+        e.named("double", "x" + std::to_string(s), "X[ix" + std::to_string(s) + "]");
+        if (mode == M_JPROD) e.named("double", "v" + std::to_string(s), "V[ix" + std::to_string(s) + "]");
+        nm.x.push_back("x" + std::to_string(s));
+        nm.v.push_back("v" + std::to_string(s));
+        nm.ix.push_back("ix" + std::to_string(s));
+    }
+    for (int s = 0; s < P.pstep(); ++s) {
+        const RefKey& k = P.pslots[s];
+        const std::string off = "Pa.roff[" + std::to_string(P.o1step() + s) + "]";
+        const std::string idx = k.col < 0 ? off : "ic" + std::to_string(k.col) + " + " + off;
+        e.named("double", "p" + std::to_string(s), "TH[" + idx + "]");
+        nm.p.push_back("p" + std::to_string(s));
+    }
+    PatternCg cg(P, mode, e, nm);
+    cg.body("r");
+    const std::set<std::string> names = e.emit(os, "    ");
+    os << "    return r;\n}\n";
+    for (int c : icols) if (names.count("ic" + std::to_string(c))) live.icols.push_back(c);
+    for (int c : fcols) if (names.count("fc" + std::to_string(c))) live.fcols.push_back(c);
+    for (int s = 0; s < P.o1step(); ++s) {
+        if (names.count("x" + std::to_string(s))) live.vrefs.push_back(s);
+        if (names.count("v" + std::to_string(s))) live.vseeds.push_back(s);
+    }
+    for (int s = 0; s < P.pstep(); ++s) if (names.count("p" + std::to_string(s))) live.prefs.push_back(s);
+    return os.str();
+}
 
 // Generates the tile function of one unit; fills `live`.
 std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLive& live) {
@@ -706,8 +758,28 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         }
         PatternCg cg(P, j.mode, e, nm);
         cg.body(oname(j));
+        if (mode == M_GRAD)
+            // every variable has at most one contribution: write g directly
+            for (int s = 0; s < P.o1step(); ++s)
+                e.out("if (C.direct) C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
+                      oname(j) + "[" + std::to_string(s) + "]");
     }
     const std::set<std::string> names = e.emit(os, "            ");
+    if (mode == M_CONS || mode == M_JPROD) {
+        // base rows pull the augmentation terms that add to them, in
+        // declaration order of the augmentations, points ascending
+        for (const Job& j : jobs) {
+            const Pattern& P = M.pats[j.p];
+            if (P.kind != EXA_CON) continue;
+            for (int a : P.augs) {
+                if (M.pats[a].ndata == 0) continue;
+                const std::string pa = "I.pat[" + std::to_string(a) + "]";
+                os << "            for (int j = " << pa << ".rptr[k]; j < " << pa << ".rptr[k + 1]; ++j) "
+                   << oname(j) << " += aug_" << mode_name(mode) << "_" << a << "(C, I, (long long)" << pa
+                   << ".ridx[j]);\n";
+            }
+        }
+    }
     os << "        }\n";
 
     // ---- liveness record
@@ -749,6 +821,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 const Pattern& P = M.pats[j.p];
                 const std::string pd = "P" + std::to_string(j.p) + "_";
                 const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
+                if (mode == M_GRAD) os << "        if (!C.direct)\n    ";
                 if (staged(P, j.mode))
                     os << "        exa_store<" << out_step(P, j.mode) << ", " << (final_out ? "true" : "false") << ">(";
                 else
@@ -768,11 +841,11 @@ bool pattern_in_mode(const Pattern& P, int mode) {
     if (P.ndata == 0) return false;
     switch (mode) {
         case M_OBJ: return P.kind == EXA_OBJ;
-        case M_CONS: return P.kind != EXA_OBJ;
+        case M_CONS: return P.kind == EXA_CON;
         case M_GRAD: return P.kind == EXA_OBJ && P.o1step() > 0;
         case M_JAC: return P.kind != EXA_OBJ && P.o1step() > 0;
         case M_HESS: return P.o2step() > 0;
-        case M_JPROD: return P.kind != EXA_OBJ;
+        case M_JPROD: return P.kind == EXA_CON;
         case M_JTPROD: return P.kind != EXA_OBJ && P.o1step() > 0;
         case M_HPROD: return P.o2step() > 0;
         case M_ADJ: return P.pstep() > 0 && P.o1step() > 0;
@@ -928,6 +1001,13 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
         std::map<int, Unit> all;
         for (int fused = 0; fused < 2; ++fused)
             for (auto& u : units_for(M, mode, fused != 0)) all[u.code] = u;
+        if (mode == M_CONS || mode == M_JPROD)
+            for (size_t a = 0; a < M.pats.size(); ++a)
+                if (M.pats[a].kind == EXA_AUG && M.pats[a].ndata > 0) {
+                    UnitLive L;
+                    os << aug_fn(M, mode, (int)a, ntmp, L);
+                    if (live) (*live)[{mode, 1000 + (int)a}] = L;
+                }
         std::vector<std::string> cases;
         for (auto& kv : all) {
             UnitLive L;
@@ -936,6 +1016,10 @@ __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
             cases.push_back("case " + std::to_string(kv.first) + ": unit_" + mode_name(mode) + "_" +
                             std::to_string(kv.first) + "(C, I, T, lds); break;");
         }
+        if (mode == M_GRAD)  // entries of g no objective term touches
+            cases.push_back("case " + std::to_string(EXA_ZERO_TILE) +
+                            ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) "
+                            "C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;");
         kernel(kernel_name(mode), mode_lds_doubles(M, mode), cases);
     }
     // Jacobian tiles (codes < 64, values to out0) and Hessian tiles (codes

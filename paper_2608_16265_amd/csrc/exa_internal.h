@@ -43,6 +43,8 @@ void set_last_error(const std::string& msg);
 // (variable slots first, then parameter slots), so that every instance of a
 // formulation runs the same code whatever its block offsets.
 #define EXA_MAX_REFS 48
+// Tile code of a zero-fill tile (entries of g no objective term touches).
+#define EXA_ZERO_TILE 1023
 
 #define EXA_DEVICE_STRUCTS                                                       \
     struct ExaPatDev {                                                           \
@@ -53,10 +55,13 @@ void set_last_error(const std::string& msg);
         long long o1;                                                            \
         long long o2;                                                            \
         long long op;                                                            \
+        long long oh;                                                            \
         long long tgt0;                                                          \
         long long row_off;                                                       \
         int row_ic;                                                              \
         int pad0;                                                                \
+        const int* rptr;                                                         \
+        const int* ridx;                                                         \
         long long roff[48];                                                      \
     };                                                                           \
     struct ExaInstDev {                                                          \
@@ -84,7 +89,7 @@ void set_last_error(const std::string& msg);
         double* out1;                                                            \
         double sigma;                                                            \
         int persistent;                                                          \
-        int pad2;                                                                \
+        int direct;                                                              \
         const long long* xcd_range;                                              \
     };
 
@@ -150,6 +155,14 @@ struct Pattern {
     // reference each of this pattern's var / param slots maps to
     int group = -1;
     std::vector<int> vg, pg;
+    // AUG: data points grouped by the target row they add to (CSR over the
+    // target block's rows, points ascending): the row's lane pulls them
+    std::vector<int32_t> rptr, ridx;
+    // CON: augmentation patterns adding to this block, declaration order
+    std::vector<int> augs;
+    // var slots that occur in some Hessian pair (the only ones H v reaches)
+    std::vector<int> hvs;
+    int64_t oh = 0;   // first entry of this pattern in the H v buffer
 
     int o1step() const { return (int)vslots.size(); }
     int o2step() const { return (int)hslots.size(); }
@@ -205,12 +218,16 @@ struct DeviceState;  // defined in exa_runtime.cpp
 
 struct Model {
     int64_t nvar = 0, ncon = 0, ntheta = 0;
-    int64_t nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0;
+    int64_t nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0, nhv = 0;
+    // every variable gets at most one objective-gradient contribution: the
+    // gradient kernel writes g directly (plus zero tiles for the rest)
+    bool grad_direct = false;
+    std::vector<std::pair<int64_t, int64_t>> grad_zero;  // untouched ranges of g
     std::vector<Pattern> pats;
     std::vector<Group> groups;
     std::vector<double> xl, xu, theta;
     // reduction maps (positions in the first-order buffer: grad part first)
-    SegMap grad_map, jt_map, h_map, aug_map, par_map;
+    SegMap grad_map, jt_map, h_map, par_map;
     bool host_only = false;
     int block = 256, epl = 4;
     bool autotune = false, fuse = false;

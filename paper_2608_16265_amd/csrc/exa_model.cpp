@@ -377,6 +377,13 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             P.op = nnzp;
             nnzp += P.ndata * P.pstep();
         }
+        for (int s = 0; s < P.o1step(); ++s) {
+            bool curved = false;
+            for (auto& h : P.hslots) curved |= h.first == s || h.second == s;
+            if (curved) P.hvs.push_back(s);
+        }
+        P.oh = M.nhv;
+        M.nhv += P.ndata * (int64_t)P.hvs.size();
     }
     M.ncon = ncon;
     M.nnzj = nnzj;
@@ -418,37 +425,53 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
         }
     }
 
+    // ---- augmentation rows: each base row pulls the terms that add to it
+    for (auto& P : M.pats) {
+        if (P.kind != EXA_AUG) continue;
+        Pattern& T = M.pats[P.target];
+        T.augs.push_back(P.index);
+        P.rptr.assign(T.ndata + 1, 0);
+        for (int64_t k = 0; k < P.ndata; ++k) P.rptr[(int64_t)P.icols[P.row_icol][k] + P.row_off + 1]++;
+        for (int64_t r = 0; r < T.ndata; ++r) P.rptr[r + 1] += P.rptr[r];
+        P.ridx.assign(P.ndata, 0);
+        std::vector<int32_t> fill(P.rptr.begin(), P.rptr.end() - 1);
+        for (int64_t k = 0; k < P.ndata; ++k) P.ridx[fill[(int64_t)P.icols[P.row_icol][k] + P.row_off]++] = (int32_t)k;
+    }
+
     // ---- reduction maps (Sec. 7.2.3): sorted by target, ascending positions
-    std::vector<std::pair<int64_t, int64_t>> g, jt, h, ag, pr;
+    std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr;
     for (auto& P : M.pats) {
         const int st = P.o1step();
-        const bool curved = P.o2step() > 0;
         for (int64_t k = 0; k < P.ndata; ++k)
             for (int s = 0; s < st; ++s) {
                 const int64_t v = P.var_index(s, k);
-                if (P.kind == EXA_OBJ) {
-                    const int64_t pos = P.o1 + k * st + s;
-                    g.emplace_back(v, pos);
-                    if (curved) h.emplace_back(v, pos);
-                } else {
-                    const int64_t pos = nnzg + P.o1 + k * st + s;
-                    jt.emplace_back(v, pos);
-                    if (curved) h.emplace_back(v, pos);
-                }
+                if (P.kind == EXA_OBJ)
+                    g.emplace_back(v, P.o1 + k * st + s);
+                else
+                    jt.emplace_back(v, nnzg + P.o1 + k * st + s);
             }
-        if (P.kind == EXA_AUG)
-            for (int64_t k = 0; k < P.ndata; ++k) ag.emplace_back(P.row(k), P.o0 + k);
+        const int hs = (int)P.hvs.size();
+        for (int64_t k = 0; k < P.ndata; ++k)
+            for (int i = 0; i < hs; ++i) h.emplace_back(P.var_index(P.hvs[i], k), P.oh + k * hs + i);
         if (P.pstep() > 0 && P.o1step() > 0)
             for (int64_t k = 0; k < P.ndata; ++k)
                 for (int t = 0; t < P.pstep(); ++t)
                     pr.emplace_back(P.par_index(t, k), P.op + k * P.pstep() + t);
     }
-    // h holds objective positions first, then constraint ones: both blocks are
-    // ascending, so the concatenation is ascending.
+    // H v positions follow declaration order, so h is ascending as built.
     build_map(M.grad_map, M.nvar, g);
+    M.grad_direct = true;
+    for (int64_t v = 0; v < M.nvar; ++v)
+        if (M.grad_map.ptr[v + 1] - M.grad_map.ptr[v] > 1) M.grad_direct = false;
+    for (int64_t v = 0; v < M.nvar;) {
+        if (M.grad_map.ptr[v + 1] > M.grad_map.ptr[v]) { ++v; continue; }
+        int64_t e = v;
+        while (e < M.nvar && M.grad_map.ptr[e + 1] == M.grad_map.ptr[e]) ++e;
+        M.grad_zero.emplace_back(v, e - v);
+        v = e;
+    }
     build_map(M.jt_map, M.nvar, jt);
     build_map(M.h_map, M.nvar, h);
-    build_map(M.aug_map, M.ncon, ag);
     build_map(M.par_map, M.ntheta, pr);
     M.signature = pattern_signature(M);
 }

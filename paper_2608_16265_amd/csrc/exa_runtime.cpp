@@ -166,9 +166,14 @@ void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
         d.o1 = P.o1;
         d.o2 = P.o2;
         d.op = P.op;
+        d.oh = P.oh;
         d.tgt0 = P.tgt0;
         d.row_off = P.row_off;
         d.row_ic = P.row_icol;
+        if (P.kind == EXA_AUG) {
+            d.rptr = (const int*)D.upload(P.rptr.data(), P.rptr.size() * sizeof(int32_t));
+            d.ridx = (const int*)D.upload(P.ridx.data(), P.ridx.size() * sizeof(int32_t));
+        }
         for (int r = 0; r < P.o1step(); ++r) d.roff[r] = P.vslots[r].off;
         for (int r = 0; r < P.pstep(); ++r) d.roff[P.o1step() + r] = P.pslots[r].off;
     }
@@ -199,8 +204,8 @@ void build_device(Model& M) {
         D.sched[mode].tuned = fixed || !M.autotune;
     }
     D.fo = (double*)D.alloc((M.nnzg + M.nnzj) * sizeof(double));
-    D.aug = (double*)D.alloc(M.naug * sizeof(double));
     D.par = (double*)D.alloc(M.nnzp * sizeof(double));
+    D.hv = (double*)D.alloc(M.nhv * sizeof(double));
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
 
     // maps go to the device as int32 whenever every position fits
@@ -221,7 +226,6 @@ void build_device(Model& M) {
     up_map(M.grad_map, D.grad_map);
     up_map(M.jt_map, D.jt_map);
     up_map(M.h_map, D.h_map);
-    up_map(M.aug_map, D.aug_map);
     up_map(M.par_map, D.par_map);
     // the caller's float columns are not kept past create
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
@@ -230,7 +234,18 @@ void build_device(Model& M) {
 void set_schedule(Model& M, int mode, int block, int epl, bool fused) {
     DeviceState& D = *M.dev;
     DeviceState::Sched& S = D.sched[mode];
-    auto tiles = make_tiles(M, mode, 0, (int64_t)block * epl, fused);
+    const int64_t tp = (int64_t)block * epl;
+    auto tiles = make_tiles(M, mode, 0, tp, fused);
+    if (mode == M_GRAD && M.grad_direct)
+        for (auto& z : M.grad_zero)
+            for (int64_t s = 0; s < z.second; s += tp) {
+                ExaTile t{};
+                t.pat = EXA_ZERO_TILE;
+                t.start = z.first + s;
+                t.count = std::min(tp, z.second - s);
+                t.slot = (int64_t)tiles.size();
+                tiles.push_back(t);
+            }
     D.release(S.tiles);
     S.tiles = (ExaTile*)D.upload(tiles.data(), tiles.size() * sizeof(ExaTile));
     S.ntiles = (int64_t)tiles.size();
@@ -340,6 +355,31 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
         for (int r : L.vseeds) mark(G.vrefs[r], vs);
         for (int r : L.prefs) mark(G.prefs[r], ts);
     }
+    // augmentation terms pulled by their base rows (cons, jprod)
+    for (int mode : modes) {
+        if (mode != M_CONS && mode != M_JPROD) continue;
+        for (size_t a = 0; a < M.pats.size(); ++a) {
+            const Pattern& P = M.pats[a];
+            auto it = M.live.find({mode, 1000 + (int)a});
+            if (P.kind != EXA_AUG || P.ndata == 0 || it == M.live.end()) continue;
+            const UnitLive& L = it->second;
+            rd += P.ndata * (4 * (int64_t)L.icols.size() + 8 * (int64_t)L.fcols.size());
+            rd += 4 * (int64_t)(P.rptr.size() + P.ridx.size());
+            for (int s : L.vrefs) {
+                const RefKey& r = P.vslots[s];
+                for (int64_t k = 0; k < P.ndata; ++k) xs[r.col < 0 ? r.off : (int64_t)P.icols[r.col][k] + r.off] = 1;
+            }
+            for (int s : L.vseeds) {
+                const RefKey& r = P.vslots[s];
+                for (int64_t k = 0; k < P.ndata; ++k) vs[r.col < 0 ? r.off : (int64_t)P.icols[r.col][k] + r.off] = 1;
+            }
+            for (int s : L.prefs) {
+                const RefKey& r = P.pslots[s];
+                for (int64_t k = 0; k < P.ndata; ++k) ts[r.col < 0 ? r.off : (int64_t)P.icols[r.col][k] + r.off] = 1;
+            }
+        }
+    }
+    if (modes.size() == 1 && modes[0] == M_GRAD && M.grad_direct) wr = 8 * M.nvar;
     for (char c : xs) rd += c ? 8 : 0;
     for (char c : vs) rd += c ? 8 : 0;
     for (char c : ts) rd += c ? 8 : 0;
@@ -524,9 +564,15 @@ exa_status exa_grad(exa_model* m, const double* x, double* g, exa_stream_t strea
         hipStream_t s = (hipStream_t)stream;
         ExaCall c = blank_call();
         c.x = x;
-        c.out0 = M.dev->fo;
-        launch_mode(M, M_GRAD, c, s);
-        segsum(M.dev->grad_map, M.dev->fo, g, 0, s);
+        if (M.grad_direct) {
+            c.out0 = g;
+            c.direct = 1;
+            launch_mode(M, M_GRAD, c, s);
+        } else {
+            c.out0 = M.dev->fo;
+            launch_mode(M, M_GRAD, c, s);
+            segsum(M.dev->grad_map, M.dev->fo, g, 0, s);
+        }
         M.counters[1]++;
     });
 }
@@ -540,9 +586,7 @@ exa_status exa_cons(exa_model* m, const double* x, double* cv, exa_stream_t stre
         ExaCall c = blank_call();
         c.x = x;
         c.out0 = cv;
-        c.out1 = M.dev->aug;
         launch_mode(M, M_CONS, c, s);
-        if (M.naug) segsum(M.dev->aug_map, M.dev->aug, cv, 1, s);
         M.counters[2]++;
     });
 }
@@ -608,9 +652,7 @@ exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv,
         c.x = x;
         c.v = v;
         c.out0 = Jv;
-        c.out1 = M.dev->aug;
         launch_mode(M, M_JPROD, c, s);
-        if (M.naug) segsum(M.dev->aug_map, M.dev->aug, Jv, 1, s);
         M.counters[5]++;
     });
 }
@@ -646,9 +688,9 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
         c.y = y;
         c.v = v;
         c.sigma = obj_weight;
-        c.out0 = M.dev->fo;
+        c.out0 = M.dev->hv;
         launch_mode(M, M_HPROD, c, s);
-        segsum(M.dev->h_map, M.dev->fo, Hv, 0, s);
+        segsum(M.dev->h_map, M.dev->hv, Hv, 0, s);
         M.counters[7]++;
     });
 }

@@ -41,10 +41,10 @@ struct DeviceState {
         int64_t ntiles = 0;
     } sched[M_COUNT];
     double* fo = nullptr;             // first-order buffer: grad part, then jac part
-    double* aug = nullptr;
     double* par = nullptr;
+    double* hv = nullptr;             // H v contributions (curved slots only)
     double* tilesum = nullptr;
-    DevMap grad_map, jt_map, h_map, aug_map, par_map;
+    DevMap grad_map, jt_map, h_map, par_map;
 
     void* alloc(size_t bytes);
     void* upload(const void* src, size_t bytes);
