@@ -252,6 +252,8 @@ std::vector<Unit> units_for(const Model& M, int mode, bool fused);
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr);
 
 // exa_runtime.cpp
+// The objective always runs this schedule, so its summation order is fixed.
+constexpr int kObjBlock = 256, kObjEpl = 4;
 void build_device(Model& M);
 
 }  // namespace exa

@@ -200,7 +200,7 @@ void build_device(Model& M) {
         // the objective keeps one fixed schedule, so that its reduction order
         // (and hence its value) never depends on tuning
         const bool fixed = mode == M_OBJ;
-        set_schedule(M, mode, fixed ? 256 : M.block, fixed ? 4 : M.epl, fixed ? false : M.fuse);
+        set_schedule(M, mode, fixed ? kObjBlock : M.block, fixed ? kObjEpl : M.epl, fixed ? false : M.fuse);
         D.sched[mode].tuned = fixed || !M.autotune;
     }
     D.fo = (double*)D.alloc((M.nnzg + M.nnzj) * sizeof(double));
@@ -342,7 +342,8 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
         const Group& G = M.groups[u.group];
         const Pattern& P0 = M.pats[G.members[0]];
         rd += u.ndata * (4 * (int64_t)L.icols.size() + 8 * (int64_t)L.fcols.size() + 8 * (int64_t)L.weights);
-        wr += u.ndata * 8 * L.outputs;
+        // the objective writes one partial sum per tile, not per data point
+        if (mode != M_OBJ) wr += u.ndata * 8 * L.outputs;
         auto mark = [&](const RefKey& r, std::vector<char>& seen) {
             if (r.col < 0) {
                 if (r.off >= 0 && r.off < (int64_t)seen.size()) seen[r.off] = 1;
@@ -379,6 +380,8 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
             }
         }
     }
+    for (int mode : modes)
+        if (mode == M_OBJ) wr += 8 * (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, false).size();
     if (modes.size() == 1 && modes[0] == M_GRAD && M.grad_direct) wr = 8 * M.nvar;
     for (char c : xs) rd += c ? 8 : 0;
     for (char c : vs) rd += c ? 8 : 0;
