@@ -63,7 +63,7 @@ class ExaBatch:
         py = self._p(y, self.total("y"), "y") if hess is not None else None
         check(LIB.exa_batch_eval(self._h, mask, px, py, float(obj_weight),
                                  self._p(jac, self.total("jac"), "jac"),
-                                 self._p(hess, self.total("hess"), "hess"), _stream()))
+                                 self._p(hess, self.total("hess"), "hess"), _stream(x.get_device())))
 
     def kernel_bytes(self, jac: bool = True, hess: bool = True):
         mask = (CB_JAC if jac else 0) | (CB_HESS if hess else 0)

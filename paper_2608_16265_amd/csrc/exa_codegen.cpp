@@ -681,6 +681,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     os << "    (void)X; (void)V; (void)Y; (void)TH; (void)P0;\n";
     os << "    const int nthr = (int)blockDim.x;\n";
     os << "    const long long kend = T.start + T.count;\n";
+    // objective: each lane sums its points in order, then one workgroup sum
     if (mode == M_OBJ) os << "    double acc = 0.0;\n";
     os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
     os << "        const long long k = kb + threadIdx.x;\n";
@@ -766,18 +767,44 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     }
     const std::set<std::string> names = e.emit(os, "            ");
     if (mode == M_CONS || mode == M_JPROD) {
-        // base rows pull the augmentation terms that add to them, in
-        // declaration order of the augmentations, points ascending
+        // Base rows pull the augmentation terms that add to them, in
+        // declaration order of the augmentations, points ascending.  The
+        // first round of up to R terms of every augmentation is evaluated
+        // before any is added, so that their chains of dependent loads (row
+        // bounds, term index, data, x) overlap; the additions keep the order.
+        struct Pull {
+            std::string out;
+            int a, R;
+        };
+        std::vector<Pull> pulls;
         for (const Job& j : jobs) {
             const Pattern& P = M.pats[j.p];
             if (P.kind != EXA_CON) continue;
             for (int a : P.augs) {
                 if (M.pats[a].ndata == 0) continue;
-                const std::string pa = "I.pat[" + std::to_string(a) + "]";
-                os << "            for (int j = " << pa << ".rptr[k]; j < " << pa << ".rptr[k + 1]; ++j) "
-                   << oname(j) << " += aug_" << mode_name(mode) << "_" << a << "(C, I, (long long)" << pa
-                   << ".ridx[j]);\n";
+                const size_t nn = M.pats[a].nodes.size();
+                pulls.push_back({oname(j), a, nn <= 16 ? 4 : nn <= 64 ? 2 : 1});
             }
+        }
+        const std::string fn = std::string("aug_") + mode_name(mode) + "_";
+        for (const Pull& q : pulls) {
+            const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+            os << "            const int ab" << a << " = " << pa << ".rptr[k], ae" << a << " = " << pa
+               << ".rptr[k + 1];\n";
+        }
+        for (const Pull& q : pulls) {
+            const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+            for (int i = 0; i < q.R; ++i)
+                os << "            const double aq" << a << "_" << i << " = " << fn << a << "(C, I, (long long)" << pa
+                   << ".ridx[exa_term(ab" << a << " + " << i << ", ae" << a << ")]);\n";
+        }
+        for (const Pull& q : pulls) {
+            const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+            for (int i = 0; i < q.R; ++i)
+                os << "            if (ab" << a << " + " << i << " < ae" << a << ") " << q.out << " += aq" << a << "_" << i
+                   << ";\n";
+            os << "            for (int j = ab" << a << " + " << q.R << "; j < ae" << a << "; ++j) " << q.out
+               << " += " << fn << a << "(C, I, (long long)" << pa << ".ridx[j]);\n";
         }
     }
     os << "        }\n";
@@ -800,7 +827,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         case M_OBJ: {
             std::string sum;
             for (const Job& j : jobs) sum += (sum.empty() ? "" : " + ") + oname(j);
-            os << "        acc += exa_block_sum(" << sum << ", lds);\n";
+            os << "        acc += " << sum << ";\n";
             break;
         }
         case M_CONS:
@@ -830,7 +857,10 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
             }
     }
     os << "    }\n";
-    if (mode == M_OBJ) os << "    if (threadIdx.x == 0) C.out0[I.off[" << EXA_OFF_TILE << "] + T.slot] = acc;\n";
+    if (mode == M_OBJ) {
+        os << "    const double tot = exa_block_sum(acc, lds);\n";
+        os << "    if (threadIdx.x == 0) C.out0[I.off[" << EXA_OFF_TILE << "] + T.slot] = tot;\n";
+    }
     os << "}\n";
     return os.str();
 }
@@ -944,18 +974,24 @@ __device__ __forceinline__ void exa_store_direct(double* __restrict__ dst, const
         for (int s = 0; s < ST; ++s) dst[threadIdx.x * ST + s] = o[s];
     }
 }
-// Sum over the workgroup in a fixed order (tree in LDS); result in lane 0.
+// Sum over the workgroup in a fixed order: a shuffle tree inside each
+// 64-lane wave, then the wave sums in wave order.  Result valid in lane 0.
 __device__ __forceinline__ double exa_block_sum(double v, double* lds) {
-    lds[threadIdx.x] = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += lds[w];
+    __syncthreads();  // lds is free again for the next call
     return r;
 }
+// Index of the i-th augmentation term of a row whose terms are
+// ridx[jb, je), clamped into [0, je) so that every lane loads a valid term
+// even when its row has fewer (the surplus values are not added).  Valid
+// when the pattern has at least one data point.
+__device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je > 0 ? je - 1 : 0); }
 )";
     os << pre;
     int ntmp = 0;

@@ -253,7 +253,8 @@ std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLi
 
 // exa_runtime.cpp
 // The objective always runs this schedule, so its summation order is fixed.
-constexpr int kObjBlock = 256, kObjEpl = 4;
+constexpr int kObjBlock = 256, kObjEpl = 8;
+constexpr bool kObjFused = true;
 void build_device(Model& M);
 
 }  // namespace exa

@@ -481,6 +481,8 @@ std::string pattern_signature(const Model& M) {
     os.precision(17);
     for (auto& P : M.pats) {
         os << "P" << P.kind << ":" << P.n_icols << "," << P.n_fcols << ":" << P.row_icol << ";";
+        // the generated code skips augmentations without data points
+        if (P.kind == EXA_AUG) os << (P.ndata > 0 ? "D;" : "E;");
         // reference offsets are per-instance data (ExaPatDev::roff): left out;
         // which references coincide inside a data-set group is kept
         for (auto& n : P.nodes)

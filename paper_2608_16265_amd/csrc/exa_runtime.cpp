@@ -200,7 +200,7 @@ void build_device(Model& M) {
         // the objective keeps one fixed schedule, so that its reduction order
         // (and hence its value) never depends on tuning
         const bool fixed = mode == M_OBJ;
-        set_schedule(M, mode, fixed ? kObjBlock : M.block, fixed ? kObjEpl : M.epl, fixed ? false : M.fuse);
+        set_schedule(M, mode, fixed ? kObjBlock : M.block, fixed ? kObjEpl : M.epl, fixed ? kObjFused : M.fuse);
         D.sched[mode].tuned = fixed || !M.autotune;
     }
     D.fo = (double*)D.alloc((M.nnzg + M.nnzj) * sizeof(double));
@@ -381,7 +381,7 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
         }
     }
     for (int mode : modes)
-        if (mode == M_OBJ) wr += 8 * (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, false).size();
+        if (mode == M_OBJ) wr += 8 * (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused).size();
     if (modes.size() == 1 && modes[0] == M_GRAD && M.grad_direct) wr = 8 * M.nvar;
     for (char c : xs) rd += c ? 8 : 0;
     for (char c : vs) rd += c ? 8 : 0;
@@ -549,11 +549,13 @@ exa_status exa_obj(exa_model* m, const double* x, double* f, exa_stream_t stream
         if (D.sched[M_OBJ].ntiles == 0) {
             hip_check(exa_launch_fill(f, 1, 0.0, s), "fill");
         } else {
+            // one tile: its workgroup sum is the objective, written in place
+            const bool one = D.sched[M_OBJ].ntiles == 1;
             ExaCall c = blank_call();
             c.x = x;
-            c.out0 = D.tilesum;
+            c.out0 = one ? f : D.tilesum;
             launch_mode(M, M_OBJ, c, s);
-            hip_check(exa_launch_sum(D.tilesum, D.sched[M_OBJ].ntiles, f, s), "objective reduction");
+            if (!one) hip_check(exa_launch_sum(D.tilesum, D.sched[M_OBJ].ntiles, f, s), "objective reduction");
         }
         M.counters[0]++;
     });
@@ -734,7 +736,7 @@ exa_status exa_kernel_bytes(const exa_model* m, int32_t callback, int64_t* read_
         const int mode = mode_of_callback(callback);
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        const bool fused = M.dev ? M.dev->sched[mode].fused : false;
+        const bool fused = mode == M_OBJ ? kObjFused : M.dev ? M.dev->sched[mode].fused : false;
         int64_t rd = 0, wr = 0;
         kernel_bytes(M, {mode}, fused, rd, wr);
         if (read_bytes) *read_bytes = rd;

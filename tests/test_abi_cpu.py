@@ -173,11 +173,12 @@ def test_kernel_bytes_accounting():
     assert wr == 8 * em.nnzj
     # the Jacobian of the stencil row needs only u_c (exp), the index column
     assert rd == ni * 4 + 8 * ni
-    # the objective writes one partial per tile (two patterns of 81 points,
-    # one tile each); it reads c and u_target, c again, and every u and f
+    # the objective writes one partial per tile (both patterns share the 81
+    # grid points: one fused tile); it reads c and u_target once per point,
+    # and every u and f
     rd, wr = em.kernel_bytes("obj")
-    assert wr == 8 * 2
-    assert rd == n * n * (4 + 8) + n * n * 4 + 8 * 2 * n * n
+    assert wr == 8
+    assert rd == n * n * (4 + 8) + 8 * 2 * n * n
     w = acopf(30, 0)
     em = ExaModel(w.model, host_only=True)
     rd, wr = em.kernel_bytes("hess")

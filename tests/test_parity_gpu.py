@@ -184,3 +184,22 @@ def test_bad_tensor_arguments_raise():
         em.grad(torch.zeros(5, dtype=torch.float64))
     with pytest.raises(ValueError):
         em.grad(torch.zeros(5, dtype=torch.float32, device="cuda:0"))
+
+
+def test_callbacks_run_on_the_current_stream():
+    """The binding enqueues on torch's current stream of the tensors' device."""
+    _need_gpu()
+    from paper_2608_16265_amd import ExaModel
+    from paper_2608_16265_amd.model import _stream
+    w = acopf(30, 0)
+    em = ExaModel(w.model)
+    X, Y = dev(w.x), dev(w.y)
+    ref = host(em.hess_coord(X, Y, 1.0))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        assert _stream(X.get_device()).value == s.cuda_stream
+        out = em.hess_coord(X, Y, 1.0)
+    s.synchronize()
+    assert np.array_equal(host(out), ref)
+    assert _stream(X.get_device()).value == torch.cuda.current_stream().cuda_stream
