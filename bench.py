@@ -2,19 +2,24 @@
 
 Workload (default): the ACOPF-shaped synthetic model with 10,000 buses,
 13,500 branches and 2,000 generators (seed 1), one instance on one GPU.
-One step = one pass of every per-iterate callback a solver makes: obj,
-grad, cons, jac_coord, hess_coord, jprod, jtprod and hprod, on inputs
-already resident in device memory.  value = (nnzj + nnzh) / step time.
+One step = every per-iterate callback a solver makes (obj, grad, cons,
+jac_coord, hess_coord, jprod, jtprod, hprod) at one iterate, on inputs
+already resident in device memory, through one exa_eval call: one
+evaluation launch and one reduction launch, outputs bit-identical to the
+separate callbacks.  value = (nnzj + nnzh) / step time.
 
 Also reported on the same JSON line:
+* step_separate_us -- the same step as seven separate callback calls;
 * callbacks_us  -- each callback alone, timed with the paper's protocol
   (Sec. 8.2: back-to-back calls, one synchronization, best of 3);
-* roofline      -- the Hessian kernel (the largest kernel of the step):
-  algorithmic bytes per launch / its average duration measured with HIP
-  events on the launch stream, against the 8 TB/s HBM peak;
+* roofline      -- the step's evaluation kernel (exa_k_multi): algorithmic
+  bytes per launch / its average duration, measured by HIP events that the
+  library records on the launch stream around each launch, against the
+  8 TB/s HBM peak; the reduction launch and the combined Jacobian+Hessian
+  kernel are reported beside it;
 * cpu_baseline  -- the CPU oracle (numpy, float64) on a bounded sample;
 * pde           -- the PDE-control model on a 1000 x 1000 grid
-  (HBM-bound), jac + hess nnz/s and its Hessian roofline;
+  (HBM-bound): the same step and rooflines;
 * batched       -- 256 uneven ACOPF instances (500 to 20,000 buses) in one
   persistent graph-replayed launch vs 256 sequential plain calls;
 * adjoint       -- 64 instances of the 10,000-bus model: grad_x L(theta)
@@ -133,7 +138,31 @@ def profiled_traffic(summary, model):
 
 
 # ------------------------------------------------------------------- legs
-def leg_single(name, wl, steps, warmup, full_step=True):
+ALL_CBS = ("obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod")
+
+
+def eval_launch_us(em, run, n=500):
+    """Average durations (us) of exa_eval's evaluation and reduction launches:
+    the library records HIP events on the launch stream around each of its
+    launches over n back-to-back calls (the queue is first filled with a long
+    matrix product so that the calls run back to back)."""
+    import torch
+    if QUICK:
+        n = min(n, 20)
+    a = torch.ones(4096, 4096, dtype=torch.float64, device="cuda:0")
+    run()
+    torch.cuda.synchronize()
+    em.eval_timing(True)
+    for _ in range(24):
+        a = a @ a * 1e-4
+    for _ in range(n):
+        run()
+    t = em.eval_timing_read()
+    em.eval_timing(False)
+    return t
+
+
+def leg_single(name, wl, steps, warmup):
     import torch
     from paper_2608_16265_amd import ExaModel
     t0 = time.perf_counter()
@@ -145,14 +174,9 @@ def leg_single(name, wl, steps, warmup, full_step=True):
     rng = np.random.default_rng(0)
     V = torch.as_tensor(rng.standard_normal(em.nvar), device=dev)
     W = torch.as_tensor(rng.standard_normal(em.ncon), device=dev)
-    f = torch.empty(1, dtype=torch.float64, device=dev)
-    g = torch.empty(em.nvar, dtype=torch.float64, device=dev)
-    c = torch.empty(em.ncon, dtype=torch.float64, device=dev)
-    jv = torch.empty(em.nnzj, dtype=torch.float64, device=dev)
-    hv = torch.empty(em.nnzh, dtype=torch.float64, device=dev)
-    Jv = torch.empty(em.ncon, dtype=torch.float64, device=dev)
-    Jtw = torch.empty(em.nvar, dtype=torch.float64, device=dev)
-    Hv = torch.empty(em.nvar, dtype=torch.float64, device=dev)
+    e = lambda n: torch.empty(n, dtype=torch.float64, device=dev)  # noqa: E731
+    f, g, c, jv, hv = e(1), e(em.nvar), e(em.ncon), e(em.nnzj), e(em.nnzh)
+    Jv, Jtw, Hv = e(em.ncon), e(em.nvar), e(em.nvar)
     cbs = {
         "obj": lambda: em.obj(X, f),
         "grad": lambda: em.grad(X, g),
@@ -164,18 +188,20 @@ def leg_single(name, wl, steps, warmup, full_step=True):
         "jtprod": lambda: em.jtprod(X, W, Jtw),
         "hprod": lambda: em.hprod(X, Y, 1.0, V, Hv),
     }
-    # a solver iterate: every callback once; Jacobian and Hessian values come
-    # from the combined call (bit-identical to jac_coord + hess_coord)
-    order = (["obj", "grad", "cons", "jac_hess_coord", "jprod", "jtprod", "hprod"] if full_step
-             else ["jac_hess_coord"])
-    for k in ("jac_coord", "hess_coord"):  # tune the separate callbacks too
-        cbs[k]()
+    # one step: every callback at one iterate through a single exa_eval call
+    # (one evaluation launch + one reduction launch), outputs bit-identical
+    # to the separate callbacks
+    step = em.bind(X, Y, 1.0, V, W, f=f, g=g, c=c, jac=jv, hess=hv, jv=Jv, jtw=Jtw, hv=Hv)
+    cbs["eval_all"] = step
+    order = ["obj", "grad", "cons", "jac_hess_coord", "jprod", "jtprod", "hprod"]
 
-    def step():
+    def step_separate():
         for k in order:
             cbs[k]()
 
-    for _ in range(max(1, warmup)):  # the first call of each callback tunes it
+    for fn in cbs.values():  # the first call of each tunes its schedule
+        fn()
+    for _ in range(max(1, warmup)):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -183,26 +209,31 @@ def leg_single(name, wl, steps, warmup, full_step=True):
         step()
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / steps
+    sep_s = best_of_3(step_separate)
     per_cb = {k: best_of_3(fn) * 1e6 for k, fn in cbs.items()}
+    tm = eval_launch_us(em, step)
+    eb = em.eval_bytes(ALL_CBS)
     k_mean, k_n = kernel_ms(cbs["jac_hess_coord"])
-    kh_mean, _ = kernel_ms(cbs["hess_coord"])
-    kj_mean, _ = kernel_ms(cbs["jac_coord"])
     rd, wr = em.kernel_bytes("jac_hess")
-    nbytes = rd + wr
-    hrd, hwr = em.kernel_bytes("hess")
     sched = {k: em.schedule(k) for k in ("jac", "hess", "jac_hess")}
+    sched["eval_all"] = em.eval_schedule(ALL_CBS)
     nnz = em.nnzj + em.nnzh
+    ev_bytes = eb["eval_read"] + eb["eval_write"]
+    red_bytes = eb["reduce_read"] + eb["reduce_write"]
     res = dict(
         name=name, nvar=em.nvar, ncon=em.ncon, nnzj=em.nnzj, nnzh=em.nnzh,
         build_s=round(build_s, 3), step_s=step_s, nnz_per_s=nnz / step_s,
+        step_separate_us=round(sep_s * 1e6, 2),
         jac_hess_nnz_per_s=nnz / (per_cb["jac_hess_coord"] * 1e-6),
         jac_plus_hess_nnz_per_s=nnz / ((per_cb["jac_coord"] + per_cb["hess_coord"]) * 1e-6),
         callbacks_us={k: round(v, 2) for k, v in per_cb.items()},
+        eval_us=round(tm["eval_us"], 3), eval_calls_timed=tm["calls"], reduce_us=round(tm["reduce_us"], 3),
+        eval_bytes=ev_bytes, eval_read_bytes=eb["eval_read"], eval_write_bytes=eb["eval_write"],
+        reduce_bytes=red_bytes,
+        eval_gbs=ev_bytes / (tm["eval_us"] * 1e-6) / 1e9,
+        reduce_gbs=red_bytes / (tm["reduce_us"] * 1e-6) / 1e9 if tm["reduce_us"] > 0 else None,
         jh_kernel_us=round(k_mean * 1e3, 3), kernel_launches_timed=k_n,
-        hess_kernel_us=round(kh_mean * 1e3, 3), jac_kernel_us=round(kj_mean * 1e3, 3),
-        jh_bytes=nbytes, jh_read_bytes=rd, jh_write_bytes=wr,
-        jh_gbs=nbytes / (k_mean * 1e-3) / 1e9,
-        hess_bytes=hrd + hwr, hess_gbs=(hrd + hwr) / (kh_mean * 1e-3) / 1e9,
+        jh_bytes=rd + wr, jh_gbs=(rd + wr) / (k_mean * 1e-3) / 1e9,
         schedule=sched,
     )
     em.close()
@@ -377,47 +408,52 @@ def main():
         log(json.dumps(r))
         out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
         out["config"] = {"workload": "acopf-10000-bus (13,500 branches, 2,000 generators, seed 1)",
-                         "step": "obj+grad+cons+jac_hess_coord+jprod+jtprod+hprod",
+                         "step": "exa_eval of obj, grad, cons, jac, hess, jprod, jtprod, hprod at one iterate",
                          "nvar": r["nvar"], "ncon": r["ncon"], "nnzj": r["nnzj"],
                          "nnzh": r["nnzh"], "schedule": r["schedule"]}
+        out["step_separate_us"] = r["step_separate_us"]
         out["callbacks_us"] = r["callbacks_us"]
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
         out["jac_plus_hess_nnz_per_s"] = r["jac_plus_hess_nnz_per_s"]
         from exa_modeling.generators import acopf as _acopf
-        traffic = profiled_traffic("acopf10k_jac_hess.md", _acopf(30, 0).model)
-        out["roofline"] = {"kernel": "exa_k_jh", "bound": "hbm", "achieved": r["jh_gbs"],
+        traffic = profiled_traffic("acopf10k_eval_all.md", _acopf(30, 0).model)
+        out["roofline"] = {"kernel": "exa_k_multi", "bound": "hbm", "achieved": r["eval_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": r["jh_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                           "bytes_per_launch": r["jh_bytes"], "read_bytes": r["jh_read_bytes"],
-                           "write_bytes": r["jh_write_bytes"], "launch_us": r["jh_kernel_us"]}
-        out["roofline_hess_kernel"] = {"kernel": "exa_k_hess", "achieved": r["hess_gbs"],
-                                       "frac": r["hess_gbs"] / HBM_PEAK_GBS,
-                                       "bytes_per_launch": r["hess_bytes"],
-                                       "launch_us": r["hess_kernel_us"]}
+                           "frac": r["eval_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                           "bytes_per_launch": r["eval_bytes"], "read_bytes": r["eval_read_bytes"],
+                           "write_bytes": r["eval_write_bytes"], "launch_us": r["eval_us"],
+                           "launches_timed": r["eval_calls_timed"]}
+        out["roofline_reduce"] = {"kernel": "k_reduce", "achieved": r["reduce_gbs"],
+                                  "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]}
+        out["roofline_jac_hess_coord"] = {"kernel": "exa_k_jh", "achieved": r["jh_gbs"],
+                                          "frac": r["jh_gbs"] / HBM_PEAK_GBS,
+                                          "bytes_per_launch": r["jh_bytes"], "launch_us": r["jh_kernel_us"]}
         if not args.no_cpu_baseline:
             log("leg: cpu baseline")
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     if not args.no_extras and args.only in (None, "pde"):
         log("leg: pde 1000")
         wl = pde(1000, 3)
-        r = leg_single("pde1000", wl, max(20, args.steps // 20), 5, full_step=False)
+        r = leg_single("pde1000", wl, max(20, args.steps // 20), 5)
         log(json.dumps(r))
         out["pde"] = {"workload": "pde-control 1000x1000 grid (2e6 variables, seed 3)",
-                      "nnzj": r["nnzj"], "nnzh": r["nnzh"],
+                      "nnzj": r["nnzj"], "nnzh": r["nnzh"], "step_us": round(r["step_s"] * 1e6, 2),
+                      "nnz_per_s": r["nnz_per_s"], "step_separate_us": r["step_separate_us"],
                       "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"],
                       "callbacks_us": r["callbacks_us"],
+                      "roofline_eval": {"kernel": "exa_k_multi", "achieved": r["eval_gbs"],
+                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": r["eval_gbs"] / HBM_PEAK_GBS,
+                                        "bytes_per_launch": r["eval_bytes"], "launch_us": r["eval_us"]},
+                      "roofline_reduce": {"kernel": "k_reduce", "achieved": r["reduce_gbs"],
+                                          "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]},
                       "roofline_jh": {"kernel": "exa_k_jh", "achieved": r["jh_gbs"],
                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                       "frac": r["jh_gbs"] / HBM_PEAK_GBS,
                                       "bytes_per_launch": r["jh_bytes"],
-                                      "launch_us": r["jh_kernel_us"]},
-                      "roofline_hess": {"kernel": "exa_k_hess", "achieved": r["hess_gbs"],
-                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                        "frac": r["hess_gbs"] / HBM_PEAK_GBS,
-                                        "bytes_per_launch": r["hess_bytes"],
-                                        "launch_us": r["hess_kernel_us"]}}
+                                      "launch_us": r["jh_kernel_us"]}}
         if args.only == "pde":
-            out.update(value=r["jac_hess_nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
+            out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
     if not args.no_extras and args.only in (None, "batch"):
         log("leg: batched 256")
         r = leg_batch()

@@ -220,6 +220,78 @@ exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jt
 exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight,
                      const double* v, double* Hv, exa_stream_t stream);
 
+/* Several callbacks at one point in one call (Sec. 2.1.3 callbacks,
+ * evaluated together).  `mask` selects callbacks with the EXA_EV_* bits;
+ * every selected callback reads the inputs it needs and writes its output
+ * exactly as its own entry point would, bit for bit:
+ *   EXA_EV_OBJ    f    [1]      from x             (as exa_obj)
+ *   EXA_EV_GRAD   g    [nvar]   from x             (as exa_grad)
+ *   EXA_EV_CONS   c    [ncon]   from x             (as exa_cons)
+ *   EXA_EV_JAC    jac  [nnzj]   from x             (as exa_jac_coord)
+ *   EXA_EV_HESS   hess [nnzh]   from x, y, sigma   (as exa_hess_coord)
+ *   EXA_EV_JPROD  jv   [ncon]   from x, v          (as exa_jprod)
+ *   EXA_EV_JTPROD jtw  [nvar]   from x, w          (as exa_jtprod)
+ *   EXA_EV_HPROD  hv   [nvar]   from x, y, sigma, v (as exa_hprod)
+ * All pointers are device arrays owned by the caller; inputs a selection
+ * does not need may be NULL, outputs it selects may not.  Outputs must not
+ * overlap each other or the inputs.  The work is one evaluation launch over
+ * the tiles of every selected callback, followed by at most one launch of
+ * the deterministic reductions (objective partials, gradient, J^T w and H v
+ * segment sums).  The first call with a given mask times candidate
+ * schedules (as with autotune) and synchronizes the stream; later calls are
+ * asynchronous on `stream`.
+ * Errors: EXA_EINVAL for a NULL model or args, an empty or unknown mask, or
+ * a NULL pointer the mask needs; EXA_ESTATE for a host-only model. */
+#define EXA_EV_OBJ (1u << 0)
+#define EXA_EV_GRAD (1u << 1)
+#define EXA_EV_CONS (1u << 2)
+#define EXA_EV_JAC (1u << 3)
+#define EXA_EV_HESS (1u << 4)
+#define EXA_EV_JPROD (1u << 5)
+#define EXA_EV_JTPROD (1u << 6)
+#define EXA_EV_HPROD (1u << 7)
+#define EXA_EV_ALL 0xffu
+typedef struct exa_eval_args {
+    uint32_t mask;
+    uint32_t reserved; /* 0 */
+    const double* x;
+    const double* y;
+    double obj_weight;
+    const double* v;
+    const double* w;
+    double* f;
+    double* g;
+    double* c;
+    double* jac;
+    double* hess;
+    double* jv;
+    double* jtw;
+    double* hv;
+} exa_eval_args;
+exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream);
+/* The schedule of exa_eval for a mask: out4 = workgroup size, points per
+ * lane, fused (0/1), number of tiles.  EXA_ESTATE until the mask's first
+ * exa_eval call. */
+exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
+/* Algorithmic traffic of exa_eval for a mask under its current schedule
+ * (the model's default before the mask's first call), host array out4:
+ * out4[0], out4[1] = bytes read and written by the evaluation launch,
+ * counted as exa_kernel_bytes counts one callback (x, v entries once over
+ * the launch); out4[2], out4[3] = bytes read and written by the reduction
+ * launch (segment maps, each buffer entry once, each output once, and the
+ * objective partials when there are several).  Works on host-only models. */
+exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4);
+/* Launch timing of exa_eval, for measurement.  With enable != 0, the next
+ * 1024 exa_eval calls of this model record HIP events on their stream
+ * around the evaluation launch and around the reduction launch (later calls
+ * are not recorded); enable == 0 frees the events.
+ * exa_eval_timing_read waits for the recorded calls and stores into the host
+ * array out4 {calls recorded, average evaluation launch in microseconds,
+ * reduction launches recorded, their average in microseconds}, then starts a
+ * new recording.  EXA_ESTATE when timing is off. */
+exa_status exa_eval_timing(exa_model* m, int32_t enable);
+exa_status exa_eval_timing_read(exa_model* m, double* out4);
+
 /* Adjoint with respect to the parameters (extension of the parametric NLP of
  * eq. nlp): theta_bar = (d grad_x L / d theta)^T w with
  * grad_x L = sigma grad f + J^T y, i.e. for every pattern instance

@@ -48,6 +48,19 @@ class BatchOptions(C.Structure):
                 ("xcd_aware", C.c_int32), ("separate", C.c_int32)]
 
 
+# exa_eval selection bits, by callback name
+EV = {"obj": 1 << 0, "grad": 1 << 1, "cons": 1 << 2, "jac": 1 << 3, "hess": 1 << 4,
+      "jprod": 1 << 5, "jtprod": 1 << 6, "hprod": 1 << 7}
+
+
+class EvalArgs(C.Structure):
+    _fields_ = [("mask", C.c_uint32), ("reserved", C.c_uint32),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("obj_weight", C.c_double),
+                ("v", C.c_void_p), ("w", C.c_void_p),
+                ("f", C.c_void_p), ("g", C.c_void_p), ("c", C.c_void_p), ("jac", C.c_void_p),
+                ("hess", C.c_void_p), ("jv", C.c_void_p), ("jtw", C.c_void_p), ("hv", C.c_void_p)]
+
+
 CALLBACKS = ["obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod", "adjoint", "jac_hess"]
 
 
@@ -83,6 +96,11 @@ def _load():
         "exa_jtprod": (C.c_int32, [vp, vp, vp, vp, vp]),
         "exa_hprod": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_adjoint_theta": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
+        "exa_eval": (C.c_int32, [vp, C.POINTER(EvalArgs), vp]),
+        "exa_eval_schedule": (C.c_int32, [vp, C.c_uint32, P_i64]),
+        "exa_eval_bytes": (C.c_int32, [vp, C.c_uint32, P_i64]),
+        "exa_eval_timing": (C.c_int32, [vp, C.c_int32]),
+        "exa_eval_timing_read": (C.c_int32, [vp, P_f64]),
         "exa_counters": (C.c_int32, [vp, P_i64]),
         "exa_generated_source": (C.c_int32, [vp, C.c_char_p, C.c_int64, P_i64]),
         "exa_compile_check": (C.c_int32, [vp]),
@@ -117,6 +135,7 @@ def exported_symbols():
     return ["exa_last_error", "exa_version", "exa_create", "exa_destroy", "exa_dims", "exa_bounds",
             "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
             "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jac_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
-            "exa_adjoint_theta", "exa_counters", "exa_generated_source", "exa_compile_check",
+            "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_bytes", "exa_eval_timing",
+            "exa_eval_timing_read", "exa_counters", "exa_generated_source", "exa_compile_check",
             "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",
             "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule", "exa_batch_bytes"]

@@ -57,6 +57,7 @@ struct Stmt {
     std::string type, name, expr;
     std::vector<int> deps;
     bool out = false;
+    bool raw = false;  // a line emitted verbatim, in recorded order
 };
 
 struct Em {
@@ -100,6 +101,10 @@ struct Em {
         Stmt s{"", lhs, e, deps_of(e), true};
         st.push_back(s);
     }
+    void raw(const std::string& line) {
+        Stmt s{"", "", line, deps_of(line), true, true};
+        st.push_back(s);
+    }
     std::string mul(const std::string& a, const std::string& b) {
         if (a == Z || b == Z) return Z;
         if (a == ONE) return b;
@@ -136,7 +141,9 @@ struct Em {
         for (size_t i = 0; i < st.size(); ++i) {
             if (!live[i]) continue;
             const Stmt& s = st[i];
-            if (s.out) {
+            if (s.raw) {
+                os << ind << s.expr << "\n";
+            } else if (s.out) {
                 os << ind << s.name << " = " << s.expr << ";\n";
             } else {
                 os << ind << "const " << s.type << " " << s.name << " = " << s.expr << ";\n";
@@ -670,6 +677,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     const int m0 = G.members[0];  // owner of the shared column pointers
     std::ostringstream os;
     const std::string fn = std::string("unit_") + mode_name(mode) + "_" + std::to_string(U.code);
+    const bool inline_stores = !scalar_mode(mode);  // modes with staged per-point outputs
     os << "__device__ __forceinline__ void " << fn
        << "(const ExaCall& C, const ExaInstDev& I, const ExaTile& T, double* lds) {\n";
     os << "    const ExaPatDev& P0 = I.pat[" << m0 << "];\n";
@@ -681,11 +689,26 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     os << "    (void)X; (void)V; (void)Y; (void)TH; (void)P0;\n";
     os << "    const int nthr = (int)blockDim.x;\n";
     os << "    const long long kend = T.start + T.count;\n";
-    // objective: each lane sums its points in order, then one workgroup sum
-    if (mode == M_OBJ) os << "    double acc = 0.0;\n";
-    os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
-    os << "        const long long k = kb + threadIdx.x;\n";
-    os << "        const int npts = (int)((kend - kb) < nthr ? (kend - kb) : nthr);\n";
+    if (mode == M_OBJ) {
+        // virtual lanes (see exa_vlane_sum): one pass per lane this thread holds
+        os << "    double acc[EXA_VLANES / 64] = {};\n";
+        os << "    for (long long kb = T.start; kb < kend; kb += EXA_VLANES) {\n";
+        os << "#pragma unroll\n";
+        os << "    for (int q = 0; q < EXA_VLANES / 64; ++q) {\n";
+        os << "        if (q * nthr >= EXA_VLANES) break;\n";
+        os << "        const long long k = kb + threadIdx.x + q * nthr;\n";
+    } else {
+        os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
+        os << "        const long long kr = kb + threadIdx.x;\n";
+        os << "        const int npts = (int)((kend - kb) < nthr ? (kend - kb) : nthr);\n";
+        if (inline_stores)
+            // every lane runs the statements, so that each job's staged store
+            // (workgroup barriers) can follow its sweep: lanes past the end
+            // recompute the last point and store nothing
+            os << "        const long long k = kr < kend ? kr : kend - 1;\n";
+        else
+            os << "        const long long k = kr;\n";
+    }
     const std::vector<Job> jobs = jobs_of(M, mode, U);
     auto oname = [&](const Job& j) {
         return (scalar_mode(j.mode) ? "r" : "o") + std::to_string(j.p) + (mode == M_JH ? std::string("_") + mode_name(j.mode) : "");
@@ -696,7 +719,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         else
             os << "        double " << oname(j) << "[" << out_step(M.pats[j.p], j.mode) << "] = {};\n";
     }
-    os << "        if (k < kend) {\n";
+    os << (inline_stores ? "        {\n" : "        if (k < kend) {\n");
 
     // ---- statements: loads (all candidates), then every member's sweeps
     Em e(ntmp);
@@ -762,8 +785,20 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         if (mode == M_GRAD)
             // every variable has at most one contribution: write g directly
             for (int s = 0; s < P.o1step(); ++s)
-                e.out("if (C.direct) C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
+                e.out("if (C.direct && kr < kend) C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
                       oname(j) + "[" + std::to_string(s) + "]");
+        if (inline_stores) {
+            // this job's outputs leave registers as soon as they are complete
+            const std::string pd = "P" + std::to_string(j.p) + "_";
+            const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
+            std::string line = mode == M_GRAD ? "if (!C.direct) " : "";
+            if (staged(P, j.mode))
+                line += "exa_store<" + std::to_string(out_step(P, j.mode)) + ", " + (final_out ? "true" : "false") + ">(";
+            else
+                line += "exa_store_direct<" + std::to_string(out_step(P, j.mode)) + ">(";
+            line += dest(P, j.mode, pd, j.out) + ", " + oname(j) + ", npts, lds);";
+            e.raw(line);
+        }
     }
     const std::set<std::string> names = e.emit(os, "            ");
     if (mode == M_CONS || mode == M_JPROD) {
@@ -786,6 +821,11 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 pulls.push_back({oname(j), a, nn <= 16 ? 4 : nn <= 64 ? 2 : 1});
             }
         }
+        // at most kPullTerms terms in flight per lane, shared by the pulls,
+        // so that the round does not cost occupancy
+        constexpr int kPullTerms = 8;
+        const int share = pulls.empty() ? 1 : std::max(1, kPullTerms / (int)pulls.size());
+        for (Pull& q : pulls) q.R = std::min(q.R, share);
         const std::string fn = std::string("aug_") + mode_name(mode) + "_";
         for (const Pull& q : pulls) {
             const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
@@ -827,7 +867,8 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         case M_OBJ: {
             std::string sum;
             for (const Job& j : jobs) sum += (sum.empty() ? "" : " + ") + oname(j);
-            os << "        acc += " << sum << ";\n";
+            os << "        acc[q] += " << sum << ";\n";
+            os << "    }\n";  // virtual lanes
             break;
         }
         case M_CONS:
@@ -843,22 +884,12 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                        << ";\n";
             }
             break;
-        default:
-            for (const Job& j : jobs) {
-                const Pattern& P = M.pats[j.p];
-                const std::string pd = "P" + std::to_string(j.p) + "_";
-                const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
-                if (mode == M_GRAD) os << "        if (!C.direct)\n    ";
-                if (staged(P, j.mode))
-                    os << "        exa_store<" << out_step(P, j.mode) << ", " << (final_out ? "true" : "false") << ">(";
-                else
-                    os << "        exa_store_direct<" << out_step(P, j.mode) << ">(";
-                os << dest(P, j.mode, pd, j.out) << ", " << oname(j) << ", npts, lds);\n";
-            }
+        default:  // stored after each job's statements
+            break;
     }
     os << "    }\n";
     if (mode == M_OBJ) {
-        os << "    const double tot = exa_block_sum(acc, lds);\n";
+        os << "    const double tot = exa_vlane_sum(acc, lds);\n";
         os << "    if (threadIdx.x == 0) C.out0[I.off[" << EXA_OFF_TILE << "] + T.slot] = tot;\n";
     }
     os << "}\n";
@@ -926,6 +957,11 @@ int mode_lds_doubles(const Model& M, int mode) {
 
 std::string kernel_name(int mode) { return std::string("exa_k_") + mode_name(mode); }
 
+const std::vector<int>& multi_modes() {
+    static const std::vector<int> m = {M_OBJ, M_GRAD, M_CONS, M_JAC, M_HESS, M_JH, M_JPROD, M_JTPROD, M_HPROD};
+    return m;
+}
+
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live) {
     std::ostringstream os;
     os << "// generated: straight-line evaluation kernels for one pattern set\n";
@@ -974,17 +1010,23 @@ __device__ __forceinline__ void exa_store_direct(double* __restrict__ dst, const
         for (int s = 0; s < ST; ++s) dst[threadIdx.x * ST + s] = o[s];
     }
 }
-// Sum over the workgroup in a fixed order: a shuffle tree inside each
-// 64-lane wave, then the wave sums in wave order.  Result valid in lane 0.
-__device__ __forceinline__ double exa_block_sum(double v, double* lds) {
+// Objective tiles are summed over 256 virtual lanes whatever the workgroup
+// width: virtual lane l takes points l, l + 256, ... of the tile in order,
+// thread t holds lanes t, t + blockDim.x, ...; the 256 lane sums then go
+// through a fixed tree in LDS.  The order never depends on the launch.
+#define EXA_VLANES 256
+__device__ __forceinline__ double exa_vlane_sum(const double* acc, double* lds) {
+    const int nthr = (int)blockDim.x;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    for (int q = 0; q < EXA_VLANES / 64; ++q)
+        if (q * nthr < EXA_VLANES) lds[threadIdx.x + q * nthr] = acc[q];
     __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += lds[w];
-    __syncthreads();  // lds is free again for the next call
+    for (int s = EXA_VLANES / 2; s > 0; s >>= 1) {
+        for (int t = threadIdx.x; t < s; t += nthr) lds[t] += lds[t + s];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();  // lds is free again for the next tile
     return r;
 }
 // Index of the i-th augmentation term of a row whose terms are
@@ -1072,6 +1114,39 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
                                 "; break;");
         }
         kernel("exa_k_jhsep", mode_lds_doubles(M, M_JH), cases);
+    }
+    // Several callbacks in one launch: a tile's mode sits above
+    // EXA_MODE_SHIFT in its code, and its case passes that mode's call (a
+    // constant index, so the calls stay in kernel arguments).  One tile per
+    // workgroup, remapped per XCD as in the single-callback kernels.
+    {
+        int lds = 0;
+        std::vector<std::string> cases;
+        for (int mode : multi_modes()) {
+            lds = std::max(lds, mode_lds_doubles(M, mode));
+            std::set<int> codes;
+            for (int fused = 0; fused < 2; ++fused)
+                for (auto& u : units_for(M, mode, fused != 0)) codes.insert(u.code);
+            const std::string K = "C.c[" + std::to_string(mode) + "]";
+            for (int c : codes)
+                cases.push_back("case " + std::to_string((mode << EXA_MODE_SHIFT) | c) + ": unit_" + mode_name(mode) +
+                                "_" + std::to_string(c) + "(" + K + ", " + K + ".inst[T.inst], T, lds); break;");
+        }
+        const std::string G = "C.c[" + std::to_string(M_GRAD) + "]";
+        cases.push_back("case " + std::to_string((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE) +
+                        ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) " + G +
+                        ".out0[" + G + ".inst[T.inst].off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;");
+        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") exa_k_multi(ExaMulti C) {\n";
+        os << "    __shared__ double lds[" << lds << "];\n";
+        os << "    (void)lds;\n";
+        os << "    const long long w = (blockIdx.x % 8) * C.per_xcd + blockIdx.x / 8;\n";
+        os << "    if (w >= C.ntiles) return;\n";
+        os << "    const ExaTile T = C.tiles[w];\n";
+        os << "    switch (T.pat) {\n";
+        for (auto& c : cases) os << "        " << c << "\n";
+        os << "        default: break;\n";
+        os << "    }\n";
+        os << "}\n";
     }
     return os.str();
 }

@@ -91,6 +91,12 @@ void set_last_error(const std::string& msg);
         int persistent;                                                          \
         int direct;                                                              \
         const long long* xcd_range;                                              \
+    };                                                                           \
+    struct ExaMulti {                                                            \
+        const struct ExaTile* tiles;                                             \
+        long long ntiles;                                                        \
+        long long per_xcd;                                                       \
+        struct ExaCall c[10];                                                    \
     };
 
 EXA_DEVICE_STRUCTS
@@ -103,17 +109,21 @@ EXA_DEVICE_STRUCTS
 
 enum Mode : int {
     M_OBJ = 0,    // objective terms -> per-tile partial sums
-    M_CONS = 1,   // constraint values (rows + aug buffer)
-    M_GRAD = 2,   // objective gradient contributions -> first-order buffer
+    M_CONS = 1,   // constraint rows; each pulls its augmentation terms
+    M_GRAD = 2,   // objective gradient: in place, or first-order buffer
     M_JAC = 3,    // Jacobian values
     M_HESS = 4,   // Lagrangian Hessian values
-    M_JPROD = 5,  // J v (rows + aug buffer)
+    M_JPROD = 5,  // J v rows; each pulls its augmentation terms
     M_JTPROD = 6, // w[row] * J -> first-order buffer (jac part)
-    M_HPROD = 7,  // local (w H) v -> first-order buffer
+    M_HPROD = 7,  // local (w H) v on curved slots -> H v buffer
     M_ADJ = 8,    // mixed partials -> parameter buffer
     M_JH = 9,     // Jacobian and Hessian values of each data point in one pass
     M_COUNT = 10
 };
+static_assert(M_COUNT == 10, "ExaMulti holds one call per mode");
+// Tiles of the several-callback kernel carry their mode above this bit of
+// the unit code (unit codes stay below 1 << EXA_MODE_SHIFT).
+#define EXA_MODE_SHIFT 12
 
 struct TNode {            // node of a simplified tree
     int op = 0;
@@ -247,12 +257,16 @@ std::string pattern_signature(const Model& M);
 // exa_codegen.cpp
 #define EXA_BLOCK_MAX 256
 bool pattern_in_mode(const Pattern& P, int mode);
+// Modes the several-callback kernel (exa_k_multi) evaluates.
+const std::vector<int>& multi_modes();
 std::vector<Unit> units_for(const Model& M, int mode, bool fused);
 // Generated source for all callbacks; fills live[(mode, unit code)].
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr);
 
 // exa_runtime.cpp
-// The objective always runs this schedule, so its summation order is fixed.
+// Objective tiles always hold kObjBlock * kObjEpl points (256 virtual lanes
+// of 8 points), so the objective's summation order is fixed; its own launch
+// uses kObjBlock-wide workgroups.
 constexpr int kObjBlock = 256, kObjEpl = 8;
 constexpr bool kObjFused = true;
 void build_device(Model& M);

@@ -10,15 +10,21 @@ namespace {
 
 constexpr int kSegBlock = 256;
 
+// Workgroup b runs on XCD b % 8.  Launches of these kernels have 8 * per_xcd
+// workgroups, and workgroup b takes logical block (b % 8) * per_xcd + b / 8,
+// so each XCD sums a contiguous range of segments and keeps its part of the
+// buffers in its own L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t per_xcd) {
+    return (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+}
+
 // out[s] (+)= sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
 // the sparse-to-dense compression of Sec. 7.2.3, one lane per segment, with
 // a fixed summation order so the result does not depend on scheduling.
 template <class I>
-__global__ void __launch_bounds__(kSegBlock)
-k_segsum(const I* __restrict__ ptr, const I* __restrict__ idx, const double* __restrict__ buf,
-         double* __restrict__ out, int64_t nseg, int accumulate) {
-    const int64_t s = (int64_t)blockIdx.x * kSegBlock + threadIdx.x;
-    if (s >= nseg) return;
+__device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __restrict__ idx,
+                                         const double* __restrict__ buf, double* __restrict__ out, int64_t s,
+                                         int accumulate) {
     const int64_t b = ptr[s], e = ptr[s + 1];
     double acc = accumulate ? out[s] : 0.0;
     int64_t j = b;
@@ -36,10 +42,10 @@ k_segsum(const I* __restrict__ ptr, const I* __restrict__ idx, const double* __r
     out[s] = acc;
 }
 
-// Sum of n partials in a fixed order: strided per-lane sums, then a tree.
-__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, int64_t n,
-                                             double* __restrict__ out) {
-    __shared__ double lds[256];
+// Sum of n partials in a fixed order by one 256-wide workgroup: strided
+// per-lane sums, then a tree.
+__device__ __forceinline__ void sum_body(const double* __restrict__ part, int64_t n, double* __restrict__ out,
+                                         double* lds) {
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
     lds[threadIdx.x] = acc;
@@ -49,6 +55,45 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, in
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = lds[0];
+}
+
+template <class I>
+__global__ void __launch_bounds__(kSegBlock)
+k_segsum(const I* __restrict__ ptr, const I* __restrict__ idx, const double* __restrict__ buf,
+         double* __restrict__ out, int64_t nseg, int accumulate, int64_t per_xcd) {
+    const int64_t s = xcd_block(per_xcd) * kSegBlock + threadIdx.x;
+    if (s < nseg) seg_body(ptr, idx, buf, out, s, accumulate);
+}
+
+__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, int64_t n,
+                                             double* __restrict__ out) {
+    __shared__ double lds[256];
+    sum_body(part, n, out, lds);
+}
+
+// Several reductions in one launch: the segment sums of each job over
+// consecutive block ranges, then (when R.part is set) one block for the
+// objective partials.  Each job sums exactly as k_segsum, the objective as
+// k_sum.
+__global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_xcd) {
+    __shared__ double lds[256];
+    int64_t b = xcd_block(per_xcd);
+    for (int k = 0; k < R.njobs; ++k) {
+        const ExaSegJob& J = R.job[k];
+        const int64_t nb = (J.nseg + kSegBlock - 1) / kSegBlock;
+        if (b < nb) {
+            const int64_t s = b * kSegBlock + threadIdx.x;
+            if (s < J.nseg) {
+                if (J.wide)
+                    seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, 0);
+                else
+                    seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, 0);
+            }
+            return;
+        }
+        b -= nb;
+    }
+    if (R.part && b == 0) sum_body(R.part, R.npart, R.f, lds);
 }
 
 __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, int64_t n, double v) {
@@ -61,18 +106,29 @@ __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, int64_t n,
 hipError_t exa_launch_segsum(const void* ptr, const void* idx, int wide, const double* buf, double* out,
                              int64_t nseg, int accumulate, hipStream_t s) {
     if (nseg <= 0) return hipSuccess;
-    const int64_t grid = (nseg + kSegBlock - 1) / kSegBlock;
+    const int64_t per_xcd = ((nseg + kSegBlock - 1) / kSegBlock + 7) / 8;
+    const unsigned grid = (unsigned)(8 * per_xcd);
     if (wide)
-        hipLaunchKernelGGL(k_segsum<int64_t>, dim3((unsigned)grid), dim3(kSegBlock), 0, s,
-                           (const int64_t*)ptr, (const int64_t*)idx, buf, out, nseg, accumulate);
+        hipLaunchKernelGGL(k_segsum<int64_t>, dim3(grid), dim3(kSegBlock), 0, s, (const int64_t*)ptr,
+                           (const int64_t*)idx, buf, out, nseg, accumulate, per_xcd);
     else
-        hipLaunchKernelGGL(k_segsum<int32_t>, dim3((unsigned)grid), dim3(kSegBlock), 0, s,
-                           (const int32_t*)ptr, (const int32_t*)idx, buf, out, nseg, accumulate);
+        hipLaunchKernelGGL(k_segsum<int32_t>, dim3(grid), dim3(kSegBlock), 0, s, (const int32_t*)ptr,
+                           (const int32_t*)idx, buf, out, nseg, accumulate, per_xcd);
     return hipGetLastError();
 }
 
 hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, n, out);
+    return hipGetLastError();
+}
+
+hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
+    if (r.njobs < 0 || r.njobs > kExaReduceJobs) return hipErrorInvalidValue;
+    int64_t blocks = r.part ? 1 : 0;
+    for (int k = 0; k < r.njobs; ++k) blocks += (r.job[k].nseg + kSegBlock - 1) / kSegBlock;
+    if (blocks == 0) return hipSuccess;
+    const int64_t per_xcd = (blocks + 7) / 8;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);
     return hipGetLastError();
 }
 

@@ -95,13 +95,21 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
     }
     if (hipModuleGetFunction(&m->fn_sep, m->mod, "exa_k_jhsep") != hipSuccess)
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jhsep");
+    if (hipModuleGetFunction(&m->fn_multi, m->mod, "exa_k_multi") != hipSuccess)
+        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_multi");
     g_mods[key] = m;
     return m;
 }
 
 // ---------------------------------------------------------------------------
 DeviceState::~DeviceState() {
+    timing_off();
     for (void* p : allocs) (void)hipFree(p);
+}
+
+void DeviceState::timing_off() {
+    for (hipEvent_t e : timing.ev) (void)hipEventDestroy(e);
+    timing = EvalTiming();
 }
 
 void* DeviceState::alloc(size_t bytes) {
@@ -231,21 +239,29 @@ void build_device(Model& M) {
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
 }
 
+namespace {
+// Tiles that write zeros to the gradient entries no objective term touches
+// (in-place gradient only).
+void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
+    if (!M.grad_direct) return;
+    for (auto& z : M.grad_zero)
+        for (int64_t s = 0; s < z.second; s += tp) {
+            ExaTile t{};
+            t.pat = EXA_ZERO_TILE;
+            t.start = z.first + s;
+            t.count = std::min(tp, z.second - s);
+            t.slot = (int64_t)tiles.size();
+            tiles.push_back(t);
+        }
+}
+}  // namespace
+
 void set_schedule(Model& M, int mode, int block, int epl, bool fused) {
     DeviceState& D = *M.dev;
     DeviceState::Sched& S = D.sched[mode];
     const int64_t tp = (int64_t)block * epl;
     auto tiles = make_tiles(M, mode, 0, tp, fused);
-    if (mode == M_GRAD && M.grad_direct)
-        for (auto& z : M.grad_zero)
-            for (int64_t s = 0; s < z.second; s += tp) {
-                ExaTile t{};
-                t.pat = EXA_ZERO_TILE;
-                t.start = z.first + s;
-                t.count = std::min(tp, z.second - s);
-                t.slot = (int64_t)tiles.size();
-                tiles.push_back(t);
-            }
+    if (mode == M_GRAD) add_zero_tiles(M, tp, tiles);
     D.release(S.tiles);
     S.tiles = (ExaTile*)D.upload(tiles.data(), tiles.size() * sizeof(ExaTile));
     S.ntiles = (int64_t)tiles.size();
@@ -328,6 +344,116 @@ void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
     raw_launch(M, mode, call, s);
 }
 
+// ---- several callbacks in one launch (exa_eval) ----------------------------
+namespace {
+
+// Modes of an exa_eval mask; Jacobian and Hessian together run as JH units.
+std::vector<int> eval_modes(uint32_t mask) {
+    std::vector<int> m;
+    if (mask & EXA_EV_OBJ) m.push_back(M_OBJ);
+    if (mask & EXA_EV_GRAD) m.push_back(M_GRAD);
+    if (mask & EXA_EV_CONS) m.push_back(M_CONS);
+    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_HESS))
+        m.push_back(M_JH);
+    else if (mask & EXA_EV_JAC)
+        m.push_back(M_JAC);
+    else if (mask & EXA_EV_HESS)
+        m.push_back(M_HESS);
+    if (mask & EXA_EV_JPROD) m.push_back(M_JPROD);
+    if (mask & EXA_EV_JTPROD) m.push_back(M_JTPROD);
+    if (mask & EXA_EV_HPROD) m.push_back(M_HPROD);
+    return m;
+}
+
+// Tile list of a mask: every selected mode's tiles (the objective's under
+// its fixed schedule), laid out as eight chunks that each hold an eighth of
+// every mode's tiles, so that the per-XCD ranges of the launch get the same
+// mix of work and contiguous point ranges.
+void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused) {
+    DeviceState& D = *M.dev;
+    DeviceState::MultiSched& S = D.multi[mask];
+    const int64_t tp = (int64_t)block * epl;
+    std::vector<std::vector<ExaTile>> per;
+    for (int mode : eval_modes(mask)) {
+        std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused)
+                                               : make_tiles(M, mode, 0, tp, fused);
+        if (mode == M_GRAD) add_zero_tiles(M, tp, t);
+        for (ExaTile& x : t) x.pat |= mode << EXA_MODE_SHIFT;
+        per.push_back(std::move(t));
+    }
+    std::vector<ExaTile> all;
+    for (int j = 0; j < 8; ++j)
+        for (const auto& t : per) all.insert(all.end(), t.begin() + t.size() * j / 8, t.begin() + t.size() * (j + 1) / 8);
+    D.release(S.tiles);
+    S.tiles = all.empty() ? nullptr : (ExaTile*)D.upload(all.data(), all.size() * sizeof(ExaTile));
+    S.ntiles = (int64_t)all.size();
+    S.block = block;
+    S.epl = epl;
+    S.fused = fused;
+}
+
+void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
+    const DeviceState::MultiSched& S = M.dev->multi.at(mask);
+    if (S.ntiles == 0) return;
+    mc.tiles = S.tiles;
+    mc.ntiles = S.ntiles;
+    mc.per_xcd = (S.ntiles + 7) / 8;
+    void* args[] = {&mc};
+    hip_check(hipModuleLaunchKernel(M.dev->module->fn_multi, (unsigned)(8 * mc.per_xcd), 1, 1, (unsigned)S.block, 1,
+                                    1, 0, s, args, nullptr),
+              "hipModuleLaunchKernel");
+}
+
+// First exa_eval call with a mask: time the candidate schedules of the
+// combined launch and keep the fastest (as tune() does for one callback).
+// Objective tiles keep their fixed size and summation order under every
+// candidate.
+void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
+    const int blocks[] = {64, 128, 256};
+    const int epls[] = {1, 2, 4, 8};
+    std::vector<int> fuses = {0};
+    for (int mode : eval_modes(mask))
+        if (mode != M_OBJ && has_fusable_group(M, mode)) {
+            fuses.push_back(1);
+            break;
+        }
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    float best = 1e30f;
+    int bb = 256, be = 1;
+    bool bf = false;
+    try {
+        for (int f : fuses)
+            for (int b : blocks)
+                for (int ep : epls) {
+                    set_multi_schedule(M, mask, b, ep, f != 0);
+                    raw_launch_multi(M, mask, mc, s);
+                    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                    for (int r = 0; r < 3; ++r) raw_launch_multi(M, mask, mc, s);
+                    hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0;
+                    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    if (ms < best) {
+                        best = ms;
+                        bb = b;
+                        be = ep;
+                        bf = f != 0;
+                    }
+                }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_multi_schedule(M, mask, bb, be, bf);
+}
+
+}  // namespace
+
 // Algorithmic bytes of one launch evaluating `modes` under schedule
 // `fused`: per-point inputs and outputs of every unit, plus each distinct x,
 // v and theta entry read, counted once over the launch.
@@ -335,7 +461,8 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
     rd = wr = 0;
     std::vector<char> xs(M.nvar, 0), vs(M.nvar, 0), ts(M.ntheta, 0);
     for (int mode : modes)
-    for (const Unit& u : units_for(M, mode, fused)) {
+    // the objective always runs its fixed schedule
+    for (const Unit& u : units_for(M, mode, mode == M_OBJ ? kObjFused : fused)) {
         auto it = M.live.find({mode, u.code});
         if (it == M.live.end()) continue;
         const UnitLive& L = it->second;
@@ -700,6 +827,223 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
     });
 }
 
+exa_status exa_eval(exa_model* m, const exa_eval_args* a, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        if (!a) fail(EXA_EINVAL, "null exa_eval_args");
+        const uint32_t mask = a->mask;
+        if (mask == 0 || (mask & ~(uint32_t)EXA_EV_ALL))
+            fail(EXA_EINVAL, "exa_eval mask must select callbacks with the EXA_EV_* bits");
+        need(a->x, M.nvar, "x");
+        if (mask & (EXA_EV_HESS | EXA_EV_HPROD)) need(a->y, M.ncon, "y");
+        if (mask & (EXA_EV_JPROD | EXA_EV_HPROD)) need(a->v, M.nvar, "v");
+        if (mask & EXA_EV_JTPROD) need(a->w, M.ncon, "w");
+        if (mask & EXA_EV_OBJ) need(a->f, 1, "f");
+        if (mask & EXA_EV_GRAD) need(a->g, M.nvar, "g");
+        if (mask & EXA_EV_CONS) need(a->c, M.ncon, "c");
+        if (mask & EXA_EV_JAC) need(a->jac, M.nnzj, "jac");
+        if (mask & EXA_EV_HESS) need(a->hess, M.nnzh, "hess");
+        if (mask & EXA_EV_JPROD) need(a->jv, M.ncon, "jv");
+        if (mask & EXA_EV_JTPROD) need(a->jtw, M.nvar, "jtw");
+        if (mask & EXA_EV_HPROD) need(a->hv, M.nvar, "hv");
+        DeviceState& D = *M.dev;
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t nobj = D.sched[M_OBJ].ntiles;
+
+        // each mode's call, as its own entry point sets it up
+        ExaMulti mc;
+        std::memset(&mc, 0, sizeof mc);
+        for (int mode : eval_modes(mask)) {
+            ExaCall& c = mc.c[mode];
+            c.inst = D.inst;
+            c.x = a->x;
+            switch (mode) {
+                case M_OBJ: c.out0 = nobj == 1 ? a->f : D.tilesum; break;
+                case M_GRAD:
+                    c.out0 = M.grad_direct ? a->g : D.fo;
+                    c.direct = M.grad_direct ? 1 : 0;
+                    break;
+                case M_CONS: c.out0 = a->c; break;
+                case M_JAC: c.out0 = a->jac; break;
+                case M_HESS:
+                    c.y = a->y;
+                    c.sigma = a->obj_weight;
+                    c.out0 = a->hess;
+                    break;
+                case M_JH:
+                    c.y = a->y;
+                    c.sigma = a->obj_weight;
+                    c.out0 = a->jac;
+                    c.out1 = a->hess;
+                    break;
+                case M_JPROD:
+                    c.v = a->v;
+                    c.out0 = a->jv;
+                    break;
+                case M_JTPROD:
+                    c.y = a->w;
+                    c.out0 = D.fo;
+                    break;
+                case M_HPROD:
+                    c.y = a->y;
+                    c.v = a->v;
+                    c.sigma = a->obj_weight;
+                    c.out0 = D.hv;
+                    break;
+                default: break;
+            }
+        }
+        auto it = D.multi.find(mask);
+        if (it == D.multi.end() || !it->second.tuned) {
+            set_multi_schedule(M, mask, M.block, M.epl, M.fuse);
+            if (M.autotune) tune_multi(M, mask, mc, s);
+            D.multi[mask].tuned = true;
+        }
+        DeviceState::EvalTiming& Tm = D.timing;
+        const bool timed = Tm.on && Tm.used < (int64_t)Tm.reduced.size();
+        hipEvent_t* ev = timed ? &Tm.ev[4 * Tm.used] : nullptr;
+        if (timed) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
+        raw_launch_multi(M, mask, mc, s);
+        if (timed) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
+
+        // the reductions of every selected callback, in one launch
+        ExaReduce R;
+        std::memset(&R, 0, sizeof R);
+        auto job = [&](const DevMap& dm, const double* buf, double* out) {
+            ExaSegJob& J = R.job[R.njobs++];
+            J.ptr = dm.ptr;
+            J.idx = dm.idx;
+            J.wide = dm.wide;
+            J.nseg = dm.nseg;
+            J.buf = buf;
+            J.out = out;
+        };
+        if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
+        if (mask & EXA_EV_JTPROD) job(D.jt_map, D.fo, a->jtw);
+        if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
+        if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0
+            R.part = D.tilesum;
+            R.npart = nobj;
+            R.f = a->f;
+        }
+        const bool reduce = R.njobs > 0 || R.part;
+        if (timed && reduce) hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
+        hip_check(exa_launch_reduce(R, s), "exa_eval reductions");
+        if (timed && reduce) hip_check(hipEventRecord(ev[3], s), "hipEventRecord");
+        if (timed) Tm.reduced[Tm.used++] = reduce ? 1 : 0;
+
+        const uint32_t bits[8] = {EXA_EV_OBJ, EXA_EV_GRAD, EXA_EV_CONS, EXA_EV_JAC,
+                                  EXA_EV_HESS, EXA_EV_JPROD, EXA_EV_JTPROD, EXA_EV_HPROD};
+        for (int i = 0; i < 8; ++i)
+            if (mask & bits[i]) M.counters[i]++;
+    });
+}
+
+exa_status exa_eval_timing(exa_model* m, int32_t enable) {
+    return guard([&] {
+        Model& M = live(m);
+        DeviceState& D = *M.dev;
+        D.timing_off();
+        if (!enable) return;
+        const int64_t calls = 1024;
+        D.timing.ev.reserve(4 * calls);
+        for (int64_t i = 0; i < 4 * calls; ++i) {
+            hipEvent_t e;
+            // timing only: no system-scope fence (cache writeback) per record
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+                D.timing_off();
+                fail(EXA_EHIP, "hipEventCreate failed");
+            }
+            D.timing.ev.push_back(e);
+        }
+        D.timing.reduced.assign(calls, 0);
+        D.timing.on = true;
+    });
+}
+
+exa_status exa_eval_timing_read(exa_model* m, double* out4) {
+    return guard([&] {
+        Model& M = live(m);
+        if (!out4) fail(EXA_EINVAL, "null out4");
+        DeviceState::EvalTiming& T = M.dev->timing;
+        if (!T.on) fail(EXA_ESTATE, "exa_eval timing is off");
+        double se = 0.0, sr = 0.0;
+        int64_t nr = 0;
+        for (int64_t i = 0; i < T.used; ++i) {
+            hipEvent_t* ev = &T.ev[4 * i];
+            hip_check(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+            se += ms;
+            if (T.reduced[i]) {
+                hip_check(hipEventSynchronize(ev[3]), "hipEventSynchronize");
+                hip_check(hipEventElapsedTime(&ms, ev[2], ev[3]), "hipEventElapsedTime");
+                sr += ms;
+                ++nr;
+            }
+        }
+        out4[0] = (double)T.used;
+        out4[1] = T.used ? 1e3 * se / (double)T.used : 0.0;
+        out4[2] = (double)nr;
+        out4[3] = nr ? 1e3 * sr / (double)nr : 0.0;
+        T.used = 0;
+    });
+}
+
+exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
+    return guard([&] {
+        if (!m || !out4) fail(EXA_EINVAL, "null argument");
+        if (mask == 0 || (mask & ~(uint32_t)EXA_EV_ALL))
+            fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
+        const Model& M = m->impl;
+        if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
+        bool fused = M.fuse;
+        if (M.dev) {
+            auto it = M.dev->multi.find(mask);
+            if (it != M.dev->multi.end()) fused = it->second.fused;
+        }
+        int64_t rd = 0, wr = 0;
+        kernel_bytes(M, eval_modes(mask), fused, rd, wr);
+        out4[0] = rd;
+        out4[1] = wr;
+        // reduction launch: maps (int32 when every position fits), buffer
+        // entries once, outputs once; objective partials when several
+        int64_t rr = 0, rw = 0;
+        auto seg = [&](const SegMap& S) {
+            const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
+            const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
+            const int64_t w = top >= INT32_MAX ? 8 : 4;
+            rr += w * (nseg + 1 + nnz) + 8 * nnz;
+            rw += 8 * nseg;
+        };
+        if ((mask & EXA_EV_GRAD) && !M.grad_direct) seg(M.grad_map);
+        if (mask & EXA_EV_JTPROD) seg(M.jt_map);
+        if (mask & EXA_EV_HPROD) seg(M.h_map);
+        if (mask & EXA_EV_OBJ) {
+            const int64_t nobj = (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused).size();
+            if (nobj != 1) {
+                rr += 8 * nobj;
+                rw += 8;
+            }
+        }
+        out4[2] = rr;
+        out4[3] = rw;
+    });
+}
+
+exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
+    return guard([&] {
+        if (!m || !out4) fail(EXA_EINVAL, "null argument");
+        if (!m->impl.dev) fail(EXA_ESTATE, "host-only model has no schedule");
+        auto it = m->impl.dev->multi.find(mask);
+        if (it == m->impl.dev->multi.end()) fail(EXA_ESTATE, "no exa_eval call with this mask yet");
+        out4[0] = it->second.block;
+        out4[1] = it->second.epl;
+        out4[2] = it->second.fused ? 1 : 0;
+        out4[3] = it->second.ntiles;
+    });
+}
+
 exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, double obj_weight,
                              const double* w, double* theta_bar, exa_stream_t stream) {
     return guard([&] {
@@ -736,7 +1080,7 @@ exa_status exa_kernel_bytes(const exa_model* m, int32_t callback, int64_t* read_
         const int mode = mode_of_callback(callback);
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        const bool fused = mode == M_OBJ ? kObjFused : M.dev ? M.dev->sched[mode].fused : false;
+        const bool fused = M.dev ? M.dev->sched[mode].fused : false;
         int64_t rd = 0, wr = 0;
         kernel_bytes(M, {mode}, fused, rd, wr);
         if (read_bytes) *read_bytes = rd;

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -14,6 +15,7 @@ struct Module {
     hipModule_t mod = nullptr;
     hipFunction_t fn[M_COUNT] = {};
     hipFunction_t fn_sep = nullptr;  // separate Jacobian and Hessian tiles in one launch
+    hipFunction_t fn_multi = nullptr;  // tiles of several callbacks in one launch
     std::string source;
     std::vector<char> code;
     ~Module();
@@ -40,6 +42,23 @@ struct DeviceState {
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;
     } sched[M_COUNT];
+    // schedule of the several-callback launch, per exa_eval mask
+    struct MultiSched {
+        int block = 256, epl = 4;
+        bool fused = false, tuned = false;
+        ExaTile* tiles = nullptr;
+        int64_t ntiles = 0;
+    };
+    std::map<uint32_t, MultiSched> multi;
+    // HIP events around exa_eval's two launches while timing is on: four per
+    // recorded call (evaluation start/end, reduction start/end)
+    struct EvalTiming {
+        bool on = false;
+        std::vector<hipEvent_t> ev;
+        std::vector<char> reduced;  // per recorded call: a reduction was launched
+        int64_t used = 0;
+    } timing;
+    void timing_off();
     double* fo = nullptr;             // first-order buffer: grad part, then jac part
     double* par = nullptr;
     double* hv = nullptr;             // H v contributions (curved slots only)

@@ -270,6 +270,109 @@ class ExaModel:
                                     C.c_void_p(out.data_ptr()), _stream(x.get_device())))
         return out
 
+    # -- several callbacks at one point (exa_eval) -----------------------------
+    _EV_OUT = (("obj", "f", "f"), ("grad", "g", "n"), ("cons", "c", "m"), ("jac", "jac", "nnzj"),
+               ("hess", "hess", "nnzh"), ("jprod", "jv", "m"), ("jtprod", "jtw", "n"),
+               ("hprod", "hv", "n"))
+
+    def _eval_args(self, x, y, obj_weight, v, w, outs):
+        sizes = {"f": 1, "n": self.nvar, "m": self.ncon, "nnzj": self.nnzj, "nnzh": self.nnzh}
+        a = _lib.EvalArgs()
+        keep = [x]
+        a.x = self._dev(x, self.nvar, "x")
+        for cb, field, size in self._EV_OUT:
+            t = outs.get(field)
+            if t is None:
+                continue
+            a.mask |= _lib.EV[cb]
+            setattr(a, field, self._dev(t, sizes[size], field))
+            keep.append(t)
+        if a.mask == 0:
+            raise ValueError("give at least one output tensor (f, g, c, jac, hess, jv, jtw, hv)")
+        for name, t, n, bits in (("y", y, self.ncon, ("hess", "hprod")), ("v", v, self.nvar, ("jprod", "hprod")),
+                                 ("w", w, self.ncon, ("jtprod",))):
+            if any(a.mask & _lib.EV[b] for b in bits):
+                if t is None:
+                    raise ValueError(f"{name} is needed by the selected callbacks")
+                setattr(a, name, self._dev(t, n, name))
+                keep.append(t)
+        a.obj_weight = float(obj_weight)
+        return a, keep
+
+    def evaluate(self, x, y=None, obj_weight=1.0, v=None, w=None, *, f=None, g=None, c=None, jac=None,
+                 hess=None, jv=None, jtw=None, hv=None):
+        """Every callback whose output tensor is given, at one point, through
+        exa_eval: one evaluation launch plus at most one reduction launch, each
+        output bit-identical to its own callback's.  Outputs: f (obj), g
+        (grad), c (cons), jac, hess, jv (jprod), jtw (jtprod), hv (hprod)."""
+        a, _ = self._eval_args(x, y, obj_weight, v, w, dict(f=f, g=g, c=c, jac=jac, hess=hess, jv=jv, jtw=jtw,
+                                                             hv=hv))
+        check(LIB.exa_eval(self._h, C.byref(a), _stream(x.get_device())))
+
+    def bind(self, x, y=None, obj_weight=1.0, v=None, w=None, *, f=None, g=None, c=None, jac=None, hess=None,
+             jv=None, jtw=None, hv=None):
+        """A reusable exa_eval call over fixed tensors: the arguments are
+        checked once, and each call of the result evaluates the selected
+        callbacks on the tensors' current contents (the caller updates them in
+        place).  The bound tensors are kept alive by the returned object."""
+        a, keep = self._eval_args(x, y, obj_weight, v, w, dict(f=f, g=g, c=c, jac=jac, hess=hess, jv=jv,
+                                                                jtw=jtw, hv=hv))
+        return BoundEval(self, a, keep, x.get_device())
+
+    def eval_schedule(self, callbacks) -> dict:
+        """Schedule exa_eval uses for a set of callback names (after its first
+        call with that set)."""
+        out = np.zeros(4, dtype=np.int64)
+        check(LIB.exa_eval_schedule(self._h, self._eval_mask(callbacks), _ptr(out, C.c_int64)))
+        return dict(block=int(out[0]), points_per_lane=int(out[1]), fused=int(out[2]), tiles=int(out[3]))
+
+    @staticmethod
+    def _eval_mask(callbacks) -> int:
+        mask = 0
+        for cb in callbacks:
+            mask |= _lib.EV[cb]
+        return mask
+
+    def eval_bytes(self, callbacks) -> dict:
+        """Algorithmic bytes of exa_eval's two launches for a set of callback
+        names: {eval_read, eval_write, reduce_read, reduce_write}."""
+        out = np.zeros(4, dtype=np.int64)
+        check(LIB.exa_eval_bytes(self._h, self._eval_mask(callbacks), _ptr(out, C.c_int64)))
+        return dict(zip(("eval_read", "eval_write", "reduce_read", "reduce_write"), out.tolist()))
+
+    def eval_timing(self, enable: bool = True):
+        """Turn on (or off) HIP-event timing of exa_eval's launches."""
+        check(LIB.exa_eval_timing(self._h, 1 if enable else 0))
+
+    def eval_timing_read(self) -> dict:
+        """Average launch durations (us) of the exa_eval calls recorded since
+        timing was turned on or last read."""
+        out = np.zeros(4, dtype=np.float64)
+        check(LIB.exa_eval_timing_read(self._h, _ptr(out, C.c_double)))
+        return dict(calls=int(out[0]), eval_us=float(out[1]), reduce_calls=int(out[2]), reduce_us=float(out[3]))
+
     def set_theta(self, theta):
         pt = self._dev(theta, self.ntheta, "theta")
         check(LIB.exa_set_theta(self._h, pt, _stream(theta.get_device())))
+
+
+class BoundEval:
+    """exa_eval with its arguments fixed (see ExaModel.bind)."""
+
+    def __init__(self, model, args, keep, device):
+        self._model = model  # the model outlives the call
+        self._args = args
+        self._keep = keep
+        self._ref = C.byref(args)
+        self._dev = device
+
+    @property
+    def obj_weight(self) -> float:
+        return self._args.obj_weight
+
+    @obj_weight.setter
+    def obj_weight(self, value: float):
+        self._args.obj_weight = float(value)
+
+    def __call__(self):
+        check(LIB.exa_eval(self._model._h, self._ref, _stream(self._dev)))

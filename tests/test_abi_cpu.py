@@ -183,3 +183,27 @@ def test_kernel_bytes_accounting():
     em = ExaModel(w.model, host_only=True)
     rd, wr = em.kernel_bytes("hess")
     assert wr == 8 * em.nnzh and rd > 0
+
+
+def test_eval_bytes_accounting():
+    """exa_eval's evaluation launch counts as the single callbacks do; its
+    reduction launch reads each map and buffer entry once."""
+    from paper_2608_16265_amd import ExaModel
+    w = pde(9, 3)
+    em = ExaModel(w.model, host_only=True)
+    n, ni = 9, 49
+    b = em.eval_bytes(("jac",))
+    assert (b["eval_read"], b["eval_write"]) == em.kernel_bytes("jac")
+    assert b["reduce_read"] == 0 and b["reduce_write"] == 0
+    # J^T w: one segment per variable over every Jacobian entry (int32 maps)
+    b = em.eval_bytes(("jtprod",))
+    nseg, nnz = 2 * n * n, em.nnzj
+    assert nnz == 6 * ni
+    assert b["reduce_read"] == 4 * (nseg + 1 + nnz) + 8 * nnz
+    assert b["reduce_write"] == 8 * nseg
+    # one objective tile and an in-place gradient: nothing to reduce
+    b = em.eval_bytes(("obj", "grad"))
+    assert b["reduce_read"] == 0 and b["reduce_write"] == 0
+    assert b["eval_write"] == 8 + 8 * 2 * n * n
+    with pytest.raises(Exception):
+        em.eval_bytes(())

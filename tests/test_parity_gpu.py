@@ -198,8 +198,9 @@ def test_callbacks_run_on_the_current_stream():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        assert _stream(X.get_device()).value == s.cuda_stream
+        assert (_stream(X.get_device()).value or 0) == s.cuda_stream
         out = em.hess_coord(X, Y, 1.0)
     s.synchronize()
     assert np.array_equal(host(out), ref)
-    assert _stream(X.get_device()).value == torch.cuda.current_stream().cuda_stream
+    # the default stream's handle is 0 (ctypes shows it as None)
+    assert (_stream(X.get_device()).value or 0) == torch.cuda.current_stream().cuda_stream
