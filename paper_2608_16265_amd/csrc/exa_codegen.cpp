@@ -701,13 +701,10 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
         os << "        const long long kr = kb + threadIdx.x;\n";
         os << "        const int npts = (int)((kend - kb) < nthr ? (kend - kb) : nthr);\n";
-        if (inline_stores)
-            // every lane runs the statements, so that each job's staged store
-            // (workgroup barriers) can follow its sweep: lanes past the end
-            // recompute the last point and store nothing
-            os << "        const long long k = kr < kend ? kr : kend - 1;\n";
-        else
-            os << "        const long long k = kr;\n";
+        // every lane runs the statements (no divergent region around them),
+        // so that each job's staged store (workgroup barriers) can follow its
+        // sweep: lanes past the end recompute the last point and store nothing
+        os << "        const long long k = kr < kend ? kr : kend - 1;\n";
     }
     const std::vector<Job> jobs = jobs_of(M, mode, U);
     auto oname = [&](const Job& j) {
@@ -719,7 +716,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         else
             os << "        double " << oname(j) << "[" << out_step(M.pats[j.p], j.mode) << "] = {};\n";
     }
-    os << (inline_stores ? "        {\n" : "        if (k < kend) {\n");
+    os << (mode != M_OBJ ? "        {\n" : "        if (k < kend) {\n");
 
     // ---- statements: loads (all candidates), then every member's sweeps
     Em e(ntmp);
@@ -877,10 +874,10 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 const Pattern& P = M.pats[p];
                 const std::string pd = "P" + std::to_string(p) + "_";
                 if (P.kind == EXA_CON)
-                    os << "        if (k < kend) __builtin_nontemporal_store(r" << p << ", &C.out0[I.off[" << EXA_OFF_ROWS
+                    os << "        if (kr < kend) __builtin_nontemporal_store(r" << p << ", &C.out0[I.off[" << EXA_OFF_ROWS
                        << "] + " << pd << ".o0 + k]);\n";
                 else
-                    os << "        if (k < kend) C.out1[I.off[" << EXA_OFF_AUG << "] + " << pd << ".o0 + k] = r" << p
+                    os << "        if (kr < kend) C.out1[I.off[" << EXA_OFF_AUG << "] + " << pd << ".o0 + k] = r" << p
                        << ";\n";
             }
             break;
@@ -1136,7 +1133,10 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
         cases.push_back("case " + std::to_string((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE) +
                         ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) " + G +
                         ".out0[" + G + ".inst[T.inst].off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;");
-        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") exa_k_multi(ExaMulti C) {\n";
+        // every unit's tiles share this kernel's register budget: ask for at
+        // least four waves per SIMD, so that one wave of the launch fits on
+        // the chip at once
+        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ", 4) exa_k_multi(ExaMulti C) {\n";
         os << "    __shared__ double lds[" << lds << "];\n";
         os << "    (void)lds;\n";
         os << "    const long long w = (blockIdx.x % 8) * C.per_xcd + blockIdx.x / 8;\n";

@@ -4,20 +4,26 @@
 
 #include <cstdint>
 
-// ptr/idx are int64 when wide != 0, else int32
-hipError_t exa_launch_segsum(const void* ptr, const void* idx, int wide, const double* buf, double* out,
-                             int64_t nseg, int accumulate, hipStream_t s);
 hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_t s);
 hipError_t exa_launch_fill(double* p, int64_t n, double v, hipStream_t s);
 
 // One segment-sum job: out[s] = sum of buf[idx[j]], j in [ptr[s], ptr[s+1]).
+// With lanes == nullptr one lane sums one segment in ascending j.  With
+// lanes set, lane l sums a chunk of at most kExaChunk consecutive entries:
+// lanes[3l] = segment (-1 for padding), lanes[3l+1] = first entry,
+// lanes[3l+2] = count | (number of chunks of the segment << 4) on the
+// segment's first chunk; a segment's chunks lie in one 256-lane block, and
+// its first lane adds the chunk sums in chunk order.
+constexpr int kExaChunk = 4;
 struct ExaSegJob {
     const void* ptr;
     const void* idx;
     const double* buf;
     double* out;
     int64_t nseg;
-    int32_t wide;  // ptr/idx are int64 when set, else int32
+    const int32_t* lanes;
+    int64_t nlanes;  // a multiple of 256 when lanes is set
+    int32_t wide;    // ptr/idx are int64 when set, else int32
     int32_t pad;
 };
 constexpr int kExaReduceJobs = 3;

@@ -18,15 +18,14 @@ __device__ __forceinline__ int64_t xcd_block(int64_t per_xcd) {
     return (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
 }
 
-// out[s] (+)= sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
+// out[s] = sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
 // the sparse-to-dense compression of Sec. 7.2.3, one lane per segment, with
 // a fixed summation order so the result does not depend on scheduling.
 template <class I>
 __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __restrict__ idx,
-                                         const double* __restrict__ buf, double* __restrict__ out, int64_t s,
-                                         int accumulate) {
+                                         const double* __restrict__ buf, double* __restrict__ out, int64_t s) {
     const int64_t b = ptr[s], e = ptr[s + 1];
-    double acc = accumulate ? out[s] : 0.0;
+    double acc = 0.0;
     int64_t j = b;
     // four entries at a time: their index and value loads are issued
     // together, the additions stay in ascending order
@@ -40,6 +39,44 @@ __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __r
     }
     for (; j < e; ++j) acc += buf[idx[j]];
     out[s] = acc;
+}
+
+// The same sums for maps with long segments: lane l of the job adds one
+// chunk of at most kExaChunk entries (its loads issued together, indices
+// clamped into the chunk), and the segment's first lane adds the chunk sums
+// of its segment, which lie in the same workgroup, in chunk order.  The
+// order depends on the map only.  Called by every lane of the workgroup.
+__device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double* lds) {
+    const int32_t* __restrict__ idx = (const int32_t*)J.idx;
+    const double* __restrict__ buf = J.buf;
+    int32_t seg = -1, beg = 0, info = 0;
+    if (l < J.nlanes) {
+        seg = J.lanes[3 * l];
+        beg = J.lanes[3 * l + 1];
+        info = J.lanes[3 * l + 2];
+    }
+    const int cnt = info & 15;
+    double part = 0.0;
+    if (cnt > 0) {
+        int32_t ix[kExaChunk];
+#pragma unroll
+        for (int u = 0; u < kExaChunk; ++u) ix[u] = idx[beg + (u < cnt ? u : cnt - 1)];
+        double v[kExaChunk];
+#pragma unroll
+        for (int u = 0; u < kExaChunk; ++u) v[u] = buf[ix[u]];
+#pragma unroll
+        for (int u = 0; u < kExaChunk; ++u)
+            if (u < cnt) part += v[u];
+    }
+    lds[threadIdx.x] = part;
+    __syncthreads();
+    const int nl = info >> 4;
+    if (seg >= 0 && nl > 0) {
+        double acc = lds[threadIdx.x];
+        for (int i = 1; i < nl; ++i) acc += lds[threadIdx.x + i];
+        J.out[seg] = acc;
+    }
+    __syncthreads();
 }
 
 // Sum of n partials in a fixed order by one 256-wide workgroup: strided
@@ -57,14 +94,6 @@ __device__ __forceinline__ void sum_body(const double* __restrict__ part, int64_
     if (threadIdx.x == 0) out[0] = lds[0];
 }
 
-template <class I>
-__global__ void __launch_bounds__(kSegBlock)
-k_segsum(const I* __restrict__ ptr, const I* __restrict__ idx, const double* __restrict__ buf,
-         double* __restrict__ out, int64_t nseg, int accumulate, int64_t per_xcd) {
-    const int64_t s = xcd_block(per_xcd) * kSegBlock + threadIdx.x;
-    if (s < nseg) seg_body(ptr, idx, buf, out, s, accumulate);
-}
-
 __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, int64_t n,
                                              double* __restrict__ out) {
     __shared__ double lds[256];
@@ -72,22 +101,30 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, in
 }
 
 // Several reductions in one launch: the segment sums of each job over
-// consecutive block ranges, then (when R.part is set) one block for the
-// objective partials.  Each job sums exactly as k_segsum, the objective as
-// k_sum.
+// consecutive block ranges (one block per 256 segments, or per 256 lanes of
+// a chunked job), then (when R.part is set) one block for the objective
+// partials, summed as k_sum does.
+__device__ __forceinline__ int64_t job_blocks(const ExaSegJob& J) {
+    return J.lanes ? J.nlanes / kSegBlock : (J.nseg + kSegBlock - 1) / kSegBlock;
+}
+
 __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_xcd) {
     __shared__ double lds[256];
     int64_t b = xcd_block(per_xcd);
     for (int k = 0; k < R.njobs; ++k) {
         const ExaSegJob& J = R.job[k];
-        const int64_t nb = (J.nseg + kSegBlock - 1) / kSegBlock;
+        const int64_t nb = job_blocks(J);
         if (b < nb) {
+            if (J.lanes) {
+                chunk_body(J, b * kSegBlock + threadIdx.x, lds);
+                return;
+            }
             const int64_t s = b * kSegBlock + threadIdx.x;
             if (s < J.nseg) {
                 if (J.wide)
-                    seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, 0);
+                    seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s);
                 else
-                    seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, 0);
+                    seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s);
             }
             return;
         }
@@ -103,20 +140,6 @@ __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, int64_t n,
 
 }  // namespace
 
-hipError_t exa_launch_segsum(const void* ptr, const void* idx, int wide, const double* buf, double* out,
-                             int64_t nseg, int accumulate, hipStream_t s) {
-    if (nseg <= 0) return hipSuccess;
-    const int64_t per_xcd = ((nseg + kSegBlock - 1) / kSegBlock + 7) / 8;
-    const unsigned grid = (unsigned)(8 * per_xcd);
-    if (wide)
-        hipLaunchKernelGGL(k_segsum<int64_t>, dim3(grid), dim3(kSegBlock), 0, s, (const int64_t*)ptr,
-                           (const int64_t*)idx, buf, out, nseg, accumulate, per_xcd);
-    else
-        hipLaunchKernelGGL(k_segsum<int32_t>, dim3(grid), dim3(kSegBlock), 0, s, (const int32_t*)ptr,
-                           (const int32_t*)idx, buf, out, nseg, accumulate, per_xcd);
-    return hipGetLastError();
-}
-
 hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, n, out);
     return hipGetLastError();
@@ -125,7 +148,11 @@ hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_
 hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     if (r.njobs < 0 || r.njobs > kExaReduceJobs) return hipErrorInvalidValue;
     int64_t blocks = r.part ? 1 : 0;
-    for (int k = 0; k < r.njobs; ++k) blocks += (r.job[k].nseg + kSegBlock - 1) / kSegBlock;
+    for (int k = 0; k < r.njobs; ++k) {
+        const ExaSegJob& J = r.job[k];
+        if (J.lanes && J.nlanes % kSegBlock) return hipErrorInvalidValue;
+        blocks += J.lanes ? J.nlanes / kSegBlock : (J.nseg + kSegBlock - 1) / kSegBlock;
+    }
     if (blocks == 0) return hipSuccess;
     const int64_t per_xcd = (blocks + 7) / 8;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);

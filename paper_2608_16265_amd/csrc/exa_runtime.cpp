@@ -229,6 +229,11 @@ void build_device(Model& M) {
             std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
             d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
             d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
+            std::vector<int32_t> lanes = chunk_lanes(S);
+            if (!lanes.empty()) {
+                d.lanes = (const int32_t*)D.upload(lanes.data(), lanes.size() * sizeof(int32_t));
+                d.nlanes = (int64_t)lanes.size() / 3;
+            }
         }
     };
     up_map(M.grad_map, D.grad_map);
@@ -255,6 +260,34 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
         }
 }
 }  // namespace
+
+// Chunk lanes of a map whose longest segment has more than 2 * kExaChunk
+// entries (one lane per kExaChunk entries, a segment's lanes inside one
+// 256-lane block); empty when one lane per segment is enough, or when some
+// segment would need more than a block.
+std::vector<int32_t> chunk_lanes(const SegMap& S) {
+    std::vector<int32_t> L;
+    int64_t longest = 0;
+    for (int64_t s = 0; s < S.nseg(); ++s) longest = std::max(longest, S.ptr[s + 1] - S.ptr[s]);
+    if (longest <= 2 * kExaChunk || (longest + kExaChunk - 1) / kExaChunk > 256) return L;
+    auto pad_to = [&](int64_t lanes) {
+        while ((int64_t)L.size() / 3 < lanes) L.insert(L.end(), {-1, 0, 0});
+    };
+    for (int64_t s = 0; s < S.nseg(); ++s) {
+        const int64_t b = S.ptr[s], len = S.ptr[s + 1] - b;
+        const int64_t nl = std::max<int64_t>(1, (len + kExaChunk - 1) / kExaChunk);
+        const int64_t here = (int64_t)L.size() / 3;
+        if (here % 256 + nl > 256) pad_to((here / 256 + 1) * 256);
+        for (int64_t c = 0; c < nl; ++c) {
+            const int64_t cnt = std::min<int64_t>(kExaChunk, len - c * kExaChunk);
+            L.push_back((int32_t)s);
+            L.push_back((int32_t)(b + c * kExaChunk));
+            L.push_back((int32_t)(std::max<int64_t>(cnt, 0) | (c == 0 ? nl << 4 : 0)));
+        }
+    }
+    pad_to(((int64_t)L.size() / 3 + 255) / 256 * 256);
+    return L;
+}
 
 void set_schedule(Model& M, int mode, int block, int epl, bool fused) {
     DeviceState& D = *M.dev;
@@ -515,8 +548,26 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
     for (char c : ts) rd += c ? 8 : 0;
 }
 
-void segsum(const DevMap& m, const double* buf, double* out, int acc, hipStream_t s) {
-    hip_check(exa_launch_segsum(m.ptr, m.idx, m.wide, buf, out, m.nseg, acc, s), "segmented reduction");
+ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
+    ExaSegJob J;
+    std::memset(&J, 0, sizeof J);
+    J.ptr = m.ptr;
+    J.idx = m.idx;
+    J.wide = m.wide;
+    J.nseg = m.nseg;
+    J.lanes = m.lanes;
+    J.nlanes = m.nlanes;
+    J.buf = buf;
+    J.out = out;
+    return J;
+}
+
+void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s) {
+    ExaReduce R;
+    std::memset(&R, 0, sizeof R);
+    R.job[0] = seg_job(m, buf, out);
+    R.njobs = 1;
+    hip_check(exa_launch_reduce(R, s), "segmented reduction");
 }
 
 }  // namespace exa
@@ -703,7 +754,7 @@ exa_status exa_grad(exa_model* m, const double* x, double* g, exa_stream_t strea
         } else {
             c.out0 = M.dev->fo;
             launch_mode(M, M_GRAD, c, s);
-            segsum(M.dev->grad_map, M.dev->fo, g, 0, s);
+            segsum(M.dev->grad_map, M.dev->fo, g, s);
         }
         M.counters[1]++;
     });
@@ -801,7 +852,7 @@ exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jt
         c.y = w;
         c.out0 = M.dev->fo;
         launch_mode(M, M_JTPROD, c, s);
-        segsum(M.dev->jt_map, M.dev->fo, Jtw, 0, s);
+        segsum(M.dev->jt_map, M.dev->fo, Jtw, s);
         M.counters[6]++;
     });
 }
@@ -822,7 +873,7 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
         c.sigma = obj_weight;
         c.out0 = M.dev->hv;
         launch_mode(M, M_HPROD, c, s);
-        segsum(M.dev->h_map, M.dev->hv, Hv, 0, s);
+        segsum(M.dev->h_map, M.dev->hv, Hv, s);
         M.counters[7]++;
     });
 }
@@ -909,15 +960,7 @@ exa_status exa_eval(exa_model* m, const exa_eval_args* a, exa_stream_t stream) {
         // the reductions of every selected callback, in one launch
         ExaReduce R;
         std::memset(&R, 0, sizeof R);
-        auto job = [&](const DevMap& dm, const double* buf, double* out) {
-            ExaSegJob& J = R.job[R.njobs++];
-            J.ptr = dm.ptr;
-            J.idx = dm.idx;
-            J.wide = dm.wide;
-            J.nseg = dm.nseg;
-            J.buf = buf;
-            J.out = out;
-        };
+        auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
         if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
         if (mask & EXA_EV_JTPROD) job(D.jt_map, D.fo, a->jtw);
         if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
@@ -1013,7 +1056,9 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
             const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
             const int64_t w = top >= INT32_MAX ? 8 : 4;
-            rr += w * (nseg + 1 + nnz) + 8 * nnz;
+            const int64_t lanes = w == 4 ? (int64_t)chunk_lanes(S).size() / 3 : 0;
+            // chunked maps read their lane table instead of the segment pointers
+            rr += (lanes ? 12 * lanes : w * (nseg + 1)) + w * nnz + 8 * nnz;
             rw += 8 * nseg;
         };
         if ((mask & EXA_EV_GRAD) && !M.grad_direct) seg(M.grad_map);
@@ -1060,7 +1105,7 @@ exa_status exa_adjoint_theta(exa_model* m, const double* x, const double* y, dou
         c.sigma = obj_weight;
         c.out0 = M.dev->par;
         launch_mode(M, M_ADJ, c, s);
-        segsum(M.dev->par_map, M.dev->par, theta_bar, 0, s);
+        segsum(M.dev->par_map, M.dev->par, theta_bar, s);
         M.counters[8]++;
     });
 }

@@ -26,6 +26,9 @@ struct DevMap {
     const void* idx = nullptr;
     int64_t nseg = 0;
     int wide = 0;
+    // chunk lanes (see ExaSegJob) for maps with long segments, else null
+    const int32_t* lanes = nullptr;
+    int64_t nlanes = 0;
 };
 
 struct DeviceState {
@@ -78,6 +81,7 @@ std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile
 std::string kernel_name(int mode);
 int mode_lds_doubles(const Model& M, int mode);
 void set_schedule(Model& M, int mode, int block, int epl, bool fused);
+std::vector<int32_t> chunk_lanes(const SegMap& S);
 void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);
 void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);
 void hess_structure_host(const Model& M, int32_t* rows, int32_t* cols);

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 from exa_modeling.generators import acopf, pde, rosenbrock
 from parity_util import dev, host
-from test_parity_gpu import aliasing_case, empty_pattern_case, single_point_case
+from test_parity_gpu import aliasing_case, empty_pattern_case, single_point_case, star_case
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +25,7 @@ CASES = {
     "alias": aliasing_case,
     "empty": empty_pattern_case,
     "single": single_point_case,
+    "star": lambda: star_case([700, 400, 3, 0, 90], 6),  # chunked segment sums
 }
 FIELD = {"obj": "f", "grad": "g", "cons": "c", "jac": "jac", "hess": "hess", "jprod": "jv",
          "jtprod": "jtw", "hprod": "hv"}

@@ -56,6 +56,22 @@ def single_point_case():
     return Workload(m, np.array([3.0, 5.0]), np.array([0.75]), 1.0)
 
 
+def star_case(sizes, seed):
+    """Hub variables shared by many terms: long gradient, J^T w and H v
+    segments (several hubs so that their chunks need block padding)."""
+    m = Model("star")
+    nh = len(sizes)
+    n = nh + int(sum(sizes))
+    x = m.add_var(n)
+    hub = np.concatenate([np.full(k, h) for h, k in enumerate(sizes)])
+    leaf = np.arange(nh, n)
+    d = DataSet(len(leaf), h=hub, l=leaf)
+    m.add_obj(x[d.h] * x[d.l] + x[d.l] ** 2, d)
+    m.add_con(sin(x[d.h]) * x[d.l], d)
+    rng = np.random.default_rng(seed)
+    return Workload(m, rng.uniform(-1, 1, n), rng.standard_normal(len(leaf)), 0.8)
+
+
 def _zoo():
     from test_oracle_pins import op_zoo
     return op_zoo()
@@ -69,6 +85,8 @@ CASES = {
     "acopf30_gb": lambda: acopf(30, 0, gb_in_theta=True),
     "pde8": lambda: pde(8, 3),
     "pde50": lambda: pde(50, 5),
+    "star_chunked": lambda: star_case([700, 400, 3, 0, 90], 6),   # chunked sums, padded blocks
+    "star_plain": lambda: star_case([1500, 2], 7),                # too long to chunk
     "zoo": _zoo,
     "alias": aliasing_case,
     "empty": empty_pattern_case,
