@@ -12,11 +12,14 @@ Also reported on the same JSON line:
 * step_separate_us -- the same step as seven separate callback calls;
 * callbacks_us  -- each callback alone, timed with the paper's protocol
   (Sec. 8.2: back-to-back calls, one synchronization, best of 3);
-* roofline      -- the step's evaluation kernel (exa_k_multi): algorithmic
+* roofline      -- the step's evaluation kernel (exa_k_multi, or exa_k_onepass
+  when the tuner picks one pass per point for every callback): algorithmic
   bytes per launch / its average duration, measured by HIP events that the
   library records on the launch stream around each launch, against the
   8 TB/s HBM peak; the reduction launch and the combined Jacobian+Hessian
   kernel are reported beside it;
+* hbm_copy_gbs  -- a plain 1 GiB device copy (read + write bytes per second),
+  the practical ceiling of a streaming kernel beside the nominal 8 TB/s;
 * cpu_baseline  -- the CPU oracle (numpy, float64) on a bounded sample;
 * pde           -- the PDE-control model on a 1000 x 1000 grid
   (HBM-bound): the same step and rooflines;
@@ -114,10 +117,11 @@ def kernel_ms(fn, n=200):
     return e0.elapsed_time(e1) / n, n
 
 
-def profiled_traffic(summary, model):
-    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
-    calibrated on a plain copy) as committed in profiles/, or None when the
-    generated kernels have changed since (their source hash differs)."""
+def profiled_traffic(summary, model, kernel):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 (FETCH_SIZE +
+    WRITE_SIZE, calibrated on a plain copy) as committed in profiles/, or
+    None when the generated kernels have changed since (their source hash
+    differs) or the summary covers another kernel."""
     import hashlib
     from paper_2608_16265_amd import ExaModel
     path = os.path.join(ROOT, "profiles", summary)
@@ -130,6 +134,8 @@ def profiled_traffic(summary, model):
             kv[k.strip()] = v.strip()
     src = ExaModel(model, host_only=True).generated_source()
     if hashlib.sha256(src.encode()).hexdigest()[:16] != kv.get("source_sha256_16"):
+        return None
+    if kv.get("kernel") != kernel:
         return None
     try:
         return int(kv["traffic_bytes_per_launch"])
@@ -160,6 +166,23 @@ def eval_launch_us(em, run, n=500):
     t = em.eval_timing_read()
     em.eval_timing(False)
     return t
+
+
+def copy_gbs(mib=1024, n=20):
+    """Bandwidth of a plain device-to-device copy (bytes read + written per
+    second): the practical ceiling of a streaming kernel on this GPU."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * a.numel() * 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def leg_single(name, wl, steps, warmup):
@@ -217,6 +240,9 @@ def leg_single(name, wl, steps, warmup):
     rd, wr = em.kernel_bytes("jac_hess")
     sched = {k: em.schedule(k) for k in ("jac", "hess", "jac_hess")}
     sched["eval_all"] = em.eval_schedule(ALL_CBS)
+    # the tuner picks per-callback tiles (exa_k_multi) or one pass per point
+    # for every callback (exa_k_onepass)
+    eval_kernel = "exa_k_onepass" if sched["eval_all"]["one_pass"] else "exa_k_multi"
     nnz = em.nnzj + em.nnzh
     ev_bytes = eb["eval_read"] + eb["eval_write"]
     red_bytes = eb["reduce_read"] + eb["reduce_write"]
@@ -227,7 +253,8 @@ def leg_single(name, wl, steps, warmup):
         jac_hess_nnz_per_s=nnz / (per_cb["jac_hess_coord"] * 1e-6),
         jac_plus_hess_nnz_per_s=nnz / ((per_cb["jac_coord"] + per_cb["hess_coord"]) * 1e-6),
         callbacks_us={k: round(v, 2) for k, v in per_cb.items()},
-        eval_us=round(tm["eval_us"], 3), eval_calls_timed=tm["calls"], reduce_us=round(tm["reduce_us"], 3),
+        eval_kernel=eval_kernel, eval_us=round(tm["eval_us"], 3), eval_calls_timed=tm["calls"],
+        reduce_us=round(tm["reduce_us"], 3),
         eval_bytes=ev_bytes, eval_read_bytes=eb["eval_read"], eval_write_bytes=eb["eval_write"],
         reduce_bytes=red_bytes,
         eval_gbs=ev_bytes / (tm["eval_us"] * 1e-6) / 1e9,
@@ -416,8 +443,8 @@ def main():
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
         out["jac_plus_hess_nnz_per_s"] = r["jac_plus_hess_nnz_per_s"]
         from exa_modeling.generators import acopf as _acopf
-        traffic = profiled_traffic("acopf10k_eval_all.md", _acopf(30, 0).model)
-        out["roofline"] = {"kernel": "exa_k_multi", "bound": "hbm", "achieved": r["eval_gbs"],
+        traffic = profiled_traffic("acopf10k_eval_all.md", _acopf(30, 0).model, r["eval_kernel"])
+        out["roofline"] = {"kernel": r["eval_kernel"], "bound": "hbm", "achieved": r["eval_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": r["eval_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                            "bytes_per_launch": r["eval_bytes"], "read_bytes": r["eval_read_bytes"],
@@ -428,6 +455,7 @@ def main():
         out["roofline_jac_hess_coord"] = {"kernel": "exa_k_jh", "achieved": r["jh_gbs"],
                                           "frac": r["jh_gbs"] / HBM_PEAK_GBS,
                                           "bytes_per_launch": r["jh_bytes"], "launch_us": r["jh_kernel_us"]}
+        out["hbm_copy_gbs"] = copy_gbs()
         if not args.no_cpu_baseline:
             log("leg: cpu baseline")
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
@@ -441,7 +469,7 @@ def main():
                       "nnz_per_s": r["nnz_per_s"], "step_separate_us": r["step_separate_us"],
                       "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"],
                       "callbacks_us": r["callbacks_us"],
-                      "roofline_eval": {"kernel": "exa_k_multi", "achieved": r["eval_gbs"],
+                      "roofline_eval": {"kernel": r["eval_kernel"], "achieved": r["eval_gbs"],
                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                         "frac": r["eval_gbs"] / HBM_PEAK_GBS,
                                         "bytes_per_launch": r["eval_bytes"], "launch_us": r["eval_us"]},

@@ -128,7 +128,12 @@ typedef struct exa_options {
     int32_t fuse;      /* without autotune: 1 evaluates patterns declared over
                           the same data arrays in one lane (shared loads),
                           0 evaluates them separately                          */
-    int32_t reserved[3];
+    int32_t eval_per_mode; /* 1: exa_eval runs one tile per callback and point
+                          (as the single callbacks do); 0: it may also run
+                          units that evaluate all selected callbacks of a point
+                          from one pass over its loads (chosen by autotune,
+                          used by default without it); results are the same  */
+    int32_t reserved[2];
 } exa_options;
 
 /* ---- Library ------------------------------------------------------------ */
@@ -270,8 +275,8 @@ typedef struct exa_eval_args {
 } exa_eval_args;
 exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream);
 /* The schedule of exa_eval for a mask: out4 = workgroup size, points per
- * lane, fused (0/1), number of tiles.  EXA_ESTATE until the mask's first
- * exa_eval call. */
+ * lane, fused (bit 0) | one pass per point for all callbacks (bit 1), number
+ * of tiles.  EXA_ESTATE until the mask's first exa_eval call. */
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 /* Algorithmic traffic of exa_eval for a mask under its current schedule
  * (the model's default before the mask's first call), host array out4:

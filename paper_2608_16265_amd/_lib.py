@@ -39,7 +39,8 @@ class PatternDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
-                ("autotune", C.c_int32), ("fuse", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("autotune", C.c_int32), ("fuse", C.c_int32), ("eval_per_mode", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class BatchOptions(C.Structure):

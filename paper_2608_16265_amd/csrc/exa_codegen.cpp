@@ -81,6 +81,10 @@ struct Em {
         }
         return d;
     }
+    // a named value several jobs use (a row weight) is defined once
+    std::string named_once(const std::string& type, const std::string& name, const std::string& e) {
+        return byname.count(name) ? name : named(type, name, e);
+    }
     std::string named(const std::string& type, const std::string& name, const std::string& e) {
         Stmt s{type, name, e, deps_of(e), false};
         st.push_back(s);
@@ -570,9 +574,12 @@ int out_step(const Pattern& P, int mode) {
 bool scalar_mode(int mode) { return mode == M_OBJ || mode == M_CONS || mode == M_JPROD; }
 
 const char* mode_name(int m) {
-    static const char* n[] = {"obj", "cons", "grad", "jac", "hess", "jprod", "jtprod", "hprod", "adj", "jh"};
+    static const char* n[] = {"obj", "cons", "grad", "jac", "hess", "jprod", "jtprod", "hprod", "adj", "jh",
+                              "sfull", "sipm"};
     return n[m];
 }
+
+bool multi_unit(int mode) { return multi_unit_mode(mode); }
 
 // Staging through LDS is used while a workgroup's slice fits in this many
 // doubles (64 KiB at the largest workgroup); wider patterns store directly.
@@ -603,15 +610,19 @@ struct Job {
     std::string out;
 };
 
+// Call record a job of `mode` reads and writes inside a unit of `umode`.
+std::string call_of(int umode, int mode) { return multi_unit(umode) ? "C.c[" + std::to_string(mode) + "]" : "C"; }
+
 std::vector<Job> jobs_of(const Model& M, int mode, const Unit& U) {
     std::vector<Job> j;
     for (int p : U.members) {
-        if (mode != M_JH) {
+        if (mode != M_JH && !multi_unit(mode)) {
             j.push_back({p, mode, "C.out0"});
             continue;
         }
-        if (pattern_in_mode(M.pats[p], M_JAC)) j.push_back({p, M_JAC, "C.out0"});
-        if (pattern_in_mode(M.pats[p], M_HESS)) j.push_back({p, M_HESS, "C.out1"});
+        for (int m : job_modes(mode))
+            if (pattern_in_mode(M.pats[p], m))
+                j.push_back({p, m, mode == M_JH ? (m == M_JAC ? "C.out0" : "C.out1") : call_of(mode, m) + ".out0"});
     }
     return j;
 }
@@ -671,22 +682,33 @@ std::string aug_fn(const Model& M, int mode, int a, int& ntmp, UnitLive& live) {
     return os.str();
 }
 
-// Generates the tile function of one unit; fills `live`.
+// Generates the tile function of one unit; fills `live`.  A plain unit runs
+// one callback's job per member (two for JH); a multi unit (M_SFULL,
+// M_SIPM) runs every job of its modes per member from one set of loads and
+// sweeps, each job with its own mode's call record of the ExaMulti.
 std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLive& live) {
     const Group& G = M.groups[U.group];
     const int m0 = G.members[0];  // owner of the shared column pointers
+    const bool multi = multi_unit(mode);
+    const std::vector<int>& jm = job_modes(mode);
+    auto has = [&](int m) { return std::find(jm.begin(), jm.end(), m) != jm.end(); };
+    auto call = [&](int m) { return call_of(mode, m); };
     std::ostringstream os;
     const std::string fn = std::string("unit_") + mode_name(mode) + "_" + std::to_string(U.code);
-    const bool inline_stores = !scalar_mode(mode);  // modes with staged per-point outputs
-    os << "__device__ __forceinline__ void " << fn
-       << "(const ExaCall& C, const ExaInstDev& I, const ExaTile& T, double* lds) {\n";
+    os << "__device__ __forceinline__ void " << fn << "(const " << (multi ? "ExaMulti" : "ExaCall")
+       << "& C, const ExaInstDev& I, const ExaTile& T, double* lds) {\n";
     os << "    const ExaPatDev& P0 = I.pat[" << m0 << "];\n";
     for (int p : U.members) os << "    const ExaPatDev& P" << p << "_ = I.pat[" << p << "];\n";
-    os << "    const double* __restrict__ X = C.x + I.off[" << EXA_OFF_X << "];\n";
-    os << "    const double* __restrict__ V = C.v + I.off[" << EXA_OFF_X << "];\n";
-    os << "    const double* __restrict__ Y = C.y + I.off[" << EXA_OFF_Y << "];\n";
+    // inputs: x for every job; v seeds jprod/hprod; y weighs hess/hprod
+    // (sigma for objectives); w weighs jtprod (in a plain jtprod call it is C.y)
+    const std::string cx = multi ? call(M_JAC) : "C", cv = multi ? call(M_JPROD) : "C",
+                      cy = multi ? call(M_HESS) : "C", cw = multi ? call(M_JTPROD) : "C";
+    os << "    const double* __restrict__ X = " << cx << ".x + I.off[" << EXA_OFF_X << "];\n";
+    os << "    const double* __restrict__ V = " << cv << ".v + I.off[" << EXA_OFF_X << "];\n";
+    os << "    const double* __restrict__ Y = " << cy << ".y + I.off[" << EXA_OFF_Y << "];\n";
+    os << "    const double* __restrict__ W = " << cw << ".y + I.off[" << EXA_OFF_Y << "];\n";
     os << "    const double* __restrict__ TH = I.theta;\n";
-    os << "    (void)X; (void)V; (void)Y; (void)TH; (void)P0;\n";
+    os << "    (void)X; (void)V; (void)Y; (void)W; (void)TH; (void)P0;\n";
     os << "    const int nthr = (int)blockDim.x;\n";
     os << "    const long long kend = T.start + T.count;\n";
     if (mode == M_OBJ) {
@@ -707,8 +729,9 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         os << "        const long long k = kr < kend ? kr : kend - 1;\n";
     }
     const std::vector<Job> jobs = jobs_of(M, mode, U);
+    const bool several = jm.size() > 1;
     auto oname = [&](const Job& j) {
-        return (scalar_mode(j.mode) ? "r" : "o") + std::to_string(j.p) + (mode == M_JH ? std::string("_") + mode_name(j.mode) : "");
+        return (scalar_mode(j.mode) ? "r" : "o") + std::to_string(j.p) + (several ? std::string("_") + mode_name(j.mode) : "");
     };
     for (const Job& j : jobs) {
         if (scalar_mode(j.mode))
@@ -718,7 +741,12 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     }
     os << (mode != M_OBJ ? "        {\n" : "        if (k < kend) {\n");
 
-    // ---- statements: loads (all candidates), then every member's sweeps
+    // ---- statements: loads (all candidates), then every job's sweeps
+    bool weighs = false, seeds = false;
+    for (int m : jm) {
+        weighs |= needs_weight(m);
+        seeds |= m == M_JPROD || m == M_HPROD || m == M_ADJ;
+    }
     Em e(ntmp);
     std::set<int> icols, fcols;
     for (int p : U.members) {
@@ -726,7 +754,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         for (auto& r : P.vslots) if (r.col >= 0) icols.insert(r.col);
         for (auto& r : P.pslots) if (r.col >= 0) icols.insert(r.col);
         for (auto& q : P.nodes) if (q.op == EXA_OP_DATA) fcols.insert(q.col);
-        if ((needs_weight(mode) || mode == M_JH) && P.kind == EXA_AUG) icols.insert(P.row_icol);
+        if (weighs && P.kind == EXA_AUG) icols.insert(P.row_icol);
     }
     for (int c : icols) e.named("long long", "ic" + std::to_string(c), "P0.ic[" + std::to_string(c) + "][k]");
     for (int c : fcols) e.named("double", "fc" + std::to_string(c), "P0.fc[" + std::to_string(c) + "][k]");
@@ -735,7 +763,6 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         for (int r : M.pats[p].vg) vrefs.insert(r);
         for (int r : M.pats[p].pg) prefs.insert(r);
     }
-    const bool seeds = mode == M_JPROD || mode == M_HPROD || mode == M_ADJ;
     for (int r : vrefs) {
         const RefKey& k = G.vrefs[r];
         const std::pair<int, int> src = G.vsrc[r];
@@ -759,6 +786,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     for (const Job& j : jobs) {
         const int p = j.p;
         const Pattern& P = M.pats[p];
+        const std::string pd = "P" + std::to_string(p) + "_";
         Names nm;
         for (int s = 0; s < P.o1step(); ++s) {
             nm.x.push_back("x" + std::to_string(P.vg[s]));
@@ -767,28 +795,30 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         }
         for (int s = 0; s < P.pstep(); ++s) nm.p.push_back("p" + std::to_string(P.pg[s]));
         if (needs_weight(j.mode)) {
-            const std::string pd = "P" + std::to_string(p) + "_";
+            // row weight: w for J^T w, y (sigma for objectives) otherwise
+            const bool byw = j.mode == M_JTPROD;
+            const std::string src = byw ? "W" : "Y";
             std::string w;
             if (P.kind == EXA_OBJ)
-                w = "C.sigma";
+                w = cy + ".sigma";
             else if (P.kind == EXA_CON)
-                w = "Y[" + pd + ".o0 + k]";
+                w = src + "[" + pd + ".o0 + k]";
             else
-                w = "Y[" + pd + ".tgt0 + ic" + std::to_string(P.row_icol) + " + " + pd + ".row_off]";
-            nm.wgt = e.named("double", "w" + std::to_string(p), w);
+                w = src + "[" + pd + ".tgt0 + ic" + std::to_string(P.row_icol) + " + " + pd + ".row_off]";
+            nm.wgt = e.named_once("double", (byw ? "ww" : "wy") + std::to_string(p), w);
         }
         PatternCg cg(P, j.mode, e, nm);
         cg.body(oname(j));
-        if (mode == M_GRAD)
+        if (j.mode == M_GRAD)
             // every variable has at most one contribution: write g directly
             for (int s = 0; s < P.o1step(); ++s)
-                e.out("if (C.direct && kr < kend) C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
+                e.out("if (" + call(M_GRAD) + ".direct && kr < kend) " + call(M_GRAD) + ".out0[I.off[" +
+                          std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
                       oname(j) + "[" + std::to_string(s) + "]");
-        if (inline_stores) {
+        if (!scalar_mode(j.mode)) {
             // this job's outputs leave registers as soon as they are complete
-            const std::string pd = "P" + std::to_string(j.p) + "_";
             const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
-            std::string line = mode == M_GRAD ? "if (!C.direct) " : "";
+            std::string line = j.mode == M_GRAD ? "if (!" + call(M_GRAD) + ".direct) " : "";
             if (staged(P, j.mode))
                 line += "exa_store<" + std::to_string(out_step(P, j.mode)) + ", " + (final_out ? "true" : "false") + ">(";
             else
@@ -798,51 +828,56 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         }
     }
     const std::set<std::string> names = e.emit(os, "            ");
-    if (mode == M_CONS || mode == M_JPROD) {
-        // Base rows pull the augmentation terms that add to them, in
-        // declaration order of the augmentations, points ascending.  The
-        // first round of up to R terms of every augmentation is evaluated
-        // before any is added, so that their chains of dependent loads (row
-        // bounds, term index, data, x) overlap; the additions keep the order.
-        struct Pull {
-            std::string out;
-            int a, R;
-        };
-        std::vector<Pull> pulls;
-        for (const Job& j : jobs) {
-            const Pattern& P = M.pats[j.p];
-            if (P.kind != EXA_CON) continue;
-            for (int a : P.augs) {
-                if (M.pats[a].ndata == 0) continue;
-                const size_t nn = M.pats[a].nodes.size();
-                pulls.push_back({oname(j), a, nn <= 16 ? 4 : nn <= 64 ? 2 : 1});
-            }
+
+    // ---- augmentation pulls of the scalar jobs (cons values, jprod tangents)
+    // Base rows pull the augmentation terms that add to them, in declaration
+    // order of the augmentations, points ascending.  The first round of up to
+    // R terms of every augmentation is evaluated before any is added, so that
+    // their chains of dependent loads (row bounds, term index, data, x)
+    // overlap; the additions keep the order.
+    struct Pull {
+        std::string out;
+        int a, R, mode;
+    };
+    std::vector<Pull> pulls;
+    for (const Job& j : jobs) {
+        const Pattern& P = M.pats[j.p];
+        if ((j.mode != M_CONS && j.mode != M_JPROD) || P.kind != EXA_CON) continue;
+        for (int a : P.augs) {
+            if (M.pats[a].ndata == 0) continue;
+            const size_t nn = M.pats[a].nodes.size();
+            pulls.push_back({oname(j), a, nn <= 16 ? 4 : nn <= 64 ? 2 : 1, j.mode});
         }
-        // at most kPullTerms terms in flight per lane, shared by the pulls,
-        // so that the round does not cost occupancy
-        constexpr int kPullTerms = 8;
-        const int share = pulls.empty() ? 1 : std::max(1, kPullTerms / (int)pulls.size());
-        for (Pull& q : pulls) q.R = std::min(q.R, share);
-        const std::string fn = std::string("aug_") + mode_name(mode) + "_";
-        for (const Pull& q : pulls) {
-            const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
-            os << "            const int ab" << a << " = " << pa << ".rptr[k], ae" << a << " = " << pa
-               << ".rptr[k + 1];\n";
-        }
-        for (const Pull& q : pulls) {
-            const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
-            for (int i = 0; i < q.R; ++i)
-                os << "            const double aq" << a << "_" << i << " = " << fn << a << "(C, I, (long long)" << pa
-                   << ".ridx[exa_term(ab" << a << " + " << i << ", ae" << a << ")]);\n";
-        }
-        for (const Pull& q : pulls) {
-            const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
-            for (int i = 0; i < q.R; ++i)
-                os << "            if (ab" << a << " + " << i << " < ae" << a << ") " << q.out << " += aq" << a << "_" << i
-                   << ";\n";
-            os << "            for (int j = ab" << a << " + " << q.R << "; j < ae" << a << "; ++j) " << q.out
-               << " += " << fn << a << "(C, I, (long long)" << pa << ".ridx[j]);\n";
-        }
+    }
+    // at most kPullTerms terms in flight per lane, shared by the pulls, so
+    // that the round does not cost occupancy
+    constexpr int kPullTerms = 8;
+    const int share = pulls.empty() ? 1 : std::max(1, kPullTerms / (int)pulls.size());
+    for (Pull& q : pulls) q.R = std::min(q.R, share);
+    std::set<int> bounds;
+    for (const Pull& q : pulls) {
+        if (!bounds.insert(q.a).second) continue;
+        const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+        os << "            const int ab" << a << " = " << pa << ".rptr[k], ae" << a << " = " << pa << ".rptr[k + 1];\n";
+    }
+    auto aq = [&](const Pull& q, int i) {
+        return "aq" + std::to_string(q.a) + "_" + mode_name(q.mode) + "_" + std::to_string(i);
+    };
+    auto fn_of = [&](const Pull& q) {
+        return std::string("aug_") + mode_name(q.mode) + "_" + std::to_string(q.a) + "(" + call(q.mode) + ", I, (long long)";
+    };
+    for (const Pull& q : pulls) {
+        const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+        for (int i = 0; i < q.R; ++i)
+            os << "            const double " << aq(q, i) << " = " << fn_of(q) << pa << ".ridx[exa_term(ab" << a << " + "
+               << i << ", ae" << a << ")]);\n";
+    }
+    for (const Pull& q : pulls) {
+        const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+        for (int i = 0; i < q.R; ++i)
+            os << "            if (ab" << a << " + " << i << " < ae" << a << ") " << q.out << " += " << aq(q, i) << ";\n";
+        os << "            for (int j = ab" << a << " + " << q.R << "; j < ae" << a << "; ++j) " << q.out << " += "
+           << fn_of(q) << pa << ".ridx[j]);\n";
     }
     os << "        }\n";
 
@@ -856,34 +891,22 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     for (int r : prefs) if (names.count("p" + std::to_string(r))) live.prefs.push_back(r);
     for (int p : U.members)
         // an objective's weight is the scalar sigma, not a per-point load
-        if (M.pats[p].kind != EXA_OBJ && names.count("w" + std::to_string(p))) live.weights++;
+        if (M.pats[p].kind != EXA_OBJ)
+            for (const char* w : {"wy", "ww"})
+                if (names.count(w + std::to_string(p))) live.weights++;
     for (const Job& j : jobs) live.outputs += out_step(M.pats[j.p], j.mode);
 
-    // ---- outputs
-    switch (mode) {
-        case M_OBJ: {
-            std::string sum;
-            for (const Job& j : jobs) sum += (sum.empty() ? "" : " + ") + oname(j);
-            os << "        acc[q] += " << sum << ";\n";
-            os << "    }\n";  // virtual lanes
-            break;
-        }
-        case M_CONS:
-        case M_JPROD:
-            for (int p : U.members) {
-                const Pattern& P = M.pats[p];
-                const std::string pd = "P" + std::to_string(p) + "_";
-                if (P.kind == EXA_CON)
-                    os << "        if (kr < kend) __builtin_nontemporal_store(r" << p << ", &C.out0[I.off[" << EXA_OFF_ROWS
-                       << "] + " << pd << ".o0 + k]);\n";
-                else
-                    os << "        if (kr < kend) C.out1[I.off[" << EXA_OFF_AUG << "] + " << pd << ".o0 + k] = r" << p
-                       << ";\n";
-            }
-            break;
-        default:  // stored after each job's statements
-            break;
+    // ---- outputs that are not staged: objective sums, constraint rows
+    if (mode == M_OBJ) {
+        std::string sum;
+        for (const Job& j : jobs) sum += (sum.empty() ? "" : " + ") + oname(j);
+        os << "        acc[q] += " << sum << ";\n";
+        os << "    }\n";  // virtual lanes
     }
+    for (const Job& j : jobs)
+        if (j.mode == M_CONS || j.mode == M_JPROD)
+            os << "        if (kr < kend) __builtin_nontemporal_store(" << oname(j) << ", &" << call(j.mode) << ".out0[I.off["
+               << EXA_OFF_ROWS << "] + P" << j.p << "_.o0 + k]);\n";
     os << "    }\n";
     if (mode == M_OBJ) {
         os << "    const double tot = exa_vlane_sum(acc, lds);\n";
@@ -895,8 +918,20 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
 
 }  // namespace
 
+const std::vector<int>& job_modes(int mode) {
+    static const std::vector<int> one[M_COUNT] = {{0}, {1}, {2}, {3}, {4}, {5}, {6}, {7}, {8}, {M_JAC, M_HESS}};
+    static const std::vector<int> full = {M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_JTPROD, M_HPROD};
+    static const std::vector<int> ipm = {M_GRAD, M_CONS, M_JAC, M_HESS};
+    return mode == M_SFULL ? full : mode == M_SIPM ? ipm : one[mode];
+}
+
 bool pattern_in_mode(const Pattern& P, int mode) {
     if (P.ndata == 0) return false;
+    if (multi_unit(mode)) {
+        for (int m : job_modes(mode))
+            if (pattern_in_mode(P, m)) return true;
+        return false;
+    }
     switch (mode) {
         case M_OBJ: return P.kind == EXA_OBJ;
         case M_CONS: return P.kind == EXA_CON;
@@ -945,7 +980,11 @@ std::vector<Unit> units_for(const Model& M, int mode, bool fused) {
 }
 
 int mode_lds_doubles(const Model& M, int mode) {
-    if (mode == M_JH) return std::max(mode_lds_doubles(M, M_JAC), mode_lds_doubles(M, M_HESS));
+    if (mode == M_JH || multi_unit(mode)) {
+        int d = EXA_BLOCK_MAX;
+        for (int m : job_modes(mode)) d = std::max(d, mode_lds_doubles(M, m));
+        return d;
+    }
     int st = 1;
     for (auto& P : M.pats)
         if (pattern_in_mode(P, mode) && staged(P, mode)) st = std::max(st, out_step(P, mode));
@@ -1116,27 +1155,14 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
     // EXA_MODE_SHIFT in its code, and its case passes that mode's call (a
     // constant index, so the calls stay in kernel arguments).  One tile per
     // workgroup, remapped per XCD as in the single-callback kernels.
-    {
-        int lds = 0;
-        std::vector<std::string> cases;
-        for (int mode : multi_modes()) {
-            lds = std::max(lds, mode_lds_doubles(M, mode));
-            std::set<int> codes;
-            for (int fused = 0; fused < 2; ++fused)
-                for (auto& u : units_for(M, mode, fused != 0)) codes.insert(u.code);
-            const std::string K = "C.c[" + std::to_string(mode) + "]";
-            for (int c : codes)
-                cases.push_back("case " + std::to_string((mode << EXA_MODE_SHIFT) | c) + ": unit_" + mode_name(mode) +
-                                "_" + std::to_string(c) + "(" + K + ", " + K + ".inst[T.inst], T, lds); break;");
-        }
-        const std::string G = "C.c[" + std::to_string(M_GRAD) + "]";
-        cases.push_back("case " + std::to_string((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE) +
-                        ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) " + G +
-                        ".out0[" + G + ".inst[T.inst].off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;");
-        // every unit's tiles share this kernel's register budget: ask for at
-        // least four waves per SIMD, so that one wave of the launch fits on
-        // the chip at once
-        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ", 4) exa_k_multi(ExaMulti C) {\n";
+    // exa_k_multi runs per-callback tiles; exa_k_onepass runs multi units
+    // (every selected job of a point from one set of loads) with the
+    // objective's and the gradient's zero tiles.  Two kernels, so that each
+    // gets the register budget of its own cases.
+    auto multi_kernel = [&](const std::string& name, int lds, const std::vector<std::string>& cases, int min_waves) {
+        os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX;
+        if (min_waves) os << ", " << min_waves;
+        os << ") " << name << "(ExaMulti C) {\n";
         os << "    __shared__ double lds[" << lds << "];\n";
         os << "    (void)lds;\n";
         os << "    const long long w = (blockIdx.x % 8) * C.per_xcd + blockIdx.x / 8;\n";
@@ -1147,6 +1173,53 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
         os << "        default: break;\n";
         os << "    }\n";
         os << "}\n";
+    };
+    auto mode_cases = [&](int mode, std::vector<std::string>& cases) {
+        std::set<int> codes;
+        for (int fused = 0; fused < 2; ++fused)
+            for (auto& u : units_for(M, mode, fused != 0)) codes.insert(u.code);
+        const std::string K = "C.c[" + std::to_string(mode) + "]";
+        for (int c : codes)
+            cases.push_back("case " + std::to_string((mode << EXA_MODE_SHIFT) | c) + ": unit_" + mode_name(mode) + "_" +
+                            std::to_string(c) + "(" + K + ", " + K + ".inst[T.inst], T, lds); break;");
+    };
+    const std::string G = "C.c[" + std::to_string(M_GRAD) + "]";
+    const std::string zero_case = "case " + std::to_string((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE) +
+                                  ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) " +
+                                  G + ".out0[" + G + ".inst[T.inst].off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;";
+    {
+        int lds = 0;
+        std::vector<std::string> cases;
+        for (int mode : multi_modes()) {
+            lds = std::max(lds, mode_lds_doubles(M, mode));
+            mode_cases(mode, cases);
+        }
+        cases.push_back(zero_case);
+        // every unit's tiles share this kernel's register budget: ask for at
+        // least four waves per SIMD, so that one wave of the launch fits on
+        // the chip at once
+        multi_kernel("exa_k_multi", lds, cases, 4);
+    }
+    {
+        int lds = mode_lds_doubles(M, M_OBJ);
+        std::vector<std::string> cases;
+        for (int mode : {M_SFULL, M_SIPM}) {
+            lds = std::max(lds, mode_lds_doubles(M, mode));
+            std::map<int, Unit> all;
+            for (int fused = 0; fused < 2; ++fused)
+                for (auto& u : units_for(M, mode, fused != 0)) all[u.code] = u;
+            for (auto& kv : all) {
+                UnitLive L;
+                os << unit_tile(M, mode, kv.second, ntmp, L);
+                if (live) (*live)[{mode, kv.first}] = L;
+                cases.push_back("case " + std::to_string((mode << EXA_MODE_SHIFT) | kv.first) + ": unit_" +
+                                mode_name(mode) + "_" + std::to_string(kv.first) + "(C, C.c[" + std::to_string(M_JAC) +
+                                "].inst[T.inst], T, lds); break;");
+            }
+        }
+        mode_cases(M_OBJ, cases);
+        cases.push_back(zero_case);
+        multi_kernel("exa_k_onepass", lds, cases, 0);
     }
     return os.str();
 }

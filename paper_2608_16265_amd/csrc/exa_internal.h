@@ -121,6 +121,15 @@ enum Mode : int {
     M_COUNT = 10
 };
 static_assert(M_COUNT == 10, "ExaMulti holds one call per mode");
+// Units that run several callbacks' jobs at one point from one set of loads
+// and sweeps, used by the several-callback kernel only (their jobs take
+// inputs and outputs from the per-mode calls of an ExaMulti):
+// M_SFULL: grad, cons, jac, hess, jprod, jtprod, hprod;
+// M_SIPM:  grad, cons, jac, hess (an interior-point iterate).
+constexpr int M_SFULL = 10, M_SIPM = 11;
+inline bool multi_unit_mode(int mode) { return mode == M_SFULL || mode == M_SIPM; }
+// Component modes of a unit mode (itself for plain modes, jac + hess for JH).
+const std::vector<int>& job_modes(int mode);
 // Tiles of the several-callback kernel carry their mode above this bit of
 // the unit code (unit codes stay below 1 << EXA_MODE_SHIFT).
 #define EXA_MODE_SHIFT 12
@@ -241,6 +250,7 @@ struct Model {
     bool host_only = false;
     int block = 256, epl = 4;
     bool autotune = false, fuse = false;
+    bool eval_per_mode = false;  // exa_eval: per-callback tiles only
     std::string signature;   // hash of the simplified trees (shared code)
     // inputs each generated unit really reads, per (mode, unit code)
     std::map<std::pair<int, int>, UnitLive> live;

@@ -97,6 +97,8 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jhsep");
     if (hipModuleGetFunction(&m->fn_multi, m->mod, "exa_k_multi") != hipSuccess)
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_multi");
+    if (hipModuleGetFunction(&m->fn_onepass, m->mod, "exa_k_onepass") != hipSuccess)
+        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_onepass");
     g_mods[key] = m;
     return m;
 }
@@ -398,20 +400,47 @@ std::vector<int> eval_modes(uint32_t mask) {
     return m;
 }
 
-// Tile list of a mask: every selected mode's tiles (the objective's under
-// its fixed schedule), laid out as eight chunks that each hold an eighth of
+// Multi-unit mode that covers a mask's callbacks besides the objective in
+// one pass per point, or -1.
+int combined_mode_of(uint32_t mask) {
+    const uint32_t full = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS | EXA_EV_JPROD | EXA_EV_JTPROD |
+                          EXA_EV_HPROD;
+    const uint32_t ipm = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS;
+    if ((mask & full) == full) return M_SFULL;
+    if ((mask & ~(uint32_t)EXA_EV_OBJ) == ipm) return M_SIPM;
+    return -1;
+}
+
+// Modes whose tiles make up a mask's launch.
+std::vector<int> launch_modes(uint32_t mask, bool combined) {
+    const int cm = combined ? combined_mode_of(mask) : -1;
+    if (cm < 0) return eval_modes(mask);
+    std::vector<int> m;
+    if (mask & EXA_EV_OBJ) m.push_back(M_OBJ);
+    m.push_back(cm);
+    return m;
+}
+
+// Tile list of a mask: every launch mode's tiles (the objective's under its
+// fixed schedule), laid out as eight chunks that each hold an eighth of
 // every mode's tiles, so that the per-XCD ranges of the launch get the same
 // mix of work and contiguous point ranges.
-void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused) {
+void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, bool combined) {
     DeviceState& D = *M.dev;
     DeviceState::MultiSched& S = D.multi[mask];
+    combined = combined && combined_mode_of(mask) >= 0;
     const int64_t tp = (int64_t)block * epl;
     std::vector<std::vector<ExaTile>> per;
-    for (int mode : eval_modes(mask)) {
+    for (int mode : launch_modes(mask, combined)) {
         std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused)
                                                : make_tiles(M, mode, 0, tp, fused);
-        if (mode == M_GRAD) add_zero_tiles(M, tp, t);
         for (ExaTile& x : t) x.pat |= mode << EXA_MODE_SHIFT;
+        if (mode == M_GRAD || (multi_unit_mode(mode) && (mask & EXA_EV_GRAD))) {
+            std::vector<ExaTile> z;
+            add_zero_tiles(M, tp, z);
+            for (ExaTile& x : z) x.pat |= M_GRAD << EXA_MODE_SHIFT;
+            t.insert(t.end(), z.begin(), z.end());
+        }
         per.push_back(std::move(t));
     }
     std::vector<ExaTile> all;
@@ -423,6 +452,7 @@ void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused)
     S.block = block;
     S.epl = epl;
     S.fused = fused;
+    S.combined = combined;
 }
 
 void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
@@ -432,7 +462,8 @@ void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
     mc.ntiles = S.ntiles;
     mc.per_xcd = (S.ntiles + 7) / 8;
     void* args[] = {&mc};
-    hip_check(hipModuleLaunchKernel(M.dev->module->fn_multi, (unsigned)(8 * mc.per_xcd), 1, 1, (unsigned)S.block, 1,
+    hipFunction_t fn = S.combined ? M.dev->module->fn_onepass : M.dev->module->fn_multi;
+    hip_check(hipModuleLaunchKernel(fn, (unsigned)(8 * mc.per_xcd), 1, 1, (unsigned)S.block, 1,
                                     1, 0, s, args, nullptr),
               "hipModuleLaunchKernel");
 }
@@ -450,17 +481,20 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
             fuses.push_back(1);
             break;
         }
+    std::vector<int> combos = {0};
+    if (combined_mode_of(mask) >= 0 && !M.eval_per_mode) combos = {1, 0};
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     float best = 1e30f;
     int bb = 256, be = 1;
-    bool bf = false;
+    bool bf = false, bc = false;
     try {
+        for (int cb : combos)
         for (int f : fuses)
             for (int b : blocks)
                 for (int ep : epls) {
-                    set_multi_schedule(M, mask, b, ep, f != 0);
+                    set_multi_schedule(M, mask, b, ep, f != 0, cb != 0);
                     raw_launch_multi(M, mask, mc, s);
                     hip_check(hipEventRecord(e0, s), "hipEventRecord");
                     for (int r = 0; r < 3; ++r) raw_launch_multi(M, mask, mc, s);
@@ -473,6 +507,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
                         bb = b;
                         be = ep;
                         bf = f != 0;
+                        bc = cb != 0;
                     }
                 }
     } catch (...) {
@@ -482,7 +517,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    set_multi_schedule(M, mask, bb, be, bf);
+    set_multi_schedule(M, mask, bb, be, bf, bc);
 }
 
 }  // namespace
@@ -517,7 +552,10 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
         for (int r : L.prefs) mark(G.prefs[r], ts);
     }
     // augmentation terms pulled by their base rows (cons, jprod)
-    for (int mode : modes) {
+    std::vector<int> pulled;
+    for (int m : modes)
+        for (int jm : job_modes(m)) pulled.push_back(jm);
+    for (int mode : pulled) {
         if (mode != M_CONS && mode != M_JPROD) continue;
         for (size_t a = 0; a < M.pats.size(); ++a) {
             const Pattern& P = M.pats[a];
@@ -650,6 +688,7 @@ exa_status exa_create(const exa_pattern_desc* pats, int32_t npats, int64_t nvar,
             if (opt->epl) M.epl = opt->epl;
             M.autotune = opt->autotune != 0;
             M.fuse = opt->fuse != 0;
+            M.eval_per_mode = opt->eval_per_mode != 0;
         }
         if (M.block != 64 && M.block != 128 && M.block != 256)
             fail(EXA_EINVAL, "block must be 64, 128 or 256");
@@ -944,9 +983,22 @@ exa_status exa_eval(exa_model* m, const exa_eval_args* a, exa_stream_t stream) {
                 default: break;
             }
         }
+        // multi units read the Jacobian and Hessian jobs' own records
+        if ((mask & EXA_EV_JAC) && (mask & EXA_EV_HESS)) {
+            ExaCall& cj = mc.c[M_JAC];
+            cj.inst = D.inst;
+            cj.x = a->x;
+            cj.out0 = a->jac;
+            ExaCall& ch = mc.c[M_HESS];
+            ch.inst = D.inst;
+            ch.x = a->x;
+            ch.y = a->y;
+            ch.sigma = a->obj_weight;
+            ch.out0 = a->hess;
+        }
         auto it = D.multi.find(mask);
         if (it == D.multi.end() || !it->second.tuned) {
-            set_multi_schedule(M, mask, M.block, M.epl, M.fuse);
+            set_multi_schedule(M, mask, M.block, M.epl, M.fuse, !M.eval_per_mode);
             if (M.autotune) tune_multi(M, mask, mc, s);
             D.multi[mask].tuned = true;
         }
@@ -1040,13 +1092,16 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        bool fused = M.fuse;
+        bool fused = M.fuse, combined = true;
         if (M.dev) {
             auto it = M.dev->multi.find(mask);
-            if (it != M.dev->multi.end()) fused = it->second.fused;
+            if (it != M.dev->multi.end()) {
+                fused = it->second.fused;
+                combined = it->second.combined;
+            }
         }
         int64_t rd = 0, wr = 0;
-        kernel_bytes(M, eval_modes(mask), fused, rd, wr);
+        kernel_bytes(M, launch_modes(mask, combined), fused, rd, wr);
         out4[0] = rd;
         out4[1] = wr;
         // reduction launch: maps (int32 when every position fits), buffer
@@ -1084,7 +1139,7 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
         if (it == m->impl.dev->multi.end()) fail(EXA_ESTATE, "no exa_eval call with this mask yet");
         out4[0] = it->second.block;
         out4[1] = it->second.epl;
-        out4[2] = it->second.fused ? 1 : 0;
+        out4[2] = (it->second.fused ? 1 : 0) | (it->second.combined ? 2 : 0);
         out4[3] = it->second.ntiles;
     });
 }

@@ -93,13 +93,14 @@ class ExaModel:
     """A compiled model on the current HIP device (Sec. 3.2 ExaModel)."""
 
     def __init__(self, model, *, host_only: bool = False, block: int = 256, epl: int = 4,
-                 autotune: bool = False, fuse: bool = False):
+                 autotune: bool = False, fuse: bool = False, eval_per_mode: bool = False):
         self.description = model
         desc = _Descriptors(model)
         xl = np.ascontiguousarray(model.xl, dtype=np.float64)
         xu = np.ascontiguousarray(model.xu, dtype=np.float64)
         th = np.ascontiguousarray(model.theta, dtype=np.float64)
-        opt = Options(1 if host_only else 0, block, epl, 1 if autotune else 0, 1 if fuse else 0)
+        opt = Options(1 if host_only else 0, block, epl, 1 if autotune else 0, 1 if fuse else 0,
+                      1 if eval_per_mode else 0)
         h = C.c_void_p()
         check(LIB.exa_create(desc.arr, desc.n, model.nvar, _ptr(xl, C.c_double), _ptr(xu, C.c_double),
                              model.ntheta, _ptr(th, C.c_double) if th.size else None,
@@ -324,7 +325,8 @@ class ExaModel:
         call with that set)."""
         out = np.zeros(4, dtype=np.int64)
         check(LIB.exa_eval_schedule(self._h, self._eval_mask(callbacks), _ptr(out, C.c_int64)))
-        return dict(block=int(out[0]), points_per_lane=int(out[1]), fused=int(out[2]), tiles=int(out[3]))
+        return dict(block=int(out[0]), points_per_lane=int(out[1]), fused=int(out[2]) & 1,
+                    one_pass=(int(out[2]) >> 1) & 1, tiles=int(out[3]))
 
     @staticmethod
     def _eval_mask(callbacks) -> int:

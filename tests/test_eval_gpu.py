@@ -55,13 +55,15 @@ def _nan_like(a):
     return torch.full((a.size,), float("nan"), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.mark.parametrize("autotune", [False, True])
+@pytest.mark.parametrize("autotune,per_mode", [(False, False), (False, True), (True, False)])
 @pytest.mark.parametrize("name", list(CASES))
-def test_eval_is_bitwise_equal_to_single_callbacks(name, autotune):
+def test_eval_is_bitwise_equal_to_single_callbacks(name, autotune, per_mode):
+    """Per-callback tiles and one-pass units (every selected callback of a
+    point from one set of loads) give the single callbacks' bits."""
     _need_gpu()
     from paper_2608_16265_amd import ExaModel
     w = CASES[name]()
-    em = ExaModel(w.model, autotune=autotune)
+    em = ExaModel(w.model, autotune=autotune, eval_per_mode=per_mode)
     X, Y, sig, V, W = _inputs(w, em)
     ref = _singles(em, X, Y, sig, V, W)
     for mask in MASKS:
@@ -70,6 +72,9 @@ def test_eval_is_bitwise_equal_to_single_callbacks(name, autotune):
         for k, t in outs.items():
             got = host(t)
             assert np.array_equal(got, ref[k]), f"{name} {mask}: {k} differs from its single callback"
+        if not autotune:
+            one_pass = mask in (ALL, ("obj", "grad", "cons", "jac", "hess"))
+            assert em.eval_schedule(mask)["one_pass"] == (one_pass and not per_mode), mask
 
 
 def test_bound_eval_follows_in_place_updates():
