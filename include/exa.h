@@ -18,8 +18,10 @@
  *     torch CUDA tensor's data_ptr()); "host" pointers are ordinary memory.
  *   - Callbacks are in place (Sec. 2.1.3): results are written into
  *     caller-owned arrays.  They are asynchronous on the given stream
- *     (exa_stream_t is a hipStream_t; NULL is the null stream) and never
- *     synchronize the device.
+ *     (exa_stream_t is a hipStream_t; NULL is the null stream) and do not
+ *     synchronize, except the first call of a callback (or of an exa_eval
+ *     mask) on a model with autotune on, which times candidate schedules on
+ *     that stream and waits for them.
  *   - Every call returns an exa_status; on failure nothing has been written
  *     to the outputs that the caller could mistake for a result only if the
  *     failure is reported before launch (argument checks); a failure of the
@@ -28,6 +30,9 @@
  *     A failed call leaves the model valid.
  *   - Concurrent callbacks on ONE model from different streams race on the
  *     model's internal work buffers; serialize them (one stream per model).
+ *     Calls on one model from several host threads must not overlap either
+ *     (a model builds its schedules at first use); different models are
+ *     independent.
  */
 #ifndef EXA_H
 #define EXA_H
@@ -356,7 +361,8 @@ typedef struct exa_batch_options {
     int32_t autotune;  /* 1: time the candidate schedules and keep the fastest */
     int32_t block;     /* fixed schedule when autotune == 0 (0: default)       */
     int32_t epl;
-    int32_t grid;      /* persistent workgroups (0: chosen by the library)     */
+    int32_t grid;      /* persistent workgroups; -1: one workgroup per tile
+                          (not persistent); 0: chosen by the library          */
     int32_t use_graph; /* 1: replay the launch from a HIP graph                */
     int32_t fuse;      /* 1: patterns over the same data arrays share a lane   */
     int32_t xcd_aware; /* 1: instances are split over the 8 XCDs by cost and
@@ -384,7 +390,8 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x_cat, cons
  * over the instances (see exa_kernel_bytes; an instance's x entries count once
  * for the Jacobian and the Hessian together). */
 exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes);
-/* The schedule in use: out6 = block, points per lane, grid, tiles (both
+/* The schedule in use: out6 = block, points per lane, grid (-1: one
+ * workgroup per tile), tiles (both
  * callbacks), the autotuner's best time in nanoseconds (0 if not tuned), and
  * 1 when Jacobian and Hessian are evaluated in one pass per data point. */
 exa_status exa_batch_schedule(const exa_batch* b, int64_t* out6);

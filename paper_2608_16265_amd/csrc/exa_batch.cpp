@@ -42,7 +42,8 @@ struct exa_batch {
     ExaTile* tiles[4] = {};
     long long* xcd_ranges[4] = {};
     int64_t ntiles[4] = {};
-    int tiles_epl = -1;
+    int64_t per_xcd[4] = {};               // tiles per XCD range of the list
+    int tiles_epl = -1, tiles_block = -1;
     bool tiles_combined = true;
     // graph for the last call signature
     hipGraph_t graph = nullptr;
@@ -52,12 +53,12 @@ struct exa_batch {
         uint32_t mask;
         const void *x, *y, *j, *h;
         double sigma;
-        int epl;
+        int epl, block;
         int64_t grid;
         bool combined;
         bool operator==(const Key& o) const {
             return mask == o.mask && x == o.x && y == o.y && j == o.j && h == o.h && sigma == o.sigma &&
-                   epl == o.epl && grid == o.grid && combined == o.combined;
+                   epl == o.epl && block == o.block && grid == o.grid && combined == o.combined;
         }
     } key{};
     bool have_graph = false;
@@ -88,7 +89,7 @@ std::vector<std::pair<int, int>> mask_modes(uint32_t mask, bool combined) {
 }
 
 void build_tiles(exa_batch& b, int epl, bool combined) {
-    if (b.tiles_epl == epl && b.tiles_combined == combined) return;
+    if (b.tiles_epl == epl && b.tiles_block == b.block && b.tiles_combined == combined) return;
     const int64_t tp = (int64_t)b.block * epl;
     for (int m = 1; m <= 3; ++m) {
         // per instance: its tiles and their total cost
@@ -127,12 +128,26 @@ void build_tiles(exa_batch& b, int epl, bool combined) {
                 bins[j].push_back(i);
                 load[j] += cost[i];
             }
+            // every bin padded with no-op tiles to the longest, so that bin j
+            // is exactly tiles [j * per_xcd, (j + 1) * per_xcd): the XCD
+            // ranges of both the persistent walk and a one-tile-per-workgroup
+            // launch
+            int64_t longest = 0;
+            for (int j = 0; j < 8; ++j) {
+                int64_t n = 0;
+                for (int i : bins[j]) n += (int64_t)per[i].size();
+                longest = std::max(longest, n);
+            }
             for (int j = 0; j < 8; ++j) {
                 range[j] = (long long)v.size();
                 for (int i : bins[j])
                     for (auto& e : per[i]) v.push_back(e.second);
+                ExaTile pad{};
+                pad.pat = EXA_PAD_TILE;
+                while ((int64_t)v.size() < (j + 1) * longest) v.push_back(pad);
             }
             range[8] = (long long)v.size();
+            b.per_xcd[m] = longest;
         } else {
             // all tiles, largest first, so the grid-stride walk of the
             // persistent grid approximates longest-processing-time-first
@@ -141,6 +156,7 @@ void build_tiles(exa_batch& b, int epl, bool combined) {
             std::stable_sort(all.begin(), all.end(),
                              [](const auto& a, const auto& c) { return a.first > c.first; });
             for (auto& e : all) v.push_back(e.second);
+            b.per_xcd[m] = ((int64_t)v.size() + 7) / 8;
         }
         for (size_t i = 0; i < v.size(); ++i) v[i].slot = (int64_t)i;
         b.mem.release(b.tiles[m]);
@@ -151,6 +167,7 @@ void build_tiles(exa_batch& b, int epl, bool combined) {
             b.xcd_aware ? (long long*)b.mem.upload(range.data(), range.size() * sizeof(long long)) : nullptr;
     }
     b.tiles_epl = epl;
+    b.tiles_block = b.block;
     b.tiles_combined = combined;
 }
 
@@ -166,8 +183,9 @@ void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, doubl
     c.x = x;
     c.y = y;
     c.sigma = sigma;
-    c.persistent = 1;
-    c.xcd_range = b.xcd_ranges[mask];
+    c.persistent = b.grid < 0 ? 0 : 1;
+    c.xcd_range = b.grid < 0 ? nullptr : b.xcd_ranges[mask];
+    c.per_xcd = b.per_xcd[mask];
     hipFunction_t fn;
     if (mask == 1) {
         fn = b.module->fn[M_JAC];
@@ -180,8 +198,14 @@ void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, doubl
         c.out0 = j;
         c.out1 = h;
     }
-    int64_t grid = std::max<int64_t>(8, std::min<int64_t>(b.grid, nt));
-    grid = (grid + 7) / 8 * 8;  // a multiple of 8 (one share per XCD)
+    // b.grid < 0: one workgroup per tile (workgroup w takes tile
+    // (w % 8) * per_xcd + w / 8); else a persistent grid, a multiple of 8
+    // (one share per XCD)
+    int64_t grid = 8 * b.per_xcd[mask];
+    if (b.grid >= 0) {
+        grid = std::max<int64_t>(8, std::min<int64_t>(b.grid, nt));
+        grid = (grid + 7) / 8 * 8;
+    }
     void* args[] = {&c};
     hip_check(hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)b.block, 1, 1, 0, s, args, nullptr),
               "hipModuleLaunchKernel");
@@ -189,20 +213,23 @@ void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, doubl
 
 void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j, double* h,
           hipStream_t s) {
+    const int blocks[] = {64, 128, 256};
     const int epls[] = {1, 2, 4, 8, 16};
-    const int64_t grids[] = {b.cus * 2, b.cus * 4, b.cus * 8, b.cus * 16};
+    const int64_t grids[] = {-1, b.cus * 2, b.cus * 4, b.cus * 8, b.cus * 16};
     std::vector<int> combos = {1};
     if (mask == 3) combos.push_back(0);
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     float best = 1e30f;
-    int best_epl = b.epl;
+    int best_epl = b.epl, best_block = b.block;
     int64_t best_grid = b.grid;
     bool best_comb = b.combined;
     try {
+        for (int bk : blocks)
         for (int comb : combos)
             for (int epl : epls) {
+                b.block = bk;
                 build_tiles(b, epl, comb != 0);
                 for (int64_t g : grids) {
                     b.grid = g;
@@ -218,6 +245,7 @@ void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double 
                     if (ms < best) {
                         best = ms;
                         best_epl = epl;
+                        best_block = bk;
                         best_grid = g;
                         best_comb = comb != 0;
                     }
@@ -231,6 +259,7 @@ void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b.epl = best_epl;
+    b.block = best_block;
     b.grid = best_grid;
     b.combined = best_comb;
     b.tuned_ns = (int64_t)(best * 1e6);
@@ -293,7 +322,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         hipDeviceProp_t prop;
         hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
         b->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-        if (b->grid <= 0) b->grid = (int64_t)b->cus * 8;
+        if (b->grid == 0 || b->grid < -1) b->grid = (int64_t)b->cus * 8;
         b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
 
         std::vector<ExaInstDev> inst(B);
@@ -380,7 +409,7 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x, const do
             launch(*b, mask, x, y, sigma, jac, hess, s);
             return;
         }
-        exa_batch::Key k{mask, x, y, jac, hess, sigma, b->epl, b->grid, b->combined};
+        exa_batch::Key k{mask, x, y, jac, hess, sigma, b->epl, b->block, b->grid, b->combined};
         if (!b->have_graph || !(k == b->key)) {
             if (b->exec) (void)hipGraphExecDestroy(b->exec);
             if (b->graph) (void)hipGraphDestroy(b->graph);

@@ -45,6 +45,7 @@ void set_last_error(const std::string& msg);
 #define EXA_MAX_REFS 48
 // Tile code of a zero-fill tile (entries of g no objective term touches).
 #define EXA_ZERO_TILE 1023
+#define EXA_PAD_TILE 4095  // a tile that matches no unit: does nothing
 
 #define EXA_DEVICE_STRUCTS                                                       \
     struct ExaPatDev {                                                           \

@@ -20,7 +20,9 @@ def _gpu():
 @pytest.mark.parametrize("autotune,epl,grid,graph,fuse,xcd,sep", [
     (False, 1, 64, True, False, False, True), (False, 8, 0, False, True, False, False),
     (False, 2, 16, True, False, True, False), (False, 3, 24, True, True, True, True),
-    (True, 4, 0, True, True, True, False)])
+    (True, 4, 0, True, True, True, False),
+    # one workgroup per tile: padded XCD bins, and the plain tile order
+    (False, 1, -1, True, True, True, False), (False, 2, -1, False, False, False, True)])
 def test_batch_bitwise_equal_to_plain(autotune, epl, grid, graph, fuse, xcd, sep):
     _gpu()
     from paper_2608_16265_amd import ExaModel
