@@ -207,3 +207,14 @@ def test_eval_bytes_accounting():
     assert b["eval_write"] == 8 + 8 * 2 * n * n
     with pytest.raises(Exception):
         em.eval_bytes(())
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py refuses several GPUs with a message (no multi-GPU path)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                                     "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
