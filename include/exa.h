@@ -302,6 +302,15 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4);
 exa_status exa_eval_timing(exa_model* m, int32_t enable);
 exa_status exa_eval_timing_read(exa_model* m, double* out4);
 
+/* Device-to-device copy of `bytes` bytes with 16-byte non-temporal loads
+ * and stores (one vector per lane; a byte-wise launch for the tail or for
+ * pointers not 16-byte aligned), asynchronous on `stream`.  A measurement
+ * utility: the practical streaming bandwidth of the device, against which
+ * the evaluation kernels' HBM rates can be read.  src and dst are device
+ * arrays that must not overlap.  Errors: EXA_EINVAL for a NULL pointer with
+ * bytes > 0 or bytes < 0. */
+exa_status exa_device_copy(void* dst, const void* src, int64_t bytes, exa_stream_t stream);
+
 /* Adjoint with respect to the parameters (extension of the parametric NLP of
  * eq. nlp): theta_bar = (d grad_x L / d theta)^T w with
  * grad_x L = sigma grad f + J^T y, i.e. for every pattern instance

@@ -6,6 +6,7 @@
 
 hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_t s);
 hipError_t exa_launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 // One segment-sum job: out[s] = sum of buf[idx[j]], j in [ptr[s], ptr[s+1]).
 // With lanes == nullptr one lane sums one segment in ascending j.  With

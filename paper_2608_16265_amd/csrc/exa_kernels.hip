@@ -133,6 +133,20 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
     if (R.part && b == 0) sum_body(R.part, R.npart, R.f, lds);
 }
 
+// Streaming copy with 16-byte non-temporal loads and stores, one vector per
+// lane: the access pattern of the evaluation kernels' final outputs, used to
+// measure the device's practical bandwidth.
+typedef double exa_d2 __attribute__((ext_vector_type(2)));
+__global__ void __launch_bounds__(256) k_copy16(const exa_d2* __restrict__ src, exa_d2* __restrict__ dst, int64_t n2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n2) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
+}
+
+__global__ void __launch_bounds__(256) k_copy1(const char* __restrict__ src, char* __restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, int64_t n, double v) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
@@ -156,6 +170,19 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
     const int64_t per_xcd = (blocks + 7) / 8;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);
+    return hipGetLastError();
+}
+
+hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return hipSuccess;
+    const bool aligned = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
+    const int64_t n2 = aligned ? bytes / 16 : 0, tail = bytes - 16 * n2;
+    if (n2 > 0)
+        hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, (const exa_d2*)src,
+                           (exa_d2*)dst, n2);
+    if (tail > 0)
+        hipLaunchKernelGGL(k_copy1, dim3((unsigned)((tail + 255) / 256)), dim3(256), 0, s,
+                           (const char*)src + 16 * n2, (char*)dst + 16 * n2, tail);
     return hipGetLastError();
 }
 

@@ -1034,6 +1034,14 @@ exa_status exa_eval(exa_model* m, const exa_eval_args* a, exa_stream_t stream) {
     });
 }
 
+exa_status exa_device_copy(void* dst, const void* src, int64_t bytes, exa_stream_t stream) {
+    return guard([&] {
+        if (bytes < 0) fail(EXA_EINVAL, "negative byte count");
+        if (bytes > 0 && (!dst || !src)) fail(EXA_EINVAL, "null pointer");
+        hip_check(exa_launch_copy(src, dst, bytes, (hipStream_t)stream), "device copy");
+    });
+}
+
 exa_status exa_eval_timing(exa_model* m, int32_t enable) {
     return guard([&] {
         Model& M = live(m);

@@ -222,3 +222,21 @@ def test_callbacks_run_on_the_current_stream():
     assert np.array_equal(host(out), ref)
     # the default stream's handle is 0 (ctypes shows it as None)
     assert (_stream(X.get_device()).value or 0) == torch.cuda.current_stream().cuda_stream
+
+
+def test_device_copy_aligned_unaligned_and_tail():
+    _need_gpu()
+    import ctypes as C
+    from paper_2608_16265_amd import _lib
+    rng = np.random.default_rng(9)
+    src = torch.as_tensor(rng.integers(0, 256, 4096 + 37, dtype=np.uint8), device="cuda:0")
+    for off, n in ((0, 4096), (0, 4096 + 37), (3, 1000), (16, 17), (0, 0), (5, 1)):
+        dst = torch.zeros_like(src)
+        st = _lib.LIB.exa_device_copy(C.c_void_p(dst.data_ptr() + off), C.c_void_p(src.data_ptr() + off),
+                                      n, None)
+        assert st == _lib.EXA_OK
+        torch.cuda.synchronize()
+        assert torch.equal(dst[off:off + n], src[off:off + n])
+        assert int(dst[:off].sum()) == 0 and int(dst[off + n:].sum()) == 0
+    assert _lib.LIB.exa_device_copy(None, C.c_void_p(src.data_ptr()), 8, None) == _lib.EXA_EINVAL
+    assert _lib.LIB.exa_device_copy(C.c_void_p(src.data_ptr()), C.c_void_p(src.data_ptr()), -1, None) == _lib.EXA_EINVAL
