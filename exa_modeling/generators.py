@@ -23,7 +23,7 @@ from typing import Dict
 
 import numpy as np
 
-from .ir import DataSet, Model, cos, sin, exp
+from .ir import (DataSet, Model, abs2, atan, cos, cosh, exp, expm1, log1p, sin, sinh, sqrt, tanh)
 
 
 @dataclass
@@ -258,3 +258,90 @@ def rosenbrock(N: int, seed: int = 0) -> Workload:
     m.add_obj(100 * (x[i - 1] ** 2 - x[i]) ** 2 + (x[i - 1] - 1) ** 2, d, "rosen")
     x0 = rng.uniform(-2.0, 2.0, N)
     return Workload(m, x0, np.zeros(0), 1.0, dict(N=N))
+
+
+def goddard(T: int, seed: int = 0) -> Workload:
+    """Goddard rocket, eq. rocket (Sec. 1), trapezoidal rule over T steps,
+    with the constants of the modeling example of Sec. 3.2.1.
+
+    Variables h, v, m, tau over t = 0..T and the step dt (one entry, shared
+    by every data point).  Constraint patterns over t = 1..T: altitude,
+    velocity and mass dynamics; four singleton rows fix h_0, v_0, m_0 and
+    m_T = m_f (m_f is a parameter).  Objective: maximise h_T, written as
+    minimising -h_T.  Drag D(h, v) = D_c v^2 exp(-h_c (h - h0)/h0), gravity
+    g(h) = g0 (h0/h)^2.  The point is the example's start point plus a
+    seeded perturbation (so that no derivative is identically zero); y ~ N(0,1).
+    """
+    h0, v0, m0, g0 = 1.0, 0.0, 1.0, 1.0
+    Tc, hc, vc, mc = 3.5, 500.0, 620.0, 0.6
+    ce = 0.5 * math.sqrt(g0 * h0)
+    mf = mc * m0
+    Dc = 0.5 * vc * (m0 / g0)
+    Tmax = Tc * m0 * g0
+    rng = _rng(seed)
+    m = Model(f"goddard{T}")
+    h = m.add_var(T + 1, lvar=1.0, name="h")
+    v = m.add_var(T + 1, name="v")
+    ms = m.add_var(T + 1, lvar=mf, uvar=m0, name="m")
+    tau = m.add_var(T + 1, lvar=0.0, uvar=Tmax, name="tau")
+    dt = m.add_var(1, lvar=0.0, name="dt")
+    th = m.add_par([mf], name="mf")
+    d = DataSet(T, t=np.arange(1, T + 1))
+    t = d.t
+
+    def drag(hh, vv):
+        return Dc * abs2(vv) * exp(-hc * (hh - h0) / h0)
+
+    def grav(hh):
+        return g0 * abs2(h0 / hh)
+
+    m.add_con(h[t] - h[t - 1] - 0.5 * dt[0] * (v[t] + v[t - 1]), d, name="alt")
+    m.add_con(v[t] - v[t - 1] - 0.5 * dt[0] * ((tau[t] - drag(h[t], v[t])) / ms[t] - grav(h[t])
+                                                + (tau[t - 1] - drag(h[t - 1], v[t - 1])) / ms[t - 1]
+                                                - grav(h[t - 1])), d, name="vel")
+    m.add_con(ms[t] - ms[t - 1] + 0.5 * dt[0] / ce * (tau[t] + tau[t - 1]), d, name="mass")
+    one = DataSet(1, k=np.zeros(1, dtype=np.int64))
+    m.add_con(h[0] - h0, one, name="h0")
+    m.add_con(v[0] - v0, one, name="v0")
+    m.add_con(ms[0] - m0, one, name="m0")
+    m.add_con(ms[T] - th[0], one, name="mT")
+    m.add_obj(-h[T], one, name="hT")
+    s = np.arange(T + 1) / T
+    x = np.concatenate([1.0 + 0.01 * rng.uniform(0.0, 1.0, T + 1),
+                        s * (1 - s) + 0.01 * rng.standard_normal(T + 1),
+                        (mf - m0) * s + m0 + 0.01 * rng.uniform(0.0, 1.0, T + 1) * (m0 - mf),
+                        Tmax / 2 + 0.1 * rng.standard_normal(T + 1),
+                        [1.0 / T]])
+    y = rng.standard_normal(m.ncon)
+    return Workload(m, x, y, 1.0, dict(T=T))
+
+
+def _sweep_patterns(a, b):
+    """Sixteen distinct algebraic patterns over a variable pair (x_i, x_i+1)
+    for the compilation-time study of Sec. 9 (the first five are the ones
+    the paper names; the rest are of the same kind)."""
+    return [a ** 2 + b, sin(a) * b, exp(a - b), sqrt(a ** 2 + 1) + b, tanh(a) - b,
+            cos(a) + b ** 2, a * b - 1, log1p(a ** 2) - b, atan(a) + sin(b), a / (1 + b ** 2),
+            exp(-(a ** 2)) * b, sinh(a) - cosh(b), (a - b) ** 3, a ** 2 * b ** 2 + a,
+            expm1(a) * b, sqrt(a ** 2 + b ** 2 + 1)]
+
+
+def kernel_sweep(k: int, n: int, seed: int = 0) -> Workload:
+    """n constraints over consecutive pairs (x_i, x_i+1), i = 0..n-1, split
+    into k contiguous blocks, block j using the j-th of the sixteen patterns
+    (the kernel-count sweep of Sec. 9: the size stays fixed while the number
+    of distinct patterns varies), plus the objective 0.5 sum x_i^2."""
+    if not 1 <= k <= 16:
+        raise ValueError("k must be in 1..16")
+    rng = _rng(seed)
+    m = Model(f"sweep{k}_{n}")
+    x = m.add_var(n + 1, name="x")
+    cuts = [n * j // k for j in range(k + 1)]
+    for j in range(k):
+        d = DataSet(cuts[j + 1] - cuts[j], i=np.arange(cuts[j], cuts[j + 1]))
+        m.add_con(_sweep_patterns(x[d.i], x[d.i + 1])[j], d, name=f"k{j}")
+    all_pts = DataSet(n + 1, i=np.arange(n + 1))
+    m.add_obj(0.5 * x[all_pts.i] ** 2, all_pts, name="reg")
+    xv = rng.uniform(-1.0, 1.0, n + 1)
+    return Workload(m, xv, rng.standard_normal(m.ncon), 1.0, dict(k=k, n=n))
+

@@ -101,8 +101,10 @@ struct Em {
         memo[e] = n;
         return n;
     }
+    // an output statement; names in its destination (e.g. the index of an
+    // in-place gradient entry) are as live as those in its value
     void out(const std::string& lhs, const std::string& e) {
-        Stmt s{"", lhs, e, deps_of(e), true};
+        Stmt s{"", lhs, e, deps_of(lhs + " " + e), true};
         st.push_back(s);
     }
     void raw(const std::string& line) {

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from exa_modeling import DataSet, Model, exp
-from exa_modeling.generators import acopf, pde, rosenbrock
+from exa_modeling.generators import goddard, kernel_sweep, acopf, pde, rosenbrock
 from oracle import OracleModel
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -33,8 +33,8 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("make", [lambda: rosenbrock(7, 2), lambda: acopf(30, 0), lambda: pde(8, 3),
-                                  lambda: acopf(211, 4)],
-                         ids=["rosen7", "acopf30", "pde8", "acopf211"])
+                                  lambda: acopf(211, 4), lambda: goddard(40, 1), lambda: kernel_sweep(16, 160, 2)],
+                         ids=["rosen7", "acopf30", "pde8", "acopf211", "goddard40", "sweep16"])
 def test_host_structure_matches_oracle(make):
     from paper_2608_16265_amd import ExaModel
     w = make()

@@ -10,7 +10,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from exa_modeling.generators import acopf, pde, rosenbrock
+from exa_modeling.generators import acopf, goddard, pde, rosenbrock
 from parity_util import dev, host
 from test_parity_gpu import aliasing_case, empty_pattern_case, single_point_case, star_case
 
@@ -26,6 +26,7 @@ CASES = {
     "empty": empty_pattern_case,
     "single": single_point_case,
     "star": lambda: star_case([700, 400, 3, 0, 90], 6),  # chunked segment sums
+    "goddard": lambda: goddard(60, 1),
 }
 FIELD = {"obj": "f", "grad": "g", "cons": "c", "jac": "jac", "hess": "hess", "jprod": "jv",
          "jtprod": "jtw", "hprod": "hv"}

@@ -10,7 +10,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from exa_modeling import DataSet, Model, exp, sin
-from exa_modeling.generators import Workload, acopf, pde, rosenbrock
+from exa_modeling.generators import Workload, acopf, goddard, kernel_sweep, pde, rosenbrock
 from oracle import OracleModel
 from parity_util import RTOL, abs_oracle, assert_close, column_scale, dev, host
 
@@ -87,6 +87,8 @@ CASES = {
     "pde50": lambda: pde(50, 5),
     "star_chunked": lambda: star_case([700, 400, 3, 0, 90], 6),   # chunked sums, padded blocks
     "star_plain": lambda: star_case([1500, 2], 7),                # too long to chunk
+    "goddard": lambda: goddard(60, 1),         # dt shared by every point; division, exp, squares
+    "sweep16": lambda: kernel_sweep(16, 200, 2),  # sixteen distinct patterns
     "zoo": _zoo,
     "alias": aliasing_case,
     "empty": empty_pattern_case,
