@@ -62,8 +62,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the PDE and batched legs")
-    ap.add_argument("--only", choices=["acopf", "pde", "batch", "adjoint"], default=None,
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the PDE, batched, adjoint, ladder and compile-time legs")
+    ap.add_argument("--only", choices=["acopf", "pde", "batch", "adjoint", "ladders", "compile"], default=None,
                     help="run one leg only (used for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--quick", action="store_true",
@@ -203,13 +204,13 @@ def copy_gbs(mib=1024, n=20):
     return out
 
 
-def leg_single(name, wl, steps, warmup):
+def _callbacks(em, wl, dev="cuda:0"):
+    """Inputs and outputs in device memory for every callback of one model,
+    and a zero-argument function per callback.  "eval_all" is every
+    per-iterate callback at one point through a single exa_eval call (one
+    evaluation launch + one reduction launch), outputs bit-identical to the
+    separate callbacks.  Returns (callbacks, inputs)."""
     import torch
-    from paper_2608_16265_amd import ExaModel
-    t0 = time.perf_counter()
-    em = ExaModel(wl.model, autotune=True)
-    build_s = time.perf_counter() - t0
-    dev = "cuda:0"
     X = torch.as_tensor(wl.x, device=dev)
     Y = torch.as_tensor(wl.y, device=dev)
     rng = np.random.default_rng(0)
@@ -229,11 +230,19 @@ def leg_single(name, wl, steps, warmup):
         "jtprod": lambda: em.jtprod(X, W, Jtw),
         "hprod": lambda: em.hprod(X, Y, 1.0, V, Hv),
     }
-    # one step: every callback at one iterate through a single exa_eval call
-    # (one evaluation launch + one reduction launch), outputs bit-identical
-    # to the separate callbacks
-    step = em.bind(X, Y, 1.0, V, W, f=f, g=g, c=c, jac=jv, hess=hv, jv=Jv, jtw=Jtw, hv=Hv)
-    cbs["eval_all"] = step
+    cbs["eval_all"] = em.bind(X, Y, 1.0, V, W, f=f, g=g, c=c, jac=jv, hess=hv, jv=Jv, jtw=Jtw, hv=Hv)
+    return cbs, (X, Y, V, W)
+
+
+def leg_single(name, wl, steps, warmup):
+    import torch
+    from paper_2608_16265_amd import ExaModel
+    t0 = time.perf_counter()
+    em = ExaModel(wl.model, autotune=True)
+    build_s = time.perf_counter() - t0
+    e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
+    cbs, (X, Y, V, W) = _callbacks(em, wl)
+    step = cbs["eval_all"]
     order = ["obj", "grad", "cons", "jac_hess_coord", "jprod", "jtprod", "hprod"]
 
     def step_separate():
@@ -415,6 +424,91 @@ def leg_adjoint(count=64, first_seed=2000):
                 backward_over_grad=t_bwd / t_grad)
 
 
+LADDER_CBS = ("obj", "grad", "cons", "jac_coord", "hess_coord", "jac_hess_coord", "jprod", "jtprod", "hprod",
+              "eval_all")
+
+
+def leg_ladders():
+    """Single instances as they grow (the per-instance scaling study of
+    Sec. 8): every callback's time, by the paper's protocol, on the extended
+    Rosenbrock objective of eq. rosenbrock at N = 20, 2,000 and 200,000, the
+    ACOPF-shaped model at 118, 1,354 and 78,484 buses and the Goddard rocket
+    of eq. rocket at T = 200, 20,000 and 2,000,000 steps.  Each model's
+    every callback is one evaluation launch plus at most one reduction
+    launch, whatever its number of patterns."""
+    import torch
+    from exa_modeling.generators import acopf, goddard, rosenbrock
+    from paper_2608_16265_amd import ExaModel
+    out = {}
+    for fam, sizes, make in (("rosenbrock", (20, 2000, 200000), lambda N: rosenbrock(N, 0)),
+                             ("acopf", (118, 1354, 78484), lambda nb: acopf(nb, 5)),
+                             ("goddard", (200, 20000, 2000000), lambda T: goddard(T, 0))):
+        rows = []
+        for size in sizes:
+            wl = make(size)
+            em = ExaModel(wl.model, autotune=True)
+            cbs, _ = _callbacks(em, wl)
+            for fn in cbs.values():  # the first call of each tunes its schedule
+                fn()
+            torch.cuda.synchronize()
+            t = {k: round(best_of_3(cbs[k], min_s=0.1) * 1e6, 2) for k in LADDER_CBS}
+            nnz = em.nnzj + em.nnzh
+            rows.append(dict(size=size, nvar=em.nvar, ncon=em.ncon, nnzj=em.nnzj, nnzh=em.nnzh,
+                             patterns=len(wl.model.patterns), callbacks_us=t,
+                             jac_plus_hess_nnz_per_s=nnz / ((t["jac_coord"] + t["hess_coord"]) * 1e-6)))
+            log(f"  ladder {fam} {size}: " + json.dumps(t))
+            em.close()
+            del cbs
+        out[fam] = rows
+    return out
+
+
+def _compile_point(k, n):
+    """Build cost of the kernel-sweep model with k distinct constraint
+    patterns over n pairs: host analysis and code generation alone
+    (host_ms), creation with run-time compilation and module load (cold:
+    no live model shares its patterns), the first exa_eval of every callback
+    (first_eval_ms), and creation while a model with the same patterns is
+    alive (cached: the compiled module is shared, nothing is compiled)."""
+    import torch
+    from exa_modeling.generators import kernel_sweep
+    from paper_2608_16265_amd import ExaModel
+    wl = kernel_sweep(k, n, 0)
+    t0 = time.perf_counter()
+    h = ExaModel(wl.model, host_only=True)
+    host_s = time.perf_counter() - t0
+    src_kb = len(h.generated_source()) / 1024
+    h.close()
+    t0 = time.perf_counter()
+    em = ExaModel(wl.model)
+    create_s = time.perf_counter() - t0
+    cbs, _ = _callbacks(em, wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cbs["eval_all"]()
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    em2 = ExaModel(wl.model)
+    cached_s = time.perf_counter() - t0
+    res = dict(kernels=k, n=n, patterns=len(wl.model.patterns), nnzj=em.nnzj, nnzh=em.nnzh,
+               source_kb=round(src_kb, 1), host_ms=round(host_s * 1e3, 1), create_ms=round(create_s * 1e3, 1),
+               first_eval_ms=round(first_s * 1e3, 2), create_cached_ms=round(cached_s * 1e3, 1))
+    em2.close()
+    em.close()
+    log("  compile " + json.dumps(res))
+    return res
+
+
+def leg_compile():
+    """Model build time (the compilation study of Sec. 8, Table compile):
+    the number of distinct constraint patterns swept over 1, 2, 4, 8 and 16
+    at 100,000 constraints, and the size swept over 1,000 to 1,000,000
+    constraints at four patterns."""
+    return dict(kernels=[_compile_point(k, 100000) for k in (1, 2, 4, 8, 16)],
+                size=[_compile_point(4, n) for n in (1000, 10000, 100000, 1000000)])
+
+
 def cpu_baseline(wl, seconds):
     """The CPU oracle as it stands, timed on a bounded sample of the same
     workload: repeated full jac_coord + hess_coord of the 10k-bus model."""
@@ -538,6 +632,12 @@ def main():
         r = leg_adjoint()
         log(json.dumps(r))
         out["adjoint"] = r
+    if not args.no_extras and args.only in (None, "ladders"):
+        log("leg: per-instance ladders")
+        out["ladders"] = leg_ladders()
+    if not args.no_extras and args.only in (None, "compile"):
+        log("leg: build time vs patterns and size")
+        out["compile"] = leg_compile()
     print(json.dumps(out), flush=True)
 
 

@@ -11,6 +11,10 @@ any of their instances.
 * :func:`pde` -- distributed control of a semilinear elliptic PDE on an
   n x n grid (5-point Laplacian), a COPS-like shape.
 * :func:`rosenbrock` -- the extended Rosenbrock objective, eq. rosenbrock.
+* :func:`goddard` -- the Goddard rocket, eq. rocket, with the constants of
+  the modeling example of Sec. 2.2.2.
+* :func:`kernel_sweep` -- k of sixteen two-variable constraint patterns over
+  a fixed number of rows (the compilation study of Sec. 8.6).
 
 Every random draw comes from ``numpy.random.Generator(PCG64(seed))`` in a
 fixed order, documented per function.  Nothing here evaluates the model.
@@ -262,7 +266,7 @@ def rosenbrock(N: int, seed: int = 0) -> Workload:
 
 def goddard(T: int, seed: int = 0) -> Workload:
     """Goddard rocket, eq. rocket (Sec. 1), trapezoidal rule over T steps,
-    with the constants of the modeling example of Sec. 3.2.1.
+    with the constants of the modeling example of Sec. 2.2.2.
 
     Variables h, v, m, tau over t = 0..T and the step dt (one entry, shared
     by every data point).  Constraint patterns over t = 1..T: altitude,
@@ -318,7 +322,7 @@ def goddard(T: int, seed: int = 0) -> Workload:
 
 def _sweep_patterns(a, b):
     """Sixteen distinct algebraic patterns over a variable pair (x_i, x_i+1)
-    for the compilation-time study of Sec. 9 (the first five are the ones
+    for the compilation-time study of Sec. 8.6 (the first five are the ones
     the paper names; the rest are of the same kind)."""
     return [a ** 2 + b, sin(a) * b, exp(a - b), sqrt(a ** 2 + 1) + b, tanh(a) - b,
             cos(a) + b ** 2, a * b - 1, log1p(a ** 2) - b, atan(a) + sin(b), a / (1 + b ** 2),
@@ -329,8 +333,9 @@ def _sweep_patterns(a, b):
 def kernel_sweep(k: int, n: int, seed: int = 0) -> Workload:
     """n constraints over consecutive pairs (x_i, x_i+1), i = 0..n-1, split
     into k contiguous blocks, block j using the j-th of the sixteen patterns
-    (the kernel-count sweep of Sec. 9: the size stays fixed while the number
-    of distinct patterns varies), plus the objective 0.5 sum x_i^2."""
+    (the kernel-count sweep of Sec. 8.6, Table compile: the size stays fixed
+    while the number of distinct patterns varies), plus the objective
+    0.5 sum x_i^2."""
     if not 1 <= k <= 16:
         raise ValueError("k must be in 1..16")
     rng = _rng(seed)

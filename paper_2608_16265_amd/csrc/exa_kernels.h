@@ -9,13 +9,22 @@ hipError_t exa_launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 // One segment-sum job: out[s] = sum of buf[idx[j]], j in [ptr[s], ptr[s+1]).
-// With lanes == nullptr one lane sums one segment in ascending j.  With
-// lanes set, lane l sums a chunk of at most kExaChunk consecutive entries:
-// lanes[3l] = segment (-1 for padding), lanes[3l+1] = first entry,
-// lanes[3l+2] = count | (number of chunks of the segment << 4) on the
-// segment's first chunk; a segment's chunks lie in one 256-lane block, and
-// its first lane adds the chunk sums in chunk order.
+// Unless chunked is set, one lane sums one segment in ascending j.  Chunked
+// jobs (int32 maps only) take every segment in chunks of at most kExaChunk
+// consecutive entries, in a summation order fixed by the map:
+// * segments of at most kExaLongSeg entries: lane l adds one chunk, with
+//   lanes[3l] = segment (-1 for padding), lanes[3l+1] = first entry,
+//   lanes[3l+2] = count | (number of chunks of the segment << 4) on the
+//   segment's first chunk; a segment's chunks lie in one 256-lane block, and
+//   its first lane adds the chunk sums in chunk order;
+// * longer segments: one block per part of kExaLongSeg entries adds its
+//   chunk sums by a fixed tree into lsum[part]; the last of a segment's part
+//   blocks to finish (counted in lcount, which is zero between launches)
+//   adds the segment's part sums, again in a fixed order.  longs[5i..5i+4]
+//   = {segment, first entry, length, first part, parts} of long segment i,
+//   and part q belongs to long segment lpart[q].
 constexpr int kExaChunk = 4;
+constexpr int kExaLongSeg = 256 * kExaChunk;
 struct ExaSegJob {
     const void* ptr;
     const void* idx;
@@ -23,9 +32,14 @@ struct ExaSegJob {
     double* out;
     int64_t nseg;
     const int32_t* lanes;
-    int64_t nlanes;  // a multiple of 256 when lanes is set
+    int64_t nlanes;  // a multiple of 256
+    const int32_t* longs;
+    const int32_t* lpart;
+    int64_t nparts;
+    double* lsum;
+    uint32_t* lcount;
     int32_t wide;    // ptr/idx are int64 when set, else int32
-    int32_t pad;
+    int32_t chunked;
 };
 constexpr int kExaReduceJobs = 3;
 // Up to three segment-sum jobs and, when part is not null, the sum of the

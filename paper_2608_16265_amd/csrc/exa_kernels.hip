@@ -79,19 +79,74 @@ __device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double
     __syncthreads();
 }
 
+// Sum of the 256 lane values v by a fixed tree; every lane gets the sum.
+// Called by every lane of the workgroup; lds is free again on return.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// Part q of a long segment (see ExaSegJob): lane t adds entries
+// 4t .. 4t+3 of the part, the block adds the lanes by block_sum, and the
+// block that completes the segment's count adds its part sums.  Called by
+// every lane of the workgroup.
+__device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t q, double* lds, int* last) {
+    const int32_t* __restrict__ idx = (const int32_t*)J.idx;
+    const double* __restrict__ buf = J.buf;
+    const int32_t ls = J.lpart[q];
+    const int32_t seg = J.longs[5 * ls], beg = J.longs[5 * ls + 1], len = J.longs[5 * ls + 2];
+    const int32_t part0 = J.longs[5 * ls + 3], nparts = J.longs[5 * ls + 4];
+    const int32_t pb = beg + ((int32_t)q - part0) * kExaLongSeg;
+    const int32_t pe = min(beg + len, pb + kExaLongSeg);
+    const int32_t j0 = pb + kExaChunk * (int32_t)threadIdx.x;
+    double part = 0.0;
+    if (j0 < pe) {
+        const int cnt = min(kExaChunk, pe - j0);
+        int32_t ix[kExaChunk];
+#pragma unroll
+        for (int u = 0; u < kExaChunk; ++u) ix[u] = idx[j0 + (u < cnt ? u : cnt - 1)];
+        double v[kExaChunk];
+#pragma unroll
+        for (int u = 0; u < kExaChunk; ++u) v[u] = buf[ix[u]];
+#pragma unroll
+        for (int u = 0; u < kExaChunk; ++u)
+            if (u < cnt) part += v[u];
+    }
+    const double s = block_sum(part, lds);
+    if (threadIdx.x == 0) {
+        J.lsum[q] = s;
+        // publish the part sum before counting it (release, device scope)
+        __threadfence();
+        *last = atomicAdd(&J.lcount[ls], 1u) == (uint32_t)(nparts - 1);
+    }
+    __syncthreads();
+    if (!*last) return;
+    // every other part sum is visible once the count is complete (acquire)
+    __threadfence();
+    double acc = 0.0;
+    for (int32_t i = threadIdx.x; i < nparts; i += 256) acc += J.lsum[part0 + i];
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        J.out[seg] = tot;
+        atomicExch(&J.lcount[ls], 0u);  // ready for the next launch
+    }
+}
+
 // Sum of n partials in a fixed order by one 256-wide workgroup: strided
 // per-lane sums, then a tree.
 __device__ __forceinline__ void sum_body(const double* __restrict__ part, int64_t n, double* __restrict__ out,
                                          double* lds) {
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = lds[0];
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[0] = s;
 }
 
 __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, int64_t n,
@@ -101,22 +156,28 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, in
 }
 
 // Several reductions in one launch: the segment sums of each job over
-// consecutive block ranges (one block per 256 segments, or per 256 lanes of
-// a chunked job), then (when R.part is set) one block for the objective
-// partials, summed as k_sum does.
+// consecutive block ranges (one block per 256 segments; for a chunked job,
+// one per 256 lanes, then one per part of a long segment), then (when
+// R.part is set) one block for the objective partials, summed as k_sum
+// does.
 __device__ __forceinline__ int64_t job_blocks(const ExaSegJob& J) {
-    return J.lanes ? J.nlanes / kSegBlock : (J.nseg + kSegBlock - 1) / kSegBlock;
+    return J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
 }
 
 __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_xcd) {
     __shared__ double lds[256];
+    __shared__ int last;
     int64_t b = xcd_block(per_xcd);
     for (int k = 0; k < R.njobs; ++k) {
         const ExaSegJob& J = R.job[k];
         const int64_t nb = job_blocks(J);
         if (b < nb) {
-            if (J.lanes) {
-                chunk_body(J, b * kSegBlock + threadIdx.x, lds);
+            if (J.chunked) {
+                const int64_t nlb = J.nlanes / kSegBlock;
+                if (b < nlb)
+                    chunk_body(J, b * kSegBlock + threadIdx.x, lds);
+                else
+                    long_part_body(J, b - nlb, lds, &last);
                 return;
             }
             const int64_t s = b * kSegBlock + threadIdx.x;
@@ -164,8 +225,10 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     int64_t blocks = r.part ? 1 : 0;
     for (int k = 0; k < r.njobs; ++k) {
         const ExaSegJob& J = r.job[k];
-        if (J.lanes && J.nlanes % kSegBlock) return hipErrorInvalidValue;
-        blocks += J.lanes ? J.nlanes / kSegBlock : (J.nseg + kSegBlock - 1) / kSegBlock;
+        if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !J.lanes) ||
+                          (J.nparts && !(J.longs && J.lpart && J.lsum && J.lcount))))
+            return hipErrorInvalidValue;
+        blocks += J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
     }
     if (blocks == 0) return hipSuccess;
     const int64_t per_xcd = (blocks + 7) / 8;

@@ -231,10 +231,21 @@ void build_device(Model& M) {
             std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
             d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
             d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
-            std::vector<int32_t> lanes = chunk_lanes(S);
-            if (!lanes.empty()) {
-                d.lanes = (const int32_t*)D.upload(lanes.data(), lanes.size() * sizeof(int32_t));
-                d.nlanes = (int64_t)lanes.size() / 3;
+            const ChunkPlan P = chunk_plan(S);
+            if (P.chunked) {
+                d.chunked = 1;
+                if (P.nlanes()) {
+                    d.lanes = (const int32_t*)D.upload(P.lanes.data(), P.lanes.size() * sizeof(int32_t));
+                    d.nlanes = P.nlanes();
+                }
+                if (P.nparts()) {
+                    d.longs = (const int32_t*)D.upload(P.longs.data(), P.longs.size() * sizeof(int32_t));
+                    d.lpart = (const int32_t*)D.upload(P.lpart.data(), P.lpart.size() * sizeof(int32_t));
+                    d.nparts = P.nparts();
+                    d.lsum = (double*)D.alloc(P.nparts() * sizeof(double));
+                    d.lcount = (uint32_t*)D.alloc(P.nlong() * sizeof(uint32_t));
+                    hip_check(hipMemset(d.lcount, 0, P.nlong() * sizeof(uint32_t)), "hipMemset");
+                }
             }
         }
     };
@@ -263,20 +274,26 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
 }
 }  // namespace
 
-// Chunk lanes of a map whose longest segment has more than 2 * kExaChunk
-// entries (one lane per kExaChunk entries, a segment's lanes inside one
-// 256-lane block); empty when one lane per segment is enough, or when some
-// segment would need more than a block.
-std::vector<int32_t> chunk_lanes(const SegMap& S) {
-    std::vector<int32_t> L;
-    int64_t longest = 0;
+ChunkPlan chunk_plan(const SegMap& S) {
+    ChunkPlan P;
+    int64_t longest = 0, top = S.ptr.empty() ? 0 : S.ptr.back();
     for (int64_t s = 0; s < S.nseg(); ++s) longest = std::max(longest, S.ptr[s + 1] - S.ptr[s]);
-    if (longest <= 2 * kExaChunk || (longest + kExaChunk - 1) / kExaChunk > 256) return L;
+    for (int64_t i : S.idx) top = std::max(top, i);
+    if (longest <= 2 * kExaChunk || top >= INT32_MAX) return P;
+    P.chunked = true;
+    auto& L = P.lanes;
     auto pad_to = [&](int64_t lanes) {
         while ((int64_t)L.size() / 3 < lanes) L.insert(L.end(), {-1, 0, 0});
     };
     for (int64_t s = 0; s < S.nseg(); ++s) {
         const int64_t b = S.ptr[s], len = S.ptr[s + 1] - b;
+        if (len > kExaLongSeg) {
+            const int64_t parts = (len + kExaLongSeg - 1) / kExaLongSeg;
+            const int64_t ls = P.nlong();
+            P.longs.insert(P.longs.end(), {(int32_t)s, (int32_t)b, (int32_t)len, (int32_t)P.nparts(), (int32_t)parts});
+            P.lpart.insert(P.lpart.end(), (size_t)parts, (int32_t)ls);
+            continue;
+        }
         const int64_t nl = std::max<int64_t>(1, (len + kExaChunk - 1) / kExaChunk);
         const int64_t here = (int64_t)L.size() / 3;
         if (here % 256 + nl > 256) pad_to((here / 256 + 1) * 256);
@@ -288,7 +305,7 @@ std::vector<int32_t> chunk_lanes(const SegMap& S) {
         }
     }
     pad_to(((int64_t)L.size() / 3 + 255) / 256 * 256);
-    return L;
+    return P;
 }
 
 void set_schedule(Model& M, int mode, int block, int epl, bool fused) {
@@ -593,8 +610,14 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
     J.idx = m.idx;
     J.wide = m.wide;
     J.nseg = m.nseg;
+    J.chunked = m.chunked;
     J.lanes = m.lanes;
     J.nlanes = m.nlanes;
+    J.longs = m.longs;
+    J.lpart = m.lpart;
+    J.nparts = m.nparts;
+    J.lsum = m.lsum;
+    J.lcount = m.lcount;
     J.buf = buf;
     J.out = out;
     return J;
@@ -1119,10 +1142,12 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
             const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
             const int64_t w = top >= INT32_MAX ? 8 : 4;
-            const int64_t lanes = w == 4 ? (int64_t)chunk_lanes(S).size() / 3 : 0;
-            // chunked maps read their lane table instead of the segment pointers
-            rr += (lanes ? 12 * lanes : w * (nseg + 1)) + w * nnz + 8 * nnz;
-            rw += 8 * nseg;
+            const ChunkPlan P = chunk_plan(S);
+            // chunked maps read their lane and part tables instead of the
+            // segment pointers; each part sum is written once and read once
+            rr += (P.chunked ? 12 * P.nlanes() + 20 * P.nlong() + 12 * P.nparts() : w * (nseg + 1)) + w * nnz +
+                  8 * nnz;
+            rw += 8 * nseg + 8 * P.nparts();
         };
         if ((mask & EXA_EV_GRAD) && !M.grad_direct) seg(M.grad_map);
         if (mask & EXA_EV_JTPROD) seg(M.jt_map);

@@ -27,9 +27,15 @@ struct DevMap {
     const void* idx = nullptr;
     int64_t nseg = 0;
     int wide = 0;
-    // chunk lanes (see ExaSegJob) for maps with long segments, else null
+    // chunked sums (see ExaSegJob) for maps with long segments
+    int chunked = 0;
     const int32_t* lanes = nullptr;
     int64_t nlanes = 0;
+    const int32_t* longs = nullptr;
+    const int32_t* lpart = nullptr;
+    int64_t nparts = 0;
+    double* lsum = nullptr;
+    uint32_t* lcount = nullptr;
 };
 
 struct DeviceState {
@@ -83,7 +89,19 @@ std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile
 std::string kernel_name(int mode);
 int mode_lds_doubles(const Model& M, int mode);
 void set_schedule(Model& M, int mode, int block, int epl, bool fused);
-std::vector<int32_t> chunk_lanes(const SegMap& S);
+// How a map's segments are summed in chunks (see ExaSegJob): chunk lanes
+// for segments of at most kExaLongSeg entries, parts for longer ones.
+// chunked is false when one lane per segment is enough (no segment longer
+// than 2 * kExaChunk) or when positions need 64 bits.
+struct ChunkPlan {
+    bool chunked = false;
+    std::vector<int32_t> lanes;         // 3 per lane, a multiple of 256 lanes
+    std::vector<int32_t> longs, lpart;  // 5 per long segment; 1 per part
+    int64_t nlanes() const { return (int64_t)lanes.size() / 3; }
+    int64_t nlong() const { return (int64_t)longs.size() / 5; }
+    int64_t nparts() const { return (int64_t)lpart.size(); }
+};
+ChunkPlan chunk_plan(const SegMap& S);
 void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);
 void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);
 void hess_structure_host(const Model& M, int32_t* rows, int32_t* cols);

@@ -86,7 +86,9 @@ CASES = {
     "pde8": lambda: pde(8, 3),
     "pde50": lambda: pde(50, 5),
     "star_chunked": lambda: star_case([700, 400, 3, 0, 90], 6),   # chunked sums, padded blocks
-    "star_plain": lambda: star_case([1500, 2], 7),                # too long to chunk
+    "star_long": lambda: star_case([1500, 2], 7),                 # one long segment: two parts
+    "star_parts": lambda: star_case([5000, 1025, 700, 3, 0, 2100], 8),  # long and short segments mixed
+    "goddard_long": lambda: goddard(2000, 3),  # dt's segments span several parts
     "goddard": lambda: goddard(60, 1),         # dt shared by every point; division, exp, squares
     "sweep16": lambda: kernel_sweep(16, 200, 2),  # sixteen distinct patterns
     "zoo": _zoo,
@@ -174,6 +176,32 @@ def test_repeated_calls_are_bitwise_identical():
                host(em.obj(X))]
         for a, b in zip(ref, got):
             assert np.array_equal(a, b)
+
+
+def test_long_segment_sums_repeat_bitwise():
+    """Segments longer than one block's worth of chunks are summed in parts
+    whose last finisher adds the part sums; its counters return to zero
+    after every launch, so back-to-back calls (without synchronization in
+    between) and calls through exa_eval give the same bits."""
+    _need_gpu()
+    import torch
+    from paper_2608_16265_amd import ExaModel
+    w = goddard(2000, 3)
+    em = ExaModel(w.model)
+    rng = np.random.default_rng(5)
+    X, Y = dev(w.x), dev(w.y)
+    V, W = dev(rng.standard_normal(em.nvar)), dev(rng.standard_normal(em.ncon))
+    ref = [host(em.jtprod(X, W)), host(em.hprod(X, Y, 1.0, V))]
+    outs = []
+    for _ in range(8):
+        outs.append((em.jtprod(X, W), em.hprod(X, Y, 1.0, V)))
+    jtw = torch.empty(em.nvar, dtype=torch.float64, device="cuda:0")
+    hv = torch.empty(em.nvar, dtype=torch.float64, device="cuda:0")
+    em.evaluate(X, Y, 1.0, V, W, jtw=jtw, hv=hv)
+    outs.append((jtw, hv))
+    for a, b in outs:
+        assert np.array_equal(host(a), ref[0])
+        assert np.array_equal(host(b), ref[1])
 
 
 def test_set_theta_updates_without_rebuild():
