@@ -18,10 +18,9 @@ hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_
 //   segment's first chunk; a segment's chunks lie in one 256-lane block, and
 //   its first lane adds the chunk sums in chunk order;
 // * longer segments: one block per part of kExaLongSeg entries adds its
-//   chunk sums by a fixed tree into lsum[part]; the last of a segment's part
-//   blocks to finish (counted in lcount, which is zero between launches)
-//   adds the segment's part sums, again in a fixed order.  longs[5i..5i+4]
-//   = {segment, first entry, length, first part, parts} of long segment i,
+//   chunk sums by a fixed tree into lsum[part], and a second launch adds
+//   each segment's part sums, again in a fixed order.  longs[5i..5i+4] =
+//   {segment, first entry, length, first part, parts} of long segment i,
 //   and part q belongs to long segment lpart[q].
 constexpr int kExaChunk = 4;
 constexpr int kExaLongSeg = 256 * kExaChunk;
@@ -35,15 +34,15 @@ struct ExaSegJob {
     int64_t nlanes;  // a multiple of 256
     const int32_t* longs;
     const int32_t* lpart;
-    int64_t nparts;
+    int64_t nparts, nlong;
     double* lsum;
-    uint32_t* lcount;
     int32_t wide;    // ptr/idx are int64 when set, else int32
     int32_t chunked;
 };
 constexpr int kExaReduceJobs = 3;
 // Up to three segment-sum jobs and, when part is not null, the sum of the
-// npart objective partials into f[0], all in one launch.
+// npart objective partials into f[0], in one launch (two when a job has
+// long segments).
 struct ExaReduce {
     ExaSegJob job[kExaReduceJobs];
     int32_t njobs;

@@ -94,15 +94,13 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 // Part q of a long segment (see ExaSegJob): lane t adds entries
-// 4t .. 4t+3 of the part, the block adds the lanes by block_sum, and the
-// block that completes the segment's count adds its part sums.  Called by
-// every lane of the workgroup.
-__device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t q, double* lds, int* last) {
+// 4t .. 4t+3 of the part and the block adds the lanes by block_sum.  Called
+// by every lane of the workgroup.
+__device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t q, double* lds) {
     const int32_t* __restrict__ idx = (const int32_t*)J.idx;
     const double* __restrict__ buf = J.buf;
     const int32_t ls = J.lpart[q];
-    const int32_t seg = J.longs[5 * ls], beg = J.longs[5 * ls + 1], len = J.longs[5 * ls + 2];
-    const int32_t part0 = J.longs[5 * ls + 3], nparts = J.longs[5 * ls + 4];
+    const int32_t beg = J.longs[5 * ls + 1], len = J.longs[5 * ls + 2], part0 = J.longs[5 * ls + 3];
     const int32_t pb = beg + ((int32_t)q - part0) * kExaLongSeg;
     const int32_t pe = min(beg + len, pb + kExaLongSeg);
     const int32_t j0 = pb + kExaChunk * (int32_t)threadIdx.x;
@@ -120,23 +118,7 @@ __device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t q, do
             if (u < cnt) part += v[u];
     }
     const double s = block_sum(part, lds);
-    if (threadIdx.x == 0) {
-        J.lsum[q] = s;
-        // publish the part sum before counting it (release, device scope)
-        __threadfence();
-        *last = atomicAdd(&J.lcount[ls], 1u) == (uint32_t)(nparts - 1);
-    }
-    __syncthreads();
-    if (!*last) return;
-    // every other part sum is visible once the count is complete (acquire)
-    __threadfence();
-    double acc = 0.0;
-    for (int32_t i = threadIdx.x; i < nparts; i += 256) acc += J.lsum[part0 + i];
-    const double tot = block_sum(acc, lds);
-    if (threadIdx.x == 0) {
-        J.out[seg] = tot;
-        atomicExch(&J.lcount[ls], 0u);  // ready for the next launch
-    }
+    if (threadIdx.x == 0) J.lsum[q] = s;
 }
 
 // Sum of n partials in a fixed order by one 256-wide workgroup: strided
@@ -166,7 +148,6 @@ __device__ __forceinline__ int64_t job_blocks(const ExaSegJob& J) {
 
 __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_xcd) {
     __shared__ double lds[256];
-    __shared__ int last;
     int64_t b = xcd_block(per_xcd);
     for (int k = 0; k < R.njobs; ++k) {
         const ExaSegJob& J = R.job[k];
@@ -177,7 +158,7 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
                 if (b < nlb)
                     chunk_body(J, b * kSegBlock + threadIdx.x, lds);
                 else
-                    long_part_body(J, b - nlb, lds, &last);
+                    long_part_body(J, b - nlb, lds);
                 return;
             }
             const int64_t s = b * kSegBlock + threadIdx.x;
@@ -192,6 +173,27 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
         b -= nb;
     }
     if (R.part && b == 0) sum_body(R.part, R.npart, R.f, lds);
+}
+
+// Second launch for jobs with long segments: block b adds the part sums of
+// one long segment (the jobs' long segments in job order), strided per lane
+// and then by block_sum.
+__global__ void __launch_bounds__(kSegBlock) k_reduce_long(ExaReduce R) {
+    __shared__ double lds[256];
+    int64_t b = blockIdx.x;
+    for (int k = 0; k < R.njobs; ++k) {
+        const ExaSegJob& J = R.job[k];
+        if (b < J.nlong) {
+            const int32_t* L = J.longs + 5 * b;
+            const int32_t seg = L[0], part0 = L[3], nparts = L[4];
+            double acc = 0.0;
+            for (int32_t i = threadIdx.x; i < nparts; i += 256) acc += J.lsum[part0 + i];
+            const double tot = block_sum(acc, lds);
+            if (threadIdx.x == 0) J.out[seg] = tot;
+            return;
+        }
+        b -= J.nlong;
+    }
 }
 
 // Streaming copy with 16-byte non-temporal loads and stores, one vector per
@@ -222,17 +224,20 @@ hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_
 
 hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     if (r.njobs < 0 || r.njobs > kExaReduceJobs) return hipErrorInvalidValue;
-    int64_t blocks = r.part ? 1 : 0;
+    int64_t blocks = r.part ? 1 : 0, nlong = 0;
     for (int k = 0; k < r.njobs; ++k) {
         const ExaSegJob& J = r.job[k];
         if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !J.lanes) ||
-                          (J.nparts && !(J.longs && J.lpart && J.lsum && J.lcount))))
+                          (J.nparts && !(J.longs && J.lpart && J.lsum && J.nlong > 0))))
             return hipErrorInvalidValue;
+        if (!J.chunked && J.nparts) return hipErrorInvalidValue;
         blocks += J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
+        nlong += J.chunked ? J.nlong : 0;
     }
     if (blocks == 0) return hipSuccess;
     const int64_t per_xcd = (blocks + 7) / 8;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);
+    if (nlong > 0) hipLaunchKernelGGL(k_reduce_long, dim3((unsigned)nlong), dim3(kSegBlock), 0, s, r);
     return hipGetLastError();
 }
 

@@ -242,9 +242,8 @@ void build_device(Model& M) {
                     d.longs = (const int32_t*)D.upload(P.longs.data(), P.longs.size() * sizeof(int32_t));
                     d.lpart = (const int32_t*)D.upload(P.lpart.data(), P.lpart.size() * sizeof(int32_t));
                     d.nparts = P.nparts();
+                    d.nlong = P.nlong();
                     d.lsum = (double*)D.alloc(P.nparts() * sizeof(double));
-                    d.lcount = (uint32_t*)D.alloc(P.nlong() * sizeof(uint32_t));
-                    hip_check(hipMemset(d.lcount, 0, P.nlong() * sizeof(uint32_t)), "hipMemset");
                 }
             }
         }
@@ -616,8 +615,8 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
     J.longs = m.longs;
     J.lpart = m.lpart;
     J.nparts = m.nparts;
+    J.nlong = m.nlong;
     J.lsum = m.lsum;
-    J.lcount = m.lcount;
     J.buf = buf;
     J.out = out;
     return J;
@@ -1144,8 +1143,9 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             const int64_t w = top >= INT32_MAX ? 8 : 4;
             const ChunkPlan P = chunk_plan(S);
             // chunked maps read their lane and part tables instead of the
-            // segment pointers; each part sum is written once and read once
-            rr += (P.chunked ? 12 * P.nlanes() + 20 * P.nlong() + 12 * P.nparts() : w * (nseg + 1)) + w * nnz +
+            // segment pointers (the long-segment table once per launch);
+            // each part sum is written once and read once
+            rr += (P.chunked ? 12 * P.nlanes() + 40 * P.nlong() + 12 * P.nparts() : w * (nseg + 1)) + w * nnz +
                   8 * nnz;
             rw += 8 * nseg + 8 * P.nparts();
         };

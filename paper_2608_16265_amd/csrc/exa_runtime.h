@@ -33,9 +33,8 @@ struct DevMap {
     int64_t nlanes = 0;
     const int32_t* longs = nullptr;
     const int32_t* lpart = nullptr;
-    int64_t nparts = 0;
+    int64_t nparts = 0, nlong = 0;
     double* lsum = nullptr;
-    uint32_t* lcount = nullptr;
 };
 
 struct DeviceState {

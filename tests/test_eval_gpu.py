@@ -27,7 +27,7 @@ CASES = {
     "single": single_point_case,
     "star": lambda: star_case([700, 400, 3, 0, 90], 6),  # chunked segment sums
     "goddard": lambda: goddard(60, 1),
-    "goddard_long": lambda: goddard(2000, 3),  # long segments: part sums combined by the last block
+    "goddard_long": lambda: goddard(2000, 3),  # long segments: part sums added by a second launch
 }
 FIELD = {"obj": "f", "grad": "g", "cons": "c", "jac": "jac", "hess": "hess", "jprod": "jv",
          "jtprod": "jtw", "hprod": "hv"}

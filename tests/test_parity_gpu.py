@@ -179,10 +179,10 @@ def test_repeated_calls_are_bitwise_identical():
 
 
 def test_long_segment_sums_repeat_bitwise():
-    """Segments longer than one block's worth of chunks are summed in parts
-    whose last finisher adds the part sums; its counters return to zero
-    after every launch, so back-to-back calls (without synchronization in
-    between) and calls through exa_eval give the same bits."""
+    """Segments longer than one block's worth of chunks are summed in parts,
+    and a second launch adds the part sums in a fixed order: back-to-back
+    calls (without synchronization in between) and calls through exa_eval
+    give the same bits."""
     _need_gpu()
     import torch
     from paper_2608_16265_amd import ExaModel
