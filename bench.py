@@ -218,7 +218,7 @@ def _callbacks(em, wl, dev="cuda:0"):
     W = torch.as_tensor(rng.standard_normal(em.ncon), device=dev)
     e = lambda n: torch.empty(n, dtype=torch.float64, device=dev)  # noqa: E731
     f, g, c, jv, hv = e(1), e(em.nvar), e(em.ncon), e(em.nnzj), e(em.nnzh)
-    Jv, Jtw, Hv = e(em.ncon), e(em.nvar), e(em.nvar)
+    Jv, Jtw, Hv, Lg = e(em.ncon), e(em.nvar), e(em.nvar), e(em.nvar)
     cbs = {
         "obj": lambda: em.obj(X, f),
         "grad": lambda: em.grad(X, g),
@@ -229,6 +229,7 @@ def _callbacks(em, wl, dev="cuda:0"):
         "jprod": lambda: em.jprod(X, V, Jv),
         "jtprod": lambda: em.jtprod(X, W, Jtw),
         "hprod": lambda: em.hprod(X, Y, 1.0, V, Hv),
+        "lag_grad": lambda: em.lag_grad(X, Y, 1.0, Lg),
     }
     cbs["eval_all"] = em.bind(X, Y, 1.0, V, W, f=f, g=g, c=c, jac=jv, hess=hv, jv=Jv, jtw=Jtw, hv=Hv)
     return cbs, (X, Y, V, W)

@@ -229,6 +229,18 @@ exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jt
 /* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod). */
 exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight,
                      const double* v, double* Hv, exa_stream_t stream);
+/* Gradient of the Lagrangian of eq. nlp, sigma grad f(x) + J(x)^T y, into
+ * out [nvar]; x [nvar] and y [ncon] are device arrays, sigma = obj_weight
+ * (the first-order half of what hess_coord weights, Sec. 2.1.3).  One
+ * evaluation launch of the gradient and J^T y terms, their reductions, and
+ * one elementwise launch out = sigma * grad + J^T y with the product rounded
+ * before the sum: bit-identical to exa_grad into out, exa_jtprod into t and
+ * then out = sigma * out followed by out = out + t.  Uses a library-owned
+ * nvar buffer for J^T y, so overlapping calls on one model race.  Counts
+ * as one grad and one jtprod evaluation.  Errors: EXA_EINVAL for a NULL
+ * pointer that a nonzero size needs; EXA_ESTATE for a host-only model. */
+exa_status exa_lag_grad(exa_model* m, const double* x, const double* y, double obj_weight, double* out,
+                        exa_stream_t stream);
 
 /* Several callbacks at one point in one call (Sec. 2.1.3 callbacks,
  * evaluated together).  `mask` selects callbacks with the EXA_EV_* bits;
@@ -245,9 +257,10 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
  * All pointers are device arrays owned by the caller; inputs a selection
  * does not need may be NULL, outputs it selects may not.  Outputs must not
  * overlap each other or the inputs.  The work is one evaluation launch over
- * the tiles of every selected callback, followed by at most one launch of
- * the deterministic reductions (objective partials, gradient, J^T w and H v
- * segment sums).  The first call with a given mask times candidate
+ * the tiles of every selected callback, followed by one launch of the
+ * deterministic reductions when any are needed (objective partials,
+ * gradient, J^T w and H v segment sums), plus one small launch that adds
+ * the part sums of segments longer than 1024 entries when there are any.  The first call with a given mask times candidate
  * schedules (as with autotune) and synchronizes the stream; later calls are
  * asynchronous on `stream`.
  * Errors: EXA_EINVAL for a NULL model or args, an empty or unknown mask, or

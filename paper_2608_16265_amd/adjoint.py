@@ -6,10 +6,11 @@ gradient
 
     F(theta) = grad_x L(x, y; theta) = sigma grad_x f(x; theta) + J(x; theta)^T y
 
-at fixed (x, y, sigma).  Its forward runs the exa_grad and exa_jtprod
-kernels; its backward runs the hand-written adjoint kernel exa_adjoint_theta,
-which returns (dF/dtheta)^T w from the mixed second derivatives of every
-pattern instance.
+at fixed (x, y, sigma).  Its forward runs exa_lag_grad (the gradient and
+J^T y terms and their sum, in the library's kernels); its backward runs the
+hand-written adjoint kernel exa_adjoint_theta, which returns
+(dF/dtheta)^T w from the mixed second derivatives of every pattern
+instance.
 """
 from __future__ import annotations
 
@@ -24,9 +25,7 @@ class LagrangianGradient(torch.autograd.Function):
                 sigma: float):
         theta_c = theta.detach().contiguous()
         model.set_theta(theta_c)
-        g = model.grad(x)
-        jt = model.jtprod(x, y)
-        out = g.mul_(float(sigma)).add_(jt)
+        out = model.lag_grad(x, y, float(sigma))
         ctx.model, ctx.sigma = model, float(sigma)
         ctx.save_for_backward(theta_c, x, y)
         return out

@@ -41,8 +41,8 @@ struct ExaSegJob {
 };
 constexpr int kExaReduceJobs = 3;
 // Up to three segment-sum jobs and, when part is not null, the sum of the
-// npart objective partials into f[0], in one launch (two when a job has
-// long segments).
+// npart objective partials into f[0], in one launch (one more when a job
+// has long segments, and one more for the ax_* update).
 struct ExaReduce {
     ExaSegJob job[kExaReduceJobs];
     int32_t njobs;
@@ -50,5 +50,11 @@ struct ExaReduce {
     const double* part;
     int64_t npart;
     double* f;
+    // when ax_out is set, after the sums: ax_out[i] = ax_alpha * ax_out[i] +
+    // ax_add[i] for i < ax_n, each operation rounded on its own
+    double* ax_out;
+    const double* ax_add;
+    double ax_alpha;
+    int64_t ax_n;
 };
 hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s);

@@ -210,6 +210,18 @@ __global__ void __launch_bounds__(256) k_copy1(const char* __restrict__ src, cha
     if (i < n) dst[i] = src[i];
 }
 
+// out[i] = a * out[i] + add[i], the product rounded before the sum (no
+// fused multiply-add), as two separate elementwise operations would give
+__global__ void __launch_bounds__(256) k_axpy(double* __restrict__ out, const double* __restrict__ add, double a,
+                                              int64_t n) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        const double p = a * out[i];
+        out[i] = p + add[i];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill(double* __restrict__ p, int64_t n, double v) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
@@ -234,10 +246,15 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
         blocks += J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
         nlong += J.chunked ? J.nlong : 0;
     }
-    if (blocks == 0) return hipSuccess;
-    const int64_t per_xcd = (blocks + 7) / 8;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);
+    if (r.ax_out && (!r.ax_add || r.ax_n < 0)) return hipErrorInvalidValue;
+    if (blocks > 0) {
+        const int64_t per_xcd = (blocks + 7) / 8;
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);
+    }
     if (nlong > 0) hipLaunchKernelGGL(k_reduce_long, dim3((unsigned)nlong), dim3(kSegBlock), 0, s, r);
+    if (r.ax_out && r.ax_n > 0)
+        hipLaunchKernelGGL(k_axpy, dim3((unsigned)((r.ax_n + 255) / 256)), dim3(256), 0, s, r.ax_out, r.ax_add,
+                           r.ax_alpha, r.ax_n);
     return hipGetLastError();
 }
 

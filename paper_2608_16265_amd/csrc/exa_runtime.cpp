@@ -217,6 +217,7 @@ void build_device(Model& M) {
     D.par = (double*)D.alloc(M.nnzp * sizeof(double));
     D.hv = (double*)D.alloc(M.nhv * sizeof(double));
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
+    D.lag_tmp = (double*)D.alloc(M.nvar * sizeof(double));
 
     // maps go to the device as int32 whenever every position fits
     auto up_map = [&](const SegMap& S, DevMap& d) {
@@ -939,120 +940,148 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
     });
 }
 
+namespace {
+// exa_eval's work; with lag set (the Lagrangian gradient), g then becomes
+// lag_sigma * g + jtw once the reductions are done
+void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false, double lag_sigma = 0.0) {
+    if (!a) fail(EXA_EINVAL, "null exa_eval_args");
+    const uint32_t mask = a->mask;
+    if (mask == 0 || (mask & ~(uint32_t)EXA_EV_ALL))
+        fail(EXA_EINVAL, "exa_eval mask must select callbacks with the EXA_EV_* bits");
+    need(a->x, M.nvar, "x");
+    if (mask & (EXA_EV_HESS | EXA_EV_HPROD)) need(a->y, M.ncon, "y");
+    if (mask & (EXA_EV_JPROD | EXA_EV_HPROD)) need(a->v, M.nvar, "v");
+    if (mask & EXA_EV_JTPROD) need(a->w, M.ncon, "w");
+    if (mask & EXA_EV_OBJ) need(a->f, 1, "f");
+    if (mask & EXA_EV_GRAD) need(a->g, M.nvar, "g");
+    if (mask & EXA_EV_CONS) need(a->c, M.ncon, "c");
+    if (mask & EXA_EV_JAC) need(a->jac, M.nnzj, "jac");
+    if (mask & EXA_EV_HESS) need(a->hess, M.nnzh, "hess");
+    if (mask & EXA_EV_JPROD) need(a->jv, M.ncon, "jv");
+    if (mask & EXA_EV_JTPROD) need(a->jtw, M.nvar, "jtw");
+    if (mask & EXA_EV_HPROD) need(a->hv, M.nvar, "hv");
+    DeviceState& D = *M.dev;
+    const int64_t nobj = D.sched[M_OBJ].ntiles;
+
+    // each mode's call, as its own entry point sets it up
+    ExaMulti mc;
+    std::memset(&mc, 0, sizeof mc);
+    for (int mode : eval_modes(mask)) {
+        ExaCall& c = mc.c[mode];
+        c.inst = D.inst;
+        c.x = a->x;
+        switch (mode) {
+            case M_OBJ: c.out0 = nobj == 1 ? a->f : D.tilesum; break;
+            case M_GRAD:
+                c.out0 = M.grad_direct ? a->g : D.fo;
+                c.direct = M.grad_direct ? 1 : 0;
+                break;
+            case M_CONS: c.out0 = a->c; break;
+            case M_JAC: c.out0 = a->jac; break;
+            case M_HESS:
+                c.y = a->y;
+                c.sigma = a->obj_weight;
+                c.out0 = a->hess;
+                break;
+            case M_JH:
+                c.y = a->y;
+                c.sigma = a->obj_weight;
+                c.out0 = a->jac;
+                c.out1 = a->hess;
+                break;
+            case M_JPROD:
+                c.v = a->v;
+                c.out0 = a->jv;
+                break;
+            case M_JTPROD:
+                c.y = a->w;
+                c.out0 = D.fo;
+                break;
+            case M_HPROD:
+                c.y = a->y;
+                c.v = a->v;
+                c.sigma = a->obj_weight;
+                c.out0 = D.hv;
+                break;
+            default: break;
+        }
+    }
+    // multi units read the Jacobian and Hessian jobs' own records
+    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_HESS)) {
+        ExaCall& cj = mc.c[M_JAC];
+        cj.inst = D.inst;
+        cj.x = a->x;
+        cj.out0 = a->jac;
+        ExaCall& ch = mc.c[M_HESS];
+        ch.inst = D.inst;
+        ch.x = a->x;
+        ch.y = a->y;
+        ch.sigma = a->obj_weight;
+        ch.out0 = a->hess;
+    }
+    auto it = D.multi.find(mask);
+    if (it == D.multi.end() || !it->second.tuned) {
+        set_multi_schedule(M, mask, M.block, M.epl, M.fuse, !M.eval_per_mode);
+        if (M.autotune) tune_multi(M, mask, mc, s);
+        D.multi[mask].tuned = true;
+    }
+    DeviceState::EvalTiming& Tm = D.timing;
+    const bool timed = Tm.on && Tm.used < (int64_t)Tm.reduced.size();
+    hipEvent_t* ev = timed ? &Tm.ev[4 * Tm.used] : nullptr;
+    if (timed) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
+    raw_launch_multi(M, mask, mc, s);
+    if (timed) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
+
+    // the reductions of every selected callback, in one launch
+    ExaReduce R;
+    std::memset(&R, 0, sizeof R);
+    auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
+    if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
+    if (mask & EXA_EV_JTPROD) job(D.jt_map, D.fo, a->jtw);
+    if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
+    if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0
+        R.part = D.tilesum;
+        R.npart = nobj;
+        R.f = a->f;
+    }
+    const bool reduce = R.njobs > 0 || R.part;
+    if (timed && reduce) hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
+    if (lag) {  // out = sigma * grad + J^T y, after the reductions
+        R.ax_out = a->g;
+        R.ax_add = a->jtw;
+        R.ax_alpha = lag_sigma;
+        R.ax_n = M.nvar;
+    }
+    hip_check(exa_launch_reduce(R, s), "exa_eval reductions");
+    if (timed && reduce) hip_check(hipEventRecord(ev[3], s), "hipEventRecord");
+    if (timed) Tm.reduced[Tm.used++] = reduce ? 1 : 0;
+
+    const uint32_t bits[8] = {EXA_EV_OBJ, EXA_EV_GRAD, EXA_EV_CONS, EXA_EV_JAC,
+                              EXA_EV_HESS, EXA_EV_JPROD, EXA_EV_JTPROD, EXA_EV_HPROD};
+    for (int i = 0; i < 8; ++i)
+        if (mask & bits[i]) M.counters[i]++;
+}
+}  // namespace
+
 exa_status exa_eval(exa_model* m, const exa_eval_args* a, exa_stream_t stream) {
+    return guard([&] { eval_body(live(m), a, (hipStream_t)stream); });
+}
+
+exa_status exa_lag_grad(exa_model* m, const double* x, const double* y, double obj_weight, double* out,
+                        exa_stream_t stream) {
     return guard([&] {
         Model& M = live(m);
-        if (!a) fail(EXA_EINVAL, "null exa_eval_args");
-        const uint32_t mask = a->mask;
-        if (mask == 0 || (mask & ~(uint32_t)EXA_EV_ALL))
-            fail(EXA_EINVAL, "exa_eval mask must select callbacks with the EXA_EV_* bits");
-        need(a->x, M.nvar, "x");
-        if (mask & (EXA_EV_HESS | EXA_EV_HPROD)) need(a->y, M.ncon, "y");
-        if (mask & (EXA_EV_JPROD | EXA_EV_HPROD)) need(a->v, M.nvar, "v");
-        if (mask & EXA_EV_JTPROD) need(a->w, M.ncon, "w");
-        if (mask & EXA_EV_OBJ) need(a->f, 1, "f");
-        if (mask & EXA_EV_GRAD) need(a->g, M.nvar, "g");
-        if (mask & EXA_EV_CONS) need(a->c, M.ncon, "c");
-        if (mask & EXA_EV_JAC) need(a->jac, M.nnzj, "jac");
-        if (mask & EXA_EV_HESS) need(a->hess, M.nnzh, "hess");
-        if (mask & EXA_EV_JPROD) need(a->jv, M.ncon, "jv");
-        if (mask & EXA_EV_JTPROD) need(a->jtw, M.nvar, "jtw");
-        if (mask & EXA_EV_HPROD) need(a->hv, M.nvar, "hv");
-        DeviceState& D = *M.dev;
-        hipStream_t s = (hipStream_t)stream;
-        const int64_t nobj = D.sched[M_OBJ].ntiles;
-
-        // each mode's call, as its own entry point sets it up
-        ExaMulti mc;
-        std::memset(&mc, 0, sizeof mc);
-        for (int mode : eval_modes(mask)) {
-            ExaCall& c = mc.c[mode];
-            c.inst = D.inst;
-            c.x = a->x;
-            switch (mode) {
-                case M_OBJ: c.out0 = nobj == 1 ? a->f : D.tilesum; break;
-                case M_GRAD:
-                    c.out0 = M.grad_direct ? a->g : D.fo;
-                    c.direct = M.grad_direct ? 1 : 0;
-                    break;
-                case M_CONS: c.out0 = a->c; break;
-                case M_JAC: c.out0 = a->jac; break;
-                case M_HESS:
-                    c.y = a->y;
-                    c.sigma = a->obj_weight;
-                    c.out0 = a->hess;
-                    break;
-                case M_JH:
-                    c.y = a->y;
-                    c.sigma = a->obj_weight;
-                    c.out0 = a->jac;
-                    c.out1 = a->hess;
-                    break;
-                case M_JPROD:
-                    c.v = a->v;
-                    c.out0 = a->jv;
-                    break;
-                case M_JTPROD:
-                    c.y = a->w;
-                    c.out0 = D.fo;
-                    break;
-                case M_HPROD:
-                    c.y = a->y;
-                    c.v = a->v;
-                    c.sigma = a->obj_weight;
-                    c.out0 = D.hv;
-                    break;
-                default: break;
-            }
-        }
-        // multi units read the Jacobian and Hessian jobs' own records
-        if ((mask & EXA_EV_JAC) && (mask & EXA_EV_HESS)) {
-            ExaCall& cj = mc.c[M_JAC];
-            cj.inst = D.inst;
-            cj.x = a->x;
-            cj.out0 = a->jac;
-            ExaCall& ch = mc.c[M_HESS];
-            ch.inst = D.inst;
-            ch.x = a->x;
-            ch.y = a->y;
-            ch.sigma = a->obj_weight;
-            ch.out0 = a->hess;
-        }
-        auto it = D.multi.find(mask);
-        if (it == D.multi.end() || !it->second.tuned) {
-            set_multi_schedule(M, mask, M.block, M.epl, M.fuse, !M.eval_per_mode);
-            if (M.autotune) tune_multi(M, mask, mc, s);
-            D.multi[mask].tuned = true;
-        }
-        DeviceState::EvalTiming& Tm = D.timing;
-        const bool timed = Tm.on && Tm.used < (int64_t)Tm.reduced.size();
-        hipEvent_t* ev = timed ? &Tm.ev[4 * Tm.used] : nullptr;
-        if (timed) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
-        raw_launch_multi(M, mask, mc, s);
-        if (timed) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
-
-        // the reductions of every selected callback, in one launch
-        ExaReduce R;
-        std::memset(&R, 0, sizeof R);
-        auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
-        if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
-        if (mask & EXA_EV_JTPROD) job(D.jt_map, D.fo, a->jtw);
-        if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
-        if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0
-            R.part = D.tilesum;
-            R.npart = nobj;
-            R.f = a->f;
-        }
-        const bool reduce = R.njobs > 0 || R.part;
-        if (timed && reduce) hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
-        hip_check(exa_launch_reduce(R, s), "exa_eval reductions");
-        if (timed && reduce) hip_check(hipEventRecord(ev[3], s), "hipEventRecord");
-        if (timed) Tm.reduced[Tm.used++] = reduce ? 1 : 0;
-
-        const uint32_t bits[8] = {EXA_EV_OBJ, EXA_EV_GRAD, EXA_EV_CONS, EXA_EV_JAC,
-                                  EXA_EV_HESS, EXA_EV_JPROD, EXA_EV_JTPROD, EXA_EV_HPROD};
-        for (int i = 0; i < 8; ++i)
-            if (mask & bits[i]) M.counters[i]++;
+        need(x, M.nvar, "x");
+        need(y, M.ncon, "y");
+        need(out, M.nvar, "out");
+        exa_eval_args a;
+        std::memset(&a, 0, sizeof a);
+        a.mask = EXA_EV_GRAD | EXA_EV_JTPROD;
+        a.x = x;
+        a.w = y;
+        a.g = out;
+        a.jtw = M.dev->lag_tmp;
+        eval_body(M, &a, (hipStream_t)stream, true, obj_weight);
     });
 }
 

@@ -73,6 +73,7 @@ struct DeviceState {
     double* par = nullptr;
     double* hv = nullptr;             // H v contributions (curved slots only)
     double* tilesum = nullptr;
+    double* lag_tmp = nullptr;  // J^T y of exa_lag_grad (nvar)
     DevMap grad_map, jt_map, h_map, par_map;
 
     void* alloc(size_t bytes);

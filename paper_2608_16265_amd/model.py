@@ -263,6 +263,14 @@ class ExaModel:
                             _stream(x.get_device())))
         return out
 
+    def lag_grad(self, x, y, obj_weight=1.0, out=None):
+        """sigma grad f(x) + J(x)^T y (exa_lag_grad)."""
+        px, py = self._dev(x, self.nvar, "x"), self._dev(y, self.ncon, "y")
+        out = self._out(out, self.nvar, x, "out")
+        check(LIB.exa_lag_grad(self._h, px, py, float(obj_weight), C.c_void_p(out.data_ptr()),
+                               _stream(x.get_device())))
+        return out
+
     def adjoint_theta(self, x, y, obj_weight, w, out=None):
         px, py = self._dev(x, self.nvar, "x"), self._dev(y, self.ncon, "y")
         pw = self._dev(w, self.nvar, "w")

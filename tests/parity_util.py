@@ -82,6 +82,7 @@ def abs_oracle(o, x, y, sigma, v, w, theta=None):
     Ja = sp.coo_matrix((jv, (rj, cj)), shape=(o.ncon, o.nvar))
     out["jprod"] = Ja @ np.abs(v)
     out["jtprod"] = Ja.T @ np.abs(w)
+    out["jtprod_y"] = Ja.T @ np.abs(y)
     rh, ch = o.hess_structure()
     hv = column_scale(o, o.hess_coord(x, y, sigma, theta), 2)
     L = sp.coo_matrix((hv, (rh, ch)), shape=(o.nvar, o.nvar)).tocsr()

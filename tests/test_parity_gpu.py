@@ -127,6 +127,13 @@ def check_all(w, em=None, o=None, tag=""):
     assert_close(tag + "jprod", host(em.jprod(X, Vd)), o.jprod(x, v), a["jprod"])
     assert_close(tag + "jtprod", host(em.jtprod(X, W)), o.jtprod(x, wv), a["jtprod"])
     assert_close(tag + "hprod", host(em.hprod(X, Y, sig, Vd)), o.hprod(x, y, sig, v), a["hprod"])
+    # Lagrangian gradient: the definition, and the two callbacks composed
+    # elementwise (product rounded before the sum) bit for bit
+    lg = em.lag_grad(X, Y, sig)
+    assert_close(tag + "lag_grad", host(lg), sig * o.grad(x) + o.jtprod(x, y),
+                 abs(sig) * a["grad"] + a["jtprod_y"])
+    comp = em.grad(X).mul_(sig).add_(em.jtprod(X, Y))
+    assert np.array_equal(host(lg), host(comp)), tag + "lag_grad vs sigma * grad + jtprod"
     if o.ntheta:
         ref = o.adjoint_theta(x, y, sig, wx)
         got = host(em.adjoint_theta(X, Y, sig, WX))
