@@ -209,7 +209,7 @@ def _callbacks(em, wl, dev="cuda:0"):
     and a zero-argument function per callback.  "eval_all" is every
     per-iterate callback at one point through a single exa_eval call (one
     evaluation launch + one reduction launch), outputs bit-identical to the
-    separate callbacks.  Returns (callbacks, inputs)."""
+    separate callbacks.  Returns (callbacks, (x, y, v, w, jac, hess))."""
     import torch
     X = torch.as_tensor(wl.x, device=dev)
     Y = torch.as_tensor(wl.y, device=dev)
@@ -232,7 +232,7 @@ def _callbacks(em, wl, dev="cuda:0"):
         "lag_grad": lambda: em.lag_grad(X, Y, 1.0, Lg),
     }
     cbs["eval_all"] = em.bind(X, Y, 1.0, V, W, f=f, g=g, c=c, jac=jv, hess=hv, jv=Jv, jtw=Jtw, hv=Hv)
-    return cbs, (X, Y, V, W)
+    return cbs, (X, Y, V, W, jv, hv)
 
 
 def leg_single(name, wl, steps, warmup):
@@ -242,8 +242,13 @@ def leg_single(name, wl, steps, warmup):
     em = ExaModel(wl.model, autotune=True)
     build_s = time.perf_counter() - t0
     e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
-    cbs, (X, Y, V, W) = _callbacks(em, wl)
+    cbs, (X, Y, V, W, jv, hv) = _callbacks(em, wl)
     step = cbs["eval_all"]
+    # compressed sparse columns from the COO values (the solver-side
+    # compression; its structure is analysed once, here)
+    for which, coo in (("jac", jv), ("hess", hv)):
+        buf = e(int(em.csc_structure(which)[0][-1]))
+        cbs[which + "_csc"] = (lambda which=which, coo=coo, buf=buf: em.csc_values(which, coo, buf))
     order = ["obj", "grad", "cons", "jac_hess_coord", "jprod", "jtprod", "hprod"]
 
     def step_separate():

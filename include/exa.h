@@ -242,6 +242,29 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
 exa_status exa_lag_grad(exa_model* m, const double* x, const double* y, double obj_weight, double* out,
                         exa_stream_t stream);
 
+/* Compressed sparse columns (CSC) of the Jacobian (which = EXA_CSC_JAC,
+ * nvar columns) or of the Hessian's lower triangle (EXA_CSC_HESS): the
+ * compression across patterns and data points that the partially compressed
+ * COO layout leaves to the solver (Sec. 5.2).  Each distinct (row, col)
+ * pair of exa_jac_structure / exa_hess_structure is one entry; columns
+ * ascend, rows ascend within a column (0-based).  The structure is analysed
+ * on the host on first use (any of the three calls) and kept.
+ * exa_csc_dims: number of entries into *nnz (host).
+ * exa_csc_structure: host arrays colptr [nvar+1] and rowval [nnz].
+ * exa_csc_values: device arrays; csc [nnz] = the sums of the COO values
+ * coo [nnzj or nnzh] (as written by exa_jac_coord / exa_hess_coord) over
+ * each entry's positions, added in ascending position, so the result does
+ * not depend on scheduling.  One reduction launch on `stream`; the first
+ * call per matrix uploads its map (allocates and synchronizes).  coo and
+ * csc must not overlap.  Errors: EXA_EINVAL for a bad `which`, a NULL
+ * pointer a nonzero size needs, or more than 2^31 - 1 COO entries;
+ * EXA_ESTATE for exa_csc_values on a host-only model. */
+#define EXA_CSC_JAC 0
+#define EXA_CSC_HESS 1
+exa_status exa_csc_dims(const exa_model* m, int32_t which, int64_t* nnz);
+exa_status exa_csc_structure(const exa_model* m, int32_t which, int32_t* colptr, int32_t* rowval);
+exa_status exa_csc_values(exa_model* m, int32_t which, const double* coo, double* csc, exa_stream_t stream);
+
 /* Several callbacks at one point in one call (Sec. 2.1.3 callbacks,
  * evaluated together).  `mask` selects callbacks with the EXA_EV_* bits;
  * every selected callback reads the inputs it needs and writes its output

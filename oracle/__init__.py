@@ -21,6 +21,8 @@ products and the parameter adjoint.  How:
   path;
 * ``nlp``     -- the callbacks, assembled from the definitions (sums over
   data points, COO layout, library matvecs for the products).
+* ``csc``     -- full compression of the COO output into compressed
+  sparse columns (duplicates summed), the solver-side step of Sec. 5.2.
 
 All arithmetic is IEEE float64 (numpy), vectorised over data points.
 
@@ -31,4 +33,4 @@ pinned only through the Rosenbrock probe example, coverage of the dense
 Hessian and symmetry ("parity unpinned" for that order beyond the rule).
 """
 from .nlp import OracleModel  # noqa: F401
-from . import rules, taylor  # noqa: F401
+from . import csc, rules, taylor  # noqa: F401

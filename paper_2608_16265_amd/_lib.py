@@ -97,6 +97,9 @@ def _load():
         "exa_jtprod": (C.c_int32, [vp, vp, vp, vp, vp]),
         "exa_hprod": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_lag_grad": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp]),
+        "exa_csc_dims": (C.c_int32, [vp, C.c_int32, vp]),
+        "exa_csc_structure": (C.c_int32, [vp, C.c_int32, vp, vp]),
+        "exa_csc_values": (C.c_int32, [vp, C.c_int32, vp, vp, vp]),
         "exa_adjoint_theta": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_eval": (C.c_int32, [vp, C.POINTER(EvalArgs), vp]),
         "exa_eval_schedule": (C.c_int32, [vp, C.c_uint32, P_i64]),
@@ -138,7 +141,7 @@ def exported_symbols():
     return ["exa_last_error", "exa_version", "exa_create", "exa_destroy", "exa_dims", "exa_bounds",
             "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
             "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jac_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
-            "exa_lag_grad",
+            "exa_lag_grad", "exa_csc_dims", "exa_csc_structure", "exa_csc_values",
             "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_bytes", "exa_eval_timing", "exa_device_copy",
             "exa_eval_timing_read", "exa_counters", "exa_generated_source", "exa_compile_check",
             "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",

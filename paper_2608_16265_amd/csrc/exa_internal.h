@@ -256,6 +256,15 @@ struct Model {
     // inputs each generated unit really reads, per (mode, unit code)
     std::map<std::pair<int, int>, UnitLive> live;
     std::atomic<int64_t> counters[9];
+    // compressed sparse columns of the Jacobian (0) and of the Hessian's
+    // lower triangle (1), analysed on first use: colptr [nvar+1], rowval,
+    // and the COO positions each entry sums (ascending)
+    struct Csc {
+        bool ready = false;
+        std::vector<int32_t> colptr, rowval;
+        SegMap map;
+    };
+    Csc csc[2];
     std::unique_ptr<DeviceState> dev;
     Model();
     ~Model();

@@ -219,40 +219,10 @@ void build_device(Model& M) {
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
     D.lag_tmp = (double*)D.alloc(M.nvar * sizeof(double));
 
-    // maps go to the device as int32 whenever every position fits
-    auto up_map = [&](const SegMap& S, DevMap& d) {
-        d.nseg = S.nseg();
-        int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
-        top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
-        d.wide = top >= INT32_MAX ? 1 : 0;
-        if (d.wide) {
-            d.ptr = D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
-            d.idx = D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
-        } else {
-            std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
-            d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
-            d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
-            const ChunkPlan P = chunk_plan(S);
-            if (P.chunked) {
-                d.chunked = 1;
-                if (P.nlanes()) {
-                    d.lanes = (const int32_t*)D.upload(P.lanes.data(), P.lanes.size() * sizeof(int32_t));
-                    d.nlanes = P.nlanes();
-                }
-                if (P.nparts()) {
-                    d.longs = (const int32_t*)D.upload(P.longs.data(), P.longs.size() * sizeof(int32_t));
-                    d.lpart = (const int32_t*)D.upload(P.lpart.data(), P.lpart.size() * sizeof(int32_t));
-                    d.nparts = P.nparts();
-                    d.nlong = P.nlong();
-                    d.lsum = (double*)D.alloc(P.nparts() * sizeof(double));
-                }
-            }
-        }
-    };
-    up_map(M.grad_map, D.grad_map);
-    up_map(M.jt_map, D.jt_map);
-    up_map(M.h_map, D.h_map);
-    up_map(M.par_map, D.par_map);
+    upload_map(D, M.grad_map, D.grad_map);
+    upload_map(D, M.jt_map, D.jt_map);
+    upload_map(D, M.h_map, D.h_map);
+    upload_map(D, M.par_map, D.par_map);
     // the caller's float columns are not kept past create
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
 }
@@ -273,6 +243,82 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
         }
 }
 }  // namespace
+
+// maps go to the device as int32 whenever every position fits
+void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
+    d.nseg = S.nseg();
+    int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
+    top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
+    d.wide = top >= INT32_MAX ? 1 : 0;
+    if (d.wide) {
+        d.ptr = D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
+        d.idx = D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
+        return;
+    }
+    std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
+    d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
+    d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
+    const ChunkPlan P = chunk_plan(S);
+    if (!P.chunked) return;
+    d.chunked = 1;
+    if (P.nlanes()) {
+        d.lanes = (const int32_t*)D.upload(P.lanes.data(), P.lanes.size() * sizeof(int32_t));
+        d.nlanes = P.nlanes();
+    }
+    if (P.nparts()) {
+        d.longs = (const int32_t*)D.upload(P.longs.data(), P.longs.size() * sizeof(int32_t));
+        d.lpart = (const int32_t*)D.upload(P.lpart.data(), P.lpart.size() * sizeof(int32_t));
+        d.nparts = P.nparts();
+        d.nlong = P.nlong();
+        d.lsum = (double*)D.alloc(P.nparts() * sizeof(double));
+    }
+}
+
+// Compressed sparse columns of a COO structure (Sec. 5.2: the compression
+// across patterns and data points that the partially compressed layout
+// leaves to the solver).  Positions are bucketed by column in ascending
+// order, then ordered by row within each column (stable, so equal pairs keep
+// ascending position); each distinct (row, col) pair is one entry.
+Model::Csc& csc_form(Model& M, int which) {
+    Model::Csc& C = M.csc[which];
+    if (C.ready) return C;
+    const int64_t nnz = which == 0 ? M.nnzj : M.nnzh;
+    if (nnz >= INT32_MAX) fail(EXA_EINVAL, "compressed columns need fewer than 2^31 entries");
+    std::vector<int32_t> r(nnz), c(nnz);
+    if (which == 0)
+        jac_structure_host(M, r.data(), c.data());
+    else
+        hess_structure_host(M, r.data(), c.data());
+    const int64_t ncol = M.nvar;
+    std::vector<int64_t> start(ncol + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) start[c[k] + 1]++;
+    for (int64_t j = 0; j < ncol; ++j) start[j + 1] += start[j];
+    std::vector<int32_t> pos(nnz);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t k = 0; k < nnz; ++k) pos[fill[c[k]]++] = (int32_t)k;
+    }
+    C.colptr.assign(ncol + 1, 0);
+    C.rowval.clear();
+    C.map.ptr.assign(1, 0);
+    C.map.idx.clear();
+    C.map.idx.reserve(nnz);
+    for (int64_t j = 0; j < ncol; ++j) {
+        auto b = pos.begin() + start[j], e = pos.begin() + start[j + 1];
+        std::stable_sort(b, e, [&](int32_t u, int32_t v) { return r[u] < r[v]; });
+        for (auto it = b; it != e; ++it) {
+            if (it == b || r[*it] != r[*(it - 1)]) {
+                if (it != b) C.map.ptr.push_back((int64_t)C.map.idx.size());
+                C.rowval.push_back(r[*it]);
+            }
+            C.map.idx.push_back(*it);
+        }
+        if (b != e) C.map.ptr.push_back((int64_t)C.map.idx.size());
+        C.colptr[j + 1] = (int32_t)C.rowval.size();
+    }
+    C.ready = true;
+    return C;
+}
 
 ChunkPlan chunk_plan(const SegMap& S) {
     ChunkPlan P;
@@ -1082,6 +1128,47 @@ exa_status exa_lag_grad(exa_model* m, const double* x, const double* y, double o
         a.g = out;
         a.jtw = M.dev->lag_tmp;
         eval_body(M, &a, (hipStream_t)stream, true, obj_weight);
+    });
+}
+
+namespace {
+Model::Csc& csc_checked(const exa_model* m, int32_t which) {
+    if (!m) fail(EXA_EINVAL, "null model");
+    if (which != EXA_CSC_JAC && which != EXA_CSC_HESS) fail(EXA_EINVAL, "which must be EXA_CSC_JAC or EXA_CSC_HESS");
+    // the analysis is a cache of the structure: computing it does not change the model
+    return csc_form(const_cast<exa_model*>(m)->impl, which);
+}
+}  // namespace
+
+exa_status exa_csc_dims(const exa_model* m, int32_t which, int64_t* nnz) {
+    return guard([&] {
+        if (!nnz) fail(EXA_EINVAL, "null nnz");
+        *nnz = (int64_t)csc_checked(m, which).rowval.size();
+    });
+}
+
+exa_status exa_csc_structure(const exa_model* m, int32_t which, int32_t* colptr, int32_t* rowval) {
+    return guard([&] {
+        const Model::Csc& C = csc_checked(m, which);
+        need(colptr, (int64_t)C.colptr.size(), "colptr");
+        need(rowval, (int64_t)C.rowval.size(), "rowval");
+        std::copy(C.colptr.begin(), C.colptr.end(), colptr);
+        std::copy(C.rowval.begin(), C.rowval.end(), rowval);
+    });
+}
+
+exa_status exa_csc_values(exa_model* m, int32_t which, const double* coo, double* csc, exa_stream_t stream) {
+    return guard([&] {
+        const Model::Csc& C = csc_checked(m, which);
+        Model& M = live(m);
+        need(coo, which == EXA_CSC_JAC ? M.nnzj : M.nnzh, "coo");
+        need(csc, (int64_t)C.rowval.size(), "csc");
+        DeviceState& D = *M.dev;
+        if (!D.csc_up[which]) {
+            upload_map(D, C.map, D.csc_map[which]);
+            D.csc_up[which] = true;
+        }
+        segsum(D.csc_map[which], coo, csc, (hipStream_t)stream);
     });
 }
 

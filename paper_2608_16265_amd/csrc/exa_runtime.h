@@ -74,6 +74,8 @@ struct DeviceState {
     double* hv = nullptr;             // H v contributions (curved slots only)
     double* tilesum = nullptr;
     double* lag_tmp = nullptr;  // J^T y of exa_lag_grad (nvar)
+    DevMap csc_map[2];          // uploaded on the first exa_csc_values call
+    bool csc_up[2] = {false, false};
     DevMap grad_map, jt_map, h_map, par_map;
 
     void* alloc(size_t bytes);
@@ -103,6 +105,11 @@ struct ChunkPlan {
 };
 ChunkPlan chunk_plan(const SegMap& S);
 void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);
+// Map and tables of a segment map on the device (int32 when positions fit,
+// chunked when segments are long).
+void upload_map(DeviceState& D, const SegMap& S, DevMap& d);
+// CSC analysis of the Jacobian (which = 0) or Hessian (1) on first use.
+Model::Csc& csc_form(Model& M, int which);
 void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);
 void hess_structure_host(const Model& M, int32_t* rows, int32_t* cols);
 const char* last_error();

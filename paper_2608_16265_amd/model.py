@@ -271,6 +271,29 @@ class ExaModel:
                                _stream(x.get_device())))
         return out
 
+    _CSC = {"jac": 0, "hess": 1}
+
+    def csc_structure(self, which: str):
+        """(colptr [nvar+1], rowval) of the compressed sparse columns of the
+        Jacobian ("jac") or of the Hessian's lower triangle ("hess")."""
+        k = self._CSC[which]
+        nnz = C.c_int64()
+        check(LIB.exa_csc_dims(self._h, k, C.byref(nnz)))
+        colptr = np.empty(self.nvar + 1, dtype=np.int32)
+        rowval = np.empty(nnz.value, dtype=np.int32)
+        check(LIB.exa_csc_structure(self._h, k, _ptr(colptr, C.c_int32), _ptr(rowval, C.c_int32)))
+        return colptr, rowval
+
+    def csc_values(self, which: str, coo, out=None):
+        """Compressed-column values from COO values (exa_csc_values)."""
+        k = self._CSC[which]
+        nnz = C.c_int64()
+        check(LIB.exa_csc_dims(self._h, k, C.byref(nnz)))
+        pc = self._dev(coo, self.nnzj if k == 0 else self.nnzh, "coo")
+        out = self._out(out, nnz.value, coo, "out")
+        check(LIB.exa_csc_values(self._h, k, pc, C.c_void_p(out.data_ptr()), _stream(coo.get_device())))
+        return out
+
     def adjoint_theta(self, x, y, obj_weight, w, out=None):
         px, py = self._dev(x, self.nvar, "x"), self._dev(y, self.ncon, "y")
         pw = self._dev(w, self.nvar, "w")
