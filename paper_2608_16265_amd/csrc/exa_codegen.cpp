@@ -715,12 +715,18 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     os << "    const long long kend = T.start + T.count;\n";
     if (mode == M_OBJ) {
         // virtual lanes (see exa_vlane_sum): one pass per lane this thread holds
+        // every round is unrolled and branch-free (lanes past the end
+        // recompute the last point and add 0.0, as an empty lane always
+        // did), so the loads of all the tile's points can be in flight at once
         os << "    double acc[EXA_VLANES / 64] = {};\n";
-        os << "    for (long long kb = T.start; kb < kend; kb += EXA_VLANES) {\n";
+        os << "#pragma unroll\n";
+        os << "    for (int rd = 0; rd < EXA_OBJ_ROUNDS; ++rd) {\n";
+        os << "        const long long kb = T.start + (long long)rd * EXA_VLANES;\n";
         os << "#pragma unroll\n";
         os << "    for (int q = 0; q < EXA_VLANES / 64; ++q) {\n";
         os << "        if (q * nthr >= EXA_VLANES) break;\n";
-        os << "        const long long k = kb + threadIdx.x + q * nthr;\n";
+        os << "        const long long kr = kb + threadIdx.x + q * nthr;\n";
+        os << "        const long long k = kr < kend ? kr : kend - 1;\n";
     } else {
         os << "    for (long long kb = T.start; kb < kend; kb += nthr) {\n";
         os << "        const long long kr = kb + threadIdx.x;\n";
@@ -741,7 +747,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         else
             os << "        double " << oname(j) << "[" << out_step(M.pats[j.p], j.mode) << "] = {};\n";
     }
-    os << (mode != M_OBJ ? "        {\n" : "        if (k < kend) {\n");
+    os << "        {\n";
 
     // ---- statements: loads (all candidates), then every job's sweeps
     bool weighs = false, seeds = false;
@@ -902,7 +908,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     if (mode == M_OBJ) {
         std::string sum;
         for (const Job& j : jobs) sum += (sum.empty() ? "" : " + ") + oname(j);
-        os << "        acc[q] += " << sum << ";\n";
+        os << "        acc[q] += kr < kend ? " << (jobs.size() > 1 ? "(" + sum + ")" : sum) << " : 0.0;\n";
         os << "    }\n";  // virtual lanes
     }
     for (const Job& j : jobs)
@@ -1074,6 +1080,9 @@ __device__ __forceinline__ double exa_vlane_sum(const double* acc, double* lds) 
 __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je > 0 ? je - 1 : 0); }
 )";
     os << pre;
+    static_assert(kObjBlock * kObjEpl % 256 == 0, "objective tiles hold whole rounds of 256 virtual lanes");
+    os << "// rounds of EXA_VLANES points in one objective tile\n#define EXA_OBJ_ROUNDS " << kObjBlock * kObjEpl / 256
+       << "\n";
     int ntmp = 0;
     // Tile loop shared by every kernel.  Non-persistent launches take one
     // tile per workgroup; workgroup w runs on XCD w % 8, so tile indices are

@@ -45,6 +45,8 @@ constexpr int kExaReduceJobs = 3;
 // has long segments, and one more for the ax_* update).
 struct ExaReduce {
     ExaSegJob job[kExaReduceJobs];
+    // first block after job k (cumulative); set by exa_launch_reduce
+    int64_t bend[kExaReduceJobs];
     int32_t njobs;
     int32_t pad;
     const double* part;

@@ -142,37 +142,39 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, in
 // one per 256 lanes, then one per part of a long segment), then (when
 // R.part is set) one block for the objective partials, summed as k_sum
 // does.
-__device__ __forceinline__ int64_t job_blocks(const ExaSegJob& J) {
+__host__ __device__ inline int64_t job_blocks(const ExaSegJob& J) {
     return J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
 }
 
 __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_xcd) {
     __shared__ double lds[256];
-    int64_t b = xcd_block(per_xcd);
-    for (int k = 0; k < R.njobs; ++k) {
-        const ExaSegJob& J = R.job[k];
-        const int64_t nb = job_blocks(J);
-        if (b < nb) {
-            if (J.chunked) {
-                const int64_t nlb = J.nlanes / kSegBlock;
-                if (b < nlb)
-                    chunk_body(J, b * kSegBlock + threadIdx.x, lds);
-                else
-                    long_part_body(J, b - nlb, lds);
-                return;
-            }
-            const int64_t s = b * kSegBlock + threadIdx.x;
-            if (s < J.nseg) {
-                if (J.wide)
-                    seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s);
-                else
-                    seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s);
-            }
-            return;
-        }
-        b -= nb;
+    const int64_t b0 = xcd_block(per_xcd);
+    // the job from the block ranges (one cache line of arguments), then the
+    // job's fields in one burst, before anything depends on them
+    static_assert(kExaReduceJobs == 3, "the job lookup below reads three block ranges");
+    const int64_t e0 = R.bend[0], e1 = R.bend[1], e2 = R.bend[2];
+    const int k = b0 < e0 ? 0 : b0 < e1 ? 1 : b0 < e2 ? 2 : 3;
+    if (k >= R.njobs) {  // ends past the last job equal the total
+        if (R.part && b0 == e2) sum_body(R.part, R.npart, R.f, lds);
+        return;
     }
-    if (R.part && b == 0) sum_body(R.part, R.npart, R.f, lds);
+    const ExaSegJob J = R.job[k];
+    const int64_t b = b0 - (k == 0 ? 0 : k == 1 ? e0 : e1);
+    if (J.chunked) {
+        const int64_t nlb = J.nlanes / kSegBlock;
+        if (b < nlb)
+            chunk_body(J, b * kSegBlock + threadIdx.x, lds);
+        else
+            long_part_body(J, b - nlb, lds);
+        return;
+    }
+    const int64_t s = b * kSegBlock + threadIdx.x;
+    if (s < J.nseg) {
+        if (J.wide)
+            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s);
+        else
+            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s);
+    }
 }
 
 // Second launch for jobs with long segments: block b adds the part sums of
@@ -248,8 +250,14 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     }
     if (r.ax_out && (!r.ax_add || r.ax_n < 0)) return hipErrorInvalidValue;
     if (blocks > 0) {
+        ExaReduce rr = r;
+        int64_t end = 0;
+        for (int k = 0; k < kExaReduceJobs; ++k) {
+            if (k < r.njobs) end += job_blocks(r.job[k]);
+            rr.bend[k] = end;
+        }
         const int64_t per_xcd = (blocks + 7) / 8;
-        hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, r, per_xcd);
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)(8 * per_xcd)), dim3(kSegBlock), 0, s, rr, per_xcd);
     }
     if (nlong > 0) hipLaunchKernelGGL(k_reduce_long, dim3((unsigned)nlong), dim3(kSegBlock), 0, s, r);
     if (r.ax_out && r.ax_n > 0)
