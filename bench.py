@@ -438,17 +438,20 @@ def leg_ladders():
     """Single instances as they grow (the per-instance scaling study of
     Sec. 8): every callback's time, by the paper's protocol, on the extended
     Rosenbrock objective of eq. rosenbrock at N = 20, 2,000 and 200,000, the
-    ACOPF-shaped model at 118, 1,354 and 78,484 buses and the Goddard rocket
-    of eq. rocket at T = 200, 20,000 and 2,000,000 steps.  Each model's
+    ACOPF-shaped model at 118, 1,354 and 78,484 buses, the Goddard rocket
+    of eq. rocket at T = 200, 20,000 and 2,000,000 steps, and a two-stage
+    stochastic model (8 root variables, 32 per scenario) at 64, 4,096 and
+    65,536 scenarios.  Each model's
     every callback is one evaluation launch plus at most one reduction
     launch, whatever its number of patterns."""
     import torch
-    from exa_modeling.generators import acopf, goddard, rosenbrock
+    from exa_modeling.generators import acopf, goddard, rosenbrock, two_stage
     from paper_2608_16265_amd import ExaModel
     out = {}
     for fam, sizes, make in (("rosenbrock", (20, 2000, 200000), lambda N: rosenbrock(N, 0)),
                              ("acopf", (118, 1354, 78484), lambda nb: acopf(nb, 5)),
-                             ("goddard", (200, 20000, 2000000), lambda T: goddard(T, 0))):
+                             ("goddard", (200, 20000, 2000000), lambda T: goddard(T, 0)),
+                             ("two_stage", (64, 4096, 65536), lambda S: two_stage(S, 8, 32, 0))):
         rows = []
         for size in sizes:
             wl = make(size)

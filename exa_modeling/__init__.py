@@ -16,8 +16,9 @@ from .ir import (Expr, Model, Pattern, VarBlock, ParBlock, DataSet, Node,
 from . import ir as ops  # noqa: F401  (ops.exp, ops.sin, ...)
 from .ir import (exp, log, sin, cos, tan, atan, sinh, cosh, tanh, sqrt, inv,
                  abs2, log1p, expm1)
+from .twostage import TwoStageModel
 
 __all__ = ["Expr", "Model", "Pattern", "VarBlock", "ParBlock", "DataSet",
            "Node", "UNARY_OPS", "BINARY_OPS", "LEAF_OPS", "exp", "log", "sin",
            "cos", "tan", "atan", "sinh", "cosh", "tanh", "sqrt", "inv", "abs2",
-           "log1p", "expm1"]
+           "log1p", "expm1", "TwoStageModel"]

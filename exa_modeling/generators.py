@@ -15,6 +15,8 @@ any of their instances.
   the modeling example of Sec. 2.2.2.
 * :func:`kernel_sweep` -- k of sixteen two-variable constraint patterns over
   a fixed number of rows (the compilation study of Sec. 8.6).
+* :func:`two_stage` -- a two-stage stochastic model (Sec. 7.4.2): a few root
+  variables shared by every scenario, replicated scenario blocks.
 
 Every random draw comes from ``numpy.random.Generator(PCG64(seed))`` in a
 fixed order, documented per function.  Nothing here evaluates the model.
@@ -350,3 +352,34 @@ def kernel_sweep(k: int, n: int, seed: int = 0) -> Workload:
     xv = rng.uniform(-1.0, 1.0, n + 1)
     return Workload(m, xv, rng.standard_normal(m.ncon), 1.0, dict(k=k, n=n))
 
+
+
+def two_stage(S: int, n0: int = 8, nz: int = 32, seed: int = 0) -> Workload:
+    """Two-stage stochastic model of eq. extensions (one batch instance, S
+    scenarios), built with :class:`TwoStageModel`.
+
+    Root: x in R^n0 with the objective 0.5 sum x_i^2 and the rows
+    x_i x_{i+1 mod n0} in [-1, 1].  Scenario s (probability 1/S): z_s in
+    R^nz, parameters d_s in R^nz (theta), objective (1/S) sum_j (z_js - d_js)^2
+    and the rows z_js exp(x_{j mod n0}) - x_{j+1 mod n0}^2 + d_js z_js in
+    [-1, 1], so every root variable is touched by about 2 nz S / n0 terms.
+    Draw order: d ~ N(0,1); then x ~ U(-1,1), z ~ N(0,1); then y ~ N(0,1).
+    """
+    from .twostage import TwoStageModel
+    rng = _rng(seed)
+    m = TwoStageModel(S, f"twostage{S}")
+    x = m.add_var(n0, lvar=-5.0, uvar=5.0, name="x")
+    z = m.add_var(nz, name="z", each_scenario=True)
+    d = m.add_par(rng.standard_normal((nz, S)), name="d", each_scenario=True)
+    root = DataSet(n0, i=np.arange(n0), i1=(np.arange(n0) + 1) % n0)
+    m.add_obj(0.5 * x[root.i] ** 2, root, name="root_obj")
+    m.add_con(x[root.i] * x[root.i1], root, lcon=-1.0, ucon=1.0, name="root_con")
+    j = np.tile(np.arange(nz), S)
+    s = np.repeat(np.arange(S), nz)
+    sc = DataSet(nz * S, k=j + nz * s, xi=j % n0, xn=(j + 1) % n0, scen=s + 1, p=np.full(nz * S, 1.0 / S))
+    m.add_obj(sc.p * (z[sc.k] - d[sc.k]) ** 2, sc, name="scen_obj")
+    m.add_con(z[sc.k] * exp(x[sc.xi]) - x[sc.xn] ** 2 + d[sc.k] * z[sc.k], sc, lcon=-1.0, ucon=1.0,
+              name="scen_con", scenario="scen")
+    xv = np.concatenate([rng.uniform(-1.0, 1.0, n0), rng.standard_normal(nz * S)])
+    y = rng.standard_normal(m.ncon)
+    return Workload(m, xv, y, 1.0, dict(S=S, n0=n0, nz=nz))

@@ -389,7 +389,7 @@ exa_status exa_pattern_info(const exa_model* m, int32_t p, int64_t* out8);
  * cons, jac, hess, jprod, jtprod, hprod, adjoint. */
 exa_status exa_counters(const exa_model* m, int64_t* out9);
 
-/* ---- Batched evaluation (Sec. 6.6.3 batch models, generalised) ----------
+/* ---- Batched evaluation (Sec. 7.4.3 batch models, generalised) ----------
  *
  * B models that share every pattern tree (the same description up to data
  * sizes and values: instances of one formulation) are evaluated together by

@@ -5,8 +5,8 @@ The evaluator writes the Jacobian and the Hessian's lower triangle in the
 partially compressed COO layout of Sec. 5.2: entries from different patterns
 or different data points that land on the same (row, col) position stay
 separate.  A solver that wants compressed sparse columns sums them, and only
-the sums depend on the point; the structure is analysed once (Sec. 5.2,
-Sec. 6.3).
+the sums depend on the point; the structure is analysed once (Sec. 5.2.2,
+Sec. 7.2.3).
 
 Definition written out here: one CSC entry per distinct (row, col) pair of
 the COO structure, columns ascending, rows ascending within a column, value

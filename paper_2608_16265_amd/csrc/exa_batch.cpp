@@ -1,4 +1,4 @@
-// Batched evaluation of many instances of one formulation (Sec. 6.6.3 batch
+// Batched evaluation of many instances of one formulation (Sec. 7.4.3 batch
 // models, generalised to instances of different sizes).
 //
 // All instances share the generated code; their data stays where each model

@@ -10,7 +10,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from exa_modeling.generators import acopf, goddard, pde, rosenbrock
+from exa_modeling.generators import acopf, goddard, pde, rosenbrock, two_stage
 from parity_util import dev, host
 from test_parity_gpu import aliasing_case, empty_pattern_case, single_point_case, star_case
 
@@ -28,6 +28,7 @@ CASES = {
     "star": lambda: star_case([700, 400, 3, 0, 90], 6),  # chunked segment sums
     "goddard": lambda: goddard(60, 1),
     "goddard_long": lambda: goddard(2000, 3),  # long segments: part sums added by a second launch
+    "two_stage": lambda: two_stage(300, 4, 16, 1),
 }
 FIELD = {"obj": "f", "grad": "g", "cons": "c", "jac": "jac", "hess": "hess", "jprod": "jv",
          "jtprod": "jtw", "hprod": "hv"}

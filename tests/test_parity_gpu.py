@@ -10,7 +10,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from exa_modeling import DataSet, Model, exp, sin
-from exa_modeling.generators import Workload, acopf, goddard, kernel_sweep, pde, rosenbrock
+from exa_modeling.generators import Workload, acopf, goddard, kernel_sweep, pde, rosenbrock, two_stage
 from oracle import OracleModel
 from parity_util import RTOL, abs_oracle, assert_close, column_scale, dev, host
 
@@ -89,6 +89,7 @@ CASES = {
     "star_long": lambda: star_case([1500, 2], 7),                 # one long segment: two parts
     "star_parts": lambda: star_case([5000, 1025, 700, 3, 0, 2100], 8),  # long and short segments mixed
     "goddard_long": lambda: goddard(2000, 3),  # dt's segments span several parts
+    "two_stage": lambda: two_stage(300, 4, 16, 1),  # root variables shared by 300 scenarios
     "goddard": lambda: goddard(60, 1),         # dt shared by every point; division, exp, squares
     "sweep16": lambda: kernel_sweep(16, 200, 2),  # sixteen distinct patterns
     "zoo": _zoo,
