@@ -1027,6 +1027,7 @@ __device__ __forceinline__ double exa_powi(double u, int n) {
 // read back by the kernel, and streaming them past the caches keeps x and the
 // data columns resident (intermediate buffers read back by a reduction use
 // ordinary stores).
+typedef double exa_d2 __attribute__((ext_vector_type(2)));
 template <int ST, bool NT>
 __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double* o, int npts, double* lds) {
     if (ST == 1) {
@@ -1039,10 +1040,31 @@ __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double
 #pragma unroll
     for (int s = 0; s < ST; ++s) lds[threadIdx.x * ST + s] = o[s];
     __syncthreads();
+    // 16-byte stores from dst's first 16-byte boundary on; the element
+    // before it (dst is only 8-byte aligned) and an odd last element are
+    // stored on their own
     const int n = npts * ST;
-    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
-        if (NT) __builtin_nontemporal_store(lds[i], &dst[i]);
-        else dst[i] = lds[i];
+    const int a = (int)(((unsigned long long)dst >> 3) & 1ull);
+    const int h = a < n ? a : n;
+    const int n2 = (n - h) >> 1;
+    for (int i = threadIdx.x; i < n2; i += (int)blockDim.x) {
+        exa_d2 v;
+        v.x = lds[h + 2 * i];
+        v.y = lds[h + 2 * i + 1];
+        exa_d2* p = (exa_d2*)(dst + h + 2 * i);
+        if (NT) __builtin_nontemporal_store(v, p);
+        else *p = v;
+    }
+    if (threadIdx.x == 0) {
+        if (h) {
+            if (NT) __builtin_nontemporal_store(lds[0], &dst[0]);
+            else dst[0] = lds[0];
+        }
+        const int last = h + 2 * n2;
+        if (last < n) {
+            if (NT) __builtin_nontemporal_store(lds[last], &dst[last]);
+            else dst[last] = lds[last];
+        }
     }
     __syncthreads();
 }
