@@ -143,10 +143,44 @@ struct Em {
             if (live[i])
                 for (int d : st[i].deps) live[d] = 1;
         }
+        // sin and cos of one argument, both live: one sincos call (a
+        // shared argument reduction), emitted at the first of the two
+        std::map<std::string, std::pair<int, int>> trig;  // argument -> (sin stmt, cos stmt)
+        auto trig_arg = [&](const Stmt& s, bool& is_sin) -> std::string {
+            if (s.raw || s.out || s.expr.size() < 6 || s.expr.back() != ')') return "";
+            const std::string f = s.expr.substr(0, 4);
+            if (f != "sin(" && f != "cos(") return "";
+            const std::string a = s.expr.substr(4, s.expr.size() - 5);
+            for (char c : a)
+                if (!(std::isalnum((unsigned char)c) || c == '_')) return "";
+            is_sin = f == "sin(";
+            return a;
+        };
+        for (size_t i = 0; i < st.size(); ++i) {
+            if (!live[i]) continue;
+            bool is_sin = false;
+            const std::string a = trig_arg(st[i], is_sin);
+            if (a.empty()) continue;
+            auto it = trig.emplace(a, std::make_pair(-1, -1)).first;
+            (is_sin ? it->second.first : it->second.second) = (int)i;
+        }
         std::set<std::string> names;
         for (size_t i = 0; i < st.size(); ++i) {
             if (!live[i]) continue;
             const Stmt& s = st[i];
+            bool is_sin = false;
+            const std::string a = trig_arg(s, is_sin);
+            auto tp = a.empty() ? trig.end() : trig.find(a);
+            if (tp != trig.end() && tp->second.first >= 0 && tp->second.second >= 0) {
+                const int si = tp->second.first, ci = tp->second.second;
+                const std::string sn = st[si].name + "_s", cn = st[si].name + "_c";
+                if ((int)i == std::min(si, ci))
+                    os << ind << "double " << sn << ", " << cn << ";\n" << ind << "sincos(" << a << ", &" << sn
+                       << ", &" << cn << ");\n";
+                os << ind << "const double " << s.name << " = " << (is_sin ? sn : cn) << ";\n";
+                names.insert(s.name);
+                continue;
+            }
             if (s.raw) {
                 os << ind << s.expr << "\n";
             } else if (s.out) {
