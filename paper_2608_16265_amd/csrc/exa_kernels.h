@@ -13,10 +13,11 @@ hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_
 // jobs (int32 maps only) take every segment in chunks of at most kExaChunk
 // consecutive entries, in a summation order fixed by the map:
 // * segments of at most kExaLongSeg entries: lane l adds one chunk, with
-//   lanes[3l] = segment (-1 for padding), lanes[3l+1] = first entry,
-//   lanes[3l+2] = count | (number of chunks of the segment << 4) on the
-//   segment's first chunk; a segment's chunks lie in one 256-lane block, and
-//   its first lane adds the chunk sums in chunk order;
+//   lanes[2l] = segment (-1 for padding), lanes[2l+1] = count | (number of
+//   chunks of the segment << 4) on the segment's first chunk, and
+//   lidx[4l .. 4l+3] = the chunk's buffer positions (the last one repeated
+//   past the count; 0 for padding); a segment's chunks lie in one 256-lane
+//   block, and its first lane adds the chunk sums in chunk order;
 // * longer segments: one block per part of kExaLongSeg entries adds its
 //   chunk sums by a fixed tree into lsum[part], and a second launch adds
 //   each segment's part sums, again in a fixed order.  longs[5i..5i+4] =
@@ -31,6 +32,7 @@ struct ExaSegJob {
     double* out;
     int64_t nseg;
     const int32_t* lanes;
+    const int32_t* lidx;
     int64_t nlanes;  // a multiple of 256
     const int32_t* longs;
     const int32_t* lpart;

@@ -42,35 +42,26 @@ __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __r
 }
 
 // The same sums for maps with long segments: lane l of the job adds one
-// chunk of at most kExaChunk entries (its loads issued together, indices
-// clamped into the chunk), and the segment's first lane adds the chunk sums
-// of its segment, which lie in the same workgroup, in chunk order.  The
-// order depends on the map only.  Called by every lane of the workgroup.
+// chunk of at most kExaChunk entries, whose positions sit in its own lane
+// record, so the record, the positions and then the values are two
+// dependent loads; the segment's first lane adds the chunk sums of its
+// segment, which lie in the same workgroup, in chunk order.  The order
+// depends on the map only.  Called by every lane of the workgroup, with
+// l < J.nlanes (launches cover whole 256-lane blocks).
 __device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double* lds) {
-    const int32_t* __restrict__ idx = (const int32_t*)J.idx;
+    static_assert(kExaChunk == 4, "one int4 of positions per lane");
     const double* __restrict__ buf = J.buf;
-    int32_t seg = -1, beg = 0, info = 0;
-    if (l < J.nlanes) {
-        seg = J.lanes[3 * l];
-        beg = J.lanes[3 * l + 1];
-        info = J.lanes[3 * l + 2];
-    }
-    const int cnt = info & 15;
+    const int2 m = ((const int2*)J.lanes)[l];
+    const int4 ix = ((const int4*)J.lidx)[l];
+    const double v0 = buf[ix.x], v1 = buf[ix.y], v2 = buf[ix.z], v3 = buf[ix.w];
+    const int seg = m.x, cnt = m.y & 15, nl = m.y >> 4;
     double part = 0.0;
-    if (cnt > 0) {
-        int32_t ix[kExaChunk];
-#pragma unroll
-        for (int u = 0; u < kExaChunk; ++u) ix[u] = idx[beg + (u < cnt ? u : cnt - 1)];
-        double v[kExaChunk];
-#pragma unroll
-        for (int u = 0; u < kExaChunk; ++u) v[u] = buf[ix[u]];
-#pragma unroll
-        for (int u = 0; u < kExaChunk; ++u)
-            if (u < cnt) part += v[u];
-    }
+    if (cnt > 0) part += v0;
+    if (cnt > 1) part += v1;
+    if (cnt > 2) part += v2;
+    if (cnt > 3) part += v3;
     lds[threadIdx.x] = part;
     __syncthreads();
-    const int nl = info >> 4;
     if (seg >= 0 && nl > 0) {
         double acc = lds[threadIdx.x];
         for (int i = 1; i < nl; ++i) acc += lds[threadIdx.x + i];
@@ -241,7 +232,7 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     int64_t blocks = r.part ? 1 : 0, nlong = 0;
     for (int k = 0; k < r.njobs; ++k) {
         const ExaSegJob& J = r.job[k];
-        if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !J.lanes) ||
+        if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !(J.lanes && J.lidx)) ||
                           (J.nparts && !(J.longs && J.lpart && J.lsum && J.nlong > 0))))
             return hipErrorInvalidValue;
         if (!J.chunked && J.nparts) return hipErrorInvalidValue;

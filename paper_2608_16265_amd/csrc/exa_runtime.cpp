@@ -262,7 +262,8 @@ void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     if (!P.chunked) return;
     d.chunked = 1;
     if (P.nlanes()) {
-        d.lanes = (const int32_t*)D.upload(P.lanes.data(), P.lanes.size() * sizeof(int32_t));
+        d.lanes = (const int32_t*)D.upload(P.meta.data(), P.meta.size() * sizeof(int32_t));
+        d.lidx = (const int32_t*)D.upload(P.lidx.data(), P.lidx.size() * sizeof(int32_t));
         d.nlanes = P.nlanes();
     }
     if (P.nparts()) {
@@ -327,9 +328,13 @@ ChunkPlan chunk_plan(const SegMap& S) {
     for (int64_t i : S.idx) top = std::max(top, i);
     if (longest <= 2 * kExaChunk || top >= INT32_MAX) return P;
     P.chunked = true;
-    auto& L = P.lanes;
+    // padding lanes: no segment, no entries, indices 0 (a valid position:
+    // a chunked map has entries)
     auto pad_to = [&](int64_t lanes) {
-        while ((int64_t)L.size() / 3 < lanes) L.insert(L.end(), {-1, 0, 0});
+        while (P.nlanes() < lanes) {
+            P.meta.insert(P.meta.end(), {-1, 0});
+            P.lidx.insert(P.lidx.end(), {0, 0, 0, 0});
+        }
     };
     for (int64_t s = 0; s < S.nseg(); ++s) {
         const int64_t b = S.ptr[s], len = S.ptr[s + 1] - b;
@@ -341,16 +346,18 @@ ChunkPlan chunk_plan(const SegMap& S) {
             continue;
         }
         const int64_t nl = std::max<int64_t>(1, (len + kExaChunk - 1) / kExaChunk);
-        const int64_t here = (int64_t)L.size() / 3;
+        const int64_t here = P.nlanes();
         if (here % 256 + nl > 256) pad_to((here / 256 + 1) * 256);
         for (int64_t c = 0; c < nl; ++c) {
-            const int64_t cnt = std::min<int64_t>(kExaChunk, len - c * kExaChunk);
-            L.push_back((int32_t)s);
-            L.push_back((int32_t)(b + c * kExaChunk));
-            L.push_back((int32_t)(std::max<int64_t>(cnt, 0) | (c == 0 ? nl << 4 : 0)));
+            const int64_t cnt = std::max<int64_t>(0, std::min<int64_t>(kExaChunk, len - c * kExaChunk));
+            P.meta.push_back((int32_t)s);
+            P.meta.push_back((int32_t)(cnt | (c == 0 ? nl << 4 : 0)));
+            // the chunk's positions, the last one repeated past its count
+            for (int64_t u = 0; u < kExaChunk; ++u)
+                P.lidx.push_back(cnt ? (int32_t)S.idx[b + c * kExaChunk + std::min(u, cnt - 1)] : 0);
         }
     }
-    pad_to(((int64_t)L.size() / 3 + 255) / 256 * 256);
+    pad_to((P.nlanes() + 255) / 256 * 256);
     return P;
 }
 
@@ -658,6 +665,7 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
     J.nseg = m.nseg;
     J.chunked = m.chunked;
     J.lanes = m.lanes;
+    J.lidx = m.lidx;
     J.nlanes = m.nlanes;
     J.longs = m.longs;
     J.lpart = m.lpart;
@@ -1258,10 +1266,15 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
             const int64_t w = top >= INT32_MAX ? 8 : 4;
             const ChunkPlan P = chunk_plan(S);
-            // chunked maps read their lane and part tables instead of the
-            // segment pointers (the long-segment table once per launch);
-            // each part sum is written once and read once
-            rr += (P.chunked ? 12 * P.nlanes() + 40 * P.nlong() + 12 * P.nparts() : w * (nseg + 1)) + w * nnz +
+            // chunked maps read a 24-byte record per lane (segment, count,
+            // four positions) instead of segment pointers and positions,
+            // positions only for entries of long segments, and their part
+            // tables (the long-segment table once per launch); each part sum
+            // is written once and read once
+            int64_t long_nnz = 0;
+            for (int64_t i = 0; i < P.nlong(); ++i) long_nnz += P.longs[5 * i + 2];
+            rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz + 40 * P.nlong() + 12 * P.nparts()
+                             : w * (nseg + 1) + w * nnz) +
                   8 * nnz;
             rw += 8 * nseg + 8 * P.nparts();
         };

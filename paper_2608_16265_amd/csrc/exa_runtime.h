@@ -29,7 +29,8 @@ struct DevMap {
     int wide = 0;
     // chunked sums (see ExaSegJob) for maps with long segments
     int chunked = 0;
-    const int32_t* lanes = nullptr;
+    const int32_t* lanes = nullptr;  // 2 per lane: segment, count | chunks << 4
+    const int32_t* lidx = nullptr;   // 4 per lane: the chunk's positions
     int64_t nlanes = 0;
     const int32_t* longs = nullptr;
     const int32_t* lpart = nullptr;
@@ -97,9 +98,9 @@ void set_schedule(Model& M, int mode, int block, int epl, bool fused);
 // than 2 * kExaChunk) or when positions need 64 bits.
 struct ChunkPlan {
     bool chunked = false;
-    std::vector<int32_t> lanes;         // 3 per lane, a multiple of 256 lanes
+    std::vector<int32_t> meta, lidx;    // 2 and 4 per lane, a multiple of 256 lanes
     std::vector<int32_t> longs, lpart;  // 5 per long segment; 1 per part
-    int64_t nlanes() const { return (int64_t)lanes.size() / 3; }
+    int64_t nlanes() const { return (int64_t)meta.size() / 2; }
     int64_t nlong() const { return (int64_t)longs.size() / 5; }
     int64_t nparts() const { return (int64_t)lpart.size(); }
 };
