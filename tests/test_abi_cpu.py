@@ -237,3 +237,44 @@ def test_rosenbrock_gradient_operation_count():
            if re.match(r"\s*const double t\d+ = [\w.()]+ [*+-] [\w.()]+;$", ln)]
     assert len(ops) == 9, ops
     assert sum(" * " in ln for ln in ops) == 6 and sum(" - " in ln for ln in ops) == 2
+
+
+def _chunk_plan_bytes(lengths, w=4):
+    """Reduction bytes of one map by its chunk plan, from the segment
+    lengths alone (a second statement of the rule): segments of at most 8
+    entries everywhere -> one lane per segment (pointers + positions);
+    otherwise lanes of at most 4 entries (24-byte records, a segment's lanes
+    inside one 256-lane block, the end padded to whole blocks), and segments
+    over 1,024 entries in parts of 1,024 (their positions read, 20-byte
+    table entries read twice, 12 bytes per part)."""
+    lengths = [int(n) for n in lengths]
+    nnz, nseg = sum(lengths), len(lengths)
+    if max(lengths, default=0) <= 8:
+        return w * (nseg + 1) + w * nnz + 8 * nnz, 8 * nseg
+    lanes = nlong = nparts = long_nnz = 0
+    for n in lengths:
+        if n > 1024:
+            nlong += 1
+            nparts += -(-n // 1024)
+            long_nnz += n
+            continue
+        nl = max(1, -(-n // 4))
+        if lanes % 256 + nl > 256:
+            lanes = (lanes // 256 + 1) * 256
+        lanes += nl
+    lanes = -(-lanes // 256) * 256
+    return 24 * lanes + 4 * long_nnz + 40 * nlong + 12 * nparts + 8 * nnz, 8 * nseg + 8 * nparts
+
+
+@pytest.mark.parametrize("sizes", [[700, 400, 3, 0, 90], [1500, 2], [5000, 1025, 700, 3, 0, 2100]],
+                         ids=["chunked", "one_long", "mixed"])
+def test_reduction_bytes_follow_the_chunk_plan(sizes):
+    from paper_2608_16265_amd import ExaModel
+    from test_parity_gpu import star_case
+    w = star_case(sizes, 1)
+    em = ExaModel(w.model, host_only=True)
+    o = OracleModel(w.model)
+    _, cols = o.jac_structure()
+    rd, wr = _chunk_plan_bytes(np.bincount(cols, minlength=o.nvar))
+    b = em.eval_bytes(("jtprod",))
+    assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
