@@ -21,7 +21,10 @@
  *     (exa_stream_t is a hipStream_t; NULL is the null stream) and do not
  *     synchronize, except the first call of a callback (or of an exa_eval
  *     mask) on a model with autotune on, which times candidate schedules on
- *     that stream and waits for them.
+ *     that stream and waits for them, and the first exa_csc_values call per
+ *     matrix.  After those first calls, a callback only enqueues kernels on
+ *     its stream (no allocation, no copy, no memset, no host wait), so a
+ *     caller may capture it into a HIP graph and replay it.
  *   - Every call returns an exa_status; on failure nothing has been written
  *     to the outputs that the caller could mistake for a result only if the
  *     failure is reported before launch (argument checks); a failure of the
