@@ -441,9 +441,9 @@ def leg_ladders():
     ACOPF-shaped model at 118, 1,354 and 78,484 buses, the Goddard rocket
     of eq. rocket at T = 200, 20,000 and 2,000,000 steps, and a two-stage
     stochastic model (8 root variables, 32 per scenario) at 64, 4,096 and
-    65,536 scenarios.  Each model's
-    every callback is one evaluation launch plus at most one reduction
-    launch, whatever its number of patterns."""
+    65,536 scenarios.  Each model's every callback is one evaluation launch
+    plus at most one reduction launch (one more where a variable is shared
+    by more than 1,024 terms), whatever its number of patterns."""
     import torch
     from exa_modeling.generators import acopf, goddard, rosenbrock, two_stage
     from paper_2608_16265_amd import ExaModel

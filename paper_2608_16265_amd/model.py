@@ -334,8 +334,9 @@ class ExaModel:
     def evaluate(self, x, y=None, obj_weight=1.0, v=None, w=None, *, f=None, g=None, c=None, jac=None,
                  hess=None, jv=None, jtw=None, hv=None):
         """Every callback whose output tensor is given, at one point, through
-        exa_eval: one evaluation launch plus at most one reduction launch, each
-        output bit-identical to its own callback's.  Outputs: f (obj), g
+        exa_eval: one evaluation launch plus at most one reduction launch (one
+        more for segments over 1,024 entries), each output bit-identical to
+        its own callback's.  Outputs: f (obj), g
         (grad), c (cons), jac, hess, jv (jprod), jtw (jtprod), hv (hprod)."""
         a, _ = self._eval_args(x, y, obj_weight, v, w, dict(f=f, g=g, c=c, jac=jac, hess=hess, jv=jv, jtw=jtw,
                                                              hv=hv))
