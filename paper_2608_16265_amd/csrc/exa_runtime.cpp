@@ -410,28 +410,37 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
-    float best = 1e30f;
-    int bb = M.block, be = M.epl;
-    bool bf = M.fuse;
+    struct Cand {
+        float ms;
+        int block, epl, fused;
+    };
+    auto time_it = [&](int reps) {
+        raw_launch(M, mode, call, s);
+        hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int r = 0; r < reps; ++r) raw_launch(M, mode, call, s);
+        hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        return ms / reps;
+    };
+    std::vector<Cand> cands;
     try {
         for (int f : fuses)
             for (int b : blocks)
                 for (int ep : epls) {
                     set_schedule(M, mode, b, ep, f != 0);
-                    raw_launch(M, mode, call, s);
-                    hip_check(hipEventRecord(e0, s), "hipEventRecord");
-                    for (int r = 0; r < 3; ++r) raw_launch(M, mode, call, s);
-                    hip_check(hipEventRecord(e1, s), "hipEventRecord");
-                    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                    float ms = 0;
-                    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                    if (ms < best) {
-                        best = ms;
-                        bb = b;
-                        be = ep;
-                        bf = f != 0;
-                    }
+                    cands.push_back({time_it(3), b, ep, f});
                 }
+        // as in tune_multi: the fastest few again, longer, in turns
+        std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+        cands.resize(std::min<size_t>(cands.size(), 4));
+        for (auto& c : cands) c.ms = 1e30f;
+        for (int round = 0; round < 3; ++round)
+            for (auto& c : cands) {
+                set_schedule(M, mode, c.block, c.epl, c.fused != 0);
+                c.ms = std::min(c.ms, time_it(12));
+            }
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -439,7 +448,8 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    set_schedule(M, mode, bb, be, bf);
+    const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    set_schedule(M, mode, w.block, w.epl, w.fused != 0);
     M.dev->sched[mode].tuned = true;
 }
 }  // namespace
