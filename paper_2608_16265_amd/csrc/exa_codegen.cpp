@@ -625,18 +625,24 @@ bool staged(const Pattern& P, int mode) { return out_step(P, mode) * EXA_BLOCK_M
 
 // Output destination of member P's slice for data point kb (first of the
 // workgroup's current points).
-std::string dest(const Pattern& P, int mode, const std::string& pd, const std::string& out = "C.out0") {
-    const std::string st = std::to_string(out_step(P, mode));
+// (at_kb false: the start of the member's block, for slot-major buffers).
+std::string dest(const Pattern& P, int mode, const std::string& pd, const std::string& out = "C.out0",
+                 bool at_kb = true) {
+    const std::string st = at_kb ? " + kb * " + std::to_string(out_step(P, mode)) : "";
     switch (mode) {
-        case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1 + kb * " + st;
-        case M_JAC: return out + " + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1 + kb * " + st;
-        case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1 + kb * " + st;
-        case M_HPROD: return out + " + " + pd + ".oh + kb * " + st;
-        case M_HESS: return out + " + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2 + kb * " + st;
-        case M_ADJ: return out + " + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op + kb * " + st;
+        case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1" + st;
+        case M_JAC: return out + " + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1" + st;
+        case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1" + st;
+        case M_HPROD: return out + " + " + pd + ".oh" + st;
+        case M_HESS: return out + " + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2" + st;
+        case M_ADJ: return out + " + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op" + st;
         default: return "";
     }
 }
+
+// Modes whose per-point outputs go to a work buffer read back by a
+// reduction (stored slot-major); the others write final outputs.
+bool buffer_mode(int mode) { return mode == M_GRAD || mode == M_JTPROD || mode == M_HPROD || mode == M_ADJ; }
 
 // The evaluations a unit performs for one data point: (pattern, sub-mode).
 // A combined Jacobian + Hessian unit runs both sweeps of each member over
@@ -857,10 +863,19 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 e.out("if (" + call(M_GRAD) + ".direct && kr < kend) " + call(M_GRAD) + ".out0[I.off[" +
                           std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
                       oname(j) + "[" + std::to_string(s) + "]");
-        if (!scalar_mode(j.mode)) {
+        if (buffer_mode(j.mode)) {
+            // contributions to a work buffer that a reduction reads back: slot
+            // s of data point k at block + s * ndata + k, one coalesced store
+            // per slot and no staging (the reduction's gathers of one slot
+            // over neighbouring points are then neighbouring too)
+            std::string line = j.mode == M_GRAD ? "if (!" + call(M_GRAD) + ".direct) " : "";
+            line += "exa_store_soa<" + std::to_string(out_step(P, j.mode)) + ">(" + dest(P, j.mode, pd, j.out, false) +
+                    ", " + pd + ".ndata, kr, kend, " + oname(j) + ");";
+            e.raw(line);
+        } else if (!scalar_mode(j.mode)) {
             // this job's outputs leave registers as soon as they are complete
             const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
-            std::string line = j.mode == M_GRAD ? "if (!" + call(M_GRAD) + ".direct) " : "";
+            std::string line;
             if (staged(P, j.mode))
                 line += "exa_store<" + std::to_string(out_step(P, j.mode)) + ", " + (final_out ? "true" : "false") + ">(";
             else
@@ -1028,8 +1043,9 @@ int mode_lds_doubles(const Model& M, int mode) {
         return d;
     }
     int st = 1;
-    for (auto& P : M.pats)
-        if (pattern_in_mode(P, mode) && staged(P, mode)) st = std::max(st, out_step(P, mode));
+    if (!buffer_mode(mode))
+        for (auto& P : M.pats)
+            if (pattern_in_mode(P, mode) && staged(P, mode)) st = std::max(st, out_step(P, mode));
     return st * EXA_BLOCK_MAX;
 }
 
@@ -1101,6 +1117,16 @@ __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double
         }
     }
     __syncthreads();
+}
+// Slot-major store to a work buffer: slot s of data point k at
+// base[s * n + k] (lanes past the end of the tile store nothing).
+template <int ST>
+__device__ __forceinline__ void exa_store_soa(double* __restrict__ base, long long n, long long k, long long kend,
+                                              const double* o) {
+    if (k < kend) {
+#pragma unroll
+        for (int s = 0; s < ST; ++s) base[s * n + k] = o[s];
+    }
 }
 // Direct (unstaged) variant for slices too wide for LDS.
 template <int ST>

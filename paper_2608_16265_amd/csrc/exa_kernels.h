@@ -9,9 +9,11 @@ hipError_t exa_launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 // One segment-sum job: out[s] = sum of buf[idx[j]], j in [ptr[s], ptr[s+1]).
-// Unless chunked is set, one lane sums one segment in ascending j.  Chunked
-// jobs (int32 maps only) take every segment in chunks of at most kExaChunk
-// consecutive entries, in a summation order fixed by the map:
+// Unless chunked is set, one lane sums one segment in ascending j, except
+// segments longer than kExaLongSeg when the job has parts (nparts > 0),
+// which the parts below sum.  Chunked jobs (int32 maps only) take every
+// segment in chunks of at most kExaChunk consecutive entries, in a
+// summation order fixed by the map:
 // * segments of at most kExaLongSeg entries: lane l adds one chunk, with
 //   lanes[2l] = segment (-1 for padding), lanes[2l+1] = count | (number of
 //   chunks of the segment << 4) on the segment's first chunk, and
@@ -25,6 +27,7 @@ hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_
 //   and part q belongs to long segment lpart[q].
 constexpr int kExaChunk = 4;
 constexpr int kExaLongSeg = 256 * kExaChunk;
+constexpr int kExaShortSeg = 16;
 struct ExaSegJob {
     const void* ptr;
     const void* idx;

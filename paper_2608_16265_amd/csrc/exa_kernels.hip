@@ -23,8 +23,10 @@ __device__ __forceinline__ int64_t xcd_block(int64_t per_xcd) {
 // a fixed summation order so the result does not depend on scheduling.
 template <class I>
 __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __restrict__ idx,
-                                         const double* __restrict__ buf, double* __restrict__ out, int64_t s) {
+                                         const double* __restrict__ buf, double* __restrict__ out, int64_t s,
+                                         bool parts) {
     const int64_t b = ptr[s], e = ptr[s + 1];
+    if (parts && e - b > kExaLongSeg) return;  // summed in parts
     double acc = 0.0;
     int64_t j = b;
     // four entries at a time: their index and value loads are issued
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, in
 // R.part is set) one block for the objective partials, summed as k_sum
 // does.
 __host__ __device__ inline int64_t job_blocks(const ExaSegJob& J) {
-    return J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
+    return (J.chunked ? J.nlanes / kSegBlock : (J.nseg + kSegBlock - 1) / kSegBlock) + J.nparts;
 }
 
 __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_xcd) {
@@ -159,12 +161,17 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
             long_part_body(J, b - nlb, lds);
         return;
     }
+    const int64_t nsb = (J.nseg + kSegBlock - 1) / kSegBlock;
+    if (b >= nsb) {
+        long_part_body(J, b - nsb, lds);
+        return;
+    }
     const int64_t s = b * kSegBlock + threadIdx.x;
     if (s < J.nseg) {
         if (J.wide)
-            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s);
+            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false);
         else
-            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s);
+            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0);
     }
 }
 
@@ -232,12 +239,11 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     int64_t blocks = r.part ? 1 : 0, nlong = 0;
     for (int k = 0; k < r.njobs; ++k) {
         const ExaSegJob& J = r.job[k];
-        if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !(J.lanes && J.lidx)) ||
-                          (J.nparts && !(J.longs && J.lpart && J.lsum && J.nlong > 0))))
+        if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !(J.lanes && J.lidx))))
             return hipErrorInvalidValue;
-        if (!J.chunked && J.nparts) return hipErrorInvalidValue;
-        blocks += J.chunked ? J.nlanes / kSegBlock + J.nparts : (J.nseg + kSegBlock - 1) / kSegBlock;
-        nlong += J.chunked ? J.nlong : 0;
+        if (J.nparts && (J.wide || !(J.longs && J.lpart && J.lsum && J.nlong > 0))) return hipErrorInvalidValue;
+        blocks += job_blocks(J);
+        nlong += J.nparts ? J.nlong : 0;
     }
     if (r.ax_out && (!r.ax_add || r.ax_n < 0)) return hipErrorInvalidValue;
     if (blocks > 0) {

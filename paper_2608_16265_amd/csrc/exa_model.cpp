@@ -267,7 +267,8 @@ void validate_desc(const exa_pattern_desc& d, int p, int npats, const exa_patter
 }
 
 void build_map(SegMap& M, int64_t nseg, const std::vector<std::pair<int64_t, int64_t>>& tp) {
-    // tp: (target segment, buffer position), already in ascending position order
+    // tp: (target segment, buffer position) in summation order; a segment
+    // keeps its entries in that order
     M.ptr.assign(nseg + 1, 0);
     for (auto& e : tp) M.ptr[e.first + 1]++;
     for (int64_t s = 0; s < nseg; ++s) M.ptr[s + 1] += M.ptr[s];
@@ -438,7 +439,10 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
         for (int64_t k = 0; k < P.ndata; ++k) P.ridx[fill[(int64_t)P.icols[P.row_icol][k] + P.row_off]++] = (int32_t)k;
     }
 
-    // ---- reduction maps (Sec. 7.2.3): sorted by target, ascending positions
+    // ---- reduction maps (Sec. 7.2.3): sorted by target; within a target
+    // the contributions are summed in (pattern, data point, slot) order.
+    // The work buffers hold each pattern's block slot-major: slot s of data
+    // point k at block + s * ndata + k.
     std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr;
     for (auto& P : M.pats) {
         const int st = P.o1step();
@@ -446,19 +450,18 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             for (int s = 0; s < st; ++s) {
                 const int64_t v = P.var_index(s, k);
                 if (P.kind == EXA_OBJ)
-                    g.emplace_back(v, P.o1 + k * st + s);
+                    g.emplace_back(v, P.o1 + s * P.ndata + k);
                 else
-                    jt.emplace_back(v, nnzg + P.o1 + k * st + s);
+                    jt.emplace_back(v, nnzg + P.o1 + s * P.ndata + k);
             }
         const int hs = (int)P.hvs.size();
         for (int64_t k = 0; k < P.ndata; ++k)
-            for (int i = 0; i < hs; ++i) h.emplace_back(P.var_index(P.hvs[i], k), P.oh + k * hs + i);
+            for (int i = 0; i < hs; ++i) h.emplace_back(P.var_index(P.hvs[i], k), P.oh + i * P.ndata + k);
         if (P.pstep() > 0 && P.o1step() > 0)
             for (int64_t k = 0; k < P.ndata; ++k)
                 for (int t = 0; t < P.pstep(); ++t)
-                    pr.emplace_back(P.par_index(t, k), P.op + k * P.pstep() + t);
+                    pr.emplace_back(P.par_index(t, k), P.op + t * P.ndata + k);
     }
-    // H v positions follow declaration order, so h is ascending as built.
     build_map(M.grad_map, M.nvar, g);
     M.grad_direct = true;
     for (int64_t v = 0; v < M.nvar; ++v)

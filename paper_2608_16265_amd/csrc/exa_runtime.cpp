@@ -259,8 +259,7 @@ void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
     d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
     const ChunkPlan P = chunk_plan(S);
-    if (!P.chunked) return;
-    d.chunked = 1;
+    d.chunked = P.chunked ? 1 : 0;
     if (P.nlanes()) {
         d.lanes = (const int32_t*)D.upload(P.meta.data(), P.meta.size() * sizeof(int32_t));
         d.lidx = (const int32_t*)D.upload(P.lidx.data(), P.lidx.size() * sizeof(int32_t));
@@ -327,7 +326,16 @@ ChunkPlan chunk_plan(const SegMap& S) {
     for (int64_t s = 0; s < S.nseg(); ++s) longest = std::max(longest, S.ptr[s + 1] - S.ptr[s]);
     for (int64_t i : S.idx) top = std::max(top, i);
     if (longest <= 2 * kExaChunk || top >= INT32_MAX) return P;
-    P.chunked = true;
+    int64_t longest_short = 0, long_nnz = 0;
+    for (int64_t s = 0; s < S.nseg(); ++s) {
+        const int64_t len = S.ptr[s + 1] - S.ptr[s];
+        if (len > kExaLongSeg)
+            long_nnz += len;
+        else
+            longest_short = std::max(longest_short, len);
+    }
+    // large maps (bandwidth-bound) whose only long segments are parts
+    P.chunked = !(longest_short <= kExaShortSeg && (int64_t)S.idx.size() - long_nnz >= (int64_t)1 << 22);
     // padding lanes: no segment, no entries, indices 0 (a valid position:
     // a chunked map has entries)
     auto pad_to = [&](int64_t lanes) {
@@ -345,6 +353,7 @@ ChunkPlan chunk_plan(const SegMap& S) {
             P.lpart.insert(P.lpart.end(), (size_t)parts, (int32_t)ls);
             continue;
         }
+        if (!P.chunked) continue;
         const int64_t nl = std::max<int64_t>(1, (len + kExaChunk - 1) / kExaChunk);
         const int64_t here = P.nlanes();
         if (here % 256 + nl > 256) pad_to((here / 256 + 1) * 256);
@@ -357,7 +366,7 @@ ChunkPlan chunk_plan(const SegMap& S) {
                 P.lidx.push_back(cnt ? (int32_t)S.idx[b + c * kExaChunk + std::min(u, cnt - 1)] : 0);
         }
     }
-    pad_to((P.nlanes() + 255) / 256 * 256);
+    if (P.chunked) pad_to((P.nlanes() + 255) / 256 * 256);
     return P;
 }
 
@@ -1289,15 +1298,15 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             const int64_t w = top >= INT32_MAX ? 8 : 4;
             const ChunkPlan P = chunk_plan(S);
             // chunked maps read a 24-byte record per lane (segment, count,
-            // four positions) instead of segment pointers and positions,
-            // positions only for entries of long segments, and their part
-            // tables (the long-segment table once per launch); each part sum
-            // is written once and read once
+            // four positions) instead of segment pointers and positions, and
+            // positions only for the entries of long segments; maps with
+            // long segments read their part tables (the long-segment table
+            // once per launch), and each part sum is written once and read
+            // once
             int64_t long_nnz = 0;
             for (int64_t i = 0; i < P.nlong(); ++i) long_nnz += P.longs[5 * i + 2];
-            rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz + 40 * P.nlong() + 12 * P.nparts()
-                             : w * (nseg + 1) + w * nnz) +
-                  8 * nnz;
+            rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz : w * (nseg + 1) + w * nnz) + 40 * P.nlong() +
+                  12 * P.nparts() + 8 * nnz;
             rw += 8 * nseg + 8 * P.nparts();
         };
         if ((mask & EXA_EV_GRAD) && !M.grad_direct) seg(M.grad_map);

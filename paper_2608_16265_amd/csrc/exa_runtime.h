@@ -92,12 +92,14 @@ std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile
 std::string kernel_name(int mode);
 int mode_lds_doubles(const Model& M, int mode);
 void set_schedule(Model& M, int mode, int block, int epl, bool fused);
-// How a map's segments are summed in chunks (see ExaSegJob): chunk lanes
-// for segments of at most kExaLongSeg entries, parts for longer ones.
-// chunked is false when one lane per segment is enough (no segment longer
-// than 2 * kExaChunk) or when positions need 64 bits.
+// How a map's segments are summed (see ExaSegJob): one lane per segment
+// when no segment is longer than 2 * kExaChunk (or positions need 64 bits);
+// otherwise parts of kExaLongSeg entries for segments longer than that, and
+// for the others chunk lanes, except on large maps whose other segments are
+// all short (at most kExaShortSeg entries), where one lane per segment reads
+// fewer bytes than a 24-byte lane record per segment.
 struct ChunkPlan {
-    bool chunked = false;
+    bool chunked = false;  // chunk lanes (else one lane per segment)
     std::vector<int32_t> meta, lidx;    // 2 and 4 per lane, a multiple of 256 lanes
     std::vector<int32_t> longs, lpart;  // 5 per long segment; 1 per part
     int64_t nlanes() const { return (int64_t)meta.size() / 2; }

@@ -240,30 +240,35 @@ def test_rosenbrock_gradient_operation_count():
 
 
 def _chunk_plan_bytes(lengths, w=4):
-    """Reduction bytes of one map by its chunk plan, from the segment
-    lengths alone (a second statement of the rule): segments of at most 8
-    entries everywhere -> one lane per segment (pointers + positions);
-    otherwise lanes of at most 4 entries (24-byte records, a segment's lanes
-    inside one 256-lane block, the end padded to whole blocks), and segments
-    over 1,024 entries in parts of 1,024 (their positions read, 20-byte
-    table entries read twice, 12 bytes per part)."""
+    """Reduction bytes of one map by its plan, from the segment lengths
+    alone (a second statement of the rule): segments of at most 8 entries
+    everywhere -> one lane per segment (pointers + positions).  Otherwise
+    segments over 1,024 entries are summed in parts of 1,024 (20-byte table
+    entries read twice, 12 bytes per part), and the others either one lane
+    per segment (when none has more than 16 entries and they hold at least
+    2^22 entries together) or in lanes of at most 4 entries (24-byte
+    records, a segment's lanes inside one 256-lane block, the end padded to
+    whole blocks; the positions of long segments read besides)."""
     lengths = [int(n) for n in lengths]
     nnz, nseg = sum(lengths), len(lengths)
     if max(lengths, default=0) <= 8:
         return w * (nseg + 1) + w * nnz + 8 * nnz, 8 * nseg
-    lanes = nlong = nparts = long_nnz = 0
-    for n in lengths:
-        if n > 1024:
-            nlong += 1
-            nparts += -(-n // 1024)
-            long_nnz += n
-            continue
-        nl = max(1, -(-n // 4))
-        if lanes % 256 + nl > 256:
-            lanes = (lanes // 256 + 1) * 256
-        lanes += nl
-    lanes = -(-lanes // 256) * 256
-    return 24 * lanes + 4 * long_nnz + 40 * nlong + 12 * nparts + 8 * nnz, 8 * nseg + 8 * nparts
+    longs = [n for n in lengths if n > 1024]
+    short = [n for n in lengths if n <= 1024]
+    nlong, nparts, long_nnz = len(longs), sum(-(-n // 1024) for n in longs), sum(longs)
+    chunked = not (max(short, default=0) <= 16 and nnz - long_nnz >= 1 << 22)
+    if chunked:
+        lanes = 0
+        for n in short:
+            nl = max(1, -(-n // 4))
+            if lanes % 256 + nl > 256:
+                lanes = (lanes // 256 + 1) * 256
+            lanes += nl
+        lanes = -(-lanes // 256) * 256
+        maps = 24 * lanes + 4 * long_nnz
+    else:
+        maps = w * (nseg + 1) + w * nnz
+    return maps + 40 * nlong + 12 * nparts + 8 * nnz, 8 * nseg + 8 * nparts
 
 
 @pytest.mark.parametrize("sizes", [[700, 400, 3, 0, 90], [1500, 2], [5000, 1025, 700, 3, 0, 2100]],
@@ -276,5 +281,18 @@ def test_reduction_bytes_follow_the_chunk_plan(sizes):
     o = OracleModel(w.model)
     _, cols = o.jac_structure()
     rd, wr = _chunk_plan_bytes(np.bincount(cols, minlength=o.nvar))
+    b = em.eval_bytes(("jtprod",))
+    assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
+
+
+def test_reduction_bytes_large_map_with_one_shared_variable():
+    """Goddard's step variable is shared by all 3T rows: on a large model its
+    segment is summed in parts and every other variable one lane each."""
+    from paper_2608_16265_amd import ExaModel
+    em = ExaModel(goddard(300000, 0).model, host_only=True)
+    _, cols = em.jac_structure()
+    lengths = np.bincount(cols, minlength=em.nvar)
+    assert lengths.max() > 1024 and np.sort(lengths)[-2] <= 16
+    rd, wr = _chunk_plan_bytes(lengths)
     b = em.eval_bytes(("jtprod",))
     assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
