@@ -235,9 +235,10 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
 /* Gradient of the Lagrangian of eq. nlp, sigma grad f(x) + J(x)^T y, into
  * out [nvar]; x [nvar] and y [ncon] are device arrays, sigma = obj_weight
  * (the first-order half of what hess_coord weights, Sec. 2.1.3).  One
- * evaluation launch of the gradient and J^T y terms, their reductions, and
- * one elementwise launch out = sigma * grad + J^T y with the product rounded
- * before the sum: bit-identical to exa_grad into out, exa_jtprod into t and
+ * evaluation launch of the gradient and J^T y terms and their reductions,
+ * which finish out = sigma * grad + J^T y with the product rounded before
+ * the sum (one elementwise launch more when the gradient itself needs a
+ * reduction): bit-identical to exa_grad into out, exa_jtprod into t and
  * then out = sigma * out followed by out = out + t.  Uses a library-owned
  * nvar buffer for J^T y, so overlapping calls on one model race.  Counts
  * as one grad and one jtprod evaluation.  Errors: EXA_EINVAL for a NULL

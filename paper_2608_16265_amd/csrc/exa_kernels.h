@@ -53,7 +53,9 @@ struct ExaReduce {
     // first block after job k (cumulative); set by exa_launch_reduce
     int64_t bend[kExaReduceJobs];
     int32_t njobs;
-    int32_t pad;
+    // job whose sums are added to ax_alpha times its output's old values
+    // (out[s] = ax_alpha * out[s] + sum, the product rounded first), or -1
+    int32_t ep_job;
     const double* part;
     int64_t npart;
     double* f;

@@ -18,13 +18,26 @@ __device__ __forceinline__ int64_t xcd_block(int64_t per_xcd) {
     return (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
 }
 
+// A segment's result: out[s] = acc, or with the epilogue out[s] = alpha *
+// out[s] + acc, the product rounded before the sum (as two separate
+// elementwise operations would give).
+__device__ __forceinline__ void put(double* __restrict__ out, int64_t s, double acc, bool ep, double alpha) {
+#pragma clang fp contract(off)
+    if (ep) {
+        const double p = alpha * out[s];
+        out[s] = p + acc;
+    } else {
+        out[s] = acc;
+    }
+}
+
 // out[s] = sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
 // the sparse-to-dense compression of Sec. 7.2.3, one lane per segment, with
 // a fixed summation order so the result does not depend on scheduling.
 template <class I>
 __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __restrict__ idx,
                                          const double* __restrict__ buf, double* __restrict__ out, int64_t s,
-                                         bool parts) {
+                                         bool parts, bool ep, double alpha) {
     const int64_t b = ptr[s], e = ptr[s + 1];
     if (parts && e - b > kExaLongSeg) return;  // summed in parts
     double acc = 0.0;
@@ -40,7 +53,7 @@ __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __r
         acc += v3;
     }
     for (; j < e; ++j) acc += buf[idx[j]];
-    out[s] = acc;
+    put(out, s, acc, ep, alpha);
 }
 
 // The same sums for maps with long segments: lane l of the job adds one
@@ -50,7 +63,7 @@ __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __r
 // segment, which lie in the same workgroup, in chunk order.  The order
 // depends on the map only.  Called by every lane of the workgroup, with
 // l < J.nlanes (launches cover whole 256-lane blocks).
-__device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double* lds) {
+__device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double* lds, bool ep, double alpha) {
     static_assert(kExaChunk == 4, "one int4 of positions per lane");
     const double* __restrict__ buf = J.buf;
     const int2 m = ((const int2*)J.lanes)[l];
@@ -67,7 +80,7 @@ __device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double
     if (seg >= 0 && nl > 0) {
         double acc = lds[threadIdx.x];
         for (int i = 1; i < nl; ++i) acc += lds[threadIdx.x + i];
-        J.out[seg] = acc;
+        put(J.out, seg, acc, ep, alpha);
     }
     __syncthreads();
 }
@@ -153,10 +166,11 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
     }
     const ExaSegJob J = R.job[k];
     const int64_t b = b0 - (k == 0 ? 0 : k == 1 ? e0 : e1);
+    const bool ep = k == R.ep_job;
     if (J.chunked) {
         const int64_t nlb = J.nlanes / kSegBlock;
         if (b < nlb)
-            chunk_body(J, b * kSegBlock + threadIdx.x, lds);
+            chunk_body(J, b * kSegBlock + threadIdx.x, lds, ep, R.ax_alpha);
         else
             long_part_body(J, b - nlb, lds);
         return;
@@ -169,9 +183,9 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
     const int64_t s = b * kSegBlock + threadIdx.x;
     if (s < J.nseg) {
         if (J.wide)
-            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false);
+            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false, ep, R.ax_alpha);
         else
-            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0);
+            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0, ep, R.ax_alpha);
     }
 }
 
@@ -189,7 +203,7 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce_long(ExaReduce R) {
             double acc = 0.0;
             for (int32_t i = threadIdx.x; i < nparts; i += 256) acc += J.lsum[part0 + i];
             const double tot = block_sum(acc, lds);
-            if (threadIdx.x == 0) J.out[seg] = tot;
+            if (threadIdx.x == 0) put(J.out, seg, tot, k == R.ep_job, R.ax_alpha);
             return;
         }
         b -= J.nlong;
@@ -246,6 +260,7 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
         nlong += J.nparts ? J.nlong : 0;
     }
     if (r.ax_out && (!r.ax_add || r.ax_n < 0)) return hipErrorInvalidValue;
+    if (r.ep_job >= r.njobs) return hipErrorInvalidValue;
     if (blocks > 0) {
         ExaReduce rr = r;
         int64_t end = 0;

@@ -711,6 +711,7 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
 void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s) {
     ExaReduce R;
     std::memset(&R, 0, sizeof R);
+    R.ep_job = -1;
     R.job[0] = seg_job(m, buf, out);
     R.njobs = 1;
     hip_check(exa_launch_reduce(R, s), "segmented reduction");
@@ -1120,9 +1121,19 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     // the reductions of every selected callback, in one launch
     ExaReduce R;
     std::memset(&R, 0, sizeof R);
+    R.ep_job = -1;
     auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
     if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
-    if (mask & EXA_EV_JTPROD) job(D.jt_map, D.fo, a->jtw);
+    // the Lagrangian gradient with g written in place by the evaluation
+    // launch: J^T y goes straight into g as g = sigma * g + J^T y
+    const bool lag_ep = lag && M.grad_direct;
+    if (lag_ep) {
+        R.ep_job = R.njobs;
+        R.ax_alpha = lag_sigma;
+        job(D.jt_map, D.fo, a->g);
+    } else if (mask & EXA_EV_JTPROD) {
+        job(D.jt_map, D.fo, a->jtw);
+    }
     if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
     if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0
         R.part = D.tilesum;
@@ -1131,7 +1142,7 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     }
     const bool reduce = R.njobs > 0 || R.part;
     if (timed && reduce) hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
-    if (lag) {  // out = sigma * grad + J^T y, after the reductions
+    if (lag && !lag_ep) {  // out = sigma * grad + J^T y, after the reductions
         R.ax_out = a->g;
         R.ax_add = a->jtw;
         R.ax_alpha = lag_sigma;
