@@ -8,23 +8,23 @@ hipError_t exa_launch_sum(const double* part, int64_t n, double* out, hipStream_
 hipError_t exa_launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
-// One segment-sum job: out[s] = sum of buf[idx[j]], j in [ptr[s], ptr[s+1]).
-// Unless chunked is set, one lane sums one segment in ascending j, except
-// segments longer than kExaLongSeg when the job has parts (nparts > 0),
-// which the parts below sum.  Chunked jobs (int32 maps only) take every
-// segment in chunks of at most kExaChunk consecutive entries, in a
-// summation order fixed by the map:
-// * segments of at most kExaLongSeg entries: lane l adds one chunk, with
-//   lanes[2l] = segment (-1 for padding), lanes[2l+1] = count | (number of
-//   chunks of the segment << 4) on the segment's first chunk, and
-//   lidx[4l .. 4l+3] = the chunk's buffer positions (the last one repeated
-//   past the count; 0 for padding); a segment's chunks lie in one 256-lane
-//   block, and its first lane adds the chunk sums in chunk order;
-// * longer segments: one block per part of kExaLongSeg entries adds its
-//   chunk sums by a fixed tree into lsum[part], and a second launch adds
-//   each segment's part sums, again in a fixed order.  longs[5i..5i+4] =
-//   {segment, first entry, length, first part, parts} of long segment i,
-//   and part q belongs to long segment lpart[q].
+// One segment-sum job: out[s] = sum of buf[idx[j]], j in [ptr[s], ptr[s+1]),
+// in a summation order fixed by the map:
+// * segments longer than kExaLongSeg, when the job has parts (nparts > 0;
+//   int32 maps only): one block per part of kExaLongSeg entries adds its
+//   entries (4 per lane) by a fixed tree into lsum[part], and a second
+//   launch adds each segment's part sums, again in a fixed order.
+//   longs[5i..5i+4] = {segment, first entry, length, first part, parts} of
+//   long segment i, and part q belongs to long segment lpart[q];
+// * the other segments, unless chunked is set: one lane per segment, entries
+//   in ascending j;
+// * with chunked set (int32 maps only): lane l adds one chunk of at most
+//   kExaChunk consecutive entries, with lanes[2l] = segment (-1 for
+//   padding), lanes[2l+1] = count | (number of chunks of the segment << 4)
+//   on the segment's first chunk, and lidx[4l .. 4l+3] = the chunk's buffer
+//   positions (the last one repeated past the count; 0 for padding); a
+//   segment's chunks lie in one 256-lane block, and its first lane adds the
+//   chunk sums in chunk order.
 constexpr int kExaChunk = 4;
 constexpr int kExaLongSeg = 256 * kExaChunk;
 constexpr int kExaShortSeg = 16;
