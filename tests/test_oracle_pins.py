@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from exa_modeling import DataSet, Model, cos, sin, exp
-from exa_modeling.generators import acopf, pde, rosenbrock, Workload
+from exa_modeling.generators import Workload, acopf, goddard, kernel_sweep, pde, rosenbrock, two_stage
 from oracle import OracleModel, rules
 from oracle_checks import check_coverage, check_first_order, check_second_order
 
@@ -179,24 +179,27 @@ def test_dims_formulae():
 
 
 # ---------------------------------------------------- complex step / FD / coverage
-@pytest.mark.parametrize("name", ["acopf30", "pde8", "rosen5"])
+@pytest.mark.parametrize("name", ["acopf30", "pde8", "rosen5", "goddard6", "sweep16", "twostage"])
 def test_first_order_vs_complex_step(name):
     wl = {"acopf30": lambda: acopf(30, 0), "pde8": lambda: pde(8, 3),
-          "rosen5": lambda: rosenbrock(5, 1)}[name]()
+          "rosen5": lambda: rosenbrock(5, 1), "goddard6": lambda: goddard(6, 2),
+          "sweep16": lambda: kernel_sweep(16, 32, 1), "twostage": lambda: two_stage(3, 2, 4, 1)}[name]()
     assert check_first_order(wl) < 1e-13
 
 
-@pytest.mark.parametrize("name", ["acopf30", "pde8", "rosen5"])
+@pytest.mark.parametrize("name", ["acopf30", "pde8", "rosen5", "goddard6", "sweep16", "twostage"])
 def test_hessian_vs_fd_of_gradient(name):
     wl = {"acopf30": lambda: acopf(30, 0), "pde8": lambda: pde(8, 3),
-          "rosen5": lambda: rosenbrock(5, 1)}[name]()
+          "rosen5": lambda: rosenbrock(5, 1), "goddard6": lambda: goddard(6, 2),
+          "sweep16": lambda: kernel_sweep(16, 32, 1), "twostage": lambda: two_stage(3, 2, 4, 1)}[name]()
     assert check_second_order(wl) < 1e-6
 
 
-@pytest.mark.parametrize("name", ["acopf30", "pde8", "rosen5", "ops"])
+@pytest.mark.parametrize("name", ["acopf30", "pde8", "rosen5", "ops", "goddard6", "sweep16", "twostage"])
 def test_structure_covers_local_hessians(name):
     wl = {"acopf30": lambda: acopf(30, 0), "pde8": lambda: pde(8, 3),
-          "rosen5": lambda: rosenbrock(5, 1), "ops": lambda: op_zoo()}[name]()
+          "rosen5": lambda: rosenbrock(5, 1), "ops": lambda: op_zoo(), "goddard6": lambda: goddard(6, 2),
+          "sweep16": lambda: kernel_sweep(16, 32, 1), "twostage": lambda: two_stage(3, 2, 4, 1)}[name]()
     assert check_coverage(wl) == 0.0
 
 
