@@ -10,6 +10,8 @@ separate callbacks.  value = (nnzj + nnzh) / step time.
 
 Also reported on the same JSON line:
 * step_separate_us -- the same step as seven separate callback calls;
+* step_graph_us -- the step captured once into a HIP graph and replayed
+  (the paper's protocol times with and without a graph);
 * callbacks_us  -- each callback alone, timed with the paper's protocol
   (Sec. 8.2: back-to-back calls, one synchronization, best of 3);
 * roofline      -- the step's evaluation kernel (exa_k_multi, or exa_k_onepass
@@ -286,6 +288,12 @@ def leg_single(name, wl, steps, warmup):
     torch.cuda.synchronize()
     rot_s = (time.perf_counter() - t0) / nrot
     del sets
+    # the paper's protocol times with and without a graph: the step captured
+    # once into a HIP graph (torch.cuda.CUDAGraph) and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    graph_s = best_of_3(g.replay)
     per_cb = {k: best_of_3(fn) * 1e6 for k, fn in cbs.items()}
     tm = eval_launch_us(em, step)
     eb = em.eval_bytes(ALL_CBS)
@@ -302,7 +310,7 @@ def leg_single(name, wl, steps, warmup):
     res = dict(
         name=name, nvar=em.nvar, ncon=em.ncon, nnzj=em.nnzj, nnzh=em.nnzh,
         build_s=round(build_s, 3), step_s=step_s, nnz_per_s=nnz / step_s,
-        step_separate_us=round(sep_s * 1e6, 2),
+        step_separate_us=round(sep_s * 1e6, 2), step_graph_us=round(graph_s * 1e6, 2),
         rotated=dict(sets=K, mb=round(K * per_set / 1e6, 1), step_us=round(rot_s * 1e6, 2),
                      nnz_per_s=(em.nnzj + em.nnzh) / rot_s),
         jac_hess_nnz_per_s=nnz / (per_cb["jac_hess_coord"] * 1e-6),
@@ -582,6 +590,7 @@ def main():
                          "nvar": r["nvar"], "ncon": r["ncon"], "nnzj": r["nnzj"],
                          "nnzh": r["nnzh"], "schedule": r["schedule"]}
         out["step_separate_us"] = r["step_separate_us"]
+        out["step_graph_us"] = r["step_graph_us"]
         out["rotated"] = r["rotated"]
         out["callbacks_us"] = r["callbacks_us"]
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
@@ -613,6 +622,7 @@ def main():
         out["pde"] = {"workload": "pde-control 1000x1000 grid (2e6 variables, seed 3)",
                       "nnzj": r["nnzj"], "nnzh": r["nnzh"], "step_us": round(r["step_s"] * 1e6, 2),
                       "nnz_per_s": r["nnz_per_s"], "step_separate_us": r["step_separate_us"],
+                      "step_graph_us": r["step_graph_us"],
                       "rotated": r["rotated"],
                       "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"],
                       "callbacks_us": r["callbacks_us"],
