@@ -89,7 +89,8 @@ def test_csc_bad_arguments():
 
 
 GPU_CASES = dict(CASES, acopf600=lambda: acopf(600, 7), pde50=lambda: pde(50, 5),
-                 goddard_long=lambda: goddard(2000, 3))
+                 goddard_long=lambda: goddard(2000, 3),
+                 star_long=lambda: star_case([1500, 2], 7))  # 1,500 duplicates of one Hessian entry: parts
 
 
 @pytest.mark.gpu
