@@ -12,6 +12,8 @@ Also reported on the same JSON line:
 * step_separate_us -- the same step as seven separate callback calls;
 * step_graph_us -- the step captured once into a HIP graph and replayed
   (the paper's protocol times with and without a graph);
+* ipm_step_us   -- what an interior-point iteration asks for (obj, grad,
+  cons, jac, hess) through one exa_eval call, and its nnz/s;
 * callbacks_us  -- each callback alone, timed with the paper's protocol
   (Sec. 8.2: back-to-back calls, one synchronization, best of 3);
 * roofline      -- the step's evaluation kernel (exa_k_multi, or exa_k_onepass
@@ -234,6 +236,8 @@ def _callbacks(em, wl, dev="cuda:0"):
         "lag_grad": lambda: em.lag_grad(X, Y, 1.0, Lg),
     }
     cbs["eval_all"] = em.bind(X, Y, 1.0, V, W, f=f, g=g, c=c, jac=jv, hess=hv, jv=Jv, jtw=Jtw, hv=Hv)
+    # what an interior-point iteration asks for: obj, grad, cons, jac, hess
+    cbs["eval_ipm"] = em.bind(X, Y, 1.0, f=f, g=g, c=c, jac=jv, hess=hv)
     return cbs, (X, Y, V, W, jv, hv)
 
 
@@ -314,6 +318,7 @@ def leg_single(name, wl, steps, warmup):
         rotated=dict(sets=K, mb=round(K * per_set / 1e6, 1), step_us=round(rot_s * 1e6, 2),
                      nnz_per_s=(em.nnzj + em.nnzh) / rot_s),
         jac_hess_nnz_per_s=nnz / (per_cb["jac_hess_coord"] * 1e-6),
+        ipm_step_us=round(per_cb["eval_ipm"], 2), ipm_nnz_per_s=nnz / (per_cb["eval_ipm"] * 1e-6),
         jac_plus_hess_nnz_per_s=nnz / ((per_cb["jac_coord"] + per_cb["hess_coord"]) * 1e-6),
         callbacks_us={k: round(v, 2) for k, v in per_cb.items()},
         eval_kernel=eval_kernel, eval_us=round(tm["eval_us"], 3), eval_calls_timed=tm["calls"],
@@ -594,6 +599,8 @@ def main():
         out["rotated"] = r["rotated"]
         out["callbacks_us"] = r["callbacks_us"]
         out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
+        out["ipm_step_us"] = r["ipm_step_us"]
+        out["ipm_nnz_per_s"] = r["ipm_nnz_per_s"]
         out["jac_plus_hess_nnz_per_s"] = r["jac_plus_hess_nnz_per_s"]
         from exa_modeling.generators import acopf as _acopf
         traffic = profiled_traffic("acopf10k_eval_all.md", _acopf(30, 0).model, r["eval_kernel"])
@@ -625,6 +632,7 @@ def main():
                       "step_graph_us": r["step_graph_us"],
                       "rotated": r["rotated"],
                       "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"],
+                      "ipm_step_us": r["ipm_step_us"], "ipm_nnz_per_s": r["ipm_nnz_per_s"],
                       "callbacks_us": r["callbacks_us"],
                       "roofline_eval": {"kernel": r["eval_kernel"], "achieved": r["eval_gbs"],
                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
