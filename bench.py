@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--quick", action="store_true",
                     help="few repetitions per measurement (for runs under a profiler)")
+    ap.add_argument("--eval-schedule", default=None,
+                    help="block,points_per_lane,fused,one_pass: fix the step's exa_eval schedule instead of "
+                         "tuning it (to profile the schedule an unprofiled run chose)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates "
                          "the profiler's HBM byte counters)")
@@ -241,12 +244,18 @@ def _callbacks(em, wl, dev="cuda:0"):
     return cbs, (X, Y, V, W, jv, hv)
 
 
+EVAL_SCHEDULE = None
+
+
 def leg_single(name, wl, steps, warmup):
     import torch
     from paper_2608_16265_amd import ExaModel
     t0 = time.perf_counter()
     em = ExaModel(wl.model, autotune=True)
     build_s = time.perf_counter() - t0
+    if EVAL_SCHEDULE:
+        b, e_, f_, p_ = (int(v) for v in EVAL_SCHEDULE.split(","))
+        em.set_eval_schedule(ALL_CBS, b, e_, bool(f_), bool(p_))
     e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
     cbs, (X, Y, V, W, jv, hv) = _callbacks(em, wl)
     step = cbs["eval_all"]
@@ -564,9 +573,10 @@ def copy_only(mib):
 
 
 def main():
-    global QUICK
+    global QUICK, EVAL_SCHEDULE
     args = parse()
     QUICK = args.quick
+    EVAL_SCHEDULE = args.eval_schedule
     if args.copy_mib:
         copy_only(args.copy_mib)
         return

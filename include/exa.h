@@ -323,6 +323,16 @@ exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream
  * lane, fused (bit 0) | one pass per point for all callbacks (bit 1), number
  * of tiles.  EXA_ESTATE until the mask's first exa_eval call. */
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
+/* Fix the schedule of exa_eval for a mask instead of tuning it at the
+ * mask's first call (for measurement: a profiled run can use the schedule
+ * an unprofiled run chose).  block = workgroup size (64, 128 or 256), epl =
+ * points per lane (1..16), fused (0/1: patterns over the same data in one
+ * lane), one_pass (0/1: one unit per point for every callback, honoured only
+ * for masks that have one-pass units, as exa_eval_schedule reports).
+ * Results do not depend on the schedule.  Errors: EXA_EINVAL for a bad mask
+ * or value; EXA_ESTATE for a host-only model. */
+exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int32_t epl, int32_t fused,
+                                 int32_t one_pass);
 /* Algorithmic traffic of exa_eval for a mask under its current schedule
  * (the model's default before the mask's first call), host array out4:
  * out4[0], out4[1] = bytes read and written by the evaluation launch,

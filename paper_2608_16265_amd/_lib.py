@@ -103,6 +103,7 @@ def _load():
         "exa_adjoint_theta": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_eval": (C.c_int32, [vp, C.POINTER(EvalArgs), vp]),
         "exa_eval_schedule": (C.c_int32, [vp, C.c_uint32, P_i64]),
+        "exa_eval_set_schedule": (C.c_int32, [vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "exa_eval_bytes": (C.c_int32, [vp, C.c_uint32, P_i64]),
         "exa_device_copy": (C.c_int32, [vp, vp, C.c_int64, vp]),
         "exa_eval_timing": (C.c_int32, [vp, C.c_int32]),
@@ -142,7 +143,7 @@ def exported_symbols():
             "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
             "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jac_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
             "exa_lag_grad", "exa_csc_dims", "exa_csc_structure", "exa_csc_values",
-            "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_bytes", "exa_eval_timing", "exa_device_copy",
+            "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_set_schedule", "exa_eval_bytes", "exa_eval_timing", "exa_device_copy",
             "exa_eval_timing_read", "exa_counters", "exa_generated_source", "exa_compile_check",
             "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",
             "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule", "exa_batch_bytes"]

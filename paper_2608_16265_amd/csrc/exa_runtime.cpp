@@ -1335,6 +1335,19 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
     });
 }
 
+exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int32_t epl, int32_t fused,
+                                 int32_t one_pass) {
+    return guard([&] {
+        Model& M = live(m);
+        if (mask == 0 || (mask & ~(uint32_t)EXA_EV_ALL))
+            fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
+        if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
+        if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
+        set_multi_schedule(M, mask, block, epl, fused != 0, one_pass != 0 && !M.eval_per_mode);
+        M.dev->multi[mask].tuned = true;
+    });
+}
+
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
     return guard([&] {
         if (!m || !out4) fail(EXA_EINVAL, "null argument");

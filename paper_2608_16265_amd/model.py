@@ -360,6 +360,12 @@ class ExaModel:
         return dict(block=int(out[0]), points_per_lane=int(out[1]), fused=int(out[2]) & 1,
                     one_pass=(int(out[2]) >> 1) & 1, tiles=int(out[3]))
 
+    def set_eval_schedule(self, callbacks, block: int, points_per_lane: int, fused: bool = False,
+                          one_pass: bool = False):
+        """Fix exa_eval's schedule for a set of callback names (no tuning)."""
+        check(LIB.exa_eval_set_schedule(self._h, self._eval_mask(callbacks), int(block), int(points_per_lane),
+                                        1 if fused else 0, 1 if one_pass else 0))
+
     @staticmethod
     def _eval_mask(callbacks) -> int:
         mask = 0

@@ -143,3 +143,33 @@ def test_eval_rejects_bad_arguments():
         assert st == _lib.EXA_EINVAL, note
     with pytest.raises(ExaError):
         em.eval_schedule(("cons",))          # never evaluated with this set
+
+
+def test_fixed_schedule_gives_the_same_bits():
+    """exa_eval_set_schedule pins a schedule (no tuning); every schedule
+    evaluates each point with the same code, so the outputs do not change."""
+    from paper_2608_16265_amd import ExaModel
+    w = acopf(200, 3)
+    rng = np.random.default_rng(4)
+    ref_m = ExaModel(w.model)
+    X, Y = dev(w.x), dev(w.y)
+    V, W = dev(rng.standard_normal(ref_m.nvar)), dev(rng.standard_normal(ref_m.ncon))
+    names = ("f", "g", "c", "jac", "hess", "jv", "jtw", "hv")
+    sizes = (1, ref_m.nvar, ref_m.ncon, ref_m.nnzj, ref_m.nnzh, ref_m.ncon, ref_m.nvar, ref_m.nvar)
+    e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
+    ref = {k: e(n) for k, n in zip(names, sizes)}
+    ref_m.evaluate(X, Y, 0.9, V, W, **ref)
+    cbs = ("obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod")
+    for block, epl, fused, one in ((64, 3, False, False), (256, 1, True, True), (128, 16, False, True)):
+        em = ExaModel(w.model, autotune=True)
+        em.set_eval_schedule(cbs, block, epl, fused, one)
+        out = {k: e(n) for k, n in zip(names, sizes)}
+        em.evaluate(X, Y, 0.9, V, W, **out)
+        sch = em.eval_schedule(cbs)
+        assert (sch["block"], sch["points_per_lane"], sch["one_pass"]) == (block, epl, int(one))
+        for k in names:
+            assert np.array_equal(host(out[k]), host(ref[k])), (block, epl, fused, one, k)
+    with pytest.raises(Exception):
+        ref_m.set_eval_schedule(cbs, 96, 1)
+    with pytest.raises(Exception):
+        ref_m.set_eval_schedule(cbs, 128, 0)
