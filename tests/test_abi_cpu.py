@@ -296,3 +296,75 @@ def test_reduction_bytes_large_map_with_one_shared_variable():
     rd, wr = _chunk_plan_bytes(lengths)
     b = em.eval_bytes(("jtprod",))
     assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
+
+
+C_PROGRAM = r"""
+#include "exa.h"
+#include <stdio.h>
+#include <string.h>
+
+/* the extended Rosenbrock pattern of eq. rosenbrock, built directly as a
+   post-order node list: 100 (x[i-1]^2 - x[i])^2 + (x[i-1] - 1)^2, i = 1..4 */
+int main(void) {
+    const int32_t op[] = {EXA_OP_VAR, EXA_OP_CONST, EXA_OP_POW, EXA_OP_VAR, EXA_OP_SUB, EXA_OP_CONST, EXA_OP_POW,
+                          EXA_OP_CONST, EXA_OP_MUL, EXA_OP_VAR, EXA_OP_CONST, EXA_OP_SUB, EXA_OP_CONST,
+                          EXA_OP_POW, EXA_OP_ADD};
+    const int32_t a[] = {0, -1, 0, 0, 2, -1, 4, -1, 7, 0, -1, 9, -1, 11, 8};
+    const int32_t b[] = {-1, -1, 1, -1, 3, -1, 5, -1, 6, -1, -1, 10, -1, 12, 13};
+    const int64_t off[] = {-1, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0, 0, 0, 0, 0};
+    const double val[] = {0, 2, 0, 0, 0, 2, 0, 100, 0, 0, 1, 0, 2, 0, 0};
+    const int32_t i_col[] = {1, 2, 3, 4};
+    const int32_t* icols[] = {i_col};
+    exa_pattern_desc d;
+    memset(&d, 0, sizeof d);
+    d.kind = EXA_OBJ;
+    d.nnodes = 15;
+    d.op = op; d.a = a; d.b = b; d.off = off; d.val = val;
+    d.ndata = 4;
+    d.n_icols = 1;
+    d.icols = icols;
+    d.target = -1;
+    exa_options opt;
+    memset(&opt, 0, sizeof opt);
+    opt.host_only = 1;
+    exa_model* m = NULL;
+    if (exa_create(&d, 1, 5, NULL, NULL, 0, NULL, &opt, &m) != EXA_OK) {
+        printf("create: %s\n", exa_last_error());
+        return 1;
+    }
+    int64_t n, c, nj, nh;
+    exa_dims(m, &n, &c, &nj, &nh);
+    int32_t rows[12], cols[12];
+    exa_hess_structure(m, rows, cols);
+    /* o2step 3 (Sec. 5.2.2 probe); the slots in emission order, (u,u),
+       (v,v), (u,v) with u = x[i-1], v = x[i], as lower-triangle pairs */
+    const int32_t er[6] = {0, 1, 1, 1, 2, 2}, ec[6] = {0, 1, 0, 1, 2, 1};
+    int ok = n == 5 && c == 0 && nj == 0 && nh == 12;
+    for (int q = 0; q < 6; ++q) ok = ok && rows[q] == er[q] && cols[q] == ec[q];
+    exa_status bad = exa_obj(m, NULL, NULL, NULL); /* host-only: no device callbacks */
+    exa_destroy(m);
+    printf("%s %d %s\n", ok ? "ok" : "wrong", (int)(bad == EXA_ESTATE), exa_version());
+    return ok ? 0 : 2;
+}
+"""
+
+
+def test_c_program_against_the_header(tmp_path):
+    """include/exa.h is plain C99: a C program builds a pattern from raw
+    node arrays, links the library and reads dims and structure."""
+    import shutil
+    import subprocess
+    from paper_2608_16265_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    libdir = os.path.dirname(_lib.LIB._name)
+    exe = tmp_path / "abi"
+    subprocess.run([gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-L", libdir, "-lexa",
+                    "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.startswith("ok 1 "), out.stdout
