@@ -16,8 +16,9 @@ Also reported on the same JSON line:
   cons, jac, hess) through one exa_eval call, and its nnz/s;
 * callbacks_us  -- each callback alone, timed with the paper's protocol
   (Sec. 8.2: back-to-back calls, one synchronization, best of 3);
-* roofline      -- the step's evaluation kernel (exa_k_multi, or exa_k_onepass
-  when the tuner picks one pass per point for every callback): algorithmic
+* roofline      -- the step's evaluation kernel (exa_k_multi, exa_k_multijh
+  with Jacobian + Hessian units, or exa_k_onepass when the tuner picks one
+  pass per point for every callback): algorithmic
   bytes per launch / its average duration, measured by HIP events that the
   library records on the launch stream around each launch, against the
   8 TB/s HBM peak; the reduction launch and the combined Jacobian+Hessian
@@ -74,7 +75,8 @@ def parse():
     ap.add_argument("--quick", action="store_true",
                     help="few repetitions per measurement (for runs under a profiler)")
     ap.add_argument("--eval-schedule", default=None,
-                    help="block,points_per_lane,fused,one_pass: fix the step's exa_eval schedule instead of "
+                    help="block,points_per_lane,fused,units (0 per callback, 1 Jacobian + Hessian units, "
+                         "2 one pass): fix the step's exa_eval schedule instead of "
                          "tuning it (to profile the schedule an unprofiled run chose)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates "
@@ -254,8 +256,8 @@ def leg_single(name, wl, steps, warmup):
     em = ExaModel(wl.model, autotune=True)
     build_s = time.perf_counter() - t0
     if EVAL_SCHEDULE:
-        b, e_, f_, p_ = (int(v) for v in EVAL_SCHEDULE.split(","))
-        em.set_eval_schedule(ALL_CBS, b, e_, bool(f_), bool(p_))
+        b, e_, f_, u_ = (int(v) for v in EVAL_SCHEDULE.split(","))
+        em.set_eval_schedule(ALL_CBS, b, e_, bool(f_), u_)
     e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
     cbs, (X, Y, V, W, jv, hv) = _callbacks(em, wl)
     step = cbs["eval_all"]
@@ -314,9 +316,11 @@ def leg_single(name, wl, steps, warmup):
     rd, wr = em.kernel_bytes("jac_hess")
     sched = {k: em.schedule(k) for k in ("jac", "hess", "jac_hess")}
     sched["eval_all"] = em.eval_schedule(ALL_CBS)
-    # the tuner picks per-callback tiles (exa_k_multi) or one pass per point
+    # the tuner picks per-callback tiles (exa_k_multi, or exa_k_multijh with
+    # Jacobian + Hessian units) or one pass per point
     # for every callback (exa_k_onepass)
-    eval_kernel = "exa_k_onepass" if sched["eval_all"]["one_pass"] else "exa_k_multi"
+    sa = sched["eval_all"]
+    eval_kernel = "exa_k_onepass" if sa["one_pass"] else "exa_k_multijh" if sa["jac_hess"] else "exa_k_multi"
     nnz = em.nnzj + em.nnzh
     ev_bytes = eb["eval_read"] + eb["eval_write"]
     red_bytes = eb["reduce_read"] + eb["reduce_write"]

@@ -320,19 +320,29 @@ typedef struct exa_eval_args {
 } exa_eval_args;
 exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream);
 /* The schedule of exa_eval for a mask: out4 = workgroup size, points per
- * lane, fused (bit 0) | one pass per point for all callbacks (bit 1), number
- * of tiles.  EXA_ESTATE until the mask's first exa_eval call. */
+ * lane, fused (bit 0) | one pass per point for all callbacks (bit 1) |
+ * Jacobian + Hessian units (bit 2), number of tiles.  EXA_ESTATE until the
+ * mask's first exa_eval call. */
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
+/* Units of an exa_eval launch: one tile per callback and point, the
+ * Jacobian and the Hessian apart (their tiles then run in a kernel with a
+ * smaller register budget); the same with Jacobian + Hessian units (both of
+ * a point from one set of loads; masks with both); one unit per point for
+ * every selected callback (masks with every callback, or exactly obj, grad,
+ * cons, jac and hess). */
+#define EXA_UNITS_PER_CALLBACK 0
+#define EXA_UNITS_JAC_HESS 1
+#define EXA_UNITS_ONE_PASS 2
 /* Fix the schedule of exa_eval for a mask instead of tuning it at the
  * mask's first call (for measurement: a profiled run can use the schedule
  * an unprofiled run chose).  block = workgroup size (64, 128 or 256), epl =
  * points per lane (1..16), fused (0/1: patterns over the same data in one
- * lane), one_pass (0/1: one unit per point for every callback, honoured only
- * for masks that have one-pass units, as exa_eval_schedule reports).
- * Results do not depend on the schedule.  Errors: EXA_EINVAL for a bad mask
- * or value; EXA_ESTATE for a host-only model. */
+ * lane), units = EXA_UNITS_* (a choice the mask does not allow falls back
+ * to the next one down, as exa_eval_schedule then reports).  Results do not
+ * depend on the schedule.  Errors: EXA_EINVAL for a bad mask or value;
+ * EXA_ESTATE for a host-only model. */
 exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int32_t epl, int32_t fused,
-                                 int32_t one_pass);
+                                 int32_t units);
 /* Algorithmic traffic of exa_eval for a mask under its current schedule
  * (the model's default before the mask's first call), host array out4:
  * out4[0], out4[1] = bytes read and written by the evaluation launch,

@@ -1051,9 +1051,10 @@ int mode_lds_doubles(const Model& M, int mode) {
 
 std::string kernel_name(int mode) { return std::string("exa_k_") + mode_name(mode); }
 
-const std::vector<int>& multi_modes() {
-    static const std::vector<int> m = {M_OBJ, M_GRAD, M_CONS, M_JAC, M_HESS, M_JH, M_JPROD, M_JTPROD, M_HPROD};
-    return m;
+const std::vector<int>& multi_modes(bool jh) {
+    static const std::vector<int> m = {M_OBJ, M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_JTPROD, M_HPROD};
+    static const std::vector<int> mjh = {M_OBJ, M_GRAD, M_CONS, M_JH, M_JPROD, M_JTPROD, M_HPROD};
+    return jh ? mjh : m;
 }
 
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live) {
@@ -1280,18 +1281,21 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
     const std::string zero_case = "case " + std::to_string((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE) +
                                   ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) " +
                                   G + ".out0[" + G + ".inst[T.inst].off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;";
-    {
+    // every unit's tiles share a kernel's register budget: ask for at least
+    // four waves per SIMD, so that one wave of the launch fits on the chip at
+    // once.  The Jacobian + Hessian units need the most registers, so they
+    // get a kernel of their own: exa_k_multi runs the Jacobian and the
+    // Hessian as separate tiles (and fits four waves without spilling),
+    // exa_k_multijh runs them as JH units.
+    for (bool jh : {false, true}) {
         int lds = 0;
         std::vector<std::string> cases;
-        for (int mode : multi_modes()) {
+        for (int mode : multi_modes(jh)) {
             lds = std::max(lds, mode_lds_doubles(M, mode));
             mode_cases(mode, cases);
         }
         cases.push_back(zero_case);
-        // every unit's tiles share this kernel's register budget: ask for at
-        // least four waves per SIMD, so that one wave of the launch fits on
-        // the chip at once
-        multi_kernel("exa_k_multi", lds, cases, 4);
+        multi_kernel(jh ? "exa_k_multijh" : "exa_k_multi", lds, cases, 4);
     }
     {
         int lds = mode_lds_doubles(M, M_OBJ);

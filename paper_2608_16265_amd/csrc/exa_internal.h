@@ -277,8 +277,9 @@ std::string pattern_signature(const Model& M);
 // exa_codegen.cpp
 #define EXA_BLOCK_MAX 256
 bool pattern_in_mode(const Pattern& P, int mode);
-// Modes the several-callback kernel (exa_k_multi) evaluates.
-const std::vector<int>& multi_modes();
+// Modes the several-callback kernels evaluate: exa_k_multi (Jacobian and
+// Hessian apart) or exa_k_multijh (with Jacobian + Hessian units).
+const std::vector<int>& multi_modes(bool jh);
 std::vector<Unit> units_for(const Model& M, int mode, bool fused);
 // Generated source for all callbacks; fills live[(mode, unit code)].
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr);

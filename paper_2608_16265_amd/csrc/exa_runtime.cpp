@@ -97,6 +97,8 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jhsep");
     if (hipModuleGetFunction(&m->fn_multi, m->mod, "exa_k_multi") != hipSuccess)
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_multi");
+    if (hipModuleGetFunction(&m->fn_multijh, m->mod, "exa_k_multijh") != hipSuccess)
+        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_multijh");
     if (hipModuleGetFunction(&m->fn_onepass, m->mod, "exa_k_onepass") != hipSuccess)
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_onepass");
     g_mods[key] = m;
@@ -471,14 +473,19 @@ void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
 // ---- several callbacks in one launch (exa_eval) ----------------------------
 namespace {
 
-// Modes of an exa_eval mask; Jacobian and Hessian together run as JH units.
-std::vector<int> eval_modes(uint32_t mask) {
+// Modes of an exa_eval mask; with jh, Jacobian and Hessian together run as
+// JH units (both jobs of a point from one set of loads).
+std::vector<int> eval_modes(uint32_t mask, bool jh) {
     std::vector<int> m;
     if (mask & EXA_EV_OBJ) m.push_back(M_OBJ);
     if (mask & EXA_EV_GRAD) m.push_back(M_GRAD);
     if (mask & EXA_EV_CONS) m.push_back(M_CONS);
-    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_HESS))
+    if (jh && (mask & EXA_EV_JAC) && (mask & EXA_EV_HESS))
         m.push_back(M_JH);
+    else if ((mask & EXA_EV_JAC) && (mask & EXA_EV_HESS)) {
+        m.push_back(M_JAC);
+        m.push_back(M_HESS);
+    }
     else if (mask & EXA_EV_JAC)
         m.push_back(M_JAC);
     else if (mask & EXA_EV_HESS)
@@ -500,13 +507,23 @@ int combined_mode_of(uint32_t mask) {
     return -1;
 }
 
+bool has_jh(uint32_t mask) { return (mask & EXA_EV_JAC) && (mask & EXA_EV_HESS); }
+
+// The units a mask can run as asked: one-pass units need a mask that has
+// them, JH units a mask with both the Jacobian and the Hessian.
+int valid_units(uint32_t mask, int units) {
+    if (units == EXA_UNITS_ONE_PASS && combined_mode_of(mask) < 0) units = EXA_UNITS_JAC_HESS;
+    if (units == EXA_UNITS_JAC_HESS && !has_jh(mask)) units = EXA_UNITS_PER_CALLBACK;
+    return units;
+}
+
 // Modes whose tiles make up a mask's launch.
-std::vector<int> launch_modes(uint32_t mask, bool combined) {
-    const int cm = combined ? combined_mode_of(mask) : -1;
-    if (cm < 0) return eval_modes(mask);
+std::vector<int> launch_modes(uint32_t mask, int units) {
+    units = valid_units(mask, units);
+    if (units != EXA_UNITS_ONE_PASS) return eval_modes(mask, units == EXA_UNITS_JAC_HESS);
     std::vector<int> m;
     if (mask & EXA_EV_OBJ) m.push_back(M_OBJ);
-    m.push_back(cm);
+    m.push_back(combined_mode_of(mask));
     return m;
 }
 
@@ -514,13 +531,13 @@ std::vector<int> launch_modes(uint32_t mask, bool combined) {
 // fixed schedule), laid out as eight chunks that each hold an eighth of
 // every mode's tiles, so that the per-XCD ranges of the launch get the same
 // mix of work and contiguous point ranges.
-void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, bool combined) {
+void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, int units) {
     DeviceState& D = *M.dev;
     DeviceState::MultiSched& S = D.multi[mask];
-    combined = combined && combined_mode_of(mask) >= 0;
+    units = valid_units(mask, units);
     const int64_t tp = (int64_t)block * epl;
     std::vector<std::vector<ExaTile>> per;
-    for (int mode : launch_modes(mask, combined)) {
+    for (int mode : launch_modes(mask, units)) {
         std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused)
                                                : make_tiles(M, mode, 0, tp, fused);
         for (ExaTile& x : t) x.pat |= mode << EXA_MODE_SHIFT;
@@ -541,7 +558,7 @@ void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused,
     S.block = block;
     S.epl = epl;
     S.fused = fused;
-    S.combined = combined;
+    S.units = units;
 }
 
 void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
@@ -551,7 +568,10 @@ void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
     mc.ntiles = S.ntiles;
     mc.per_xcd = (S.ntiles + 7) / 8;
     void* args[] = {&mc};
-    hipFunction_t fn = S.combined ? M.dev->module->fn_onepass : M.dev->module->fn_multi;
+    const Module& K = *M.dev->module;
+    hipFunction_t fn = S.units == EXA_UNITS_ONE_PASS   ? K.fn_onepass
+                       : S.units == EXA_UNITS_JAC_HESS ? K.fn_multijh
+                                                       : K.fn_multi;
     hip_check(hipModuleLaunchKernel(fn, (unsigned)(8 * mc.per_xcd), 1, 1, (unsigned)S.block, 1,
                                     1, 0, s, args, nullptr),
               "hipModuleLaunchKernel");
@@ -565,13 +585,14 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
     const int blocks[] = {64, 128, 256};
     const int epls[] = {1, 2, 4, 8};
     std::vector<int> fuses = {0};
-    for (int mode : eval_modes(mask))
+    for (int mode : eval_modes(mask, false))
         if (mode != M_OBJ && has_fusable_group(M, mode)) {
             fuses.push_back(1);
             break;
         }
-    std::vector<int> combos = {0};
-    if (combined_mode_of(mask) >= 0 && !M.eval_per_mode) combos = {1, 0};
+    std::vector<int> combos = {EXA_UNITS_PER_CALLBACK};
+    if (has_jh(mask)) combos.push_back(EXA_UNITS_JAC_HESS);
+    if (combined_mode_of(mask) >= 0 && !M.eval_per_mode) combos.push_back(EXA_UNITS_ONE_PASS);
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
@@ -596,7 +617,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
         for (int f : fuses)
             for (int b : blocks)
                 for (int ep : epls) {
-                    set_multi_schedule(M, mask, b, ep, f != 0, cb != 0);
+                    set_multi_schedule(M, mask, b, ep, f != 0, cb);
                     cands.push_back({time_it(3), b, ep, f, cb});
                 }
         // neighbouring schedules differ by less than one timing's noise: the
@@ -607,7 +628,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
         for (auto& c : cands) c.ms = 1e30f;
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
-                set_multi_schedule(M, mask, c.block, c.epl, c.fused != 0, c.comb != 0);
+                set_multi_schedule(M, mask, c.block, c.epl, c.fused != 0, c.comb);
                 c.ms = std::min(c.ms, time_it(16));
             }
     } catch (...) {
@@ -618,7 +639,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb != 0);
+    set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb);
 }
 
 }  // namespace
@@ -1052,7 +1073,9 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     // each mode's call, as its own entry point sets it up
     ExaMulti mc;
     std::memset(&mc, 0, sizeof mc);
-    for (int mode : eval_modes(mask)) {
+    std::vector<int> rec_modes = eval_modes(mask, true);
+    if (has_jh(mask)) rec_modes.insert(rec_modes.end(), {M_JAC, M_HESS});
+    for (int mode : rec_modes) {
         ExaCall& c = mc.c[mode];
         c.inst = D.inst;
         c.x = a->x;
@@ -1107,7 +1130,8 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     }
     auto it = D.multi.find(mask);
     if (it == D.multi.end() || !it->second.tuned) {
-        set_multi_schedule(M, mask, M.block, M.epl, M.fuse, !M.eval_per_mode);
+        set_multi_schedule(M, mask, M.block, M.epl, M.fuse,
+                           M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS);
         if (M.autotune) tune_multi(M, mask, mc, s);
         D.multi[mask].tuned = true;
     }
@@ -1288,16 +1312,17 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        bool fused = M.fuse, combined = true;
+        bool fused = M.fuse;
+        int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
         if (M.dev) {
             auto it = M.dev->multi.find(mask);
             if (it != M.dev->multi.end()) {
                 fused = it->second.fused;
-                combined = it->second.combined;
+                units = it->second.units;
             }
         }
         int64_t rd = 0, wr = 0;
-        kernel_bytes(M, launch_modes(mask, combined), fused, rd, wr);
+        kernel_bytes(M, launch_modes(mask, units), fused, rd, wr);
         out4[0] = rd;
         out4[1] = wr;
         // reduction launch: maps (int32 when every position fits), buffer
@@ -1336,14 +1361,17 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
 }
 
 exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int32_t epl, int32_t fused,
-                                 int32_t one_pass) {
+                                 int32_t units) {
     return guard([&] {
         Model& M = live(m);
         if (mask == 0 || (mask & ~(uint32_t)EXA_EV_ALL))
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
-        set_multi_schedule(M, mask, block, epl, fused != 0, one_pass != 0 && !M.eval_per_mode);
+        if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_ONE_PASS)
+            fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
+        if (units == EXA_UNITS_ONE_PASS && M.eval_per_mode) units = EXA_UNITS_JAC_HESS;
+        set_multi_schedule(M, mask, block, epl, fused != 0, units);
         M.dev->multi[mask].tuned = true;
     });
 }
@@ -1356,7 +1384,8 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
         if (it == m->impl.dev->multi.end()) fail(EXA_ESTATE, "no exa_eval call with this mask yet");
         out4[0] = it->second.block;
         out4[1] = it->second.epl;
-        out4[2] = (it->second.fused ? 1 : 0) | (it->second.combined ? 2 : 0);
+        out4[2] = (it->second.fused ? 1 : 0) | (it->second.units == EXA_UNITS_ONE_PASS ? 2 : 0) |
+                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0);
         out4[3] = it->second.ntiles;
     });
 }

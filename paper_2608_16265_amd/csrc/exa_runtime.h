@@ -15,7 +15,8 @@ struct Module {
     hipModule_t mod = nullptr;
     hipFunction_t fn[M_COUNT] = {};
     hipFunction_t fn_sep = nullptr;  // separate Jacobian and Hessian tiles in one launch
-    hipFunction_t fn_multi = nullptr;    // tiles of several callbacks in one launch
+    hipFunction_t fn_multi = nullptr;    // tiles of several callbacks in one launch (Jacobian and Hessian apart)
+    hipFunction_t fn_multijh = nullptr;  // the same with Jacobian + Hessian units
     hipFunction_t fn_onepass = nullptr;  // one pass per point for several callbacks
     std::string source;
     std::vector<char> code;
@@ -56,7 +57,7 @@ struct DeviceState {
     struct MultiSched {
         int block = 256, epl = 4;
         bool fused = false, tuned = false;
-        bool combined = false;  // multi units (one pass per point) instead of per-mode tiles
+        int units = EXA_UNITS_PER_CALLBACK;  // EXA_UNITS_*: which kernel and units run the tiles
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;
     };

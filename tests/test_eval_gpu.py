@@ -146,8 +146,9 @@ def test_eval_rejects_bad_arguments():
 
 
 def test_fixed_schedule_gives_the_same_bits():
-    """exa_eval_set_schedule pins a schedule (no tuning); every schedule
-    evaluates each point with the same code, so the outputs do not change."""
+    """exa_eval_set_schedule pins a schedule (no tuning); every schedule and
+    every kind of units evaluates each point with the same code, so the
+    outputs do not change."""
     from paper_2608_16265_amd import ExaModel
     w = acopf(200, 3)
     rng = np.random.default_rng(4)
@@ -156,20 +157,30 @@ def test_fixed_schedule_gives_the_same_bits():
     V, W = dev(rng.standard_normal(ref_m.nvar)), dev(rng.standard_normal(ref_m.ncon))
     names = ("f", "g", "c", "jac", "hess", "jv", "jtw", "hv")
     sizes = (1, ref_m.nvar, ref_m.ncon, ref_m.nnzj, ref_m.nnzh, ref_m.ncon, ref_m.nvar, ref_m.nvar)
+    field = dict(zip(("obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod"), names))
     e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
     ref = {k: e(n) for k, n in zip(names, sizes)}
     ref_m.evaluate(X, Y, 0.9, V, W, **ref)
-    cbs = ("obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod")
-    for block, epl, fused, one in ((64, 3, False, False), (256, 1, True, True), (128, 16, False, True)):
+    every = ("obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod")
+    ipm = ("obj", "grad", "cons", "jac", "hess")
+    for cbs, block, epl, fused, units, expect in (
+            (every, 64, 3, False, "per_callback", (0, 0)), (every, 256, 1, True, "one_pass", (1, 0)),
+            (every, 128, 16, False, "jac_hess", (0, 1)), (ipm, 128, 2, True, "per_callback", (0, 0)),
+            (ipm, 64, 1, False, "one_pass", (1, 0)), (("jac", "hess"), 256, 4, False, "per_callback", (0, 0)),
+            (("jac", "hess"), 64, 2, True, "one_pass", (0, 1)),   # no one-pass units: JH units
+            (("jac", "jprod"), 128, 1, False, "jac_hess", (0, 0))):  # no Hessian: per callback
         em = ExaModel(w.model, autotune=True)
-        em.set_eval_schedule(cbs, block, epl, fused, one)
-        out = {k: e(n) for k, n in zip(names, sizes)}
+        em.set_eval_schedule(cbs, block, epl, fused, units)
+        out = {field[cb]: e(n) for cb, n in zip(every, sizes) if cb in cbs}
         em.evaluate(X, Y, 0.9, V, W, **out)
         sch = em.eval_schedule(cbs)
-        assert (sch["block"], sch["points_per_lane"], sch["one_pass"]) == (block, epl, int(one))
-        for k in names:
-            assert np.array_equal(host(out[k]), host(ref[k])), (block, epl, fused, one, k)
+        assert (sch["block"], sch["points_per_lane"]) == (block, epl)
+        assert (sch["one_pass"], sch["jac_hess"]) == expect, (cbs, units)
+        for k, t in out.items():
+            assert np.array_equal(host(t), host(ref[k])), (cbs, block, epl, fused, units, k)
     with pytest.raises(Exception):
-        ref_m.set_eval_schedule(cbs, 96, 1)
+        ref_m.set_eval_schedule(every, 96, 1)
     with pytest.raises(Exception):
-        ref_m.set_eval_schedule(cbs, 128, 0)
+        ref_m.set_eval_schedule(every, 128, 0)
+    with pytest.raises(Exception):
+        ref_m.set_eval_schedule(every, 128, 1, units=3)
