@@ -585,8 +585,8 @@ def main():
         copy_only(args.copy_mib)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(instances of a batch would be sharded across GPUs with no exchange; not built).",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(instances of a batch would be sharded across GPUs with no exchange; not implemented).",
               file=sys.stderr)
         sys.exit(2)
     import torch
