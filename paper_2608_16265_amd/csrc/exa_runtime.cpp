@@ -790,6 +790,15 @@ Model::Model() {
 Model::~Model() = default;
 }  // namespace exa
 
+namespace {
+Model::Csc& csc_checked(const exa_model* m, int32_t which) {
+    if (!m) fail(EXA_EINVAL, "null model");
+    if (which != EXA_CSC_JAC && which != EXA_CSC_HESS) fail(EXA_EINVAL, "which must be EXA_CSC_JAC or EXA_CSC_HESS");
+    // the analysis is a cache of the structure: computing it does not change the model
+    return csc_form(const_cast<exa_model*>(m)->impl, which);
+}
+}  // namespace
+
 extern "C" {
 
 const char* exa_last_error(void) { return exa::last_error(); }
@@ -1204,15 +1213,6 @@ exa_status exa_lag_grad(exa_model* m, const double* x, const double* y, double o
         eval_body(M, &a, (hipStream_t)stream, true, obj_weight);
     });
 }
-
-namespace {
-Model::Csc& csc_checked(const exa_model* m, int32_t which) {
-    if (!m) fail(EXA_EINVAL, "null model");
-    if (which != EXA_CSC_JAC && which != EXA_CSC_HESS) fail(EXA_EINVAL, "which must be EXA_CSC_JAC or EXA_CSC_HESS");
-    // the analysis is a cache of the structure: computing it does not change the model
-    return csc_form(const_cast<exa_model*>(m)->impl, which);
-}
-}  // namespace
 
 exa_status exa_csc_dims(const exa_model* m, int32_t which, int64_t* nnz) {
     return guard([&] {
