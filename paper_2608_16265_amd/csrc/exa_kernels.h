@@ -15,7 +15,11 @@ hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_
 //   entries (4 per lane) by a fixed tree into lsum[part], and a second
 //   launch adds each segment's part sums, again in a fixed order.
 //   longs[5i..5i+4] = {segment, first entry, length, first part, parts} of
-//   long segment i, and part q belongs to long segment lpart[q];
+//   long segment i; part block r adds part lpart[2r+1] of long segment
+//   lpart[2r] (the segment's parts are numbered from its first part up).
+//   Part blocks are interleaved over the segments (the i-th part of every
+//   long segment before any (i+1)-th), so a contiguous range of part blocks
+//   covers the same range of points for every long segment;
 // * the other segments, unless chunked is set: one lane per segment, entries
 //   in ascending j;
 // * with chunked set (int32 maps only): lane l adds one chunk of at most

@@ -99,13 +99,14 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return r;
 }
 
-// Part q of a long segment (see ExaSegJob): lane t adds entries
-// 4t .. 4t+3 of the part and the block adds the lanes by block_sum.  Called
-// by every lane of the workgroup.
-__device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t q, double* lds) {
+// Part block r (see ExaSegJob): part q of long segment ls, lane t adds
+// entries 4t .. 4t+3 of the part and the block adds the lanes by block_sum
+// into lsum[q].  Called by every lane of the workgroup.
+__device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t r, double* lds) {
     const int32_t* __restrict__ idx = (const int32_t*)J.idx;
     const double* __restrict__ buf = J.buf;
-    const int32_t ls = J.lpart[q];
+    const int2 lq = ((const int2*)J.lpart)[r];
+    const int32_t ls = lq.x, q = lq.y;
     const int32_t beg = J.longs[5 * ls + 1], len = J.longs[5 * ls + 2], part0 = J.longs[5 * ls + 3];
     const int32_t pb = beg + ((int32_t)q - part0) * kExaLongSeg;
     const int32_t pe = min(beg + len, pb + kExaLongSeg);

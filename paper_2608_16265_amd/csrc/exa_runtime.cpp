@@ -269,7 +269,7 @@ void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     }
     if (P.nparts()) {
         d.longs = (const int32_t*)D.upload(P.longs.data(), P.longs.size() * sizeof(int32_t));
-        d.lpart = (const int32_t*)D.upload(P.lpart.data(), P.lpart.size() * sizeof(int32_t));
+        d.lpart = (const int32_t*)D.upload(P.lpart.data(), P.lpart.size() * sizeof(int32_t));  // 2 per part
         d.nparts = P.nparts();
         d.nlong = P.nlong();
         d.lsum = (double*)D.alloc(P.nparts() * sizeof(double));
@@ -346,13 +346,14 @@ ChunkPlan chunk_plan(const SegMap& S) {
             P.lidx.insert(P.lidx.end(), {0, 0, 0, 0});
         }
     };
+    int64_t nparts = 0, most = 0;
     for (int64_t s = 0; s < S.nseg(); ++s) {
         const int64_t b = S.ptr[s], len = S.ptr[s + 1] - b;
         if (len > kExaLongSeg) {
             const int64_t parts = (len + kExaLongSeg - 1) / kExaLongSeg;
-            const int64_t ls = P.nlong();
-            P.longs.insert(P.longs.end(), {(int32_t)s, (int32_t)b, (int32_t)len, (int32_t)P.nparts(), (int32_t)parts});
-            P.lpart.insert(P.lpart.end(), (size_t)parts, (int32_t)ls);
+            P.longs.insert(P.longs.end(), {(int32_t)s, (int32_t)b, (int32_t)len, (int32_t)nparts, (int32_t)parts});
+            nparts += parts;
+            most = std::max(most, parts);
             continue;
         }
         if (!P.chunked) continue;
@@ -369,6 +370,13 @@ ChunkPlan chunk_plan(const SegMap& S) {
         }
     }
     if (P.chunked) pad_to((P.nlanes() + 255) / 256 * 256);
+    // part blocks: the i-th part of every long segment, then the (i+1)-th;
+    // segments that share a variable over interleaved points (x_{k mod n})
+    // then read the same range of the buffer in neighbouring blocks, on one
+    // XCD, instead of each XCD reading every line of it
+    for (int64_t i = 0; i < most; ++i)
+        for (int64_t ls = 0; ls < P.nlong(); ++ls)
+            if (i < P.longs[5 * ls + 4]) P.lpart.insert(P.lpart.end(), {(int32_t)ls, (int32_t)(P.longs[5 * ls + 3] + i)});
     return P;
 }
 
@@ -1342,7 +1350,7 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             int64_t long_nnz = 0;
             for (int64_t i = 0; i < P.nlong(); ++i) long_nnz += P.longs[5 * i + 2];
             rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz : w * (nseg + 1) + w * nnz) + 40 * P.nlong() +
-                  12 * P.nparts() + 8 * nnz;
+                  16 * P.nparts() + 8 * nnz;
             rw += 8 * nseg + 8 * P.nparts();
         };
         if ((mask & EXA_EV_GRAD) && !M.grad_direct) seg(M.grad_map);

@@ -102,10 +102,10 @@ void set_schedule(Model& M, int mode, int block, int epl, bool fused);
 struct ChunkPlan {
     bool chunked = false;  // chunk lanes (else one lane per segment)
     std::vector<int32_t> meta, lidx;    // 2 and 4 per lane, a multiple of 256 lanes
-    std::vector<int32_t> longs, lpart;  // 5 per long segment; 1 per part
+    std::vector<int32_t> longs, lpart;  // 5 per long segment; 2 per part block
     int64_t nlanes() const { return (int64_t)meta.size() / 2; }
     int64_t nlong() const { return (int64_t)longs.size() / 5; }
-    int64_t nparts() const { return (int64_t)lpart.size(); }
+    int64_t nparts() const { return (int64_t)lpart.size() / 2; }
 };
 ChunkPlan chunk_plan(const SegMap& S);
 void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);

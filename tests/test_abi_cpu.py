@@ -244,7 +244,7 @@ def _chunk_plan_bytes(lengths, w=4):
     alone (a second statement of the rule): segments of at most 8 entries
     everywhere -> one lane per segment (pointers + positions).  Otherwise
     segments over 1,024 entries are summed in parts of 1,024 (20-byte table
-    entries read twice, 12 bytes per part), and the others either one lane
+    entries read twice, 16 bytes per part), and the others either one lane
     per segment (when none has more than 16 entries and they hold at least
     2^22 entries together) or in lanes of at most 4 entries (24-byte
     records, a segment's lanes inside one 256-lane block, the end padded to
@@ -268,7 +268,7 @@ def _chunk_plan_bytes(lengths, w=4):
         maps = 24 * lanes + 4 * long_nnz
     else:
         maps = w * (nseg + 1) + w * nnz
-    return maps + 40 * nlong + 12 * nparts + 8 * nnz, 8 * nseg + 8 * nparts
+    return maps + 40 * nlong + 16 * nparts + 8 * nnz, 8 * nseg + 8 * nparts
 
 
 @pytest.mark.parametrize("sizes", [[700, 400, 3, 0, 90], [1500, 2], [5000, 1025, 700, 3, 0, 2100]],
