@@ -201,8 +201,18 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce_long(ExaReduce R) {
         if (b < J.nlong) {
             const int32_t* L = J.longs + 5 * b;
             const int32_t seg = L[0], part0 = L[3], nparts = L[4];
+            // lane t adds parts t, t + 256, ... in that order; eight loads
+            // are issued before their adds, so a segment of thousands of
+            // parts is a few dependent round trips deep, not one per part
             double acc = 0.0;
-            for (int32_t i = threadIdx.x; i < nparts; i += 256) acc += J.lsum[part0 + i];
+            for (int32_t i0 = threadIdx.x; i0 < nparts; i0 += 256 * 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = i0 + 256 * u < nparts ? J.lsum[part0 + i0 + 256 * u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + 256 * u < nparts) acc += v[u];
+            }
             const double tot = block_sum(acc, lds);
             if (threadIdx.x == 0) put(J.out, seg, tot, k == R.ep_job, R.ax_alpha);
             return;
