@@ -630,9 +630,9 @@ std::string dest(const Pattern& P, int mode, const std::string& pd, const std::s
                  bool at_kb = true) {
     const std::string st = at_kb ? " + kb * " + std::to_string(out_step(P, mode)) : "";
     switch (mode) {
-        case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".o1" + st;
+        case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".ob" + st;
         case M_JAC: return out + " + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1" + st;
-        case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".o1" + st;
+        case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".ob" + st;
         case M_HPROD: return out + " + " + pd + ".oh" + st;
         case M_HESS: return out + " + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2" + st;
         case M_ADJ: return out + " + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op" + st;
@@ -865,12 +865,14 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                       oname(j) + "[" + std::to_string(s) + "]");
         if (buffer_mode(j.mode)) {
             // contributions to a work buffer that a reduction reads back: slot
-            // s of data point k at block + s * ndata + k, one coalesced store
-            // per slot and no staging (the reduction's gathers of one slot
-            // over neighbouring points are then neighbouring too)
+            // s of data point k at block + s * stride + k (stride: ndata
+            // rounded up to 16, so every slot array starts on a 128-byte
+            // line), one coalesced store per slot and no staging (the
+            // reduction's gathers of one slot over neighbouring points are
+            // then neighbouring too)
             std::string line = j.mode == M_GRAD ? "if (!" + call(M_GRAD) + ".direct) " : "";
             line += "exa_store_soa<" + std::to_string(out_step(P, j.mode)) + ">(" + dest(P, j.mode, pd, j.out, false) +
-                    ", " + pd + ".ndata, kr, kend, " + oname(j) + ");";
+                    ", (" + pd + ".ndata + 15) & ~15LL, kr, kend, " + oname(j) + ");";
             e.raw(line);
         } else if (!scalar_mode(j.mode)) {
             // this job's outputs leave registers as soon as they are complete
@@ -1120,7 +1122,8 @@ __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double
     __syncthreads();
 }
 // Slot-major store to a work buffer: slot s of data point k at
-// base[s * n + k] (lanes past the end of the tile store nothing).
+// base[s * n + k], n the padded slot stride (lanes past the end of the tile
+// store nothing).
 template <int ST>
 __device__ __forceinline__ void exa_store_soa(double* __restrict__ base, long long n, long long k, long long kend,
                                               const double* o) {

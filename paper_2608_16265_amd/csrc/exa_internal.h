@@ -57,6 +57,7 @@ void set_last_error(const std::string& msg);
         long long o2;                                                            \
         long long op;                                                            \
         long long oh;                                                            \
+        long long ob;                                                            \
         long long tgt0;                                                          \
         long long row_off;                                                       \
         int row_ic;                                                              \
@@ -166,6 +167,7 @@ struct Pattern {
     int64_t o1 = 0;   // CON/AUG first jac entry; OBJ first grad-buffer entry
     int64_t o2 = 0;   // first hess entry
     int64_t op = 0;   // first param-buffer entry
+    int64_t ob = 0;   // first entry of this pattern's block in its part of the first-order buffer
     int target = -1;
     int row_icol = -1;
     int64_t row_off = 0;
@@ -184,6 +186,10 @@ struct Pattern {
     std::vector<int> hvs;
     int64_t oh = 0;   // first entry of this pattern in the H v buffer
 
+    // work buffers (first-order, H v, parameter) hold each pattern's block
+    // slot-major: slot s of data point k at block + s * bstride() + k, with
+    // every slot array padded to whole 128-byte lines
+    int64_t bstride() const { return (ndata + 15) & ~(int64_t)15; }
     int o1step() const { return (int)vslots.size(); }
     int o2step() const { return (int)hslots.size(); }
     int pstep() const { return (int)pslots.size(); }
@@ -239,6 +245,9 @@ struct DeviceState;  // defined in exa_runtime.cpp
 struct Model {
     int64_t nvar = 0, ncon = 0, ntheta = 0;
     int64_t nnzj = 0, nnzh = 0, nnzg = 0, naug = 0, nnzp = 0, nobj = 0, nhv = 0;
+    // work-buffer lengths (entries, slot arrays padded): first-order buffer
+    // (objective part, then constraint part), H v buffer, parameter buffer
+    int64_t fo_obj_len = 0, fo_con_len = 0, hv_len = 0, par_len = 0;
     // every variable gets at most one objective-gradient contribution: the
     // gradient kernel writes g directly (plus zero tiles for the rest)
     bool grad_direct = false;

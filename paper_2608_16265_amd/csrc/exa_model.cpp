@@ -374,8 +374,17 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             P.o1 = nnzj;
             nnzj += P.ndata * P.o1step();
         }
+        const int64_t bs = P.bstride();
+        if (P.kind == EXA_OBJ) {
+            P.ob = M.fo_obj_len;
+            M.fo_obj_len += bs * P.o1step();
+        } else {
+            P.ob = M.fo_con_len;
+            M.fo_con_len += bs * P.o1step();
+        }
         if (P.pstep() > 0 && P.o1step() > 0) {
-            P.op = nnzp;
+            P.op = M.par_len;
+            M.par_len += bs * P.pstep();
             nnzp += P.ndata * P.pstep();
         }
         for (int s = 0; s < P.o1step(); ++s) {
@@ -383,7 +392,8 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             for (auto& h : P.hslots) curved |= h.first == s || h.second == s;
             if (curved) P.hvs.push_back(s);
         }
-        P.oh = M.nhv;
+        P.oh = M.hv_len;
+        M.hv_len += bs * (int64_t)P.hvs.size();
         M.nhv += P.ndata * (int64_t)P.hvs.size();
     }
     M.ncon = ncon;
@@ -442,25 +452,44 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     // ---- reduction maps (Sec. 7.2.3): sorted by target; within a target
     // the contributions are summed in (pattern, data point, slot) order.
     // The work buffers hold each pattern's block slot-major: slot s of data
-    // point k at block + s * ndata + k.
+    // point k at block + s * bstride() + k (the constraint part of the
+    // first-order buffer after the objective part).
     std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr;
     for (auto& P : M.pats) {
         const int st = P.o1step();
+        const int64_t bs = P.bstride();
         for (int64_t k = 0; k < P.ndata; ++k)
             for (int s = 0; s < st; ++s) {
                 const int64_t v = P.var_index(s, k);
                 if (P.kind == EXA_OBJ)
-                    g.emplace_back(v, P.o1 + s * P.ndata + k);
+                    g.emplace_back(v, P.ob + s * bs + k);
                 else
-                    jt.emplace_back(v, nnzg + P.o1 + s * P.ndata + k);
+                    jt.emplace_back(v, M.fo_obj_len + P.ob + s * bs + k);
             }
         const int hs = (int)P.hvs.size();
         for (int64_t k = 0; k < P.ndata; ++k)
-            for (int i = 0; i < hs; ++i) h.emplace_back(P.var_index(P.hvs[i], k), P.oh + i * P.ndata + k);
+            for (int i = 0; i < hs; ++i) h.emplace_back(P.var_index(P.hvs[i], k), P.oh + i * bs + k);
         if (P.pstep() > 0 && P.o1step() > 0)
             for (int64_t k = 0; k < P.ndata; ++k)
                 for (int t = 0; t < P.pstep(); ++t)
-                    pr.emplace_back(P.par_index(t, k), P.op + t * P.ndata + k);
+                    pr.emplace_back(P.par_index(t, k), P.op + t * bs + k);
+    }
+    // every position lies inside its buffer (the kernels store to the same
+    // positions: block + slot * bstride() + k, k < ndata)
+    auto inside = [](const std::vector<std::pair<int64_t, int64_t>>& e, int64_t len, const char* what) {
+        for (auto& x : e)
+            if (x.second < 0 || x.second >= len) fail(EXA_EINVAL, std::string("internal: work-buffer position outside the ") + what);
+    };
+    inside(g, M.fo_obj_len, "objective part of the first-order buffer");
+    inside(jt, M.fo_obj_len + M.fo_con_len, "first-order buffer");
+    inside(h, M.hv_len, "H v buffer");
+    inside(pr, M.par_len, "parameter buffer");
+    for (auto& P : M.pats) {
+        const int64_t bs = P.bstride();
+        if (P.ob + bs * P.o1step() > (P.kind == EXA_OBJ ? M.fo_obj_len : M.fo_con_len) ||
+            P.oh + bs * (int64_t)P.hvs.size() > M.hv_len ||
+            (P.pstep() > 0 && P.o1step() > 0 && P.op + bs * P.pstep() > M.par_len))
+            fail(EXA_EINVAL, "internal: a pattern's work-buffer block ends past its buffer");
     }
     build_map(M.grad_map, M.nvar, g);
     M.grad_direct = true;

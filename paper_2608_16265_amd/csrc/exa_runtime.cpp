@@ -179,6 +179,7 @@ void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
         d.o2 = P.o2;
         d.op = P.op;
         d.oh = P.oh;
+        d.ob = P.ob;
         d.tgt0 = P.tgt0;
         d.row_off = P.row_off;
         d.row_ic = P.row_icol;
@@ -204,7 +205,7 @@ void build_device(Model& M) {
     ExaInstDev inst;
     fill_patdev(M, D, inst);
     inst.theta = D.theta;
-    inst.off[EXA_OFF_FO_CON] = M.nnzg;
+    inst.off[EXA_OFF_FO_CON] = M.fo_obj_len;
     D.inst_host = inst;
     D.inst = (ExaInstDev*)D.upload(&inst, sizeof inst);
 
@@ -215,9 +216,9 @@ void build_device(Model& M) {
         set_schedule(M, mode, fixed ? kObjBlock : M.block, fixed ? kObjEpl : M.epl, fixed ? kObjFused : M.fuse);
         D.sched[mode].tuned = fixed || !M.autotune;
     }
-    D.fo = (double*)D.alloc((M.nnzg + M.nnzj) * sizeof(double));
-    D.par = (double*)D.alloc(M.nnzp * sizeof(double));
-    D.hv = (double*)D.alloc(M.nhv * sizeof(double));
+    D.fo = (double*)D.alloc((M.fo_obj_len + M.fo_con_len) * sizeof(double));
+    D.par = (double*)D.alloc(M.par_len * sizeof(double));
+    D.hv = (double*)D.alloc(M.hv_len * sizeof(double));
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
     D.lag_tmp = (double*)D.alloc(M.nvar * sizeof(double));
 
