@@ -1,44 +1,36 @@
 """Benchmark: Jacobian + Hessian nonzeros evaluated per second (FP64).
 
-Workload (default): the ACOPF-shaped synthetic model with 10,000 buses,
-13,500 branches and 2,000 generators (seed 1), one instance on one GPU.
-One step = every per-iterate callback a solver makes (obj, grad, cons,
-jac_coord, hess_coord, jprod, jtprod, hprod) at one iterate, on inputs
-already resident in device memory, through one exa_eval call: one
-evaluation launch and one reduction launch, outputs bit-identical to the
-separate callbacks.  value = (nnzj + nnzh) / step time.
+Workload (default headline): 256 ACOPF-shaped synthetic instances of uneven
+size (buses log-uniform in 500-20,000, loads perturbed by U(0.9, 1.1),
+seeds 1000-1255), the batched configuration, on one GPU.  One step = every
+per-iterate callback a solver makes (obj, grad, cons, jac_coord,
+hess_coord, jprod, jtprod, hprod) for every instance at one iterate, on
+inputs already resident in device memory, through one exa_batch_eval call
+replayed from a HIP graph: one evaluation launch over every instance's
+tiles and one launch of every instance's reductions, each instance's
+outputs bit-identical to its own callbacks.
+value = sum over instances of (nnzj + nnzh) / step time.
 
 Also reported on the same JSON line:
-* step_separate_us -- the same step as seven separate callback calls;
-* step_graph_us -- the step captured once into a HIP graph and replayed
-  (the paper's protocol times with and without a graph);
-* ipm_step_us   -- what an interior-point iteration asks for (obj, grad,
-  cons, jac, hess) through one exa_eval call, and its nnz/s;
-* callbacks_us  -- each callback alone, timed with the paper's protocol
-  (Sec. 8.2: back-to-back calls, one synchronization, best of 3);
-* roofline      -- the step's evaluation kernel (exa_k_multi, exa_k_multijh
-  with Jacobian + Hessian units, or exa_k_onepass when the tuner picks one
-  pass per point for every callback): algorithmic
-  bytes per launch / its average duration, measured by HIP events that the
-  library records on the launch stream around each launch, against the
-  8 TB/s HBM peak; the reduction launch and the combined Jacobian+Hessian
-  kernel are reported beside it;
-* hbm_copy_gbs  -- a 1 GiB device copy with the library's 16-byte
-  non-temporal copy kernel (read + write bytes per second), the practical
-  ceiling of a streaming kernel beside the nominal 8 TB/s (torch's copy in
-  hbm_copy_torch_gbs);
-* rotated       -- the same step cycling over K sets of inputs and outputs
-  (>= 512 MB together), so that they come from HBM and not from the 256 MB
-  last-level cache (the steady-state step reuses one set, as the paper's
-  protocol does);
-* cpu_baseline  -- the CPU oracle (numpy, float64) on a bounded sample;
-* pde           -- the PDE-control model on a 1000 x 1000 grid
-  (HBM-bound): the same step and rooflines;
-* batched       -- 256 uneven ACOPF instances (500 to 20,000 buses) in one
-  persistent graph-replayed launch vs 256 sequential plain calls;
+* batched       -- the same batch against the plain per-instance path: 256
+  exa_eval calls of every callback, 256 exa_jac_hess_coord calls, 256
+  exa_jac_coord + exa_hess_coord pairs, and the batched Jacobian + Hessian
+  alone; speedups, and a bitwise check of every instance's every output;
+* roofline      -- the step's evaluation launch: algorithmic bytes per
+  launch / its average duration, from HIP events that the library records
+  on the launch stream around each launch, against the 8 TB/s HBM peak
+  (traffic: rocprofv3 FETCH_SIZE + WRITE_SIZE of the committed profile);
+  the reduction launch beside it;
+* cpu_baseline  -- the CPU oracle (numpy, float64) on a bounded sample of
+  the same workload: every callback of whole instances, one process and
+  one process per core (before the GPU is touched);
+* acopf10k, pde -- one 10,000-bus ACOPF instance and the PDE-control model
+  on a 1000 x 1000 grid: the same step through exa_eval, graph replay,
+  separate callbacks, rotated buffers, rooflines;
 * adjoint       -- 64 instances of the 10,000-bus model: grad_x L(theta)
-  through torch.autograd and its hand-written adjoint, timed against the
-  forward and the plain gradient.
+  of all of them as one torch.autograd.Function over the batch and its
+  hand-written adjoint, timed against the forward and the plain gradient;
+* ladders, compile -- per-instance scaling and build time.
 """
 from __future__ import annotations
 
@@ -69,7 +61,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the PDE, batched, adjoint, ladder and compile-time legs")
-    ap.add_argument("--only", choices=["acopf", "pde", "batch", "adjoint", "ladders", "compile"], default=None,
+    ap.add_argument("--only", choices=["batch", "acopf", "pde", "adjoint", "ladders", "compile"], default=None,
                     help="run one leg only (used for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--quick", action="store_true",
@@ -78,6 +70,10 @@ def parse():
                     help="block,points_per_lane,fused,units (0 per callback, 1 Jacobian + Hessian units, "
                          "2 one pass): fix the step's exa_eval schedule instead of "
                          "tuning it (to profile the schedule an unprofiled run chose)")
+    ap.add_argument("--batch-schedule", default=None,
+                    help="block,points_per_lane,fused,units (per_callback, jac_hess or one_pass): fix the "
+                         "headline batch step's schedule instead of tuning it (to profile the schedule an "
+                         "unprofiled run chose)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates "
                          "the profiler's HBM byte counters)")
@@ -247,6 +243,7 @@ def _callbacks(em, wl, dev="cuda:0"):
 
 
 EVAL_SCHEDULE = None
+BATCH_SCHEDULE = None
 
 
 def leg_single(name, wl, steps, warmup):
@@ -348,7 +345,34 @@ def leg_single(name, wl, steps, warmup):
     return res
 
 
-def leg_batch(count=256, first_seed=1000):
+ALL8 = dict(f="B", g="x", c="y", jac="jac", hess="hess", jv="y", jtw="x", hv="x")
+BATCH_CBS = ("obj", "grad", "cons", "jac", "hess", "jprod", "jtprod", "hprod")
+
+
+def batch_launch_us(b, run, n=50):
+    """Average durations (us) of the batched evaluation and reduction
+    launches: with timing on, the library launches directly and records HIP
+    events on the launch stream around each launch; the queue is first
+    filled with a long matrix product so that the calls run back to back."""
+    import torch
+    if QUICK:
+        n = min(n, 5)
+    a = torch.ones(4096, 4096, dtype=torch.float64, device="cuda:0")
+    b.timing(True)
+    run()
+    torch.cuda.synchronize()
+    b.timing_read()
+    for _ in range(24):
+        a = a @ a * 1e-4
+    for _ in range(n):
+        run()
+    t = b.timing_read()
+    b.timing(False)
+    return t
+
+
+def leg_batch(steps, warmup, count=256, first_seed=1000):
+    """The headline: all callbacks of 256 uneven instances per step."""
     import torch
     from exa_modeling.generators import acopf_batch
     from paper_2608_16265_amd import ExaModel
@@ -362,58 +386,125 @@ def leg_batch(count=256, first_seed=1000):
             log(f"  batch: {i + 1}/{count} models built")
     build_s = time.perf_counter() - t0
     b = ExaBatch(ems, autotune=True)
-    X = b.concat_x([w.x for w in wls])
-    Y = b.concat_y([w.y for w in wls])
-    J = torch.empty(b.total("jac"), dtype=torch.float64, device="cuda:0")
-    H = torch.empty(b.total("hess"), dtype=torch.float64, device="cuda:0")
-    b.eval(X, Y, 1.0, J, H)  # tunes the schedule, records the graph
+    if BATCH_SCHEDULE:
+        bk, ep, fu, un = BATCH_SCHEDULE.split(",")
+        b.set_schedule(BATCH_CBS, int(bk), int(ep), bool(int(fu)), un)
+    dev = "cuda:0"
+    rng = np.random.default_rng(0)
+    X = b.concat([w.x for w in wls])
+    Y = b.concat([w.y for w in wls])
+    V = torch.as_tensor(rng.standard_normal(b.total("x")), device=dev)
+    W = torch.as_tensor(rng.standard_normal(b.total("y")), device=dev)
+    outs = {k: b.empty(kind) for k, kind in ALL8.items()}
+    step = b.bind(X, Y, 1.0, V, W, **outs)
+    t0 = time.perf_counter()
+    step()  # tunes the schedule, records the graph
     torch.cuda.synchronize()
-    t_batch = best_of_3(lambda: b.eval(X, Y, 1.0, J, H))
-    xs = [torch.as_tensor(w.x, device="cuda:0") for w in wls]
-    ys = [torch.as_tensor(w.y, device="cuda:0") for w in wls]
-    js = [torch.empty(e.nnzj, dtype=torch.float64, device="cuda:0") for e in ems]
-    hs = [torch.empty(e.nnzh, dtype=torch.float64, device="cuda:0") for e in ems]
+    tune_s = time.perf_counter() - t0
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / steps
+    log(f"  batch step {step_s * 1e6:.1f} us")
+    tm = batch_launch_us(b, step)
+    eb = b.kernel_bytes(BATCH_CBS)
+    sched = b.schedule(BATCH_CBS)
+    eval_kernel = ("exa_k_onepass" if sched["units"] == "one_pass" else
+                   "exa_k_multijh" if sched["units"] == "jac_hess" else "exa_k_multi")
+    # the batched Jacobian + Hessian alone (the metric's own pair)
+    J, H = b.empty("jac"), b.empty("hess")
+    jh = b.bind(X, Y, 1.0, jac=J, hess=H)
+    jh()
+    torch.cuda.synchronize()
+    t_jh = best_of_3(jh)
+    jh_sched = b.schedule(("jac", "hess"))
+    jh_bytes = b.kernel_bytes(("jac", "hess"))
+    jh_tm = batch_launch_us(b, jh)
+    # the plain per-instance path on the same data
+    off = b.offsets()
+    xs = [X[b.slice("x", i)].clone() for i in range(count)]
+    ys = [Y[b.slice("y", i)].clone() for i in range(count)]
+    vs = [V[b.slice("x", i)].clone() for i in range(count)]
+    ws = [W[b.slice("y", i)].clone() for i in range(count)]
+    e = lambda n: torch.empty(n, dtype=torch.float64, device=dev)  # noqa: E731
+    plain_outs = [dict(f=e(1), g=e(m.nvar), c=e(m.ncon), jac=e(m.nnzj), hess=e(m.nnzh), jv=e(m.ncon),
+                       jtw=e(m.nvar), hv=e(m.nvar)) for m in ems]
+    binds = [m.bind(x, y, 1.0, v, w, **o) for m, x, y, v, w, o in zip(ems, xs, ys, vs, ws, plain_outs)]
+    for f in binds:
+        f()
+    torch.cuda.synchronize()
 
-    def plain():
-        for e, x, y, j, h in zip(ems, xs, ys, js, hs):
-            e.jac_coord(x, j)
-            e.hess_coord(x, y, 1.0, h)
+    def plain_all():
+        for f in binds:
+            f()
 
-    t_plain = best_of_3(plain, min_s=0.3)
-    nnz = b.total("jac") + b.total("hess")
-    # identical results, instance by instance
+    def plain_jh():
+        for m, x, y, o in zip(ems, xs, ys, plain_outs):
+            m.jac_hess_coord(x, y, 1.0, o["jac"], o["hess"])
+
+    def plain_two():
+        for m, x, y, o in zip(ems, xs, ys, plain_outs):
+            m.jac_coord(x, o["jac"])
+            m.hess_coord(x, y, 1.0, o["hess"])
+
+    t_plain_all = best_of_3(plain_all, min_s=0.3)
+    t_plain_jh = best_of_3(plain_jh, min_s=0.3)
+    t_plain_two = best_of_3(plain_two, min_s=0.3)
+    # every instance's every output, bit for bit
+    for f in binds:
+        f()
+    step()
     torch.cuda.synchronize()
     same = True
-    off = b.offsets()
-    for i in range(0, count, 17):
-        same &= bool(torch.equal(J[off[i, 2]:off[i + 1, 2]], js[i]))
-        same &= bool(torch.equal(H[off[i, 3]:off[i + 1, 3]], hs[i]))
-    sched = b.schedule()
-    k_mean, _ = kernel_ms(lambda: b.eval(X, Y, 1.0, J, H), n=50)
-    rd, wr = b.kernel_bytes()
-    res = dict(instances=count, buses=int(sum(w.meta["nb"] for w in wls)), nnz=int(nnz),
-               build_s=round(build_s, 2), batched_us=round(t_batch * 1e6, 1),
-               plain_us=round(t_plain * 1e6, 1), speedup=t_plain / t_batch,
-               batched_nnz_per_s=nnz / t_batch, plain_nnz_per_s=nnz / t_plain,
-               bitwise_equal_sampled=same, schedule=sched,
-               kernel_us=round(k_mean * 1e3, 1), read_bytes=rd, write_bytes=wr,
-               roofline={"kernel": "exa_k_jh", "bound": "hbm",
-                         "achieved": (rd + wr) / (k_mean * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": (rd + wr) / (k_mean * 1e-3) / 1e9 / HBM_PEAK_GBS})
+    for i in range(count):
+        for k, kind in ALL8.items():
+            sl = slice(i, i + 1) if kind == "B" else b.slice(kind, i)
+            same &= bool(torch.equal(outs[k][sl], plain_outs[i][k]))
+    same_jh = all(bool(torch.equal(J[b.slice("jac", i)], plain_outs[i]["jac"])) and
+                  bool(torch.equal(H[b.slice("hess", i)], plain_outs[i]["hess"])) for i in range(count))
+    nnz = b.total("jac") + b.total("hess")
+    ev_bytes = eb["eval_read"] + eb["eval_write"]
+    red_bytes = eb["reduce_read"] + eb["reduce_write"]
+    res = dict(
+        instances=count, buses=int(sum(w.meta["nb"] for w in wls)),
+        nvar=b.total("x"), ncon=b.total("y"), nnzj=b.total("jac"), nnzh=b.total("hess"), nnz=int(nnz),
+        build_s=round(build_s, 2), first_call_s=round(tune_s, 2),
+        step_s=step_s, nnz_per_s=nnz / step_s, schedule=sched, eval_kernel=eval_kernel,
+        eval_us=round(tm["eval_us"], 2), reduce_us=round(tm["reduce_us"], 2), launches_timed=tm["calls"],
+        eval_read_bytes=eb["eval_read"], eval_write_bytes=eb["eval_write"], eval_bytes=ev_bytes,
+        reduce_bytes=red_bytes, eval_gbs=ev_bytes / (tm["eval_us"] * 1e-6) / 1e9,
+        reduce_gbs=red_bytes / (tm["reduce_us"] * 1e-6) / 1e9 if tm["reduce_us"] > 0 else None,
+        plain_eval_all_us=round(t_plain_all * 1e6, 1), speedup_vs_plain_eval_all=t_plain_all / step_s,
+        batched_jac_hess_us=round(t_jh * 1e6, 1), batched_jac_hess_nnz_per_s=nnz / t_jh,
+        jac_hess_schedule=jh_sched, jac_hess_eval_us=round(jh_tm["eval_us"], 2),
+        jac_hess_bytes=jh_bytes["eval_read"] + jh_bytes["eval_write"],
+        jac_hess_gbs=(jh_bytes["eval_read"] + jh_bytes["eval_write"]) / (jh_tm["eval_us"] * 1e-6) / 1e9,
+        plain_jac_hess_coord_us=round(t_plain_jh * 1e6, 1),
+        plain_jac_then_hess_us=round(t_plain_two * 1e6, 1),
+        speedup_jac_hess_vs_plain_jac_hess_coord=t_plain_jh / t_jh,
+        speedup_jac_hess_vs_plain_jac_then_hess=t_plain_two / t_jh,
+        bitwise_equal_all_instances=bool(same), bitwise_equal_jac_hess=bool(same_jh))
+    del off
     b.close()
-    for e in ems:
-        e.close()
+    for m in ems:
+        m.close()
     return res
 
 
 def leg_adjoint(count=64, first_seed=2000):
-    """64 instances of the 10,000-bus model: the Lagrangian gradient as a
-    function of theta (forward) and its hand-written adjoint (backward),
-    through torch.autograd, vs the plain gradient callback."""
+    """64 instances of the 10,000-bus model: the Lagrangian gradients as one
+    function of the concatenated parameters (forward: one batched call of
+    EXA_EV_LAG), its hand-written adjoint (backward: one batched call of
+    EXA_EV_ADJ), through torch.autograd, vs the plain gradient."""
     import torch
     from exa_modeling.generators import acopf
     from paper_2608_16265_amd import ExaModel
-    from paper_2608_16265_amd.adjoint import lagrangian_gradient
+    from paper_2608_16265_amd.adjoint import batch_lagrangian_gradient, lagrangian_gradient
+    from paper_2608_16265_amd.batch import ExaBatch
     t0 = time.perf_counter()
     wls, ems = [], []
     for i in range(count):
@@ -423,37 +514,51 @@ def leg_adjoint(count=64, first_seed=2000):
             log(f"  adjoint: {i + 1}/{count} models built")
     build_s = time.perf_counter() - t0
     dev = "cuda:0"
-    xs = [torch.as_tensor(w.x, device=dev) for w in wls]
-    ys = [torch.as_tensor(w.y, device=dev) for w in wls]
-    ths = [torch.as_tensor(w.model.theta, device=dev).requires_grad_(True) for w in wls]
-    ws = [torch.as_tensor(np.random.default_rng(first_seed + i).standard_normal(e.nvar), device=dev)
-          for i, e in enumerate(ems)]
-    gs = [torch.empty(e.nvar, dtype=torch.float64, device=dev) for e in ems]
+    b = ExaBatch(ems, autotune=True)
+    X = b.concat([w.x for w in wls])
+    Y = b.concat([w.y for w in wls])
+    TH = b.concat([w.model.theta for w in wls])
+    theta = TH.clone().requires_grad_(True)
+    Wc = torch.as_tensor(np.concatenate([np.random.default_rng(first_seed + i).standard_normal(e.nvar)
+                                         for i, e in enumerate(ems)]), device=dev)
+    G = b.empty("x")
+    TB = b.empty("theta")
+    grad_only = b.bind(X, Y, 1.0, g=G)
+    adj_only = b.bind(X, Y, 1.0, wx=Wc, theta_bar=TB)
 
     def forward():
-        return [lagrangian_gradient(th, e, x, y, 1.0) for th, e, x, y in zip(ths, ems, xs, ys)]
+        return batch_lagrangian_gradient(theta, b, X, Y, 1.0)
 
     def fwd_bwd():
-        outs = forward()
-        torch.autograd.backward(outs, ws)
+        out = forward()
+        torch.autograd.backward(out, Wc)
 
-    def backward_only():
-        for th, e, x, y, w in zip(ths, ems, xs, ys, ws):
-            e.adjoint_theta(x, y, 1.0, w)
-
-    def grad_only():
-        for e, x, g in zip(ems, xs, gs):
-            e.grad(x, g)
-
-    t_fwd = best_of_3(lambda: forward(), min_s=0.2)
+    for fn in (forward, fwd_bwd, grad_only, adj_only):  # first calls tune and record
+        fn()
+    torch.cuda.synchronize()
+    t_fwd = best_of_3(forward, min_s=0.2)
     t_fb = best_of_3(fwd_bwd, min_s=0.2)
-    t_bwd = best_of_3(backward_only, min_s=0.2)
+    t_bwd = best_of_3(adj_only, min_s=0.2)
     t_grad = best_of_3(grad_only, min_s=0.2)
+    # the per-instance path it replaces: 64 autograd nodes over 64 models
+    xs = [X[b.slice("x", i)].clone() for i in range(count)]
+    ys = [Y[b.slice("y", i)].clone() for i in range(count)]
+    ths = [TH[b.slice("theta", i)].clone().requires_grad_(True) for i in range(count)]
+    wss = [Wc[b.slice("x", i)].clone() for i in range(count)]
+
+    def per_instance_fb():
+        outs = [lagrangian_gradient(th, e, x, y, 1.0) for th, e, x, y in zip(ths, ems, xs, ys)]
+        torch.autograd.backward(outs, wss)
+
+    t_pi = best_of_3(per_instance_fb, min_s=0.2)
+    b.close()
     return dict(instances=count, buses_each=10000, ntheta_each=ems[0].ntheta,
                 build_s=round(build_s, 2), forward_us=round(t_fwd * 1e6, 1),
                 forward_backward_us=round(t_fb * 1e6, 1), adjoint_kernel_path_us=round(t_bwd * 1e6, 1),
                 grad_us=round(t_grad * 1e6, 1), backward_over_forward=t_bwd / t_fwd,
-                backward_over_grad=t_bwd / t_grad)
+                backward_over_grad=t_bwd / t_grad,
+                autograd_overhead_us=round((t_fb - t_fwd - t_bwd) * 1e6, 1),
+                per_instance_forward_backward_us=round(t_pi * 1e6, 1))
 
 
 LADDER_CBS = ("obj", "grad", "cons", "jac_coord", "hess_coord", "jac_hess_coord", "jprod", "jtprod", "hprod",
@@ -544,25 +649,72 @@ def leg_compile():
                 size=[_compile_point(4, n) for n in (1000, 10000, 100000, 1000000)])
 
 
-def cpu_baseline(wl, seconds):
-    """The CPU oracle as it stands, timed on a bounded sample of the same
-    workload: repeated full jac_coord + hess_coord of the 10k-bus model."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_instances(worker, workers, seconds, first_seed=1000, count=256):
+    """Every callback of whole instances of the batch workload through the
+    oracle as it stands (instances worker, worker + workers, ...), until
+    `seconds` of timed work; setup (drawing the instance and the oracle's
+    structure analysis) is not timed.  Returns (nnz, timed seconds,
+    instances)."""
+    from exa_modeling.generators import acopf_batch_instance
     from oracle import OracleModel
-    o = OracleModel(wl.model)
-    o.jac_coord(wl.x)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.jac_coord(wl.x)
-        o.hess_coord(wl.x, wl.y, 1.0)
+    nnz, busy, n = 0, 0.0, 0
+    i = worker
+    while busy < seconds and i < count:
+        w = acopf_batch_instance(first_seed + i)
+        o = OracleModel(w.model)
+        rng = np.random.default_rng(i)
+        v, wv = rng.standard_normal(o.nvar), rng.standard_normal(o.ncon)
+        t0 = time.perf_counter()
+        o.obj(w.x)
+        o.grad(w.x)
+        o.cons(w.x)
+        o.jac_coord(w.x)
+        o.hess_coord(w.x, w.y, 1.0)
+        o.jprod(w.x, v)
+        o.jtprod(w.x, wv)
+        o.hprod(w.x, w.y, 1.0, v)
+        busy += time.perf_counter() - t0
+        nnz += o.nnzj + o.nnzh
         n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    per = (time.perf_counter() - t0) / n
-    nnz = o.nnzj + o.nnzh
-    return dict(value=nnz / per, unit="nnz/s", cores=1, kind="oracle",
-                sample=f"{n} x (jac_coord + hess_coord) of the full 10,000-bus model, "
-                       f"{per:.3f} s each, numpy float64 single thread")
+        i += workers
+    return nnz, busy, n
+
+
+def cpu_baseline(seconds):
+    """The CPU oracle timed on the host's cores (before the GPU is used):
+    one process, then one process per core (at most 16, the CPU share of
+    one GPU on the measured boxes), each evaluating every callback of whole
+    instances of the 256-instance workload.  nnz/s = Jacobian + Hessian
+    entries of the instances done / wall time."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    nnz1, t1, n1 = _oracle_instances(0, 1, seconds)
+    workers = max(1, min(os.cpu_count() or 1, 16))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+        res = list(ex.map(_oracle_instances, range(workers), [workers] * workers, [seconds] * workers))
+    wall = time.perf_counter() - t0
+    nnzp = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    np_ = sum(r[2] for r in res)
+    return dict(value=nnzp / busy, unit="nnz/s", cores=workers, kind="oracle",
+                single_thread_value=nnz1 / t1, single_thread_cores=1,
+                cpu_model=_cpu_model(), host_cpus=os.cpu_count(),
+                sample=(f"every callback (obj, grad, cons, jac, hess, jprod, jtprod, hprod) of whole instances of "
+                        f"the 256-instance ACOPF batch (seeds 1000+): {n1} instances in {t1:.1f} s on one core; "
+                        f"{np_} instances on {workers} processes, the longest busy {busy:.1f} s "
+                        f"(wall {wall:.1f} s with setup); numpy float64, the oracle as it stands"))
 
 
 def copy_only(mib):
@@ -577,10 +729,11 @@ def copy_only(mib):
 
 
 def main():
-    global QUICK, EVAL_SCHEDULE
+    global QUICK, EVAL_SCHEDULE, BATCH_SCHEDULE
     args = parse()
     QUICK = args.quick
     EVAL_SCHEDULE = args.eval_schedule
+    BATCH_SCHEDULE = args.batch_schedule
     if args.copy_mib:
         copy_only(args.copy_mib)
         return
@@ -589,52 +742,73 @@ def main():
               "(instances of a batch would be sharded across GPUs with no exchange; not implemented).",
               file=sys.stderr)
         sys.exit(2)
+    out = {"metric": METRIC, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    cpu = None
+    if args.only in (None, "batch") and not args.no_cpu_baseline:
+        # before anything touches the GPU: the worker processes are forked
+        log("leg: cpu baseline")
+        cpu = cpu_baseline(args.cpu_seconds)
+        log(json.dumps(cpu))
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     from exa_modeling.generators import acopf, pde
 
-    out = {"metric": METRIC, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
-    if args.only in (None, "acopf"):
+    if args.only in (None, "batch"):
+        log("leg: batched 256 (headline)")
+        r = leg_batch(args.steps, args.warmup)
+        log(json.dumps(r))
+        out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
+        out["config"] = {"workload": "acopf-batch-256: 256 uneven ACOPF instances, buses log-uniform in "
+                                     "500-20,000 (1,399,478 in total), loads x U(0.9, 1.1), seeds 1000-1255",
+                         "step": "exa_batch_eval of obj, grad, cons, jac, hess, jprod, jtprod, hprod for every "
+                                 "instance at one iterate (one graph replay: evaluation launch + reduction launch)",
+                         "instances": r["instances"], "buses": r["buses"], "nvar": r["nvar"], "ncon": r["ncon"],
+                         "nnzj": r["nnzj"], "nnzh": r["nnzh"], "schedule": r["schedule"]}
+        from exa_modeling.generators import acopf as _acopf
+        traffic = profiled_traffic("batch256_eval_all.md", _acopf(30, 0).model, r["eval_kernel"])
+        out["roofline"] = {"kernel": r["eval_kernel"], "bound": "hbm", "achieved": r["eval_gbs"],
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r["eval_gbs"] / HBM_PEAK_GBS,
+                           "traffic": traffic, "bytes_per_launch": r["eval_bytes"],
+                           "read_bytes": r["eval_read_bytes"], "write_bytes": r["eval_write_bytes"],
+                           "launch_us": r["eval_us"], "launches_timed": r["launches_timed"]}
+        out["roofline_reduce"] = {"kernel": "k_reduce_batch", "achieved": r["reduce_gbs"],
+                                  "frac": (r["reduce_gbs"] or 0.0) / HBM_PEAK_GBS,
+                                  "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]}
+        out["batched"] = {k: v for k, v in r.items() if k not in ("schedule",)}
+        if cpu is not None:
+            out["cpu_baseline"] = cpu
+        cg = copy_gbs()
+        out["hbm_copy_gbs"] = cg["exa_device_copy"]
+        out["hbm_copy_torch_gbs"] = cg["torch"]
+    if not args.no_extras and args.only in (None, "acopf"):
         log("leg: acopf 10k")
         wl = acopf(10000, 1)
         r = leg_single("acopf10k", wl, args.steps, args.warmup)
         log(json.dumps(r))
-        out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
-        out["config"] = {"workload": "acopf-10000-bus (13,500 branches, 2,000 generators, seed 1)",
-                         "step": "exa_eval of obj, grad, cons, jac, hess, jprod, jtprod, hprod at one iterate",
-                         "nvar": r["nvar"], "ncon": r["ncon"], "nnzj": r["nnzj"],
-                         "nnzh": r["nnzh"], "schedule": r["schedule"]}
-        out["step_separate_us"] = r["step_separate_us"]
-        out["step_graph_us"] = r["step_graph_us"]
-        out["rotated"] = r["rotated"]
-        out["callbacks_us"] = r["callbacks_us"]
-        out["jac_hess_nnz_per_s"] = r["jac_hess_nnz_per_s"]
-        out["ipm_step_us"] = r["ipm_step_us"]
-        out["ipm_nnz_per_s"] = r["ipm_nnz_per_s"]
-        out["jac_plus_hess_nnz_per_s"] = r["jac_plus_hess_nnz_per_s"]
-        from exa_modeling.generators import acopf as _acopf
-        traffic = profiled_traffic("acopf10k_eval_all.md", _acopf(30, 0).model, r["eval_kernel"])
-        out["roofline"] = {"kernel": r["eval_kernel"], "bound": "hbm", "achieved": r["eval_gbs"],
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": r["eval_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                           "bytes_per_launch": r["eval_bytes"], "read_bytes": r["eval_read_bytes"],
-                           "write_bytes": r["eval_write_bytes"], "launch_us": r["eval_us"],
-                           "launches_timed": r["eval_calls_timed"]}
-        out["roofline_reduce"] = {"kernel": "k_reduce", "achieved": r["reduce_gbs"],
-                                  "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]}
-        out["roofline_jac_hess_coord"] = {"kernel": "exa_k_jh", "achieved": r["jh_gbs"],
-                                          "frac": r["jh_gbs"] / HBM_PEAK_GBS,
-                                          "bytes_per_launch": r["jh_bytes"], "launch_us": r["jh_kernel_us"]}
-        cg = copy_gbs()
-        out["hbm_copy_gbs"] = cg["exa_device_copy"]
-        out["hbm_copy_torch_gbs"] = cg["torch"]
-        if not args.no_cpu_baseline:
-            log("leg: cpu baseline")
-            out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        traffic = profiled_traffic("acopf10k_eval_all.md", acopf(30, 0).model, r["eval_kernel"])
+        out["acopf10k"] = {
+            "workload": "acopf-10000-bus (13,500 branches, 2,000 generators, seed 1)",
+            "step": "exa_eval of obj, grad, cons, jac, hess, jprod, jtprod, hprod at one iterate",
+            "nvar": r["nvar"], "ncon": r["ncon"], "nnzj": r["nnzj"], "nnzh": r["nnzh"],
+            "step_us": round(r["step_s"] * 1e6, 2), "nnz_per_s": r["nnz_per_s"], "schedule": r["schedule"],
+            "step_separate_us": r["step_separate_us"], "step_graph_us": r["step_graph_us"],
+            "rotated": r["rotated"], "callbacks_us": r["callbacks_us"],
+            "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"], "ipm_step_us": r["ipm_step_us"],
+            "ipm_nnz_per_s": r["ipm_nnz_per_s"], "jac_plus_hess_nnz_per_s": r["jac_plus_hess_nnz_per_s"],
+            "roofline_eval": {"kernel": r["eval_kernel"], "achieved": r["eval_gbs"], "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": r["eval_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                              "bytes_per_launch": r["eval_bytes"], "launch_us": r["eval_us"]},
+            "roofline_reduce": {"kernel": "k_reduce", "achieved": r["reduce_gbs"],
+                                "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]},
+            "roofline_jac_hess_coord": {"kernel": "exa_k_jh", "achieved": r["jh_gbs"],
+                                        "frac": r["jh_gbs"] / HBM_PEAK_GBS, "bytes_per_launch": r["jh_bytes"],
+                                        "launch_us": r["jh_kernel_us"]}}
+        if args.only == "acopf":
+            out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
     if not args.no_extras and args.only in (None, "pde"):
         log("leg: pde 1000")
         wl = pde(1000, 3)
@@ -643,7 +817,7 @@ def main():
         out["pde"] = {"workload": "pde-control 1000x1000 grid (2e6 variables, seed 3)",
                       "nnzj": r["nnzj"], "nnzh": r["nnzh"], "step_us": round(r["step_s"] * 1e6, 2),
                       "nnz_per_s": r["nnz_per_s"], "step_separate_us": r["step_separate_us"],
-                      "step_graph_us": r["step_graph_us"],
+                      "step_graph_us": r["step_graph_us"], "schedule": r["schedule"],
                       "rotated": r["rotated"],
                       "jac_hess_nnz_per_s": r["jac_hess_nnz_per_s"],
                       "ipm_step_us": r["ipm_step_us"], "ipm_nnz_per_s": r["ipm_nnz_per_s"],
@@ -661,13 +835,6 @@ def main():
                                       "launch_us": r["jh_kernel_us"]}}
         if args.only == "pde":
             out.update(value=r["nnz_per_s"], ms_per_step=r["step_s"] * 1e3)
-    if not args.no_extras and args.only in (None, "batch"):
-        log("leg: batched 256")
-        r = leg_batch()
-        log(json.dumps(r))
-        out["batched"] = r
-        if args.only == "batch":
-            out.update(value=r["batched_nnz_per_s"], ms_per_step=r["batched_us"] * 1e-3)
     if not args.no_extras and args.only in (None, "adjoint"):
         log("leg: adjoint 64 x 10k")
         r = leg_adjoint()

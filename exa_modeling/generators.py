@@ -206,6 +206,14 @@ def acopf_batch(count: int = 256, first_seed: int = 1000, lo: int = 500, hi: int
             for seed, nb, rng in acopf_batch_sizes(count, first_seed, lo, hi)]
 
 
+def acopf_batch_instance(seed: int, lo: int = 500, hi: int = 20000) -> Workload:
+    """Instance ``seed - first_seed`` of :func:`acopf_batch`, drawn alone
+    (each instance has a generator of its own)."""
+    rng = _rng(seed)
+    nb = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    return acopf(nb, seed, load_perturb=True, rng=rng)
+
+
 def pde(n: int, seed: int) -> Workload:
     """Distributed control of -Laplace(u) + exp(u) = f on an n x n grid.
 

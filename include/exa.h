@@ -202,6 +202,13 @@ exa_status exa_hess_structure(const exa_model* m, int32_t* rows, int32_t* cols);
 /* f(x): objective terms reduced in a fixed order (Sec. 7.2.3, buffer then
  * reduce); *f is a device scalar. */
 exa_status exa_obj(exa_model* m, const double* x, double* f, exa_stream_t stream);
+/* f(x) as exa_obj computes it (same bits), returned in the host scalar *f:
+ * the objective reduction lands in a library-owned device scalar, is copied
+ * to pinned host memory on `stream`, and the call waits for the stream (the
+ * one callback that synchronizes with the host, as the objective of
+ * Sec. 7.2.3 returns a number).  Not capturable into a graph.  Errors:
+ * EXA_EINVAL for a NULL x (nvar > 0) or f; EXA_ESTATE for a host-only model. */
+exa_status exa_obj_host(exa_model* m, const double* x, double* f, exa_stream_t stream);
 /* grad f(x) into g [nvar] (dense; zero where no objective term depends on a
  * variable).  Per-term contributions are merged by a fixed-order segmented
  * reduction over a precomputed sort (Sec. 7.2.3 compress_to_dense). */
@@ -416,54 +423,130 @@ exa_status exa_counters(const exa_model* m, int64_t* out9);
 /* ---- Batched evaluation (Sec. 7.4.3 batch models, generalised) ----------
  *
  * B models that share every pattern tree (the same description up to data
- * sizes and values: instances of one formulation) are evaluated together by
- * ONE persistent kernel launch per callback set, replayed from a HIP graph.
- * Instance sizes may differ.  The batch keeps references to the models,
- * which must outlive it.
+ * sizes and values: instances of one formulation, which also agree on which
+ * patterns have no data points) are evaluated together: every selected
+ * callback of every instance in ONE evaluation launch over a tile list of
+ * (instance, unit, data range) tiles, one workgroup per tile, with the
+ * instances binned over the 8 XCDs by cost; then ONE launch of every
+ * instance's deterministic reductions (gradient, J^T w, H v, parameter
+ * adjoint segment sums, objective partials), plus one small launch when a
+ * segment is longer than 1024 entries.  The launches are recorded once into
+ * a HIP graph and replayed (re-recorded when the call's pointers, sigma, mask
+ * or schedule change).  Instance sizes may differ.  The batch keeps
+ * references to the models, which must outlive it; it reads their data,
+ * maps and compiled code and owns its own work buffers and parameter copy.
  *
- * Call arrays are the concatenation of the per-instance arrays in instance
- * order; exa_batch_offsets gives, for i = 0..B, the start of instance i in
- * x (nvar), y (ncon), jac vals (nnzj) and hess vals (nnzh):
- * offsets[4*i + 0..3]; entry B holds the totals.
+ * Concatenated arrays: an input or output of the batch is the concatenation
+ * of the per-instance arrays in instance order; exa_batch_offsets gives, for
+ * i = 0..B, the start of instance i in arrays of nvar (x, v, g, jtw, hv, lag,
+ * wx), ncon (y, w, c, jv), nnzj (jac), nnzh (hess) and ntheta (theta,
+ * theta_bar) entries: offsets[5*i + 0..4]; row B holds the totals.  The
+ * objective output f holds one value per instance.
+ *
+ * Every instance's outputs are bit-identical to its own single-instance
+ * callbacks (exa_obj, exa_grad, exa_cons, exa_jac_coord, exa_hess_coord,
+ * exa_jprod, exa_jtprod, exa_hprod, exa_lag_grad, exa_adjoint_theta) at
+ * the batch's parameters: each data point is evaluated by the same code,
+ * and each reduction sums the same entries in the same order.
  */
 typedef struct exa_batch_options {
-    int32_t autotune;  /* 1: time the candidate schedules and keep the fastest */
-    int32_t block;     /* fixed schedule when autotune == 0 (0: default)       */
-    int32_t epl;
-    int32_t grid;      /* persistent workgroups; -1: one workgroup per tile
-                          (not persistent); 0: chosen by the library          */
-    int32_t use_graph; /* 1: replay the launch from a HIP graph                */
-    int32_t fuse;      /* 1: patterns over the same data arrays share a lane   */
+    int32_t autotune;  /* 1: at the first call with a mask, time the candidate
+                          schedules (workgroup size, points per lane, fused or
+                          separate patterns, units) and keep the fastest      */
+    int32_t block;     /* schedule without autotune: workgroup size (0: 256)   */
+    int32_t epl;       /*   points per lane 1..16 (0: 4)                       */
+    int32_t fuse;      /*   1: patterns over the same data arrays share a lane */
+    int32_t units;     /*   EXA_UNITS_* (a choice a mask does not allow falls
+                            back to the next one down)                         */
+    int32_t use_graph; /* 1: replay the launches from a HIP graph              */
     int32_t xcd_aware; /* 1: instances are split over the 8 XCDs by cost and
-                          each XCD walks its own instances one after another
-                          (their x stays in that XCD's L2)                     */
-    int32_t separate;  /* without autotune: 1 keeps Jacobian and Hessian tiles
-                          apart; 0 evaluates both for a data point in one pass */
+                          each XCD takes its instances' tiles (an instance's x
+                          stays in that XCD's L2); 0: tiles in instance order  */
+    int32_t reserved;
 } exa_batch_options;
 
-#define EXA_CB_JAC 1u
-#define EXA_CB_HESS 2u
+/* Batched-only selection bits, beside the EXA_EV_* callbacks:
+ *   EXA_EV_LAG  lag       [nvar]   sigma grad f + J^T y from x, y, sigma
+ *                                  (as exa_lag_grad); not with EXA_EV_GRAD
+ *                                  or EXA_EV_JTPROD in the same call
+ *   EXA_EV_ADJ  theta_bar [ntheta] from x, y, sigma, wx (as
+ *                                  exa_adjoint_theta with w = wx); its tiles
+ *                                  run in a second evaluation launch */
+#define EXA_EV_LAG (1u << 8)
+#define EXA_EV_ADJ (1u << 9)
+#define EXA_BATCH_ALL 0x3ffu
 
+/* Inputs and outputs of exa_batch_eval: device arrays, concatenated over
+ * the instances (see above).  Inputs a mask does not need may be NULL,
+ * outputs it selects may not; outputs must not overlap each other or the
+ * inputs. */
+typedef struct exa_batch_io {
+    const double* x;   /* [sum nvar]   the point                              */
+    const double* y;   /* [sum ncon]   multipliers (hess, hprod, lag, adj)    */
+    double obj_weight; /* sigma, the same for every instance                  */
+    const double* v;   /* [sum nvar]   direction of jprod and hprod           */
+    const double* w;   /* [sum ncon]   weights of jtprod                      */
+    const double* wx;  /* [sum nvar]   cotangent of the parameter adjoint     */
+    double* f;         /* [B]          objective values                       */
+    double* g;         /* [sum nvar]   gradients                              */
+    double* c;         /* [sum ncon]   constraint values                      */
+    double* jac;       /* [sum nnzj]   Jacobian values                        */
+    double* hess;      /* [sum nnzh]   Hessian values                         */
+    double* jv;        /* [sum ncon]   J v                                    */
+    double* jtw;       /* [sum nvar]   J^T w                                  */
+    double* hv;        /* [sum nvar]   H v                                    */
+    double* lag;       /* [sum nvar]   sigma grad f + J^T y                   */
+    double* theta_bar; /* [sum ntheta] (d grad_x L / d theta)^T wx            */
+} exa_batch_io;
+
+/* Errors: EXA_EINVAL for B < 1, a NULL model or handle, models that do not
+ * share their pattern trees, or a bad option; EXA_ESTATE for a host-only
+ * model; EXA_ENOMEM, EXA_EHIP.  The batch's parameters start as a copy of
+ * each model's device parameters at create. */
 exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch_options* opt,
                             exa_batch** out);
 exa_status exa_batch_destroy(exa_batch* b);
-exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets /* [4*(B+1)] */);
-/* Evaluate the callbacks in mask (EXA_CB_JAC | EXA_CB_HESS) for every
- * instance: x_cat, y_cat device inputs; jac_cat, hess_cat device outputs (a
- * pointer may be NULL when its callback is not in the mask).  Instance i's
- * slices are bit-identical to exa_jac_coord / exa_hess_coord on model i. */
-exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x_cat, const double* y_cat,
-                          double obj_weight, double* jac_cat, double* hess_cat,
-                          exa_stream_t stream);
-/* Algorithmic traffic of one batched launch for the callbacks in mask, summed
- * over the instances (see exa_kernel_bytes; an instance's x entries count once
- * for the Jacobian and the Hessian together). */
-exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes);
-/* The schedule in use: out6 = block, points per lane, grid (-1: one
- * workgroup per tile), tiles (both
- * callbacks), the autotuner's best time in nanoseconds (0 if not tuned), and
- * 1 when Jacobian and Hessian are evaluated in one pass per data point. */
-exa_status exa_batch_schedule(const exa_batch* b, int64_t* out6);
+/* Host array offsets [5*(B+1)], see above. */
+exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets);
+/* Replace the batch's parameters: theta device [sum ntheta], copied on
+ * `stream` (the models' own parameters are not changed). */
+exa_status exa_batch_set_theta(exa_batch* b, const double* theta, exa_stream_t stream);
+/* Evaluate the callbacks selected by `mask` (EXA_EV_* and the batched-only
+ * bits above) for every instance.  The first call with a mask builds its
+ * tile list and reduction table, allocates the work buffers it needs and,
+ * with autotune, times candidate schedules (synchronizing the stream); a
+ * call whose pointers, sigma or schedule differ from the previous call's
+ * records a new graph.  Otherwise a call is one graph launch on `stream`.
+ * Errors: EXA_EINVAL for a NULL batch or io, an empty or unknown mask, LAG
+ * with GRAD or JTPROD, a NULL pointer the mask needs, or GRAD or LAG over
+ * instances that disagree on whether every variable has at most one
+ * objective term (their gradients are written differently). */
+exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, exa_stream_t stream);
+/* Algorithmic traffic of a mask under its current schedule (the batch's
+ * default before the mask's first call), summed over the instances as
+ * exa_eval_bytes counts one model: out4 = bytes read and written by the
+ * evaluation launch(es), bytes read and written by the reduction launch. */
+exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4);
+/* Schedule of a mask: out6 = workgroup size, points per lane, fused (0/1),
+ * units (EXA_UNITS_*), number of evaluation tiles, the autotuner's best
+ * evaluation-launch time in nanoseconds (0 if not tuned).  EXA_ESTATE before
+ * the mask's first call. */
+exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6);
+/* Fix a mask's schedule instead of tuning it (for measurement: a profiled
+ * run can use the schedule an unprofiled run chose).  Errors: EXA_EINVAL for
+ * a bad mask or value. */
+exa_status exa_batch_set_schedule(exa_batch* b, uint32_t mask, int32_t block, int32_t epl, int32_t fused,
+                                  int32_t units);
+/* Launch timing, for measurement: with enable != 0 the next 1024
+ * exa_batch_eval calls launch directly (not from the graph) and record HIP
+ * events on their stream around the evaluation launch and around the
+ * reduction launch; enable == 0 frees the events and returns to graph
+ * replay.  exa_batch_timing_read waits for the recorded calls and stores
+ * {calls, average evaluation launch in us, reduction launches, their
+ * average in us} into the host array out4, then starts a new recording.
+ * EXA_ESTATE when timing is off. */
+exa_status exa_batch_timing(exa_batch* b, int32_t enable);
+exa_status exa_batch_timing_read(exa_batch* b, double* out4);
 
 #ifdef __cplusplus
 }

@@ -133,9 +133,9 @@ class OracleModel:
         for s in range(0, P.ndata, CHUNK):
             yield np.arange(s, min(P.ndata, s + CHUNK))
 
-    def _taylor(self, P, ks, x, theta, with_params=False):
+    def _taylor(self, P, ks, x, theta, with_params=False, dtype=np.float64):
         m = len(P.vslots) + (len(P.pslots) if with_params else 0)
-        return taylor.evaluate(P.tree, self._leaf_fn(P, ks, x, theta, with_params), m, ks.size)
+        return taylor.evaluate(P.tree, self._leaf_fn(P, ks, x, theta, with_params), m, ks.size, dtype)
 
     def _theta(self, theta):
         return self.model.theta if theta is None else np.asarray(theta, dtype=np.float64)
@@ -148,9 +148,10 @@ class OracleModel:
         return taylor.evaluate_value(P.tree, self._leaf_fn(P, ks, x, th, False), ks.size, dtype)
 
     # ------------------------------------------------------------ callbacks
-    def obj(self, x, theta=None):
-        return float(sum(np.sum(self.pattern_values(i, x, theta))
-                         for i, P in enumerate(self.pats) if P.kind == "obj"))
+    def obj(self, x, theta=None, dtype=np.float64):
+        tot = sum(np.sum(self.pattern_values(i, x, theta, dtype))
+                  for i, P in enumerate(self.pats) if P.kind == "obj")
+        return float(tot) if dtype == np.float64 else dtype(tot)
 
     def cons(self, x, theta=None, dtype=np.float64):
         c = np.zeros(self.ncon, dtype=dtype)
@@ -161,14 +162,14 @@ class OracleModel:
             np.add.at(c, self._rows(P, np.arange(P.ndata)), vals)
         return c
 
-    def grad(self, x, theta=None):
-        g = np.zeros(self.nvar)
+    def grad(self, x, theta=None, dtype=np.float64):
+        g = np.zeros(self.nvar, dtype=dtype)
         th = self._theta(theta)
         for P in self.pats:
             if P.kind != "obj":
                 continue
             for ks in self._chunks(P):
-                tay = self._taylor(P, ks, x, th)
+                tay = self._taylor(P, ks, x, th, dtype=dtype)
                 for s, key in enumerate(P.vslots):
                     np.add.at(g, self._index(P, key, ks), tay.g[:, s])
         return g
@@ -188,17 +189,20 @@ class OracleModel:
                 cols[pos] = self._index(P, key, ks)
         return rows, cols
 
-    def jac_coord(self, x, theta=None):
-        vals = np.zeros(self.nnzj)
-        th = self._theta(theta)
-        for P in self.pats:
+    def jac_coord(self, x, theta=None, dtype=np.float64):
+        """Data point k of constraint or augmentation pattern P owns entries
+        o1 + k*o1step + s (Sec. 5.3.2); their values are the pattern's
+        jac_block at k, so the full array and the sampled blocks come from
+        one code path."""
+        vals = np.zeros(self.nnzj, dtype=dtype)
+        for i, P in enumerate(self.pats):
             if P.kind == "obj":
                 continue
             step = len(P.vslots)
             for ks in self._chunks(P):
-                tay = self._taylor(P, ks, x, th)
+                blk = self.jac_block(i, ks, x, theta, dtype)
                 for s in range(step):
-                    vals[P.o1 + ks * step + s] = tay.g[:, s]
+                    vals[P.o1 + ks * step + s] = blk[:, s]
         return vals
 
     def hess_structure(self):
@@ -215,49 +219,45 @@ class OracleModel:
                 cols[pos] = np.minimum(ga, gb)
         return rows, cols
 
-    def _weights(self, P, ks, y, sigma):
+    def _weights(self, P, ks, y, sigma, dtype=np.float64):
         if P.kind == "obj":
-            return np.full(ks.size, float(sigma))
-        return np.asarray(y, dtype=np.float64)[self._rows(P, ks)]
+            return np.full(ks.size, sigma, dtype=dtype)
+        return np.asarray(y, dtype=dtype)[self._rows(P, ks)]
 
-    def hess_coord(self, x, y, sigma=1.0, theta=None):
-        vals = np.zeros(self.nnzh)
-        th = self._theta(theta)
-        for P in self.pats:
+    def hess_coord(self, x, y, sigma=1.0, theta=None, dtype=np.float64):
+        """Data point k of pattern P owns entries o2 + k*o2step + s (Sec.
+        5.3.2); their values are the pattern's hess_block at k."""
+        vals = np.zeros(self.nnzh, dtype=dtype)
+        for i, P in enumerate(self.pats):
             step = len(P.hslots)
             if step == 0:
                 continue
             for ks in self._chunks(P):
-                tay = self._taylor(P, ks, x, th)
-                w = self._weights(P, ks, y, sigma)
-                for s, (a, b) in enumerate(P.hslots):
-                    v = w * tay.h[:, a, b]
-                    if a != b:
-                        same = (self._index(P, P.vslots[a], ks) == self._index(P, P.vslots[b], ks))
-                        v = np.where(same, 2.0 * v, v)
-                    vals[P.o2 + ks * step + s] = v
+                blk = self.hess_block(i, ks, x, y, sigma, theta, dtype)
+                for s in range(step):
+                    vals[P.o2 + ks * step + s] = blk[:, s]
         return vals
 
     # ------------------------------------------------------------ products
-    def jac_matrix(self, x, theta=None):
+    def jac_matrix(self, x, theta=None, dtype=np.float64):
         r, c = self.jac_structure()
-        return sp.coo_matrix((self.jac_coord(x, theta), (r, c)), shape=(self.ncon, self.nvar))
+        return sp.coo_matrix((self.jac_coord(x, theta, dtype), (r, c)), shape=(self.ncon, self.nvar))
 
-    def hess_matrix(self, x, y, sigma=1.0, theta=None):
+    def hess_matrix(self, x, y, sigma=1.0, theta=None, dtype=np.float64):
         """Full symmetric Hessian of the Lagrangian from the lower-triangle COO."""
         r, c = self.hess_structure()
-        L = sp.coo_matrix((self.hess_coord(x, y, sigma, theta), (r, c)),
+        L = sp.coo_matrix((self.hess_coord(x, y, sigma, theta, dtype), (r, c)),
                           shape=(self.nvar, self.nvar)).tocsr()
         return L + L.T - sp.diags(L.diagonal())
 
-    def jprod(self, x, v, theta=None):
-        return self.jac_matrix(x, theta) @ np.asarray(v, dtype=np.float64)
+    def jprod(self, x, v, theta=None, dtype=np.float64):
+        return self.jac_matrix(x, theta, dtype) @ np.asarray(v, dtype=dtype)
 
-    def jtprod(self, x, w, theta=None):
-        return self.jac_matrix(x, theta).T @ np.asarray(w, dtype=np.float64)
+    def jtprod(self, x, w, theta=None, dtype=np.float64):
+        return self.jac_matrix(x, theta, dtype).T @ np.asarray(w, dtype=dtype)
 
-    def hprod(self, x, y, sigma, v, theta=None):
-        return self.hess_matrix(x, y, sigma, theta) @ np.asarray(v, dtype=np.float64)
+    def hprod(self, x, y, sigma, v, theta=None, dtype=np.float64):
+        return self.hess_matrix(x, y, sigma, theta, dtype) @ np.asarray(v, dtype=dtype)
 
     def grad_lagrangian(self, x, y, sigma=1.0, theta=None):
         """sigma * grad f + J^T y."""
@@ -284,24 +284,32 @@ class OracleModel:
         return out
 
     # ------------------------------------------------- values at sample points
-    def jac_block(self, i, ks, x, theta=None):
-        """Jacobian values (len(ks), o1step) of pattern i at data points ks."""
+    def jac_block(self, i, ks, x, theta=None, dtype=np.float64):
+        """Jacobian values (len(ks), o1step) of pattern i at data points ks:
+        column s is dT/dx of the s-th unique variable reference, summed over
+        every leaf of that reference (the within-tree merge of Sec. 5.2.2).
+        ``dtype`` np.longdouble gives the extended-precision reference."""
         P = self.pats[i]
         ks = np.asarray(ks, dtype=np.int64)
-        return self._taylor(P, ks, x, self._theta(theta)).g.copy()
+        return self._taylor(P, ks, x, self._theta(theta), dtype=dtype).g.copy()
 
-    def hess_block(self, i, ks, x, y, sigma=1.0, theta=None):
-        """Hessian values (len(ks), o2step) of pattern i at data points ks."""
+    def hess_block(self, i, ks, x, y, sigma=1.0, theta=None, dtype=np.float64):
+        """Hessian values (len(ks), o2step) of pattern i at data points ks:
+        column s is w * d2T/dx_a dx_b for the s-th unique pair (a, b), with w
+        = sigma for an objective pattern and y of the point's row otherwise
+        (Sec. 2.1.3); a cross pair whose two references resolve to the same
+        variable holds twice the mixed derivative, so that summing duplicate
+        COO entries reproduces the Hessian."""
         P = self.pats[i]
         ks = np.asarray(ks, dtype=np.int64)
-        tay = self._taylor(P, ks, x, self._theta(theta))
-        w = self._weights(P, ks, y, sigma)
-        out = np.zeros((ks.size, len(P.hslots)))
+        tay = self._taylor(P, ks, x, self._theta(theta), dtype=dtype)
+        w = self._weights(P, ks, y, sigma, dtype)
+        out = np.zeros((ks.size, len(P.hslots)), dtype=dtype)
         for s, (a, b) in enumerate(P.hslots):
             v = w * tay.h[:, a, b]
             if a != b:
                 same = (self._index(P, P.vslots[a], ks) == self._index(P, P.vslots[b], ks))
-                v = np.where(same, 2.0 * v, v)
+                v = np.where(same, 2 * v, v)
             out[:, s] = v
         return out
 

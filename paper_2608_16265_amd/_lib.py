@@ -19,7 +19,6 @@ OPCODE = {
     "cos": 17, "tan": 18, "atan": 19, "sinh": 20, "cosh": 21, "tanh": 22, "log1p": 23,
     "expm1": 24, "add": 40, "sub": 41, "mul": 42, "div": 43, "pow": 44,
 }
-CB_JAC, CB_HESS = 1, 2
 
 P_i32 = C.POINTER(C.c_int32)
 P_i64 = C.POINTER(C.c_int64)
@@ -45,13 +44,23 @@ class Options(C.Structure):
 
 class BatchOptions(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
-                ("grid", C.c_int32), ("use_graph", C.c_int32), ("fuse", C.c_int32),
-                ("xcd_aware", C.c_int32), ("separate", C.c_int32)]
+                ("fuse", C.c_int32), ("units", C.c_int32), ("use_graph", C.c_int32),
+                ("xcd_aware", C.c_int32), ("reserved", C.c_int32)]
 
 
-# exa_eval selection bits, by callback name
+class BatchIO(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("obj_weight", C.c_double),
+                ("v", C.c_void_p), ("w", C.c_void_p), ("wx", C.c_void_p),
+                ("f", C.c_void_p), ("g", C.c_void_p), ("c", C.c_void_p), ("jac", C.c_void_p),
+                ("hess", C.c_void_p), ("jv", C.c_void_p), ("jtw", C.c_void_p), ("hv", C.c_void_p),
+                ("lag", C.c_void_p), ("theta_bar", C.c_void_p)]
+
+
+# exa_eval selection bits, by callback name (lag and adjoint: batched only)
 EV = {"obj": 1 << 0, "grad": 1 << 1, "cons": 1 << 2, "jac": 1 << 3, "hess": 1 << 4,
       "jprod": 1 << 5, "jtprod": 1 << 6, "hprod": 1 << 7}
+EV_BATCH = dict(EV, lag=1 << 8, adjoint=1 << 9)
+UNITS = {"per_callback": 0, "jac_hess": 1, "one_pass": 2}
 
 
 class EvalArgs(C.Structure):
@@ -88,6 +97,7 @@ def _load():
         "exa_jac_structure": (C.c_int32, [vp, P_i32, P_i32]),
         "exa_hess_structure": (C.c_int32, [vp, P_i32, P_i32]),
         "exa_obj": (C.c_int32, [vp, vp, vp, vp]),
+        "exa_obj_host": (C.c_int32, [vp, vp, P_f64, vp]),
         "exa_grad": (C.c_int32, [vp, vp, vp, vp]),
         "exa_cons": (C.c_int32, [vp, vp, vp, vp]),
         "exa_jac_coord": (C.c_int32, [vp, vp, vp, vp]),
@@ -118,9 +128,13 @@ def _load():
                                          C.POINTER(vp)]),
         "exa_batch_destroy": (C.c_int32, [vp]),
         "exa_batch_offsets": (C.c_int32, [vp, P_i64]),
-        "exa_batch_eval": (C.c_int32, [vp, C.c_uint32, vp, vp, C.c_double, vp, vp, vp]),
-        "exa_batch_schedule": (C.c_int32, [vp, P_i64]),
-        "exa_batch_bytes": (C.c_int32, [vp, C.c_uint32, P_i64, P_i64]),
+        "exa_batch_set_theta": (C.c_int32, [vp, vp, vp]),
+        "exa_batch_eval": (C.c_int32, [vp, C.c_uint32, C.POINTER(BatchIO), vp]),
+        "exa_batch_schedule": (C.c_int32, [vp, C.c_uint32, P_i64]),
+        "exa_batch_set_schedule": (C.c_int32, [vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "exa_batch_bytes": (C.c_int32, [vp, C.c_uint32, P_i64]),
+        "exa_batch_timing": (C.c_int32, [vp, C.c_int32]),
+        "exa_batch_timing_read": (C.c_int32, [vp, P_f64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -140,10 +154,11 @@ def check(status: int):
 def exported_symbols():
     """Names of the C ABI entry points this binding declares."""
     return ["exa_last_error", "exa_version", "exa_create", "exa_destroy", "exa_dims", "exa_bounds",
-            "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_grad",
+            "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_obj_host", "exa_grad",
             "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jac_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
             "exa_lag_grad", "exa_csc_dims", "exa_csc_structure", "exa_csc_values",
             "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_set_schedule", "exa_eval_bytes", "exa_eval_timing", "exa_device_copy",
             "exa_eval_timing_read", "exa_counters", "exa_generated_source", "exa_compile_check",
             "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",
-            "exa_batch_offsets", "exa_batch_eval", "exa_batch_schedule", "exa_batch_bytes"]
+            "exa_batch_offsets", "exa_batch_set_theta", "exa_batch_eval", "exa_batch_schedule",
+            "exa_batch_set_schedule", "exa_batch_bytes", "exa_batch_timing", "exa_batch_timing_read"]

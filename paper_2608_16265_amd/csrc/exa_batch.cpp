@@ -1,236 +1,551 @@
 // Batched evaluation of many instances of one formulation (Sec. 7.4.3 batch
-// models, generalised to instances of different sizes).
+// models, generalised to instances of different sizes and to every
+// callback).
 //
 // All instances share the generated code; their data stays where each model
-// put it, and their sizes and offsets are table data.  A tile list spans
-// (instance, unit, data range); ONE persistent launch walks it and the launch
-// is recorded once into a HIP graph and replayed.  For the Jacobian and the
-// Hessian together the tiles are either combined units (both sweeps of a data
-// point in one pass over one set of loads) or separate Jacobian and Hessian
-// tiles.  With xcd_aware, instances are binned over the 8 XCDs by estimated
-// cost and each XCD walks its bin instance by instance, so an instance's x
-// stays in that XCD's L2.  Points per tile, grid size and combined/separate
-// are picked by timing candidates at the first evaluation; results do not
-// depend on the schedule because every data point is evaluated by the same
-// code and written to its own slice.
+// put it, and their sizes and offsets are table data (one ExaInstDev per
+// instance, whose offsets place the instance in the concatenated inputs,
+// outputs and work buffers).  A call is
+//   * ONE evaluation launch over a tile list of (instance, unit, data range)
+//     tiles of every selected callback, one workgroup per tile (the kernels
+//     and units of exa_eval: per-callback tiles, Jacobian + Hessian units or
+//     one pass per point), plus a second launch for the parameter adjoint;
+//   * ONE launch of every instance's deterministic reductions (the same
+//     segment sums, chunks and parts as the instance's own reduction, and
+//     its objective partials), plus one small launch for the part sums of
+//     segments longer than 1024 entries;
+// recorded once into a HIP graph and replayed.  With xcd_aware, instances are
+// binned over the 8 XCDs by algorithmic bytes (largest first into the
+// lightest bin) and XCD j takes bin j's tiles and reduction blocks, so an
+// instance's x and work buffers stay in that XCD's L2.  Workgroup size,
+// points per lane, fused or separate patterns and the units are picked by
+// timing candidates at a mask's first call; results do not depend on the
+// schedule because every data point is evaluated by the same code and every
+// reduction sums the same entries in the same order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <numeric>
 
 #include "exa_internal.h"
+#include "exa_kernels.h"
 #include "exa_runtime.h"
 
 using namespace exa;
 
+namespace {
+// work buffers of the batch (ExaBatchReduce::bufs)
+constexpr int kBufFo = 0, kBufHv = 1, kBufPar = 2, kBufTile = 3;
+// outputs of the reduction launch (ExaBatchReduce::outs)
+constexpr int kOutF = 0, kOutG = 1, kOutJtw = 2, kOutHv = 3, kOutLag = 4, kOutLagTmp = 5, kOutThetaBar = 6;
+constexpr int kOffX = 0, kOffY = 1, kOffJac = 2, kOffHess = 3, kOffTheta = 4, kNoff = 5;
+constexpr int64_t kAlign = 16;  // entries: 128-byte lines
+int64_t aligned(int64_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
+
 struct exa_batch {
     std::vector<exa_model*> models;
     int B = 0;
-    int block = 256;
     std::shared_ptr<Module> module;
-    DeviceState mem;                       // owns the tables below
-    ExaInstDev* inst = nullptr;
-    std::vector<int64_t> offsets;          // 4 * (B + 1): x, y, jac, hess
-    // schedule
-    bool autotune = true, use_graph = true, tuned = false, fuse = true, xcd_aware = true;
-    bool combined = true;                  // Jacobian + Hessian units (mask 3)
-    int epl = 4;
-    int64_t grid = 0;
-    int64_t tuned_ns = 0;
-    // tile lists per mask value (1: jac, 2: hess, 3: both) for (epl, combined)
-    ExaTile* tiles[4] = {};
-    long long* xcd_ranges[4] = {};
-    int64_t ntiles[4] = {};
-    int64_t per_xcd[4] = {};               // tiles per XCD range of the list
-    int tiles_epl = -1, tiles_block = -1;
-    bool tiles_combined = true;
-    // graph for the last call signature
+    DeviceState mem;                   // owns every device array below
+    ExaInstDev* inst = nullptr;        // per-instance tables (device)
+    std::vector<int64_t> offsets;      // kNoff * (B + 1)
+    double* theta = nullptr;           // the batch's parameters
+    // work buffers, allocated on first use; instance i's block starts at
+    // entry base[k][i] (a 128-byte line)
+    double* buf[kExaBatchBufs] = {};
+    std::vector<int64_t> base[kExaBatchBufs];
+    int64_t buf_len[kExaBatchBufs] = {};
+    double* lag_tmp = nullptr;         // J^T y of EXA_EV_LAG when the gradient is reduced
+    // per instance: its models' device maps, with part sums of the batch's own
+    struct Maps {
+        DevMap grad, jt, h, par;
+    };
+    std::vector<Maps> maps;
+    std::vector<int64_t> nobj;         // objective tiles per instance
+    bool grad_direct_all = true, grad_direct_any = false;
+    // options
+    bool autotune = true, use_graph = true, xcd_aware = true, fuse = true;
+    int block = 256, epl = 4, units = EXA_UNITS_JAC_HESS;
+    // per mask: schedule, tile lists, reduction table
+    struct Sched {
+        int block = 256, epl = 4, units = EXA_UNITS_PER_CALLBACK;
+        bool fused = true, tuned = false;
+        std::vector<std::vector<int>> bins;  // instances per XCD
+        ExaTile* tiles = nullptr;
+        int64_t ntiles = 0;
+        ExaTile* atiles = nullptr;           // parameter adjoint launch
+        int64_t antiles = 0;
+        int64_t tuned_ns = 0;
+        ExaBatchJob* jobs = nullptr;
+        int32_t* blocks = nullptr;
+        int64_t nblocks = 0;
+        int32_t* lblocks = nullptr;
+        int64_t nlblocks = 0;
+        bool axpy = false, reduce_built = false;
+    };
+    std::map<uint32_t, Sched> sched;
+    // graph of the last call
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
     struct Key {
-        uint32_t mask;
-        const void *x, *y, *j, *h;
-        double sigma;
-        int epl, block;
-        int64_t grid;
-        bool combined;
-        bool operator==(const Key& o) const {
-            return mask == o.mask && x == o.x && y == o.y && j == o.j && h == o.h && sigma == o.sigma &&
-                   epl == o.epl && block == o.block && grid == o.grid && combined == o.combined;
-        }
-    } key{};
+        uint32_t mask = 0;
+        exa_batch_io io;
+        int block = 0, epl = 0, units = 0;
+        bool fused = false;
+    } key;
     bool have_graph = false;
-    int cus = 256;
+    // launch timing (exa_batch_timing)
+    struct Timing {
+        bool on = false;
+        std::vector<hipEvent_t> ev;
+        std::vector<char> reduced;
+        int64_t used = 0;
+    } timing;
 
-    ~exa_batch() {
+    void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        have_graph = false;
+    }
+    void timing_off() {
+        for (hipEvent_t e : timing.ev) (void)hipEventDestroy(e);
+        timing = Timing();
+    }
+    ~exa_batch() {
+        drop_graph();
+        timing_off();
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
 namespace {
 
-// Estimated cost of one data point of pattern P (in 8-byte words moved).
-int64_t point_cost(const Pattern& P, int mode) {
-    const int64_t loads = P.n_icols / 2 + P.n_fcols + P.o1step() + 1;
-    if (mode == M_JH) return loads + P.o1step() + P.o2step();
-    return loads + (mode == M_JAC ? P.o1step() : P.o2step());
+// The exa_eval mask whose tiles a batch mask launches (the Lagrangian
+// gradient is the gradient and J^T y tiles; the adjoint has a launch of its
+// own).
+uint32_t eval_mask(uint32_t mask) {
+    uint32_t e = mask & EXA_EV_ALL;
+    if (mask & EXA_EV_LAG) e |= EXA_EV_GRAD | EXA_EV_JTPROD;
+    return e;
 }
 
-// Modes whose tiles a mask launches: (mode, tile code offset).
-std::vector<std::pair<int, int>> mask_modes(uint32_t mask, bool combined) {
-    if (mask == 1) return {{M_JAC, 0}};
-    if (mask == 2) return {{M_HESS, 0}};
-    if (combined) return {{M_JH, 0}};
-    return {{M_JAC, 0}, {M_HESS, 64}};
+const std::vector<int>& main_modes(const exa_batch::Sched& S, uint32_t mask, std::vector<int>& tmp) {
+    const uint32_t em = eval_mask(mask);
+    tmp = em ? launch_modes(em, S.units) : std::vector<int>();
+    return tmp;
 }
 
-void build_tiles(exa_batch& b, int epl, bool combined) {
-    if (b.tiles_epl == epl && b.tiles_block == b.block && b.tiles_combined == combined) return;
-    const int64_t tp = (int64_t)b.block * epl;
-    for (int m = 1; m <= 3; ++m) {
-        // per instance: its tiles and their total cost
-        std::vector<std::vector<std::pair<int64_t, ExaTile>>> per(b.B);
-        std::vector<int64_t> cost(b.B, 0);
+// A launch of one plain mode runs that mode's own kernel (exa_k_<mode>);
+// several modes, or units of several callbacks, run a several-callback kernel.
+bool single_kernel(const std::vector<int>& modes) { return modes.size() == 1 && !multi_unit_mode(modes[0]); }
+
+// Per-instance algorithmic bytes of a mask's evaluation, the cost by which
+// instances are binned over the XCDs.
+std::vector<int64_t> instance_cost(const exa_batch& b, uint32_t mask, int units, bool fused) {
+    std::vector<int64_t> cost(b.B, 0);
+    const uint32_t em = eval_mask(mask);
+    for (int i = 0; i < b.B; ++i) {
+        const Model& M = b.models[i]->impl;
+        int64_t rd = 0, wr = 0;
+        if (em) {
+            kernel_bytes(M, launch_modes(em, units), fused, rd, wr);
+            cost[i] += rd + wr;
+        }
+        if (mask & EXA_EV_ADJ) {
+            kernel_bytes(M, {M_ADJ}, fused, rd, wr);
+            cost[i] += rd + wr;
+        }
+    }
+    return cost;
+}
+
+void make_bins(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
+    S.bins.assign(8, {});
+    if (!b.xcd_aware) {
+        // instances in order, cut into eight contiguous runs of similar cost
+        const std::vector<int64_t> cost = instance_cost(b, mask, S.units, S.fused);
+        const int64_t tot = std::accumulate(cost.begin(), cost.end(), (int64_t)0);
+        int64_t acc = 0;
         for (int i = 0; i < b.B; ++i) {
-            const Model& M = b.models[i]->impl;
-            for (auto mc : mask_modes((uint32_t)m, combined)) {
-                for (const Unit& u : units_for(M, mc.first, b.fuse)) {
-                    int64_t pc = 0;
-                    for (int p : u.members) pc += point_cost(M.pats[p], mc.first);
-                    for (int64_t s = 0; s < u.ndata; s += tp) {
-                        ExaTile t{};
-                        t.pat = u.code + mc.second;
-                        t.inst = i;
-                        t.start = s;
-                        t.count = std::min(tp, u.ndata - s);
-                        per[i].emplace_back(t.count * pc, t);
-                        cost[i] += t.count * pc;
-                    }
+            const int j = tot > 0 ? (int)std::min<int64_t>(7, 8 * acc / tot) : 0;
+            S.bins[j].push_back(i);
+            acc += cost[i];
+        }
+        return;
+    }
+    const std::vector<int64_t> cost = instance_cost(b, mask, S.units, S.fused);
+    std::vector<int> order(b.B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<int64_t> load(8, 0);
+    for (int i : order) {
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        S.bins[j].push_back(i);
+        load[j] += cost[i];
+    }
+    for (auto& bin : S.bins) std::sort(bin.begin(), bin.end());
+}
+
+// Tiles of instance i for one launch of `modes` (mode bits in the codes when
+// the launch is a several-callback kernel).
+void instance_tiles(const exa_batch& b, int i, const std::vector<int>& modes, bool tagged, uint32_t em,
+                    int64_t tp, bool fused, std::vector<ExaTile>& out) {
+    const Model& M = b.models[i]->impl;
+    for (int mode : modes) {
+        std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, i, (int64_t)kObjBlock * kObjEpl, kObjFused)
+                                               : make_tiles(M, mode, i, tp, fused);
+        if (mode == M_GRAD || (multi_unit_mode(mode) && (em & EXA_EV_GRAD))) {
+            std::vector<ExaTile> z;
+            add_zero_tiles(M, tp, z);
+            for (ExaTile& x : z) {
+                x.inst = i;
+                if (tagged) x.pat |= M_GRAD << EXA_MODE_SHIFT;
+            }
+            if (tagged || mode == M_GRAD) t.insert(t.end(), z.begin(), z.end());
+        }
+        for (ExaTile& x : t) {
+            x.inst = i;
+            if (tagged && x.pat != ((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE)) x.pat |= mode << EXA_MODE_SHIFT;
+        }
+        out.insert(out.end(), t.begin(), t.end());
+    }
+}
+
+// Bin j's tiles, then bin j+1's, each bin padded with no-op tiles to the
+// longest, so that XCD j (workgroups w with w % 8 == j) takes exactly bin j.
+ExaTile* upload_binned(exa_batch& b, const exa_batch::Sched& S, const std::vector<std::vector<ExaTile>>& per,
+                       int64_t& n) {
+    int64_t longest = 0;
+    for (const auto& bin : S.bins) {
+        int64_t c = 0;
+        for (int i : bin) c += (int64_t)per[i].size();
+        longest = std::max(longest, c);
+    }
+    n = 8 * longest;
+    if (n == 0) return nullptr;
+    std::vector<ExaTile> v;
+    v.reserve(n);
+    ExaTile pad{};
+    pad.pat = EXA_PAD_TILE;
+    for (int j = 0; j < 8; ++j) {
+        for (int i : S.bins[j]) v.insert(v.end(), per[i].begin(), per[i].end());
+        while ((int64_t)v.size() < (j + 1) * longest) v.push_back(pad);
+    }
+    return (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
+}
+
+void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fused, int units) {
+    exa_batch::Sched& S = b.sched[mask];
+    const uint32_t em = eval_mask(mask);
+    S.units = em ? valid_units(em, units) : EXA_UNITS_PER_CALLBACK;
+    S.block = block;
+    S.epl = epl;
+    S.fused = fused;
+    if (S.bins.empty()) make_bins(b, S, mask);
+    const int64_t tp = (int64_t)block * epl;
+    std::vector<int> tmp;
+    const std::vector<int>& modes = main_modes(S, mask, tmp);
+    std::vector<std::vector<ExaTile>> per(b.B), adj(b.B);
+    for (int i = 0; i < b.B; ++i) {
+        if (!modes.empty()) instance_tiles(b, i, modes, !single_kernel(modes), em, tp, fused, per[i]);
+        if (mask & EXA_EV_ADJ) instance_tiles(b, i, {M_ADJ}, false, 0, tp, fused, adj[i]);
+    }
+    b.mem.release(S.tiles);
+    b.mem.release(S.atiles);
+    S.tiles = upload_binned(b, S, per, S.ntiles);
+    S.atiles = upload_binned(b, S, adj, S.antiles);
+}
+
+double* need_buf(exa_batch& b, int k) {
+    if (!b.buf[k]) b.buf[k] = (double*)b.mem.alloc(std::max<int64_t>(1, b.buf_len[k]) * sizeof(double));
+    return b.buf[k];
+}
+
+ExaBatchJob seg_batch_job(const DevMap& m, int bufk, int64_t buf_off, int out, int64_t out_off, bool ep) {
+    ExaBatchJob J;
+    std::memset(&J, 0, sizeof J);
+    J.ptr = m.ptr;
+    J.idx = m.idx;
+    J.lanes = m.lanes;
+    J.lidx = m.lidx;
+    J.longs = m.longs;
+    J.lpart = m.lpart;
+    J.lsum = m.lsum;
+    J.nseg = m.nseg;
+    J.nlanes = m.nlanes;
+    J.nparts = m.nparts;
+    J.nlong = m.nlong;
+    J.wide = m.wide;
+    J.chunked = m.chunked;
+    J.buf = bufk;
+    J.buf_off = buf_off;
+    J.out = out;
+    J.out_off = out_off;
+    J.ep = ep ? 1 : 0;
+    return J;
+}
+
+int64_t batch_job_blocks(const ExaBatchJob& J) {
+    if (J.kind == 1) return 1;
+    ExaSegJob S;
+    std::memset(&S, 0, sizeof S);
+    S.nseg = J.nseg;
+    S.chunked = J.chunked;
+    S.nlanes = J.nlanes;
+    S.nparts = J.nparts;
+    return exa_job_blocks(S);
+}
+
+// The reduction table of a mask: every instance's jobs, their blocks laid out
+// by the mask's XCD bins (bin j's blocks are the j-th eighth of the launch).
+void build_reductions(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
+    std::vector<ExaBatchJob> jobs;
+    std::vector<std::vector<int32_t>> per_bin(8);
+    std::vector<int32_t> lbl;
+    S.axpy = false;
+    for (int j = 0; j < 8; ++j)
+        for (int i : S.bins[j]) {
+            const exa_batch::Maps& mp = b.maps[i];
+            const int64_t xo = b.offsets[kNoff * i + kOffX];
+            const int64_t fo = b.base[kBufFo].empty() ? 0 : b.base[kBufFo][i];
+            std::vector<ExaBatchJob> mine;
+            if ((mask & EXA_EV_GRAD) && !b.grad_direct_all) mine.push_back(seg_batch_job(mp.grad, kBufFo, fo, kOutG, xo, false));
+            if (mask & EXA_EV_LAG) {
+                if (b.grad_direct_all) {
+                    // g was written in place by the evaluation launch: the
+                    // J^T y sums finish it as g = sigma g + J^T y
+                    mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutLag, xo, true));
+                } else {
+                    mine.push_back(seg_batch_job(mp.grad, kBufFo, fo, kOutLag, xo, false));
+                    mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutLagTmp, xo, false));
+                    S.axpy = true;
                 }
             }
+            if (mask & EXA_EV_JTPROD) mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false));
+            if (mask & EXA_EV_HPROD) mine.push_back(seg_batch_job(mp.h, kBufHv, b.base[kBufHv][i], kOutHv, xo, false));
+            if (mask & EXA_EV_ADJ)
+                mine.push_back(seg_batch_job(mp.par, kBufPar, b.base[kBufPar][i], kOutThetaBar,
+                                             b.offsets[kNoff * i + kOffTheta], false));
+            if (mask & EXA_EV_OBJ) {
+                ExaBatchJob J;
+                std::memset(&J, 0, sizeof J);
+                J.kind = 1;
+                J.buf = kBufTile;
+                J.buf_off = b.base[kBufTile][i];
+                J.nseg = b.nobj[i];
+                J.out = kOutF;
+                J.out_off = i;
+                mine.push_back(J);
+            }
+            for (const ExaBatchJob& J : mine) {
+                const int32_t id = (int32_t)jobs.size();
+                jobs.push_back(J);
+                const int64_t nb = batch_job_blocks(J);
+                for (int64_t k = 0; k < nb; ++k) per_bin[j].insert(per_bin[j].end(), {id, (int32_t)k});
+                if (J.kind == 0 && J.nparts > 0)
+                    for (int64_t l = 0; l < J.nlong; ++l) lbl.insert(lbl.end(), {id, (int32_t)l});
+            }
         }
-        std::vector<ExaTile> v;
-        std::vector<long long> range(9, 0);
-        if (b.xcd_aware) {
-            // instances to 8 bins, largest first into the lightest bin; each
-            // bin lists its instances one after another
-            std::vector<int> order(b.B);
-            std::iota(order.begin(), order.end(), 0);
-            std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-            std::vector<std::vector<int>> bins(8);
-            std::vector<int64_t> load(8, 0);
-            for (int i : order) {
-                const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                bins[j].push_back(i);
-                load[j] += cost[i];
-            }
-            // every bin padded with no-op tiles to the longest, so that bin j
-            // is exactly tiles [j * per_xcd, (j + 1) * per_xcd): the XCD
-            // ranges of both the persistent walk and a one-tile-per-workgroup
-            // launch
-            int64_t longest = 0;
-            for (int j = 0; j < 8; ++j) {
-                int64_t n = 0;
-                for (int i : bins[j]) n += (int64_t)per[i].size();
-                longest = std::max(longest, n);
-            }
-            for (int j = 0; j < 8; ++j) {
-                range[j] = (long long)v.size();
-                for (int i : bins[j])
-                    for (auto& e : per[i]) v.push_back(e.second);
-                ExaTile pad{};
-                pad.pat = EXA_PAD_TILE;
-                while ((int64_t)v.size() < (j + 1) * longest) v.push_back(pad);
-            }
-            range[8] = (long long)v.size();
-            b.per_xcd[m] = longest;
+    size_t longest = 0;
+    for (auto& v : per_bin) longest = std::max(longest, v.size() / 2);
+    std::vector<int32_t> blocks;
+    for (auto& v : per_bin) {
+        blocks.insert(blocks.end(), v.begin(), v.end());
+        for (size_t k = v.size() / 2; k < longest; ++k) blocks.insert(blocks.end(), {-1, 0});
+    }
+    b.mem.release(S.jobs);
+    b.mem.release(S.blocks);
+    b.mem.release(S.lblocks);
+    S.jobs = jobs.empty() ? nullptr : (ExaBatchJob*)b.mem.upload(jobs.data(), jobs.size() * sizeof(ExaBatchJob));
+    S.nblocks = (int64_t)blocks.size() / 2;
+    S.blocks = blocks.empty() ? nullptr : (int32_t*)b.mem.upload(blocks.data(), blocks.size() * sizeof(int32_t));
+    S.nlblocks = (int64_t)lbl.size() / 2;
+    S.lblocks = lbl.empty() ? nullptr : (int32_t*)b.mem.upload(lbl.data(), lbl.size() * sizeof(int32_t));
+    S.reduce_built = true;
+}
+
+// Call records of the selected callbacks, as exa_eval sets them up for one
+// model, with the batch's buffers and instance table.
+ExaMulti call_records(exa_batch& b, uint32_t mask, const exa_batch_io& io) {
+    ExaMulti mc;
+    std::memset(&mc, 0, sizeof mc);
+    const bool lag = (mask & EXA_EV_LAG) != 0;
+    for (int mode = 0; mode < M_COUNT; ++mode) {
+        ExaCall& c = mc.c[mode];
+        c.inst = b.inst;
+        c.x = io.x;
+        switch (mode) {
+            case M_OBJ: c.out0 = b.buf[kBufTile]; break;
+            case M_GRAD:
+                c.direct = b.grad_direct_all ? 1 : 0;
+                c.out0 = b.grad_direct_all ? (lag ? io.lag : io.g) : b.buf[kBufFo];
+                break;
+            case M_CONS: c.out0 = io.c; break;
+            case M_JAC: c.out0 = io.jac; break;
+            case M_HESS:
+                c.y = io.y;
+                c.sigma = io.obj_weight;
+                c.out0 = io.hess;
+                break;
+            case M_JH:
+                c.y = io.y;
+                c.sigma = io.obj_weight;
+                c.out0 = io.jac;
+                c.out1 = io.hess;
+                break;
+            case M_JPROD:
+                c.v = io.v;
+                c.out0 = io.jv;
+                break;
+            case M_JTPROD:
+                c.y = lag ? io.y : io.w;
+                c.out0 = b.buf[kBufFo];
+                break;
+            case M_HPROD:
+                c.y = io.y;
+                c.v = io.v;
+                c.sigma = io.obj_weight;
+                c.out0 = b.buf[kBufHv];
+                break;
+            case M_ADJ:
+                c.y = io.y;
+                c.v = io.wx;
+                c.sigma = io.obj_weight;
+                c.out0 = b.buf[kBufPar];
+                break;
+            default: break;
+        }
+    }
+    return mc;
+}
+
+// The evaluation launch(es) of a mask under its current schedule.
+void launch_eval(exa_batch& b, uint32_t mask, const ExaMulti& rec, hipStream_t s) {
+    const exa_batch::Sched& S = b.sched.at(mask);
+    const Module& K = *b.module;
+    std::vector<int> tmp;
+    const std::vector<int>& modes = main_modes(S, mask, tmp);
+    if (S.ntiles > 0) {
+        if (single_kernel(modes)) {
+            ExaCall c = rec.c[modes[0]];
+            c.tiles = S.tiles;
+            c.ntiles = S.ntiles;
+            c.per_xcd = S.ntiles / 8;
+            void* args[] = {&c};
+            hip_check(hipModuleLaunchKernel(K.fn[modes[0]], (unsigned)S.ntiles, 1, 1, (unsigned)S.block, 1, 1, 0, s,
+                                            args, nullptr),
+                      "hipModuleLaunchKernel");
         } else {
-            // all tiles, largest first, so the grid-stride walk of the
-            // persistent grid approximates longest-processing-time-first
-            std::vector<std::pair<int64_t, ExaTile>> all;
-            for (auto& pi : per) all.insert(all.end(), pi.begin(), pi.end());
-            std::stable_sort(all.begin(), all.end(),
-                             [](const auto& a, const auto& c) { return a.first > c.first; });
-            for (auto& e : all) v.push_back(e.second);
-            b.per_xcd[m] = ((int64_t)v.size() + 7) / 8;
+            ExaMulti mc = rec;
+            mc.tiles = S.tiles;
+            mc.ntiles = S.ntiles;
+            mc.per_xcd = S.ntiles / 8;
+            hipFunction_t fn = S.units == EXA_UNITS_ONE_PASS   ? K.fn_onepass
+                               : S.units == EXA_UNITS_JAC_HESS ? K.fn_multijh
+                                                               : K.fn_multi;
+            void* args[] = {&mc};
+            hip_check(hipModuleLaunchKernel(fn, (unsigned)S.ntiles, 1, 1, (unsigned)S.block, 1, 1, 0, s, args, nullptr),
+                      "hipModuleLaunchKernel");
         }
-        for (size_t i = 0; i < v.size(); ++i) v[i].slot = (int64_t)i;
-        b.mem.release(b.tiles[m]);
-        b.mem.release(b.xcd_ranges[m]);
-        b.tiles[m] = (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
-        b.ntiles[m] = (int64_t)v.size();
-        b.xcd_ranges[m] =
-            b.xcd_aware ? (long long*)b.mem.upload(range.data(), range.size() * sizeof(long long)) : nullptr;
     }
-    b.tiles_epl = epl;
-    b.tiles_block = b.block;
-    b.tiles_combined = combined;
+    if (S.antiles > 0) {
+        ExaCall c = rec.c[M_ADJ];
+        c.tiles = S.atiles;
+        c.ntiles = S.antiles;
+        c.per_xcd = S.antiles / 8;
+        void* args[] = {&c};
+        hip_check(hipModuleLaunchKernel(K.fn[M_ADJ], (unsigned)S.antiles, 1, 1, (unsigned)S.block, 1, 1, 0, s, args,
+                                        nullptr),
+                  "hipModuleLaunchKernel");
+    }
 }
 
-void launch(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j, double* h,
-            hipStream_t s) {
-    const int64_t nt = b.ntiles[mask];
-    if (nt == 0) return;
-    ExaCall c;
-    std::memset(&c, 0, sizeof c);
-    c.tiles = b.tiles[mask];
-    c.ntiles = nt;
-    c.inst = b.inst;
-    c.x = x;
-    c.y = y;
-    c.sigma = sigma;
-    c.persistent = b.grid < 0 ? 0 : 1;
-    c.xcd_range = b.grid < 0 ? nullptr : b.xcd_ranges[mask];
-    c.per_xcd = b.per_xcd[mask];
-    hipFunction_t fn;
-    if (mask == 1) {
-        fn = b.module->fn[M_JAC];
-        c.out0 = j;
-    } else if (mask == 2) {
-        fn = b.module->fn[M_HESS];
-        c.out0 = h;
-    } else {
-        fn = b.tiles_combined ? b.module->fn[M_JH] : b.module->fn_sep;
-        c.out0 = j;
-        c.out1 = h;
+// The reduction launch(es) of a mask.  Returns whether anything was launched.
+bool launch_reduce(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
+    const exa_batch::Sched& S = b.sched.at(mask);
+    ExaBatchReduce R;
+    std::memset(&R, 0, sizeof R);
+    R.jobs = S.jobs;
+    R.blocks = S.blocks;
+    R.nblocks = S.nblocks;
+    R.lblocks = S.lblocks;
+    R.nlblocks = S.nlblocks;
+    for (int k = 0; k < kExaBatchBufs; ++k) R.bufs[k] = b.buf[k];
+    R.outs[kOutF] = io.f;
+    R.outs[kOutG] = io.g;
+    R.outs[kOutJtw] = io.jtw;
+    R.outs[kOutHv] = io.hv;
+    R.outs[kOutLag] = io.lag;
+    R.outs[kOutLagTmp] = b.lag_tmp;
+    R.outs[kOutThetaBar] = io.theta_bar;
+    R.alpha = io.obj_weight;
+    hip_check(exa_launch_reduce_batch(R, s), "batched reductions");
+    if (S.axpy) {
+        // lag = sigma * lag + J^T y, each operation rounded on its own (as
+        // exa_lag_grad finishes a reduced gradient)
+        ExaReduce A;
+        std::memset(&A, 0, sizeof A);
+        A.ep_job = -1;
+        A.ax_out = io.lag;
+        A.ax_add = b.lag_tmp;
+        A.ax_alpha = io.obj_weight;
+        A.ax_n = b.offsets[kNoff * b.B + kOffX];
+        hip_check(exa_launch_reduce(A, s), "batched Lagrangian gradient");
     }
-    // b.grid < 0: one workgroup per tile (workgroup w takes tile
-    // (w % 8) * per_xcd + w / 8); else a persistent grid, a multiple of 8
-    // (one share per XCD)
-    int64_t grid = 8 * b.per_xcd[mask];
-    if (b.grid >= 0) {
-        grid = std::max<int64_t>(8, std::min<int64_t>(b.grid, nt));
-        grid = (grid + 7) / 8 * 8;
-    }
-    void* args[] = {&c};
-    hip_check(hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)b.block, 1, 1, 0, s, args, nullptr),
-              "hipModuleLaunchKernel");
+    return S.nblocks > 0 || S.nlblocks > 0 || S.axpy;
 }
 
-void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double sigma, double* j, double* h,
-          hipStream_t s) {
+void run(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
+    const ExaMulti rec = call_records(b, mask, io);
+    exa_batch::Timing& T = b.timing;
+    const bool timed = T.on && T.used < (int64_t)T.reduced.size();
+    hipEvent_t* ev = timed ? &T.ev[4 * T.used] : nullptr;
+    if (timed) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
+    launch_eval(b, mask, rec, s);
+    if (timed) {
+        hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
+        hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
+    }
+    const bool red = launch_reduce(b, mask, io, s);
+    if (timed) {
+        hip_check(hipEventRecord(ev[3], s), "hipEventRecord");
+        T.reduced[T.used++] = red ? 1 : 0;
+    }
+}
+
+// First call with a mask under autotune: time every candidate schedule's
+// evaluation launch(es) on the caller's arguments and keep the fastest.
+void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
+    const uint32_t em = eval_mask(mask);
     const int blocks[] = {64, 128, 256};
-    const int epls[] = {1, 2, 4, 8, 16};
-    const int64_t grids[] = {-1, b.cus * 2, b.cus * 4, b.cus * 8, b.cus * 16};
-    std::vector<int> combos = {1};
-    if (mask == 3) combos.push_back(0);
+    const int epls[] = {1, 2, 4, 8};
+    std::vector<int> fuses = {0};
+    bool fusable = false;
+    for (int mode : eval_modes(em, false))
+        if (mode != M_OBJ && has_fusable_group(b.models[0]->impl, mode)) fusable = true;
+    if ((mask & EXA_EV_ADJ) && has_fusable_group(b.models[0]->impl, M_ADJ)) fusable = true;
+    if (fusable) fuses.push_back(1);
+    std::vector<int> combos = {EXA_UNITS_PER_CALLBACK};
+    if (em && has_jh(em)) combos.push_back(EXA_UNITS_JAC_HESS);
+    if (em && combined_mode_of(em) >= 0) combos.push_back(EXA_UNITS_ONE_PASS);
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     struct Cand {
         float ms;
-        int block, epl, comb;
-        int64_t grid;
+        int block, epl, fused, units;
     };
-    // average of `reps` back-to-back launches of the current schedule
+    const ExaMulti rec = call_records(b, mask, io);
     auto time_it = [&](int reps) {
-        launch(b, mask, x, y, sigma, j, h, s);  // warm
+        launch_eval(b, mask, rec, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
-        for (int r = 0; r < reps; ++r) launch(b, mask, x, y, sigma, j, h, s);
+        for (int r = 0; r < reps; ++r) launch_eval(b, mask, rec, s);
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
         hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0;
@@ -239,28 +554,22 @@ void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double 
     };
     std::vector<Cand> cands;
     try {
-        for (int bk : blocks)
-        for (int comb : combos)
-            for (int epl : epls) {
-                b.block = bk;
-                build_tiles(b, epl, comb != 0);
-                for (int64_t g : grids) {
-                    b.grid = g;
-                    cands.push_back({time_it(3), bk, epl, comb, g});
-                }
-            }
-        // candidates within a few percent differ by less than one run's
-        // noise: the fastest few are timed again, longer, in turns, and the
-        // best of their rounds decides
-        std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& c) { return a.ms < c.ms; });
+        for (int u : combos)
+            for (int f : fuses)
+                for (int bk : blocks)
+                    for (int ep : epls) {
+                        set_batch_schedule(b, mask, bk, ep, f != 0, u);
+                        cands.push_back({time_it(2), bk, ep, f, u});
+                    }
+        // neighbouring schedules differ by less than one timing's noise: the
+        // fastest few again, longer, in turns; the best of their rounds decides
+        std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
         cands.resize(std::min<size_t>(cands.size(), 6));
         for (auto& c : cands) c.ms = 1e30f;
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
-                b.block = c.block;
-                b.grid = c.grid;
-                build_tiles(b, c.epl, c.comb != 0);
-                c.ms = std::min(c.ms, time_it(8));
+                set_batch_schedule(b, mask, c.block, c.epl, c.fused != 0, c.units);
+                c.ms = std::min(c.ms, time_it(6));
             }
     } catch (...) {
         (void)hipEventDestroy(e0);
@@ -269,14 +578,16 @@ void tune(exa_batch& b, uint32_t mask, const double* x, const double* y, double 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& a, const Cand& c) { return a.ms < c.ms; });
-    b.epl = w.epl;
-    b.block = w.block;
-    b.grid = w.grid;
-    b.combined = w.comb != 0;
-    b.tuned_ns = (int64_t)(w.ms * 1e6);
-    build_tiles(b, b.epl, b.combined);
-    b.tuned = true;
+    const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units);
+    b.sched[mask].tuned_ns = (int64_t)(w.ms * 1e6);
+}
+
+void check_mask(uint32_t mask) {
+    if (mask == 0 || (mask & ~(uint32_t)EXA_BATCH_ALL))
+        fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
+    if ((mask & EXA_EV_LAG) && (mask & (EXA_EV_GRAD | EXA_EV_JTPROD)))
+        fail(EXA_EINVAL, "EXA_EV_LAG cannot be combined with EXA_EV_GRAD or EXA_EV_JTPROD");
 }
 
 template <class F>
@@ -307,54 +618,95 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         if (!out) fail(EXA_EINVAL, "null output handle");
         *out = nullptr;
         if (B < 1 || !models) fail(EXA_EINVAL, "a batch needs at least one model");
-        std::unique_ptr<exa_batch> b(new exa_batch());
-        b->B = B;
-        b->models.assign(models, models + B);
         for (int i = 0; i < B; ++i) {
             if (!models[i]) fail(EXA_EINVAL, "null model in batch");
-            if (models[i]->impl.host_only || !models[i]->impl.dev)
-                fail(EXA_ESTATE, "batched models need a device");
             if (models[i]->impl.signature != models[0]->impl.signature)
                 fail(EXA_EINVAL, "model " + std::to_string(i) + " does not share the pattern trees of model 0");
         }
+        for (int i = 0; i < B; ++i)
+            if (models[i]->impl.host_only || !models[i]->impl.dev)
+                fail(EXA_ESTATE, "batched models need a device");
+        std::unique_ptr<exa_batch> b(new exa_batch());
+        b->B = B;
+        b->models.assign(models, models + B);
         if (opt) {
             b->autotune = opt->autotune != 0;
             if (opt->block) b->block = opt->block;
             if (opt->epl) b->epl = opt->epl;
-            b->grid = opt->grid;
-            b->use_graph = opt->use_graph != 0;
             b->fuse = opt->fuse != 0;
+            b->units = opt->units;
+            b->use_graph = opt->use_graph != 0;
             b->xcd_aware = opt->xcd_aware != 0;
-            b->combined = opt->separate == 0;
         }
         if (b->block != 64 && b->block != 128 && b->block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
-        int dev = 0;
-        hip_check(hipGetDevice(&dev), "hipGetDevice");
-        hipDeviceProp_t prop;
-        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        b->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-        if (b->grid == 0 || b->grid < -1) b->grid = (int64_t)b->cus * 8;
+        if (b->units < EXA_UNITS_PER_CALLBACK || b->units > EXA_UNITS_ONE_PASS)
+            fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
 
+        // offsets in the concatenated arrays and bases in the work buffers
+        b->offsets.assign(kNoff * (B + 1), 0);
+        for (int k = 0; k < kExaBatchBufs; ++k) b->base[k].assign(B, 0);
+        b->nobj.assign(B, 0);
+        for (int i = 0; i < B; ++i) {
+            const Model& M = models[i]->impl;
+            const int64_t* o = &b->offsets[kNoff * i];
+            int64_t* n = &b->offsets[kNoff * (i + 1)];
+            n[kOffX] = o[kOffX] + M.nvar;
+            n[kOffY] = o[kOffY] + M.ncon;
+            n[kOffJac] = o[kOffJac] + M.nnzj;
+            n[kOffHess] = o[kOffHess] + M.nnzh;
+            n[kOffTheta] = o[kOffTheta] + M.ntheta;
+            b->nobj[i] = M.dev->sched[M_OBJ].ntiles;
+            const int64_t len[kExaBatchBufs] = {M.fo_obj_len + M.fo_con_len, M.hv_len, M.par_len, b->nobj[i]};
+            for (int k = 0; k < kExaBatchBufs; ++k) {
+                b->base[k][i] = b->buf_len[k];
+                b->buf_len[k] += aligned(len[k]);
+            }
+            b->grad_direct_all = b->grad_direct_all && M.grad_direct;
+            b->grad_direct_any = b->grad_direct_any || M.grad_direct;
+        }
+        // the batch's parameters: a copy of each model's device parameters
+        const int64_t nth = b->offsets[kNoff * B + kOffTheta];
+        b->theta = (double*)b->mem.alloc(std::max<int64_t>(1, nth) * sizeof(double));
+        for (int i = 0; i < B; ++i) {
+            const Model& M = models[i]->impl;
+            if (M.ntheta)
+                hip_check(hipMemcpy(b->theta + b->offsets[kNoff * i + kOffTheta], M.dev->theta,
+                                    M.ntheta * sizeof(double), hipMemcpyDeviceToDevice),
+                          "hipMemcpy");
+        }
+        // instance tables
         std::vector<ExaInstDev> inst(B);
-        b->offsets.assign(4 * (B + 1), 0);
         for (int i = 0; i < B; ++i) {
             const Model& M = models[i]->impl;
             inst[i] = M.dev->inst_host;
             std::memset(inst[i].off, 0, sizeof inst[i].off);
-            int64_t* o = &b->offsets[4 * i];
-            inst[i].off[EXA_OFF_X] = o[0];
-            inst[i].off[EXA_OFF_Y] = o[1];
-            inst[i].off[EXA_OFF_JAC] = o[2];
-            inst[i].off[EXA_OFF_HESS] = o[3];
-            o[4] = o[0] + M.nvar;
-            o[5] = o[1] + M.ncon;
-            o[6] = o[2] + M.nnzj;
-            o[7] = o[3] + M.nnzh;
+            inst[i].off[EXA_OFF_X] = b->offsets[kNoff * i + kOffX];
+            inst[i].off[EXA_OFF_Y] = b->offsets[kNoff * i + kOffY];
+            inst[i].off[EXA_OFF_ROWS] = b->offsets[kNoff * i + kOffY];
+            inst[i].off[EXA_OFF_JAC] = b->offsets[kNoff * i + kOffJac];
+            inst[i].off[EXA_OFF_HESS] = b->offsets[kNoff * i + kOffHess];
+            inst[i].off[EXA_OFF_FO_OBJ] = b->base[kBufFo][i];
+            inst[i].off[EXA_OFF_FO_CON] = b->base[kBufFo][i] + M.fo_obj_len;
+            inst[i].off[EXA_OFF_HV] = b->base[kBufHv][i];
+            inst[i].off[EXA_OFF_PAR] = b->base[kBufPar][i];
+            inst[i].off[EXA_OFF_TILE] = b->base[kBufTile][i];
+            inst[i].theta = b->theta + b->offsets[kNoff * i + kOffTheta];
         }
         b->inst = (ExaInstDev*)b->mem.upload(inst.data(), inst.size() * sizeof(ExaInstDev));
-        build_tiles(*b, b->epl, b->combined);
+        // the models' maps, each with part sums of the batch's own
+        b->maps.resize(B);
+        for (int i = 0; i < B; ++i) {
+            const DeviceState& D = *models[i]->impl.dev;
+            exa_batch::Maps& mp = b->maps[i];
+            mp.grad = D.grad_map;
+            mp.jt = D.jt_map;
+            mp.h = D.h_map;
+            mp.par = D.par_map;
+            for (DevMap* m : {&mp.grad, &mp.jt, &mp.h, &mp.par})
+                if (m->nparts > 0) m->lsum = (double*)b->mem.alloc(m->nparts * sizeof(double));
+        }
         hip_check(hipStreamCreate(&b->cap), "hipStreamCreate");
         *out = b.release();
     });
@@ -371,77 +723,226 @@ exa_status exa_batch_offsets(const exa_batch* b, int64_t* offsets) {
     });
 }
 
-exa_status exa_batch_schedule(const exa_batch* b, int64_t* out6) {
+exa_status exa_batch_set_theta(exa_batch* b, const double* theta, exa_stream_t stream) {
+    return guard([&] {
+        if (!b) fail(EXA_EINVAL, "null batch");
+        const int64_t n = b->offsets[kNoff * b->B + kOffTheta];
+        if (n > 0 && !theta) fail(EXA_EINVAL, "null theta");
+        if (n > 0)
+            hip_check(hipMemcpyAsync(b->theta, theta, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                     (hipStream_t)stream),
+                      "hipMemcpyAsync");
+    });
+}
+
+exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6) {
     return guard([&] {
         if (!b || !out6) fail(EXA_EINVAL, "null argument");
-        out6[0] = b->block;
-        out6[1] = b->epl;
-        out6[2] = b->grid;
-        out6[3] = b->ntiles[3];
-        out6[4] = b->tuned_ns;
-        out6[5] = b->combined ? 1 : 0;
+        auto it = b->sched.find(mask);
+        if (it == b->sched.end()) fail(EXA_ESTATE, "no exa_batch_eval call with this mask yet");
+        const exa_batch::Sched& S = it->second;
+        out6[0] = S.block;
+        out6[1] = S.epl;
+        out6[2] = S.fused ? 1 : 0;
+        out6[3] = S.units;
+        out6[4] = S.ntiles + S.antiles;
+        out6[5] = S.tuned_ns;
     });
 }
 
-exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* read_bytes, int64_t* write_bytes) {
+exa_status exa_batch_set_schedule(exa_batch* b, uint32_t mask, int32_t block, int32_t epl, int32_t fused,
+                                  int32_t units) {
     return guard([&] {
         if (!b) fail(EXA_EINVAL, "null batch");
-        if (mask == 0 || mask > 3) fail(EXA_EINVAL, "mask must be EXA_CB_JAC, EXA_CB_HESS or both");
-        std::vector<int> modes;
-        for (auto mc : mask_modes(mask, b->combined)) modes.push_back(mc.first);
-        int64_t rd = 0, wr = 0;
+        check_mask(mask);
+        if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
+        if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
+        if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_ONE_PASS)
+            fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
+        set_batch_schedule(*b, mask, block, epl, fused != 0, units);
+        b->sched[mask].tuned = true;
+        b->drop_graph();
+    });
+}
+
+exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
+    return guard([&] {
+        if (!b || !out4) fail(EXA_EINVAL, "null argument");
+        check_mask(mask);
+        int units = b->units;
+        bool fused = b->fuse;
+        auto it = b->sched.find(mask);
+        if (it != b->sched.end()) {
+            units = it->second.units;
+            fused = it->second.fused;
+        }
+        const uint32_t em = eval_mask(mask);
+        int64_t er = 0, ew = 0, rr = 0, rw = 0;
         for (int i = 0; i < b->B; ++i) {
+            const Model& M = b->models[i]->impl;
             int64_t r = 0, w = 0;
-            kernel_bytes(b->models[i]->impl, modes, b->fuse, r, w);
-            rd += r;
-            wr += w;
+            if (em) {
+                kernel_bytes(M, launch_modes(em, valid_units(em, units)), fused, r, w);
+                er += r;
+                ew += w;
+            }
+            if (mask & EXA_EV_ADJ) {
+                kernel_bytes(M, {M_ADJ}, fused, r, w);
+                er += r;
+                ew += w;
+            }
+            reduce_bytes(M, mask, r, w);
+            rr += r;
+            rw += w;
+            // one objective partial is copied by the reduction launch
+            if ((mask & EXA_EV_OBJ) && b->nobj[i] == 1) {
+                rr += 8;
+                rw += 8;
+            }
+            // g = sigma g + J^T y reads g once; a reduced gradient is finished
+            // by an elementwise launch (two reads and a write per entry)
+            if (mask & EXA_EV_LAG) rr += (b->grad_direct_all ? 8 : 16) * M.nvar, rw += b->grad_direct_all ? 0 : 8 * M.nvar;
         }
-        if (read_bytes) *read_bytes = rd;
-        if (write_bytes) *write_bytes = wr;
+        out4[0] = er;
+        out4[1] = ew;
+        out4[2] = rr;
+        out4[3] = rw;
     });
 }
 
-exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const double* x, const double* y, double sigma,
-                          double* jac, double* hess, exa_stream_t stream) {
+exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, exa_stream_t stream) {
     return guard([&] {
         if (!b) fail(EXA_EINVAL, "null batch");
-        if (mask == 0 || mask > 3) fail(EXA_EINVAL, "mask must be EXA_CB_JAC, EXA_CB_HESS or both");
-        const int64_t* tot = &b->offsets[4 * b->B];
-        if (!x && tot[0]) fail(EXA_EINVAL, "null x");
-        if ((mask & EXA_CB_HESS) && !y && tot[1]) fail(EXA_EINVAL, "null y");
-        if ((mask & EXA_CB_JAC) && !jac && tot[2]) fail(EXA_EINVAL, "null jac output");
-        if ((mask & EXA_CB_HESS) && !hess && tot[3]) fail(EXA_EINVAL, "null hess output");
+        if (!io) fail(EXA_EINVAL, "null exa_batch_io");
+        check_mask(mask);
+        const int64_t* tot = &b->offsets[kNoff * b->B];
+        auto need = [](const void* p, int64_t n, const char* what) {
+            if (n > 0 && !p) fail(EXA_EINVAL, std::string("null pointer: ") + what);
+        };
+        need(io->x, tot[kOffX], "x");
+        if (mask & (EXA_EV_HESS | EXA_EV_HPROD | EXA_EV_LAG | EXA_EV_ADJ)) need(io->y, tot[kOffY], "y");
+        if (mask & (EXA_EV_JPROD | EXA_EV_HPROD)) need(io->v, tot[kOffX], "v");
+        if (mask & EXA_EV_JTPROD) need(io->w, tot[kOffY], "w");
+        if (mask & EXA_EV_ADJ) need(io->wx, tot[kOffX], "wx");
+        if (mask & EXA_EV_OBJ) need(io->f, b->B, "f");
+        if (mask & EXA_EV_GRAD) need(io->g, tot[kOffX], "g");
+        if (mask & EXA_EV_CONS) need(io->c, tot[kOffY], "c");
+        if (mask & EXA_EV_JAC) need(io->jac, tot[kOffJac], "jac");
+        if (mask & EXA_EV_HESS) need(io->hess, tot[kOffHess], "hess");
+        if (mask & EXA_EV_JPROD) need(io->jv, tot[kOffY], "jv");
+        if (mask & EXA_EV_JTPROD) need(io->jtw, tot[kOffX], "jtw");
+        if (mask & EXA_EV_HPROD) need(io->hv, tot[kOffX], "hv");
+        if (mask & EXA_EV_LAG) need(io->lag, tot[kOffX], "lag");
+        if (mask & EXA_EV_ADJ) need(io->theta_bar, tot[kOffTheta], "theta_bar");
+        if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && b->grad_direct_all != b->grad_direct_any)
+            fail(EXA_EINVAL,
+                 "the instances disagree on whether every variable has at most one objective term; their "
+                 "gradients cannot be evaluated in one batch");
         hipStream_t s = (hipStream_t)stream;
-        if (b->autotune && !b->tuned) {
-            tune(*b, mask, x, y, sigma, jac, hess, s);
-            b->have_graph = false;
+        // work buffers this mask needs
+        if ((mask & (EXA_EV_GRAD | EXA_EV_JTPROD | EXA_EV_LAG))) need_buf(*b, kBufFo);
+        if (mask & EXA_EV_HPROD) need_buf(*b, kBufHv);
+        if (mask & EXA_EV_ADJ) need_buf(*b, kBufPar);
+        if (mask & EXA_EV_OBJ) need_buf(*b, kBufTile);
+        if ((mask & EXA_EV_LAG) && !b->grad_direct_all && !b->lag_tmp)
+            b->lag_tmp = (double*)b->mem.alloc(std::max<int64_t>(1, tot[kOffX]) * sizeof(double));
+        auto it = b->sched.find(mask);
+        if (it == b->sched.end() || !it->second.tuned) {
+            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units);
+            if (b->autotune) tune_batch(*b, mask, *io, s);
+            b->sched[mask].tuned = true;
+            b->drop_graph();
         }
-        build_tiles(*b, b->epl, b->combined);
-        if (!b->use_graph) {
-            launch(*b, mask, x, y, sigma, jac, hess, s);
-            return;
-        }
-        exa_batch::Key k{mask, x, y, jac, hess, sigma, b->epl, b->block, b->grid, b->combined};
-        if (!b->have_graph || !(k == b->key)) {
-            if (b->exec) (void)hipGraphExecDestroy(b->exec);
-            if (b->graph) (void)hipGraphDestroy(b->graph);
-            b->exec = nullptr;
-            b->graph = nullptr;
-            hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            try {
-                launch(*b, mask, x, y, sigma, jac, hess, b->cap);
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(b->cap, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
+        exa_batch::Sched& S = b->sched[mask];
+        if (!S.reduce_built) build_reductions(*b, S, mask);
+        if (!b->use_graph || b->timing.on) {
+            run(*b, mask, *io, s);
+        } else {
+            exa_batch::Key k;
+            k.mask = mask;
+            k.io = *io;
+            k.block = S.block;
+            k.epl = S.epl;
+            k.units = S.units;
+            k.fused = S.fused;
+            const bool same = b->have_graph && k.mask == b->key.mask && std::memcmp(&k.io, &b->key.io, sizeof k.io) == 0 &&
+                              k.block == b->key.block && k.epl == b->key.epl && k.units == b->key.units &&
+                              k.fused == b->key.fused;
+            if (!same) {
+                b->drop_graph();
+                hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+                try {
+                    run(*b, mask, *io, b->cap);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(b->cap, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                hip_check(hipStreamEndCapture(b->cap, &b->graph), "hipStreamEndCapture");
+                hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+                b->key = k;
+                b->have_graph = true;
             }
-            hip_check(hipStreamEndCapture(b->cap, &b->graph), "hipStreamEndCapture");
-            hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-            b->key = k;
-            b->have_graph = true;
+            hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
         }
-        hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+        const uint32_t bits[10] = {EXA_EV_OBJ, EXA_EV_GRAD, EXA_EV_CONS, EXA_EV_JAC, EXA_EV_HESS,
+                                   EXA_EV_JPROD, EXA_EV_JTPROD, EXA_EV_HPROD, EXA_EV_LAG, EXA_EV_ADJ};
+        for (exa_model* m : b->models)
+            for (int i = 0; i < 10; ++i)
+                if (mask & bits[i]) {
+                    if (i < 8) m->impl.counters[i]++;
+                    else if (i == 8) m->impl.counters[1]++, m->impl.counters[6]++;
+                    else m->impl.counters[8]++;
+                }
+    });
+}
+
+exa_status exa_batch_timing(exa_batch* b, int32_t enable) {
+    return guard([&] {
+        if (!b) fail(EXA_EINVAL, "null batch");
+        b->timing_off();
+        if (!enable) return;
+        const int64_t calls = 1024;
+        b->timing.ev.reserve(4 * calls);
+        for (int64_t i = 0; i < 4 * calls; ++i) {
+            hipEvent_t e;
+            // timing only: no system-scope fence (cache writeback) per record
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+                b->timing_off();
+                fail(EXA_EHIP, "hipEventCreate failed");
+            }
+            b->timing.ev.push_back(e);
+        }
+        b->timing.reduced.assign(calls, 0);
+        b->timing.on = true;
+    });
+}
+
+exa_status exa_batch_timing_read(exa_batch* b, double* out4) {
+    return guard([&] {
+        if (!b || !out4) fail(EXA_EINVAL, "null argument");
+        exa_batch::Timing& T = b->timing;
+        if (!T.on) fail(EXA_ESTATE, "batch timing is off");
+        double se = 0.0, sr = 0.0;
+        int64_t nr = 0;
+        for (int64_t i = 0; i < T.used; ++i) {
+            hipEvent_t* ev = &T.ev[4 * i];
+            hip_check(hipEventSynchronize(ev[3]), "hipEventSynchronize");
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+            se += ms;
+            if (T.reduced[i]) {
+                hip_check(hipEventElapsedTime(&ms, ev[2], ev[3]), "hipEventElapsedTime");
+                sr += ms;
+                ++nr;
+            }
+        }
+        out4[0] = (double)T.used;
+        out4[1] = T.used ? 1e3 * se / (double)T.used : 0.0;
+        out4[2] = (double)nr;
+        out4[3] = nr ? 1e3 * sr / (double)nr : 0.0;
+        T.used = 0;
     });
 }
 

@@ -633,7 +633,7 @@ std::string dest(const Pattern& P, int mode, const std::string& pd, const std::s
         case M_GRAD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_OBJ) + "] + " + pd + ".ob" + st;
         case M_JAC: return out + " + I.off[" + std::to_string(EXA_OFF_JAC) + "] + " + pd + ".o1" + st;
         case M_JTPROD: return out + " + I.off[" + std::to_string(EXA_OFF_FO_CON) + "] + " + pd + ".ob" + st;
-        case M_HPROD: return out + " + " + pd + ".oh" + st;
+        case M_HPROD: return out + " + I.off[" + std::to_string(EXA_OFF_HV) + "] + " + pd + ".oh" + st;
         case M_HESS: return out + " + I.off[" + std::to_string(EXA_OFF_HESS) + "] + " + pd + ".o2" + st;
         case M_ADJ: return out + " + I.off[" + std::to_string(EXA_OFF_PAR) + "] + " + pd + ".op" + st;
         default: return "";
@@ -1170,34 +1170,16 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
     os << "// rounds of EXA_VLANES points in one objective tile\n#define EXA_OBJ_ROUNDS " << kObjBlock * kObjEpl / 256
        << "\n";
     int ntmp = 0;
-    // Tile loop shared by every kernel.  Non-persistent launches take one
-    // tile per workgroup; workgroup w runs on XCD w % 8, so tile indices are
-    // remapped to give each XCD a contiguous range.  Persistent launches walk
-    // the list with a grid stride, or, with xcd_range, XCD j walks tiles
-    // [xcd_range[j], xcd_range[j+1]) (the grid is then a multiple of 8).
+    // Tile loop shared by every kernel: one tile per workgroup; workgroup w
+    // runs on XCD w % 8, so tile indices are remapped to give each XCD a
+    // contiguous range.
     auto kernel = [&](const std::string& name, int lds, const std::vector<std::string>& cases) {
         os << "extern \"C\" __global__ void __launch_bounds__(" << EXA_BLOCK_MAX << ") " << name << "(ExaCall C) {\n";
         os << "    __shared__ double lds[" << lds << "];\n";
         os << "    (void)lds;\n";
-        os << "    ExaCall H = C;\n";
-        os << "    H.out0 = C.out1;\n";
-        os << "    (void)H;\n";
-        os << "    long long w0, hi, step;\n";
-        os << "    if (!C.persistent) {\n";
-        os << "        w0 = (blockIdx.x % 8) * C.per_xcd + blockIdx.x / 8;\n";
-        os << "        hi = w0 < C.ntiles ? w0 + 1 : 0;\n";
-        os << "        step = 1;\n";
-        os << "    } else if (C.xcd_range) {\n";
-        os << "        const int j = blockIdx.x % 8;\n";
-        os << "        w0 = C.xcd_range[j] + blockIdx.x / 8;\n";
-        os << "        hi = C.xcd_range[j + 1];\n";
-        os << "        step = gridDim.x / 8;\n";
-        os << "    } else {\n";
-        os << "        w0 = blockIdx.x;\n";
-        os << "        hi = C.ntiles;\n";
-        os << "        step = gridDim.x;\n";
-        os << "    }\n";
-        os << "    for (long long w = w0; w < hi; w += step) {\n";
+        os << "    {\n";
+        os << "        const long long w = (blockIdx.x % 8) * C.per_xcd + blockIdx.x / 8;\n";
+        os << "        if (w >= C.ntiles) return;\n";
         os << "        const ExaTile T = C.tiles[w];\n";
         os << "        const ExaInstDev& I = C.inst[T.inst];\n";
         os << "        switch (T.pat) {\n";
@@ -1232,21 +1214,6 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
                             ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) "
                             "C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;");
         kernel(kernel_name(mode), mode_lds_doubles(M, mode), cases);
-    }
-    // Jacobian tiles (codes < 64, values to out0) and Hessian tiles (codes
-    // 64 + u, values to out1) of separate units in one launch.
-    {
-        std::vector<std::string> cases;
-        for (int mode : {M_JAC, M_HESS}) {
-            std::set<int> codes;
-            for (int fused = 0; fused < 2; ++fused)
-                for (auto& u : units_for(M, mode, fused != 0)) codes.insert(u.code);
-            for (int c : codes)
-                cases.push_back("case " + std::to_string(c + (mode == M_HESS ? 64 : 0)) + ": unit_" + mode_name(mode) +
-                                "_" + std::to_string(c) + (mode == M_HESS ? "(H, I, T, lds)" : "(C, I, T, lds)") +
-                                "; break;");
-        }
-        kernel("exa_k_jhsep", mode_lds_doubles(M, M_JH), cases);
     }
     // Several callbacks in one launch: a tile's mode sits above
     // EXA_MODE_SHIFT in its code, and its case passes that mode's call (a

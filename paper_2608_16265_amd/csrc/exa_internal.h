@@ -38,6 +38,7 @@ void set_last_error(const std::string& msg);
 #define EXA_OFF_Y 7       /* y (ncon)                                        */
 #define EXA_OFF_FO_OBJ 8  /* first-order buffer, objective part (nnzg)       */
 #define EXA_OFF_FO_CON 9  /* first-order buffer, constraint part (nnzj)      */
+#define EXA_OFF_HV 10     /* H v buffer (curved slots)                       */
 #define EXA_NOFF 12
 // Index offsets of a pattern's unique references live in ExaPatDev::roff
 // (variable slots first, then parameter slots), so that every instance of a
@@ -90,9 +91,8 @@ void set_last_error(const std::string& msg);
         double* out0;                                                            \
         double* out1;                                                            \
         double sigma;                                                            \
-        int persistent;                                                          \
         int direct;                                                              \
-        const long long* xcd_range;                                              \
+        int pad2;                                                                \
     };                                                                           \
     struct ExaMulti {                                                            \
         const struct ExaTile* tiles;                                             \

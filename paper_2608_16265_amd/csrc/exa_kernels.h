@@ -71,3 +71,47 @@ struct ExaReduce {
     int64_t ax_n;
 };
 hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s);
+
+// Segment sums and objective sums of many instances in one launch (the
+// batched reductions).  Job j sums one instance's map, exactly as a single
+// ExaSegJob over the same map would (same chunking, same parts, same order),
+// or adds one instance's objective partials as the objective's own
+// reduction does (one partial: copied; none: 0).  Buffers and outputs are
+// named by index and offset, so the job table does not depend on the
+// caller's pointers: bufs[buf] + buf_off is the job's buffer and
+// outs[out] + out_off its output.
+constexpr int kExaBatchBufs = 4;   // first-order, H v, parameter, objective partials
+constexpr int kExaBatchOuts = 8;
+struct ExaBatchJob {
+    const void* ptr;
+    const void* idx;
+    const int32_t* lanes;
+    const int32_t* lidx;
+    const int32_t* longs;
+    const int32_t* lpart;
+    double* lsum;
+    int64_t nseg, nlanes, nparts, nlong;
+    int64_t buf_off, out_off;
+    int32_t wide, chunked;
+    int32_t buf, out;
+    int32_t kind;  // 0: segment sums; 1: objective partials (nseg of them) into one value
+    int32_t ep;    // 1: out = alpha * out + sum, the product rounded first
+};
+struct ExaBatchReduce {
+    const ExaBatchJob* jobs;
+    // block b of the first launch runs (job, block within the job) =
+    // blocks[b] (job -1: nothing); nblocks is a multiple of 8, and XCD j
+    // takes blocks [j * nblocks / 8, (j + 1) * nblocks / 8)
+    const int32_t* blocks;
+    int64_t nblocks;
+    // block b of the second launch adds the part sums of long segment
+    // lblocks[2b + 1] of job lblocks[2b]
+    const int32_t* lblocks;
+    int64_t nlblocks;
+    const double* bufs[kExaBatchBufs];
+    double* outs[kExaBatchOuts];
+    double alpha;
+};
+hipError_t exa_launch_reduce_batch(const ExaBatchReduce& r, hipStream_t s);
+int64_t exa_job_blocks(const ExaSegJob& J);
+

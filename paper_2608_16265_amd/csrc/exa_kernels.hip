@@ -221,6 +221,96 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce_long(ExaReduce R) {
     }
 }
 
+// The segment-sum job of a batched job, with its buffer and output resolved.
+__device__ __forceinline__ ExaSegJob batch_seg(const ExaBatchReduce& R, const ExaBatchJob& B) {
+    ExaSegJob J;
+    J.ptr = B.ptr;
+    J.idx = B.idx;
+    J.buf = R.bufs[B.buf] + B.buf_off;
+    J.out = R.outs[B.out] + B.out_off;
+    J.nseg = B.nseg;
+    J.lanes = B.lanes;
+    J.lidx = B.lidx;
+    J.nlanes = B.nlanes;
+    J.longs = B.longs;
+    J.lpart = B.lpart;
+    J.nparts = B.nparts;
+    J.nlong = B.nlong;
+    J.lsum = B.lsum;
+    J.wide = B.wide;
+    J.chunked = B.chunked;
+    return J;
+}
+
+// Batched reductions: every block runs one block of one instance's job, the
+// same block k_reduce would run for that job alone, so each instance's sums
+// come out bit for bit as its own reduction gives them.
+__global__ void __launch_bounds__(kSegBlock) k_reduce_batch(ExaBatchReduce R) {
+    __shared__ double lds[256];
+    const int64_t per_xcd = R.nblocks / 8;
+    const int64_t b0 = xcd_block(per_xcd);
+    const int2 jb = ((const int2*)R.blocks)[b0];
+    if (jb.x < 0) return;
+    const ExaBatchJob& B = R.jobs[jb.x];
+    if (B.kind == 1) {
+        // objective partials: none -> 0, one -> itself (the value a single
+        // tile writes directly), several -> the fixed-order sum
+        const double* part = R.bufs[B.buf] + B.buf_off;
+        double* f = R.outs[B.out] + B.out_off;
+        if (B.nseg > 1) {
+            sum_body(part, B.nseg, f, lds);
+        } else if (threadIdx.x == 0) {
+            f[0] = B.nseg == 1 ? part[0] : 0.0;
+        }
+        return;
+    }
+    const ExaSegJob J = batch_seg(R, B);
+    const int64_t b = jb.y;
+    const bool ep = B.ep != 0;
+    if (J.chunked) {
+        const int64_t nlb = J.nlanes / kSegBlock;
+        if (b < nlb)
+            chunk_body(J, b * kSegBlock + threadIdx.x, lds, ep, R.alpha);
+        else
+            long_part_body(J, b - nlb, lds);
+        return;
+    }
+    const int64_t nsb = (J.nseg + kSegBlock - 1) / kSegBlock;
+    if (b >= nsb) {
+        long_part_body(J, b - nsb, lds);
+        return;
+    }
+    const int64_t s = b * kSegBlock + threadIdx.x;
+    if (s < J.nseg) {
+        if (J.wide)
+            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false, ep, R.alpha);
+        else
+            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0, ep, R.alpha);
+    }
+}
+
+// Second batched launch: the part sums of one long segment of one job per
+// block, added as k_reduce_long adds them.
+__global__ void __launch_bounds__(kSegBlock) k_reduce_batch_long(ExaBatchReduce R) {
+    __shared__ double lds[256];
+    const int2 jl = ((const int2*)R.lblocks)[blockIdx.x];
+    const ExaBatchJob& B = R.jobs[jl.x];
+    const ExaSegJob J = batch_seg(R, B);
+    const int32_t* L = J.longs + 5 * jl.y;
+    const int32_t seg = L[0], part0 = L[3], nparts = L[4];
+    double acc = 0.0;
+    for (int32_t i0 = threadIdx.x; i0 < nparts; i0 += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = i0 + 256 * u < nparts ? J.lsum[part0 + i0 + 256 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + 256 * u < nparts) acc += v[u];
+    }
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) put(J.out, seg, tot, B.ep != 0, R.alpha);
+}
+
 // Streaming copy with 16-byte non-temporal loads and stores, one vector per
 // lane: the access pattern of the evaluation kernels' final outputs, used to
 // measure the device's practical bandwidth.
@@ -286,6 +376,16 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
     if (r.ax_out && r.ax_n > 0)
         hipLaunchKernelGGL(k_axpy, dim3((unsigned)((r.ax_n + 255) / 256)), dim3(256), 0, s, r.ax_out, r.ax_add,
                            r.ax_alpha, r.ax_n);
+    return hipGetLastError();
+}
+
+int64_t exa_job_blocks(const ExaSegJob& J) { return job_blocks(J); }
+
+hipError_t exa_launch_reduce_batch(const ExaBatchReduce& r, hipStream_t s) {
+    if (r.nblocks % 8 || r.nblocks < 0 || r.nlblocks < 0) return hipErrorInvalidValue;
+    if ((r.nblocks && !(r.jobs && r.blocks)) || (r.nlblocks && !(r.jobs && r.lblocks))) return hipErrorInvalidValue;
+    if (r.nblocks > 0) hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)r.nblocks), dim3(kSegBlock), 0, s, r);
+    if (r.nlblocks > 0) hipLaunchKernelGGL(k_reduce_batch_long, dim3((unsigned)r.nlblocks), dim3(kSegBlock), 0, s, r);
     return hipGetLastError();
 }
 

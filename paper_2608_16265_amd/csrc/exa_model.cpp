@@ -513,8 +513,10 @@ std::string pattern_signature(const Model& M) {
     os.precision(17);
     for (auto& P : M.pats) {
         os << "P" << P.kind << ":" << P.n_icols << "," << P.n_fcols << ":" << P.row_icol << ";";
-        // the generated code skips augmentations without data points
-        if (P.kind == EXA_AUG) os << (P.ndata > 0 ? "D;" : "E;");
+        // the generated code has no unit for a pattern without data points
+        // (of any kind), so instances that share code agree on which
+        // patterns are empty
+        os << (P.ndata > 0 ? "D;" : "E;");
         // reference offsets are per-instance data (ExaPatDev::roff): left out;
         // which references coincide inside a data-set group is kept
         for (auto& n : P.nodes)

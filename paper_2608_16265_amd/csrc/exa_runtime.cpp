@@ -93,8 +93,6 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
             fail(EXA_ECOMPILE, "generated kernel missing: " + kernel_name(mode));
         m->fn[mode] = f;
     }
-    if (hipModuleGetFunction(&m->fn_sep, m->mod, "exa_k_jhsep") != hipSuccess)
-        fail(EXA_ECOMPILE, "generated kernel missing: exa_k_jhsep");
     if (hipModuleGetFunction(&m->fn_multi, m->mod, "exa_k_multi") != hipSuccess)
         fail(EXA_ECOMPILE, "generated kernel missing: exa_k_multi");
     if (hipModuleGetFunction(&m->fn_multijh, m->mod, "exa_k_multijh") != hipSuccess)
@@ -109,6 +107,7 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
 DeviceState::~DeviceState() {
     timing_off();
     for (void* p : allocs) (void)hipFree(p);
+    if (fhost) (void)hipHostFree(fhost);
 }
 
 void DeviceState::timing_off() {
@@ -221,6 +220,9 @@ void build_device(Model& M) {
     D.hv = (double*)D.alloc(M.hv_len * sizeof(double));
     D.tilesum = (double*)D.alloc(std::max<int64_t>(1, D.sched[M_OBJ].ntiles) * sizeof(double));
     D.lag_tmp = (double*)D.alloc(M.nvar * sizeof(double));
+    D.fval = (double*)D.alloc(sizeof(double));
+    if (hipHostMalloc((void**)&D.fhost, sizeof(double), hipHostMallocDefault) != hipSuccess)
+        fail(EXA_ENOMEM, "hipHostMalloc of the objective's host copy failed");
 
     upload_map(D, M.grad_map, D.grad_map);
     upload_map(D, M.jt_map, D.jt_map);
@@ -230,7 +232,6 @@ void build_device(Model& M) {
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
 }
 
-namespace {
 // Tiles that write zeros to the gradient entries no objective term touches
 // (in-place gradient only).
 void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
@@ -245,7 +246,6 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
             tiles.push_back(t);
         }
 }
-}  // namespace
 
 // maps go to the device as int32 whenever every position fits
 void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
@@ -404,7 +404,6 @@ void raw_launch(Model& M, int mode, ExaCall call, hipStream_t s) {
     call.ntiles = S.ntiles;
     call.per_xcd = (S.ntiles + 7) / 8;
     call.inst = D.inst;
-    call.persistent = 0;
     const int64_t grid = 8 * call.per_xcd;
     void* args[] = {&call};
     hip_check(hipModuleLaunchKernel(D.module->fn[mode], (unsigned)grid, 1, 1, (unsigned)S.block, 1, 1, 0, s,
@@ -412,11 +411,15 @@ void raw_launch(Model& M, int mode, ExaCall call, hipStream_t s) {
               "hipModuleLaunchKernel");
 }
 
+}  // namespace
+
 bool has_fusable_group(const Model& M, int mode) {
     for (const Unit& u : units_for(M, mode, true))
         if (u.members.size() > 1) return true;
     return false;
 }
+
+namespace {
 
 // First call of a callback with autotuning on: time every candidate
 // schedule on the caller's own arguments and keep the fastest.  Every
@@ -480,7 +483,6 @@ void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
 }
 
 // ---- several callbacks in one launch (exa_eval) ----------------------------
-namespace {
 
 // Modes of an exa_eval mask; with jh, Jacobian and Hessian together run as
 // JH units (both jobs of a point from one set of loads).
@@ -535,6 +537,8 @@ std::vector<int> launch_modes(uint32_t mask, int units) {
     m.push_back(combined_mode_of(mask));
     return m;
 }
+
+namespace {
 
 // Tile list of a mask: every launch mode's tiles (the objective's under its
 // fixed schedule), laid out as eight chunks that each hold an eighth of
@@ -715,6 +719,40 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
     for (char c : xs) rd += c ? 8 : 0;
     for (char c : vs) rd += c ? 8 : 0;
     for (char c : ts) rd += c ? 8 : 0;
+}
+
+// Reduction launch of an exa_eval mask: maps (int32 when every position
+// fits), buffer entries once, outputs once; objective partials when several.
+void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
+    rr = rw = 0;
+    auto seg = [&](const SegMap& S) {
+        const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
+        const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
+        const int64_t w = top >= INT32_MAX ? 8 : 4;
+        const ChunkPlan P = chunk_plan(S);
+        // chunked maps read a 24-byte record per lane (segment, count,
+        // four positions) instead of segment pointers and positions, and
+        // positions only for the entries of long segments; maps with
+        // long segments read their part tables (the long-segment table
+        // once per launch), and each part sum is written once and read
+        // once
+        int64_t long_nnz = 0;
+        for (int64_t i = 0; i < P.nlong(); ++i) long_nnz += P.longs[5 * i + 2];
+        rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz : w * (nseg + 1) + w * nnz) + 40 * P.nlong() +
+              16 * P.nparts() + 8 * nnz;
+        rw += 8 * nseg + 8 * P.nparts();
+    };
+    if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && !M.grad_direct) seg(M.grad_map);
+    if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) seg(M.jt_map);
+    if (mask & EXA_EV_HPROD) seg(M.h_map);
+    if (mask & EXA_EV_ADJ) seg(M.par_map);
+    if (mask & EXA_EV_OBJ) {
+        const int64_t nobj = (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused).size();
+        if (nobj != 1) {
+            rr += 8 * nobj;
+            rw += 8;
+        }
+    }
 }
 
 ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
@@ -904,25 +942,44 @@ exa_status exa_hess_structure(const exa_model* m, int32_t* rows, int32_t* cols) 
     });
 }
 
+namespace {
+void obj_body(Model& M, const double* x, double* f, hipStream_t s) {
+    DeviceState& D = *M.dev;
+    if (D.sched[M_OBJ].ntiles == 0) {
+        hip_check(exa_launch_fill(f, 1, 0.0, s), "fill");
+    } else {
+        // one tile: its workgroup sum is the objective, written in place
+        const bool one = D.sched[M_OBJ].ntiles == 1;
+        ExaCall c = blank_call();
+        c.x = x;
+        c.out0 = one ? f : D.tilesum;
+        launch_mode(M, M_OBJ, c, s);
+        if (!one) hip_check(exa_launch_sum(D.tilesum, D.sched[M_OBJ].ntiles, f, s), "objective reduction");
+    }
+    M.counters[0]++;
+}
+}  // namespace
+
 exa_status exa_obj(exa_model* m, const double* x, double* f, exa_stream_t stream) {
     return guard([&] {
         Model& M = live(m);
         need(x, M.nvar, "x");
         need(f, 1, "f");
+        obj_body(M, x, f, (hipStream_t)stream);
+    });
+}
+
+exa_status exa_obj_host(exa_model* m, const double* x, double* f, exa_stream_t stream) {
+    return guard([&] {
+        Model& M = live(m);
+        need(x, M.nvar, "x");
+        if (!f) fail(EXA_EINVAL, "null pointer: f");
         hipStream_t s = (hipStream_t)stream;
         DeviceState& D = *M.dev;
-        if (D.sched[M_OBJ].ntiles == 0) {
-            hip_check(exa_launch_fill(f, 1, 0.0, s), "fill");
-        } else {
-            // one tile: its workgroup sum is the objective, written in place
-            const bool one = D.sched[M_OBJ].ntiles == 1;
-            ExaCall c = blank_call();
-            c.x = x;
-            c.out0 = one ? f : D.tilesum;
-            launch_mode(M, M_OBJ, c, s);
-            if (!one) hip_check(exa_launch_sum(D.tilesum, D.sched[M_OBJ].ntiles, f, s), "objective reduction");
-        }
-        M.counters[0]++;
+        obj_body(M, x, D.fval, s);
+        hip_check(hipMemcpyAsync(D.fhost, D.fval, sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *f = *D.fhost;
     });
 }
 
@@ -1334,36 +1391,8 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
         kernel_bytes(M, launch_modes(mask, units), fused, rd, wr);
         out4[0] = rd;
         out4[1] = wr;
-        // reduction launch: maps (int32 when every position fits), buffer
-        // entries once, outputs once; objective partials when several
         int64_t rr = 0, rw = 0;
-        auto seg = [&](const SegMap& S) {
-            const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
-            const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
-            const int64_t w = top >= INT32_MAX ? 8 : 4;
-            const ChunkPlan P = chunk_plan(S);
-            // chunked maps read a 24-byte record per lane (segment, count,
-            // four positions) instead of segment pointers and positions, and
-            // positions only for the entries of long segments; maps with
-            // long segments read their part tables (the long-segment table
-            // once per launch), and each part sum is written once and read
-            // once
-            int64_t long_nnz = 0;
-            for (int64_t i = 0; i < P.nlong(); ++i) long_nnz += P.longs[5 * i + 2];
-            rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz : w * (nseg + 1) + w * nnz) + 40 * P.nlong() +
-                  16 * P.nparts() + 8 * nnz;
-            rw += 8 * nseg + 8 * P.nparts();
-        };
-        if ((mask & EXA_EV_GRAD) && !M.grad_direct) seg(M.grad_map);
-        if (mask & EXA_EV_JTPROD) seg(M.jt_map);
-        if (mask & EXA_EV_HPROD) seg(M.h_map);
-        if (mask & EXA_EV_OBJ) {
-            const int64_t nobj = (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused).size();
-            if (nobj != 1) {
-                rr += 8 * nobj;
-                rw += 8;
-            }
-        }
+        reduce_bytes(M, mask, rr, rw);
         out4[2] = rr;
         out4[3] = rw;
     });

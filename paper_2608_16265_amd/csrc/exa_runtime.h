@@ -14,7 +14,6 @@ namespace exa {
 struct Module {
     hipModule_t mod = nullptr;
     hipFunction_t fn[M_COUNT] = {};
-    hipFunction_t fn_sep = nullptr;  // separate Jacobian and Hessian tiles in one launch
     hipFunction_t fn_multi = nullptr;    // tiles of several callbacks in one launch (Jacobian and Hessian apart)
     hipFunction_t fn_multijh = nullptr;  // the same with Jacobian + Hessian units
     hipFunction_t fn_onepass = nullptr;  // one pass per point for several callbacks
@@ -76,6 +75,8 @@ struct DeviceState {
     double* hv = nullptr;             // H v contributions (curved slots only)
     double* tilesum = nullptr;
     double* lag_tmp = nullptr;  // J^T y of exa_lag_grad (nvar)
+    double* fval = nullptr;     // objective of exa_obj_host (device)
+    double* fhost = nullptr;    // its pinned host copy
     DevMap csc_map[2];          // uploaded on the first exa_csc_values call
     bool csc_up[2] = {false, false};
     DevMap grad_map, jt_map, h_map, par_map;
@@ -87,6 +88,21 @@ struct DeviceState {
 };
 
 void hip_check(hipError_t e, const char* what);
+// Tiles that write zeros to the gradient entries no objective term touches.
+void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles);
+bool has_fusable_group(const Model& M, int mode);
+// Modes of an exa_eval mask (with jh: Jacobian + Hessian as JH units), the
+// one-pass unit mode covering a mask (or -1), whether a mask has both the
+// Jacobian and the Hessian, the units a mask can run as asked, and the modes
+// whose tiles make up a mask's launch under those units.
+std::vector<int> eval_modes(uint32_t mask, bool jh);
+int combined_mode_of(uint32_t mask);
+bool has_jh(uint32_t mask);
+int valid_units(uint32_t mask, int units);
+std::vector<int> launch_modes(uint32_t mask, int units);
+// Algorithmic bytes of the reduction launch of a mask (maps, buffer entries,
+// outputs, objective partials when there are several).
+void reduce_bytes(const Model& M, uint32_t mask, int64_t& rd, int64_t& wr);
 std::vector<char> compile_code(const std::string& src);
 std::shared_ptr<Module> compile_module(const std::string& src);
 std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused);

@@ -206,6 +206,13 @@ class ExaModel:
         check(LIB.exa_obj(self._h, px, C.c_void_p(out.data_ptr()), _stream(x.get_device())))
         return out
 
+    def obj_host(self, x) -> float:
+        """f(x) as a Python float (the call waits for the stream)."""
+        px = self._dev(x, self.nvar, "x")
+        f = C.c_double()
+        check(LIB.exa_obj_host(self._h, px, C.byref(f), _stream(x.get_device())))
+        return f.value
+
     def grad(self, x, out=None):
         px = self._dev(x, self.nvar, "x")
         out = self._out(out, self.nvar, x, "out")

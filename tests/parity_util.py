@@ -99,3 +99,27 @@ def abs_oracle(o, x, y, sigma, v, w, theta=None):
             np.add.at(g, o._index(P, key, ks), np.max(np.abs(tay.g[:, s_])))
     out["grad"] = g
     return out
+
+
+def adjoint_scale(o, x, y, sigma, w, theta=None):
+    """Per-entry scale for the parameter adjoint theta_bar = sum over
+    pattern instances of weight * sum_a w[col_a] d2T/dx_a dtheta_t: every
+    term counts with |weight| |w[col_a]| times the largest |d2T/dx_a
+    dtheta_t| in its (pattern, slot pair) column, as column_scale measures
+    COO values against their column."""
+    th = o._theta(theta)
+    out = np.zeros(o.ntheta)
+    w = np.asarray(w, dtype=np.float64)
+    for P in o.pats:
+        if not P.pslots or not P.vslots or P.ndata == 0:
+            continue
+        nv = len(P.vslots)
+        ks = np.arange(P.ndata)
+        tay = o._taylor(P, ks, x, th, with_params=True)
+        wt = np.abs(o._weights(P, ks, y, sigma))
+        for t, pkey in enumerate(P.pslots):
+            acc = np.zeros(ks.size)
+            for a, vkey in enumerate(P.vslots):
+                acc += np.abs(w[o._index(P, vkey, ks)]) * np.max(np.abs(tay.h[:, a, nv + t]))
+            np.add.at(out, o._index(P, pkey, ks), wt * acc)
+    return out

@@ -368,3 +368,31 @@ def test_c_program_against_the_header(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.startswith("ok 1 "), out.stdout
+
+
+def test_batch_create_checks_pattern_signature_before_device():
+    """Instances share code only when they agree on every tree and on which
+    patterns are empty: a constraint pattern empty in model 0 but not in
+    model 1 is a different formulation (EXA_EINVAL), checked before the
+    device requirement (host-only models then give EXA_ESTATE)."""
+    import ctypes as C
+    from paper_2608_16265_amd import ExaModel, _lib
+
+    def model(n_extra):
+        m = Model("sig")
+        x = m.add_var(4)
+        d = DataSet(3, i=np.arange(3))
+        m.add_con(x[d.i] * x[d.i + 1], d)
+        e = DataSet(n_extra, i=np.arange(n_extra))
+        m.add_con(exp(x[e.i]), e)
+        m.add_obj(x[d.i] ** 2, d)
+        return m
+    a, b, c = (ExaModel(model(k), host_only=True) for k in (0, 2, 0))
+    opt = _lib.BatchOptions(0, 256, 4, 1, 1, 1, 1, 0)
+    out = C.c_void_p()
+    for pair, want in (((a, b), _lib.EXA_EINVAL), ((b, a), _lib.EXA_EINVAL), ((a, c), _lib.EXA_ESTATE)):
+        arr = (C.c_void_p * 2)(*[m.handle.value for m in pair])
+        assert _lib.LIB.exa_batch_create(arr, 2, C.byref(opt), C.byref(out)) == want
+    arr = (C.c_void_p * 2)(a.handle.value, b.handle.value)
+    assert _lib.LIB.exa_batch_create(arr, 2, C.byref(opt), C.byref(out)) == _lib.EXA_EINVAL
+    assert b"pattern trees" in _lib.LIB.exa_last_error()

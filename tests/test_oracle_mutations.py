@@ -81,3 +81,60 @@ def test_missing_cross_pairs_are_caught(monkeypatch):
 def test_wrong_linear_classification_is_caught(monkeypatch):
     monkeypatch.setattr(rules, "_UNARY_AFFINE", {"neg", "sin", "cos"})
     assert check_coverage(acopf(30, 0)) > 0.0
+
+
+def test_dropped_row_offset_is_caught(monkeypatch):
+    """An augmentation row without its offset (icol[k] instead of
+    icol[k] + row_off) must fail the closed-form pin."""
+    from oracle.nlp import OracleModel
+    from test_oracle_pins import aug_offset_case
+    from oracle_checks import check_aug_offset
+
+    def rows_without_offset(self, P, ks):
+        if P.kind == "con":
+            return P.o0 + ks
+        return P.target_o0 + P.icols[P.row_col][ks].astype(np.int64)
+    assert check_aug_offset(aug_offset_case()) < 1e-15
+    monkeypatch.setattr(OracleModel, "_rows", rows_without_offset)
+    assert check_aug_offset(aug_offset_case()) > 1e-3
+
+
+@pytest.mark.parametrize("kind", ["neighbour_row", "sigma_for_all", "no_weight"])
+def test_hessian_weight_mistake_is_caught(monkeypatch, kind):
+    """A wrong Hessian weight in hess_block (y of another row, sigma for a
+    constraint, no weight at all) must fail a closed-form pin."""
+    from oracle.nlp import OracleModel
+    from test_oracle_pins import aug_offset_case
+    from oracle_checks import check_aug_offset
+    orig = OracleModel._weights
+
+    def bad(self, P, ks, y, sigma, dtype=np.float64):
+        w = orig(self, P, ks, y, sigma, dtype)
+        if P.kind == "obj":
+            return w
+        if kind == "neighbour_row":
+            return np.asarray(y, dtype=dtype)[(self._rows(P, ks) + 1) % len(y)]
+        if kind == "sigma_for_all":
+            return np.full(ks.size, sigma, dtype=dtype)
+        return np.ones(ks.size, dtype=dtype)
+    monkeypatch.setattr(OracleModel, "_weights", bad)
+    assert check_aug_offset(aug_offset_case()) > 1e-3
+
+
+def test_dropped_alias_doubling_is_caught(monkeypatch):
+    """hess_block without the doubling of a cross pair that resolves to a
+    diagonal position must fail the aliasing pin (duplicates summing to the
+    true Hessian)."""
+    import test_oracle_pins
+    from oracle.nlp import OracleModel
+
+    def no_doubling(self, i, ks, x, y, sigma=1.0, theta=None, dtype=np.float64):
+        P = self.pats[i]
+        ks = np.asarray(ks, dtype=np.int64)
+        t = self._taylor(P, ks, x, self._theta(theta), dtype=dtype)
+        w = self._weights(P, ks, y, sigma, dtype)
+        return np.stack([w * t.h[:, a, b] for a, b in P.hslots], axis=1) if P.hslots else \
+            np.zeros((ks.size, 0), dtype=dtype)
+    monkeypatch.setattr(OracleModel, "hess_block", no_doubling)
+    with pytest.raises(AssertionError):
+        test_oracle_pins.test_aliased_references_sum_to_true_hessian()

@@ -9,7 +9,7 @@ import pytest
 from exa_modeling import DataSet, Model, cos, sin, exp
 from exa_modeling.generators import Workload, acopf, goddard, kernel_sweep, pde, rosenbrock, two_stage
 from oracle import OracleModel, rules
-from oracle_checks import check_coverage, check_first_order, check_second_order
+from oracle_checks import check_aug_offset, check_coverage, check_first_order, check_second_order
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
 
@@ -300,3 +300,93 @@ def test_products_match_dense():
     assert np.allclose(o.jprod(w.x, v), J @ v, rtol=1e-14, atol=1e-12)
     assert np.allclose(o.hprod(w.x, w.y, 0.8, v), H @ v, rtol=1e-14, atol=1e-12)
     assert np.allclose(H, H.T)
+
+
+# ------------------------------------------------- augmentation row offsets
+def aug_offset_case(seed=12):
+    """Augmentations whose row is an index column plus a nonzero offset
+    (eq. simd:con, Sec. 3.3.2), added to a base block that is not the first,
+    so that the target block's first row, the index column and the offset
+    all enter the row: c_k sin(x_j) x_m into row bus_k + 2 of block B and
+    exp(x_j) into row bus_k - 1 of block B."""
+    rng = np.random.default_rng(seed)
+    m = Model("augoff")
+    n = 12
+    x = m.add_var(n)
+    a = DataSet(3, i=np.arange(3))
+    m.add_con(x[a.i] * x[a.i + 1], a)               # block A: rows 0..2
+    r = DataSet(8, r=np.arange(8))
+    blk = m.add_con(x[r.r] ** 2, r)                  # block B: rows 3..10
+    K = 10
+    j = rng.integers(0, n, K)
+    mm = (j + 1 + rng.integers(0, n - 1, K)) % n    # never equal to j
+    d1 = dict(bus=rng.integers(0, 6, K), j=j, m=mm, c=rng.uniform(0.5, 2.0, K))
+    d = DataSet(K, **d1)
+    m.add_con_aug(blk, d.bus + 2, d.c * sin(x[d.j]) * x[d.m], d)
+    d2 = dict(bus=rng.integers(1, 9, 6), j=rng.integers(0, n, 6))
+    e = DataSet(6, **d2)
+    m.add_con_aug(blk, e.bus - 1, exp(x[e.j]), e)
+    xv = rng.uniform(-1.0, 1.0, n)
+    return Workload(m, xv, rng.standard_normal(m.ncon), 0.9, dict(aug1=d1, aug2=d2))
+
+
+def test_aug_row_offset_closed_form():
+    wl = aug_offset_case()
+    assert [p.row_off for p in wl.model.patterns[2:]] == [2, -1]
+    assert check_aug_offset(wl) < 1e-15
+
+
+def test_aug_row_offset_first_and_second_order():
+    wl = aug_offset_case()
+    assert check_first_order(wl) < 1e-13
+    assert check_second_order(wl) < 1e-6
+
+
+# --------------------------------------- sampled blocks = the full arrays
+@pytest.mark.parametrize("name", ["acopf30", "pde8", "alias", "augoff", "goddard6"])
+def test_blocks_equal_coord_slices(name):
+    """jac_block / hess_block (used to check sampled points of large
+    models) give, at every data point, exactly the entries of jac_coord /
+    hess_coord, which the closed forms, complex step and FD pin."""
+    def alias():
+        m = Model()
+        x = m.add_var(3)
+        d = DataSet(3, i=np.array([0, 1, 2]), j=np.array([0, 2, 2]))
+        m.add_obj(exp(x[d.i] * x[d.j]), d)
+        m.add_con(sin(x[d.i]) * x[d.j], d)
+        return Workload(m, np.array([0.3, -0.2, 0.5]), np.array([0.7, -1.1, 0.4]), 1.3)
+    wl = {"acopf30": lambda: acopf(30, 0), "pde8": lambda: pde(8, 3), "alias": alias,
+          "augoff": aug_offset_case, "goddard6": lambda: goddard(6, 2)}[name]()
+    o = OracleModel(wl.model)
+    J = o.jac_coord(wl.x)
+    H = o.hess_coord(wl.x, wl.y, wl.sigma)
+    for i, P in enumerate(o.pats):
+        ks = np.arange(P.ndata)[::-1]       # any order of points
+        if P.kind != "obj" and P.vslots:
+            st = len(P.vslots)
+            blk = o.jac_block(i, ks, wl.x)
+            assert np.array_equal(blk, J[P.o1:P.o1 + P.ndata * st].reshape(P.ndata, st)[ks])
+        if P.hslots:
+            st = len(P.hslots)
+            blk = o.hess_block(i, ks, wl.x, wl.y, wl.sigma)
+            assert np.array_equal(blk, H[P.o2:P.o2 + P.ndata * st].reshape(P.ndata, st)[ks])
+
+
+# --------------------------------------------- extended-precision reference
+def test_longdouble_reference_agrees():
+    """The oracle evaluated in x87 extended precision (64-bit significand)
+    is the reference for reporting true errors; in float64 it must agree
+    with it to the parity tolerance on the 30-bus model."""
+    from parity_util import column_scale
+    assert np.finfo(np.longdouble).nmant >= 63
+    wl = acopf(30, 0)
+    o = OracleModel(wl.model)
+    ld = np.longdouble
+    for f, order in ((lambda d: o.jac_coord(wl.x, dtype=d), 1),
+                     (lambda d: o.hess_coord(wl.x, wl.y, 1.0, dtype=d), 2)):
+        a, b = f(np.float64), f(ld)
+        assert b.dtype == ld
+        sc = column_scale(o, a, order)
+        err = np.abs(a.astype(ld) - b)
+        assert np.all(err <= 1e-12 * np.maximum(np.abs(b), sc))
+        assert np.any(err > 0)            # the two precisions really differ

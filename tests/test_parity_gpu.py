@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 from exa_modeling import DataSet, Model, exp, sin
 from exa_modeling.generators import Workload, acopf, goddard, kernel_sweep, pde, rosenbrock, two_stage
 from oracle import OracleModel
-from parity_util import RTOL, abs_oracle, assert_close, column_scale, dev, host
+from parity_util import RTOL, abs_oracle, adjoint_scale, assert_close, column_scale, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +77,11 @@ def _zoo():
     return op_zoo()
 
 
+def _augoff():
+    from test_oracle_pins import aug_offset_case
+    return aug_offset_case()
+
+
 CASES = {
     "rosen5": lambda: rosenbrock(5, 1),
     "rosen3000": lambda: rosenbrock(3000, 2),
@@ -93,6 +98,7 @@ CASES = {
     "goddard": lambda: goddard(60, 1),         # dt shared by every point; division, exp, squares
     "sweep16": lambda: kernel_sweep(16, 200, 2),  # sixteen distinct patterns
     "zoo": _zoo,
+    "aug_offset": _augoff,       # augmentation rows = index column + nonzero offset
     "alias": aliasing_case,
     "empty": empty_pattern_case,
     "single": single_point_case,
@@ -138,7 +144,7 @@ def check_all(w, em=None, o=None, tag=""):
     if o.ntheta:
         ref = o.adjoint_theta(x, y, sig, wx)
         got = host(em.adjoint_theta(X, Y, sig, WX))
-        assert_close(tag + "adjoint", got, ref, np.max(np.abs(ref)) if ref.size else 0.0)
+        assert_close(tag + "adjoint", got, ref, adjoint_scale(o, x, y, sig, wx))
     return em, o
 
 
