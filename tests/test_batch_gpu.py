@@ -94,7 +94,7 @@ def test_every_callback_bitwise_equal_to_plain(family, autotune, block, epl, fus
         b.evaluate(X, Y, sigma, V, W, **outs)
         _check_against_plain(b, ems, X, Y, V, W, WX, sigma, outs, tag=f"{family} rep {rep}")
     # single callbacks and other selections
-    for sel in (("jac",), ("hess",), ("jac", "hess"), ("obj",), ("grad", "cons"), ("hv",), ("jtw", "jv")):
+    for sel in (("jac",), ("hess",), ("jac", "hess"), ("f",), ("g", "c"), ("hv",), ("jtw", "jv")):
         sub = {k: _nan(b, ALL8[k]) for k in sel}
         b.evaluate(X, Y, sigma, V, W, **sub)
         _check_against_plain(b, ems, X, Y, V, W, WX, sigma, sub, tag=f"{family} {sel}")
