@@ -239,6 +239,24 @@ exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jt
 /* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod). */
 exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight,
                      const double* v, double* Hv, exa_stream_t stream);
+/* exa_hprod for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels in the same order, so Hv is bit-identical to exa_hprod's,
+ * but the H v work buffer and the part sums of long segments live in a
+ * fixed library array of 4,194,304 doubles (32 MiB) that each GPU the
+ * library runs on holds until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine) and never tunes: it
+ * runs hprod's schedule as it stands (the model's default, or the tuned one
+ * after an autotuned exa_hprod call).  Nothing in the array needs to start
+ * at zero (every entry read was written by the same call).  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other host threads, other
+ * models) race.  Arguments as exa_hprod.  Errors: EXA_EINVAL for a NULL
+ * pointer a nonzero size needs, a model whose H v work space exceeds the
+ * array (hv entries plus part sums; use exa_hprod), or a model on another
+ * device than the current one; EXA_ESTATE for a host-only model; EXA_EHIP. */
+exa_status exa_hprod_noalloc(exa_model* m, const double* x, const double* y, double obj_weight,
+                             const double* v, double* Hv, exa_stream_t stream);
 /* Gradient of the Lagrangian of eq. nlp, sigma grad f(x) + J(x)^T y, into
  * out [nvar]; x [nvar] and y [ncon] are device arrays, sigma = obj_weight
  * (the first-order half of what hess_coord weights, Sec. 2.1.3).  One

@@ -106,6 +106,7 @@ def _load():
         "exa_jac_hess_coord": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_jtprod": (C.c_int32, [vp, vp, vp, vp, vp]),
         "exa_hprod": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
+        "exa_hprod_noalloc": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp, vp]),
         "exa_lag_grad": (C.c_int32, [vp, vp, vp, C.c_double, vp, vp]),
         "exa_csc_dims": (C.c_int32, [vp, C.c_int32, vp]),
         "exa_csc_structure": (C.c_int32, [vp, C.c_int32, vp, vp]),
@@ -156,6 +157,7 @@ def exported_symbols():
     return ["exa_last_error", "exa_version", "exa_create", "exa_destroy", "exa_dims", "exa_bounds",
             "exa_set_theta", "exa_jac_structure", "exa_hess_structure", "exa_obj", "exa_obj_host", "exa_grad",
             "exa_cons", "exa_jac_coord", "exa_hess_coord", "exa_jac_hess_coord", "exa_jprod", "exa_jtprod", "exa_hprod",
+            "exa_hprod_noalloc",
             "exa_lag_grad", "exa_csc_dims", "exa_csc_structure", "exa_csc_values",
             "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_set_schedule", "exa_eval_bytes", "exa_eval_timing", "exa_device_copy",
             "exa_eval_timing_read", "exa_counters", "exa_generated_source", "exa_compile_check",

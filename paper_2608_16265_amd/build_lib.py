@@ -15,7 +15,8 @@ OUT = os.path.join(HERE, "libexa.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["exa_model.cpp", "exa_codegen.cpp", "exa_runtime.cpp", "exa_batch.cpp", "exa_kernels.hip"]
+SOURCES = ["exa_model.cpp", "exa_codegen.cpp", "exa_runtime.cpp", "exa_batch.cpp", "exa_kernels.hip",
+           "exa_noalloc.hip"]
 # packed FP32 instructions are kept out of every device compile
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]

@@ -482,6 +482,8 @@ void launch_mode(Model& M, int mode, ExaCall call, hipStream_t s) {
     raw_launch(M, mode, call, s);
 }
 
+void launch_mode_untuned(Model& M, int mode, ExaCall call, hipStream_t s) { raw_launch(M, mode, call, s); }
+
 // ---- several callbacks in one launch (exa_eval) ----------------------------
 
 // Modes of an exa_eval mask; with jh, Jacobian and Hessian together run as
@@ -835,6 +837,8 @@ Model::Model() {
     for (auto& c : counters) c.store(0);
 }
 Model::~Model() = default;
+Model& live_model(exa_model* m) { return live(m); }
+exa_status guard_status(const std::function<void()>& f) { return guard(f); }
 }  // namespace exa
 
 namespace {

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -88,6 +89,16 @@ struct DeviceState {
 };
 
 void hip_check(hipError_t e, const char* what);
+// The model's own checks of a live (device) model, for entry points in other
+// source files: EXA_EINVAL / EXA_ESTATE as the callbacks raise them.
+Model& live_model(exa_model* m);
+// One callback's evaluation launch under its current schedule (no tuning,
+// no allocation).
+void launch_mode_untuned(Model& M, int mode, ExaCall call, hipStream_t s);
+// The segment sums of a map from `buf` into `out` (one reduction launch,
+// plus one for long segments).
+void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s);
+exa_status guard_status(const std::function<void()>& f);
 // Tiles that write zeros to the gradient entries no objective term touches.
 void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles);
 bool has_fusable_group(const Model& M, int mode);
