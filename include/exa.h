@@ -31,6 +31,11 @@
  *     HIP runtime after launch is reported as EXA_EHIP.  The text of the
  *     last error of the calling thread is returned by exa_last_error().
  *     A failed call leaves the model valid.
+ *   - Environment: EXA_LOG=1 writes one line per model build, tuning
+ *     decision and cache event to stderr; EXA_CACHE_DIR sets the default
+ *     code-object cache (exa_options.cache_dir); EXA_TEST_BAD_SOURCE=1
+ *     appends a line that does not compile to every generated source (a
+ *     test hook for the EXA_ECOMPILE path).
  *   - Concurrent callbacks on ONE model from different streams race on the
  *     model's internal work buffers; serialize them (one stream per model).
  *     Calls on one model from several host threads must not overlap either
@@ -142,6 +147,21 @@ typedef struct exa_options {
                           from one pass over its loads (chosen by autotune,
                           used by default without it); results are the same  */
     int32_t reserved[2];
+    const char* cache_dir; /* directory of the on-disk code-object cache (NULL
+                          or "": the environment variable EXA_CACHE_DIR, else
+                          no cache).  The compiled code of a pattern set is
+                          stored there under a key hashing the generated
+                          source, the compile options and the hiprtc version,
+                          beside the source itself; a later process whose
+                          generated source is byte-identical loads it instead
+                          of compiling (Sec. 8.6: compilation is paid once per
+                          pattern set).  Unreadable or unwritable caches only
+                          cost the compilation.                              */
+    int64_t max_device_bytes; /* device memory budget of the model (0: none):
+                          exa_create fails with EXA_ENOMEM when the footprint
+                          estimated after the host analysis (see
+                          exa_device_bytes) exceeds it, or when an allocation
+                          would take the model past it                     */
 } exa_options;
 
 /* ---- Library ------------------------------------------------------------ */
@@ -433,6 +453,17 @@ exa_status exa_schedule(const exa_model* m, int32_t callback, int64_t* out4);
  * objective), o2 (first Hessian entry) -- the SIMDFunction offsets and strides
  * of Sec. 3.4, 0-based. */
 exa_status exa_pattern_info(const exa_model* m, int32_t p, int64_t* out8);
+
+/* Device memory of a model in bytes: what it holds (device models) or the
+ * footprint estimated from the host analysis (host-only models: data
+ * columns, tables, work buffers, reduction maps), into *bytes. */
+exa_status exa_device_bytes(const exa_model* m, int64_t* bytes);
+/* Build statistics of a model (Sec. 8.6 compilation study), host array
+ * out6 = {host analysis ms, code generation ms, compilation ms (or cache
+ * read), origin of the code object (0 compiled, 1 read from the on-disk
+ * cache, 2 shared with a live model of the same pattern set, -1 host-only),
+ * device bytes (as exa_device_bytes), 1 when a cache directory is in use}. */
+exa_status exa_build_info(const exa_model* m, double* out6);
 
 /* Callback counters (Sec. 3.2 NLPModels.Counters): out[0..8] = obj, grad,
  * cons, jac, hess, jprod, jtprod, hprod, adjoint. */

@@ -39,7 +39,7 @@ class PatternDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("block", C.c_int32), ("epl", C.c_int32),
                 ("autotune", C.c_int32), ("fuse", C.c_int32), ("eval_per_mode", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("reserved", C.c_int32 * 2), ("cache_dir", C.c_char_p), ("max_device_bytes", C.c_int64)]
 
 
 class BatchOptions(C.Structure):
@@ -120,6 +120,8 @@ def _load():
         "exa_eval_timing": (C.c_int32, [vp, C.c_int32]),
         "exa_eval_timing_read": (C.c_int32, [vp, P_f64]),
         "exa_counters": (C.c_int32, [vp, P_i64]),
+        "exa_device_bytes": (C.c_int32, [vp, P_i64]),
+        "exa_build_info": (C.c_int32, [vp, P_f64]),
         "exa_generated_source": (C.c_int32, [vp, C.c_char_p, C.c_int64, P_i64]),
         "exa_compile_check": (C.c_int32, [vp]),
         "exa_pattern_info": (C.c_int32, [vp, C.c_int32, P_i64]),
@@ -160,7 +162,8 @@ def exported_symbols():
             "exa_hprod_noalloc",
             "exa_lag_grad", "exa_csc_dims", "exa_csc_structure", "exa_csc_values",
             "exa_adjoint_theta", "exa_eval", "exa_eval_schedule", "exa_eval_set_schedule", "exa_eval_bytes", "exa_eval_timing", "exa_device_copy",
-            "exa_eval_timing_read", "exa_counters", "exa_generated_source", "exa_compile_check",
+            "exa_eval_timing_read", "exa_counters", "exa_device_bytes", "exa_build_info",
+            "exa_generated_source", "exa_compile_check",
             "exa_pattern_info", "exa_kernel_bytes", "exa_schedule", "exa_batch_create", "exa_batch_destroy",
             "exa_batch_offsets", "exa_batch_set_theta", "exa_batch_eval", "exa_batch_schedule",
             "exa_batch_set_schedule", "exa_batch_bytes", "exa_batch_timing", "exa_batch_timing_read"]

@@ -581,6 +581,11 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
     set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units);
     b.sched[mask].tuned_ns = (int64_t)(w.ms * 1e6);
+    if (log_on())
+        log_msg("tuned batch of " + std::to_string(b.B) + " mask " + std::to_string(mask) + ": block " +
+                std::to_string(w.block) + ", points per lane " + std::to_string(w.epl) + ", fused " +
+                std::to_string(w.fused) + ", units " + std::to_string(w.units) + " (" + std::to_string(w.ms * 1e3) +
+                " us)");
 }
 
 void check_mask(uint32_t mask) {

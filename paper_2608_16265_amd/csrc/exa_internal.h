@@ -262,6 +262,13 @@ struct Model {
     bool autotune = false, fuse = false;
     bool eval_per_mode = false;  // exa_eval: per-callback tiles only
     std::string signature;   // hash of the simplified trees (shared code)
+    std::string cache_dir;   // code-object cache directory ("" : none)
+    int64_t max_device_bytes = 0;  // device memory budget (0: none)
+    // build statistics: host analysis, code generation and compilation (or
+    // cache read) in milliseconds; whether the code object came from the
+    // on-disk cache; whether it was shared with a live model
+    double host_ms = 0, codegen_ms = 0, compile_ms = 0;
+    bool cache_hit = false, module_shared = false;
     // inputs each generated unit really reads, per (mode, unit code)
     std::map<std::pair<int, int>, UnitLive> live;
     std::atomic<int64_t> counters[9];
@@ -300,6 +307,9 @@ std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLi
 constexpr int kObjBlock = 256, kObjEpl = 8;
 constexpr bool kObjFused = true;
 void build_device(Model& M);
+// Device memory a model needs (data columns, tables, work buffers, maps),
+// estimated from the host analysis before anything is allocated.
+int64_t estimate_device_bytes(const Model& M);
 
 }  // namespace exa
 

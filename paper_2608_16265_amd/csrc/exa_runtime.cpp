@@ -3,8 +3,13 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <chrono>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -49,17 +54,35 @@ std::string hex_hash(const std::string& s) {
 }
 }  // namespace
 
-std::vector<char> compile_code(const std::string& src) {
+// The options every generated source is compiled with.  -ffp-contract=off:
+// every multiply and add is rounded on its own, so a data point's result does
+// not depend on how its code was scheduled or fused with other patterns
+// (bitwise-equal batched and plain results).
+const char* const kCompileOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+
+bool log_on() {
+    static const bool on = [] {
+        const char* e = std::getenv("EXA_LOG");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+
+void log_msg(const std::string& msg) {
+    if (log_on()) std::fprintf(stderr, "[exa] %s\n", msg.c_str());
+}
+
+std::vector<char> compile_code(const std::string& src_in) {
+    // test hook: a source that cannot compile, to exercise EXA_ECOMPILE
+    const char* bad = std::getenv("EXA_TEST_BAD_SOURCE");
+    const std::string src =
+        (bad && *bad && std::strcmp(bad, "0") != 0) ? src_in + "\nthis line does not compile;\n" : src_in;
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "exa_generated.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         fail(EXA_ECOMPILE, "hiprtcCreateProgram failed");
-    // -ffp-contract=off: every multiply and add is rounded on its own, so a
-    // data point's result does not depend on how its code was scheduled or
-    // fused with other patterns (bitwise-equal batched and plain results)
-    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof kCompileOpts / sizeof kCompileOpts[0]), kCompileOpts);
     size_t logsz = 0;
     hiprtcGetProgramLogSize(prog, &logsz);
     std::string log(logsz, '\0');
@@ -76,7 +99,77 @@ std::vector<char> compile_code(const std::string& src) {
     return code;
 }
 
-std::shared_ptr<Module> compile_module(const std::string& src) {
+namespace {
+// ---- on-disk code-object cache --------------------------------------------
+// A compiled module is stored as <dir>/exa-<key>.hsaco next to its source
+// <dir>/exa-<key>.hip, where key hashes the generated source, the compile
+// options and the hiprtc version.  A hit needs the stored source to equal
+// the generated one byte for byte, so a hash collision cannot load the wrong
+// code.  Files are written under a temporary name and renamed into place, so
+// concurrent processes see whole files or none.  Cache errors are not fatal:
+// the source is compiled as without a cache.
+std::string cache_key(const std::string& src) {
+    int maj = 0, min = 0;
+    hiprtcVersion(&maj, &min);
+    std::string k = src + "|hiprtc " + std::to_string(maj) + "." + std::to_string(min) + "|";
+    for (const char* o : kCompileOpts) k += std::string(o) + " ";
+    return hex_hash(k) + "-" + std::to_string(src.size());
+}
+
+bool read_file(const std::string& path, std::string& out) {
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (!f) return false;
+    std::string s;
+    char buf[1 << 16];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+    const bool ok = !std::ferror(f);
+    std::fclose(f);
+    if (ok) out.swap(s);
+    return ok;
+}
+
+bool write_file_atomic(const std::string& path, const char* data, size_t n) {
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    const bool ok = std::fwrite(data, 1, n, f) == n;
+    if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), path.c_str()) != 0) {
+        std::remove(tmp.c_str());
+        return false;
+    }
+    return true;
+}
+}  // namespace
+
+std::vector<char> cached_code(const std::string& src, const std::string& dir, bool* hit) {
+    if (hit) *hit = false;
+    if (dir.empty()) return compile_code(src);
+    const std::string base = dir + "/exa-" + cache_key(src);
+    std::string stored, code;
+    if (read_file(base + ".hip", stored) && stored == src && read_file(base + ".hsaco", code) && !code.empty()) {
+        if (hit) *hit = true;
+        log_msg("code-object cache hit: " + base + ".hsaco");
+        return std::vector<char>(code.begin(), code.end());
+    }
+    std::vector<char> out = compile_code(src);
+    // the code object first, then the source that validates it
+    if (write_file_atomic(base + ".hsaco", out.data(), out.size()) &&
+        write_file_atomic(base + ".hip", src.data(), src.size()))
+        log_msg("code-object cache write: " + base + ".hsaco");
+    else
+        log_msg("code-object cache: cannot write under " + dir + " (compiled without caching)");
+    return out;
+}
+
+std::string cache_dir_of(const char* opt_dir) {
+    if (opt_dir && *opt_dir) return opt_dir;
+    const char* e = std::getenv("EXA_CACHE_DIR");
+    return (e && *e) ? e : "";
+}
+
+std::shared_ptr<Module> compile_module(const std::string& src, const std::string& cache_dir, bool* cache_hit) {
+    if (cache_hit) *cache_hit = false;
     const std::string key = hex_hash(src) + ":" + std::to_string(src.size());
     std::lock_guard<std::mutex> lk(g_mod_mu);
     auto it = g_mods.find(key);
@@ -85,7 +178,7 @@ std::shared_ptr<Module> compile_module(const std::string& src) {
             if (m->source == src) return m;
     auto m = std::make_shared<Module>();
     m->source = src;
-    m->code = compile_code(src);
+    m->code = cached_code(src, cache_dir, cache_hit);
     hip_check(hipModuleLoadData(&m->mod, m->code.data()), "hipModuleLoadData");
     for (int mode = 0; mode < M_COUNT; ++mode) {
         hipFunction_t f = nullptr;
@@ -117,10 +210,15 @@ void DeviceState::timing_off() {
 
 void* DeviceState::alloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
+    if (budget > 0 && allocated + (int64_t)bytes > budget)
+        fail(EXA_ENOMEM, "device memory budget of " + std::to_string(budget) + " bytes exceeded (" +
+                             std::to_string(allocated) + " allocated, " + std::to_string(bytes) + " more asked)");
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) fail(EXA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     allocs.push_back(p);
+    sizes.push_back((int64_t)bytes);
+    allocated += (int64_t)bytes;
     return p;
 }
 
@@ -135,6 +233,9 @@ void DeviceState::release(void* p) {
     auto it = std::find(allocs.begin(), allocs.end(), p);
     if (it != allocs.end()) {
         (void)hipFree(p);
+        const size_t i = (size_t)(it - allocs.begin());
+        allocated -= sizes[i];
+        sizes.erase(sizes.begin() + i);
         allocs.erase(it);
     }
 }
@@ -191,14 +292,52 @@ void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
     }
 }
 
+int64_t estimate_device_bytes(const Model& M) {
+    int64_t b = 0;
+    for (const Group& G : M.groups) {
+        const Pattern& P = M.pats[G.members[0]];
+        b += P.ndata * (4 * (int64_t)P.n_icols + 8 * (int64_t)P.n_fcols);
+    }
+    for (const Pattern& P : M.pats)
+        if (P.kind == EXA_AUG) b += 4 * (int64_t)(P.rptr.size() + P.ridx.size());
+    b += 8 * M.ntheta + (int64_t)sizeof(ExaInstDev);
+    for (int mode = 0; mode < M_COUNT; ++mode) {
+        const bool fixed = mode == M_OBJ;
+        const int64_t tp = fixed ? (int64_t)kObjBlock * kObjEpl : (int64_t)M.block * M.epl;
+        b += (int64_t)sizeof(ExaTile) * (int64_t)make_tiles(M, mode, 0, tp, fixed ? kObjFused : M.fuse).size();
+    }
+    const int64_t nobj = (int64_t)make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused).size();
+    b += 8 * (M.fo_obj_len + M.fo_con_len + M.par_len + M.hv_len + std::max<int64_t>(1, nobj) + M.nvar + 1);
+    // maps: pointers and positions, plus at most a 24-byte record per four
+    // entries (chunked sums, with padding) and part sums
+    for (const SegMap* S : {&M.grad_map, &M.jt_map, &M.h_map, &M.par_map}) {
+        const int64_t nnz = (int64_t)S->idx.size();
+        b += 8 * (S->nseg() + 1) + 8 * nnz + 8 * nnz + 24 * 256 + 8 * (nnz / kExaLongSeg + 1);
+    }
+    return b;
+}
+
 void build_device(Model& M) {
     int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
     M.dev.reset(new DeviceState());
     DeviceState& D = *M.dev;
     D.device = dev;
+    D.budget = M.max_device_bytes;
+    auto t0 = std::chrono::steady_clock::now();
     const std::string src = generate_source(M, &M.live);
-    D.module = compile_module(src);
+    auto t1 = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(g_mod_mu);
+        M.module_shared = false;
+        auto it = g_mods.find(hex_hash(src) + ":" + std::to_string(src.size()));
+        if (it != g_mods.end())
+            if (auto m = it->second.lock()) M.module_shared = m->source == src;
+    }
+    D.module = compile_module(src, M.cache_dir, &M.cache_hit);
+    auto t2 = std::chrono::steady_clock::now();
+    M.codegen_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    M.compile_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
 
     D.theta = (double*)D.upload(M.theta.data(), M.theta.size() * sizeof(double));
     ExaInstDev inst;
@@ -474,6 +613,10 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
     set_schedule(M, mode, w.block, w.epl, w.fused != 0);
     M.dev->sched[mode].tuned = true;
+    if (log_on())
+        log_msg("tuned " + kernel_name(mode) + ": block " + std::to_string(w.block) + ", points per lane " +
+                std::to_string(w.epl) + ", fused " + std::to_string(w.fused) + " (" + std::to_string(w.ms * 1e3) +
+                " us)");
 }
 }  // namespace
 
@@ -655,6 +798,10 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
     set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb);
+    if (log_on())
+        log_msg("tuned exa_eval mask " + std::to_string(mask) + ": block " + std::to_string(w.block) +
+                ", points per lane " + std::to_string(w.epl) + ", fused " + std::to_string(w.fused) + ", units " +
+                std::to_string(w.comb) + " (" + std::to_string(w.ms * 1e3) + " us)");
 }
 
 }  // namespace
@@ -879,12 +1026,35 @@ exa_status exa_create(const exa_pattern_desc* pats, int32_t npats, int64_t nvar,
             M.autotune = opt->autotune != 0;
             M.fuse = opt->fuse != 0;
             M.eval_per_mode = opt->eval_per_mode != 0;
+            M.max_device_bytes = opt->max_device_bytes;
         }
+        M.cache_dir = cache_dir_of(opt ? opt->cache_dir : nullptr);
+        if (M.max_device_bytes < 0) fail(EXA_EINVAL, "max_device_bytes must be >= 0");
         if (M.block != 64 && M.block != 128 && M.block != 256)
             fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (M.epl < 1 || M.epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
+        auto t0 = std::chrono::steady_clock::now();
         build_host(M, pats, npats);
+        M.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (M.max_device_bytes > 0) {
+            const int64_t need = estimate_device_bytes(M);
+            if (need > M.max_device_bytes)
+                fail(EXA_ENOMEM, "the model needs about " + std::to_string(need) +
+                                     " bytes of device memory, more than its budget of " +
+                                     std::to_string(M.max_device_bytes));
+        }
         if (!M.host_only) build_device(M);
+        if (log_on()) {
+            char buf[400];
+            std::snprintf(buf, sizeof buf,
+                          "create: %zu patterns, nvar %lld, ncon %lld, nnzj %lld, nnzh %lld; host %.1f ms, codegen "
+                          "%.1f ms, compile %.1f ms (%s); device bytes %lld",
+                          M.pats.size(), (long long)M.nvar, (long long)M.ncon, (long long)M.nnzj, (long long)M.nnzh,
+                          M.host_ms, M.codegen_ms, M.compile_ms,
+                          M.host_only ? "host only" : M.module_shared ? "shared module" : M.cache_hit ? "cache hit" : "compiled",
+                          (long long)(M.dev ? M.dev->allocated : estimate_device_bytes(M)));
+            log_msg(buf);
+        }
         *out = h.release();
     });
 }
@@ -1505,7 +1675,28 @@ exa_status exa_generated_source(const exa_model* m, char* buf, int64_t cap, int6
 exa_status exa_compile_check(const exa_model* m) {
     return guard([&] {
         if (!m) fail(EXA_EINVAL, "null model");
-        (void)compile_code(generate_source(m->impl));
+        bool hit = false;
+        (void)cached_code(generate_source(m->impl), m->impl.cache_dir, &hit);
+    });
+}
+
+exa_status exa_device_bytes(const exa_model* m, int64_t* bytes) {
+    return guard([&] {
+        if (!m || !bytes) fail(EXA_EINVAL, "null argument");
+        *bytes = m->impl.dev ? m->impl.dev->allocated : estimate_device_bytes(m->impl);
+    });
+}
+
+exa_status exa_build_info(const exa_model* m, double* out6) {
+    return guard([&] {
+        if (!m || !out6) fail(EXA_EINVAL, "null argument");
+        const Model& M = m->impl;
+        out6[0] = M.host_ms;
+        out6[1] = M.codegen_ms;
+        out6[2] = M.compile_ms;
+        out6[3] = M.host_only ? -1.0 : M.module_shared ? 2.0 : M.cache_hit ? 1.0 : 0.0;
+        out6[4] = (double)(M.dev ? M.dev->allocated : estimate_device_bytes(M));
+        out6[5] = M.cache_dir.empty() ? 0.0 : 1.0;
     });
 }
 

@@ -43,6 +43,9 @@ struct DeviceState {
     int device = 0;
     std::shared_ptr<Module> module;
     std::vector<void*> allocs;
+    std::vector<int64_t> sizes;       // bytes of each allocation
+    int64_t allocated = 0;            // bytes allocated now
+    int64_t budget = 0;               // 0: no limit; else alloc fails past it (EXA_ENOMEM)
     double* theta = nullptr;
     ExaInstDev* inst = nullptr;       // device copy of the single-instance table
     ExaInstDev inst_host;             // host copy (device pointers), reused by batches
@@ -115,7 +118,15 @@ std::vector<int> launch_modes(uint32_t mask, int units);
 // outputs, objective partials when there are several).
 void reduce_bytes(const Model& M, uint32_t mask, int64_t& rd, int64_t& wr);
 std::vector<char> compile_code(const std::string& src);
-std::shared_ptr<Module> compile_module(const std::string& src);
+// The code object of a source through the on-disk cache in `dir` (empty: no
+// cache); *hit tells whether it was read from the cache.
+std::vector<char> cached_code(const std::string& src, const std::string& dir, bool* hit);
+// The cache directory: the option's, else $EXA_CACHE_DIR, else none.
+std::string cache_dir_of(const char* opt_dir);
+std::shared_ptr<Module> compile_module(const std::string& src, const std::string& cache_dir, bool* cache_hit);
+// One line to stderr when the environment variable EXA_LOG is set (not "0").
+bool log_on();
+void log_msg(const std::string& msg);
 std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused);
 std::string kernel_name(int mode);
 int mode_lds_doubles(const Model& M, int mode);

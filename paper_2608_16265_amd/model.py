@@ -93,7 +93,8 @@ class ExaModel:
     """A compiled model on the current HIP device (Sec. 3.2 ExaModel)."""
 
     def __init__(self, model, *, host_only: bool = False, block: int = 256, epl: int = 4,
-                 autotune: bool = False, fuse: bool = False, eval_per_mode: bool = False):
+                 autotune: bool = False, fuse: bool = False, eval_per_mode: bool = False,
+                 cache_dir: str = None, max_device_bytes: int = 0):
         self.description = model
         desc = _Descriptors(model)
         xl = np.ascontiguousarray(model.xl, dtype=np.float64)
@@ -101,6 +102,8 @@ class ExaModel:
         th = np.ascontiguousarray(model.theta, dtype=np.float64)
         opt = Options(1 if host_only else 0, block, epl, 1 if autotune else 0, 1 if fuse else 0,
                       1 if eval_per_mode else 0)
+        opt.cache_dir = cache_dir.encode() if cache_dir else None
+        opt.max_device_bytes = int(max_device_bytes)
         h = C.c_void_p()
         check(LIB.exa_create(desc.arr, desc.n, model.nvar, _ptr(xl, C.c_double), _ptr(xu, C.c_double),
                              model.ntheta, _ptr(th, C.c_double) if th.size else None,
@@ -176,6 +179,18 @@ class ExaModel:
         out = np.zeros(4, dtype=np.int64)
         check(LIB.exa_schedule(self._h, _lib.CALLBACKS.index(callback), _ptr(out, C.c_int64)))
         return dict(zip(["block", "points_per_lane", "fused", "tiles"], out.tolist()))
+
+    def device_bytes(self) -> int:
+        out = C.c_int64()
+        check(LIB.exa_device_bytes(self._h, C.byref(out)))
+        return out.value
+
+    def build_info(self) -> dict:
+        out = np.zeros(6, dtype=np.float64)
+        check(LIB.exa_build_info(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        origin = {-1: "host_only", 0: "compiled", 1: "cache", 2: "shared"}[int(out[3])]
+        return dict(host_ms=float(out[0]), codegen_ms=float(out[1]), compile_ms=float(out[2]), origin=origin,
+                    device_bytes=int(out[4]), cache=bool(out[5]))
 
     def counters(self):
         out = np.zeros(9, dtype=np.int64)
