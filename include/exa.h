@@ -378,6 +378,9 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 #define EXA_UNITS_PER_CALLBACK 0
 #define EXA_UNITS_JAC_HESS 1
 #define EXA_UNITS_ONE_PASS 2
+/* Batched evaluation only: every callback's tiles in a launch of its own,
+ * one after another (each kernel with the register budget of its own units). */
+#define EXA_UNITS_SEPARATE 3
 /* Fix the schedule of exa_eval for a mask instead of tuning it at the
  * mask's first call (for measurement: a profiled run can use the schedule
  * an unprofiled run chose).  block = workgroup size (64, 128 or 256), epl =
@@ -476,7 +479,8 @@ exa_status exa_counters(const exa_model* m, int64_t* out9);
  * patterns have no data points) are evaluated together: every selected
  * callback of every instance in ONE evaluation launch over a tile list of
  * (instance, unit, data range) tiles, one workgroup per tile, with the
- * instances binned over the 8 XCDs by cost; then ONE launch of every
+ * instances binned over the 8 XCDs by cost (or, with EXA_UNITS_SEPARATE,
+ * one such launch per callback, one after another); then ONE launch of every
  * instance's deterministic reductions (gradient, J^T w, H v, parameter
  * adjoint segment sums, objective partials), plus one small launch when a
  * segment is longer than 1024 entries.  The launches are recorded once into
@@ -506,7 +510,8 @@ typedef struct exa_batch_options {
     int32_t epl;       /*   points per lane 1..16 (0: 4)                       */
     int32_t fuse;      /*   1: patterns over the same data arrays share a lane */
     int32_t units;     /*   EXA_UNITS_* (a choice a mask does not allow falls
-                            back to the next one down)                         */
+                            back to the next one down; EXA_UNITS_SEPARATE to
+                            per-callback tiles)                                */
     int32_t use_graph; /* 1: replay the launches from a HIP graph              */
     int32_t xcd_aware; /* 1: instances are split over the 8 XCDs by cost and
                           each XCD takes its instances' tiles (an instance's x

@@ -9,7 +9,9 @@
 //   * ONE evaluation launch over a tile list of (instance, unit, data range)
 //     tiles of every selected callback, one workgroup per tile (the kernels
 //     and units of exa_eval: per-callback tiles, Jacobian + Hessian units or
-//     one pass per point), plus a second launch for the parameter adjoint;
+//     one pass per point), or one launch per callback (each kernel with the
+//     register budget of its own units), plus a launch for the parameter
+//     adjoint;
 //   * ONE launch of every instance's deterministic reductions (the same
 //     segment sums, chunks and parts as the instance's own reduction, and
 //     its objective partials), plus one small launch for the part sums of
@@ -37,7 +39,8 @@ using namespace exa;
 
 namespace {
 // work buffers of the batch (ExaBatchReduce::bufs)
-constexpr int kBufFo = 0, kBufHv = 1, kBufPar = 2, kBufTile = 3;
+constexpr int kBufFo = 0, kBufHv = 1, kBufPar = 2, kBufTile = 3, kBufJac = 4, kBufW = 5;
+constexpr int kWorkBufs = 4;  // the batch's own buffers (the others are the caller's)
 // outputs of the reduction launch (ExaBatchReduce::outs)
 constexpr int kOutF = 0, kOutG = 1, kOutJtw = 2, kOutHv = 3, kOutLag = 4, kOutLagTmp = 5, kOutThetaBar = 6;
 constexpr int kOffX = 0, kOffY = 1, kOffJac = 2, kOffHess = 3, kOffTheta = 4, kNoff = 5;
@@ -55,17 +58,18 @@ struct exa_batch {
     double* theta = nullptr;           // the batch's parameters
     // work buffers, allocated on first use; instance i's block starts at
     // entry base[k][i] (a 128-byte line)
-    double* buf[kExaBatchBufs] = {};
-    std::vector<int64_t> base[kExaBatchBufs];
-    int64_t buf_len[kExaBatchBufs] = {};
+    double* buf[kWorkBufs] = {};
+    std::vector<int64_t> base[kWorkBufs];
+    int64_t buf_len[kWorkBufs] = {};
     double* lag_tmp = nullptr;         // J^T y of EXA_EV_LAG when the gradient is reduced
     // per instance: its models' device maps, with part sums of the batch's own
     struct Maps {
-        DevMap grad, jt, h, par;
+        DevMap grad, jt, h, par, jtc;
     };
     std::vector<Maps> maps;
     std::vector<int64_t> nobj;         // objective tiles per instance
     bool grad_direct_all = true, grad_direct_any = false;
+    bool jtc_ok = true;  // every instance can sum J^T w from its Jacobian values
     // options
     bool autotune = true, use_graph = true, xcd_aware = true, fuse = true;
     int block = 256, epl = 4, units = EXA_UNITS_JAC_HESS;
@@ -78,6 +82,13 @@ struct exa_batch {
         int64_t ntiles = 0;
         ExaTile* atiles = nullptr;           // parameter adjoint launch
         int64_t antiles = 0;
+        // EXA_UNITS_SEPARATE: one launch per callback (mode, tiles, count)
+        struct Part {
+            int mode;
+            ExaTile* tiles;
+            int64_t ntiles;
+        };
+        std::vector<Part> parts;
         int64_t tuned_ns = 0;
         ExaBatchJob* jobs = nullptr;
         int32_t* blocks = nullptr;
@@ -135,9 +146,23 @@ uint32_t eval_mask(uint32_t mask) {
     return e;
 }
 
+// The units a batch mask can run as asked: EXA_UNITS_SEPARATE needs two
+// callbacks or more; the others as exa_eval allows them.
+int batch_units(uint32_t em, int units) {
+    if (!em) return EXA_UNITS_PER_CALLBACK;
+    if (units == EXA_UNITS_SEPARATE) return eval_modes(em, false).size() > 1 ? units : EXA_UNITS_PER_CALLBACK;
+    return valid_units(em, units);
+}
+
+// Modes of the evaluation launch(es) of a mask under units.
+std::vector<int> modes_of(uint32_t em, int units) {
+    if (!em) return {};
+    if (units == EXA_UNITS_SEPARATE) return eval_modes(em, false);
+    return launch_modes(em, units);
+}
+
 const std::vector<int>& main_modes(const exa_batch::Sched& S, uint32_t mask, std::vector<int>& tmp) {
-    const uint32_t em = eval_mask(mask);
-    tmp = em ? launch_modes(em, S.units) : std::vector<int>();
+    tmp = modes_of(eval_mask(mask), S.units);
     return tmp;
 }
 
@@ -154,7 +179,7 @@ std::vector<int64_t> instance_cost(const exa_batch& b, uint32_t mask, int units,
         const Model& M = b.models[i]->impl;
         int64_t rd = 0, wr = 0;
         if (em) {
-            kernel_bytes(M, launch_modes(em, units), fused, rd, wr);
+            kernel_bytes(M, modes_of(em, batch_units(em, units)), fused, rd, wr);
             cost[i] += rd + wr;
         }
         if (mask & EXA_EV_ADJ) {
@@ -243,7 +268,7 @@ ExaTile* upload_binned(exa_batch& b, const exa_batch::Sched& S, const std::vecto
 void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fused, int units) {
     exa_batch::Sched& S = b.sched[mask];
     const uint32_t em = eval_mask(mask);
-    S.units = em ? valid_units(em, units) : EXA_UNITS_PER_CALLBACK;
+    S.units = batch_units(em, units);
     S.block = block;
     S.epl = epl;
     S.fused = fused;
@@ -251,15 +276,29 @@ void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fu
     const int64_t tp = (int64_t)block * epl;
     std::vector<int> tmp;
     const std::vector<int>& modes = main_modes(S, mask, tmp);
-    std::vector<std::vector<ExaTile>> per(b.B), adj(b.B);
-    for (int i = 0; i < b.B; ++i) {
-        if (!modes.empty()) instance_tiles(b, i, modes, !single_kernel(modes), em, tp, fused, per[i]);
-        if (mask & EXA_EV_ADJ) instance_tiles(b, i, {M_ADJ}, false, 0, tp, fused, adj[i]);
-    }
     b.mem.release(S.tiles);
     b.mem.release(S.atiles);
-    S.tiles = upload_binned(b, S, per, S.ntiles);
-    S.atiles = upload_binned(b, S, adj, S.antiles);
+    for (auto& p : S.parts) b.mem.release(p.tiles);
+    S.tiles = nullptr;
+    S.ntiles = 0;
+    S.parts.clear();
+    std::vector<std::vector<ExaTile>> per(b.B), adj(b.B);
+    if (S.units == EXA_UNITS_SEPARATE) {
+        for (int mode : modes) {
+            for (auto& v : per) v.clear();
+            for (int i = 0; i < b.B; ++i) instance_tiles(b, i, {mode}, false, em, tp, fused, per[i]);
+            exa_batch::Sched::Part part{mode, nullptr, 0};
+            part.tiles = upload_binned(b, S, per, part.ntiles);
+            S.parts.push_back(part);
+        }
+    } else if (!modes.empty()) {
+        for (int i = 0; i < b.B; ++i) instance_tiles(b, i, modes, !single_kernel(modes), em, tp, fused, per[i]);
+        S.tiles = upload_binned(b, S, per, S.ntiles);
+    }
+    if (mask & EXA_EV_ADJ) {
+        for (int i = 0; i < b.B; ++i) instance_tiles(b, i, {M_ADJ}, false, 0, tp, fused, adj[i]);
+        S.atiles = upload_binned(b, S, adj, S.antiles);
+    }
 }
 
 double* need_buf(exa_batch& b, int k) {
@@ -283,6 +322,9 @@ ExaBatchJob seg_batch_job(const DevMap& m, int bufk, int64_t buf_off, int out, i
     J.nlong = m.nlong;
     J.wide = m.wide;
     J.chunked = m.chunked;
+    J.rows = m.rows;
+    J.lrow = m.lrow;
+    J.wv = -1;
     J.buf = bufk;
     J.buf_off = buf_off;
     J.out = out;
@@ -327,7 +369,15 @@ void build_reductions(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
                     S.axpy = true;
                 }
             }
-            if (mask & EXA_EV_JTPROD) mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false));
+            if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) {
+                // from the Jacobian values of this call, times w[row]
+                ExaBatchJob J = seg_batch_job(mp.jtc, kBufJac, b.offsets[kNoff * i + kOffJac], kOutJtw, xo, false);
+                J.wv = kBufW;
+                J.wv_off = b.offsets[kNoff * i + kOffY];
+                mine.push_back(J);
+            } else if (mask & EXA_EV_JTPROD) {
+                mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false));
+            }
             if (mask & EXA_EV_HPROD) mine.push_back(seg_batch_job(mp.h, kBufHv, b.base[kBufHv][i], kOutHv, xo, false));
             if (mask & EXA_EV_ADJ)
                 mine.push_back(seg_batch_job(mp.par, kBufPar, b.base[kBufPar][i], kOutThetaBar,
@@ -431,6 +481,17 @@ void launch_eval(exa_batch& b, uint32_t mask, const ExaMulti& rec, hipStream_t s
     const Module& K = *b.module;
     std::vector<int> tmp;
     const std::vector<int>& modes = main_modes(S, mask, tmp);
+    auto launch_single = [&](int mode, ExaTile* tiles, int64_t n) {
+        if (n == 0) return;
+        ExaCall c = rec.c[mode];
+        c.tiles = tiles;
+        c.ntiles = n;
+        c.per_xcd = n / 8;
+        void* args[] = {&c};
+        hip_check(hipModuleLaunchKernel(K.fn[mode], (unsigned)n, 1, 1, (unsigned)S.block, 1, 1, 0, s, args, nullptr),
+                  "hipModuleLaunchKernel");
+    };
+    for (const auto& p : S.parts) launch_single(p.mode, p.tiles, p.ntiles);
     if (S.ntiles > 0) {
         if (single_kernel(modes)) {
             ExaCall c = rec.c[modes[0]];
@@ -476,7 +537,9 @@ bool launch_reduce(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStrea
     R.nblocks = S.nblocks;
     R.lblocks = S.lblocks;
     R.nlblocks = S.nlblocks;
-    for (int k = 0; k < kExaBatchBufs; ++k) R.bufs[k] = b.buf[k];
+    for (int k = 0; k < kWorkBufs; ++k) R.bufs[k] = b.buf[k];
+    R.bufs[kBufJac] = io.jac;
+    R.bufs[kBufW] = io.w;
     R.outs[kOutF] = io.f;
     R.outs[kOutG] = io.g;
     R.outs[kOutJtw] = io.jtw;
@@ -534,6 +597,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
     std::vector<int> combos = {EXA_UNITS_PER_CALLBACK};
     if (em && has_jh(em)) combos.push_back(EXA_UNITS_JAC_HESS);
     if (em && combined_mode_of(em) >= 0) combos.push_back(EXA_UNITS_ONE_PASS);
+    if (em && eval_modes(em, false).size() > 1) combos.push_back(EXA_UNITS_SEPARATE);
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
@@ -645,13 +709,13 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         }
         if (b->block != 64 && b->block != 128 && b->block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
-        if (b->units < EXA_UNITS_PER_CALLBACK || b->units > EXA_UNITS_ONE_PASS)
+        if (b->units < EXA_UNITS_PER_CALLBACK || b->units > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
 
         // offsets in the concatenated arrays and bases in the work buffers
         b->offsets.assign(kNoff * (B + 1), 0);
-        for (int k = 0; k < kExaBatchBufs; ++k) b->base[k].assign(B, 0);
+        for (int k = 0; k < kWorkBufs; ++k) b->base[k].assign(B, 0);
         b->nobj.assign(B, 0);
         for (int i = 0; i < B; ++i) {
             const Model& M = models[i]->impl;
@@ -663,8 +727,8 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             n[kOffHess] = o[kOffHess] + M.nnzh;
             n[kOffTheta] = o[kOffTheta] + M.ntheta;
             b->nobj[i] = M.dev->sched[M_OBJ].ntiles;
-            const int64_t len[kExaBatchBufs] = {M.fo_obj_len + M.fo_con_len, M.hv_len, M.par_len, b->nobj[i]};
-            for (int k = 0; k < kExaBatchBufs; ++k) {
+            const int64_t len[kWorkBufs] = {M.fo_obj_len + M.fo_con_len, M.hv_len, M.par_len, b->nobj[i]};
+            for (int k = 0; k < kWorkBufs; ++k) {
                 b->base[k][i] = b->buf_len[k];
                 b->buf_len[k] += aligned(len[k]);
             }
@@ -709,7 +773,9 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             mp.jt = D.jt_map;
             mp.h = D.h_map;
             mp.par = D.par_map;
-            for (DevMap* m : {&mp.grad, &mp.jt, &mp.h, &mp.par})
+            mp.jtc = D.jtc_map;
+            if (!D.jtc_ok) b->jtc_ok = false;
+            for (DevMap* m : {&mp.grad, &mp.jt, &mp.h, &mp.par, &mp.jtc})
                 if (m->nparts > 0) m->lsum = (double*)b->mem.alloc(m->nparts * sizeof(double));
         }
         hip_check(hipStreamCreate(&b->cap), "hipStreamCreate");
@@ -750,7 +816,9 @@ exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6) 
         out6[1] = S.epl;
         out6[2] = S.fused ? 1 : 0;
         out6[3] = S.units;
-        out6[4] = S.ntiles + S.antiles;
+        int64_t nt = S.ntiles + S.antiles;
+        for (const auto& p : S.parts) nt += p.ntiles;
+        out6[4] = nt;
         out6[5] = S.tuned_ns;
     });
 }
@@ -762,7 +830,7 @@ exa_status exa_batch_set_schedule(exa_batch* b, uint32_t mask, int32_t block, in
         check_mask(mask);
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
-        if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_ONE_PASS)
+        if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         set_batch_schedule(*b, mask, block, epl, fused != 0, units);
         b->sched[mask].tuned = true;
@@ -787,7 +855,7 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
             const Model& M = b->models[i]->impl;
             int64_t r = 0, w = 0;
             if (em) {
-                kernel_bytes(M, launch_modes(em, valid_units(em, units)), fused, r, w);
+                kernel_bytes(M, modes_of(em, batch_units(em, units)), fused, r, w);
                 er += r;
                 ew += w;
             }
@@ -839,13 +907,18 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
         if (mask & EXA_EV_HPROD) need(io->hv, tot[kOffX], "hv");
         if (mask & EXA_EV_LAG) need(io->lag, tot[kOffX], "lag");
         if (mask & EXA_EV_ADJ) need(io->theta_bar, tot[kOffTheta], "theta_bar");
+        if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && !b->jtc_ok)
+            fail(EXA_EINVAL, "J^T w with the Jacobian in one call needs fewer than 2^31 Jacobian entries per "
+                             "instance; evaluate J^T w in a call of its own");
         if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && b->grad_direct_all != b->grad_direct_any)
             fail(EXA_EINVAL,
                  "the instances disagree on whether every variable has at most one objective term; their "
                  "gradients cannot be evaluated in one batch");
         hipStream_t s = (hipStream_t)stream;
         // work buffers this mask needs
-        if ((mask & (EXA_EV_GRAD | EXA_EV_JTPROD | EXA_EV_LAG))) need_buf(*b, kBufFo);
+        if (((mask & EXA_EV_GRAD) && !b->grad_direct_all) || (mask & EXA_EV_LAG) ||
+            ((mask & EXA_EV_JTPROD) && !(mask & EXA_EV_JAC)))
+            need_buf(*b, kBufFo);
         if (mask & EXA_EV_HPROD) need_buf(*b, kBufHv);
         if (mask & EXA_EV_ADJ) need_buf(*b, kBufPar);
         if (mask & EXA_EV_OBJ) need_buf(*b, kBufTile);

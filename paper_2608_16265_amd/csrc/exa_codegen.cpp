@@ -235,9 +235,14 @@ class PatternCg {
             case M_GRAD:
             case M_JAC:
             case M_JTPROD: {
+                // J^T w contributions are the Jacobian entries (seed 1, the
+                // jac job's very statements) times the row's weight, one
+                // rounding each: so the reduction of the Jacobian's COO
+                // values times w gives the same bits
                 std::vector<std::string> J(P_.o1step(), Z), Pacc, adj;
-                reverse(mode_ == M_JTPROD ? nm_.wgt : ONE, adj, J, Pacc, false);
-                for (int s = 0; s < P_.o1step(); ++s) e_.out(slot(s), J[s]);
+                reverse(ONE, adj, J, Pacc, false);
+                for (int s = 0; s < P_.o1step(); ++s)
+                    e_.out(slot(s), mode_ == M_JTPROD ? e_.mul(J[s], nm_.wgt) : J[s]);
                 break;
             }
             case M_JPROD: {
@@ -979,7 +984,8 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
 
 const std::vector<int>& job_modes(int mode) {
     static const std::vector<int> one[M_COUNT] = {{0}, {1}, {2}, {3}, {4}, {5}, {6}, {7}, {8}, {M_JAC, M_HESS}};
-    static const std::vector<int> full = {M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_JTPROD, M_HPROD};
+    // with the Jacobian in the same pass, J^T w is summed from its values
+    static const std::vector<int> full = {M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_HPROD};
     static const std::vector<int> ipm = {M_GRAD, M_CONS, M_JAC, M_HESS};
     return mode == M_SFULL ? full : mode == M_SIPM ? ipm : one[mode];
 }

@@ -126,7 +126,8 @@ static_assert(M_COUNT == 10, "ExaMulti holds one call per mode");
 // Units that run several callbacks' jobs at one point from one set of loads
 // and sweeps, used by the several-callback kernel only (their jobs take
 // inputs and outputs from the per-mode calls of an ExaMulti):
-// M_SFULL: grad, cons, jac, hess, jprod, jtprod, hprod;
+// M_SFULL: grad, cons, jac, hess, jprod, hprod (a J^T w of the same call is
+//          summed from the Jacobian values by the reduction launch);
 // M_SIPM:  grad, cons, jac, hess (an interior-point iterate).
 constexpr int M_SFULL = 10, M_SIPM = 11;
 inline bool multi_unit_mode(int mode) { return mode == M_SFULL || mode == M_SIPM; }
@@ -257,6 +258,9 @@ struct Model {
     std::vector<double> xl, xu, theta;
     // reduction maps (positions in the first-order buffer: grad part first)
     SegMap grad_map, jt_map, h_map, par_map;
+    // J^T w from the Jacobian's COO values: jt_map's segments and order with
+    // COO positions (jtc_map) and the row of each entry (jtc_rows.idx)
+    SegMap jtc_map, jtc_rows;
     bool host_only = false;
     int block = 256, epl = 4;
     bool autotune = false, fuse = false;

@@ -454,17 +454,21 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     // The work buffers hold each pattern's block slot-major: slot s of data
     // point k at block + s * bstride() + k (the constraint part of the
     // first-order buffer after the objective part).
-    std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr;
+    std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr, jtc, jtr;
     for (auto& P : M.pats) {
         const int st = P.o1step();
         const int64_t bs = P.bstride();
         for (int64_t k = 0; k < P.ndata; ++k)
             for (int s = 0; s < st; ++s) {
                 const int64_t v = P.var_index(s, k);
-                if (P.kind == EXA_OBJ)
+                if (P.kind == EXA_OBJ) {
                     g.emplace_back(v, P.ob + s * bs + k);
-                else
+                } else {
                     jt.emplace_back(v, M.fo_obj_len + P.ob + s * bs + k);
+                    // the same entry of the COO Jacobian, and its row
+                    jtc.emplace_back(v, P.o1 + k * st + s);
+                    jtr.emplace_back(v, P.row(k));
+                }
             }
         const int hs = (int)P.hvs.size();
         for (int64_t k = 0; k < P.ndata; ++k)
@@ -503,6 +507,8 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
         v = e;
     }
     build_map(M.jt_map, M.nvar, jt);
+    build_map(M.jtc_map, M.nvar, jtc);
+    build_map(M.jtc_rows, M.nvar, jtr);
     build_map(M.h_map, M.nvar, h);
     build_map(M.par_map, M.ntheta, pr);
     M.signature = pattern_signature(M);

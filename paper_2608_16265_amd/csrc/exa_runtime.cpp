@@ -310,10 +310,11 @@ int64_t estimate_device_bytes(const Model& M) {
     b += 8 * (M.fo_obj_len + M.fo_con_len + M.par_len + M.hv_len + std::max<int64_t>(1, nobj) + M.nvar + 1);
     // maps: pointers and positions, plus at most a 24-byte record per four
     // entries (chunked sums, with padding) and part sums
-    for (const SegMap* S : {&M.grad_map, &M.jt_map, &M.h_map, &M.par_map}) {
+    for (const SegMap* S : {&M.grad_map, &M.jt_map, &M.h_map, &M.par_map, &M.jtc_map}) {
         const int64_t nnz = (int64_t)S->idx.size();
         b += 8 * (S->nseg() + 1) + 8 * nnz + 8 * nnz + 24 * 256 + 8 * (nnz / kExaLongSeg + 1);
     }
+    b += 8 * (int64_t)M.jtc_map.idx.size() + 16 * 256;  // rows of the products map
     return b;
 }
 
@@ -367,6 +368,9 @@ void build_device(Model& M) {
     upload_map(D, M.jt_map, D.jt_map);
     upload_map(D, M.h_map, D.h_map);
     upload_map(D, M.par_map, D.par_map);
+    // J^T w from the Jacobian values needs every COO position in int32
+    D.jtc_ok = M.nnzj < INT32_MAX && M.ncon < INT32_MAX;
+    if (D.jtc_ok) upload_map(D, M.jtc_map, D.jtc_map, &M.jtc_rows);
     // the caller's float columns are not kept past create
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
 }
@@ -387,12 +391,13 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
 }
 
 // maps go to the device as int32 whenever every position fits
-void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
+void upload_map(DeviceState& D, const SegMap& S, DevMap& d, const SegMap* rows) {
     d.nseg = S.nseg();
     int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
     top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
     d.wide = top >= INT32_MAX ? 1 : 0;
     if (d.wide) {
+        if (rows) fail(EXA_EINVAL, "internal: sums of products need int32 maps");
         d.ptr = D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
         d.idx = D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
         return;
@@ -400,11 +405,16 @@ void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
     d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
     d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
-    const ChunkPlan P = chunk_plan(S);
+    if (rows) {
+        std::vector<int32_t> r32(rows->idx.begin(), rows->idx.end());
+        d.rows = (const int32_t*)D.upload(r32.data(), r32.size() * sizeof(int32_t));
+    }
+    const ChunkPlan P = chunk_plan(S, rows);
     d.chunked = P.chunked ? 1 : 0;
     if (P.nlanes()) {
         d.lanes = (const int32_t*)D.upload(P.meta.data(), P.meta.size() * sizeof(int32_t));
         d.lidx = (const int32_t*)D.upload(P.lidx.data(), P.lidx.size() * sizeof(int32_t));
+        if (rows) d.lrow = (const int32_t*)D.upload(P.lrow.data(), P.lrow.size() * sizeof(int32_t));
         d.nlanes = P.nlanes();
     }
     if (P.nparts()) {
@@ -462,7 +472,7 @@ Model::Csc& csc_form(Model& M, int which) {
     return C;
 }
 
-ChunkPlan chunk_plan(const SegMap& S) {
+ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows) {
     ChunkPlan P;
     int64_t longest = 0, top = S.ptr.empty() ? 0 : S.ptr.back();
     for (int64_t s = 0; s < S.nseg(); ++s) longest = std::max(longest, S.ptr[s + 1] - S.ptr[s]);
@@ -484,6 +494,7 @@ ChunkPlan chunk_plan(const SegMap& S) {
         while (P.nlanes() < lanes) {
             P.meta.insert(P.meta.end(), {-1, 0});
             P.lidx.insert(P.lidx.end(), {0, 0, 0, 0});
+            if (rows) P.lrow.insert(P.lrow.end(), {0, 0, 0, 0});
         }
     };
     int64_t nparts = 0, most = 0;
@@ -507,6 +518,9 @@ ChunkPlan chunk_plan(const SegMap& S) {
             // the chunk's positions, the last one repeated past its count
             for (int64_t u = 0; u < kExaChunk; ++u)
                 P.lidx.push_back(cnt ? (int32_t)S.idx[b + c * kExaChunk + std::min(u, cnt - 1)] : 0);
+            if (rows)
+                for (int64_t u = 0; u < kExaChunk; ++u)
+                    P.lrow.push_back(cnt ? (int32_t)rows->idx[b + c * kExaChunk + std::min(u, cnt - 1)] : 0);
         }
     }
     if (P.chunked) pad_to((P.nlanes() + 255) / 256 * 256);
@@ -647,7 +661,9 @@ std::vector<int> eval_modes(uint32_t mask, bool jh) {
     else if (mask & EXA_EV_HESS)
         m.push_back(M_HESS);
     if (mask & EXA_EV_JPROD) m.push_back(M_JPROD);
-    if (mask & EXA_EV_JTPROD) m.push_back(M_JTPROD);
+    // with the Jacobian in the same call, J^T w is summed from its values by
+    // the reduction launch: no tiles of its own
+    if ((mask & EXA_EV_JTPROD) && !(mask & EXA_EV_JAC)) m.push_back(M_JTPROD);
     if (mask & EXA_EV_HPROD) m.push_back(M_HPROD);
     return m;
 }
@@ -655,8 +671,7 @@ std::vector<int> eval_modes(uint32_t mask, bool jh) {
 // Multi-unit mode that covers a mask's callbacks besides the objective in
 // one pass per point, or -1.
 int combined_mode_of(uint32_t mask) {
-    const uint32_t full = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS | EXA_EV_JPROD | EXA_EV_JTPROD |
-                          EXA_EV_HPROD;
+    const uint32_t full = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS | EXA_EV_JPROD | EXA_EV_HPROD;
     const uint32_t ipm = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS;
     if ((mask & full) == full) return M_SFULL;
     if ((mask & ~(uint32_t)EXA_EV_OBJ) == ipm) return M_SIPM;
@@ -892,7 +907,16 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
         rw += 8 * nseg + 8 * P.nparts();
     };
     if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && !M.grad_direct) seg(M.grad_map);
-    if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) seg(M.jt_map);
+    if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) {
+        // sums of products of the Jacobian values: the map as above plus a
+        // row per entry (4 bytes, in the lane records or beside the
+        // positions), and each weight w[row] once
+        seg(M.jtc_map);
+        rr += 4 * (int64_t)M.jtc_map.idx.size() + 8 * M.ncon;
+    } else if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) {
+        seg(M.jt_map);
+    }
+    if ((mask & EXA_EV_LAG) && (mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) seg(M.jt_map);
     if (mask & EXA_EV_HPROD) seg(M.h_map);
     if (mask & EXA_EV_ADJ) seg(M.par_map);
     if (mask & EXA_EV_OBJ) {
@@ -920,6 +944,8 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
     J.nparts = m.nparts;
     J.nlong = m.nlong;
     J.lsum = m.lsum;
+    J.rows = m.rows;
+    J.lrow = m.lrow;
     J.buf = buf;
     J.out = out;
     return J;
@@ -1318,6 +1344,9 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     if (mask & EXA_EV_HPROD) need(a->hv, M.nvar, "hv");
     DeviceState& D = *M.dev;
     const int64_t nobj = D.sched[M_OBJ].ntiles;
+    if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && !D.jtc_ok)
+        fail(EXA_EINVAL, "J^T w with the Jacobian in one exa_eval call needs fewer than 2^31 Jacobian entries; "
+                         "call exa_jtprod separately");
 
     // each mode's call, as its own entry point sets it up
     ExaMulti mc;
@@ -1404,6 +1433,11 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
         R.ep_job = R.njobs;
         R.ax_alpha = lag_sigma;
         job(D.jt_map, D.fo, a->g);
+    } else if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) {
+        // J^T w from the Jacobian values this launch wrote: w[row] times
+        // each entry, summed per variable in the order of jt_map
+        job(D.jtc_map, a->jac, a->jtw);
+        R.job[R.njobs - 1].wv = a->w;
     } else if (mask & EXA_EV_JTPROD) {
         job(D.jt_map, D.fo, a->jtw);
     }

@@ -37,6 +37,10 @@ struct DevMap {
     const int32_t* lpart = nullptr;
     int64_t nparts = 0, nlong = 0;
     double* lsum = nullptr;
+    // products (see ExaSegJob): the row of each entry, and of each lane's
+    // four positions
+    const int32_t* rows = nullptr;
+    const int32_t* lrow = nullptr;
 };
 
 struct DeviceState {
@@ -84,6 +88,8 @@ struct DeviceState {
     DevMap csc_map[2];          // uploaded on the first exa_csc_values call
     bool csc_up[2] = {false, false};
     DevMap grad_map, jt_map, h_map, par_map;
+    DevMap jtc_map;  // J^T w from the Jacobian's COO values (int32 maps only)
+    bool jtc_ok = false;
 
     void* alloc(size_t bytes);
     void* upload(const void* src, size_t bytes);
@@ -140,16 +146,17 @@ void set_schedule(Model& M, int mode, int block, int epl, bool fused);
 struct ChunkPlan {
     bool chunked = false;  // chunk lanes (else one lane per segment)
     std::vector<int32_t> meta, lidx;    // 2 and 4 per lane, a multiple of 256 lanes
+    std::vector<int32_t> lrow;          // with rows: 4 per lane, beside lidx
     std::vector<int32_t> longs, lpart;  // 5 per long segment; 2 per part block
     int64_t nlanes() const { return (int64_t)meta.size() / 2; }
     int64_t nlong() const { return (int64_t)longs.size() / 5; }
     int64_t nparts() const { return (int64_t)lpart.size() / 2; }
 };
-ChunkPlan chunk_plan(const SegMap& S);
+ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows = nullptr);
 void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);
 // Map and tables of a segment map on the device (int32 when positions fit,
 // chunked when segments are long).
-void upload_map(DeviceState& D, const SegMap& S, DevMap& d);
+void upload_map(DeviceState& D, const SegMap& S, DevMap& d, const SegMap* rows = nullptr);
 // CSC analysis of the Jacobian (which = 0) or Hessian (1) on first use.
 Model::Csc& csc_form(Model& M, int which);
 void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);

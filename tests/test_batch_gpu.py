@@ -78,6 +78,7 @@ def _star(sizes, seed):
     (False, 64, 1, False, "per_callback", True, False),
     (False, 256, 3, True, "jac_hess", False, True),
     (False, 128, 8, True, "one_pass", True, True),
+    (False, 256, 2, True, "separate", True, True),
     (True, 256, 4, True, "jac_hess", True, True)])
 def test_every_callback_bitwise_equal_to_plain(family, autotune, block, epl, fuse, units, graph, xcd):
     _gpu()
