@@ -67,13 +67,14 @@ def parse():
     ap.add_argument("--quick", action="store_true",
                     help="few repetitions per measurement (for runs under a profiler)")
     ap.add_argument("--eval-schedule", default=None,
-                    help="block,points_per_lane,fused,units (0 per callback, 1 Jacobian + Hessian units, "
-                         "2 one pass): fix the step's exa_eval schedule instead of "
+                    help="block,points_per_lane,fused,units[,jt] (units 0 per callback, 1 Jacobian + Hessian "
+                         "units, 2 one pass; jt 1: J^T w from the Jacobian values): fix the step's exa_eval "
+                         "schedule instead of "
                          "tuning it (to profile the schedule an unprofiled run chose)")
     ap.add_argument("--batch-schedule", default=None,
-                    help="block,points_per_lane,fused,units (per_callback, jac_hess or one_pass): fix the "
-                         "headline batch step's schedule instead of tuning it (to profile the schedule an "
-                         "unprofiled run chose)")
+                    help="block,points_per_lane,fused,units[,jt] (units per_callback, jac_hess, one_pass or "
+                         "separate; jt 1: J^T w from the Jacobian values): fix the headline batch step's "
+                         "schedule instead of tuning it (to profile the schedule an unprofiled run chose)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates "
                          "the profiler's HBM byte counters)")
@@ -253,8 +254,8 @@ def leg_single(name, wl, steps, warmup):
     em = ExaModel(wl.model, autotune=True)
     build_s = time.perf_counter() - t0
     if EVAL_SCHEDULE:
-        b, e_, f_, u_ = (int(v) for v in EVAL_SCHEDULE.split(","))
-        em.set_eval_schedule(ALL_CBS, b, e_, bool(f_), u_)
+        v = [int(t) for t in EVAL_SCHEDULE.split(",")]
+        em.set_eval_schedule(ALL_CBS, v[0], v[1], bool(v[2]), v[3], jt_from_jac=len(v) > 4 and bool(v[4]))
     e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
     cbs, (X, Y, V, W, jv, hv) = _callbacks(em, wl)
     step = cbs["eval_all"]
@@ -387,8 +388,9 @@ def leg_batch(steps, warmup, count=256, first_seed=1000):
     build_s = time.perf_counter() - t0
     b = ExaBatch(ems, autotune=True)
     if BATCH_SCHEDULE:
-        bk, ep, fu, un = BATCH_SCHEDULE.split(",")
-        b.set_schedule(BATCH_CBS, int(bk), int(ep), bool(int(fu)), un)
+        v = BATCH_SCHEDULE.split(",")
+        b.set_schedule(BATCH_CBS, int(v[0]), int(v[1]), bool(int(v[2])), v[3],
+                       jt_from_jac=len(v) > 4 and bool(int(v[4])))
     dev = "cuda:0"
     rng = np.random.default_rng(0)
     X = b.concat([w.x for w in wls])

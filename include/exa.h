@@ -366,8 +366,8 @@ typedef struct exa_eval_args {
 exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream);
 /* The schedule of exa_eval for a mask: out4 = workgroup size, points per
  * lane, fused (bit 0) | one pass per point for all callbacks (bit 1) |
- * Jacobian + Hessian units (bit 2), number of tiles.  EXA_ESTATE until the
- * mask's first exa_eval call. */
+ * Jacobian + Hessian units (bit 2) | J^T w from the Jacobian values (bit 3),
+ * number of tiles.  EXA_ESTATE until the mask's first exa_eval call. */
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 /* Units of an exa_eval launch: one tile per callback and point, the
  * Jacobian and the Hessian apart (their tiles then run in a kernel with a
@@ -378,6 +378,15 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 #define EXA_UNITS_PER_CALLBACK 0
 #define EXA_UNITS_JAC_HESS 1
 #define EXA_UNITS_ONE_PASS 2
+/* Flag OR'ed into `units` (exa_eval_set_schedule, exa_batch_set_schedule,
+ * the batch options): a mask with both the Jacobian and J^T w sums J^T w
+ * from the Jacobian values the same launch writes (w[row] times each entry,
+ * per variable in ascending COO position) instead of evaluating J^T w tiles
+ * into a work buffer; the bits are the same either way (J^T w contributions
+ * are the Jacobian entries times w).  The tuner times both; without it the
+ * Jacobian values are used when the launch writes more than the 256 MB
+ * last-level cache holds. */
+#define EXA_JT_FROM_JAC 0x10
 /* Batched evaluation only: every callback's tiles in a launch of its own,
  * one after another (each kernel with the register budget of its own units). */
 #define EXA_UNITS_SEPARATE 3
@@ -568,9 +577,12 @@ exa_status exa_batch_set_theta(exa_batch* b, const double* theta, exa_stream_t s
 /* Evaluate the callbacks selected by `mask` (EXA_EV_* and the batched-only
  * bits above) for every instance.  The first call with a mask builds its
  * tile list and reduction table, allocates the work buffers it needs and,
- * with autotune, times candidate schedules (synchronizing the stream); a
- * call whose pointers, sigma or schedule differ from the previous call's
- * records a new graph.  Otherwise a call is one graph launch on `stream`.
+ * with autotune, times candidate schedules (synchronizing the stream).  A
+ * call that repeats the previous call (same mask, pointers, sigma and
+ * schedule) records the launches into a HIP graph, and later calls that
+ * match it are one graph launch on `stream`; a call with other arguments
+ * launches directly (arguments that change at every call cost no
+ * recording).
  * Errors: EXA_EINVAL for a NULL batch or io, an empty or unknown mask, LAG
  * with GRAD or JTPROD, a NULL pointer the mask needs, or GRAD or LAG over
  * instances that disagree on whether every variable has at most one
@@ -582,7 +594,8 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
  * evaluation launch(es), bytes read and written by the reduction launch. */
 exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4);
 /* Schedule of a mask: out6 = workgroup size, points per lane, fused (0/1),
- * units (EXA_UNITS_*), number of evaluation tiles, the autotuner's best
+ * units (EXA_UNITS_*, | EXA_JT_FROM_JAC when J^T w is summed from the
+ * Jacobian values), number of evaluation tiles, the autotuner's best
  * evaluation-launch time in nanoseconds (0 if not tuned).  EXA_ESTATE before
  * the mask's first call. */
 exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6);

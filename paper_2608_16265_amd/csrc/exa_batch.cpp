@@ -77,6 +77,7 @@ struct exa_batch {
     struct Sched {
         int block = 256, epl = 4, units = EXA_UNITS_PER_CALLBACK;
         bool fused = true, tuned = false;
+        bool jt = false;                     // J^T w from the Jacobian values (EXA_JT_FROM_JAC)
         std::vector<std::vector<int>> bins;  // instances per XCD
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;
@@ -106,9 +107,13 @@ struct exa_batch {
         uint32_t mask = 0;
         exa_batch_io io;
         int block = 0, epl = 0, units = 0;
-        bool fused = false;
-    } key;
-    bool have_graph = false;
+        bool fused = false, jt = false;
+        bool operator==(const Key& o) const {
+            return mask == o.mask && std::memcmp(&io, &o.io, sizeof io) == 0 && block == o.block && epl == o.epl &&
+                   units == o.units && fused == o.fused && jt == o.jt;
+        }
+    } key, last;  // the graph's call; the previous call
+    bool have_graph = false, have_last = false;
     // launch timing (exa_batch_timing)
     struct Timing {
         bool on = false;
@@ -162,8 +167,17 @@ std::vector<int> modes_of(uint32_t em, int units) {
 }
 
 const std::vector<int>& main_modes(const exa_batch::Sched& S, uint32_t mask, std::vector<int>& tmp) {
-    tmp = modes_of(eval_mask(mask), S.units);
+    tmp = modes_of(tile_mask(eval_mask(mask), S.jt), S.units);
     return tmp;
+}
+
+// Without timing, as exa_eval decides for one model: J^T w from the
+// Jacobian values when the launch writes more than the last-level cache.
+bool default_jt(const exa_batch& b, uint32_t mask) {
+    if (!((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD)) || !b.jtc_ok) return false;
+    int64_t w = 0;
+    for (const exa_model* m : b.models) w += 8 * (m->impl.nnzj + m->impl.nnzh + m->impl.fo_con_len);
+    return w > ((int64_t)256 << 20);
 }
 
 // A launch of one plain mode runs that mode's own kernel (exa_k_<mode>);
@@ -174,7 +188,7 @@ bool single_kernel(const std::vector<int>& modes) { return modes.size() == 1 && 
 // instances are binned over the XCDs.
 std::vector<int64_t> instance_cost(const exa_batch& b, uint32_t mask, int units, bool fused) {
     std::vector<int64_t> cost(b.B, 0);
-    const uint32_t em = eval_mask(mask);
+    const uint32_t em = tile_mask(eval_mask(mask), b.sched.count(mask) ? b.sched.at(mask).jt : false);
     for (int i = 0; i < b.B; ++i) {
         const Model& M = b.models[i]->impl;
         int64_t rd = 0, wr = 0;
@@ -265,9 +279,10 @@ ExaTile* upload_binned(exa_batch& b, const exa_batch::Sched& S, const std::vecto
     return (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
 }
 
-void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fused, int units) {
+void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fused, int units, bool jt) {
     exa_batch::Sched& S = b.sched[mask];
-    const uint32_t em = eval_mask(mask);
+    S.jt = jt && (mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && b.jtc_ok;
+    const uint32_t em = tile_mask(eval_mask(mask), S.jt);
     S.units = batch_units(em, units);
     S.block = block;
     S.epl = epl;
@@ -369,7 +384,7 @@ void build_reductions(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
                     S.axpy = true;
                 }
             }
-            if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) {
+            if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && S.jt) {
                 // from the Jacobian values of this call, times w[row]
                 ExaBatchJob J = seg_batch_job(mp.jtc, kBufJac, b.offsets[kNoff * i + kOffJac], kOutJtw, xo, false);
                 J.wv = kBufW;
@@ -585,7 +600,8 @@ void run(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
 // First call with a mask under autotune: time every candidate schedule's
 // evaluation launch(es) on the caller's arguments and keep the fastest.
 void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
-    const uint32_t em = eval_mask(mask);
+    const bool jt0 = b.sched[mask].jt;
+    const uint32_t em = tile_mask(eval_mask(mask), jt0);
     const int blocks[] = {64, 128, 256};
     const int epls[] = {1, 2, 4, 8};
     std::vector<int> fuses = {0};
@@ -622,7 +638,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
             for (int f : fuses)
                 for (int bk : blocks)
                     for (int ep : epls) {
-                        set_batch_schedule(b, mask, bk, ep, f != 0, u);
+                        set_batch_schedule(b, mask, bk, ep, f != 0, u, jt0);
                         cands.push_back({time_it(2), bk, ep, f, u});
                     }
         // neighbouring schedules differ by less than one timing's noise: the
@@ -632,7 +648,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
         for (auto& c : cands) c.ms = 1e30f;
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
-                set_batch_schedule(b, mask, c.block, c.epl, c.fused != 0, c.units);
+                set_batch_schedule(b, mask, c.block, c.epl, c.fused != 0, c.units, jt0);
                 c.ms = std::min(c.ms, time_it(6));
             }
     } catch (...) {
@@ -643,8 +659,36 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units);
+    set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units, jt0);
     b.sched[mask].tuned_ns = (int64_t)(w.ms * 1e6);
+    // J^T w with the Jacobian: its own tiles and buffer, or the Jacobian
+    // values; the whole call (evaluation and reductions) decides
+    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && b.jtc_ok) {
+        float best[2] = {1e30f, 1e30f};
+        int units[2] = {w.units, w.units};
+        for (int round = 0; round < 2; ++round)
+            for (int jt = 0; jt < 2; ++jt) {
+                set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units, jt != 0);
+                units[jt] = b.sched[mask].units;
+                build_reductions(b, b.sched[mask], mask);
+                if ((mask & EXA_EV_JTPROD) && !jt) need_buf(b, kBufFo);
+                hip_check(hipEventCreate(&e0), "hipEventCreate");
+                hip_check(hipEventCreate(&e1), "hipEventCreate");
+                run(b, mask, io, s);
+                hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                for (int r = 0; r < 4; ++r) run(b, mask, io, s);
+                hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                best[jt] = std::min(best[jt], ms / 4);
+            }
+        const bool jt = best[1] < best[0];
+        set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, units[jt], jt);
+        b.sched[mask].reduce_built = false;
+    }
     if (log_on())
         log_msg("tuned batch of " + std::to_string(b.B) + " mask " + std::to_string(mask) + ": block " +
                 std::to_string(w.block) + ", points per lane " + std::to_string(w.epl) + ", fused " +
@@ -709,7 +753,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         }
         if (b->block != 64 && b->block != 128 && b->block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
-        if (b->units < EXA_UNITS_PER_CALLBACK || b->units > EXA_UNITS_SEPARATE)
+        if ((b->units & ~EXA_JT_FROM_JAC) < EXA_UNITS_PER_CALLBACK || (b->units & ~EXA_JT_FROM_JAC) > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
 
@@ -815,7 +859,7 @@ exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6) 
         out6[0] = S.block;
         out6[1] = S.epl;
         out6[2] = S.fused ? 1 : 0;
-        out6[3] = S.units;
+        out6[3] = S.units | (S.jt ? EXA_JT_FROM_JAC : 0);
         int64_t nt = S.ntiles + S.antiles;
         for (const auto& p : S.parts) nt += p.ntiles;
         out6[4] = nt;
@@ -830,9 +874,12 @@ exa_status exa_batch_set_schedule(exa_batch* b, uint32_t mask, int32_t block, in
         check_mask(mask);
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
+        const bool jt = (units & EXA_JT_FROM_JAC) != 0;
+        units &= ~EXA_JT_FROM_JAC;
         if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
-        set_batch_schedule(*b, mask, block, epl, fused != 0, units);
+        set_batch_schedule(*b, mask, block, epl, fused != 0, units, jt);
+        b->sched[mask].reduce_built = false;
         b->sched[mask].tuned = true;
         b->drop_graph();
     });
@@ -842,14 +889,16 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
     return guard([&] {
         if (!b || !out4) fail(EXA_EINVAL, "null argument");
         check_mask(mask);
-        int units = b->units;
+        int units = b->units & ~EXA_JT_FROM_JAC;
         bool fused = b->fuse;
+        bool jt = (b->units & EXA_JT_FROM_JAC) ? true : default_jt(*b, mask);
         auto it = b->sched.find(mask);
         if (it != b->sched.end()) {
             units = it->second.units;
             fused = it->second.fused;
+            jt = it->second.jt;
         }
-        const uint32_t em = eval_mask(mask);
+        const uint32_t em = tile_mask(eval_mask(mask), jt);
         int64_t er = 0, ew = 0, rr = 0, rw = 0;
         for (int i = 0; i < b->B; ++i) {
             const Model& M = b->models[i]->impl;
@@ -864,7 +913,7 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
                 er += r;
                 ew += w;
             }
-            reduce_bytes(M, mask, r, w);
+            reduce_bytes(M, mask, jt, r, w);
             rr += r;
             rw += w;
             // one objective partial is copied by the reduction launch
@@ -916,8 +965,7 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
                  "gradients cannot be evaluated in one batch");
         hipStream_t s = (hipStream_t)stream;
         // work buffers this mask needs
-        if (((mask & EXA_EV_GRAD) && !b->grad_direct_all) || (mask & EXA_EV_LAG) ||
-            ((mask & EXA_EV_JTPROD) && !(mask & EXA_EV_JAC)))
+        if (((mask & EXA_EV_GRAD) && !b->grad_direct_all) || (mask & (EXA_EV_LAG | EXA_EV_JTPROD)))
             need_buf(*b, kBufFo);
         if (mask & EXA_EV_HPROD) need_buf(*b, kBufHv);
         if (mask & EXA_EV_ADJ) need_buf(*b, kBufPar);
@@ -926,27 +974,38 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
             b->lag_tmp = (double*)b->mem.alloc(std::max<int64_t>(1, tot[kOffX]) * sizeof(double));
         auto it = b->sched.find(mask);
         if (it == b->sched.end() || !it->second.tuned) {
-            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units);
+            // the options' units, and the options' J^T w choice, else the default
+            const bool jt = (b->units & EXA_JT_FROM_JAC) ? true : default_jt(*b, mask);
+            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units & ~EXA_JT_FROM_JAC, jt);
+            b->sched[mask].reduce_built = false;
             if (b->autotune) tune_batch(*b, mask, *io, s);
             b->sched[mask].tuned = true;
             b->drop_graph();
         }
         exa_batch::Sched& S = b->sched[mask];
         if (!S.reduce_built) build_reductions(*b, S, mask);
-        if (!b->use_graph || b->timing.on) {
+        exa_batch::Key k;
+        std::memset(&k, 0, sizeof k);
+        k.mask = mask;
+        k.io = *io;
+        k.block = S.block;
+        k.epl = S.epl;
+        k.units = S.units;
+        k.fused = S.fused;
+        k.jt = S.jt;
+        // a graph is recorded when a call repeats the previous one (same
+        // pointers, sigma and schedule) and replayed while calls keep
+        // matching it; a call with new arguments launches directly, so
+        // arguments that change at every call (fresh output tensors) cost
+        // no recording
+        const bool replay = b->have_graph && k == b->key;
+        const bool record = !replay && b->have_last && k == b->last;
+        b->last = k;
+        b->have_last = true;
+        if (!b->use_graph || b->timing.on || (!replay && !record)) {
             run(*b, mask, *io, s);
         } else {
-            exa_batch::Key k;
-            k.mask = mask;
-            k.io = *io;
-            k.block = S.block;
-            k.epl = S.epl;
-            k.units = S.units;
-            k.fused = S.fused;
-            const bool same = b->have_graph && k.mask == b->key.mask && std::memcmp(&k.io, &b->key.io, sizeof k.io) == 0 &&
-                              k.block == b->key.block && k.epl == b->key.epl && k.units == b->key.units &&
-                              k.fused == b->key.fused;
-            if (!same) {
+            if (record) {
                 b->drop_graph();
                 hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
                 try {

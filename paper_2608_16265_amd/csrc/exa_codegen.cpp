@@ -1290,7 +1290,11 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
                                 "].inst[T.inst], T, lds); break;");
             }
         }
+        // the objective's tiles, and J^T w tiles when J^T w is not summed
+        // from the Jacobian values
         mode_cases(M_OBJ, cases);
+        mode_cases(M_JTPROD, cases);
+        lds = std::max(lds, mode_lds_doubles(M, M_JTPROD));
         cases.push_back(zero_case);
         multi_kernel("exa_k_onepass", lds, cases, 0);
     }

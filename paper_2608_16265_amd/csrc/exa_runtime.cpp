@@ -661,11 +661,15 @@ std::vector<int> eval_modes(uint32_t mask, bool jh) {
     else if (mask & EXA_EV_HESS)
         m.push_back(M_HESS);
     if (mask & EXA_EV_JPROD) m.push_back(M_JPROD);
-    // with the Jacobian in the same call, J^T w is summed from its values by
-    // the reduction launch: no tiles of its own
-    if ((mask & EXA_EV_JTPROD) && !(mask & EXA_EV_JAC)) m.push_back(M_JTPROD);
+    if (mask & EXA_EV_JTPROD) m.push_back(M_JTPROD);
     if (mask & EXA_EV_HPROD) m.push_back(M_HPROD);
     return m;
+}
+
+// The callbacks whose tiles a launch runs: a J^T w summed from the Jacobian
+// values of the same call has none.
+uint32_t tile_mask(uint32_t mask, bool jt_from_jac) {
+    return (jt_from_jac && (mask & EXA_EV_JAC)) ? mask & ~(uint32_t)EXA_EV_JTPROD : mask;
 }
 
 // Multi-unit mode that covers a mask's callbacks besides the objective in
@@ -673,8 +677,10 @@ std::vector<int> eval_modes(uint32_t mask, bool jh) {
 int combined_mode_of(uint32_t mask) {
     const uint32_t full = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS | EXA_EV_JPROD | EXA_EV_HPROD;
     const uint32_t ipm = EXA_EV_GRAD | EXA_EV_CONS | EXA_EV_JAC | EXA_EV_HESS;
-    if ((mask & full) == full) return M_SFULL;
-    if ((mask & ~(uint32_t)EXA_EV_OBJ) == ipm) return M_SIPM;
+    // the objective and J^T w run as tiles of their own beside the units
+    const uint32_t rest = mask & ~(uint32_t)(EXA_EV_OBJ | EXA_EV_JTPROD);
+    if ((rest & full) == full) return M_SFULL;
+    if (rest == ipm) return M_SIPM;
     return -1;
 }
 
@@ -695,7 +701,17 @@ std::vector<int> launch_modes(uint32_t mask, int units) {
     std::vector<int> m;
     if (mask & EXA_EV_OBJ) m.push_back(M_OBJ);
     m.push_back(combined_mode_of(mask));
+    if (mask & EXA_EV_JTPROD) m.push_back(M_JTPROD);
     return m;
+}
+
+// Without timing: J^T w of a mask with the Jacobian comes from the Jacobian
+// values when the evaluation launch writes more than the 256 MB last-level
+// cache holds (its contribution buffer would be read back from HBM), else
+// from its own tiles' buffer, which the reduction then reads from cache.
+bool default_jt_from_jac(const Model& M, uint32_t mask) {
+    if (!((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD)) || !M.dev || !M.dev->jtc_ok) return false;
+    return 8 * (M.nnzj + M.nnzh + M.fo_con_len) > ((int64_t)256 << 20);
 }
 
 namespace {
@@ -704,13 +720,15 @@ namespace {
 // fixed schedule), laid out as eight chunks that each hold an eighth of
 // every mode's tiles, so that the per-XCD ranges of the launch get the same
 // mix of work and contiguous point ranges.
-void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, int units) {
+void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, int units, bool jt_from_jac) {
     DeviceState& D = *M.dev;
     DeviceState::MultiSched& S = D.multi[mask];
-    units = valid_units(mask, units);
+    jt_from_jac = jt_from_jac && (mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && D.jtc_ok;
+    const uint32_t tm = tile_mask(mask, jt_from_jac);
+    units = valid_units(tm, units);
     const int64_t tp = (int64_t)block * epl;
     std::vector<std::vector<ExaTile>> per;
-    for (int mode : launch_modes(mask, units)) {
+    for (int mode : launch_modes(tm, units)) {
         std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused)
                                                : make_tiles(M, mode, 0, tp, fused);
         for (ExaTile& x : t) x.pat |= mode << EXA_MODE_SHIFT;
@@ -732,7 +750,10 @@ void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused,
     S.epl = epl;
     S.fused = fused;
     S.units = units;
+    S.jt_from_jac = jt_from_jac;
 }
+
+
 
 void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
     const DeviceState::MultiSched& S = M.dev->multi.at(mask);
@@ -754,7 +775,8 @@ void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
 // combined launch and keep the fastest (as tune() does for one callback).
 // Objective tiles keep their fixed size and summation order under every
 // candidate.
-void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
+void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, const std::function<void(bool)>& step) {
+    const bool jt0 = M.dev->multi[mask].jt_from_jac;
     const int blocks[] = {64, 128, 256};
     const int epls[] = {1, 2, 4, 8};
     std::vector<int> fuses = {0};
@@ -790,7 +812,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
         for (int f : fuses)
             for (int b : blocks)
                 for (int ep : epls) {
-                    set_multi_schedule(M, mask, b, ep, f != 0, cb);
+                    set_multi_schedule(M, mask, b, ep, f != 0, cb, jt0);
                     cands.push_back({time_it(3), b, ep, f, cb});
                 }
         // neighbouring schedules differ by less than one timing's noise: the
@@ -801,7 +823,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
         for (auto& c : cands) c.ms = 1e30f;
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
-                set_multi_schedule(M, mask, c.block, c.epl, c.fused != 0, c.comb);
+                set_multi_schedule(M, mask, c.block, c.epl, c.fused != 0, c.comb, jt0);
                 c.ms = std::min(c.ms, time_it(16));
             }
     } catch (...) {
@@ -812,7 +834,29 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb);
+    set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, jt0);
+    // J^T w with the Jacobian: its own tiles and buffer, or the Jacobian
+    // values; the whole step (evaluation and reductions) decides
+    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && M.dev->jtc_ok) {
+        float best[2] = {1e30f, 1e30f};
+        for (int round = 0; round < 3; ++round)
+            for (int jt = 0; jt < 2; ++jt) {
+                set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, jt != 0);
+                step(jt != 0);
+                hip_check(hipEventCreate(&e0), "hipEventCreate");
+                hip_check(hipEventCreate(&e1), "hipEventCreate");
+                hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                for (int r = 0; r < 16; ++r) step(jt != 0);
+                hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                best[jt] = std::min(best[jt], ms / 16);
+            }
+        set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, best[1] < best[0]);
+    }
     if (log_on())
         log_msg("tuned exa_eval mask " + std::to_string(mask) + ": block " + std::to_string(w.block) +
                 ", points per lane " + std::to_string(w.epl) + ", fused " + std::to_string(w.fused) + ", units " +
@@ -887,7 +931,7 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
 
 // Reduction launch of an exa_eval mask: maps (int32 when every position
 // fits), buffer entries once, outputs once; objective partials when several.
-void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
+void reduce_bytes(const Model& M, uint32_t mask, bool jt_from_jac, int64_t& rr, int64_t& rw) {
     rr = rw = 0;
     auto seg = [&](const SegMap& S) {
         const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
@@ -907,7 +951,7 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
         rw += 8 * nseg + 8 * P.nparts();
     };
     if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && !M.grad_direct) seg(M.grad_map);
-    if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) {
+    if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && jt_from_jac) {
         // sums of products of the Jacobian values: the map as above plus a
         // row per entry (4 bytes, in the lane records or beside the
         // positions), and each weight w[row] once
@@ -916,7 +960,7 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
     } else if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) {
         seg(M.jt_map);
     }
-    if ((mask & EXA_EV_LAG) && (mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) seg(M.jt_map);
+
     if (mask & EXA_EV_HPROD) seg(M.h_map);
     if (mask & EXA_EV_ADJ) seg(M.par_map);
     if (mask & EXA_EV_OBJ) {
@@ -1406,55 +1450,63 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
         ch.sigma = a->obj_weight;
         ch.out0 = a->hess;
     }
+    // the reductions of every selected callback, in one launch
+    auto reduce_of = [&](bool jt_from_jac) {
+        ExaReduce R;
+        std::memset(&R, 0, sizeof R);
+        R.ep_job = -1;
+        auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
+        if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
+        // the Lagrangian gradient with g written in place by the evaluation
+        // launch: J^T y goes straight into g as g = sigma * g + J^T y
+        const bool lag_ep = lag && M.grad_direct;
+        if (lag_ep) {
+            R.ep_job = R.njobs;
+            R.ax_alpha = lag_sigma;
+            job(D.jt_map, D.fo, a->g);
+        } else if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && jt_from_jac) {
+            // J^T w from the Jacobian values this launch wrote: w[row] times
+            // each entry, summed per variable in the order of jt_map
+            job(D.jtc_map, a->jac, a->jtw);
+            R.job[R.njobs - 1].wv = a->w;
+        } else if (mask & EXA_EV_JTPROD) {
+            job(D.jt_map, D.fo, a->jtw);
+        }
+        if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
+        if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0
+            R.part = D.tilesum;
+            R.npart = nobj;
+            R.f = a->f;
+        }
+        if (lag && !lag_ep) {  // out = sigma * grad + J^T y, after the reductions
+            R.ax_out = a->g;
+            R.ax_add = a->jtw;
+            R.ax_alpha = lag_sigma;
+            R.ax_n = M.nvar;
+        }
+        return R;
+    };
     auto it = D.multi.find(mask);
     if (it == D.multi.end() || !it->second.tuned) {
-        set_multi_schedule(M, mask, M.block, M.epl, M.fuse,
-                           M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS);
-        if (M.autotune) tune_multi(M, mask, mc, s);
+        const int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
+        set_multi_schedule(M, mask, M.block, M.epl, M.fuse, units, default_jt_from_jac(M, mask));
+        if (M.autotune)
+            tune_multi(M, mask, mc, s, [&](bool jt) {
+                raw_launch_multi(M, mask, mc, s);
+                hip_check(exa_launch_reduce(reduce_of(jt), s), "exa_eval reductions");
+            });
         D.multi[mask].tuned = true;
     }
+    const DeviceState::MultiSched& S = D.multi.at(mask);
     DeviceState::EvalTiming& Tm = D.timing;
     const bool timed = Tm.on && Tm.used < (int64_t)Tm.reduced.size();
     hipEvent_t* ev = timed ? &Tm.ev[4 * Tm.used] : nullptr;
     if (timed) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
     raw_launch_multi(M, mask, mc, s);
     if (timed) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
-
-    // the reductions of every selected callback, in one launch
-    ExaReduce R;
-    std::memset(&R, 0, sizeof R);
-    R.ep_job = -1;
-    auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
-    if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
-    // the Lagrangian gradient with g written in place by the evaluation
-    // launch: J^T y goes straight into g as g = sigma * g + J^T y
-    const bool lag_ep = lag && M.grad_direct;
-    if (lag_ep) {
-        R.ep_job = R.njobs;
-        R.ax_alpha = lag_sigma;
-        job(D.jt_map, D.fo, a->g);
-    } else if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC)) {
-        // J^T w from the Jacobian values this launch wrote: w[row] times
-        // each entry, summed per variable in the order of jt_map
-        job(D.jtc_map, a->jac, a->jtw);
-        R.job[R.njobs - 1].wv = a->w;
-    } else if (mask & EXA_EV_JTPROD) {
-        job(D.jt_map, D.fo, a->jtw);
-    }
-    if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
-    if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0
-        R.part = D.tilesum;
-        R.npart = nobj;
-        R.f = a->f;
-    }
+    const ExaReduce R = reduce_of(S.jt_from_jac);
     const bool reduce = R.njobs > 0 || R.part;
     if (timed && reduce) hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
-    if (lag && !lag_ep) {  // out = sigma * grad + J^T y, after the reductions
-        R.ax_out = a->g;
-        R.ax_add = a->jtw;
-        R.ax_alpha = lag_sigma;
-        R.ax_n = M.nvar;
-    }
     hip_check(exa_launch_reduce(R, s), "exa_eval reductions");
     if (timed && reduce) hip_check(hipEventRecord(ev[3], s), "hipEventRecord");
     if (timed) Tm.reduced[Tm.used++] = reduce ? 1 : 0;
@@ -1586,21 +1638,23 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        bool fused = M.fuse;
+        bool fused = M.fuse, jt = M.dev ? default_jt_from_jac(M, mask) : false;
         int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
         if (M.dev) {
             auto it = M.dev->multi.find(mask);
             if (it != M.dev->multi.end()) {
                 fused = it->second.fused;
                 units = it->second.units;
+                jt = it->second.jt_from_jac;
             }
         }
         int64_t rd = 0, wr = 0;
-        kernel_bytes(M, launch_modes(mask, units), fused, rd, wr);
+        const uint32_t tm = tile_mask(mask, jt);
+        kernel_bytes(M, launch_modes(tm, valid_units(tm, units)), fused, rd, wr);
         out4[0] = rd;
         out4[1] = wr;
         int64_t rr = 0, rw = 0;
-        reduce_bytes(M, mask, rr, rw);
+        reduce_bytes(M, mask, jt, rr, rw);
         out4[2] = rr;
         out4[3] = rw;
     });
@@ -1614,10 +1668,14 @@ exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
+        if ((units & ~EXA_JT_FROM_JAC) < EXA_UNITS_PER_CALLBACK)
+            fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
+        const bool jt = (units & EXA_JT_FROM_JAC) != 0;
+        units &= ~EXA_JT_FROM_JAC;
         if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_ONE_PASS)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         if (units == EXA_UNITS_ONE_PASS && M.eval_per_mode) units = EXA_UNITS_JAC_HESS;
-        set_multi_schedule(M, mask, block, epl, fused != 0, units);
+        set_multi_schedule(M, mask, block, epl, fused != 0, units, jt);
         M.dev->multi[mask].tuned = true;
     });
 }
@@ -1631,7 +1689,7 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
         out4[0] = it->second.block;
         out4[1] = it->second.epl;
         out4[2] = (it->second.fused ? 1 : 0) | (it->second.units == EXA_UNITS_ONE_PASS ? 2 : 0) |
-                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0);
+                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0) | (it->second.jt_from_jac ? 8 : 0);
         out4[3] = it->second.ntiles;
     });
 }

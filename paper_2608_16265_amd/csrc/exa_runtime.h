@@ -64,6 +64,9 @@ struct DeviceState {
     struct MultiSched {
         int block = 256, epl = 4;
         bool fused = false, tuned = false;
+        // J^T w of a mask with the Jacobian: summed from the Jacobian values
+        // (no tiles, no buffer) or from its own tiles' buffer
+        bool jt_from_jac = false;
         int units = EXA_UNITS_PER_CALLBACK;  // EXA_UNITS_*: which kernel and units run the tiles
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;
@@ -119,10 +122,17 @@ std::vector<int> eval_modes(uint32_t mask, bool jh);
 int combined_mode_of(uint32_t mask);
 bool has_jh(uint32_t mask);
 int valid_units(uint32_t mask, int units);
+// The callbacks whose tiles a launch runs (J^T w from the Jacobian values of
+// the same call has none).
+uint32_t tile_mask(uint32_t mask, bool jt_from_jac);
 std::vector<int> launch_modes(uint32_t mask, int units);
 // Algorithmic bytes of the reduction launch of a mask (maps, buffer entries,
 // outputs, objective partials when there are several).
-void reduce_bytes(const Model& M, uint32_t mask, int64_t& rd, int64_t& wr);
+void reduce_bytes(const Model& M, uint32_t mask, bool jt_from_jac, int64_t& rd, int64_t& wr);
+// Whether J^T w of a mask with the Jacobian is summed from the Jacobian
+// values when no tuning decides (the launch writes more than the last-level
+// cache holds).
+bool default_jt_from_jac(const Model& M, uint32_t mask);
 std::vector<char> compile_code(const std::string& src);
 // The code object of a source through the on-disk cache in `dir` (empty: no
 // cache); *hit tells whether it was read from the cache.

@@ -184,3 +184,25 @@ def test_fixed_schedule_gives_the_same_bits():
         ref_m.set_eval_schedule(every, 128, 0)
     with pytest.raises(Exception):
         ref_m.set_eval_schedule(every, 128, 1, units=3)
+
+
+@pytest.mark.parametrize("units", ["per_callback", "jac_hess", "one_pass"])
+@pytest.mark.parametrize("name", ["acopf600", "pde50", "star", "goddard_long", "two_stage", "alias", "empty"])
+def test_jtprod_from_jacobian_values(name, units):
+    """J^T w summed from the Jacobian values of the same call (no J^T w
+    tiles, no contribution buffer) gives the bits of exa_jtprod, whose
+    contributions are the Jacobian entries times w."""
+    _need_gpu()
+    from paper_2608_16265_amd import ExaModel
+    w = CASES[name]()
+    em = ExaModel(w.model)
+    X, Y, sig, V, W = _inputs(w, em, seed=3)
+    ref = _singles(em, X, Y, sig, V, W)
+    for mask in (ALL, ("jac", "jtprod"), ("jac", "hess", "jtprod", "hprod"), ("grad", "jac", "jtprod")):
+        for jt in (True, False):
+            em.set_eval_schedule(mask, 128, 2, True, units, jt_from_jac=jt)
+            outs = {FIELD[cb]: _nan_like(ref[FIELD[cb]]) for cb in mask}
+            em.evaluate(X, Y, sig, V, W, **outs)
+            for k, t in outs.items():
+                assert np.array_equal(host(t), ref[k]), f"{name} {mask} jt={jt}: {k}"
+            assert em.eval_schedule(mask)["jt_from_jac"] == int(jt), mask
