@@ -366,8 +366,9 @@ typedef struct exa_eval_args {
 exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream);
 /* The schedule of exa_eval for a mask: out4 = workgroup size, points per
  * lane, fused (bit 0) | one pass per point for all callbacks (bit 1) |
- * Jacobian + Hessian units (bit 2) | J^T w from the Jacobian values (bit 3),
- * number of tiles.  EXA_ESTATE until the mask's first exa_eval call. */
+ * Jacobian + Hessian units (bit 2) | J^T w from the Jacobian values (bit 3) |
+ * unstaged stores (bit 4), number of tiles.  EXA_ESTATE until the mask's
+ * first exa_eval call. */
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 /* Units of an exa_eval launch: one tile per callback and point, the
  * Jacobian and the Hessian apart (their tiles then run in a kernel with a
@@ -387,6 +388,11 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
  * Jacobian values are used when the launch writes more than the 256 MB
  * last-level cache holds. */
 #define EXA_JT_FROM_JAC 0x10
+/* Flag OR'ed into `units` as EXA_JT_FROM_JAC: Jacobian and Hessian values
+ * leave each lane as its own stores instead of being staged through LDS into
+ * contiguous 16-byte stores (a schedule choice the tuners time; the values
+ * are the same). */
+#define EXA_UNSTAGED 0x20
 /* Batched evaluation only: every callback's tiles in a launch of its own,
  * one after another (each kernel with the register budget of its own units). */
 #define EXA_UNITS_SEPARATE 3
@@ -456,7 +462,7 @@ exa_status exa_compile_check(const exa_model* m);
 exa_status exa_kernel_bytes(const exa_model* m, int32_t callback, int64_t* read_bytes,
                             int64_t* write_bytes);
 /* The schedule a callback's kernel uses: out4 = workgroup size, points per
- * lane, fused (1/0), number of tiles. */
+ * lane, fused (bit 0) | unstaged stores (bit 1), number of tiles. */
 exa_status exa_schedule(const exa_model* m, int32_t callback, int64_t* out4);
 
 /* Layout of pattern p (declaration position): out8 = kind, ndata, o1step,
@@ -595,7 +601,7 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
 exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4);
 /* Schedule of a mask: out6 = workgroup size, points per lane, fused (0/1),
  * units (EXA_UNITS_*, | EXA_JT_FROM_JAC when J^T w is summed from the
- * Jacobian values), number of evaluation tiles, the autotuner's best
+ * Jacobian values, | EXA_UNSTAGED), number of evaluation tiles, the autotuner's best
  * evaluation-launch time in nanoseconds (0 if not tuned).  EXA_ESTATE before
  * the mask's first call. */
 exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6);

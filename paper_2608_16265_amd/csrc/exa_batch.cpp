@@ -78,6 +78,7 @@ struct exa_batch {
         int block = 256, epl = 4, units = EXA_UNITS_PER_CALLBACK;
         bool fused = true, tuned = false;
         bool jt = false;                     // J^T w from the Jacobian values (EXA_JT_FROM_JAC)
+        bool unstaged = false;               // each lane's own output stores (EXA_UNSTAGED)
         std::vector<std::vector<int>> bins;  // instances per XCD
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;
@@ -441,10 +442,12 @@ ExaMulti call_records(exa_batch& b, uint32_t mask, const exa_batch_io& io) {
     ExaMulti mc;
     std::memset(&mc, 0, sizeof mc);
     const bool lag = (mask & EXA_EV_LAG) != 0;
+    const bool unstaged = b.sched.count(mask) && b.sched.at(mask).unstaged;
     for (int mode = 0; mode < M_COUNT; ++mode) {
         ExaCall& c = mc.c[mode];
         c.inst = b.inst;
         c.x = io.x;
+        c.unstaged = unstaged ? 1 : 0;
         switch (mode) {
             case M_OBJ: c.out0 = b.buf[kBufTile]; break;
             case M_GRAD:
@@ -656,11 +659,30 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
         (void)hipEventDestroy(e1);
         throw;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
     set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units, jt0);
     b.sched[mask].tuned_ns = (int64_t)(w.ms * 1e6);
+    // staged or each lane's own stores of the Jacobian and Hessian values
+    if (mask & (EXA_EV_JAC | EXA_EV_HESS)) {
+        float best[2] = {1e30f, 1e30f};
+        for (int round = 0; round < 2; ++round)
+            for (int u = 0; u < 2; ++u) {
+                b.sched[mask].unstaged = u != 0;
+                const ExaMulti r2 = call_records(b, mask, io);
+                launch_eval(b, mask, r2, s);
+                hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                for (int r = 0; r < 6; ++r) launch_eval(b, mask, r2, s);
+                hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                best[u] = std::min(best[u], ms / 6);
+            }
+        b.sched[mask].unstaged = best[1] < best[0];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const bool unstaged = b.sched[mask].unstaged;
     // J^T w with the Jacobian: its own tiles and buffer, or the Jacobian
     // values; the whole call (evaluation and reductions) decides
     if ((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && b.jtc_ok) {
@@ -669,6 +691,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
         for (int round = 0; round < 2; ++round)
             for (int jt = 0; jt < 2; ++jt) {
                 set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units, jt != 0);
+                b.sched[mask].unstaged = unstaged;
                 units[jt] = b.sched[mask].units;
                 build_reductions(b, b.sched[mask], mask);
                 if ((mask & EXA_EV_JTPROD) && !jt) need_buf(b, kBufFo);
@@ -687,6 +710,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
             }
         const bool jt = best[1] < best[0];
         set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, units[jt], jt);
+        b.sched[mask].unstaged = unstaged;
         b.sched[mask].reduce_built = false;
     }
     if (log_on())
@@ -753,7 +777,8 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         }
         if (b->block != 64 && b->block != 128 && b->block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
-        if ((b->units & ~EXA_JT_FROM_JAC) < EXA_UNITS_PER_CALLBACK || (b->units & ~EXA_JT_FROM_JAC) > EXA_UNITS_SEPARATE)
+        if ((b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) < EXA_UNITS_PER_CALLBACK ||
+            (b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
 
@@ -859,7 +884,7 @@ exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6) 
         out6[0] = S.block;
         out6[1] = S.epl;
         out6[2] = S.fused ? 1 : 0;
-        out6[3] = S.units | (S.jt ? EXA_JT_FROM_JAC : 0);
+        out6[3] = S.units | (S.jt ? EXA_JT_FROM_JAC : 0) | (S.unstaged ? EXA_UNSTAGED : 0);
         int64_t nt = S.ntiles + S.antiles;
         for (const auto& p : S.parts) nt += p.ntiles;
         out6[4] = nt;
@@ -874,11 +899,12 @@ exa_status exa_batch_set_schedule(exa_batch* b, uint32_t mask, int32_t block, in
         check_mask(mask);
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
-        const bool jt = (units & EXA_JT_FROM_JAC) != 0;
-        units &= ~EXA_JT_FROM_JAC;
+        const bool jt = (units & EXA_JT_FROM_JAC) != 0, unstaged = (units & EXA_UNSTAGED) != 0;
+        units &= ~(EXA_JT_FROM_JAC | EXA_UNSTAGED);
         if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         set_batch_schedule(*b, mask, block, epl, fused != 0, units, jt);
+        b->sched[mask].unstaged = unstaged;
         b->sched[mask].reduce_built = false;
         b->sched[mask].tuned = true;
         b->drop_graph();
@@ -889,7 +915,7 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
     return guard([&] {
         if (!b || !out4) fail(EXA_EINVAL, "null argument");
         check_mask(mask);
-        int units = b->units & ~EXA_JT_FROM_JAC;
+        int units = b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED);
         bool fused = b->fuse;
         bool jt = (b->units & EXA_JT_FROM_JAC) ? true : default_jt(*b, mask);
         auto it = b->sched.find(mask);
@@ -976,7 +1002,8 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
         if (it == b->sched.end() || !it->second.tuned) {
             // the options' units, and the options' J^T w choice, else the default
             const bool jt = (b->units & EXA_JT_FROM_JAC) ? true : default_jt(*b, mask);
-            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units & ~EXA_JT_FROM_JAC, jt);
+            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED), jt);
+            b->sched[mask].unstaged = (b->units & EXA_UNSTAGED) != 0;
             b->sched[mask].reduce_built = false;
             if (b->autotune) tune_batch(*b, mask, *io, s);
             b->sched[mask].tuned = true;

@@ -882,12 +882,19 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         } else if (!scalar_mode(j.mode)) {
             // this job's outputs leave registers as soon as they are complete
             const bool final_out = j.mode == M_JAC || j.mode == M_HESS;
+            const std::string st = std::to_string(out_step(P, j.mode)), nt = final_out ? "true" : "false";
+            const std::string args = "(" + dest(P, j.mode, pd, j.out) + ", " + oname(j) + ", npts, lds);";
             std::string line;
-            if (staged(P, j.mode))
-                line += "exa_store<" + std::to_string(out_step(P, j.mode)) + ", " + (final_out ? "true" : "false") + ">(";
+            if (staged(P, j.mode) && out_step(P, j.mode) > 1)
+                // staged through LDS into contiguous 16-byte stores, unless the
+                // call asks for each lane's own stores (a schedule choice; the
+                // flag is the same for the whole workgroup)
+                line = "if (" + call(j.mode) + ".unstaged) exa_store_direct<" + st + ", " + nt + ">" + args +
+                       " else exa_store<" + st + ", " + nt + ">" + args;
+            else if (staged(P, j.mode))
+                line = "exa_store<" + st + ", " + nt + ">" + args;
             else
-                line += "exa_store_direct<" + std::to_string(out_step(P, j.mode)) + ">(";
-            line += dest(P, j.mode, pd, j.out) + ", " + oname(j) + ", npts, lds);";
+                line = "exa_store_direct<" + st + ", " + nt + ">" + args;
             e.raw(line);
         }
     }
@@ -1138,12 +1145,16 @@ __device__ __forceinline__ void exa_store_soa(double* __restrict__ base, long lo
         for (int s = 0; s < ST; ++s) base[s * n + k] = o[s];
     }
 }
-// Direct (unstaged) variant for slices too wide for LDS.
-template <int ST>
+// Direct (unstaged) variant: each lane stores its own slice (slices too wide
+// for LDS, or when the call asks for unstaged stores); NT as in exa_store.
+template <int ST, bool NT>
 __device__ __forceinline__ void exa_store_direct(double* __restrict__ dst, const double* o, int npts, double*) {
     if ((int)threadIdx.x < npts) {
 #pragma unroll
-        for (int s = 0; s < ST; ++s) dst[threadIdx.x * ST + s] = o[s];
+        for (int s = 0; s < ST; ++s) {
+            if (NT) __builtin_nontemporal_store(o[s], &dst[threadIdx.x * ST + s]);
+            else dst[threadIdx.x * ST + s] = o[s];
+        }
     }
 }
 // Objective tiles are summed over 256 virtual lanes whatever the workgroup

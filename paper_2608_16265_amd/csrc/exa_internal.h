@@ -92,7 +92,7 @@ void set_last_error(const std::string& msg);
         double* out1;                                                            \
         double sigma;                                                            \
         int direct;                                                              \
-        int pad2;                                                                \
+        int unstaged;                                                            \
     };                                                                           \
     struct ExaMulti {                                                            \
         const struct ExaTile* tiles;                                             \

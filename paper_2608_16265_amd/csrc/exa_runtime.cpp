@@ -557,6 +557,7 @@ void raw_launch(Model& M, int mode, ExaCall call, hipStream_t s) {
     call.ntiles = S.ntiles;
     call.per_xcd = (S.ntiles + 7) / 8;
     call.inst = D.inst;
+    call.unstaged = S.unstaged ? 1 : 0;
     const int64_t grid = 8 * call.per_xcd;
     void* args[] = {&call};
     hip_check(hipModuleLaunchKernel(D.module->fn[mode], (unsigned)grid, 1, 1, (unsigned)S.block, 1, 1, 0, s,
@@ -586,9 +587,13 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
+    // staged or each lane's own stores: only modes with multi-entry final outputs
+    const bool stores = mode == M_JAC || mode == M_HESS || mode == M_JH;
+    std::vector<int> unst = {0};
+    if (stores) unst.push_back(1);
     struct Cand {
         float ms;
-        int block, epl, fused;
+        int block, epl, fused, unstaged;
     };
     auto time_it = [&](int reps) {
         raw_launch(M, mode, call, s);
@@ -602,11 +607,13 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
     };
     std::vector<Cand> cands;
     try {
+        for (int u : unst)
         for (int f : fuses)
             for (int b : blocks)
                 for (int ep : epls) {
                     set_schedule(M, mode, b, ep, f != 0);
-                    cands.push_back({time_it(3), b, ep, f});
+                    M.dev->sched[mode].unstaged = u != 0;
+                    cands.push_back({time_it(3), b, ep, f, u});
                 }
         // as in tune_multi: the fastest few again, longer, in turns
         std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
@@ -615,6 +622,7 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
                 set_schedule(M, mode, c.block, c.epl, c.fused != 0);
+                M.dev->sched[mode].unstaged = c.unstaged != 0;
                 c.ms = std::min(c.ms, time_it(12));
             }
     } catch (...) {
@@ -626,11 +634,12 @@ void tune(Model& M, int mode, const ExaCall& call, hipStream_t s) {
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
     set_schedule(M, mode, w.block, w.epl, w.fused != 0);
+    M.dev->sched[mode].unstaged = w.unstaged != 0;
     M.dev->sched[mode].tuned = true;
     if (log_on())
         log_msg("tuned " + kernel_name(mode) + ": block " + std::to_string(w.block) + ", points per lane " +
-                std::to_string(w.epl) + ", fused " + std::to_string(w.fused) + " (" + std::to_string(w.ms * 1e3) +
-                " us)");
+                std::to_string(w.epl) + ", fused " + std::to_string(w.fused) + ", unstaged " +
+                std::to_string(w.unstaged) + " (" + std::to_string(w.ms * 1e3) + " us)");
 }
 }  // namespace
 
@@ -761,6 +770,7 @@ void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
     mc.tiles = S.tiles;
     mc.ntiles = S.ntiles;
     mc.per_xcd = (S.ntiles + 7) / 8;
+    for (ExaCall& c : mc.c) c.unstaged = S.unstaged ? 1 : 0;
     void* args[] = {&mc};
     const Module& K = *M.dev->module;
     hipFunction_t fn = S.units == EXA_UNITS_ONE_PASS   ? K.fn_onepass
@@ -835,13 +845,36 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
     set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, jt0);
-    // J^T w with the Jacobian: its own tiles and buffer, or the Jacobian
-    // values; the whole step (evaluation and reductions) decides
+    // staged or each lane's own stores, then (with the Jacobian and J^T w)
+    // J^T w from its own tiles and buffer or from the Jacobian values: the
+    // whole step (evaluation and reductions) decides
+    if (mask & (EXA_EV_JAC | EXA_EV_HESS)) {
+        float best[2] = {1e30f, 1e30f};
+        for (int round = 0; round < 3; ++round)
+            for (int u = 0; u < 2; ++u) {
+                M.dev->multi[mask].unstaged = u != 0;
+                step(jt0);
+                hip_check(hipEventCreate(&e0), "hipEventCreate");
+                hip_check(hipEventCreate(&e1), "hipEventCreate");
+                hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                for (int r = 0; r < 16; ++r) step(jt0);
+                hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                best[u] = std::min(best[u], ms / 16);
+            }
+        M.dev->multi[mask].unstaged = best[1] < best[0];
+    }
+    const bool unstaged = M.dev->multi[mask].unstaged;
     if ((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && M.dev->jtc_ok) {
         float best[2] = {1e30f, 1e30f};
         for (int round = 0; round < 3; ++round)
             for (int jt = 0; jt < 2; ++jt) {
                 set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, jt != 0);
+                M.dev->multi[mask].unstaged = unstaged;
                 step(jt != 0);
                 hip_check(hipEventCreate(&e0), "hipEventCreate");
                 hip_check(hipEventCreate(&e1), "hipEventCreate");
@@ -856,6 +889,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
                 best[jt] = std::min(best[jt], ms / 16);
             }
         set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, best[1] < best[0]);
+        M.dev->multi[mask].unstaged = unstaged;
     }
     if (log_on())
         log_msg("tuned exa_eval mask " + std::to_string(mask) + ": block " + std::to_string(w.block) +
@@ -1668,14 +1702,15 @@ exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
-        if ((units & ~EXA_JT_FROM_JAC) < EXA_UNITS_PER_CALLBACK)
+        if ((units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) < EXA_UNITS_PER_CALLBACK)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
-        const bool jt = (units & EXA_JT_FROM_JAC) != 0;
-        units &= ~EXA_JT_FROM_JAC;
+        const bool jt = (units & EXA_JT_FROM_JAC) != 0, unstaged = (units & EXA_UNSTAGED) != 0;
+        units &= ~(EXA_JT_FROM_JAC | EXA_UNSTAGED);
         if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_ONE_PASS)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         if (units == EXA_UNITS_ONE_PASS && M.eval_per_mode) units = EXA_UNITS_JAC_HESS;
         set_multi_schedule(M, mask, block, epl, fused != 0, units, jt);
+        M.dev->multi[mask].unstaged = unstaged;
         M.dev->multi[mask].tuned = true;
     });
 }
@@ -1689,7 +1724,8 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
         out4[0] = it->second.block;
         out4[1] = it->second.epl;
         out4[2] = (it->second.fused ? 1 : 0) | (it->second.units == EXA_UNITS_ONE_PASS ? 2 : 0) |
-                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0) | (it->second.jt_from_jac ? 8 : 0);
+                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0) | (it->second.jt_from_jac ? 8 : 0) |
+                  (it->second.unstaged ? 16 : 0);
         out4[3] = it->second.ntiles;
     });
 }
@@ -1746,7 +1782,7 @@ exa_status exa_schedule(const exa_model* m, int32_t callback, int64_t* out4) {
         const DeviceState::Sched& S = m->impl.dev->sched[mode];
         out4[0] = S.block;
         out4[1] = S.epl;
-        out4[2] = S.fused ? 1 : 0;
+        out4[2] = (S.fused ? 1 : 0) | (S.unstaged ? 2 : 0);
         out4[3] = S.ntiles;
     });
 }

@@ -57,6 +57,7 @@ struct DeviceState {
     struct Sched {
         int block = 256, epl = 4;
         bool fused = false, tuned = false;
+        bool unstaged = false;  // each lane stores its own output slice (no LDS staging)
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;
     } sched[M_COUNT];
@@ -67,6 +68,7 @@ struct DeviceState {
         // J^T w of a mask with the Jacobian: summed from the Jacobian values
         // (no tiles, no buffer) or from its own tiles' buffer
         bool jt_from_jac = false;
+        bool unstaged = false;  // each lane stores its own output slices
         int units = EXA_UNITS_PER_CALLBACK;  // EXA_UNITS_*: which kernel and units run the tiles
         ExaTile* tiles = nullptr;
         int64_t ntiles = 0;

@@ -199,10 +199,11 @@ def test_jtprod_from_jacobian_values(name, units):
     X, Y, sig, V, W = _inputs(w, em, seed=3)
     ref = _singles(em, X, Y, sig, V, W)
     for mask in (ALL, ("jac", "jtprod"), ("jac", "hess", "jtprod", "hprod"), ("grad", "jac", "jtprod")):
-        for jt in (True, False):
-            em.set_eval_schedule(mask, 128, 2, True, units, jt_from_jac=jt)
+        for jt, unstaged in ((True, False), (False, False), (True, True), (False, True)):
+            em.set_eval_schedule(mask, 128, 2, True, units, jt_from_jac=jt, unstaged=unstaged)
             outs = {FIELD[cb]: _nan_like(ref[FIELD[cb]]) for cb in mask}
             em.evaluate(X, Y, sig, V, W, **outs)
             for k, t in outs.items():
-                assert np.array_equal(host(t), ref[k]), f"{name} {mask} jt={jt}: {k}"
-            assert em.eval_schedule(mask)["jt_from_jac"] == int(jt), mask
+                assert np.array_equal(host(t), ref[k]), f"{name} {mask} jt={jt} unstaged={unstaged}: {k}"
+            sch = em.eval_schedule(mask)
+            assert sch["jt_from_jac"] == int(jt) and sch["unstaged"] == int(unstaged), mask
