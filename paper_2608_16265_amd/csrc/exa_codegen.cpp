@@ -1134,6 +1134,21 @@ __device__ __forceinline__ void exa_store(double* __restrict__ dst, const double
     }
     __syncthreads();
 }
+// Zeros to dst[0 .. n) by the whole workgroup: 16-byte stores from dst's
+// first 16-byte boundary on, the element before it and an odd last element
+// on their own (ordinary stores: a reduction may read the entries back).
+__device__ __forceinline__ void exa_zero_fill(double* __restrict__ dst, long long n) {
+    const long long h = ((((unsigned long long)dst >> 3) & 1ull) && n > 0) ? 1 : 0;
+    const long long n2 = (n - h) >> 1;
+    exa_d2 z;
+    z.x = 0.0;
+    z.y = 0.0;
+    for (long long i = threadIdx.x; i < n2; i += blockDim.x) *(exa_d2*)(dst + h + 2 * i) = z;
+    if (threadIdx.x == 0) {
+        if (h) dst[0] = 0.0;
+        if (h + 2 * n2 < n) dst[n - 1] = 0.0;
+    }
+}
 // Slot-major store to a work buffer: slot s of data point k at
 // base[s * n + k], n the padded slot stride (lanes past the end of the tile
 // store nothing).
@@ -1227,9 +1242,8 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
                             std::to_string(kv.first) + "(C, I, T, lds); break;");
         }
         if (mode == M_GRAD)  // entries of g no objective term touches
-            cases.push_back("case " + std::to_string(EXA_ZERO_TILE) +
-                            ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) "
-                            "C.out0[I.off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;");
+            cases.push_back("case " + std::to_string(EXA_ZERO_TILE) + ": exa_zero_fill(C.out0 + I.off[" +
+                            std::to_string(EXA_OFF_X) + "] + T.start, T.count); break;");
         kernel(kernel_name(mode), mode_lds_doubles(M, mode), cases);
     }
     // Several callbacks in one launch: a tile's mode sits above
@@ -1266,8 +1280,8 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
     };
     const std::string G = "C.c[" + std::to_string(M_GRAD) + "]";
     const std::string zero_case = "case " + std::to_string((M_GRAD << EXA_MODE_SHIFT) | EXA_ZERO_TILE) +
-                                  ": for (long long i = T.start + threadIdx.x; i < T.start + T.count; i += blockDim.x) " +
-                                  G + ".out0[" + G + ".inst[T.inst].off[" + std::to_string(EXA_OFF_X) + "] + i] = 0.0; break;";
+                                  ": exa_zero_fill(" + G + ".out0 + " + G + ".inst[T.inst].off[" +
+                                  std::to_string(EXA_OFF_X) + "] + T.start, T.count); break;";
     // every unit's tiles share a kernel's register budget: ask for at least
     // four waves per SIMD, so that one wave of the launch fits on the chip at
     // once.  The Jacobian + Hessian units need the most registers, so they

@@ -379,12 +379,16 @@ void build_device(Model& M) {
 // (in-place gradient only).
 void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
     if (!M.grad_direct) return;
+    // a zero tile is a plain fill: far more entries than a tile of points
+    // (16-byte stores, 16 entries per lane of a 256-wide workgroup), so the
+    // fill takes a few workgroups instead of one per tile of points
+    const int64_t tz = std::max<int64_t>(tp, kZeroTileEntries);
     for (auto& z : M.grad_zero)
-        for (int64_t s = 0; s < z.second; s += tp) {
+        for (int64_t s = 0; s < z.second; s += tz) {
             ExaTile t{};
             t.pat = EXA_ZERO_TILE;
             t.start = z.first + s;
-            t.count = std::min(tp, z.second - s);
+            t.count = std::min(tz, z.second - s);
             t.slot = (int64_t)tiles.size();
             tiles.push_back(t);
         }

@@ -113,7 +113,9 @@ void launch_mode_untuned(Model& M, int mode, ExaCall call, hipStream_t s);
 // plus one for long segments).
 void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s);
 exa_status guard_status(const std::function<void()>& f);
-// Tiles that write zeros to the gradient entries no objective term touches.
+// Tiles that write zeros to the gradient entries no objective term touches,
+// kZeroTileEntries entries each (more when a tile of points is larger).
+constexpr int64_t kZeroTileEntries = 4096;
 void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles);
 bool has_fusable_group(const Model& M, int mode);
 // Modes of an exa_eval mask (with jh: Jacobian + Hessian as JH units), the
