@@ -902,13 +902,17 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
 
     // ---- augmentation pulls of the scalar jobs (cons values, jprod tangents)
     // Base rows pull the augmentation terms that add to them, in declaration
-    // order of the augmentations, points ascending.  The first round of up to
-    // R terms of every augmentation is evaluated before any is added, so that
-    // their chains of dependent loads (row bounds, term index, data, x)
-    // overlap; the additions keep the order.
+    // order of the augmentations, points ascending.  Terms are evaluated in
+    // rounds of R before any of the round is added, so that their chains of
+    // dependent loads (row bounds, term index, data, x) overlap; the first
+    // round of every pull is issued before any addition.  Augmentations over
+    // the same data arrays whose rows come from the same index column and
+    // offset have the same row lists (their targets are members of this unit,
+    // hence of one size): they share one walk (row bounds and term indices).
+    // The additions keep the order.
     struct Pull {
         std::string out;
-        int a, R, mode;
+        int a, R, mode, walk;
     };
     std::vector<Pull> pulls;
     for (const Job& j : jobs) {
@@ -917,38 +921,56 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         for (int a : P.augs) {
             if (M.pats[a].ndata == 0) continue;
             const size_t nn = M.pats[a].nodes.size();
-            pulls.push_back({oname(j), a, nn <= 16 ? 4 : nn <= 64 ? 2 : 1, j.mode});
+            pulls.push_back({oname(j), a, nn <= 16 ? 4 : nn <= 64 ? 2 : 1, j.mode, a});
         }
     }
+    for (Pull& q : pulls)
+        for (const Pull& r : pulls)
+            if (same_walk(M, r.a, q.a)) {
+                q.walk = r.a;
+                break;
+            }
     // at most kPullTerms terms in flight per lane, shared by the pulls, so
-    // that the round does not cost occupancy
-    constexpr int kPullTerms = 8;
+    // that a round does not cost occupancy
+    constexpr int kPullTerms = 16;
     const int share = pulls.empty() ? 1 : std::max(1, kPullTerms / (int)pulls.size());
     for (Pull& q : pulls) q.R = std::min(q.R, share);
-    std::set<int> bounds;
-    for (const Pull& q : pulls) {
-        if (!bounds.insert(q.a).second) continue;
-        const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
-        os << "            const int ab" << a << " = " << pa << ".rptr[k], ae" << a << " = " << pa << ".rptr[k + 1];\n";
+    // one round size per walk: the smallest of its pulls'
+    std::map<int, int> walk_R;
+    for (const Pull& q : pulls) walk_R[q.walk] = walk_R.count(q.walk) ? std::min(walk_R[q.walk], q.R) : q.R;
+    for (Pull& q : pulls) q.R = walk_R[q.walk];
+    auto wname = [](int w) { return std::to_string(w); };
+    for (auto& wr : walk_R) {
+        const std::string pa = "I.pat[" + wname(wr.first) + "]", w = wname(wr.first);
+        os << "            const int ab" << w << " = " << pa << ".rptr[k], ae" << w << " = " << pa << ".rptr[k + 1];\n";
+        for (int i = 0; i < wr.second; ++i)
+            os << "            const long long at" << w << "_" << i << " = " << pa << ".ridx[exa_term(ab" << w << " + "
+               << i << ", ae" << w << ")];\n";
     }
     auto aq = [&](const Pull& q, int i) {
         return "aq" + std::to_string(q.a) + "_" + mode_name(q.mode) + "_" + std::to_string(i);
     };
     auto fn_of = [&](const Pull& q) {
-        return std::string("aug_") + mode_name(q.mode) + "_" + std::to_string(q.a) + "(" + call(q.mode) + ", I, (long long)";
+        return std::string("aug_") + mode_name(q.mode) + "_" + std::to_string(q.a) + "(" + call(q.mode) + ", I, ";
     };
-    for (const Pull& q : pulls) {
-        const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+    for (const Pull& q : pulls)
         for (int i = 0; i < q.R; ++i)
-            os << "            const double " << aq(q, i) << " = " << fn_of(q) << pa << ".ridx[exa_term(ab" << a << " + "
-               << i << ", ae" << a << ")]);\n";
-    }
+            os << "            const double " << aq(q, i) << " = " << fn_of(q) << "at" << wname(q.walk) << "_" << i
+               << ");\n";
     for (const Pull& q : pulls) {
-        const std::string pa = "I.pat[" + std::to_string(q.a) + "]", a = std::to_string(q.a);
+        const std::string w = wname(q.walk), pa = "I.pat[" + w + "]";
         for (int i = 0; i < q.R; ++i)
-            os << "            if (ab" << a << " + " << i << " < ae" << a << ") " << q.out << " += " << aq(q, i) << ";\n";
-        os << "            for (int j = ab" << a << " + " << q.R << "; j < ae" << a << "; ++j) " << q.out << " += "
-           << fn_of(q) << pa << ".ridx[j]);\n";
+            os << "            if (ab" << w << " + " << i << " < ae" << w << ") " << q.out << " += " << aq(q, i) << ";\n";
+        // later rounds: the round's term indices and values first, then
+        // its additions in order
+        os << "            for (int j0 = ab" << w << " + " << q.R << "; j0 < ae" << w << "; j0 += " << q.R << ") {\n";
+        for (int i = 0; i < q.R; ++i)
+            os << "                const double u" << i << " = " << fn_of(q) << "(long long)" << pa << ".ridx["
+               << (i == 0 ? std::string("j0") : "exa_term(j0 + " + std::to_string(i) + ", ae" + w + ")") << "]);\n";
+        for (int i = 0; i < q.R; ++i)
+            os << "                " << (i ? "if (j0 + " + std::to_string(i) + " < ae" + w + ") " : std::string())
+               << q.out << " += u" << i << ";\n";
+        os << "            }\n";
     }
     os << "        }\n";
 

@@ -293,6 +293,10 @@ struct Model {
 // exa_model.cpp
 void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats);
 std::string pattern_signature(const Model& M);
+// Augmentations a and b have the same row lists (rptr / ridx): the same data
+// arrays, rows from the same index column plus the same offset, and targets
+// of one size.  The generated pulls of such augmentations share one walk.
+bool same_walk(const Model& M, int a, int b);
 
 // exa_codegen.cpp
 #define EXA_BLOCK_MAX 256

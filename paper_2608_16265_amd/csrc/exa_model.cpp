@@ -514,6 +514,15 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     M.signature = pattern_signature(M);
 }
 
+bool same_walk(const Model& M, int a, int b) {
+    if (a == b) return true;
+    const Pattern& A = M.pats[a];
+    const Pattern& B = M.pats[b];
+    return A.kind == EXA_AUG && B.kind == EXA_AUG && A.group >= 0 && A.group == B.group &&
+           A.row_icol == B.row_icol && A.row_off == B.row_off &&
+           M.pats[A.target].ndata == M.pats[B.target].ndata;
+}
+
 std::string pattern_signature(const Model& M) {
     std::ostringstream os;
     os.precision(17);
@@ -529,6 +538,13 @@ std::string pattern_signature(const Model& M) {
             os << n.op << "," << n.a << "," << n.b << "," << n.col << "," << n.val << "," << n.slot
                << ";";
         os << "G" << P.group << ":";
+        // which augmentation pulls share a walk is fixed by the code
+        if (P.kind == EXA_AUG) {
+            int w = -1;
+            for (int q = 0; q < P.index && w < 0; ++q)
+                if (same_walk(M, q, P.index)) w = q;
+            os << "W" << w << ":";
+        }
         for (int r : P.vg) os << r << ",";
         os << "|";
         for (int r : P.pg) os << r << ",";
