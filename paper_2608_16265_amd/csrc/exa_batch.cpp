@@ -239,7 +239,7 @@ void instance_tiles(const exa_batch& b, int i, const std::vector<int>& modes, bo
     const Model& M = b.models[i]->impl;
     for (int mode : modes) {
         std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, i, (int64_t)kObjBlock * kObjEpl, kObjFused)
-                                               : make_tiles(M, mode, i, tp, fused);
+                                               : make_tiles(M, mode, i, tp, fused, true);
         if (mode == M_GRAD || (multi_unit_mode(mode) && (em & EXA_EV_GRAD))) {
             std::vector<ExaTile> z;
             add_zero_tiles(M, tp, z);

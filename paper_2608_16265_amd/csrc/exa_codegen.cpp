@@ -957,6 +957,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         for (int i = 0; i < q.R; ++i)
             os << "            const double " << aq(q, i) << " = " << fn_of(q) << "at" << wname(q.walk) << "_" << i
                << ");\n";
+    live.pulls = !pulls.empty();
     for (const Pull& q : pulls) {
         const std::string w = wname(q.walk), pa = "I.pat[" + w + "]";
         for (int i = 0; i < q.R; ++i)

@@ -233,6 +233,7 @@ struct UnitLive {
     std::vector<int> vrefs, vseeds, prefs;  // group-level references
     int weights = 0;                   // y entries (one per member that needs it)
     int64_t outputs = 0;               // doubles written per data point
+    bool pulls = false;                // base rows pull augmentation terms
 };
 
 // Sorted reduction map (CSR): segment s sums buf[idx[ptr[s] .. ptr[s+1])].

@@ -241,15 +241,29 @@ void DeviceState::release(void* p) {
 }
 
 // Tiles of `tile_pts` consecutive data points over the units of a callback.
-std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused) {
+std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused, bool fills) {
     std::vector<ExaTile> tiles;
     for (const Unit& u : units_for(M, mode, fused)) {
-        for (int64_t s = 0; s < u.ndata; s += tile_pts) {
+        // a unit whose code reads nothing (constant derivatives only, such as
+        // the Jacobian entries of a linear augmentation) is a plain fill: far
+        // more points per tile, like the gradient's zero tiles (the
+        // objective keeps its fixed tiles, which fix its summation order).
+        // A launch bound by latency rather than bandwidth keeps short tiles.
+        int64_t tp = tile_pts;
+        const auto lv = M.live.find({mode, u.code});
+        const bool many = u.ndata > (int64_t)4096 * tile_pts;
+        if (mode != M_OBJ && (fills || many) && lv != M.live.end()) {
+            const UnitLive& L = lv->second;
+            if (L.icols.empty() && L.fcols.empty() && L.vrefs.empty() && L.vseeds.empty() && L.prefs.empty() &&
+                L.weights == 0 && !L.pulls)
+                tp = std::max<int64_t>(tp, kZeroTileEntries);
+        }
+        for (int64_t s = 0; s < u.ndata; s += tp) {
             ExaTile t{};
             t.pat = u.code;
             t.inst = inst;
             t.start = s;
-            t.count = std::min(tile_pts, u.ndata - s);
+            t.count = std::min(tp, u.ndata - s);
             t.slot = (int64_t)tiles.size();
             tiles.push_back(t);
         }

@@ -147,7 +147,12 @@ std::shared_ptr<Module> compile_module(const std::string& src, const std::string
 // One line to stderr when the environment variable EXA_LOG is set (not "0").
 bool log_on();
 void log_msg(const std::string& msg);
-std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused);
+// Tiles of tile_pts points per unit.  With fills, a unit whose code reads
+// nothing (constant derivatives only) gets tiles of kZeroTileEntries points
+// (the batch, which is throughput-bound); without, only when its tiles
+// would far outnumber the workgroups the chip holds at once.
+std::vector<ExaTile> make_tiles(const Model& M, int mode, int inst, int64_t tile_pts, bool fused,
+                                bool fills = false);
 std::string kernel_name(int mode);
 int mode_lds_doubles(const Model& M, int mode);
 void set_schedule(Model& M, int mode, int block, int epl, bool fused);
