@@ -52,6 +52,11 @@ struct exa_batch {
     std::vector<exa_model*> models;
     int B = 0;
     std::shared_ptr<Module> module;
+    // code of the batch's own when the instances disagree on which index
+    // columns are 0, 1, ..., n-1 (then only the columns that are so in every
+    // instance use the data point itself), with its liveness records
+    bool own_code = false;
+    std::map<std::pair<int, int>, UnitLive> live;
     DeviceState mem;                   // owns every device array below
     ExaInstDev* inst = nullptr;        // per-instance tables (device)
     std::vector<int64_t> offsets;      // kNoff * (B + 1)
@@ -194,11 +199,11 @@ std::vector<int64_t> instance_cost(const exa_batch& b, uint32_t mask, int units,
         const Model& M = b.models[i]->impl;
         int64_t rd = 0, wr = 0;
         if (em) {
-            kernel_bytes(M, modes_of(em, batch_units(em, units)), fused, rd, wr);
+            kernel_bytes(M, modes_of(em, batch_units(em, units)), fused, rd, wr, b.own_code ? &b.live : nullptr);
             cost[i] += rd + wr;
         }
         if (mask & EXA_EV_ADJ) {
-            kernel_bytes(M, {M_ADJ}, fused, rd, wr);
+            kernel_bytes(M, {M_ADJ}, fused, rd, wr, b.own_code ? &b.live : nullptr);
             cost[i] += rd + wr;
         }
     }
@@ -780,7 +785,22 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         if ((b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) < EXA_UNITS_PER_CALLBACK ||
             (b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
-        b->module = models[0]->impl.dev->module;  // every instance runs the same generated code
+        // every instance runs the same generated code
+        const Model& M0 = models[0]->impl;
+        std::vector<std::vector<char>> ident;
+        for (const Pattern& P : M0.pats) ident.push_back(P.ident);
+        for (int i = 1; i < B; ++i)
+            for (size_t p = 0; p < ident.size(); ++p)
+                for (size_t c = 0; c < ident[p].size(); ++c) ident[p][c] &= models[i]->impl.pats[p].ident[c];
+        bool same = true;
+        for (size_t p = 0; p < ident.size(); ++p) same = same && ident[p] == M0.pats[p].ident;
+        if (same) {
+            b->module = M0.dev->module;
+        } else {
+            bool hit = false;
+            b->module = compile_module(generate_source(M0, &b->live, &ident), M0.cache_dir, &hit);
+            b->own_code = true;
+        }
 
         // offsets in the concatenated arrays and bases in the work buffers
         b->offsets.assign(kNoff * (B + 1), 0);
@@ -930,12 +950,12 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
             const Model& M = b->models[i]->impl;
             int64_t r = 0, w = 0;
             if (em) {
-                kernel_bytes(M, modes_of(em, batch_units(em, units)), fused, r, w);
+                kernel_bytes(M, modes_of(em, batch_units(em, units)), fused, r, w, b->own_code ? &b->live : nullptr);
                 er += r;
                 ew += w;
             }
             if (mask & EXA_EV_ADJ) {
-                kernel_bytes(M, {M_ADJ}, fused, r, w);
+                kernel_bytes(M, {M_ADJ}, fused, r, w, b->own_code ? &b->live : nullptr);
                 er += r;
                 ew += w;
             }

@@ -676,6 +676,14 @@ std::vector<Job> jobs_of(const Model& M, int mode, const Unit& U) {
 
 bool needs_weight(int mode) { return mode == M_HESS || mode == M_HPROD || mode == M_ADJ || mode == M_JTPROD; }
 
+// Index columns the code replaces by the data point itself: the patterns'
+// own flags, or (for code shared by a batch) the flags every instance has.
+thread_local const std::vector<std::vector<char>>* g_ident = nullptr;
+bool ident(const Model& M, int p, int c) {
+    const std::vector<char>& f = g_ident ? (*g_ident)[p] : M.pats[p].ident;
+    return c < (int)f.size() && f[c] != 0;
+}
+
 // Value (cons) or tangent (jprod) of augmentation pattern a at one of its
 // data points, for the base row that pulls it; fills `live`.
 std::string aug_fn(const Model& M, int mode, int a, int& ntmp, UnitLive& live) {
@@ -694,7 +702,8 @@ std::string aug_fn(const Model& M, int mode, int a, int& ntmp, UnitLive& live) {
     for (auto& r : P.vslots) if (r.col >= 0) icols.insert(r.col);
     for (auto& r : P.pslots) if (r.col >= 0) icols.insert(r.col);
     for (auto& q : P.nodes) if (q.op == EXA_OP_DATA) fcols.insert(q.col);
-    for (int c : icols) e.named("long long", "ic" + std::to_string(c), "Pa.ic[" + std::to_string(c) + "][k]");
+    for (int c : icols)
+        e.named("long long", "ic" + std::to_string(c), ident(M, a, c) ? "k" : "Pa.ic[" + std::to_string(c) + "][k]");
     for (int c : fcols) e.named("double", "fc" + std::to_string(c), "Pa.fc[" + std::to_string(c) + "][k]");
     Names nm;
     for (int s = 0; s < P.o1step(); ++s) {
@@ -719,7 +728,7 @@ std::string aug_fn(const Model& M, int mode, int a, int& ntmp, UnitLive& live) {
     cg.body("r");
     const std::set<std::string> names = e.emit(os, "    ");
     os << "    return r;\n}\n";
-    for (int c : icols) if (names.count("ic" + std::to_string(c))) live.icols.push_back(c);
+    for (int c : icols) if (names.count("ic" + std::to_string(c)) && !ident(M, a, c)) live.icols.push_back(c);
     for (int c : fcols) if (names.count("fc" + std::to_string(c))) live.fcols.push_back(c);
     for (int s = 0; s < P.o1step(); ++s) {
         if (names.count("x" + std::to_string(s))) live.vrefs.push_back(s);
@@ -809,7 +818,9 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         for (auto& q : P.nodes) if (q.op == EXA_OP_DATA) fcols.insert(q.col);
         if (weighs && P.kind == EXA_AUG) icols.insert(P.row_icol);
     }
-    for (int c : icols) e.named("long long", "ic" + std::to_string(c), "P0.ic[" + std::to_string(c) + "][k]");
+    const int p0 = U.members[0];  // the unit's data arrays
+    for (int c : icols)
+        e.named("long long", "ic" + std::to_string(c), ident(M, p0, c) ? "k" : "P0.ic[" + std::to_string(c) + "][k]");
     for (int c : fcols) e.named("double", "fc" + std::to_string(c), "P0.fc[" + std::to_string(c) + "][k]");
     std::set<int> vrefs, prefs;
     for (int p : U.members) {
@@ -976,7 +987,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
     os << "        }\n";
 
     // ---- liveness record
-    for (int c : icols) if (names.count("ic" + std::to_string(c))) live.icols.push_back(c);
+    for (int c : icols) if (names.count("ic" + std::to_string(c)) && !ident(M, p0, c)) live.icols.push_back(c);
     for (int c : fcols) if (names.count("fc" + std::to_string(c))) live.fcols.push_back(c);
     for (int r : vrefs) {
         if (names.count("x" + std::to_string(r))) live.vrefs.push_back(r);
@@ -1095,7 +1106,13 @@ const std::vector<int>& multi_modes(bool jh) {
     return jh ? mjh : m;
 }
 
-std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live) {
+std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live,
+                            const std::vector<std::vector<char>>* ident_flags) {
+    struct Restore {
+        const std::vector<std::vector<char>>* prev;
+        ~Restore() { g_ident = prev; }
+    } restore{g_ident};
+    g_ident = ident_flags;
     std::ostringstream os;
     os << "// generated: straight-line evaluation kernels for one pattern set\n";
     os << EXA_STR(EXA_DEVICE_STRUCTS) << "\n";

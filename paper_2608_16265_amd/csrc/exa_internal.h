@@ -159,6 +159,9 @@ struct Pattern {
     int64_t ndata = 0;
     int n_icols = 0, n_fcols = 0;
     std::vector<std::vector<int32_t>> icols;   // host copies (index columns)
+    // index column c holds 0, 1, ..., ndata - 1 (at least kIdentMin points):
+    // the generated code uses the data point itself instead of loading it
+    std::vector<char> ident;
     std::vector<const double*> fcols_src;      // caller's float columns (create only)
     std::vector<RefKey> vslots;       // unique var refs, first-visit order
     std::vector<RefKey> pslots;       // unique param refs
@@ -307,13 +310,17 @@ bool pattern_in_mode(const Pattern& P, int mode);
 const std::vector<int>& multi_modes(bool jh);
 std::vector<Unit> units_for(const Model& M, int mode, bool fused);
 // Generated source for all callbacks; fills live[(mode, unit code)].
-std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr);
+// ident_flags: per pattern and index column, whether the code may use the
+// data point itself (default: each pattern's own flags)
+std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr,
+                            const std::vector<std::vector<char>>* ident_flags = nullptr);
 
 // exa_runtime.cpp
 // Objective tiles always hold kObjBlock * kObjEpl points (256 virtual lanes
 // of 8 points), so the objective's summation order is fixed; its own launch
 // uses kObjBlock-wide workgroups.
 constexpr int kObjBlock = 256, kObjEpl = 8;
+constexpr int64_t kIdentMin = 64;
 constexpr bool kObjFused = true;
 void build_device(Model& M);
 // Device memory a model needs (data columns, tables, work buffers, maps),

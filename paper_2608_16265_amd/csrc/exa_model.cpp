@@ -511,6 +511,15 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     build_map(M.jtc_rows, M.nvar, jtr);
     build_map(M.h_map, M.nvar, h);
     build_map(M.par_map, M.ntheta, pr);
+    for (auto& P : M.pats) {
+        P.ident.assign(P.n_icols, 0);
+        if (P.ndata < kIdentMin) continue;
+        for (int c = 0; c < P.n_icols; ++c) {
+            bool id = true;
+            for (int64_t k = 0; k < P.ndata && id; ++k) id = P.icols[c][k] == k;
+            P.ident[c] = id ? 1 : 0;
+        }
+    }
     M.signature = pattern_signature(M);
 }
 

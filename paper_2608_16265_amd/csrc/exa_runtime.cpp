@@ -920,14 +920,16 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
 // Algorithmic bytes of one launch evaluating `modes` under schedule
 // `fused`: per-point inputs and outputs of every unit, plus each distinct x,
 // v and theta entry read, counted once over the launch.
-void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr) {
+void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr,
+                  const std::map<std::pair<int, int>, UnitLive>* live) {
+    const std::map<std::pair<int, int>, UnitLive>& LV = live ? *live : M.live;
     rd = wr = 0;
     std::vector<char> xs(M.nvar, 0), vs(M.nvar, 0), ts(M.ntheta, 0);
     for (int mode : modes)
     // the objective always runs its fixed schedule
     for (const Unit& u : units_for(M, mode, mode == M_OBJ ? kObjFused : fused)) {
-        auto it = M.live.find({mode, u.code});
-        if (it == M.live.end()) continue;
+        auto it = LV.find({mode, u.code});
+        if (it == LV.end()) continue;
         const UnitLive& L = it->second;
         const Group& G = M.groups[u.group];
         const Pattern& P0 = M.pats[G.members[0]];
@@ -954,8 +956,8 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
         if (mode != M_CONS && mode != M_JPROD) continue;
         for (size_t a = 0; a < M.pats.size(); ++a) {
             const Pattern& P = M.pats[a];
-            auto it = M.live.find({mode, 1000 + (int)a});
-            if (P.kind != EXA_AUG || P.ndata == 0 || it == M.live.end()) continue;
+            auto it = LV.find({mode, 1000 + (int)a});
+            if (P.kind != EXA_AUG || P.ndata == 0 || it == LV.end()) continue;
             const UnitLive& L = it->second;
             rd += P.ndata * (4 * (int64_t)L.icols.size() + 8 * (int64_t)L.fcols.size());
             rd += 4 * (int64_t)(P.rptr.size() + P.ridx.size());

@@ -172,7 +172,9 @@ struct ChunkPlan {
     int64_t nparts() const { return (int64_t)lpart.size() / 2; }
 };
 ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows = nullptr);
-void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr);
+// live: the liveness records of the code that runs (default: the model's own)
+void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr,
+                  const std::map<std::pair<int, int>, UnitLive>* live = nullptr);
 // Map and tables of a segment map on the device (int32 when positions fit,
 // chunked when segments are long).
 void upload_map(DeviceState& D, const SegMap& S, DevMap& d, const SegMap* rows = nullptr);

@@ -174,11 +174,12 @@ def test_kernel_bytes_accounting():
     # the Jacobian of the stencil row needs only u_c (exp), the index column
     assert rd == ni * 4 + 8 * ni
     # the objective writes one partial per tile (both patterns share the 81
-    # grid points: one fused tile); it reads c and u_target once per point,
-    # and every u and f
+    # grid points: one fused tile); it reads u_target once per point and
+    # every u and f; its index column is 0, 1, ..., 80, so the code uses the
+    # point itself and reads no index
     rd, wr = em.kernel_bytes("obj")
     assert wr == 8
-    assert rd == n * n * (4 + 8) + 8 * 2 * n * n
+    assert rd == n * n * 8 + 8 * 2 * n * n
     w = acopf(30, 0)
     em = ExaModel(w.model, host_only=True)
     rd, wr = em.kernel_bytes("hess")
@@ -396,3 +397,41 @@ def test_batch_create_checks_pattern_signature_before_device():
     arr = (C.c_void_p * 2)(a.handle.value, b.handle.value)
     assert _lib.LIB.exa_batch_create(arr, 2, C.byref(opt), C.byref(out)) == _lib.EXA_EINVAL
     assert b"pattern trees" in _lib.LIB.exa_last_error()
+
+
+def test_identity_index_columns():
+    """An index column holding 0, 1, ..., n-1 (n >= 64) is replaced by the
+    data point itself in the generated code: no load, no bytes counted; a
+    permuted column is loaded.  Instances that disagree on it still share a
+    formulation (a batch of them gets code of its own, checked on the GPU):
+    batch creation passes the signature check and stops at the device
+    requirement of host-only models (EXA_ESTATE)."""
+    import ctypes as C
+    from paper_2608_16265_amd import ExaModel, _lib
+
+    def model(perm):
+        m = Model("ident")
+        n = 100
+        x = m.add_var(n + 1)
+        i = np.arange(n)
+        if perm:
+            i = np.random.default_rng(0).permutation(n)
+        d = DataSet(n, i=i)
+        m.add_con(exp(x[d.i]) * x[d.i + 1], d)
+        return m
+    a, b = ExaModel(model(False), host_only=True), ExaModel(model(True), host_only=True)
+    src_a, src_b = a.generated_source(), b.generated_source()
+    assert "const long long ic0 = k;" in src_a and "const long long ic0 = k;" not in src_b
+    ra, wa = a.kernel_bytes("jac")
+    rb, wb = b.kernel_bytes("jac")
+    assert wa == wb and rb - ra == 4 * 100
+    opt = _lib.BatchOptions(0, 256, 4, 1, 1, 1, 1, 0)
+    out = C.c_void_p()
+    arr = (C.c_void_p * 2)(a.handle.value, b.handle.value)
+    assert _lib.LIB.exa_batch_create(arr, 2, C.byref(opt), C.byref(out)) == _lib.EXA_ESTATE
+    # too short to be specialised: loaded like any column
+    m = Model("short")
+    x = m.add_var(11)
+    d = DataSet(10, i=np.arange(10))
+    m.add_con(exp(x[d.i]) * x[d.i + 1], d)
+    assert "const long long ic0 = k;" not in ExaModel(m, host_only=True).generated_source()

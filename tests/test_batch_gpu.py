@@ -239,3 +239,31 @@ def test_batch_rejects_bad_calls():
         b.evaluate(X, Y, 1.0, g=_nan(b, "x"), lag=_nan(b, "x"))
     with pytest.raises(ValueError):
         b.evaluate(X, Y, 1.0, jac=torch.zeros(3, dtype=torch.float64, device="cuda:0"))
+
+
+def test_instances_that_disagree_on_identity_columns():
+    """An index column that is 0, 1, ..., n-1 in some instances and permuted
+    in others: the batch runs code of its own that loads the column, and
+    every output still equals each instance's own callbacks bit for bit."""
+    _gpu()
+    from exa_modeling import DataSet, Model, exp, sin
+    from exa_modeling.generators import Workload
+    from paper_2608_16265_amd import ExaModel
+    from paper_2608_16265_amd.batch import ExaBatch
+
+    def inst(n, perm, seed):
+        rng = np.random.default_rng(seed)
+        m = Model("ident")
+        x = m.add_var(n + 1)
+        i = rng.permutation(n) if perm else np.arange(n)
+        d = DataSet(n, i=i, c=rng.uniform(0.5, 2.0, n))
+        m.add_obj(d.c * x[d.i] ** 2, d)
+        m.add_con(exp(x[d.i]) * sin(x[d.i + 1]), d)
+        return Workload(m, rng.uniform(-1, 1, n + 1), rng.standard_normal(n), 1.0)
+    wls = [inst(300, False, 1), inst(200, True, 2), inst(500, False, 3)]
+    ems = [ExaModel(w.model) for w in wls]
+    b = ExaBatch(ems, autotune=False, units="per_callback")
+    X, Y, V, W, WX = _inputs(b, wls)
+    outs = {k: _nan(b, kind) for k, kind in ALL8.items()}
+    b.evaluate(X, Y, 1.0, V, W, **outs)
+    _check_against_plain(b, ems, X, Y, V, W, WX, 1.0, outs, tag="ident")
