@@ -67,14 +67,12 @@ def parse():
     ap.add_argument("--quick", action="store_true",
                     help="few repetitions per measurement (for runs under a profiler)")
     ap.add_argument("--eval-schedule", default=None,
-                    help="block,points_per_lane,fused,units[,jt[,unstaged]] (units 0 per callback, 1 Jacobian + "
-                         "Hessian units, 2 one pass; jt 1: J^T w from the Jacobian values; unstaged 1: each lane's "
-                         "own stores): fix the step's exa_eval "
-                         "schedule instead of "
-                         "tuning it (to profile the schedule an unprofiled run chose)")
+                    help="block,points_per_lane,fused,units[,unstaged] (units 0 per callback, 1 Jacobian + "
+                         "Hessian units, 2 one pass; unstaged 1: each lane's own stores): fix the step's exa_eval "
+                         "schedule instead of tuning it (to profile the schedule an unprofiled run chose)")
     ap.add_argument("--batch-schedule", default=None,
-                    help="block,points_per_lane,fused,units[,jt[,unstaged]] (units per_callback, jac_hess, one_pass "
-                         "or separate; jt 1: J^T w from the Jacobian values; unstaged 1: each lane's own stores): fix the headline batch step's "
+                    help="block,points_per_lane,fused,units[,unstaged] (units per_callback, jac_hess, one_pass "
+                         "or separate; unstaged 1: each lane's own stores): fix the headline batch step's "
                          "schedule instead of tuning it (to profile the schedule an unprofiled run chose)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates "
@@ -256,8 +254,7 @@ def leg_single(name, wl, steps, warmup):
     build_s = time.perf_counter() - t0
     if EVAL_SCHEDULE:
         v = [int(t) for t in EVAL_SCHEDULE.split(",")]
-        em.set_eval_schedule(ALL_CBS, v[0], v[1], bool(v[2]), v[3], jt_from_jac=len(v) > 4 and bool(v[4]),
-                             unstaged=len(v) > 5 and bool(v[5]))
+        em.set_eval_schedule(ALL_CBS, v[0], v[1], bool(v[2]), v[3], unstaged=len(v) > 4 and bool(v[4]))
     e = lambda n: torch.empty(n, dtype=torch.float64, device="cuda:0")  # noqa: E731
     cbs, (X, Y, V, W, jv, hv) = _callbacks(em, wl)
     step = cbs["eval_all"]
@@ -392,7 +389,7 @@ def leg_batch(steps, warmup, count=256, first_seed=1000):
     if BATCH_SCHEDULE:
         v = BATCH_SCHEDULE.split(",")
         b.set_schedule(BATCH_CBS, int(v[0]), int(v[1]), bool(int(v[2])), v[3],
-                       jt_from_jac=len(v) > 4 and bool(int(v[4])), unstaged=len(v) > 5 and bool(int(v[5])))
+                       unstaged=len(v) > 4 and bool(int(v[4])))
     dev = "cuda:0"
     rng = np.random.default_rng(0)
     X = b.concat([w.x for w in wls])

@@ -253,10 +253,15 @@ exa_status exa_jac_hess_coord(exa_model* m, const double* x, const double* y, do
 /* J(x) v into Jv [ncon]; v is device [nvar] (Sec. 2.1.3 jprod). */
 exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv,
                      exa_stream_t stream);
-/* J(x)^T w into Jtw [nvar]; w is device [ncon] (Sec. 2.1.3 jtprod). */
+/* J(x)^T w into Jtw [nvar]; w is device [ncon] (Sec. 2.1.3 jtprod).  The
+ * patterns declared over the same data arrays add their contributions
+ * (Jacobian entry times w of its row, members in declaration order) to one
+ * variable reference in the lane; the reduction then sums these per
+ * variable in a fixed order (Sec. 7.2.3). */
 exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jtw,
                       exa_stream_t stream);
-/* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod). */
+/* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod).
+ * Contributions are summed as exa_jtprod sums them. */
 exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight,
                      const double* v, double* Hv, exa_stream_t stream);
 /* exa_hprod for callers that cannot allocate device memory (code under HIP
@@ -366,9 +371,8 @@ typedef struct exa_eval_args {
 exa_status exa_eval(exa_model* m, const exa_eval_args* args, exa_stream_t stream);
 /* The schedule of exa_eval for a mask: out4 = workgroup size, points per
  * lane, fused (bit 0) | one pass per point for all callbacks (bit 1) |
- * Jacobian + Hessian units (bit 2) | J^T w from the Jacobian values (bit 3) |
- * unstaged stores (bit 4), number of tiles.  EXA_ESTATE until the mask's
- * first exa_eval call. */
+ * Jacobian + Hessian units (bit 2) | unstaged stores (bit 4), number of
+ * tiles.  EXA_ESTATE until the mask's first exa_eval call. */
 exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 /* Units of an exa_eval launch: one tile per callback and point, the
  * Jacobian and the Hessian apart (their tiles then run in a kernel with a
@@ -380,18 +384,9 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4);
 #define EXA_UNITS_JAC_HESS 1
 #define EXA_UNITS_ONE_PASS 2
 /* Flag OR'ed into `units` (exa_eval_set_schedule, exa_batch_set_schedule,
- * the batch options): a mask with both the Jacobian and J^T w sums J^T w
- * from the Jacobian values the same launch writes (w[row] times each entry,
- * per variable in ascending COO position) instead of evaluating J^T w tiles
- * into a work buffer; the bits are the same either way (J^T w contributions
- * are the Jacobian entries times w).  The tuner times both; without it the
- * Jacobian values are used when the launch writes more than the 256 MB
- * last-level cache holds. */
-#define EXA_JT_FROM_JAC 0x10
-/* Flag OR'ed into `units` as EXA_JT_FROM_JAC: Jacobian and Hessian values
- * leave each lane as its own stores instead of being staged through LDS into
- * contiguous 16-byte stores (a schedule choice the tuners time; the values
- * are the same). */
+ * the batch options): Jacobian and Hessian values leave each lane as its
+ * own stores instead of being staged through LDS into contiguous 16-byte
+ * stores (a schedule choice the tuners time; the values are the same). */
 #define EXA_UNSTAGED 0x20
 /* Batched evaluation only: every callback's tiles in a launch of its own,
  * one after another (each kernel with the register budget of its own units). */
@@ -600,8 +595,7 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
  * evaluation launch(es), bytes read and written by the reduction launch. */
 exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4);
 /* Schedule of a mask: out6 = workgroup size, points per lane, fused (0/1),
- * units (EXA_UNITS_*, | EXA_JT_FROM_JAC when J^T w is summed from the
- * Jacobian values, | EXA_UNSTAGED), number of evaluation tiles, the autotuner's best
+ * units (EXA_UNITS_*, | EXA_UNSTAGED), number of evaluation tiles, the autotuner's best
  * evaluation-launch time in nanoseconds (0 if not tuned).  EXA_ESTATE before
  * the mask's first call. */
 exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6);

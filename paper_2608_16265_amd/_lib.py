@@ -61,7 +61,6 @@ EV = {"obj": 1 << 0, "grad": 1 << 1, "cons": 1 << 2, "jac": 1 << 3, "hess": 1 <<
       "jprod": 1 << 5, "jtprod": 1 << 6, "hprod": 1 << 7}
 EV_BATCH = dict(EV, lag=1 << 8, adjoint=1 << 9)
 UNITS = {"per_callback": 0, "jac_hess": 1, "one_pass": 2, "separate": 3}
-JT_FROM_JAC = 0x10  # OR'ed into units: J^T w summed from the Jacobian values
 UNSTAGED = 0x20     # OR'ed into units: each lane's own output stores
 
 

@@ -14,7 +14,7 @@ from typing import Sequence
 import numpy as np
 import torch
 
-from ._lib import EV_BATCH, JT_FROM_JAC, LIB, UNITS, UNSTAGED, BatchIO, BatchOptions, check
+from ._lib import EV_BATCH, LIB, UNITS, UNSTAGED, BatchIO, BatchOptions, check
 from .model import ExaModel, _stream
 
 _F64 = torch.float64
@@ -139,14 +139,13 @@ class ExaBatch:
         out = np.zeros(6, dtype=np.int64)
         check(LIB.exa_batch_schedule(self._h, self.mask(callbacks), out.ctypes.data_as(C.POINTER(C.c_int64))))
         d = dict(zip(["block", "points_per_lane", "fused", "units", "tiles", "tuned_ns"], out.tolist()))
-        d["jt_from_jac"] = int(bool(d["units"] & JT_FROM_JAC))
         d["unstaged"] = int(bool(d["units"] & UNSTAGED))
-        d["units"] = {v: k for k, v in UNITS.items()}[d["units"] & ~(JT_FROM_JAC | UNSTAGED)]
+        d["units"] = {v: k for k, v in UNITS.items()}[d["units"] & ~UNSTAGED]
         return d
 
     def set_schedule(self, callbacks, block: int, points_per_lane: int, fused: bool = True,
-                     units: str = "jac_hess", jt_from_jac: bool = False, unstaged: bool = False):
-        u = UNITS[units] | (JT_FROM_JAC if jt_from_jac else 0) | (UNSTAGED if unstaged else 0)
+                     units: str = "jac_hess", unstaged: bool = False):
+        u = UNITS[units] | (UNSTAGED if unstaged else 0)
         check(LIB.exa_batch_set_schedule(self._h, self.mask(callbacks), block, points_per_lane,
                                          1 if fused else 0, u))
 

@@ -39,7 +39,7 @@ using namespace exa;
 
 namespace {
 // work buffers of the batch (ExaBatchReduce::bufs)
-constexpr int kBufFo = 0, kBufHv = 1, kBufPar = 2, kBufTile = 3, kBufJac = 4, kBufW = 5;
+constexpr int kBufFo = 0, kBufHv = 1, kBufPar = 2, kBufTile = 3;
 constexpr int kWorkBufs = 4;  // the batch's own buffers (the others are the caller's)
 // outputs of the reduction launch (ExaBatchReduce::outs)
 constexpr int kOutF = 0, kOutG = 1, kOutJtw = 2, kOutHv = 3, kOutLag = 4, kOutLagTmp = 5, kOutThetaBar = 6;
@@ -69,12 +69,11 @@ struct exa_batch {
     double* lag_tmp = nullptr;         // J^T y of EXA_EV_LAG when the gradient is reduced
     // per instance: its models' device maps, with part sums of the batch's own
     struct Maps {
-        DevMap grad, jt, h, par, jtc;
+        DevMap grad, jt, h, par;
     };
     std::vector<Maps> maps;
     std::vector<int64_t> nobj;         // objective tiles per instance
     bool grad_direct_all = true, grad_direct_any = false;
-    bool jtc_ok = true;  // every instance can sum J^T w from its Jacobian values
     // options
     bool autotune = true, use_graph = true, xcd_aware = true, fuse = true;
     int block = 256, epl = 4, units = EXA_UNITS_JAC_HESS;
@@ -82,7 +81,6 @@ struct exa_batch {
     struct Sched {
         int block = 256, epl = 4, units = EXA_UNITS_PER_CALLBACK;
         bool fused = true, tuned = false;
-        bool jt = false;                     // J^T w from the Jacobian values (EXA_JT_FROM_JAC)
         bool unstaged = false;               // each lane's own output stores (EXA_UNSTAGED)
         std::vector<std::vector<int>> bins;  // instances per XCD
         ExaTile* tiles = nullptr;
@@ -113,10 +111,10 @@ struct exa_batch {
         uint32_t mask = 0;
         exa_batch_io io;
         int block = 0, epl = 0, units = 0;
-        bool fused = false, jt = false;
+        bool fused = false;
         bool operator==(const Key& o) const {
             return mask == o.mask && std::memcmp(&io, &o.io, sizeof io) == 0 && block == o.block && epl == o.epl &&
-                   units == o.units && fused == o.fused && jt == o.jt;
+                   units == o.units && fused == o.fused;
         }
     } key, last;  // the graph's call; the previous call
     bool have_graph = false, have_last = false;
@@ -173,17 +171,8 @@ std::vector<int> modes_of(uint32_t em, int units) {
 }
 
 const std::vector<int>& main_modes(const exa_batch::Sched& S, uint32_t mask, std::vector<int>& tmp) {
-    tmp = modes_of(tile_mask(eval_mask(mask), S.jt), S.units);
+    tmp = modes_of(eval_mask(mask), S.units);
     return tmp;
-}
-
-// Without timing, as exa_eval decides for one model: J^T w from the
-// Jacobian values when the launch writes more than the last-level cache.
-bool default_jt(const exa_batch& b, uint32_t mask) {
-    if (!((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD)) || !b.jtc_ok) return false;
-    int64_t w = 0;
-    for (const exa_model* m : b.models) w += 8 * (m->impl.nnzj + m->impl.nnzh + m->impl.fo_con_len);
-    return w > ((int64_t)256 << 20);
 }
 
 // A launch of one plain mode runs that mode's own kernel (exa_k_<mode>);
@@ -194,7 +183,7 @@ bool single_kernel(const std::vector<int>& modes) { return modes.size() == 1 && 
 // instances are binned over the XCDs.
 std::vector<int64_t> instance_cost(const exa_batch& b, uint32_t mask, int units, bool fused) {
     std::vector<int64_t> cost(b.B, 0);
-    const uint32_t em = tile_mask(eval_mask(mask), b.sched.count(mask) ? b.sched.at(mask).jt : false);
+    const uint32_t em = eval_mask(mask);
     for (int i = 0; i < b.B; ++i) {
         const Model& M = b.models[i]->impl;
         int64_t rd = 0, wr = 0;
@@ -285,10 +274,9 @@ ExaTile* upload_binned(exa_batch& b, const exa_batch::Sched& S, const std::vecto
     return (ExaTile*)b.mem.upload(v.data(), v.size() * sizeof(ExaTile));
 }
 
-void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fused, int units, bool jt) {
+void set_batch_schedule(exa_batch& b, uint32_t mask, int block, int epl, bool fused, int units) {
     exa_batch::Sched& S = b.sched[mask];
-    S.jt = jt && (mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && b.jtc_ok;
-    const uint32_t em = tile_mask(eval_mask(mask), S.jt);
+    const uint32_t em = eval_mask(mask);
     S.units = batch_units(em, units);
     S.block = block;
     S.epl = epl;
@@ -343,9 +331,6 @@ ExaBatchJob seg_batch_job(const DevMap& m, int bufk, int64_t buf_off, int out, i
     J.nlong = m.nlong;
     J.wide = m.wide;
     J.chunked = m.chunked;
-    J.rows = m.rows;
-    J.lrow = m.lrow;
-    J.wv = -1;
     J.buf = bufk;
     J.buf_off = buf_off;
     J.out = out;
@@ -390,15 +375,7 @@ void build_reductions(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
                     S.axpy = true;
                 }
             }
-            if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && S.jt) {
-                // from the Jacobian values of this call, times w[row]
-                ExaBatchJob J = seg_batch_job(mp.jtc, kBufJac, b.offsets[kNoff * i + kOffJac], kOutJtw, xo, false);
-                J.wv = kBufW;
-                J.wv_off = b.offsets[kNoff * i + kOffY];
-                mine.push_back(J);
-            } else if (mask & EXA_EV_JTPROD) {
-                mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false));
-            }
+            if (mask & EXA_EV_JTPROD) mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false));
             if (mask & EXA_EV_HPROD) mine.push_back(seg_batch_job(mp.h, kBufHv, b.base[kBufHv][i], kOutHv, xo, false));
             if (mask & EXA_EV_ADJ)
                 mine.push_back(seg_batch_job(mp.par, kBufPar, b.base[kBufPar][i], kOutThetaBar,
@@ -561,8 +538,6 @@ bool launch_reduce(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStrea
     R.lblocks = S.lblocks;
     R.nlblocks = S.nlblocks;
     for (int k = 0; k < kWorkBufs; ++k) R.bufs[k] = b.buf[k];
-    R.bufs[kBufJac] = io.jac;
-    R.bufs[kBufW] = io.w;
     R.outs[kOutF] = io.f;
     R.outs[kOutG] = io.g;
     R.outs[kOutJtw] = io.jtw;
@@ -608,8 +583,7 @@ void run(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
 // First call with a mask under autotune: time every candidate schedule's
 // evaluation launch(es) on the caller's arguments and keep the fastest.
 void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t s) {
-    const bool jt0 = b.sched[mask].jt;
-    const uint32_t em = tile_mask(eval_mask(mask), jt0);
+    const uint32_t em = eval_mask(mask);
     const int blocks[] = {64, 128, 256};
     const int epls[] = {1, 2, 4, 8};
     std::vector<int> fuses = {0};
@@ -646,7 +620,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
             for (int f : fuses)
                 for (int bk : blocks)
                     for (int ep : epls) {
-                        set_batch_schedule(b, mask, bk, ep, f != 0, u, jt0);
+                        set_batch_schedule(b, mask, bk, ep, f != 0, u);
                         cands.push_back({time_it(2), bk, ep, f, u});
                     }
         // neighbouring schedules differ by less than one timing's noise: the
@@ -656,7 +630,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
         for (auto& c : cands) c.ms = 1e30f;
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
-                set_batch_schedule(b, mask, c.block, c.epl, c.fused != 0, c.units, jt0);
+                set_batch_schedule(b, mask, c.block, c.epl, c.fused != 0, c.units);
                 c.ms = std::min(c.ms, time_it(6));
             }
     } catch (...) {
@@ -665,7 +639,7 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
         throw;
     }
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units, jt0);
+    set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units);
     b.sched[mask].tuned_ns = (int64_t)(w.ms * 1e6);
     // staged or each lane's own stores of the Jacobian and Hessian values
     if (mask & (EXA_EV_JAC | EXA_EV_HESS)) {
@@ -687,37 +661,6 @@ void tune_batch(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStream_t
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const bool unstaged = b.sched[mask].unstaged;
-    // J^T w with the Jacobian: its own tiles and buffer, or the Jacobian
-    // values; the whole call (evaluation and reductions) decides
-    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && b.jtc_ok) {
-        float best[2] = {1e30f, 1e30f};
-        int units[2] = {w.units, w.units};
-        for (int round = 0; round < 2; ++round)
-            for (int jt = 0; jt < 2; ++jt) {
-                set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, w.units, jt != 0);
-                b.sched[mask].unstaged = unstaged;
-                units[jt] = b.sched[mask].units;
-                build_reductions(b, b.sched[mask], mask);
-                if ((mask & EXA_EV_JTPROD) && !jt) need_buf(b, kBufFo);
-                hip_check(hipEventCreate(&e0), "hipEventCreate");
-                hip_check(hipEventCreate(&e1), "hipEventCreate");
-                run(b, mask, io, s);
-                hip_check(hipEventRecord(e0, s), "hipEventRecord");
-                for (int r = 0; r < 4; ++r) run(b, mask, io, s);
-                hip_check(hipEventRecord(e1, s), "hipEventRecord");
-                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                float ms = 0;
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                best[jt] = std::min(best[jt], ms / 4);
-            }
-        const bool jt = best[1] < best[0];
-        set_batch_schedule(b, mask, w.block, w.epl, w.fused != 0, units[jt], jt);
-        b.sched[mask].unstaged = unstaged;
-        b.sched[mask].reduce_built = false;
-    }
     if (log_on())
         log_msg("tuned batch of " + std::to_string(b.B) + " mask " + std::to_string(mask) + ": block " +
                 std::to_string(w.block) + ", points per lane " + std::to_string(w.epl) + ", fused " +
@@ -782,8 +725,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         }
         if (b->block != 64 && b->block != 128 && b->block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (b->epl < 1 || b->epl > 16) fail(EXA_EINVAL, "epl must be in 1..16");
-        if ((b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) < EXA_UNITS_PER_CALLBACK ||
-            (b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) > EXA_UNITS_SEPARATE)
+        if ((b->units & ~EXA_UNSTAGED) < EXA_UNITS_PER_CALLBACK || (b->units & ~EXA_UNSTAGED) > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         // every instance runs the same generated code
         const Model& M0 = models[0]->impl;
@@ -862,9 +804,7 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
             mp.jt = D.jt_map;
             mp.h = D.h_map;
             mp.par = D.par_map;
-            mp.jtc = D.jtc_map;
-            if (!D.jtc_ok) b->jtc_ok = false;
-            for (DevMap* m : {&mp.grad, &mp.jt, &mp.h, &mp.par, &mp.jtc})
+            for (DevMap* m : {&mp.grad, &mp.jt, &mp.h, &mp.par})
                 if (m->nparts > 0) m->lsum = (double*)b->mem.alloc(m->nparts * sizeof(double));
         }
         hip_check(hipStreamCreate(&b->cap), "hipStreamCreate");
@@ -904,7 +844,7 @@ exa_status exa_batch_schedule(const exa_batch* b, uint32_t mask, int64_t* out6) 
         out6[0] = S.block;
         out6[1] = S.epl;
         out6[2] = S.fused ? 1 : 0;
-        out6[3] = S.units | (S.jt ? EXA_JT_FROM_JAC : 0) | (S.unstaged ? EXA_UNSTAGED : 0);
+        out6[3] = S.units | (S.unstaged ? EXA_UNSTAGED : 0);
         int64_t nt = S.ntiles + S.antiles;
         for (const auto& p : S.parts) nt += p.ntiles;
         out6[4] = nt;
@@ -919,11 +859,11 @@ exa_status exa_batch_set_schedule(exa_batch* b, uint32_t mask, int32_t block, in
         check_mask(mask);
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
-        const bool jt = (units & EXA_JT_FROM_JAC) != 0, unstaged = (units & EXA_UNSTAGED) != 0;
-        units &= ~(EXA_JT_FROM_JAC | EXA_UNSTAGED);
+        const bool unstaged = (units & EXA_UNSTAGED) != 0;
+        units &= ~EXA_UNSTAGED;
         if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_SEPARATE)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
-        set_batch_schedule(*b, mask, block, epl, fused != 0, units, jt);
+        set_batch_schedule(*b, mask, block, epl, fused != 0, units);
         b->sched[mask].unstaged = unstaged;
         b->sched[mask].reduce_built = false;
         b->sched[mask].tuned = true;
@@ -935,16 +875,14 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
     return guard([&] {
         if (!b || !out4) fail(EXA_EINVAL, "null argument");
         check_mask(mask);
-        int units = b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED);
+        int units = b->units & ~EXA_UNSTAGED;
         bool fused = b->fuse;
-        bool jt = (b->units & EXA_JT_FROM_JAC) ? true : default_jt(*b, mask);
         auto it = b->sched.find(mask);
         if (it != b->sched.end()) {
             units = it->second.units;
             fused = it->second.fused;
-            jt = it->second.jt;
         }
-        const uint32_t em = tile_mask(eval_mask(mask), jt);
+        const uint32_t em = eval_mask(mask);
         int64_t er = 0, ew = 0, rr = 0, rw = 0;
         for (int i = 0; i < b->B; ++i) {
             const Model& M = b->models[i]->impl;
@@ -959,7 +897,7 @@ exa_status exa_batch_bytes(const exa_batch* b, uint32_t mask, int64_t* out4) {
                 er += r;
                 ew += w;
             }
-            reduce_bytes(M, mask, jt, r, w);
+            reduce_bytes(M, mask, r, w);
             rr += r;
             rw += w;
             // one objective partial is copied by the reduction launch
@@ -1002,9 +940,6 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
         if (mask & EXA_EV_HPROD) need(io->hv, tot[kOffX], "hv");
         if (mask & EXA_EV_LAG) need(io->lag, tot[kOffX], "lag");
         if (mask & EXA_EV_ADJ) need(io->theta_bar, tot[kOffTheta], "theta_bar");
-        if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && !b->jtc_ok)
-            fail(EXA_EINVAL, "J^T w with the Jacobian in one call needs fewer than 2^31 Jacobian entries per "
-                             "instance; evaluate J^T w in a call of its own");
         if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && b->grad_direct_all != b->grad_direct_any)
             fail(EXA_EINVAL,
                  "the instances disagree on whether every variable has at most one objective term; their "
@@ -1020,9 +955,8 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
             b->lag_tmp = (double*)b->mem.alloc(std::max<int64_t>(1, tot[kOffX]) * sizeof(double));
         auto it = b->sched.find(mask);
         if (it == b->sched.end() || !it->second.tuned) {
-            // the options' units, and the options' J^T w choice, else the default
-            const bool jt = (b->units & EXA_JT_FROM_JAC) ? true : default_jt(*b, mask);
-            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED), jt);
+            // the options' units
+            set_batch_schedule(*b, mask, b->block, b->epl, b->fuse, b->units & ~EXA_UNSTAGED);
             b->sched[mask].unstaged = (b->units & EXA_UNSTAGED) != 0;
             b->sched[mask].reduce_built = false;
             if (b->autotune) tune_batch(*b, mask, *io, s);
@@ -1039,7 +973,6 @@ exa_status exa_batch_eval(exa_batch* b, uint32_t mask, const exa_batch_io* io, e
         k.epl = S.epl;
         k.units = S.units;
         k.fused = S.fused;
-        k.jt = S.jt;
         // a graph is recorded when a call repeats the previous one (same
         // pointers, sigma and schedule) and replayed while calls keep
         // matching it; a call with new arguments launches directly, so

@@ -801,6 +801,26 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         else
             os << "        double " << oname(j) << "[" << out_step(M.pats[j.p], j.mode) << "] = {};\n";
     }
+    // J^T w / H v: the members' contributions summed per group reference
+    const Group& UG = M.groups[U.group];
+    std::map<int, std::string> gout;  // mode -> output array of its first job
+    for (const Job& j : jobs)
+        if ((j.mode == M_JTPROD || j.mode == M_HPROD) && !gout.count(j.mode)) gout[j.mode] = j.out;
+    auto gname = [](int m) { return std::string(m == M_JTPROD ? "gjt" : "ghv"); };
+    auto grefs = [&](int m) -> const std::vector<int>& { return m == M_JTPROD ? UG.jt_refs : UG.hv_refs; };
+    // (mode, group slot) -> the last member whose job adds to it
+    std::map<std::pair<int, int>, int> last_adder;
+    for (const Job& j : jobs) {
+        if (j.mode != M_JTPROD && j.mode != M_HPROD) continue;
+        const Pattern& P = M.pats[j.p];
+        const std::vector<int>& refs = grefs(j.mode);
+        for (int i = 0; i < out_step(P, j.mode); ++i) {
+            const int r = P.vg[j.mode == M_HPROD ? P.hvs[i] : i];
+            last_adder[{j.mode, (int)(std::find(refs.begin(), refs.end(), r) - refs.begin())}] = j.p;
+        }
+    }
+    for (auto& kv : gout)
+        os << "        double " << gname(kv.first) << "[" << std::max<size_t>(1, grefs(kv.first).size()) << "] = {};\n";
     os << "        {\n";
 
     // ---- statements: loads (all candidates), then every job's sweeps
@@ -879,7 +899,24 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 e.out("if (" + call(M_GRAD) + ".direct && kr < kend) " + call(M_GRAD) + ".out0[I.off[" +
                           std::to_string(EXA_OFF_X) + "] + " + nm.ix[s] + "]",
                       oname(j) + "[" + std::to_string(s) + "]");
-        if (buffer_mode(j.mode)) {
+        if (j.mode == M_JTPROD || j.mode == M_HPROD) {
+            // this member's contributions added to the group's, members in
+            // declaration order; a reference's sum is stored (slot-major, as
+            // exa_store_soa does) right after the last member that adds to
+            // it, so that it leaves registers early
+            const std::vector<int>& refs = grefs(j.mode);
+            const int n = out_step(P, j.mode);
+            const std::string stride = "((" + pd + ".ndata + 15) & ~15LL)";
+            for (int i = 0; i < n; ++i) {
+                const int r = P.vg[j.mode == M_HPROD ? P.hvs[i] : i];
+                const int at = (int)(std::find(refs.begin(), refs.end(), r) - refs.begin());
+                const std::string g = gname(j.mode) + "[" + std::to_string(at) + "]";
+                e.out(g, g + " + " + oname(j) + "[" + std::to_string(i) + "]");
+                if (last_adder[{j.mode, at}] == p)
+                    e.raw("if (kr < kend) (" + dest(P, j.mode, pd, j.out, false) + ")[" + std::to_string(at) + " * " +
+                          stride + " + kr] = " + g + ";");
+            }
+        } else if (buffer_mode(j.mode)) {
             // contributions to a work buffer that a reduction reads back: slot
             // s of data point k at block + s * stride + k (stride: ndata
             // rounded up to 16, so every slot array starts on a 128-byte
@@ -999,7 +1036,9 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
         if (M.pats[p].kind != EXA_OBJ)
             for (const char* w : {"wy", "ww"})
                 if (names.count(w + std::to_string(p))) live.weights++;
-    for (const Job& j : jobs) live.outputs += out_step(M.pats[j.p], j.mode);
+    for (const Job& j : jobs)
+        if (j.mode != M_JTPROD && j.mode != M_HPROD) live.outputs += out_step(M.pats[j.p], j.mode);
+    for (auto& kv : gout) live.outputs += (int64_t)grefs(kv.first).size();
 
     // ---- outputs that are not staged: objective sums, constraint rows
     if (mode == M_OBJ) {
@@ -1025,7 +1064,8 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
 
 const std::vector<int>& job_modes(int mode) {
     static const std::vector<int> one[M_COUNT] = {{0}, {1}, {2}, {3}, {4}, {5}, {6}, {7}, {8}, {M_JAC, M_HESS}};
-    // with the Jacobian in the same pass, J^T w is summed from its values
+    // J^T w runs as tiles of its own beside the one-pass units (with it, the
+    // units hold too many registers)
     static const std::vector<int> full = {M_GRAD, M_CONS, M_JAC, M_HESS, M_JPROD, M_HPROD};
     static const std::vector<int> ipm = {M_GRAD, M_CONS, M_JAC, M_HESS};
     return mode == M_SFULL ? full : mode == M_SIPM ? ipm : one[mode];
@@ -1054,6 +1094,11 @@ bool pattern_in_mode(const Pattern& P, int mode) {
 }
 
 std::vector<Unit> units_for(const Model& M, int mode, bool fused) {
+    // J^T w and H v contributions are summed over a group's members in the
+    // lane: their units always hold the whole group
+    if (mode == M_JTPROD || mode == M_HPROD) fused = true;
+    if (multi_unit(mode))
+        for (int m : job_modes(mode)) fused = fused || m == M_JTPROD || m == M_HPROD;
     std::vector<Unit> out;
     for (size_t g = 0; g < M.groups.size(); ++g) {
         const Group& G = M.groups[g];
@@ -1355,8 +1400,7 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
                                 "].inst[T.inst], T, lds); break;");
             }
         }
-        // the objective's tiles, and J^T w tiles when J^T w is not summed
-        // from the Jacobian values
+        // the objective's and J^T w's tiles
         mode_cases(M_OBJ, cases);
         mode_cases(M_JTPROD, cases);
         lds = std::max(lds, mode_lds_doubles(M, M_JTPROD));

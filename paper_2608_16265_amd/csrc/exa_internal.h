@@ -218,6 +218,12 @@ struct Group {
     std::vector<RefKey> vrefs, prefs;  // distinct references over all members
     std::vector<std::pair<int, int>> vsrc, psrc;  // first (member, slot) of each
     int64_t ndata = 0;
+    // J^T w and H v contributions are summed over the members of a point
+    // before they leave the lane: one buffer slot per group-level reference
+    // that some member contributes to (ascending reference index), blocks at
+    // ob (constraint part of the first-order buffer) and oh (H v buffer)
+    std::vector<int> jt_refs, hv_refs;
+    int64_t ob = 0, oh = 0;
 };
 
 // A unit of generated code for one callback: one pattern, or the members of
@@ -262,9 +268,6 @@ struct Model {
     std::vector<double> xl, xu, theta;
     // reduction maps (positions in the first-order buffer: grad part first)
     SegMap grad_map, jt_map, h_map, par_map;
-    // J^T w from the Jacobian's COO values: jt_map's segments and order with
-    // COO positions (jtc_map) and the row of each entry (jtc_rows.idx)
-    SegMap jtc_map, jtc_rows;
     bool host_only = false;
     int block = 256, epl = 4;
     bool autotune = false, fuse = false;

@@ -47,12 +47,6 @@ struct ExaSegJob {
     double* lsum;
     int32_t wide;    // ptr/idx are int64 when set, else int32
     int32_t chunked;
-    // products (int32 maps only): when wv is set, entry j adds
-    // buf[idx[j]] * wv[rows[j]] (the product rounded on its own) instead of
-    // buf[idx[j]]; lrow holds the rows of each lane's four positions
-    const double* wv;
-    const int32_t* rows;
-    const int32_t* lrow;
 };
 constexpr int kExaReduceJobs = 3;
 // Up to three segment-sum jobs and, when part is not null, the sum of the
@@ -86,8 +80,8 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s);
 // named by index and offset, so the job table does not depend on the
 // caller's pointers: bufs[buf] + buf_off is the job's buffer and
 // outs[out] + out_off its output.
-// first-order, H v, parameter, objective partials, Jacobian values, J^T w weights
-constexpr int kExaBatchBufs = 6;
+// first-order, H v, parameter, objective partials
+constexpr int kExaBatchBufs = 4;
 constexpr int kExaBatchOuts = 8;
 struct ExaBatchJob {
     const void* ptr;
@@ -97,16 +91,12 @@ struct ExaBatchJob {
     const int32_t* longs;
     const int32_t* lpart;
     double* lsum;
-    const int32_t* rows;  // products: see ExaSegJob
-    const int32_t* lrow;
     int64_t nseg, nlanes, nparts, nlong;
-    int64_t buf_off, out_off, wv_off;
+    int64_t buf_off, out_off;
     int32_t wide, chunked;
     int32_t buf, out;
     int32_t kind;  // 0: segment sums; 1: objective partials (nseg of them) into one value
     int32_t ep;    // 1: out = alpha * out + sum, the product rounded first
-    int32_t wv;    // products: bufs[wv] + wv_off is the multiplier vector; -1: plain sums
-    int32_t pad;
 };
 struct ExaBatchReduce {
     const ExaBatchJob* jobs;

@@ -56,33 +56,6 @@ __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __r
     put(out, s, acc, ep, alpha);
 }
 
-// The same sums of products buf[idx[j]] * wv[rows[j]], each product rounded
-// before it is added (no fused multiply-add), in the same order.
-__device__ __forceinline__ void seg_body_prod(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                              const int32_t* __restrict__ rows, const double* __restrict__ buf,
-                                              const double* __restrict__ wv, double* __restrict__ out, int64_t s,
-                                              bool parts, bool ep, double alpha) {
-#pragma clang fp contract(off)
-    const int64_t b = ptr[s], e = ptr[s + 1];
-    if (parts && e - b > kExaLongSeg) return;  // summed in parts
-    double acc = 0.0;
-    int64_t j = b;
-    for (; j + 4 <= e; j += 4) {
-        const int32_t i0 = idx[j], i1 = idx[j + 1], i2 = idx[j + 2], i3 = idx[j + 3];
-        const int32_t r0 = rows[j], r1 = rows[j + 1], r2 = rows[j + 2], r3 = rows[j + 3];
-        const double v0 = buf[i0] * wv[r0], v1 = buf[i1] * wv[r1], v2 = buf[i2] * wv[r2], v3 = buf[i3] * wv[r3];
-        acc += v0;
-        acc += v1;
-        acc += v2;
-        acc += v3;
-    }
-    for (; j < e; ++j) {
-        const double v = buf[idx[j]] * wv[rows[j]];
-        acc += v;
-    }
-    put(out, s, acc, ep, alpha);
-}
-
 // The same sums for maps with long segments: lane l of the job adds one
 // chunk of at most kExaChunk entries, whose positions sit in its own lane
 // record, so the record, the positions and then the values are two
@@ -91,19 +64,11 @@ __device__ __forceinline__ void seg_body_prod(const int32_t* __restrict__ ptr, c
 // depends on the map only.  Called by every lane of the workgroup, with
 // l < J.nlanes (launches cover whole 256-lane blocks).
 __device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double* lds, bool ep, double alpha) {
-#pragma clang fp contract(off)
     static_assert(kExaChunk == 4, "one int4 of positions per lane");
     const double* __restrict__ buf = J.buf;
     const int2 m = ((const int2*)J.lanes)[l];
     const int4 ix = ((const int4*)J.lidx)[l];
-    double v0 = buf[ix.x], v1 = buf[ix.y], v2 = buf[ix.z], v3 = buf[ix.w];
-    if (J.wv) {  // products, each rounded before the sums
-        const int4 rw = ((const int4*)J.lrow)[l];
-        v0 = v0 * J.wv[rw.x];
-        v1 = v1 * J.wv[rw.y];
-        v2 = v2 * J.wv[rw.z];
-        v3 = v3 * J.wv[rw.w];
-    }
+    const double v0 = buf[ix.x], v1 = buf[ix.y], v2 = buf[ix.z], v3 = buf[ix.w];
     const int seg = m.x, cnt = m.y & 15, nl = m.y >> 4;
     double part = 0.0;
     if (cnt > 0) part += v0;
@@ -156,10 +121,6 @@ __device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t r, do
         double v[kExaChunk];
 #pragma unroll
         for (int u = 0; u < kExaChunk; ++u) v[u] = buf[ix[u]];
-        if (J.wv) {
-#pragma unroll
-            for (int u = 0; u < kExaChunk; ++u) v[u] = v[u] * J.wv[J.rows[j0 + (u < cnt ? u : cnt - 1)]];
-        }
 #pragma unroll
         for (int u = 0; u < kExaChunk; ++u)
             if (u < cnt) part += v[u];
@@ -225,9 +186,6 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
     if (s < J.nseg) {
         if (J.wide)
             seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false, ep, R.ax_alpha);
-        else if (J.wv)
-            seg_body_prod((const int32_t*)J.ptr, (const int32_t*)J.idx, J.rows, J.buf, J.wv, J.out, s, J.nparts > 0, ep,
-                          R.ax_alpha);
         else
             seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0, ep, R.ax_alpha);
     }
@@ -282,9 +240,6 @@ __device__ __forceinline__ ExaSegJob batch_seg(const ExaBatchReduce& R, const Ex
     J.lsum = B.lsum;
     J.wide = B.wide;
     J.chunked = B.chunked;
-    J.wv = B.wv >= 0 ? R.bufs[B.wv] + B.wv_off : nullptr;
-    J.rows = B.rows;
-    J.lrow = B.lrow;
     return J;
 }
 
@@ -330,9 +285,6 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce_batch(ExaBatchReduce R) {
     if (s < J.nseg) {
         if (J.wide)
             seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false, ep, R.alpha);
-        else if (J.wv)
-            seg_body_prod((const int32_t*)J.ptr, (const int32_t*)J.idx, J.rows, J.buf, J.wv, J.out, s, J.nparts > 0, ep,
-                          R.alpha);
         else
             seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0, ep, R.alpha);
     }
@@ -406,7 +358,6 @@ hipError_t exa_launch_reduce(const ExaReduce& r, hipStream_t s) {
         if (J.chunked && (J.nlanes % kSegBlock || J.wide || (J.nlanes && !(J.lanes && J.lidx))))
             return hipErrorInvalidValue;
         if (J.nparts && (J.wide || !(J.longs && J.lpart && J.lsum && J.nlong > 0))) return hipErrorInvalidValue;
-        if (J.wv && (J.wide || !J.rows || (J.chunked && J.nlanes && !J.lrow))) return hipErrorInvalidValue;
         blocks += job_blocks(J);
         nlong += J.nparts ? J.nlong : 0;
     }

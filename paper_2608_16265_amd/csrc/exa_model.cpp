@@ -1,6 +1,7 @@
 // Model build on the host: validation, build-time simplification (Sec. 7.1.2),
 // sparsity structure by the probe rule of Sec. 5.2, output offsets and strides
 // (Sec. 3.4, Sec. 5.3.2) and the sorted reduction maps (Sec. 7.2.3).
+#include <set>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -378,9 +379,6 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
         if (P.kind == EXA_OBJ) {
             P.ob = M.fo_obj_len;
             M.fo_obj_len += bs * P.o1step();
-        } else {
-            P.ob = M.fo_con_len;
-            M.fo_con_len += bs * P.o1step();
         }
         if (P.pstep() > 0 && P.o1step() > 0) {
             P.op = M.par_len;
@@ -392,9 +390,33 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             for (auto& h : P.hslots) curved |= h.first == s || h.second == s;
             if (curved) P.hvs.push_back(s);
         }
-        P.oh = M.hv_len;
-        M.hv_len += bs * (int64_t)P.hvs.size();
-        M.nhv += P.ndata * (int64_t)P.hvs.size();
+    }
+    // J^T w and H v blocks per data-set group: the members' contributions to
+    // one variable reference are summed in the lane (members in declaration
+    // order), so a group writes one slot per reference instead of one per
+    // member and slot
+    for (Group& G : M.groups) {
+        std::set<int> jr, hr;
+        for (int p : G.members) {
+            const Pattern& P = M.pats[p];
+            if (P.ndata == 0) continue;
+            if (P.kind != EXA_OBJ)
+                for (int s = 0; s < P.o1step(); ++s) jr.insert(P.vg[s]);
+            for (int s : P.hvs) hr.insert(P.vg[s]);
+        }
+        G.jt_refs.assign(jr.begin(), jr.end());
+        G.hv_refs.assign(hr.begin(), hr.end());
+        const int64_t bs = (G.ndata + 15) & ~(int64_t)15;
+        G.ob = M.fo_con_len;
+        M.fo_con_len += bs * (int64_t)G.jt_refs.size();
+        G.oh = M.hv_len;
+        M.hv_len += bs * (int64_t)G.hv_refs.size();
+        M.nhv += G.ndata * (int64_t)G.hv_refs.size();
+        for (int p : G.members) {
+            Pattern& P = M.pats[p];
+            if (P.kind != EXA_OBJ) P.ob = G.ob;
+            P.oh = G.oh;
+        }
     }
     M.ncon = ncon;
     M.nnzj = nnzj;
@@ -450,29 +472,34 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     }
 
     // ---- reduction maps (Sec. 7.2.3): sorted by target; within a target
-    // the contributions are summed in (pattern, data point, slot) order.
+    // the contributions are summed in (pattern, data point, slot) order, and
+    // the J^T w and H v group entries in (group, data point, reference) order.
     // The work buffers hold each pattern's block slot-major: slot s of data
     // point k at block + s * bstride() + k (the constraint part of the
     // first-order buffer after the objective part).
-    std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr, jtc, jtr;
+    std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr;
+    for (const Group& G : M.groups) {
+        const Pattern& P0 = M.pats[G.members[0]];  // the group's data arrays
+        const int64_t bs = (G.ndata + 15) & ~(int64_t)15;
+        auto var = [&](int r, int64_t k) {
+            const RefKey& rk = G.vrefs[r];
+            return rk.col < 0 ? rk.off : (int64_t)P0.icols[rk.col][k] + rk.off;
+        };
+        // a variable sums its group entries in (group, data point, reference)
+        // order
+        for (int64_t k = 0; k < G.ndata; ++k) {
+            for (size_t j = 0; j < G.jt_refs.size(); ++j)
+                jt.emplace_back(var(G.jt_refs[j], k), M.fo_obj_len + G.ob + (int64_t)j * bs + k);
+            for (size_t j = 0; j < G.hv_refs.size(); ++j)
+                h.emplace_back(var(G.hv_refs[j], k), G.oh + (int64_t)j * bs + k);
+        }
+    }
     for (auto& P : M.pats) {
         const int st = P.o1step();
         const int64_t bs = P.bstride();
-        for (int64_t k = 0; k < P.ndata; ++k)
-            for (int s = 0; s < st; ++s) {
-                const int64_t v = P.var_index(s, k);
-                if (P.kind == EXA_OBJ) {
-                    g.emplace_back(v, P.ob + s * bs + k);
-                } else {
-                    jt.emplace_back(v, M.fo_obj_len + P.ob + s * bs + k);
-                    // the same entry of the COO Jacobian, and its row
-                    jtc.emplace_back(v, P.o1 + k * st + s);
-                    jtr.emplace_back(v, P.row(k));
-                }
-            }
-        const int hs = (int)P.hvs.size();
-        for (int64_t k = 0; k < P.ndata; ++k)
-            for (int i = 0; i < hs; ++i) h.emplace_back(P.var_index(P.hvs[i], k), P.oh + i * bs + k);
+        if (P.kind == EXA_OBJ)
+            for (int64_t k = 0; k < P.ndata; ++k)
+                for (int s = 0; s < st; ++s) g.emplace_back(P.var_index(s, k), P.ob + s * bs + k);
         if (P.pstep() > 0 && P.o1step() > 0)
             for (int64_t k = 0; k < P.ndata; ++k)
                 for (int t = 0; t < P.pstep(); ++t)
@@ -490,10 +517,14 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     inside(pr, M.par_len, "parameter buffer");
     for (auto& P : M.pats) {
         const int64_t bs = P.bstride();
-        if (P.ob + bs * P.o1step() > (P.kind == EXA_OBJ ? M.fo_obj_len : M.fo_con_len) ||
-            P.oh + bs * (int64_t)P.hvs.size() > M.hv_len ||
+        if ((P.kind == EXA_OBJ && P.ob + bs * P.o1step() > M.fo_obj_len) ||
             (P.pstep() > 0 && P.o1step() > 0 && P.op + bs * P.pstep() > M.par_len))
             fail(EXA_EINVAL, "internal: a pattern's work-buffer block ends past its buffer");
+    }
+    for (const Group& G : M.groups) {
+        const int64_t bs = (G.ndata + 15) & ~(int64_t)15;
+        if (G.ob + bs * (int64_t)G.jt_refs.size() > M.fo_con_len || G.oh + bs * (int64_t)G.hv_refs.size() > M.hv_len)
+            fail(EXA_EINVAL, "internal: a group's work-buffer block ends past its buffer");
     }
     build_map(M.grad_map, M.nvar, g);
     M.grad_direct = true;
@@ -507,8 +538,6 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
         v = e;
     }
     build_map(M.jt_map, M.nvar, jt);
-    build_map(M.jtc_map, M.nvar, jtc);
-    build_map(M.jtc_rows, M.nvar, jtr);
     build_map(M.h_map, M.nvar, h);
     build_map(M.par_map, M.ntheta, pr);
     for (auto& P : M.pats) {

@@ -324,11 +324,10 @@ int64_t estimate_device_bytes(const Model& M) {
     b += 8 * (M.fo_obj_len + M.fo_con_len + M.par_len + M.hv_len + std::max<int64_t>(1, nobj) + M.nvar + 1);
     // maps: pointers and positions, plus at most a 24-byte record per four
     // entries (chunked sums, with padding) and part sums
-    for (const SegMap* S : {&M.grad_map, &M.jt_map, &M.h_map, &M.par_map, &M.jtc_map}) {
+    for (const SegMap* S : {&M.grad_map, &M.jt_map, &M.h_map, &M.par_map}) {
         const int64_t nnz = (int64_t)S->idx.size();
         b += 8 * (S->nseg() + 1) + 8 * nnz + 8 * nnz + 24 * 256 + 8 * (nnz / kExaLongSeg + 1);
     }
-    b += 8 * (int64_t)M.jtc_map.idx.size() + 16 * 256;  // rows of the products map
     return b;
 }
 
@@ -382,9 +381,6 @@ void build_device(Model& M) {
     upload_map(D, M.jt_map, D.jt_map);
     upload_map(D, M.h_map, D.h_map);
     upload_map(D, M.par_map, D.par_map);
-    // J^T w from the Jacobian values needs every COO position in int32
-    D.jtc_ok = M.nnzj < INT32_MAX && M.ncon < INT32_MAX;
-    if (D.jtc_ok) upload_map(D, M.jtc_map, D.jtc_map, &M.jtc_rows);
     // the caller's float columns are not kept past create
     for (auto& P : M.pats) P.fcols_src.assign(P.fcols_src.size(), nullptr);
 }
@@ -409,13 +405,12 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
 }
 
 // maps go to the device as int32 whenever every position fits
-void upload_map(DeviceState& D, const SegMap& S, DevMap& d, const SegMap* rows) {
+void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     d.nseg = S.nseg();
     int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
     top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
     d.wide = top >= INT32_MAX ? 1 : 0;
     if (d.wide) {
-        if (rows) fail(EXA_EINVAL, "internal: sums of products need int32 maps");
         d.ptr = D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
         d.idx = D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
         return;
@@ -423,16 +418,11 @@ void upload_map(DeviceState& D, const SegMap& S, DevMap& d, const SegMap* rows) 
     std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
     d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
     d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
-    if (rows) {
-        std::vector<int32_t> r32(rows->idx.begin(), rows->idx.end());
-        d.rows = (const int32_t*)D.upload(r32.data(), r32.size() * sizeof(int32_t));
-    }
-    const ChunkPlan P = chunk_plan(S, rows);
+    const ChunkPlan P = chunk_plan(S);
     d.chunked = P.chunked ? 1 : 0;
     if (P.nlanes()) {
         d.lanes = (const int32_t*)D.upload(P.meta.data(), P.meta.size() * sizeof(int32_t));
         d.lidx = (const int32_t*)D.upload(P.lidx.data(), P.lidx.size() * sizeof(int32_t));
-        if (rows) d.lrow = (const int32_t*)D.upload(P.lrow.data(), P.lrow.size() * sizeof(int32_t));
         d.nlanes = P.nlanes();
     }
     if (P.nparts()) {
@@ -490,7 +480,7 @@ Model::Csc& csc_form(Model& M, int which) {
     return C;
 }
 
-ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows) {
+ChunkPlan chunk_plan(const SegMap& S) {
     ChunkPlan P;
     int64_t longest = 0, top = S.ptr.empty() ? 0 : S.ptr.back();
     for (int64_t s = 0; s < S.nseg(); ++s) longest = std::max(longest, S.ptr[s + 1] - S.ptr[s]);
@@ -512,7 +502,6 @@ ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows) {
         while (P.nlanes() < lanes) {
             P.meta.insert(P.meta.end(), {-1, 0});
             P.lidx.insert(P.lidx.end(), {0, 0, 0, 0});
-            if (rows) P.lrow.insert(P.lrow.end(), {0, 0, 0, 0});
         }
     };
     int64_t nparts = 0, most = 0;
@@ -536,9 +525,6 @@ ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows) {
             // the chunk's positions, the last one repeated past its count
             for (int64_t u = 0; u < kExaChunk; ++u)
                 P.lidx.push_back(cnt ? (int32_t)S.idx[b + c * kExaChunk + std::min(u, cnt - 1)] : 0);
-            if (rows)
-                for (int64_t u = 0; u < kExaChunk; ++u)
-                    P.lrow.push_back(cnt ? (int32_t)rows->idx[b + c * kExaChunk + std::min(u, cnt - 1)] : 0);
         }
     }
     if (P.chunked) pad_to((P.nlanes() + 255) / 256 * 256);
@@ -693,12 +679,6 @@ std::vector<int> eval_modes(uint32_t mask, bool jh) {
     return m;
 }
 
-// The callbacks whose tiles a launch runs: a J^T w summed from the Jacobian
-// values of the same call has none.
-uint32_t tile_mask(uint32_t mask, bool jt_from_jac) {
-    return (jt_from_jac && (mask & EXA_EV_JAC)) ? mask & ~(uint32_t)EXA_EV_JTPROD : mask;
-}
-
 // Multi-unit mode that covers a mask's callbacks besides the objective in
 // one pass per point, or -1.
 int combined_mode_of(uint32_t mask) {
@@ -732,30 +712,19 @@ std::vector<int> launch_modes(uint32_t mask, int units) {
     return m;
 }
 
-// Without timing: J^T w of a mask with the Jacobian comes from the Jacobian
-// values when the evaluation launch writes more than the 256 MB last-level
-// cache holds (its contribution buffer would be read back from HBM), else
-// from its own tiles' buffer, which the reduction then reads from cache.
-bool default_jt_from_jac(const Model& M, uint32_t mask) {
-    if (!((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD)) || !M.dev || !M.dev->jtc_ok) return false;
-    return 8 * (M.nnzj + M.nnzh + M.fo_con_len) > ((int64_t)256 << 20);
-}
-
 namespace {
 
 // Tile list of a mask: every launch mode's tiles (the objective's under its
 // fixed schedule), laid out as eight chunks that each hold an eighth of
 // every mode's tiles, so that the per-XCD ranges of the launch get the same
 // mix of work and contiguous point ranges.
-void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, int units, bool jt_from_jac) {
+void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused, int units) {
     DeviceState& D = *M.dev;
     DeviceState::MultiSched& S = D.multi[mask];
-    jt_from_jac = jt_from_jac && (mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && D.jtc_ok;
-    const uint32_t tm = tile_mask(mask, jt_from_jac);
-    units = valid_units(tm, units);
+    units = valid_units(mask, units);
     const int64_t tp = (int64_t)block * epl;
     std::vector<std::vector<ExaTile>> per;
-    for (int mode : launch_modes(tm, units)) {
+    for (int mode : launch_modes(mask, units)) {
         std::vector<ExaTile> t = mode == M_OBJ ? make_tiles(M, M_OBJ, 0, (int64_t)kObjBlock * kObjEpl, kObjFused)
                                                : make_tiles(M, mode, 0, tp, fused);
         for (ExaTile& x : t) x.pat |= mode << EXA_MODE_SHIFT;
@@ -777,7 +746,6 @@ void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused,
     S.epl = epl;
     S.fused = fused;
     S.units = units;
-    S.jt_from_jac = jt_from_jac;
 }
 
 
@@ -803,8 +771,7 @@ void raw_launch_multi(Model& M, uint32_t mask, ExaMulti mc, hipStream_t s) {
 // combined launch and keep the fastest (as tune() does for one callback).
 // Objective tiles keep their fixed size and summation order under every
 // candidate.
-void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, const std::function<void(bool)>& step) {
-    const bool jt0 = M.dev->multi[mask].jt_from_jac;
+void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, const std::function<void()>& step) {
     const int blocks[] = {64, 128, 256};
     const int epls[] = {1, 2, 4, 8};
     std::vector<int> fuses = {0};
@@ -840,7 +807,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
         for (int f : fuses)
             for (int b : blocks)
                 for (int ep : epls) {
-                    set_multi_schedule(M, mask, b, ep, f != 0, cb, jt0);
+                    set_multi_schedule(M, mask, b, ep, f != 0, cb);
                     cands.push_back({time_it(3), b, ep, f, cb});
                 }
         // neighbouring schedules differ by less than one timing's noise: the
@@ -851,7 +818,7 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
         for (auto& c : cands) c.ms = 1e30f;
         for (int round = 0; round < 3; ++round)
             for (auto& c : cands) {
-                set_multi_schedule(M, mask, c.block, c.epl, c.fused != 0, c.comb, jt0);
+                set_multi_schedule(M, mask, c.block, c.epl, c.fused != 0, c.comb);
                 c.ms = std::min(c.ms, time_it(16));
             }
     } catch (...) {
@@ -862,20 +829,19 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const Cand& w = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, jt0);
-    // staged or each lane's own stores, then (with the Jacobian and J^T w)
-    // J^T w from its own tiles and buffer or from the Jacobian values: the
-    // whole step (evaluation and reductions) decides
+    set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb);
+    // staged or each lane's own stores: the whole step (evaluation and
+    // reductions) decides
     if (mask & (EXA_EV_JAC | EXA_EV_HESS)) {
         float best[2] = {1e30f, 1e30f};
         for (int round = 0; round < 3; ++round)
             for (int u = 0; u < 2; ++u) {
                 M.dev->multi[mask].unstaged = u != 0;
-                step(jt0);
+                step();
                 hip_check(hipEventCreate(&e0), "hipEventCreate");
                 hip_check(hipEventCreate(&e1), "hipEventCreate");
                 hip_check(hipEventRecord(e0, s), "hipEventRecord");
-                for (int r = 0; r < 16; ++r) step(jt0);
+                for (int r = 0; r < 16; ++r) step();
                 hip_check(hipEventRecord(e1, s), "hipEventRecord");
                 hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
                 float ms = 0;
@@ -885,29 +851,6 @@ void tune_multi(Model& M, uint32_t mask, const ExaMulti& mc, hipStream_t s, cons
                 best[u] = std::min(best[u], ms / 16);
             }
         M.dev->multi[mask].unstaged = best[1] < best[0];
-    }
-    const bool unstaged = M.dev->multi[mask].unstaged;
-    if ((mask & EXA_EV_JAC) && (mask & EXA_EV_JTPROD) && M.dev->jtc_ok) {
-        float best[2] = {1e30f, 1e30f};
-        for (int round = 0; round < 3; ++round)
-            for (int jt = 0; jt < 2; ++jt) {
-                set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, jt != 0);
-                M.dev->multi[mask].unstaged = unstaged;
-                step(jt != 0);
-                hip_check(hipEventCreate(&e0), "hipEventCreate");
-                hip_check(hipEventCreate(&e1), "hipEventCreate");
-                hip_check(hipEventRecord(e0, s), "hipEventRecord");
-                for (int r = 0; r < 16; ++r) step(jt != 0);
-                hip_check(hipEventRecord(e1, s), "hipEventRecord");
-                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                float ms = 0;
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                best[jt] = std::min(best[jt], ms / 16);
-            }
-        set_multi_schedule(M, mask, w.block, w.epl, w.fused != 0, w.comb, best[1] < best[0]);
-        M.dev->multi[mask].unstaged = unstaged;
     }
     if (log_on())
         log_msg("tuned exa_eval mask " + std::to_string(mask) + ": block " + std::to_string(w.block) +
@@ -985,7 +928,7 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
 
 // Reduction launch of an exa_eval mask: maps (int32 when every position
 // fits), buffer entries once, outputs once; objective partials when several.
-void reduce_bytes(const Model& M, uint32_t mask, bool jt_from_jac, int64_t& rr, int64_t& rw) {
+void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
     rr = rw = 0;
     auto seg = [&](const SegMap& S) {
         const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
@@ -1005,16 +948,7 @@ void reduce_bytes(const Model& M, uint32_t mask, bool jt_from_jac, int64_t& rr, 
         rw += 8 * nseg + 8 * P.nparts();
     };
     if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && !M.grad_direct) seg(M.grad_map);
-    if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && jt_from_jac) {
-        // sums of products of the Jacobian values: the map as above plus a
-        // row per entry (4 bytes, in the lane records or beside the
-        // positions), and each weight w[row] once
-        seg(M.jtc_map);
-        rr += 4 * (int64_t)M.jtc_map.idx.size() + 8 * M.ncon;
-    } else if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) {
-        seg(M.jt_map);
-    }
-
+    if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) seg(M.jt_map);
     if (mask & EXA_EV_HPROD) seg(M.h_map);
     if (mask & EXA_EV_ADJ) seg(M.par_map);
     if (mask & EXA_EV_OBJ) {
@@ -1042,8 +976,6 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
     J.nparts = m.nparts;
     J.nlong = m.nlong;
     J.lsum = m.lsum;
-    J.rows = m.rows;
-    J.lrow = m.lrow;
     J.buf = buf;
     J.out = out;
     return J;
@@ -1442,9 +1374,6 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     if (mask & EXA_EV_HPROD) need(a->hv, M.nvar, "hv");
     DeviceState& D = *M.dev;
     const int64_t nobj = D.sched[M_OBJ].ntiles;
-    if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && !D.jtc_ok)
-        fail(EXA_EINVAL, "J^T w with the Jacobian in one exa_eval call needs fewer than 2^31 Jacobian entries; "
-                         "call exa_jtprod separately");
 
     // each mode's call, as its own entry point sets it up
     ExaMulti mc;
@@ -1505,7 +1434,7 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
         ch.out0 = a->hess;
     }
     // the reductions of every selected callback, in one launch
-    auto reduce_of = [&](bool jt_from_jac) {
+    auto reduce_of = [&]() {
         ExaReduce R;
         std::memset(&R, 0, sizeof R);
         R.ep_job = -1;
@@ -1518,11 +1447,6 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
             R.ep_job = R.njobs;
             R.ax_alpha = lag_sigma;
             job(D.jt_map, D.fo, a->g);
-        } else if ((mask & EXA_EV_JTPROD) && (mask & EXA_EV_JAC) && jt_from_jac) {
-            // J^T w from the Jacobian values this launch wrote: w[row] times
-            // each entry, summed per variable in the order of jt_map
-            job(D.jtc_map, a->jac, a->jtw);
-            R.job[R.njobs - 1].wv = a->w;
         } else if (mask & EXA_EV_JTPROD) {
             job(D.jt_map, D.fo, a->jtw);
         }
@@ -1543,11 +1467,11 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     auto it = D.multi.find(mask);
     if (it == D.multi.end() || !it->second.tuned) {
         const int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
-        set_multi_schedule(M, mask, M.block, M.epl, M.fuse, units, default_jt_from_jac(M, mask));
+        set_multi_schedule(M, mask, M.block, M.epl, M.fuse, units);
         if (M.autotune)
-            tune_multi(M, mask, mc, s, [&](bool jt) {
+            tune_multi(M, mask, mc, s, [&]() {
                 raw_launch_multi(M, mask, mc, s);
-                hip_check(exa_launch_reduce(reduce_of(jt), s), "exa_eval reductions");
+                hip_check(exa_launch_reduce(reduce_of(), s), "exa_eval reductions");
             });
         D.multi[mask].tuned = true;
     }
@@ -1558,7 +1482,7 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     if (timed) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
     raw_launch_multi(M, mask, mc, s);
     if (timed) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
-    const ExaReduce R = reduce_of(S.jt_from_jac);
+    const ExaReduce R = reduce_of();
     const bool reduce = R.njobs > 0 || R.part;
     if (timed && reduce) hip_check(hipEventRecord(ev[2], s), "hipEventRecord");
     hip_check(exa_launch_reduce(R, s), "exa_eval reductions");
@@ -1692,23 +1616,21 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        bool fused = M.fuse, jt = M.dev ? default_jt_from_jac(M, mask) : false;
+        bool fused = M.fuse;
         int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
         if (M.dev) {
             auto it = M.dev->multi.find(mask);
             if (it != M.dev->multi.end()) {
                 fused = it->second.fused;
                 units = it->second.units;
-                jt = it->second.jt_from_jac;
             }
         }
         int64_t rd = 0, wr = 0;
-        const uint32_t tm = tile_mask(mask, jt);
-        kernel_bytes(M, launch_modes(tm, valid_units(tm, units)), fused, rd, wr);
+        kernel_bytes(M, launch_modes(mask, valid_units(mask, units)), fused, rd, wr);
         out4[0] = rd;
         out4[1] = wr;
         int64_t rr = 0, rw = 0;
-        reduce_bytes(M, mask, jt, rr, rw);
+        reduce_bytes(M, mask, rr, rw);
         out4[2] = rr;
         out4[3] = rw;
     });
@@ -1722,14 +1644,14 @@ exa_status exa_eval_set_schedule(exa_model* m, uint32_t mask, int32_t block, int
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         if (block != 64 && block != 128 && block != 256) fail(EXA_EINVAL, "block must be 64, 128 or 256");
         if (epl < 1 || epl > 16) fail(EXA_EINVAL, "points per lane must be in 1..16");
-        if ((units & ~(EXA_JT_FROM_JAC | EXA_UNSTAGED)) < EXA_UNITS_PER_CALLBACK)
+        if ((units & ~EXA_UNSTAGED) < EXA_UNITS_PER_CALLBACK)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
-        const bool jt = (units & EXA_JT_FROM_JAC) != 0, unstaged = (units & EXA_UNSTAGED) != 0;
-        units &= ~(EXA_JT_FROM_JAC | EXA_UNSTAGED);
+        const bool unstaged = (units & EXA_UNSTAGED) != 0;
+        units &= ~EXA_UNSTAGED;
         if (units < EXA_UNITS_PER_CALLBACK || units > EXA_UNITS_ONE_PASS)
             fail(EXA_EINVAL, "units must be one of the EXA_UNITS_* values");
         if (units == EXA_UNITS_ONE_PASS && M.eval_per_mode) units = EXA_UNITS_JAC_HESS;
-        set_multi_schedule(M, mask, block, epl, fused != 0, units, jt);
+        set_multi_schedule(M, mask, block, epl, fused != 0, units);
         M.dev->multi[mask].unstaged = unstaged;
         M.dev->multi[mask].tuned = true;
     });
@@ -1744,8 +1666,7 @@ exa_status exa_eval_schedule(const exa_model* m, uint32_t mask, int64_t* out4) {
         out4[0] = it->second.block;
         out4[1] = it->second.epl;
         out4[2] = (it->second.fused ? 1 : 0) | (it->second.units == EXA_UNITS_ONE_PASS ? 2 : 0) |
-                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0) | (it->second.jt_from_jac ? 8 : 0) |
-                  (it->second.unstaged ? 16 : 0);
+                  (it->second.units == EXA_UNITS_JAC_HESS ? 4 : 0) | (it->second.unstaged ? 16 : 0);
         out4[3] = it->second.ntiles;
     });
 }

@@ -37,10 +37,6 @@ struct DevMap {
     const int32_t* lpart = nullptr;
     int64_t nparts = 0, nlong = 0;
     double* lsum = nullptr;
-    // products (see ExaSegJob): the row of each entry, and of each lane's
-    // four positions
-    const int32_t* rows = nullptr;
-    const int32_t* lrow = nullptr;
 };
 
 struct DeviceState {
@@ -65,9 +61,6 @@ struct DeviceState {
     struct MultiSched {
         int block = 256, epl = 4;
         bool fused = false, tuned = false;
-        // J^T w of a mask with the Jacobian: summed from the Jacobian values
-        // (no tiles, no buffer) or from its own tiles' buffer
-        bool jt_from_jac = false;
         bool unstaged = false;  // each lane stores its own output slices
         int units = EXA_UNITS_PER_CALLBACK;  // EXA_UNITS_*: which kernel and units run the tiles
         ExaTile* tiles = nullptr;
@@ -93,8 +86,6 @@ struct DeviceState {
     DevMap csc_map[2];          // uploaded on the first exa_csc_values call
     bool csc_up[2] = {false, false};
     DevMap grad_map, jt_map, h_map, par_map;
-    DevMap jtc_map;  // J^T w from the Jacobian's COO values (int32 maps only)
-    bool jtc_ok = false;
 
     void* alloc(size_t bytes);
     void* upload(const void* src, size_t bytes);
@@ -126,17 +117,10 @@ std::vector<int> eval_modes(uint32_t mask, bool jh);
 int combined_mode_of(uint32_t mask);
 bool has_jh(uint32_t mask);
 int valid_units(uint32_t mask, int units);
-// The callbacks whose tiles a launch runs (J^T w from the Jacobian values of
-// the same call has none).
-uint32_t tile_mask(uint32_t mask, bool jt_from_jac);
 std::vector<int> launch_modes(uint32_t mask, int units);
 // Algorithmic bytes of the reduction launch of a mask (maps, buffer entries,
 // outputs, objective partials when there are several).
-void reduce_bytes(const Model& M, uint32_t mask, bool jt_from_jac, int64_t& rd, int64_t& wr);
-// Whether J^T w of a mask with the Jacobian is summed from the Jacobian
-// values when no tuning decides (the launch writes more than the last-level
-// cache holds).
-bool default_jt_from_jac(const Model& M, uint32_t mask);
+void reduce_bytes(const Model& M, uint32_t mask, int64_t& rd, int64_t& wr);
 std::vector<char> compile_code(const std::string& src);
 // The code object of a source through the on-disk cache in `dir` (empty: no
 // cache); *hit tells whether it was read from the cache.
@@ -165,19 +149,18 @@ void set_schedule(Model& M, int mode, int block, int epl, bool fused);
 struct ChunkPlan {
     bool chunked = false;  // chunk lanes (else one lane per segment)
     std::vector<int32_t> meta, lidx;    // 2 and 4 per lane, a multiple of 256 lanes
-    std::vector<int32_t> lrow;          // with rows: 4 per lane, beside lidx
     std::vector<int32_t> longs, lpart;  // 5 per long segment; 2 per part block
     int64_t nlanes() const { return (int64_t)meta.size() / 2; }
     int64_t nlong() const { return (int64_t)longs.size() / 5; }
     int64_t nparts() const { return (int64_t)lpart.size() / 2; }
 };
-ChunkPlan chunk_plan(const SegMap& S, const SegMap* rows = nullptr);
+ChunkPlan chunk_plan(const SegMap& S);
 // live: the liveness records of the code that runs (default: the model's own)
 void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int64_t& rd, int64_t& wr,
                   const std::map<std::pair<int, int>, UnitLive>* live = nullptr);
 // Map and tables of a segment map on the device (int32 when positions fit,
 // chunked when segments are long).
-void upload_map(DeviceState& D, const SegMap& S, DevMap& d, const SegMap* rows = nullptr);
+void upload_map(DeviceState& D, const SegMap& S, DevMap& d);
 // CSC analysis of the Jacobian (which = 0) or Hessian (1) on first use.
 Model::Csc& csc_form(Model& M, int which);
 void jac_structure_host(const Model& M, int32_t* rows, int32_t* cols);

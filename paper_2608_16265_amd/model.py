@@ -382,18 +382,18 @@ class ExaModel:
         check(LIB.exa_eval_schedule(self._h, self._eval_mask(callbacks), _ptr(out, C.c_int64)))
         return dict(block=int(out[0]), points_per_lane=int(out[1]), fused=int(out[2]) & 1,
                     one_pass=(int(out[2]) >> 1) & 1, jac_hess=(int(out[2]) >> 2) & 1,
-                    jt_from_jac=(int(out[2]) >> 3) & 1, unstaged=(int(out[2]) >> 4) & 1, tiles=int(out[3]))
+                    unstaged=(int(out[2]) >> 4) & 1, tiles=int(out[3]))
 
     UNITS = {"per_callback": 0, "jac_hess": 1, "one_pass": 2}
 
     def set_eval_schedule(self, callbacks, block: int, points_per_lane: int, fused: bool = False,
-                          units="per_callback", jt_from_jac: bool = False, unstaged: bool = False):
+                          units="per_callback", unstaged: bool = False):
         """Fix exa_eval's schedule for a set of callback names (no tuning):
         units is "per_callback" (Jacobian and Hessian tiles apart),
-        "jac_hess" (Jacobian + Hessian units) or "one_pass"; jt_from_jac sums
-        J^T w from the Jacobian values when both are selected."""
+        "jac_hess" (Jacobian + Hessian units) or "one_pass"; unstaged stores
+        each lane's Jacobian and Hessian values itself."""
         u = self.UNITS[units] if isinstance(units, str) else int(units)
-        u |= (_lib.JT_FROM_JAC if jt_from_jac else 0) | (_lib.UNSTAGED if unstaged else 0)
+        u |= _lib.UNSTAGED if unstaged else 0
         check(LIB.exa_eval_set_schedule(self._h, self._eval_mask(callbacks), int(block), int(points_per_lane),
                                         1 if fused else 0, u))
 

@@ -286,13 +286,32 @@ def test_reduction_bytes_follow_the_chunk_plan(sizes):
     assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
 
 
+def _jt_entry_lengths(model):
+    """Entries per variable of the J^T w map: the constraint and augmentation
+    patterns over one data set add their contributions to one variable
+    reference in the lane, so a data point of a data set gives one entry per
+    distinct reference of those patterns (a second statement of the layout,
+    from the model description and the oracle's reference keys)."""
+    o = OracleModel(model)
+    refs = {}
+    for P, p in zip(o.pats, model.patterns):
+        if p.kind != "obj" and P.ndata > 0:
+            refs.setdefault(id(p.data), (P, set()))[1].update(P.vslots)
+    lengths = np.zeros(model.nvar, dtype=np.int64)
+    for P, keys in refs.values():
+        ks = np.arange(P.ndata)
+        for key in keys:
+            np.add.at(lengths, o._index(P, key, ks), 1)
+    return lengths
+
+
 def test_reduction_bytes_large_map_with_one_shared_variable():
     """Goddard's step variable is shared by all 3T rows: on a large model its
     segment is summed in parts and every other variable one lane each."""
     from paper_2608_16265_amd import ExaModel
-    em = ExaModel(goddard(300000, 0).model, host_only=True)
-    _, cols = em.jac_structure()
-    lengths = np.bincount(cols, minlength=em.nvar)
+    w = goddard(300000, 0)
+    em = ExaModel(w.model, host_only=True)
+    lengths = _jt_entry_lengths(w.model)
     assert lengths.max() > 1024 and np.sort(lengths)[-2] <= 16
     rd, wr = _chunk_plan_bytes(lengths)
     b = em.eval_bytes(("jtprod",))

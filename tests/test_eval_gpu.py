@@ -188,10 +188,11 @@ def test_fixed_schedule_gives_the_same_bits():
 
 @pytest.mark.parametrize("units", ["per_callback", "jac_hess", "one_pass"])
 @pytest.mark.parametrize("name", ["acopf600", "pde50", "star", "goddard_long", "two_stage", "alias", "empty"])
-def test_jtprod_from_jacobian_values(name, units):
-    """J^T w summed from the Jacobian values of the same call (no J^T w
-    tiles, no contribution buffer) gives the bits of exa_jtprod, whose
-    contributions are the Jacobian entries times w."""
+def test_store_choice_and_unfused_schedules_change_no_bit(name, units):
+    """Staged or each lane's own stores, fused or separate patterns (J^T w
+    and H v units always hold a data set's patterns, which add their
+    contributions in the lane): exa_eval gives the bits of the single
+    callbacks."""
     _need_gpu()
     from paper_2608_16265_amd import ExaModel
     w = CASES[name]()
@@ -199,11 +200,10 @@ def test_jtprod_from_jacobian_values(name, units):
     X, Y, sig, V, W = _inputs(w, em, seed=3)
     ref = _singles(em, X, Y, sig, V, W)
     for mask in (ALL, ("jac", "jtprod"), ("jac", "hess", "jtprod", "hprod"), ("grad", "jac", "jtprod")):
-        for jt, unstaged in ((True, False), (False, False), (True, True), (False, True)):
-            em.set_eval_schedule(mask, 128, 2, True, units, jt_from_jac=jt, unstaged=unstaged)
+        for fused, unstaged in ((True, False), (False, False), (True, True), (False, True)):
+            em.set_eval_schedule(mask, 128, 2, fused, units, unstaged=unstaged)
             outs = {FIELD[cb]: _nan_like(ref[FIELD[cb]]) for cb in mask}
             em.evaluate(X, Y, sig, V, W, **outs)
             for k, t in outs.items():
-                assert np.array_equal(host(t), ref[k]), f"{name} {mask} jt={jt} unstaged={unstaged}: {k}"
-            sch = em.eval_schedule(mask)
-            assert sch["jt_from_jac"] == int(jt) and sch["unstaged"] == int(unstaged), mask
+                assert np.array_equal(host(t), ref[k]), f"{name} {mask} fused={fused} unstaged={unstaged}: {k}"
+            assert em.eval_schedule(mask)["unstaged"] == int(unstaged), mask
