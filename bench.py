@@ -381,7 +381,9 @@ def leg_batch(steps, warmup, count=256, first_seed=1000):
     wls = acopf_batch(count, first_seed)
     ems = []
     for i, w in enumerate(wls):
-        ems.append(ExaModel(w.model))
+        # tuned per instance: the plain baseline is each instance's fastest
+        # exa_eval (the batch tunes its own schedule)
+        ems.append(ExaModel(w.model, autotune=True))
         if (i + 1) % 64 == 0:
             log(f"  batch: {i + 1}/{count} models built")
     build_s = time.perf_counter() - t0

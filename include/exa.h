@@ -144,8 +144,10 @@ typedef struct exa_options {
     int32_t eval_per_mode; /* 1: exa_eval runs one tile per callback and point
                           (as the single callbacks do); 0: it may also run
                           units that evaluate all selected callbacks of a point
-                          from one pass over its loads (chosen by autotune,
-                          used by default without it); results are the same  */
+                          from one pass over its loads, when autotune chooses
+                          them.  Without autotune exa_eval runs one tile per
+                          callback, patterns over the same data in one lane,
+                          with the block and epl above; results are the same  */
     int32_t reserved[2];
     const char* cache_dir; /* directory of the on-disk code-object cache (NULL
                           or "": the environment variable EXA_CACHE_DIR, else

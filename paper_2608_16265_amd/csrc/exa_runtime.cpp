@@ -1466,8 +1466,10 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
     };
     auto it = D.multi.find(mask);
     if (it == D.multi.end() || !it->second.tuned) {
-        const int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
-        set_multi_schedule(M, mask, M.block, M.epl, M.fuse, units);
+        // untuned: per-callback tiles (the kind the tuner picks on most
+        // models; one-pass units hold many registers), patterns over the
+        // same data in one lane
+        set_multi_schedule(M, mask, M.block, M.epl, true, EXA_UNITS_PER_CALLBACK);
         if (M.autotune)
             tune_multi(M, mask, mc, s, [&]() {
                 raw_launch_multi(M, mask, mc, s);
@@ -1616,8 +1618,8 @@ exa_status exa_eval_bytes(const exa_model* m, uint32_t mask, int64_t* out4) {
             fail(EXA_EINVAL, "mask must select callbacks with the EXA_EV_* bits");
         const Model& M = m->impl;
         if (M.live.empty()) generate_source(M, const_cast<std::map<std::pair<int, int>, UnitLive>*>(&M.live));
-        bool fused = M.fuse;
-        int units = M.eval_per_mode ? EXA_UNITS_JAC_HESS : EXA_UNITS_ONE_PASS;
+        bool fused = true;  // the untuned exa_eval schedule
+        int units = EXA_UNITS_PER_CALLBACK;
         if (M.dev) {
             auto it = M.dev->multi.find(mask);
             if (it != M.dev->multi.end()) {

@@ -61,8 +61,9 @@ def _nan_like(a):
 @pytest.mark.parametrize("autotune,per_mode", [(False, False), (False, True), (True, False)])
 @pytest.mark.parametrize("name", list(CASES))
 def test_eval_is_bitwise_equal_to_single_callbacks(name, autotune, per_mode):
-    """Per-callback tiles and one-pass units (every selected callback of a
-    point from one set of loads) give the single callbacks' bits."""
+    """Per-callback tiles (the untuned default) and one-pass units (every
+    selected callback of a point from one set of loads) give the single
+    callbacks' bits."""
     _need_gpu()
     from paper_2608_16265_amd import ExaModel
     w = CASES[name]()
@@ -70,14 +71,17 @@ def test_eval_is_bitwise_equal_to_single_callbacks(name, autotune, per_mode):
     X, Y, sig, V, W = _inputs(w, em)
     ref = _singles(em, X, Y, sig, V, W)
     for mask in MASKS:
-        outs = {FIELD[cb]: _nan_like(ref[FIELD[cb]]) for cb in mask}
-        em.evaluate(X, Y, sig, V, W, **outs)
-        for k, t in outs.items():
-            got = host(t)
-            assert np.array_equal(got, ref[k]), f"{name} {mask}: {k} differs from its single callback"
-        if not autotune:
-            one_pass = mask in (ALL, ("obj", "grad", "cons", "jac", "hess"))
-            assert em.eval_schedule(mask)["one_pass"] == (one_pass and not per_mode), mask
+        one_pass = mask in (ALL, ("obj", "grad", "cons", "jac", "hess"))
+        for units in ([None, "one_pass"] if one_pass and not autotune else [None]):
+            if units:
+                em.set_eval_schedule(mask, 256, 2, True, units)
+            outs = {FIELD[cb]: _nan_like(ref[FIELD[cb]]) for cb in mask}
+            em.evaluate(X, Y, sig, V, W, **outs)
+            for k, t in outs.items():
+                got = host(t)
+                assert np.array_equal(got, ref[k]), f"{name} {mask} {units}: {k} differs from its single callback"
+            if not autotune:
+                assert em.eval_schedule(mask)["one_pass"] == (units == "one_pass" and not per_mode), mask
 
 
 def test_bound_eval_follows_in_place_updates():
