@@ -263,7 +263,10 @@ exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv,
 exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jtw,
                       exa_stream_t stream);
 /* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod).
- * Contributions are summed as exa_jtprod sums them. */
+ * Contributions are summed as exa_jtprod sums them.  A variable reference
+ * of a data set whose every entry is the only H v contribution to its
+ * variable (ACOPF's branch flows, for instance) is written into Hv by the
+ * evaluation kernel; the reduction sums the other variables. */
 exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_weight,
                      const double* v, double* Hv, exa_stream_t stream);
 /* exa_hprod for callers that cannot allocate device memory (code under HIP

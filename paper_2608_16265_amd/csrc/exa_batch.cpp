@@ -462,6 +462,7 @@ ExaMulti call_records(exa_batch& b, uint32_t mask, const exa_batch_io& io) {
                 c.v = io.v;
                 c.sigma = io.obj_weight;
                 c.out0 = b.buf[kBufHv];
+                c.out1 = io.hv;
                 break;
             case M_ADJ:
                 c.y = io.y;

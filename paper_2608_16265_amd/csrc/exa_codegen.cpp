@@ -912,9 +912,17 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 const int at = (int)(std::find(refs.begin(), refs.end(), r) - refs.begin());
                 const std::string g = gname(j.mode) + "[" + std::to_string(at) + "]";
                 e.out(g, g + " + " + oname(j) + "[" + std::to_string(i) + "]");
-                if (last_adder[{j.mode, at}] == p)
-                    e.raw("if (kr < kend) (" + dest(P, j.mode, pd, j.out, false) + ")[" + std::to_string(at) + " * " +
-                          stride + " + kr] = " + g + ";");
+                if (last_adder[{j.mode, at}] != p) continue;
+                const std::string buf = "(" + dest(P, j.mode, pd, j.out, false) + ")[" + std::to_string(at) + " * " +
+                                        stride + " + kr] = " + g + ";";
+                if (j.mode == M_HPROD && at < 32)
+                    // a reference whose entries are their variables' only H v
+                    // contributions (this instance's bit) goes to the output
+                    e.raw("if (kr < kend) { if ((" + pd + ".hvd >> " + std::to_string(at) + ") & 1) " +
+                          call(M_HPROD) + ".out1[I.off[" + std::to_string(EXA_OFF_X) + "] + ix" + std::to_string(r) +
+                          "] = " + g + "; else " + buf + " }");
+                else
+                    e.raw("if (kr < kend) " + buf);
             }
         } else if (buffer_mode(j.mode)) {
             // contributions to a work buffer that a reduction reads back: slot
@@ -980,7 +988,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
             }
     // at most kPullTerms terms in flight per lane, shared by the pulls, so
     // that a round does not cost occupancy
-    constexpr int kPullTerms = 16;
+    constexpr int kPullTerms = 12;
     const int share = pulls.empty() ? 1 : std::max(1, kPullTerms / (int)pulls.size());
     for (Pull& q : pulls) q.R = std::min(q.R, share);
     // one round size per walk: the smallest of its pulls'
@@ -1371,8 +1379,9 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
     // four waves per SIMD, so that one wave of the launch fits on the chip at
     // once.  The Jacobian + Hessian units need the most registers, so they
     // get a kernel of their own: exa_k_multi runs the Jacobian and the
-    // Hessian as separate tiles (and fits four waves without spilling),
-    // exa_k_multijh runs them as JH units.
+    // Hessian as separate tiles and asks for five waves (its latency-bound
+    // pulls and gathers gain more from the fifth wave than the few values
+    // it then keeps in scratch cost), exa_k_multijh runs them as JH units.
     for (bool jh : {false, true}) {
         int lds = 0;
         std::vector<std::string> cases;
@@ -1381,7 +1390,7 @@ __device__ __forceinline__ int exa_term(int j, int je) { return j < je ? j : (je
             mode_cases(mode, cases);
         }
         cases.push_back(zero_case);
-        multi_kernel(jh ? "exa_k_multijh" : "exa_k_multi", lds, cases, 4);
+        multi_kernel(jh ? "exa_k_multijh" : "exa_k_multi", lds, cases, jh ? 4 : 5);
     }
     {
         int lds = mode_lds_doubles(M, M_OBJ);

@@ -48,6 +48,8 @@ void set_last_error(const std::string& msg);
 #define EXA_ZERO_TILE 1023
 #define EXA_PAD_TILE 4095  // a tile that matches no unit: does nothing
 
+// ExaPatDev::hvd: bit r set when the pattern's group stores H v reference r
+// straight into the output (Group::hv_direct, for this instance's data).
 #define EXA_DEVICE_STRUCTS                                                       \
     struct ExaPatDev {                                                           \
         const int* ic[8];                                                        \
@@ -62,7 +64,7 @@ void set_last_error(const std::string& msg);
         long long tgt0;                                                          \
         long long row_off;                                                       \
         int row_ic;                                                              \
-        int pad0;                                                                \
+        int hvd;                                                                 \
         const int* rptr;                                                         \
         const int* ridx;                                                         \
         long long roff[48];                                                      \
@@ -224,6 +226,10 @@ struct Group {
     // ob (constraint part of the first-order buffer) and oh (H v buffer)
     std::vector<int> jt_refs, hv_refs;
     int64_t ob = 0, oh = 0;
+    // per H v reference: every entry it stores is the only H v contribution
+    // to its variable (the kernel then writes the output entry itself when
+    // the instance's bit in ExaPatDev::hvd is set; at most 32 references)
+    std::vector<char> hv_direct;
 };
 
 // A unit of generated code for one callback: one pattern, or the members of
@@ -248,6 +254,9 @@ struct UnitLive {
 // Sorted reduction map (CSR): segment s sums buf[idx[ptr[s] .. ptr[s+1])].
 struct SegMap {
     std::vector<int64_t> ptr, idx;
+    // segments the reduction leaves alone (empty: none); such a segment has
+    // no entries, its output is written by the evaluation kernel
+    std::vector<char> skip;
     int64_t nseg() const { return ptr.empty() ? 0 : (int64_t)ptr.size() - 1; }
 };
 

@@ -33,12 +33,16 @@ __device__ __forceinline__ void put(double* __restrict__ out, int64_t s, double 
 
 // out[s] = sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
 // the sparse-to-dense compression of Sec. 7.2.3, one lane per segment, with
-// a fixed summation order so the result does not depend on scheduling.
+// a fixed summation order so the result does not depend on scheduling.  A
+// negative end (~end) marks a segment whose output the evaluation kernel
+// writes itself: it is left alone.
 template <class I>
 __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __restrict__ idx,
                                          const double* __restrict__ buf, double* __restrict__ out, int64_t s,
                                          bool parts, bool ep, double alpha) {
-    const int64_t b = ptr[s], e = ptr[s + 1];
+    const I pb = ptr[s], pe = ptr[s + 1];
+    if (pe < 0) return;
+    const int64_t b = pb < 0 ? ~pb : pb, e = pe;
     if (parts && e - b > kExaLongSeg) return;  // summed in parts
     double acc = 0.0;
     int64_t j = b;

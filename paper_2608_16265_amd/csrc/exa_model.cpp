@@ -478,20 +478,41 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     // point k at block + s * bstride() + k (the constraint part of the
     // first-order buffer after the objective part).
     std::vector<std::pair<int64_t, int64_t>> g, jt, h, pr;
+    auto gvar = [&](const Group& G, int r, int64_t k) {
+        const RefKey& rk = G.vrefs[r];
+        return rk.col < 0 ? rk.off : (int64_t)M.pats[G.members[0]].icols[rk.col][k] + rk.off;
+    };
+    // H v references whose every entry is the only H v contribution to its
+    // variable (at most 32 per group): the kernel stores those entries into
+    // the output directly, so they take no buffer round trip and no map
+    // entry, and the reduction skips their variables
+    std::vector<int32_t> hcount(M.nvar, 0);
+    for (const Group& G : M.groups)
+        for (int64_t k = 0; k < G.ndata; ++k)
+            for (int r : G.hv_refs) hcount[gvar(G, r, k)]++;
+    for (Group& G : M.groups) {
+        G.hv_direct.assign(G.hv_refs.size(), 0);
+        for (size_t j = 0; j < G.hv_refs.size() && j < 32; ++j) {
+            bool alone = G.ndata > 0;
+            for (int64_t k = 0; k < G.ndata && alone; ++k) alone = hcount[gvar(G, G.hv_refs[j], k)] == 1;
+            G.hv_direct[j] = alone ? 1 : 0;
+        }
+    }
+    std::vector<char> hskip(M.nvar, 0);
     for (const Group& G : M.groups) {
-        const Pattern& P0 = M.pats[G.members[0]];  // the group's data arrays
         const int64_t bs = (G.ndata + 15) & ~(int64_t)15;
-        auto var = [&](int r, int64_t k) {
-            const RefKey& rk = G.vrefs[r];
-            return rk.col < 0 ? rk.off : (int64_t)P0.icols[rk.col][k] + rk.off;
-        };
         // a variable sums its group entries in (group, data point, reference)
         // order
         for (int64_t k = 0; k < G.ndata; ++k) {
             for (size_t j = 0; j < G.jt_refs.size(); ++j)
-                jt.emplace_back(var(G.jt_refs[j], k), M.fo_obj_len + G.ob + (int64_t)j * bs + k);
-            for (size_t j = 0; j < G.hv_refs.size(); ++j)
-                h.emplace_back(var(G.hv_refs[j], k), G.oh + (int64_t)j * bs + k);
+                jt.emplace_back(gvar(G, G.jt_refs[j], k), M.fo_obj_len + G.ob + (int64_t)j * bs + k);
+            for (size_t j = 0; j < G.hv_refs.size(); ++j) {
+                const int64_t v = gvar(G, G.hv_refs[j], k);
+                if (G.hv_direct[j])
+                    hskip[v] = 1;
+                else
+                    h.emplace_back(v, G.oh + (int64_t)j * bs + k);
+            }
         }
     }
     for (auto& P : M.pats) {
@@ -539,6 +560,7 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     }
     build_map(M.jt_map, M.nvar, jt);
     build_map(M.h_map, M.nvar, h);
+    if (std::find(hskip.begin(), hskip.end(), 1) != hskip.end()) M.h_map.skip = std::move(hskip);
     build_map(M.par_map, M.ntheta, pr);
     for (auto& P : M.pats) {
         P.ident.assign(P.n_icols, 0);

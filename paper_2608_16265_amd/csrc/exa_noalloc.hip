@@ -83,6 +83,7 @@ exa_status exa_hprod_noalloc(exa_model* m, const double* x, const double* y, dou
         c.v = v;
         c.sigma = obj_weight;
         c.out0 = sp;
+        c.out1 = Hv;
         launch_mode_untuned(M, M_HPROD, c, s);
         DevMap map = D.h_map;
         if (map.nparts > 0) map.lsum = sp + hv_len;

@@ -297,6 +297,9 @@ void fill_patdev(const Model& M, DeviceState& D, ExaInstDev& inst) {
         d.tgt0 = P.tgt0;
         d.row_off = P.row_off;
         d.row_ic = P.row_icol;
+        const Group& G = M.groups[P.group];
+        for (size_t j = 0; j < G.hv_direct.size(); ++j)
+            if (G.hv_direct[j]) d.hvd |= 1 << j;
         if (P.kind == EXA_AUG) {
             d.rptr = (const int*)D.upload(P.rptr.data(), P.rptr.size() * sizeof(int32_t));
             d.ridx = (const int*)D.upload(P.ridx.data(), P.ridx.size() * sizeof(int32_t));
@@ -410,12 +413,17 @@ void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
     top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
     d.wide = top >= INT32_MAX ? 1 : 0;
+    // a segment the reduction skips has its end stored complemented (a
+    // negative value; see seg_body)
+    std::vector<int64_t> ptr = S.ptr;
+    for (size_t s = 0; s < S.skip.size(); ++s)
+        if (S.skip[s]) ptr[s + 1] = ~ptr[s + 1];
     if (d.wide) {
-        d.ptr = D.upload(S.ptr.data(), S.ptr.size() * sizeof(int64_t));
+        d.ptr = D.upload(ptr.data(), ptr.size() * sizeof(int64_t));
         d.idx = D.upload(S.idx.data(), S.idx.size() * sizeof(int64_t));
         return;
     }
-    std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end()), i32(S.idx.begin(), S.idx.end());
+    std::vector<int32_t> p32(ptr.begin(), ptr.end()), i32(S.idx.begin(), S.idx.end());
     d.ptr = D.upload(p32.data(), p32.size() * sizeof(int32_t));
     d.idx = D.upload(i32.data(), i32.size() * sizeof(int32_t));
     const ChunkPlan P = chunk_plan(S);
@@ -514,7 +522,7 @@ ChunkPlan chunk_plan(const SegMap& S) {
             most = std::max(most, parts);
             continue;
         }
-        if (!P.chunked) continue;
+        if (!P.chunked || (!S.skip.empty() && S.skip[s])) continue;
         const int64_t nl = std::max<int64_t>(1, (len + kExaChunk - 1) / kExaChunk);
         const int64_t here = P.nlanes();
         if (here % 256 + nl > 256) pad_to((here / 256 + 1) * 256);
@@ -945,7 +953,9 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
         for (int64_t i = 0; i < P.nlong(); ++i) long_nnz += P.longs[5 * i + 2];
         rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz : w * (nseg + 1) + w * nnz) + 40 * P.nlong() +
               16 * P.nparts() + 8 * nnz;
-        rw += 8 * nseg + 8 * P.nparts();
+        // segments written by the evaluation kernel are not written here
+        const int64_t nskip = (int64_t)std::count(S.skip.begin(), S.skip.end(), 1);
+        rw += 8 * (nseg - nskip) + 8 * P.nparts();
     };
     if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && !M.grad_direct) seg(M.grad_map);
     if (mask & (EXA_EV_JTPROD | EXA_EV_LAG)) seg(M.jt_map);
@@ -1346,6 +1356,7 @@ exa_status exa_hprod(exa_model* m, const double* x, const double* y, double obj_
         c.v = v;
         c.sigma = obj_weight;
         c.out0 = M.dev->hv;
+        c.out1 = Hv;
         launch_mode(M, M_HPROD, c, s);
         segsum(M.dev->h_map, M.dev->hv, Hv, s);
         M.counters[7]++;
@@ -1416,6 +1427,7 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
                 c.v = a->v;
                 c.sigma = a->obj_weight;
                 c.out0 = D.hv;
+                c.out1 = a->hv;
                 break;
             default: break;
         }

@@ -240,7 +240,7 @@ def test_rosenbrock_gradient_operation_count():
     assert sum(" * " in ln for ln in ops) == 6 and sum(" - " in ln for ln in ops) == 2
 
 
-def _chunk_plan_bytes(lengths, w=4):
+def _chunk_plan_bytes(lengths, w=4, skip=None):
     """Reduction bytes of one map by its plan, from the segment lengths
     alone (a second statement of the rule): segments of at most 8 entries
     everywhere -> one lane per segment (pointers + positions).  Otherwise
@@ -251,16 +251,19 @@ def _chunk_plan_bytes(lengths, w=4):
     records, a segment's lanes inside one 256-lane block, the end padded to
     whole blocks; the positions of long segments read besides)."""
     lengths = [int(n) for n in lengths]
-    nnz, nseg = sum(lengths), len(lengths)
+    skip = [False] * len(lengths) if skip is None else [bool(t) for t in skip]
+    nnz, nseg, nskip = sum(lengths), len(lengths), sum(skip)
     if max(lengths, default=0) <= 8:
-        return w * (nseg + 1) + w * nnz + 8 * nnz, 8 * nseg
+        return w * (nseg + 1) + w * nnz + 8 * nnz, 8 * (nseg - nskip)
     longs = [n for n in lengths if n > 1024]
     short = [n for n in lengths if n <= 1024]
     nlong, nparts, long_nnz = len(longs), sum(-(-n // 1024) for n in longs), sum(longs)
     chunked = not (max(short, default=0) <= 16 and nnz - long_nnz >= 1 << 22)
     if chunked:
         lanes = 0
-        for n in short:
+        for n, t in zip(lengths, skip):
+            if n > 1024 or t:
+                continue
             nl = max(1, -(-n // 4))
             if lanes % 256 + nl > 256:
                 lanes = (lanes // 256 + 1) * 256
@@ -269,7 +272,7 @@ def _chunk_plan_bytes(lengths, w=4):
         maps = 24 * lanes + 4 * long_nnz
     else:
         maps = w * (nseg + 1) + w * nnz
-    return maps + 40 * nlong + 16 * nparts + 8 * nnz, 8 * nseg + 8 * nparts
+    return maps + 40 * nlong + 16 * nparts + 8 * nnz, 8 * (nseg - nskip) + 8 * nparts
 
 
 @pytest.mark.parametrize("sizes", [[700, 400, 3, 0, 90], [1500, 2], [5000, 1025, 700, 3, 0, 2100]],
@@ -303,6 +306,55 @@ def _jt_entry_lengths(model):
         for key in keys:
             np.add.at(lengths, o._index(P, key, ks), 1)
     return lengths
+
+
+def _hv_entries(model):
+    """H v entries per variable and the references stored straight into the
+    output: the patterns over one data set add their contributions to one
+    variable reference in the lane (a reference counts when it sits in some
+    Hessian slot of the pattern), so a data point gives one entry per such
+    reference; a reference all of whose points' variables get no other entry
+    is stored by the kernel (a second statement of the layout, from the
+    model description and the oracle's slot keys)."""
+    o = OracleModel(model)
+    refs = {}
+    for P, p in zip(o.pats, model.patterns):
+        if P.ndata > 0:
+            curved = {P.vslots[a] for ab in P.hslots for a in ab}
+            refs.setdefault(id(p.data), (P, set()))[1].update(curved)
+    per_ref = []
+    for P, keys in refs.values():
+        assert len(keys) <= 32
+        ks = np.arange(P.ndata)
+        per_ref += [o._index(P, key, ks) for key in keys]
+    lengths = np.zeros(model.nvar, dtype=np.int64)
+    for idx in per_ref:
+        np.add.at(lengths, idx, 1)
+    skip = np.zeros(model.nvar, dtype=bool)
+    for idx in per_ref:
+        if np.all(lengths[idx] == 1):
+            skip[idx] = True
+    lengths[skip] = 0
+    return lengths, skip
+
+
+@pytest.mark.parametrize("nb", [30, 1200])
+def test_hv_references_stored_by_the_kernel(nb):
+    """ACOPF: the branch flow variables p and q each get one H v entry (from
+    the line limit of their branch end) and the generator powers one (the
+    objective), so those references go straight to the output; the bus
+    voltages sum over their branches in the reduction, which skips the
+    others (no buffer entry, no write)."""
+    from paper_2608_16265_amd import ExaModel
+    w = acopf(nb, 1)
+    em = ExaModel(w.model, host_only=True)
+    lengths, skip = _hv_entries(w.model)
+    off, nl, ng = w.meta["offsets"], w.meta["nl"], w.meta["ng"]
+    assert skip[off["p"]:off["p"] + 2 * nl].all() and skip[off["q"]:off["q"] + 2 * nl].all()
+    assert skip[off["pg"]:off["pg"] + ng].all() and not skip[off["va"]:off["va"] + nb].any()
+    rd, wr = _chunk_plan_bytes(lengths, skip=skip)
+    b = em.eval_bytes(("hprod",))
+    assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
 
 
 def test_reduction_bytes_large_map_with_one_shared_variable():

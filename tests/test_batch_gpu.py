@@ -240,6 +240,41 @@ def test_batch_rejects_bad_calls():
         b.evaluate(X, Y, 1.0, jac=torch.zeros(3, dtype=torch.float64, device="cuda:0"))
 
 
+def test_instances_that_disagree_on_hv_references_stored_by_the_kernel():
+    """A data set whose reference z[i] is its variables' only H v entry in
+    some instances (i a permutation) and not in others (i with repeats):
+    each instance's bit picks the kernel's own store or the reduction, in
+    one launch, and every output equals the instance's own callbacks bit
+    for bit."""
+    _gpu()
+    from exa_modeling import DataSet, Model, exp, sin
+    from exa_modeling.generators import Workload
+    from paper_2608_16265_amd import ExaModel
+    from paper_2608_16265_amd.batch import ExaBatch
+
+    def inst(n, repeats, seed):
+        rng = np.random.default_rng(seed)
+        m = Model("hvd")
+        x = m.add_var(n + 1)
+        z = m.add_var(n)
+        i = rng.integers(0, n, n) if repeats else rng.permutation(n)
+        d = DataSet(n, i=i, j=np.arange(n), c=rng.uniform(0.5, 2.0, n))
+        m.add_obj(d.c * z[d.i] ** 2 + x[d.j] * x[d.j + 1], d)
+        m.add_con(exp(x[d.j]) * sin(z[d.i]), d)
+        return Workload(m, rng.uniform(-1, 1, 2 * n + 1), rng.standard_normal(n), 1.0)
+    wls = [inst(300, False, 1), inst(200, True, 2), inst(500, False, 3)]
+    ems = [ExaModel(w.model) for w in wls]
+    b = ExaBatch(ems, autotune=False, units="per_callback")
+    X, Y, V, W, WX = _inputs(b, wls)
+    outs = {k: _nan(b, kind) for k, kind in ALL8.items()}
+    b.evaluate(X, Y, 1.0, V, W, **outs)
+    _check_against_plain(b, ems, X, Y, V, W, WX, 1.0, outs, tag="hvd")
+    # and each instance's own callbacks (H v among them) against the oracle
+    from test_parity_gpu import check_all
+    for i, (w, em) in enumerate(zip(wls, ems)):
+        check_all(w, em, tag=f"hvd{i} ")
+
+
 def test_instances_that_disagree_on_identity_columns():
     """An index column that is 0, 1, ..., n-1 in some instances and permuted
     in others: the batch runs code of its own that loads the column, and
