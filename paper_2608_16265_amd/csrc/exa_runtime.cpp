@@ -546,12 +546,47 @@ ChunkPlan chunk_plan(const SegMap& S) {
     return P;
 }
 
+// Launch order of tile lists (each list one unit's tiles over its points in
+// order; a launch's workgroups go to the 8 XCDs in contiguous eighths): XCD
+// j takes the j-th eighth of every unit's points, in rounds that each take
+// the same fraction of every unit.  Units over related data (a grid's points
+// and its interior points, the patterns of a model and its J^T w tiles) then
+// read the same x lines from one L2 at about the same time, instead of each
+// XCD fetching them for the units it happens to hold.  A round holds at
+// least 32 tiles (one per CU of the XCD) of the largest unit, at most 16
+// rounds per XCD: with fewer tiles per round, consecutive rounds would put
+// a unit's tiles on the same few CUs, and a launch whose tiles all fit on
+// the chip at once would wait on those CUs.  Results do not depend on the
+// order (every output has one writer; objective tiles keep their slots).
+std::vector<ExaTile> interleave_units(const std::vector<std::vector<ExaTile>>& units) {
+    size_t most = 0;
+    for (const auto& u : units) most = std::max(most, u.size());
+    const int kRounds = 8 * (int)std::min<size_t>(16, std::max<size_t>(1, most / (8 * 32)));
+    std::vector<ExaTile> all;
+    for (int r = 0; r < kRounds; ++r)
+        for (const auto& u : units)
+            all.insert(all.end(), u.begin() + u.size() * r / kRounds, u.begin() + u.size() * (r + 1) / kRounds);
+    return all;
+}
+
+// A tile list split at changes of unit (make_tiles lists each unit's tiles
+// together).
+void split_units(const std::vector<ExaTile>& t, std::vector<std::vector<ExaTile>>& out) {
+    for (size_t i = 0; i < t.size(); ++i) {
+        if (i == 0 || t[i].pat != t[i - 1].pat) out.emplace_back();
+        out.back().push_back(t[i]);
+    }
+}
+
 void set_schedule(Model& M, int mode, int block, int epl, bool fused) {
     DeviceState& D = *M.dev;
     DeviceState::Sched& S = D.sched[mode];
     const int64_t tp = (int64_t)block * epl;
-    auto tiles = make_tiles(M, mode, 0, tp, fused);
-    if (mode == M_GRAD) add_zero_tiles(M, tp, tiles);
+    auto made = make_tiles(M, mode, 0, tp, fused);
+    if (mode == M_GRAD) add_zero_tiles(M, tp, made);
+    std::vector<std::vector<ExaTile>> units;
+    split_units(made, units);
+    const std::vector<ExaTile> tiles = interleave_units(units);
     D.release(S.tiles);
     S.tiles = (ExaTile*)D.upload(tiles.data(), tiles.size() * sizeof(ExaTile));
     S.ntiles = (int64_t)tiles.size();
@@ -742,11 +777,9 @@ void set_multi_schedule(Model& M, uint32_t mask, int block, int epl, bool fused,
             for (ExaTile& x : z) x.pat |= M_GRAD << EXA_MODE_SHIFT;
             t.insert(t.end(), z.begin(), z.end());
         }
-        per.push_back(std::move(t));
+        split_units(t, per);
     }
-    std::vector<ExaTile> all;
-    for (int j = 0; j < 8; ++j)
-        for (const auto& t : per) all.insert(all.end(), t.begin() + t.size() * j / 8, t.begin() + t.size() * (j + 1) / 8);
+    const std::vector<ExaTile> all = interleave_units(per);
     D.release(S.tiles);
     S.tiles = all.empty() ? nullptr : (ExaTile*)D.upload(all.data(), all.size() * sizeof(ExaTile));
     S.ntiles = (int64_t)all.size();
