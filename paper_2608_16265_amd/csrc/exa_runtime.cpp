@@ -408,8 +408,16 @@ void add_zero_tiles(const Model& M, int64_t tp, std::vector<ExaTile>& tiles) {
 }
 
 // maps go to the device as int32 whenever every position fits
+// Segments the reduction visits: skipped segments at the end of a map need
+// no lane (those of the ACOPF H v map are most of its variables).
+int64_t visited_segments(const SegMap& S) {
+    int64_t n = S.nseg();
+    while (n > 0 && !S.skip.empty() && S.skip[n - 1]) --n;
+    return n;
+}
+
 void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
-    d.nseg = S.nseg();
+    d.nseg = visited_segments(S);
     int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
     top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
     d.wide = top >= INT32_MAX ? 1 : 0;
@@ -972,7 +980,7 @@ void kernel_bytes(const Model& M, const std::vector<int>& modes, bool fused, int
 void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
     rr = rw = 0;
     auto seg = [&](const SegMap& S) {
-        const int64_t nseg = S.nseg(), nnz = (int64_t)S.idx.size();
+        const int64_t nseg = visited_segments(S), nnz = (int64_t)S.idx.size();
         const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
         const int64_t w = top >= INT32_MAX ? 8 : 4;
         const ChunkPlan P = chunk_plan(S);
@@ -987,7 +995,7 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
         rr += (P.chunked ? 24 * P.nlanes() + 4 * long_nnz : w * (nseg + 1) + w * nnz) + 40 * P.nlong() +
               16 * P.nparts() + 8 * nnz;
         // segments written by the evaluation kernel are not written here
-        const int64_t nskip = (int64_t)std::count(S.skip.begin(), S.skip.end(), 1);
+        const int64_t nskip = (int64_t)std::count(S.skip.begin(), S.skip.begin() + (S.skip.empty() ? 0 : nseg), 1);
         rw += 8 * (nseg - nskip) + 8 * P.nparts();
     };
     if ((mask & (EXA_EV_GRAD | EXA_EV_LAG)) && !M.grad_direct) seg(M.grad_map);

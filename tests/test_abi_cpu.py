@@ -252,6 +252,10 @@ def _chunk_plan_bytes(lengths, w=4, skip=None):
     whole blocks; the positions of long segments read besides)."""
     lengths = [int(n) for n in lengths]
     skip = [False] * len(lengths) if skip is None else [bool(t) for t in skip]
+    # skipped segments at the end of the map get no lane at all
+    while skip and skip[-1]:
+        skip.pop()
+        assert lengths.pop() == 0
     nnz, nseg, nskip = sum(lengths), len(lengths), sum(skip)
     if max(lengths, default=0) <= 8:
         return w * (nseg + 1) + w * nnz + 8 * nnz, 8 * (nseg - nskip)
