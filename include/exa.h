@@ -259,7 +259,10 @@ exa_status exa_jprod(exa_model* m, const double* x, const double* v, double* Jv,
  * patterns declared over the same data arrays add their contributions
  * (Jacobian entry times w of its row, members in declaration order) to one
  * variable reference in the lane; the reduction then sums these per
- * variable in a fixed order (Sec. 7.2.3). */
+ * variable in a fixed order (Sec. 7.2.3).  An augmentation term that is
+ * plus or minus one variable, and its data set's only contribution to that
+ * reference, contributes plus or minus w of its row: the reduction reads
+ * that weight from w itself, at the same place in the order. */
 exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jtw,
                       exa_stream_t stream);
 /* (sigma grad^2 f + sum y_j grad^2 g_j) v into Hv [nvar] (Sec. 2.1.3 hprod).

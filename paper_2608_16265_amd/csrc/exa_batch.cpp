@@ -315,7 +315,8 @@ double* need_buf(exa_batch& b, int k) {
     return b.buf[k];
 }
 
-ExaBatchJob seg_batch_job(const DevMap& m, int bufk, int64_t buf_off, int out, int64_t out_off, bool ep) {
+ExaBatchJob seg_batch_job(const DevMap& m, int bufk, int64_t buf_off, int out, int64_t out_off, bool ep,
+                          int64_t w_off = 0) {
     ExaBatchJob J;
     std::memset(&J, 0, sizeof J);
     J.ptr = m.ptr;
@@ -335,6 +336,7 @@ ExaBatchJob seg_batch_job(const DevMap& m, int bufk, int64_t buf_off, int out, i
     J.buf_off = buf_off;
     J.out = out;
     J.out_off = out_off;
+    J.w_off = w_off;
     J.ep = ep ? 1 : 0;
     return J;
 }
@@ -360,7 +362,7 @@ void build_reductions(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
     for (int j = 0; j < 8; ++j)
         for (int i : S.bins[j]) {
             const exa_batch::Maps& mp = b.maps[i];
-            const int64_t xo = b.offsets[kNoff * i + kOffX];
+            const int64_t xo = b.offsets[kNoff * i + kOffX], yo = b.offsets[kNoff * i + kOffY];
             const int64_t fo = b.base[kBufFo].empty() ? 0 : b.base[kBufFo][i];
             std::vector<ExaBatchJob> mine;
             if ((mask & EXA_EV_GRAD) && !b.grad_direct_all) mine.push_back(seg_batch_job(mp.grad, kBufFo, fo, kOutG, xo, false));
@@ -368,14 +370,14 @@ void build_reductions(exa_batch& b, exa_batch::Sched& S, uint32_t mask) {
                 if (b.grad_direct_all) {
                     // g was written in place by the evaluation launch: the
                     // J^T y sums finish it as g = sigma g + J^T y
-                    mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutLag, xo, true));
+                    mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutLag, xo, true, yo));
                 } else {
                     mine.push_back(seg_batch_job(mp.grad, kBufFo, fo, kOutLag, xo, false));
-                    mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutLagTmp, xo, false));
+                    mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutLagTmp, xo, false, yo));
                     S.axpy = true;
                 }
             }
-            if (mask & EXA_EV_JTPROD) mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false));
+            if (mask & EXA_EV_JTPROD) mine.push_back(seg_batch_job(mp.jt, kBufFo, fo, kOutJtw, xo, false, yo));
             if (mask & EXA_EV_HPROD) mine.push_back(seg_batch_job(mp.h, kBufHv, b.base[kBufHv][i], kOutHv, xo, false));
             if (mask & EXA_EV_ADJ)
                 mine.push_back(seg_batch_job(mp.par, kBufPar, b.base[kBufPar][i], kOutThetaBar,
@@ -546,6 +548,8 @@ bool launch_reduce(exa_batch& b, uint32_t mask, const exa_batch_io& io, hipStrea
     R.outs[kOutLag] = io.lag;
     R.outs[kOutLagTmp] = b.lag_tmp;
     R.outs[kOutThetaBar] = io.theta_bar;
+    // the weights of J^T w (J^T y for the Lagrangian gradient)
+    R.w = (mask & EXA_EV_LAG) ? io.y : io.w;
     R.alpha = io.obj_weight;
     hip_check(exa_launch_reduce_batch(R, s), "batched reductions");
     if (S.axpy) {

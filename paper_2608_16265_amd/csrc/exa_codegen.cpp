@@ -1093,7 +1093,7 @@ bool pattern_in_mode(const Pattern& P, int mode) {
         case M_JAC: return P.kind != EXA_OBJ && P.o1step() > 0;
         case M_HESS: return P.o2step() > 0;
         case M_JPROD: return P.kind == EXA_CON;
-        case M_JTPROD: return P.kind != EXA_OBJ && P.o1step() > 0;
+        case M_JTPROD: return P.kind != EXA_OBJ && P.o1step() > 0 && !P.wread;
         case M_HPROD: return P.o2step() > 0;
         case M_ADJ: return P.pstep() > 0 && P.o1step() > 0;
         case M_JH: return pattern_in_mode(P, M_JAC) || pattern_in_mode(P, M_HESS);

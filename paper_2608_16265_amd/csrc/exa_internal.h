@@ -190,6 +190,10 @@ struct Pattern {
     std::vector<int> augs;
     // var slots that occur in some Hessian pair (the only ones H v reaches)
     std::vector<int> hvs;
+    // AUG whose expression is plus or minus one variable, the only J^T w
+    // contribution of its data set to that reference: its contribution is
+    // +-w[row], which the reduction reads from w itself (no J^T w job)
+    int wread = 0;  // +1, -1, or 0
     int64_t oh = 0;   // first entry of this pattern in the H v buffer
 
     // work buffers (first-order, H v, parameter) hold each pattern's block

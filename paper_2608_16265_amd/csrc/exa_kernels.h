@@ -22,6 +22,9 @@ hipError_t exa_launch_copy(const void* src, void* dst, int64_t bytes, hipStream_
 //   covers the same range of points for every long segment;
 // * the other segments, unless chunked is set: one lane per segment, entries
 //   in ascending j;
+// A position below zero is a weight entry ~(2 row + neg): the value is
+// w[row], negated when neg is set (an augmentation term that is plus or
+// minus one variable adds plus or minus its row's weight to J^T w).
 // * with chunked set (int32 maps only): lane l adds one chunk of at most
 //   kExaChunk consecutive entries, with lanes[2l] = segment (-1 for
 //   padding), lanes[2l+1] = count | (number of chunks of the segment << 4)
@@ -36,6 +39,7 @@ struct ExaSegJob {
     const void* ptr;
     const void* idx;
     const double* buf;
+    const double* w;  // weights of the weight entries (maps without any: unused)
     double* out;
     int64_t nseg;
     const int32_t* lanes;
@@ -93,6 +97,7 @@ struct ExaBatchJob {
     double* lsum;
     int64_t nseg, nlanes, nparts, nlong;
     int64_t buf_off, out_off;
+    int64_t w_off;  // the instance's first row in the call's weights
     int32_t wide, chunked;
     int32_t buf, out;
     int32_t kind;  // 0: segment sums; 1: objective partials (nseg of them) into one value
@@ -111,6 +116,7 @@ struct ExaBatchReduce {
     int64_t nlblocks;
     const double* bufs[kExaBatchBufs];
     double* outs[kExaBatchOuts];
+    const double* w;  // weights of the J^T w (or J^T y) weight entries
     double alpha;
 };
 hipError_t exa_launch_reduce_batch(const ExaBatchReduce& r, hipStream_t s);

@@ -31,6 +31,16 @@ __device__ __forceinline__ void put(double* __restrict__ out, int64_t s, double 
     }
 }
 
+// Value of map position i: buf[i], or for a weight entry i = ~(2 row + neg)
+// the weight w[row], negated when neg is set.
+template <class I>
+__device__ __forceinline__ double entry(const double* __restrict__ buf, const double* __restrict__ w, I i) {
+    if (i >= 0) return buf[i];
+    const I e = ~i;
+    const double v = w[e >> 1];
+    return (e & 1) ? -v : v;
+}
+
 // out[s] = sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
 // the sparse-to-dense compression of Sec. 7.2.3, one lane per segment, with
 // a fixed summation order so the result does not depend on scheduling.  A
@@ -38,8 +48,8 @@ __device__ __forceinline__ void put(double* __restrict__ out, int64_t s, double 
 // writes itself: it is left alone.
 template <class I>
 __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __restrict__ idx,
-                                         const double* __restrict__ buf, double* __restrict__ out, int64_t s,
-                                         bool parts, bool ep, double alpha) {
+                                         const double* __restrict__ buf, const double* __restrict__ w,
+                                         double* __restrict__ out, int64_t s, bool parts, bool ep, double alpha) {
     const I pb = ptr[s], pe = ptr[s + 1];
     if (pe < 0) return;
     const int64_t b = pb < 0 ? ~pb : pb, e = pe;
@@ -50,13 +60,13 @@ __device__ __forceinline__ void seg_body(const I* __restrict__ ptr, const I* __r
     // together, the additions stay in ascending order
     for (; j + 4 <= e; j += 4) {
         const I i0 = idx[j], i1 = idx[j + 1], i2 = idx[j + 2], i3 = idx[j + 3];
-        const double v0 = buf[i0], v1 = buf[i1], v2 = buf[i2], v3 = buf[i3];
+        const double v0 = entry(buf, w, i0), v1 = entry(buf, w, i1), v2 = entry(buf, w, i2), v3 = entry(buf, w, i3);
         acc += v0;
         acc += v1;
         acc += v2;
         acc += v3;
     }
-    for (; j < e; ++j) acc += buf[idx[j]];
+    for (; j < e; ++j) acc += entry(buf, w, idx[j]);
     put(out, s, acc, ep, alpha);
 }
 
@@ -72,7 +82,8 @@ __device__ __forceinline__ void chunk_body(const ExaSegJob& J, int64_t l, double
     const double* __restrict__ buf = J.buf;
     const int2 m = ((const int2*)J.lanes)[l];
     const int4 ix = ((const int4*)J.lidx)[l];
-    const double v0 = buf[ix.x], v1 = buf[ix.y], v2 = buf[ix.z], v3 = buf[ix.w];
+    const double* __restrict__ w = J.w;
+    const double v0 = entry(buf, w, ix.x), v1 = entry(buf, w, ix.y), v2 = entry(buf, w, ix.z), v3 = entry(buf, w, ix.w);
     const int seg = m.x, cnt = m.y & 15, nl = m.y >> 4;
     double part = 0.0;
     if (cnt > 0) part += v0;
@@ -124,7 +135,7 @@ __device__ __forceinline__ void long_part_body(const ExaSegJob& J, int64_t r, do
         for (int u = 0; u < kExaChunk; ++u) ix[u] = idx[j0 + (u < cnt ? u : cnt - 1)];
         double v[kExaChunk];
 #pragma unroll
-        for (int u = 0; u < kExaChunk; ++u) v[u] = buf[ix[u]];
+        for (int u = 0; u < kExaChunk; ++u) v[u] = entry(buf, J.w, ix[u]);
 #pragma unroll
         for (int u = 0; u < kExaChunk; ++u)
             if (u < cnt) part += v[u];
@@ -189,9 +200,10 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce(ExaReduce R, int64_t per_x
     const int64_t s = b * kSegBlock + threadIdx.x;
     if (s < J.nseg) {
         if (J.wide)
-            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false, ep, R.ax_alpha);
+            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.w, J.out, s, false, ep, R.ax_alpha);
         else
-            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0, ep, R.ax_alpha);
+            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.w, J.out, s, J.nparts > 0, ep,
+                     R.ax_alpha);
     }
 }
 
@@ -232,6 +244,7 @@ __device__ __forceinline__ ExaSegJob batch_seg(const ExaBatchReduce& R, const Ex
     J.ptr = B.ptr;
     J.idx = B.idx;
     J.buf = R.bufs[B.buf] + B.buf_off;
+    J.w = R.w ? R.w + B.w_off : nullptr;
     J.out = R.outs[B.out] + B.out_off;
     J.nseg = B.nseg;
     J.lanes = B.lanes;
@@ -288,9 +301,9 @@ __global__ void __launch_bounds__(kSegBlock) k_reduce_batch(ExaBatchReduce R) {
     const int64_t s = b * kSegBlock + threadIdx.x;
     if (s < J.nseg) {
         if (J.wide)
-            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.out, s, false, ep, R.alpha);
+            seg_body((const int64_t*)J.ptr, (const int64_t*)J.idx, J.buf, J.w, J.out, s, false, ep, R.alpha);
         else
-            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.out, s, J.nparts > 0, ep, R.alpha);
+            seg_body((const int32_t*)J.ptr, (const int32_t*)J.idx, J.buf, J.w, J.out, s, J.nparts > 0, ep, R.alpha);
     }
 }
 

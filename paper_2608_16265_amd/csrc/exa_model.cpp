@@ -396,11 +396,30 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     // order), so a group writes one slot per reference instead of one per
     // member and slot
     for (Group& G : M.groups) {
+        // an augmentation term that is +-(one variable) and the only J^T w
+        // contribution of the group to that reference adds +-w[row] to it:
+        // the reduction reads that weight itself
+        std::map<int, int> users;  // reference -> members that contribute J^T w to it
+        for (int p : G.members) {
+            const Pattern& P = M.pats[p];
+            if (P.ndata > 0 && P.kind != EXA_OBJ)
+                for (int s = 0; s < P.o1step(); ++s) users[P.vg[s]]++;
+        }
+        for (int p : G.members) {
+            Pattern& P = M.pats[p];
+            P.wread = 0;
+            if (P.kind != EXA_AUG || P.ndata == 0 || P.o1step() != 1 || P.pstep() != 0 || users[P.vg[0]] != 1) continue;
+            const std::vector<TNode>& n = P.nodes;
+            if (n.size() == 1 && n[0].op == EXA_OP_VAR)
+                P.wread = 1;
+            else if (n.size() == 2 && n[0].op == EXA_OP_VAR && n[1].op == EXA_OP_NEG && n[1].a == 0)
+                P.wread = -1;
+        }
         std::set<int> jr, hr;
         for (int p : G.members) {
             const Pattern& P = M.pats[p];
             if (P.ndata == 0) continue;
-            if (P.kind != EXA_OBJ)
+            if (P.kind != EXA_OBJ && !P.wread)
                 for (int s = 0; s < P.o1step(); ++s) jr.insert(P.vg[s]);
             for (int s : P.hvs) hr.insert(P.vg[s]);
         }
@@ -418,6 +437,8 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             P.oh = G.oh;
         }
     }
+    // chunked sums' padding lanes read position 0 of the first-order buffer
+    if (M.fo_obj_len + M.fo_con_len == 0) M.fo_con_len = 16;
     M.ncon = ncon;
     M.nnzj = nnzj;
     M.nnzh = nnzh;
@@ -501,11 +522,27 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
     std::vector<char> hskip(M.nvar, 0);
     for (const Group& G : M.groups) {
         const int64_t bs = (G.ndata + 15) & ~(int64_t)15;
+        // weight entries (Pattern::wread) by reference: ~(2 row + negated)
+        std::map<int, int> wr;
+        for (int p : G.members)
+            if (M.pats[p].wread) wr[M.pats[p].vg[0]] = p;
+        std::vector<int> jall(G.jt_refs.begin(), G.jt_refs.end());
+        for (auto& x : wr) jall.push_back(x.first);
+        std::sort(jall.begin(), jall.end());
         // a variable sums its group entries in (group, data point, reference)
         // order
         for (int64_t k = 0; k < G.ndata; ++k) {
-            for (size_t j = 0; j < G.jt_refs.size(); ++j)
-                jt.emplace_back(gvar(G, G.jt_refs[j], k), M.fo_obj_len + G.ob + (int64_t)j * bs + k);
+            for (int r : jall) {
+                const auto w = wr.find(r);
+                if (w != wr.end()) {
+                    const Pattern& A = M.pats[w->second];
+                    const int64_t row = A.tgt0 + (int64_t)A.icols[A.row_icol][k] + A.row_off;
+                    jt.emplace_back(gvar(G, r, k), ~(2 * row + (A.wread < 0 ? 1 : 0)));
+                    continue;
+                }
+                const int64_t j = std::find(G.jt_refs.begin(), G.jt_refs.end(), r) - G.jt_refs.begin();
+                jt.emplace_back(gvar(G, r, k), M.fo_obj_len + G.ob + j * bs + k);
+            }
             for (size_t j = 0; j < G.hv_refs.size(); ++j) {
                 const int64_t v = gvar(G, G.hv_refs[j], k);
                 if (G.hv_direct[j])
@@ -533,7 +570,15 @@ void build_host(Model& M, const exa_pattern_desc* pats, int32_t npats) {
             if (x.second < 0 || x.second >= len) fail(EXA_EINVAL, std::string("internal: work-buffer position outside the ") + what);
     };
     inside(g, M.fo_obj_len, "objective part of the first-order buffer");
-    inside(jt, M.fo_obj_len + M.fo_con_len, "first-order buffer");
+    for (auto& x : jt)  // weight entries name a constraint row
+        if (x.second < 0 && (~x.second >> 1) >= M.ncon)
+            fail(EXA_EINVAL, "internal: a J^T w weight entry outside the constraint rows");
+    {
+        std::vector<std::pair<int64_t, int64_t>> jb;
+        for (auto& x : jt)
+            if (x.second >= 0) jb.push_back(x);
+        inside(jb, M.fo_obj_len + M.fo_con_len, "first-order buffer");
+    }
     inside(h, M.hv_len, "H v buffer");
     inside(pr, M.par_len, "parameter buffer");
     for (auto& P : M.pats) {

@@ -419,8 +419,9 @@ int64_t visited_segments(const SegMap& S) {
 void upload_map(DeviceState& D, const SegMap& S, DevMap& d) {
     d.nseg = visited_segments(S);
     int64_t top = S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end());
+    const int64_t low = S.idx.empty() ? 0 : *std::min_element(S.idx.begin(), S.idx.end());
     top = std::max<int64_t>(top, S.ptr.empty() ? 0 : S.ptr.back());
-    d.wide = top >= INT32_MAX ? 1 : 0;
+    d.wide = top >= INT32_MAX || low < INT32_MIN ? 1 : 0;
     // a segment the reduction skips has its end stored complemented (a
     // negative value; see seg_body)
     std::vector<int64_t> ptr = S.ptr;
@@ -498,10 +499,10 @@ Model::Csc& csc_form(Model& M, int which) {
 
 ChunkPlan chunk_plan(const SegMap& S) {
     ChunkPlan P;
-    int64_t longest = 0, top = S.ptr.empty() ? 0 : S.ptr.back();
+    int64_t longest = 0, top = S.ptr.empty() ? 0 : S.ptr.back(), low = 0;
     for (int64_t s = 0; s < S.nseg(); ++s) longest = std::max(longest, S.ptr[s + 1] - S.ptr[s]);
-    for (int64_t i : S.idx) top = std::max(top, i);
-    if (longest <= 2 * kExaChunk || top >= INT32_MAX) return P;
+    for (int64_t i : S.idx) top = std::max(top, i), low = std::min(low, i);
+    if (longest <= 2 * kExaChunk || top >= INT32_MAX || low < INT32_MIN) return P;
     int64_t longest_short = 0, long_nnz = 0;
     for (int64_t s = 0; s < S.nseg(); ++s) {
         const int64_t len = S.ptr[s + 1] - S.ptr[s];
@@ -982,7 +983,8 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
     auto seg = [&](const SegMap& S) {
         const int64_t nseg = visited_segments(S), nnz = (int64_t)S.idx.size();
         const int64_t top = std::max<int64_t>(nnz, S.idx.empty() ? 0 : *std::max_element(S.idx.begin(), S.idx.end()));
-        const int64_t w = top >= INT32_MAX ? 8 : 4;
+        const int64_t low = S.idx.empty() ? 0 : *std::min_element(S.idx.begin(), S.idx.end());
+        const int64_t w = top >= INT32_MAX || low < INT32_MIN ? 8 : 4;
         const ChunkPlan P = chunk_plan(S);
         // chunked maps read a 24-byte record per lane (segment, count,
         // four positions) instead of segment pointers and positions, and
@@ -1011,7 +1013,7 @@ void reduce_bytes(const Model& M, uint32_t mask, int64_t& rr, int64_t& rw) {
     }
 }
 
-ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
+ExaSegJob seg_job(const DevMap& m, const double* buf, double* out, const double* w) {
     ExaSegJob J;
     std::memset(&J, 0, sizeof J);
     J.ptr = m.ptr;
@@ -1028,15 +1030,16 @@ ExaSegJob seg_job(const DevMap& m, const double* buf, double* out) {
     J.nlong = m.nlong;
     J.lsum = m.lsum;
     J.buf = buf;
+    J.w = w;
     J.out = out;
     return J;
 }
 
-void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s) {
+void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s, const double* w) {
     ExaReduce R;
     std::memset(&R, 0, sizeof R);
     R.ep_job = -1;
-    R.job[0] = seg_job(m, buf, out);
+    R.job[0] = seg_job(m, buf, out, w);
     R.njobs = 1;
     hip_check(exa_launch_reduce(R, s), "segmented reduction");
 }
@@ -1377,7 +1380,7 @@ exa_status exa_jtprod(exa_model* m, const double* x, const double* w, double* Jt
         c.y = w;
         c.out0 = M.dev->fo;
         launch_mode(M, M_JTPROD, c, s);
-        segsum(M.dev->jt_map, M.dev->fo, Jtw, s);
+        segsum(M.dev->jt_map, M.dev->fo, Jtw, s, w);
         M.counters[6]++;
     });
 }
@@ -1491,7 +1494,9 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
         ExaReduce R;
         std::memset(&R, 0, sizeof R);
         R.ep_job = -1;
-        auto job = [&](const DevMap& dm, const double* buf, double* out) { R.job[R.njobs++] = seg_job(dm, buf, out); };
+        auto job = [&](const DevMap& dm, const double* buf, double* out, const double* w = nullptr) {
+            R.job[R.njobs++] = seg_job(dm, buf, out, w);
+        };
         if ((mask & EXA_EV_GRAD) && !M.grad_direct) job(D.grad_map, D.fo, a->g);
         // the Lagrangian gradient with g written in place by the evaluation
         // launch: J^T y goes straight into g as g = sigma * g + J^T y
@@ -1499,9 +1504,9 @@ void eval_body(Model& M, const exa_eval_args* a, hipStream_t s, bool lag = false
         if (lag_ep) {
             R.ep_job = R.njobs;
             R.ax_alpha = lag_sigma;
-            job(D.jt_map, D.fo, a->g);
+            job(D.jt_map, D.fo, a->g, a->w);
         } else if (mask & EXA_EV_JTPROD) {
-            job(D.jt_map, D.fo, a->jtw);
+            job(D.jt_map, D.fo, a->jtw, a->w);
         }
         if (mask & EXA_EV_HPROD) job(D.h_map, D.hv, a->hv);
         if ((mask & EXA_EV_OBJ) && nobj != 1) {  // no tiles: the sum of nothing, 0

@@ -102,7 +102,7 @@ Model& live_model(exa_model* m);
 void launch_mode_untuned(Model& M, int mode, ExaCall call, hipStream_t s);
 // The segment sums of a map from `buf` into `out` (one reduction launch,
 // plus one for long segments).
-void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s);
+void segsum(const DevMap& m, const double* buf, double* out, hipStream_t s, const double* w = nullptr);
 exa_status guard_status(const std::function<void()>& f);
 // Tiles that write zeros to the gradient entries no objective term touches,
 // kZeroTileEntries entries each (more when a tile of points is larger).

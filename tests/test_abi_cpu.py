@@ -361,6 +361,30 @@ def test_hv_references_stored_by_the_kernel(nb):
     assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
 
 
+def test_augmentation_terms_that_are_one_variable_read_their_weight():
+    """J^T w of an augmentation term that is plus or minus one variable (and
+    the only contribution of its data set to that reference) is +-w of its
+    row: no J^T w job, the reduction reads w.  ACOPF: the arcs' flows and
+    the generators' powers, so only the branches keep a J^T w unit; the map
+    keeps one entry per (data set, point, reference) all the same."""
+    from paper_2608_16265_amd import ExaModel
+    from test_parity_gpu import aug_weight_case
+    w = acopf(1200, 1)
+    em = ExaModel(w.model, host_only=True)
+    units = re.findall(r"void unit_jtprod_(\d+)\(", em.generated_source())
+    assert len(units) == 1
+    rd, wr = _chunk_plan_bytes(_jt_entry_lengths(w.model))
+    b = em.eval_bytes(("jtprod",))
+    assert (b["reduce_read"], b["reduce_write"]) == (rd, wr)
+    # the case: x[d.j] and -x[n] (patterns 1, 2; data set 1) read their
+    # weight; the base block x[r]^2 (pattern 0), 2 x[e.j] (pattern 3) and the
+    # data set of x[f.j] and sin(x[f.j]) (group 3, unit code 32 + 3) keep
+    # their J^T w units
+    w = aug_weight_case()
+    src = ExaModel(w.model, host_only=True).generated_source()
+    assert re.findall(r"void unit_jtprod_(\d+)\(", src) == ["0", "3", "35"]
+
+
 def test_reduction_bytes_large_map_with_one_shared_variable():
     """Goddard's step variable is shared by all 3T rows: on a large model its
     segment is summed in parts and every other variable one lane each."""

@@ -56,6 +56,31 @@ def single_point_case():
     return Workload(m, np.array([3.0, 5.0]), np.array([0.75]), 1.0)
 
 
+def aug_weight_case(seed=5):
+    """Augmentation terms that are plus or minus one variable add plus or
+    minus their row's weight to J^T w, which the reduction reads itself:
+    x[d.j] (rows spread over 10 targets) and -x[n] (one variable for all
+    1,500 points: a segment summed in parts).  A scaled term (2 x[e.j]) and
+    a term whose reference another pattern over the same data set shares
+    (x[f.j], with sin(x[f.j])) stay in the lane."""
+    rng = np.random.default_rng(seed)
+    m = Model("augw")
+    n = 40
+    x = m.add_var(n + 1)
+    r = DataSet(10, r=np.arange(10))
+    blk = m.add_con(x[r.r] ** 2, r)
+    K = 1500
+    d = DataSet(K, bus=rng.integers(0, 10, K), j=rng.integers(0, n, K))
+    m.add_con_aug(blk, d.bus, x[d.j], d)
+    m.add_con_aug(blk, d.bus, -x[n], d)
+    e = DataSet(30, bus=rng.integers(0, 10, 30), j=rng.integers(0, n, 30))
+    m.add_con_aug(blk, e.bus, 2.0 * x[e.j], e)
+    f = DataSet(20, bus=rng.integers(0, 10, 20), j=rng.integers(0, n, 20))
+    m.add_con_aug(blk, f.bus, x[f.j], f)
+    m.add_con(sin(x[f.j]), f)
+    return Workload(m, rng.uniform(-1, 1, n + 1), rng.standard_normal(m.ncon), 0.7)
+
+
 def star_case(sizes, seed):
     """Hub variables shared by many terms: long gradient, J^T w and H v
     segments (several hubs so that their chunks need block padding)."""
@@ -99,6 +124,7 @@ CASES = {
     "sweep16": lambda: kernel_sweep(16, 200, 2),  # sixteen distinct patterns
     "zoo": _zoo,
     "aug_offset": _augoff,       # augmentation rows = index column + nonzero offset
+    "aug_weights": aug_weight_case,  # J^T w of +-x augmentation terms read from w by the reduction
     "alias": aliasing_case,
     "empty": empty_pattern_case,
     "single": single_point_case,
