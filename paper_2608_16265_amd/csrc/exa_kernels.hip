@@ -32,13 +32,16 @@ __device__ __forceinline__ void put(double* __restrict__ out, int64_t s, double 
 }
 
 // Value of map position i: buf[i], or for a weight entry i = ~(2 row + neg)
-// the weight w[row], negated when neg is set.
+// the weight w[row], negated when neg is set.  One load either way (the
+// base and offset are selected), so lanes that mix both kinds issue one
+// load instruction, not two.
 template <class I>
 __device__ __forceinline__ double entry(const double* __restrict__ buf, const double* __restrict__ w, I i) {
-    if (i >= 0) return buf[i];
+    const bool wt = i < 0;
     const I e = ~i;
-    const double v = w[e >> 1];
-    return (e & 1) ? -v : v;
+    const double* base = wt ? w : buf;
+    const double v = base[wt ? (e >> 1) : i];
+    return wt && (e & 1) ? -v : v;
 }
 
 // out[s] = sum of buf[idx[j]] for j in [ptr[s], ptr[s+1]), in ascending j:
