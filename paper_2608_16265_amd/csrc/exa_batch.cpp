@@ -739,13 +739,21 @@ exa_status exa_batch_create(exa_model* const* models, int32_t B, const exa_batch
         for (int i = 1; i < B; ++i)
             for (size_t p = 0; p < ident.size(); ++p)
                 for (size_t c = 0; c < ident[p].size(); ++c) ident[p][c] &= models[i]->impl.pats[p].ident[c];
+        // H v references stored into the output: code for any instance that
+        // may (the others take the buffer path by their own bits)
+        std::vector<std::vector<char>> hvd;
+        for (const Group& G : M0.groups) hvd.push_back(G.hv_direct);
+        for (int i = 1; i < B; ++i)
+            for (size_t g = 0; g < hvd.size(); ++g)
+                for (size_t r = 0; r < hvd[g].size(); ++r) hvd[g][r] |= models[i]->impl.groups[g].hv_direct[r];
         bool same = true;
         for (size_t p = 0; p < ident.size(); ++p) same = same && ident[p] == M0.pats[p].ident;
+        for (size_t g = 0; g < hvd.size(); ++g) same = same && hvd[g] == M0.groups[g].hv_direct;
         if (same) {
             b->module = M0.dev->module;
         } else {
             bool hit = false;
-            b->module = compile_module(generate_source(M0, &b->live, &ident), M0.cache_dir, &hit);
+            b->module = compile_module(generate_source(M0, &b->live, &ident, &hvd), M0.cache_dir, &hit);
             b->own_code = true;
         }
 

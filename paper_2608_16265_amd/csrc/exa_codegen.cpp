@@ -684,6 +684,14 @@ bool ident(const Model& M, int p, int c) {
     return c < (int)f.size() && f[c] != 0;
 }
 
+// H v references whose code may store into the output: the groups' own
+// flags, or (for code shared by a batch) those of any instance.
+thread_local const std::vector<std::vector<char>>* g_hvd = nullptr;
+bool may_store_hv(const Model& M, int g, int at) {
+    const std::vector<char>& f = g_hvd ? (*g_hvd)[g] : M.groups[g].hv_direct;
+    return at < (int)f.size() && f[at] != 0;
+}
+
 // Value (cons) or tangent (jprod) of augmentation pattern a at one of its
 // data points, for the base row that pulls it; fills `live`.
 std::string aug_fn(const Model& M, int mode, int a, int& ntmp, UnitLive& live) {
@@ -915,7 +923,7 @@ std::string unit_tile(const Model& M, int mode, const Unit& U, int& ntmp, UnitLi
                 if (last_adder[{j.mode, at}] != p) continue;
                 const std::string buf = "(" + dest(P, j.mode, pd, j.out, false) + ")[" + std::to_string(at) + " * " +
                                         stride + " + kr] = " + g + ";";
-                if (j.mode == M_HPROD && at < 32)
+                if (j.mode == M_HPROD && at < 32 && may_store_hv(M, U.group, at))
                     // a reference whose entries are their variables' only H v
                     // contributions (this instance's bit) goes to the output
                     e.raw("if (kr < kend) { if ((" + pd + ".hvd >> " + std::to_string(at) + ") & 1) " +
@@ -1160,12 +1168,15 @@ const std::vector<int>& multi_modes(bool jh) {
 }
 
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live,
-                            const std::vector<std::vector<char>>* ident_flags) {
+                            const std::vector<std::vector<char>>* ident_flags,
+                            const std::vector<std::vector<char>>* hvd_flags) {
     struct Restore {
         const std::vector<std::vector<char>>* prev;
-        ~Restore() { g_ident = prev; }
-    } restore{g_ident};
+        const std::vector<std::vector<char>>** where;
+        ~Restore() { *where = prev; }
+    } restore_ident{g_ident, &g_ident}, restore_hvd{g_hvd, &g_hvd};
     g_ident = ident_flags;
+    g_hvd = hvd_flags;
     std::ostringstream os;
     os << "// generated: straight-line evaluation kernels for one pattern set\n";
     os << EXA_STR(EXA_DEVICE_STRUCTS) << "\n";

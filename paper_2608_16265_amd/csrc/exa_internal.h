@@ -231,8 +231,10 @@ struct Group {
     std::vector<int> jt_refs, hv_refs;
     int64_t ob = 0, oh = 0;
     // per H v reference: every entry it stores is the only H v contribution
-    // to its variable (the kernel then writes the output entry itself when
-    // the instance's bit in ExaPatDev::hvd is set; at most 32 references)
+    // to its variable (at most 32 references).  Code generated with the flag
+    // set writes the output entry itself when the instance's bit in
+    // ExaPatDev::hvd is set, and the buffer entry otherwise; code generated
+    // without it always writes the buffer entry (no index kept live)
     std::vector<char> hv_direct;
 };
 
@@ -327,9 +329,12 @@ const std::vector<int>& multi_modes(bool jh);
 std::vector<Unit> units_for(const Model& M, int mode, bool fused);
 // Generated source for all callbacks; fills live[(mode, unit code)].
 // ident_flags: per pattern and index column, whether the code may use the
-// data point itself (default: each pattern's own flags)
+// data point itself (default: each pattern's own flags); hvd_flags: per
+// group and H v reference, whether the code may store the reference into
+// the output (default: each group's own Group::hv_direct)
 std::string generate_source(const Model& M, std::map<std::pair<int, int>, UnitLive>* live = nullptr,
-                            const std::vector<std::vector<char>>* ident_flags = nullptr);
+                            const std::vector<std::vector<char>>* ident_flags = nullptr,
+                            const std::vector<std::vector<char>>* hvd_flags = nullptr);
 
 // exa_runtime.cpp
 // Objective tiles always hold kObjBlock * kObjEpl points (256 virtual lanes

@@ -264,11 +264,15 @@ def test_instances_that_disagree_on_hv_references_stored_by_the_kernel():
         return Workload(m, rng.uniform(-1, 1, 2 * n + 1), rng.standard_normal(n), 1.0)
     wls = [inst(300, False, 1), inst(200, True, 2), inst(500, False, 3)]
     ems = [ExaModel(w.model) for w in wls]
-    b = ExaBatch(ems, autotune=False, units="per_callback")
-    X, Y, V, W, WX = _inputs(b, wls)
-    outs = {k: _nan(b, kind) for k, kind in ALL8.items()}
-    b.evaluate(X, Y, 1.0, V, W, **outs)
-    _check_against_plain(b, ems, X, Y, V, W, WX, 1.0, outs, tag="hvd")
+    # the first instance's code stores z[i] (the batch runs it), then the
+    # first instance's code does not (the batch compiles code that may)
+    for order in ([0, 1, 2], [1, 0, 2]):
+        sub = [ems[i] for i in order]
+        b = ExaBatch(sub, autotune=False, units="per_callback")
+        X, Y, V, W, WX = _inputs(b, [wls[i] for i in order])
+        outs = {k: _nan(b, kind) for k, kind in ALL8.items()}
+        b.evaluate(X, Y, 1.0, V, W, **outs)
+        _check_against_plain(b, sub, X, Y, V, W, WX, 1.0, outs, tag=f"hvd{order}")
     # and each instance's own callbacks (H v among them) against the oracle
     from test_parity_gpu import check_all
     for i, (w, em) in enumerate(zip(wls, ems)):
