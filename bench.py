@@ -131,14 +131,15 @@ def kernel_ms(fn, n=200):
 
 def profiled_traffic(summary, model, kernel):
     """HBM bytes per launch of `kernel` measured by rocprofv3 (FETCH_SIZE +
-    WRITE_SIZE, calibrated on a plain copy) as committed in profiles/, or
-    None when the generated kernels have changed since (their source hash
-    differs) or the summary covers another kernel."""
+    WRITE_SIZE, calibrated on a plain copy) as committed in profiles/, with
+    the schedule the counted launches ran; (None, None) when the generated
+    kernels have changed since (their source hash differs) or the summary
+    covers another kernel."""
     import hashlib
     from paper_2608_16265_amd import ExaModel
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
-        return None
+        return None, None
     kv = {}
     for line in open(path):
         if ":" in line and line.startswith("    "):
@@ -146,13 +147,13 @@ def profiled_traffic(summary, model, kernel):
             kv[k.strip()] = v.strip()
     src = ExaModel(model, host_only=True).generated_source()
     if hashlib.sha256(src.encode()).hexdigest()[:16] != kv.get("source_sha256_16"):
-        return None
+        return None, None
     if kv.get("kernel") != kernel:
-        return None
+        return None, None
     try:
-        return int(kv["traffic_bytes_per_launch"])
+        return int(kv["traffic_bytes_per_launch"]), kv.get("schedule")
     except (KeyError, ValueError):
-        return None
+        return None, None
 
 
 # ------------------------------------------------------------------- legs
@@ -803,10 +804,10 @@ def main():
                          "instances": r["instances"], "buses": r["buses"], "nvar": r["nvar"], "ncon": r["ncon"],
                          "nnzj": r["nnzj"], "nnzh": r["nnzh"], "schedule": r["schedule"]}
         from exa_modeling.generators import acopf as _acopf
-        traffic = profiled_traffic("batch256_eval_all.md", _acopf(30, 0).model, r["eval_kernel"])
+        traffic, tsched = profiled_traffic("batch256_eval_all.md", _acopf(30, 0).model, r["eval_kernel"])
         out["roofline"] = {"kernel": r["eval_kernel"], "bound": "hbm", "achieved": r["eval_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r["eval_gbs"] / HBM_PEAK_GBS,
-                           "traffic": traffic, "bytes_per_launch": r["eval_bytes"],
+                           "traffic": traffic, "traffic_schedule": tsched, "bytes_per_launch": r["eval_bytes"],
                            "read_bytes": r["eval_read_bytes"], "write_bytes": r["eval_write_bytes"],
                            "launch_us": r["eval_us"], "launches_timed": r["launches_timed"]}
         out["roofline_reduce"] = {"kernel": "k_reduce_batch", "achieved": r["reduce_gbs"],
@@ -823,7 +824,7 @@ def main():
         wl = acopf(10000, 1)
         r = leg_single("acopf10k", wl, args.steps, args.warmup)
         log(json.dumps(r))
-        traffic = profiled_traffic("acopf10k_eval_all.md", acopf(30, 0).model, r["eval_kernel"])
+        traffic, tsched = profiled_traffic("acopf10k_eval_all.md", acopf(30, 0).model, r["eval_kernel"])
         out["acopf10k"] = {
             "workload": "acopf-10000-bus (13,500 branches, 2,000 generators, seed 1)",
             "step": "exa_eval of obj, grad, cons, jac, hess, jprod, jtprod, hprod at one iterate",
@@ -835,6 +836,7 @@ def main():
             "ipm_nnz_per_s": r["ipm_nnz_per_s"], "jac_plus_hess_nnz_per_s": r["jac_plus_hess_nnz_per_s"],
             "roofline_eval": {"kernel": r["eval_kernel"], "achieved": r["eval_gbs"], "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": r["eval_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                              "traffic_schedule": tsched,
                               "bytes_per_launch": r["eval_bytes"], "launch_us": r["eval_us"]},
             "roofline_reduce": {"kernel": "k_reduce", "achieved": r["reduce_gbs"],
                                 "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]},
@@ -848,6 +850,7 @@ def main():
         wl = pde(1000, 3)
         r = leg_single("pde1000", wl, max(20, args.steps // 20), 5)
         log(json.dumps(r))
+        traffic, tsched = profiled_traffic("pde1000_eval_all.md", pde(8, 3).model, r["eval_kernel"])
         out["pde"] = {"workload": "pde-control 1000x1000 grid (2e6 variables, seed 3)",
                       "nnzj": r["nnzj"], "nnzh": r["nnzh"], "step_us": round(r["step_s"] * 1e6, 2),
                       "nnz_per_s": r["nnz_per_s"], "step_separate_us": r["step_separate_us"],
@@ -858,7 +861,8 @@ def main():
                       "callbacks_us": r["callbacks_us"],
                       "roofline_eval": {"kernel": r["eval_kernel"], "achieved": r["eval_gbs"],
                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                        "frac": r["eval_gbs"] / HBM_PEAK_GBS,
+                                        "frac": r["eval_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                                        "traffic_schedule": tsched,
                                         "bytes_per_launch": r["eval_bytes"], "launch_us": r["eval_us"]},
                       "roofline_reduce": {"kernel": "k_reduce", "achieved": r["reduce_gbs"],
                                           "bytes_per_launch": r["reduce_bytes"], "launch_us": r["reduce_us"]},
